@@ -1,0 +1,155 @@
+/*
+ * respca.h -- C ABI of librespca, an MI355X (gfx950) implementation of RES-PCA
+ * (Peng et al., "RES-PCA: A Scalable Approach to Recovering Low-rank Matrices",
+ * arXiv 1904.07497).
+ *
+ * Problem (Sec. 3, eq. eq_obj): split a d x n matrix X into L + S, where the
+ * columns of L are pulled toward the means of c groups (the within-group
+ * variance term, weight lambda) and S is sparse (l1 norm), the groups being
+ * learned by K-means.  Solved by the ALM iteration of Sec. 4: an L-step in
+ * closed form (Sec. 4.1), a p-step by K-means on the columns of L (Sec. 4.2), a
+ * soft-threshold S-step (Sec. 4.3) and the multiplier/penalty update (Sec. 4.4),
+ * stopped by the rule of Sec. 5.
+ *
+ * Conventions shared by every call
+ *   - Matrices are column-major (BLAS convention): entry (i, j) of an array
+ *     with leading dimension ld is at ptr[j*ld + i]; column j is sample j.
+ *     Leading dimensions must be >= d.
+ *   - Matrix and label pointers are DEVICE pointers on the handle's device
+ *     unless a comment says "host".  Element type: double for RESPCA_F64,
+ *     float for RESPCA_F32 and RESPCA_BF16GEMM_F32.
+ *   - The caller owns every buffer passed in; the library keeps no pointer
+ *     after a call returns.  X is read-only.  L, S, Theta, X must not overlap.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  All work
+ *     is enqueued on it; calls that return an info struct block until it is
+ *     complete (they read a few bytes back per iteration).
+ *   - Errors are reported only by the return code; no call throws or aborts.
+ *     On an error (< 0) the outputs are unspecified; respca_last_error()
+ *     gives a message.  Calls on one handle must not overlap in time.
+ *   - Limits: 1 <= c <= min(n, 1024); d, n < 2^31.
+ */
+#ifndef RESPCA_H
+#define RESPCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RESPCA_OK = 0,               /* converged (criterion <= tol)                      */
+    RESPCA_NOT_CONVERGED = 1,    /* max_iter reached; outputs are the last iterate    */
+    RESPCA_ERR_INVALID = -1,     /* bad size, parameter, pointer or aliasing          */
+    RESPCA_ERR_NONFINITE = -2,   /* X holds NaN or Inf (found by the ||X||_F pass)    */
+    RESPCA_ERR_NOMEM = -3,       /* device allocation failed                          */
+    RESPCA_ERR_HIP = -4,         /* a HIP runtime call failed                         */
+    RESPCA_ERR_UNSUPPORTED = -5  /* valid request outside this build's limits         */
+} respca_status;
+
+typedef enum {
+    RESPCA_F64 = 0,              /* everything in double                              */
+    RESPCA_F32 = 1,              /* float data and arithmetic, double accumulators    */
+    RESPCA_BF16GEMM_F32 = 2      /* as F32, but K-means distances on bf16 MFMA with an
+                                    exact FP32 re-check of close calls               */
+} respca_precision;
+
+typedef struct {
+    double   lambda;      /* weight of the group-variance term of eq_obj (Sec. 3); must be
+                             >= 0.  NaN selects sqrt(max(d, n)), the value of Sec. 5.1.   */
+    int32_t  rank;        /* c, the number of groups; 0 selects 5 (Sec. 5.1, unknown rank) */
+    double   tol;         /* stopping tolerance of the Sec. 5 criterion; default 1e-3      */
+    int32_t  max_iter;    /* outer-iteration cap; default 500 (Sec. 5)                      */
+    double   rho0;        /* initial penalty; default 1e-4 (Sec. 5.1)                       */
+    double   kappa;       /* penalty growth factor, > 1; default 1.5 (Sec. 4.4, 5.1)        */
+    double   rho_max;     /* cap on rho (not in the paper); default 1e10                    */
+    int32_t  max_lloyd;   /* cap on Lloyd assignment passes per K-means call; default 100   */
+    uint64_t seed;        /* splitmix64 seed of the k-means++ initialisation; default 0     */
+    int32_t  precision;   /* respca_precision; default RESPCA_F32                           */
+    const int32_t *init_labels; /* optional device int32[n] in [0, c): initial groups used
+                             instead of k-means++ + Lloyd on X (warm start); NULL = none   */
+    double  *history;     /* optional HOST double[3 * max_iter]: per iteration the three
+                             relative criterion terms (primal, dL, dS); NULL = none        */
+} respca_params;
+
+typedef struct {
+    int32_t iters;        /* outer iterations run                                       */
+    int32_t lloyd_steps;  /* assignment passes summed over the outer iterations         */
+    int32_t init_lloyd;   /* assignment passes of the initial K-means on X              */
+    int32_t status;       /* respca_status of the call                                  */
+    double  primal;       /* ||X - L - S||_F / ||X||_F at the last iteration            */
+    double  dL;           /* ||L_t - L_{t-1}||_F / ||X||_F                              */
+    double  dS;           /* ||S_t - S_{t-1}||_F / ||X||_F                              */
+    double  rho_final;    /* rho used by the last iteration                             */
+} respca_info;
+
+typedef struct respca_handle_s *respca_handle;
+
+/* Create a handle bound to HIP device `device` (its workspace grows on demand
+ * and is freed by respca_destroy).  Returns RESPCA_ERR_HIP if the device is
+ * unavailable. */
+respca_status respca_create(respca_handle *out, int32_t device);
+void          respca_destroy(respca_handle h);
+
+/* Fill *p with the defaults listed above.  Needs no device. */
+void          respca_params_default(respca_params *p);
+/* Static strings.  Need no device. */
+const char   *respca_status_string(respca_status s);
+const char   *respca_last_error(respca_handle h);
+/* Version string of the library build.  Needs no device. */
+const char   *respca_version(void);
+
+/*
+ * Whole solve (Sec. 4 iteration with the Sec. 5 stopping rule).
+ *   X (d x n, ldx), read-only.  L (d x n, ldl) and S (d x n, lds) receive the
+ *   low-rank and sparse parts.  labels (nullable, device int32[n]) receives the
+ *   final groups.  info (host, nullable) receives the counters.
+ * Initialisation (not specified by the paper): S = Theta = 0, L_0 = 0,
+ * rho = rho0, groups = K-means of the columns of X (k-means++ seeding from
+ * splitmix64(seed), then Lloyd) unless params->init_labels is given.
+ * ||X||_F == 0 returns RESPCA_OK with L = S = 0, labels 0 and iters = 0.
+ * Returns RESPCA_OK, RESPCA_NOT_CONVERGED or an error.
+ */
+respca_status respca_solve(respca_handle h, const respca_params *params,
+                           int64_t d, int64_t n,
+                           const void *X, int64_t ldx,
+                           void *L, int64_t ldl,
+                           void *S, int64_t lds,
+                           int32_t *labels, respca_info *info, void *stream);
+
+/*
+ * Run `iters` outer iterations (Sec. 4.1 -> 4.2 -> 4.3 -> 4.4) from a state the
+ * caller holds, updating it in place; no initialisation and no stopping test.
+ *   L (ldl): on entry L_{t-1}, on exit L_t.   S (lds), Theta (ldt): previous ->
+ *   new iterate.   labels (device int32[n]) and C (device d x c, leading
+ *   dimension d: group centroids, used for groups that are empty) in/out.
+ *   *rho (host): rho_t on entry, the next rho on exit.
+ *   norms (host, nullable): 3 doubles per iteration, the absolute Frobenius
+ *   norms ||X-L-S||, ||L_t-L_{t-1}||, ||S_t-S_{t-1}||.
+ * This is the checkpoint/resume and step-by-step interface.
+ */
+respca_status respca_iterate(respca_handle h, const respca_params *params,
+                             int64_t d, int64_t n,
+                             const void *X, int64_t ldx,
+                             void *L, int64_t ldl,
+                             void *S, int64_t lds,
+                             void *Theta, int64_t ldt,
+                             int32_t *labels, void *C, double *rho, int32_t iters,
+                             double *norms, respca_info *info, void *stream);
+
+/*
+ * K-means of the columns of Y (d x n, ldy): k-means++ seeding driven by
+ * splitmix64(params->seed), nearest-seed assignment, group means (an empty group
+ * keeps its seed), then Lloyd passes until no label changes or max_lloyd.
+ * labels (device int32[n]) and C (device d x c, leading dimension d) are
+ * outputs; info->init_lloyd receives the number of Lloyd passes.  This is the
+ * initialisation respca_solve uses (the p-step of Sec. 4.2 applied to X).
+ */
+respca_status respca_kmeans(respca_handle h, const respca_params *params,
+                            int64_t d, int64_t n, const void *Y, int64_t ldy,
+                            int32_t *labels, void *C, respca_info *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

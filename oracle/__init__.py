@@ -74,6 +74,8 @@ def lib():
         L.oracle_theta_step.argtypes = [i64, i64, f64, dp, dp, dp, dp]
         L.oracle_step.restype = i32
         L.oracle_step.argtypes = [P(Params), i64, i64, dp, dp, dp, dp, ip, dp, dp, dp]
+        L.oracle_step_columns.argtypes = [P(Params), i64, i64, dp, dp, dp, ip, dp, f64, i64, lp,
+                                          dp, dp, dp, ip, dp]
         L.oracle_solve.restype = i32
         L.oracle_solve.argtypes = [P(Params), i64, i64, dp, dp, dp, ip, dp, ip, P(Info), dp]
         _lib = L
@@ -212,6 +214,25 @@ def step(params: Params, X, state: dict) -> dict:
                               _dp(C), ct.byref(rho), _dp(norms))
     return {"L": L, "S": S, "Theta": T, "labels": lab, "C": C, "rho": rho.value,
             "norms": norms, "lloyd": int(steps)}
+
+
+def step_columns(params: Params, X, state: dict, sel):
+    """One iteration (single assignment pass) evaluated only at columns ``sel``;
+    group means still use every column.  Returns dict(L, S, Theta, labels) of
+    shape (d, len(sel)) / (len(sel),)."""
+    X = _f64(X)
+    d, n = X.shape
+    S, T, C = _f64(state["S"]), _f64(state["Theta"]), _f64(state["C"])
+    lab = np.ascontiguousarray(state["labels"], dtype=np.int32)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    m = sel.size
+    Lo, So, To = (np.zeros((d, m), order="F") for _ in range(3))
+    lo = np.zeros(m, dtype=np.int32)
+    mu = np.zeros((d, params.c), order="F")
+    lib().oracle_step_columns(ct.byref(params), d, n, _dp(X), _dp(S), _dp(T), _ip(lab), _dp(C),
+                              float(state["rho"]), m, _lp(sel), _dp(Lo), _dp(So), _dp(To), _ip(lo),
+                              _dp(mu))
+    return {"L": Lo, "S": So, "Theta": To, "labels": lo, "mu": mu}
 
 
 def solve(X, params: Params, init_labels=None, history=False):

@@ -246,6 +246,39 @@ int32_t oracle_step(const oracle_params *p, int64_t d, int64_t n, const double *
     return steps;
 }
 
+void oracle_step_columns(const oracle_params *p, int64_t d, int64_t n, const double *X,
+                         const double *S, const double *Theta, const int32_t *labels,
+                         const double *C, double rho, int64_t nsel, const int64_t *sel,
+                         double *L_out, double *S_out, double *Theta_out, int32_t *labels_out,
+                         double *mu_out)
+{
+    size_t dn = (size_t)d * (size_t)n;
+    int32_t c = p->c;
+    double *D = (double *)malloc(dn * sizeof(double));
+    double *mu = (double *)malloc((size_t)d * (size_t)c * sizeof(double));
+    int64_t *counts = (int64_t *)malloc((size_t)c * sizeof(int64_t));
+    for (size_t e = 0; e < dn; ++e) D[e] = X[e] - S[e] + Theta[e] / rho;
+    memcpy(mu, C, (size_t)d * (size_t)c * sizeof(double));
+    oracle_group_means(d, n, c, D, labels, mu, counts);   /* empty groups keep C */
+
+    double alpha = rho / (2.0 * p->lambda + rho);
+    double beta = (2.0 * p->lambda) / (2.0 * p->lambda + rho);
+    for (int64_t q = 0; q < nsel; ++q) {
+        int64_t j = sel[q];
+        int32_t k = labels[j];
+        double *Lq = L_out + q * d;
+        for (int64_t i = 0; i < d; ++i) Lq[i] = alpha * D[j * d + i] + beta * mu[k * d + i];
+        oracle_assign(d, 1, c, Lq, mu, labels_out + q);
+        oracle_s_step(d, 1, rho, X + j * d, Lq, Theta + j * d, S_out + q * d);
+        memcpy(Theta_out + q * d, Theta + j * d, (size_t)d * sizeof(double));
+        oracle_theta_step(d, 1, rho, X + j * d, Lq, S_out + q * d, Theta_out + q * d);
+    }
+    if (mu_out) memcpy(mu_out, mu, (size_t)d * (size_t)c * sizeof(double));
+    free(counts);
+    free(mu);
+    free(D);
+}
+
 /* --------------------------------------------------------- whole solve --- */
 
 static int params_valid(const oracle_params *p, int64_t d, int64_t n)

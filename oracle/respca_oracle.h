@@ -122,6 +122,19 @@ int32_t oracle_step(const oracle_params *p, int64_t d, int64_t n, const double *
                     double *L, double *S, double *Theta, int32_t *labels,
                     double *C, double *rho, double norms[3]);
 
+/* One outer iteration restricted to selected columns, with a single assignment
+ * pass (max_lloyd = 1): the group means of D are taken over ALL n columns, then
+ * for each selected column sel[q] the outputs L, S, Theta (d values each, stored
+ * as column q of d x nsel arrays) and its new label are computed from them.
+ * C (d x c, in) supplies the centroid of groups that are empty; mu_out
+ * (d x c, nullable) receives the centroids the assignment used.  Used to check
+ * large runs column by column. */
+void oracle_step_columns(const oracle_params *p, int64_t d, int64_t n, const double *X,
+                         const double *S, const double *Theta, const int32_t *labels,
+                         const double *C, double rho, int64_t nsel, const int64_t *sel,
+                         double *L_out, double *S_out, double *Theta_out, int32_t *labels_out,
+                         double *mu_out);
+
 /* Whole solve.  init_labels (nullable) replaces the k-means++ initialisation;
  * the centroids then start as group means of X (zero for empty groups).
  * history (nullable) receives 3 doubles per iteration (the relative criterion

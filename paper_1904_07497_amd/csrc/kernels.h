@@ -1,0 +1,85 @@
+// Internal launchers of librespca's gfx950 kernels.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace respca {
+
+constexpr int kBlock = 256;          // threads of a streaming workgroup (4 wave64)
+constexpr int kRowsPerBlock = 1024;  // rows of the d-slice one streaming workgroup covers
+constexpr int kSegCols = 64;         // max columns of one group segment in the means pass
+constexpr int kMaxGroups = 1024;     // c limit (LDS histogram of the label sort)
+constexpr int kSortThreads = 512;    // single-workgroup label sort
+constexpr int kPickThreads = 1024;   // single-workgroup k-means++ draw
+
+inline int row_blocks(int64_t d) { return (int)((d + kRowsPerBlock - 1) / kRowsPerBlock); }
+inline int max_segments(int64_t n, int c) { return (int)((n + kSegCols - 1) / kSegCols) + c; }
+
+// Fill a d x n column-major array (leading dimension ld) with zeros.
+template <typename T>
+void launch_zero2d(T* A, int64_t ld, int64_t d, int64_t n, hipStream_t st);
+void launch_zero_i32(int32_t* a, int64_t count, hipStream_t st);
+
+// Sum of squares of X in double: per-workgroup partials, count returned.
+template <typename T>
+int launch_sumsq(const T* X, int64_t ldx, int64_t d, int64_t n, double* partial, hipStream_t st);
+// Fixed-order sum of `count` partial triples/singles into out[0..width).
+void launch_sum_partials(const double* partial, int count, int width, double* out, hipStream_t st);
+
+// Stable counting sort of labels: counts[c], perm[n] (columns grouped by label,
+// increasing index within a group), and the segment table of the means pass.
+void launch_label_sort(const int32_t* labels, int64_t n, int c, int32_t* counts, int32_t* perm,
+                       int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg,
+                       hipStream_t st);
+
+// Group partial sums: partial[s*d + i] = sum over the columns j of segment s of
+// Y[i, j], where Y = X - S + Theta*inv_rho (with_d = true) or Y = A (with_d = false).
+template <typename T>
+void launch_group_partial(bool with_d, const T* A, int64_t lda, const T* S, int64_t lds,
+                          const T* Th, int64_t ldt, T inv_rho, int64_t d, int64_t n, int c,
+                          const int32_t* perm, const int32_t* seg_begin, const int32_t* seg_len,
+                          const int32_t* nseg, double* partial, hipStream_t st);
+
+// C[:, k] = (sum of the segment partials of group k) / n_k for non-empty groups.
+template <typename T>
+void launch_group_finalize(const double* partial, int64_t d, int c, const int32_t* counts,
+                           const int32_t* seg_first, T* C, hipStream_t st);
+
+// out[k] = ||C[:, k]||^2 in double.
+template <typename T>
+void launch_col_sqnorm(const T* C, int64_t d, int c, double* out, hipStream_t st);
+
+// One ALM sweep over every entry: L-step, S-step, multiplier update, and the
+// three squared-norm partials (returns the number of partial triples).
+template <typename T>
+int launch_sweep(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th,
+                 int64_t ldt, const T* C, const int32_t* labels, int64_t d, int64_t n,
+                 double alpha, double beta, double rho, double inv_rho, double* norm_partial,
+                 hipStream_t st);
+int sweep_partials(int64_t d, int64_t n);
+
+// Split-d centroid/column dot products: part[(rb*c + k)*n + j] = sum_{i in slice rb} C[i,k] Y[i,j].
+template <typename T>
+void launch_dots(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t n, T* part,
+                 hipStream_t st);
+
+// labels_new[j] = argmin_k ||C_k||^2 - 2 C_k . Y_j (ties: lowest k); per-block
+// counts of changed labels.  Returns the number of count partials.
+template <typename T>
+int launch_argmin(const T* part, int nrb, int c, int64_t n, const double* cnorm,
+                  const int32_t* old_labels, int32_t* new_labels, double* changed_partial,
+                  hipStream_t st);
+
+// k-means++ helpers.
+template <typename T>
+void launch_d2(const T* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* seeds, int m,
+               double* d2, hipStream_t st);
+void launch_pick(const double* d2, int64_t n, const double* u, int m, int32_t* seeds,
+                 int32_t* chosen, hipStream_t st);
+template <typename T>
+void launch_gather_cols(const T* Y, int64_t ldy, int64_t d, const int32_t* idx, int c, T* C,
+                        hipStream_t st);
+
+}  // namespace respca

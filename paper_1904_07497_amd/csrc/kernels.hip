@@ -1,0 +1,725 @@
+// gfx950 kernels of librespca: the per-iteration RES-PCA sweep and its K-means.
+//
+// Layout: every d x n matrix is column-major; a streaming workgroup owns a
+// slice of kRowsPerBlock consecutive rows and walks columns, so each wave64
+// load touches 64 consecutive rows of one column (coalesced), vectorised to
+// 16-byte loads when d and the leading dimensions allow it.  All reductions
+// are two-level (workgroup partials, then one fixed-order pass), so results
+// are bitwise reproducible run to run; no floating-point atomics are used.
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+namespace respca {
+
+namespace {
+
+// ------------------------------------------------------------ small helpers
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sum of 3 values over a 256-thread block; result valid in thread 0.
+__device__ inline void block_sum3(double& a, double& b, double& c) {
+    __shared__ double sh[3][kBlock / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = sh[0][0]; b = sh[1][0]; c = sh[2][0];
+        for (int i = 1; i < kBlock / 64; ++i) { a += sh[0][i]; b += sh[1][i]; c += sh[2][i]; }
+    }
+}
+
+template <typename T, int V> struct Vec;
+template <> struct Vec<float, 4> { using type = float4; };
+template <> struct Vec<double, 2> { using type = double2; };
+
+template <typename T, int V>
+__device__ inline void vload(const T* p, T (&r)[V]) {
+    if constexpr (V == 1) {
+        r[0] = *p;
+    } else {
+        using VT = typename Vec<T, V>::type;
+        VT v = *reinterpret_cast<const VT*>(p);
+        if constexpr (V == 4) { r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w; }
+        else { r[0] = v.x; r[1] = v.y; }
+    }
+}
+
+template <typename T, int V>
+__device__ inline void vstore(T* p, const T (&r)[V]) {
+    if constexpr (V == 1) {
+        *p = r[0];
+    } else {
+        using VT = typename Vec<T, V>::type;
+        VT v;
+        if constexpr (V == 4) { v.x = r[0]; v.y = r[1]; v.z = r[2]; v.w = r[3]; }
+        else { v.x = r[0]; v.y = r[1]; }
+        *reinterpret_cast<VT*>(p) = v;
+    }
+}
+
+// Vector width usable for a set of column-major operands: 16-byte accesses
+// need d and every leading dimension to be multiples of the width and 16-byte
+// aligned bases, so that a vector never straddles a column end.
+template <typename T>
+inline int pick_vec(int64_t d, std::initializer_list<std::pair<const void*, int64_t>> ops) {
+    constexpr int V = 16 / sizeof(T);
+    if (d % V) return 1;
+    for (auto& o : ops) {
+        if (o.second % V) return 1;
+        if (reinterpret_cast<uintptr_t>(o.first) % 16) return 1;
+    }
+    return V;
+}
+
+// ------------------------------------------------------------------ fills
+
+template <typename T>
+__global__ void k_zero2d(T* A, int64_t ld, int64_t d, int64_t n) {
+    const int64_t total = d * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / d, i = e - j * d;
+        A[j * ld + i] = T(0);
+    }
+}
+
+__global__ void k_zero_i32(int32_t* a, int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        a[e] = 0;
+}
+
+// ----------------------------------------------------------- sum of squares
+
+// Workgroup (cb, rb): columns [cb*jc, cb*jc + jc) of row slice rb.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sumsq(const T* X, int64_t ldx, int64_t d, int64_t n,
+                                                  int jc, double* partial) {
+    const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
+    const int64_t j0 = (int64_t)blockIdx.x * jc;
+    const int64_t j1 = j0 + jc < n ? j0 + jc : n;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t j = j0; j < j1; ++j)
+        for (int s = 0; s < kRowsPerBlock / kBlock; ++s) {
+            const int64_t i = r0 + s * kBlock + threadIdx.x;
+            if (i < d) { const double x = (double)X[j * ldx + i]; a += x * x; }
+        }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * gridDim.y + blockIdx.y] = a;
+}
+
+// One workgroup; `width` interleaved sums over `count` records, fixed order.
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, int count,
+                                                         int width, double* out) {
+    for (int w = 0; w < width; ++w) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int r = threadIdx.x; r < count; r += kBlock) a += partial[(int64_t)r * width + w];
+        block_sum3(a, b, c);
+        if (threadIdx.x == 0) out[w] = a;
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------- label sort
+
+// Stable counting sort in one workgroup of kSortThreads threads.  Wave w owns
+// a contiguous range of columns; per-(wave, label) counts give every wave its
+// own output offsets, and inside a wave equal labels are ranked with ballots,
+// so the output order is "by label, then by column index".
+__global__ __launch_bounds__(kSortThreads) void k_label_sort(
+    const int32_t* __restrict__ labels, int n, int c, int32_t* counts, int32_t* perm,
+    int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg_out) {
+    constexpr int W = kSortThreads / 64;
+    __shared__ int cnt[W * kMaxGroups];
+    __shared__ int wsum[W];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+    for (int e = tid; e < W * c; e += kSortThreads) cnt[e] = 0;
+    __syncthreads();
+    const int per = (n + W - 1) / W;
+    const int lo = wave * per, hi = min(n, lo + per);
+    for (int j = lo + lane; j < hi; j += 64) atomicAdd(&cnt[wave * c + labels[j]], 1);
+    __syncthreads();
+
+    // exclusive scan over groups of (total count) and of (segments), two passes
+    // of a chunked block scan: each thread owns up to 2 consecutive groups.
+    constexpr int GPT = kMaxGroups / kSortThreads;
+    int tot[GPT], nsg[GPT];
+    int my_tot = 0, my_seg = 0;
+#pragma unroll
+    for (int g = 0; g < GPT; ++g) {
+        const int k = tid * GPT + g;
+        int t = 0;
+        if (k < c)
+            for (int w = 0; w < W; ++w) t += cnt[w * c + k];
+        tot[g] = t;
+        nsg[g] = (t + kSegCols - 1) / kSegCols;
+        my_tot += t;
+        my_seg += nsg[g];
+    }
+    // block exclusive scan of (my_tot, my_seg) packed into two passes
+    auto block_exscan = [&](int v) -> int {
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        int base = 0;
+        for (int w = 0; w < wave; ++w) base += wsum[w];
+        __syncthreads();
+        return base + x - v;
+    };
+    int base_cnt = block_exscan(my_tot);
+    int base_seg = block_exscan(my_seg);
+
+#pragma unroll
+    for (int g = 0; g < GPT; ++g) {
+        const int k = tid * GPT + g;
+        if (k < c) {
+            counts[k] = tot[g];
+            seg_first[k] = base_seg;
+            for (int q = 0; q < nsg[g]; ++q) {
+                seg_begin[base_seg + q] = base_cnt + q * kSegCols;
+                seg_len[base_seg + q] = min(kSegCols, tot[g] - q * kSegCols);
+            }
+            // per-wave output offsets, in place
+            int run = base_cnt;
+            for (int w = 0; w < W; ++w) {
+                const int t = cnt[w * c + k];
+                cnt[w * c + k] = run;
+                run += t;
+            }
+            if (k == c - 1) { seg_first[c] = base_seg + nsg[g]; *nseg_out = base_seg + nsg[g]; }
+        }
+        base_cnt += tot[g];
+        base_seg += nsg[g];
+    }
+    __syncthreads();
+
+    for (int b0 = lo; b0 < hi; b0 += 64) {
+        const int j = b0 + lane;
+        const bool valid = j < hi;
+        const int lab = valid ? labels[j] : -1;
+        unsigned long long pending = __ballot(valid);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int L = __shfl(lab, leader);
+            const unsigned long long m = __ballot(valid && lab == L);
+            const int b = cnt[wave * c + L];
+            if (valid && lab == L) perm[b + __popcll(m & ((1ull << lane) - 1ull))] = j;
+            __builtin_amdgcn_wave_barrier();
+            if (lane == leader) cnt[wave * c + L] = b + __popcll(m);
+            __builtin_amdgcn_wave_barrier();
+            pending &= ~m;
+        }
+    }
+}
+
+// ---------------------------------------------------------- group partials
+
+// Grid (segment slots, row slices).  Segment s sums its columns (taken in the
+// sorted order) into a double accumulator per row; slots past the real
+// segment count exit at once.
+template <typename T, int V, bool WITH_D>
+__global__ __launch_bounds__(kBlock) void k_group_partial(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ S, int64_t lds,
+    const T* __restrict__ Th, int64_t ldt, T inv_rho, int64_t d, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ seg_begin, const int32_t* __restrict__ seg_len,
+    const int32_t* __restrict__ nseg, double* __restrict__ partial) {
+    const int s = blockIdx.x;
+    if (s >= *nseg) return;
+    constexpr int NS = kRowsPerBlock / (kBlock * V);
+    const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
+    const int begin = seg_begin[s], len = seg_len[s];
+    double acc[NS][V];
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
+
+    for (int q = 0; q < len; ++q) {
+        const int64_t j = perm[begin + q];
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            if (i < d) {
+                T x[V];
+                vload<T, V>(A + j * lda + i, x);
+                if constexpr (WITH_D) {
+                    T sv[V], tv[V];
+                    vload<T, V>(S + j * lds + i, sv);
+                    vload<T, V>(Th + j * ldt + i, tv);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) x[v] = x[v] - sv[v] + tv[v] * inv_rho;
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[a][v] += (double)x[v];
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+        const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+        if (i < d)
+#pragma unroll
+            for (int v = 0; v < V; ++v) partial[(int64_t)s * d + i + v] = acc[a][v];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_group_finalize(const double* __restrict__ partial,
+                                                           int64_t d, const int32_t* counts,
+                                                           const int32_t* seg_first, T* C) {
+    const int k = blockIdx.y;
+    const int nk = counts[k];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (nk == 0 || i >= d) return;
+    double s = 0.0;
+    for (int g = seg_first[k]; g < seg_first[k + 1]; ++g) s += partial[(int64_t)g * d + i];
+    C[(int64_t)k * d + i] = (T)(s / (double)nk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_col_sqnorm(const T* C, int64_t d, double* out) {
+    const int k = blockIdx.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < d; i += kBlock) {
+        const double x = (double)C[(int64_t)k * d + i];
+        a += x * x;
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) out[k] = a;
+}
+
+// ------------------------------------------------------------------- sweep
+
+// The fused ALM sweep.  Per entry (i, j) with group p = labels[j]:
+//   D  = X - S + Theta/rho                     (matrix the L-step pulls toward)
+//   L  = alpha D + beta C[:, p]                (Sec. 4.1 closed form, C = group mean of D)
+//   B  = X - L + Theta/rho;  S' = sign(B) max(|B| - 1/rho, 0)      (Sec. 4.3)
+//   Theta' = Theta + rho (X - L - S')                              (Sec. 4.4)
+// and the squared norms of X - L - S', L - L_prev, S' - S in double.
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void k_sweep(
+    const T* __restrict__ X, int64_t ldx, T* __restrict__ L, int64_t ldl, T* __restrict__ S,
+    int64_t lds, T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
+    const int32_t* __restrict__ labels, int64_t d, int64_t n, int jc, T alpha, T beta, T rho,
+    T inv_rho, double* __restrict__ norm_partial) {
+    constexpr int NS = kRowsPerBlock / (kBlock * V);
+    const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
+    const int64_t j0 = (int64_t)blockIdx.x * jc;
+    const int64_t j1 = j0 + jc < n ? j0 + jc : n;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        const int64_t p = labels[j];
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            if (i >= d) continue;
+            T x[V], s[V], t[V], lp[V], m[V], ln[V], sn[V], tn[V];
+            vload<T, V>(X + j * ldx + i, x);
+            vload<T, V>(S + j * lds + i, s);
+            vload<T, V>(Th + j * ldt + i, t);
+            vload<T, V>(L + j * ldl + i, lp);
+            vload<T, V>(C + p * d + i, m);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const T dv = x[v] - s[v] + t[v] * inv_rho;
+                ln[v] = alpha * dv + beta * m[v];
+                const T b = x[v] - ln[v] + t[v] * inv_rho;
+                const T mag = fabs(b) - inv_rho;
+                sn[v] = mag > T(0) ? copysign(mag, b) : T(0);
+                const T r = x[v] - ln[v] - sn[v];
+                tn[v] = t[v] + rho * r;
+                const double dl = (double)ln[v] - (double)lp[v];
+                const double ds = (double)sn[v] - (double)s[v];
+                a0 += (double)r * (double)r;
+                a1 += dl * dl;
+                a2 += ds * ds;
+            }
+            vstore<T, V>(L + j * ldl + i, ln);
+            vstore<T, V>(S + j * lds + i, sn);
+            vstore<T, V>(Th + j * ldt + i, tn);
+        }
+    }
+    block_sum3(a0, a1, a2);
+    if (threadIdx.x == 0) {
+        double* o = norm_partial + 3 * ((int64_t)blockIdx.x * gridDim.y + blockIdx.y);
+        o[0] = a0; o[1] = a1; o[2] = a2;
+    }
+}
+
+// -------------------------------------------------------------------- dots
+
+// Tile: 64 columns x CT = 16*KB groups, over one kRowsPerBlock slice of rows,
+// staged through LDS 32 rows at a time; each thread owns a KB x 4 block.
+template <typename T, int KB>
+__global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ C, int64_t d, int c,
+                                                 const T* __restrict__ Y, int64_t ldy, int64_t n,
+                                                 T* __restrict__ part) {
+    constexpr int CT = 16 * KB, JT = 64, RT = 32;
+    __shared__ T As[RT][CT + 4];
+    __shared__ T Bs[RT][JT + 4];
+    const int tid = threadIdx.x, tk = tid >> 4, tj = tid & 15;
+    const int64_t j0 = (int64_t)blockIdx.x * JT;
+    const int k0 = blockIdx.y * CT;
+    const int rb = blockIdx.z;
+    const int64_t rbeg = (int64_t)rb * kRowsPerBlock;
+    const int64_t rend = rbeg + kRowsPerBlock < d ? rbeg + kRowsPerBlock : d;
+    T acc[KB][4];
+#pragma unroll
+    for (int a = 0; a < KB; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+
+    for (int64_t r = rbeg; r < rend; r += RT) {
+#pragma unroll
+        for (int m = 0; m < (RT * JT) / kBlock; ++m) {
+            const int e = tid + kBlock * m, row = e & (RT - 1), col = e / RT;
+            const int64_t gi = r + row, gj = j0 + col;
+            Bs[row][col] = (gi < rend && gj < n) ? Y[gj * ldy + gi] : T(0);
+        }
+#pragma unroll
+        for (int m = 0; m < (RT * CT) / kBlock; ++m) {
+            const int e = tid + kBlock * m, row = e & (RT - 1), col = e / RT;
+            const int64_t gi = r + row;
+            const int gk = k0 + col;
+            As[row][col] = (gi < rend && gk < c) ? C[(int64_t)gk * d + gi] : T(0);
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int rr = 0; rr < RT; ++rr) {
+            T a[KB], b[4];
+#pragma unroll
+            for (int q = 0; q < KB; ++q) a[q] = As[rr][tk * KB + q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[q] = Bs[rr][tj * 4 + q];
+#pragma unroll
+            for (int x = 0; x < KB; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < KB; ++x) {
+        const int k = k0 + tk * KB + x;
+        if (k >= c) continue;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int64_t j = j0 + tj * 4 + y;
+            if (j < n) part[((int64_t)rb * c + k) * n + j] = acc[x][y];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_argmin(const T* __restrict__ part, int nrb, int c,
+                                                   int64_t n, const double* __restrict__ cnorm,
+                                                   const int32_t* __restrict__ old_labels,
+                                                   int32_t* __restrict__ new_labels,
+                                                   double* __restrict__ changed_partial) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double changed = 0.0;
+    if (j < n) {
+        int best = 0;
+        double bestd = INFINITY;
+        for (int k = 0; k < c; ++k) {
+            double dot = 0.0;
+            for (int rb = 0; rb < nrb; ++rb) dot += (double)part[((int64_t)rb * c + k) * n + j];
+            const double dist = cnorm[k] - 2.0 * dot;
+            if (dist < bestd) { bestd = dist; best = k; }
+        }
+        new_labels[j] = best;
+        changed = (old_labels[j] != best) ? 1.0 : 0.0;
+    }
+    double b = 0.0, c2 = 0.0;
+    block_sum3(changed, b, c2);
+    if (threadIdx.x == 0) changed_partial[blockIdx.x] = changed;
+}
+
+// -------------------------------------------------------------- k-means++
+
+// One wave per column: d2[j] = min(d2[j], ||Y_j - Y_s||^2) in double, s = seeds[m].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_d2(const T* __restrict__ Y, int64_t ldy, int64_t d,
+                                               int64_t n, const int32_t* __restrict__ seeds, int m,
+                                               double* __restrict__ d2) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const int64_t s = seeds[m];
+    double acc = 0.0;
+    for (int64_t i = lane; i < d; i += 64) {
+        const double t = (double)Y[j * ldy + i] - (double)Y[s * ldy + i];
+        acc += t * t;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) d2[j] = (m == 0) ? acc : fmin(d2[j], acc);
+}
+
+__device__ inline int block_min_i(int v, int* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    int r = sh[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = min(r, sh[i]);
+    return r;
+}
+
+// Inverse-CDF draw of the next seed: thread t sums a contiguous chunk, a block
+// scan gives each chunk its starting running sum, and the first index whose
+// running sum exceeds u*total wins.
+__global__ __launch_bounds__(kPickThreads) void k_pick(const double* __restrict__ d2, int64_t n,
+                                                       const double* __restrict__ u, int m,
+                                                       int32_t* seeds, int32_t* chosen) {
+    __shared__ double wtot[kPickThreads / 64];
+    __shared__ int ish[kPickThreads / 64];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t chunk = (n + kPickThreads - 1) / kPickThreads;
+    const int64_t lo = tid * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    double loc = 0.0;
+    for (int64_t j = lo; j < hi; ++j) loc += d2[j];
+    double x = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[wave] = x;
+    __syncthreads();
+    double pre = 0.0, total = 0.0;
+    for (int w = 0; w < kPickThreads / 64; ++w) {
+        if (w < wave) pre += wtot[w];
+        total += wtot[w];
+    }
+    pre += x - loc;
+    int s;
+    if (total > 0.0) {
+        const double target = u[m] * total;
+        int cand = INT_MAX;
+        double run = pre;
+        for (int64_t j = lo; j < hi; ++j) {
+            run += d2[j];
+            if (run > target) { cand = (int)j; break; }
+        }
+        s = block_min_i(cand, ish);
+        if (s == INT_MAX) {
+            int last = INT_MAX;  // largest index with a non-zero weight, via min of -j
+            for (int64_t j = hi - 1; j >= lo; --j)
+                if (d2[j] > 0.0) { last = -(int)j; break; }
+            s = -block_min_i(last, ish);
+        }
+    } else {
+        int cand = INT_MAX;
+        for (int64_t j = lo; j < hi; ++j)
+            if (!chosen[j]) { cand = (int)j; break; }
+        s = block_min_i(cand, ish);
+    }
+    if (tid == 0) { seeds[m] = s; chosen[s] = 1; }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_cols(const T* __restrict__ Y, int64_t ldy,
+                                                        int64_t d, const int32_t* __restrict__ idx,
+                                                        T* __restrict__ C) {
+    const int k = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < d) C[(int64_t)k * d + i] = Y[(int64_t)idx[k] * ldy + i];
+}
+
+inline int grid_cap(int64_t work, int per) {
+    int64_t g = (work + per - 1) / per;
+    if (g > 65535) g = 65535;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+// ================================================================ launchers
+
+template <typename T>
+void launch_zero2d(T* A, int64_t ld, int64_t d, int64_t n, hipStream_t st) {
+    k_zero2d<T><<<grid_cap(d * n, kBlock * 8), kBlock, 0, st>>>(A, ld, d, n);
+}
+
+void launch_zero_i32(int32_t* a, int64_t count, hipStream_t st) {
+    k_zero_i32<<<grid_cap(count, kBlock * 8), kBlock, 0, st>>>(a, count);
+}
+
+template <typename T>
+int launch_sumsq(const T* X, int64_t ldx, int64_t d, int64_t n, double* partial, hipStream_t st) {
+    const int nrb = row_blocks(d);
+    const int jc = 16;
+    const int ncb = (int)((n + jc - 1) / jc);
+    k_sumsq<T><<<dim3(ncb, nrb), kBlock, 0, st>>>(X, ldx, d, n, jc, partial);
+    return nrb * ncb;
+}
+
+void launch_sum_partials(const double* partial, int count, int width, double* out,
+                         hipStream_t st) {
+    k_sum_partials<<<1, kBlock, 0, st>>>(partial, count, width, out);
+}
+
+void launch_label_sort(const int32_t* labels, int64_t n, int c, int32_t* counts, int32_t* perm,
+                       int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg,
+                       hipStream_t st) {
+    k_label_sort<<<1, kSortThreads, 0, st>>>(labels, (int)n, c, counts, perm, seg_begin, seg_len,
+                                             seg_first, nseg);
+}
+
+template <typename T>
+void launch_group_partial(bool with_d, const T* A, int64_t lda, const T* S, int64_t lds,
+                          const T* Th, int64_t ldt, T inv_rho, int64_t d, int64_t n, int c,
+                          const int32_t* perm, const int32_t* seg_begin, const int32_t* seg_len,
+                          const int32_t* nseg, double* partial, hipStream_t st) {
+    const dim3 grid(max_segments(n, c), row_blocks(d));
+    int v = with_d ? pick_vec<T>(d, {{A, lda}, {S, lds}, {Th, ldt}}) : pick_vec<T>(d, {{A, lda}});
+    constexpr int VV = 16 / sizeof(T);
+    if (with_d) {
+        if (v == VV)
+            k_group_partial<T, VV, true><<<grid, kBlock, 0, st>>>(A, lda, S, lds, Th, ldt, inv_rho, d,
+                                                                  perm, seg_begin, seg_len, nseg, partial);
+        else
+            k_group_partial<T, 1, true><<<grid, kBlock, 0, st>>>(A, lda, S, lds, Th, ldt, inv_rho, d,
+                                                                 perm, seg_begin, seg_len, nseg, partial);
+    } else {
+        if (v == VV)
+            k_group_partial<T, VV, false><<<grid, kBlock, 0, st>>>(A, lda, A, lda, A, lda, inv_rho, d,
+                                                                   perm, seg_begin, seg_len, nseg, partial);
+        else
+            k_group_partial<T, 1, false><<<grid, kBlock, 0, st>>>(A, lda, A, lda, A, lda, inv_rho, d,
+                                                                  perm, seg_begin, seg_len, nseg, partial);
+    }
+}
+
+template <typename T>
+void launch_group_finalize(const double* partial, int64_t d, int c, const int32_t* counts,
+                           const int32_t* seg_first, T* C, hipStream_t st) {
+    k_group_finalize<T><<<dim3((unsigned)((d + kBlock - 1) / kBlock), c), kBlock, 0, st>>>(
+        partial, d, counts, seg_first, C);
+}
+
+template <typename T>
+void launch_col_sqnorm(const T* C, int64_t d, int c, double* out, hipStream_t st) {
+    k_col_sqnorm<T><<<c, kBlock, 0, st>>>(C, d, out);
+}
+
+static int sweep_cols(int64_t d, int64_t n) {
+    const int64_t nrb = row_blocks(d);
+    int64_t jc = (nrb * n) / 4096;
+    if (jc < 1) jc = 1;
+    if (jc > 64) jc = 64;
+    return (int)jc;
+}
+
+int sweep_partials(int64_t d, int64_t n) {
+    const int jc = sweep_cols(d, n);
+    return row_blocks(d) * (int)((n + jc - 1) / jc);
+}
+
+template <typename T>
+int launch_sweep(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th,
+                 int64_t ldt, const T* C, const int32_t* labels, int64_t d, int64_t n,
+                 double alpha, double beta, double rho, double inv_rho, double* norm_partial,
+                 hipStream_t st) {
+    const int jc = sweep_cols(d, n);
+    const dim3 grid((unsigned)((n + jc - 1) / jc), row_blocks(d));
+    constexpr int VV = 16 / sizeof(T);
+    const int v = pick_vec<T>(d, {{X, ldx}, {L, ldl}, {S, lds}, {Th, ldt}, {C, d}});
+    if (v == VV)
+        k_sweep<T, VV><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, d, n, jc,
+                                                (T)alpha, (T)beta, (T)rho, (T)inv_rho, norm_partial);
+    else
+        k_sweep<T, 1><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, d, n, jc,
+                                               (T)alpha, (T)beta, (T)rho, (T)inv_rho, norm_partial);
+    return (int)(grid.x * grid.y);
+}
+
+template <typename T>
+void launch_dots(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t n, T* part,
+                 hipStream_t st) {
+    const unsigned gx = (unsigned)((n + 63) / 64), gz = (unsigned)row_blocks(d);
+    if (c <= 32)
+        k_dots<T, 2><<<dim3(gx, (c + 31) / 32, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, part);
+    else if (c <= 64)
+        k_dots<T, 4><<<dim3(gx, (c + 63) / 64, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, part);
+    else
+        k_dots<T, 8><<<dim3(gx, (c + 127) / 128, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, part);
+}
+
+template <typename T>
+int launch_argmin(const T* part, int nrb, int c, int64_t n, const double* cnorm,
+                  const int32_t* old_labels, int32_t* new_labels, double* changed_partial,
+                  hipStream_t st) {
+    const int g = (int)((n + kBlock - 1) / kBlock);
+    k_argmin<T><<<g, kBlock, 0, st>>>(part, nrb, c, n, cnorm, old_labels, new_labels,
+                                      changed_partial);
+    return g;
+}
+
+template <typename T>
+void launch_d2(const T* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* seeds, int m,
+               double* d2, hipStream_t st) {
+    const int per = kBlock / 64;
+    k_d2<T><<<(unsigned)((n + per - 1) / per), kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2);
+}
+
+void launch_pick(const double* d2, int64_t n, const double* u, int m, int32_t* seeds,
+                 int32_t* chosen, hipStream_t st) {
+    k_pick<<<1, kPickThreads, 0, st>>>(d2, n, u, m, seeds, chosen);
+}
+
+template <typename T>
+void launch_gather_cols(const T* Y, int64_t ldy, int64_t d, const int32_t* idx, int c, T* C,
+                        hipStream_t st) {
+    k_gather_cols<T><<<dim3((unsigned)((d + kBlock - 1) / kBlock), c), kBlock, 0, st>>>(Y, ldy, d,
+                                                                                          idx, C);
+}
+
+// ------------------------------------------------------ instantiations
+
+#define RESPCA_INSTANTIATE(T)                                                                      \
+    template void launch_zero2d<T>(T*, int64_t, int64_t, int64_t, hipStream_t);                    \
+    template int launch_sumsq<T>(const T*, int64_t, int64_t, int64_t, double*, hipStream_t);       \
+    template void launch_group_partial<T>(bool, const T*, int64_t, const T*, int64_t, const T*,     \
+                                          int64_t, T, int64_t, int64_t, int, const int32_t*,       \
+                                          const int32_t*, const int32_t*, const int32_t*, double*, \
+                                          hipStream_t);                                            \
+    template void launch_group_finalize<T>(const double*, int64_t, int, const int32_t*,            \
+                                           const int32_t*, T*, hipStream_t);                       \
+    template void launch_col_sqnorm<T>(const T*, int64_t, int, double*, hipStream_t);              \
+    template int launch_sweep<T>(const T*, int64_t, T*, int64_t, T*, int64_t, T*, int64_t,        \
+                                 const T*, const int32_t*, int64_t, int64_t, double, double,       \
+                                 double, double, double*, hipStream_t);                            \
+    template void launch_dots<T>(const T*, int64_t, int, const T*, int64_t, int64_t, T*,           \
+                                 hipStream_t);                                                     \
+    template int launch_argmin<T>(const T*, int, int, int64_t, const double*, const int32_t*,     \
+                                  int32_t*, double*, hipStream_t);                                 \
+    template void launch_d2<T>(const T*, int64_t, int64_t, int64_t, const int32_t*, int, double*, \
+                               hipStream_t);                                                       \
+    template void launch_gather_cols<T>(const T*, int64_t, int64_t, const int32_t*, int, T*,      \
+                                        hipStream_t);
+
+RESPCA_INSTANTIATE(float)
+RESPCA_INSTANTIATE(double)
+
+}  // namespace respca

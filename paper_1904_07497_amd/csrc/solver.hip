@@ -1,0 +1,601 @@
+// Host runtime and C ABI of librespca: handle/workspace management, argument
+// checks, and the RES-PCA driver loop (initial K-means, then outer ALM
+// iterations L -> p -> S -> Theta/rho until the Sec. 5 criterion holds).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/respca.h"
+#include "kernels.h"
+
+using namespace respca;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct respca_handle_s {
+    int device = 0;
+    std::string err;
+    DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, pmeans, dots, cnorm, lab_a, lab_b, d2,
+        chosen, seeds, u, normp, chgp, status;
+    double* hstage = nullptr;  // pinned host staging (status readback, uniforms)
+    size_t hstage_bytes = 0;
+};
+
+namespace {
+
+const char* kVersion = "librespca 0.1 (gfx950)";
+
+struct HipFail {
+    respca_status code;
+};
+
+#define CK(expr)                                                                            \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            h->err = std::string(#expr) + ": " + hipGetErrorString(e_);                     \
+            return e_ == hipErrorOutOfMemory ? RESPCA_ERR_NOMEM : RESPCA_ERR_HIP;           \
+        }                                                                                   \
+    } while (0)
+
+#define CKS(expr)                                    \
+    do {                                             \
+        respca_status s_ = (expr);                   \
+        if (s_ < 0) return s_;                       \
+    } while (0)
+
+respca_status ensure(respca_handle h, DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return RESPCA_OK;
+    if (b.p) CK(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    CK(hipMalloc(&b.p, bytes));
+    b.bytes = bytes;
+    return RESPCA_OK;
+}
+
+respca_status ensure_host(respca_handle h, size_t bytes) {
+    if (h->hstage_bytes >= bytes) return RESPCA_OK;
+    if (h->hstage) CK(hipHostFree(h->hstage));
+    h->hstage = nullptr;
+    h->hstage_bytes = 0;
+    CK(hipHostMalloc((void**)&h->hstage, bytes, hipHostMallocDefault));
+    h->hstage_bytes = bytes;
+    return RESPCA_OK;
+}
+
+respca_status fail(respca_handle h, respca_status s, const std::string& msg) {
+    if (h) h->err = msg;
+    return s;
+}
+
+uint64_t splitmix64_next(uint64_t& state) {
+    uint64_t z = (state += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t& state) { return (double)(splitmix64_next(state) >> 11) * 0x1.0p-53; }
+
+// Parameters after defaults are applied.
+struct Resolved {
+    double lambda, tol, rho0, kappa, rho_max;
+    int c, max_iter, max_lloyd, precision;
+    uint64_t seed;
+    const int32_t* init_labels;
+    double* history;
+};
+
+respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_t n, Resolved& r) {
+    if (!p) return fail(h, RESPCA_ERR_INVALID, "params is NULL");
+    if (d < 1 || n < 1 || d >= (int64_t)INT32_MAX || n >= (int64_t)INT32_MAX)
+        return fail(h, RESPCA_ERR_INVALID, "d and n must be in [1, 2^31)");
+    r.lambda = std::isnan(p->lambda) ? std::sqrt((double)(d > n ? d : n)) : p->lambda;
+    r.c = p->rank == 0 ? 5 : p->rank;
+    r.tol = p->tol;
+    r.max_iter = p->max_iter;
+    r.rho0 = p->rho0;
+    r.kappa = p->kappa;
+    r.rho_max = p->rho_max;
+    r.max_lloyd = p->max_lloyd;
+    r.precision = p->precision;
+    r.seed = p->seed;
+    r.init_labels = p->init_labels;
+    r.history = p->history;
+    if (!(r.lambda >= 0.0) || !std::isfinite(2.0 * r.lambda))
+        return fail(h, RESPCA_ERR_INVALID, "lambda must be finite and >= 0");
+    if (r.c < 1 || (int64_t)r.c > n) return fail(h, RESPCA_ERR_INVALID, "rank must be in [1, n]");
+    if (r.c > kMaxGroups) return fail(h, RESPCA_ERR_UNSUPPORTED, "rank above 1024 is not supported");
+    if (!(r.tol >= 0.0)) return fail(h, RESPCA_ERR_INVALID, "tol must be >= 0");
+    if (r.max_iter < 1) return fail(h, RESPCA_ERR_INVALID, "max_iter must be >= 1");
+    if (!(r.rho0 > 0.0) || !std::isfinite(r.rho0)) return fail(h, RESPCA_ERR_INVALID, "rho0 must be > 0");
+    if (!(r.kappa > 1.0) || !std::isfinite(r.kappa)) return fail(h, RESPCA_ERR_INVALID, "kappa must be > 1");
+    if (!(r.rho_max >= r.rho0)) return fail(h, RESPCA_ERR_INVALID, "rho_max must be >= rho0");
+    if (r.max_lloyd < 1) return fail(h, RESPCA_ERR_INVALID, "max_lloyd must be >= 1");
+    if (r.precision != RESPCA_F64 && r.precision != RESPCA_F32 && r.precision != RESPCA_BF16GEMM_F32)
+        return fail(h, RESPCA_ERR_INVALID, "unknown precision");
+    if (r.precision == RESPCA_BF16GEMM_F32)
+        return fail(h, RESPCA_ERR_UNSUPPORTED, "bf16 distance path not built");
+    return RESPCA_OK;
+}
+
+struct Span {
+    uintptr_t lo, hi;
+};
+
+Span span_of(const void* p, int64_t ld, int64_t d, int64_t n, size_t w) {
+    uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    return {lo, lo + (uintptr_t)((ld * (n - 1) + d) * (int64_t)w)};
+}
+
+bool overlap(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
+
+// ------------------------------------------------------------------- engine
+
+template <typename T>
+struct Engine {
+    respca_handle h;
+    hipStream_t st;
+    int64_t d, n;
+    int c;
+    int nrb;
+    double* status;  // device: [0..2] norms^2, [3] changed count
+
+    respca_status setup() {
+        nrb = row_blocks(d);
+        const size_t segs = (size_t)max_segments(n, c);
+        CKS(ensure(h, h->perm, n * sizeof(int32_t)));
+        CKS(ensure(h, h->counts, c * sizeof(int32_t)));
+        CKS(ensure(h, h->segb, segs * sizeof(int32_t)));
+        CKS(ensure(h, h->segl, segs * sizeof(int32_t)));
+        CKS(ensure(h, h->segf, (c + 1) * sizeof(int32_t)));
+        CKS(ensure(h, h->nseg, sizeof(int32_t)));
+        CKS(ensure(h, h->pmeans, segs * d * sizeof(double)));
+        CKS(ensure(h, h->dots, (size_t)nrb * c * n * sizeof(T)));
+        CKS(ensure(h, h->cnorm, c * sizeof(double)));
+        CKS(ensure(h, h->lab_a, n * sizeof(int32_t)));
+        CKS(ensure(h, h->lab_b, n * sizeof(int32_t)));
+        const size_t np = (size_t)sweep_partials(d, n);
+        size_t nsum = (size_t)nrb * (size_t)((n + 15) / 16);
+        CKS(ensure(h, h->normp, 3 * (np > nsum ? np : nsum) * sizeof(double)));
+        CKS(ensure(h, h->chgp, ((n + kBlock - 1) / kBlock) * sizeof(double)));
+        CKS(ensure(h, h->status, 8 * sizeof(double)));
+        CKS(ensure_host(h, (16 + 2 * (size_t)c) * sizeof(double)));
+        status = (double*)h->status.p;
+        return RESPCA_OK;
+    }
+
+    int32_t* perm() { return (int32_t*)h->perm.p; }
+    int32_t* counts() { return (int32_t*)h->counts.p; }
+
+    respca_status readback(double out[4]) {
+        CK(hipGetLastError());
+        CK(hipMemcpyAsync(h->hstage, status, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (int i = 0; i < 4; ++i) out[i] = h->hstage[i];
+        return RESPCA_OK;
+    }
+
+    respca_status sumsq(const T* X, int64_t ldx, double& out) {
+        const int np = launch_sumsq<T>(X, ldx, d, n, (double*)h->normp.p, st);
+        launch_sum_partials((double*)h->normp.p, np, 1, status, st);
+        double s[4];
+        CKS(readback(s));
+        out = s[0];
+        return RESPCA_OK;
+    }
+
+    void sort(const int32_t* labels) {
+        launch_label_sort(labels, n, c, counts(), perm(), (int32_t*)h->segb.p, (int32_t*)h->segl.p,
+                          (int32_t*)h->segf.p, (int32_t*)h->nseg.p, st);
+    }
+
+    // C[:, k] <- mean over group k of Y (Y = X - S + Theta*inv_rho when with_d),
+    // for the groups of the last sort; empty groups keep C[:, k].
+    void group_means(bool with_d, const T* A, int64_t lda, const T* S, int64_t lds, const T* Th,
+                     int64_t ldt, T inv_rho, T* C) {
+        launch_group_partial<T>(with_d, A, lda, S, lds, Th, ldt, inv_rho, d, n, c, perm(),
+                                (const int32_t*)h->segb.p, (const int32_t*)h->segl.p,
+                                (const int32_t*)h->nseg.p, (double*)h->pmeans.p, st);
+        launch_group_finalize<T>((const double*)h->pmeans.p, d, c, counts(),
+                                 (const int32_t*)h->segf.p, C, st);
+    }
+
+    // Assignment pass: new = nearest centroid of every column of Y; status[3] = #changed.
+    void assign(const T* Y, int64_t ldy, const T* C, const int32_t* old, int32_t* neu) {
+        launch_col_sqnorm<T>(C, d, c, (double*)h->cnorm.p, st);
+        launch_dots<T>(C, d, c, Y, ldy, n, (T*)h->dots.p, st);
+        const int g = launch_argmin<T>((const T*)h->dots.p, nrb, c, n, (const double*)h->cnorm.p, old,
+                                       neu, (double*)h->chgp.p, st);
+        launch_sum_partials((const double*)h->chgp.p, g, 1, status + 3, st);
+    }
+
+    // Lloyd passes on the columns of Y from (cur, C); see oracle_lloyd for the
+    // exact rule.  `first` receives the status of the first pass.
+    respca_status lloyd(const T* Y, int64_t ldy, T* C, int32_t*& cur, int32_t*& alt, int max_lloyd,
+                        int& steps, double first[4]) {
+        steps = 0;
+        while (steps < max_lloyd) {
+            assign(Y, ldy, C, cur, alt);
+            double s[4];
+            CKS(readback(s));
+            if (steps == 0 && first) std::memcpy(first, s, sizeof(s));
+            ++steps;
+            if (s[3] == 0.0) break;
+            std::swap(cur, alt);
+            sort(cur);
+            group_means(false, Y, ldy, nullptr, 0, nullptr, 0, T(0), C);
+        }
+        return RESPCA_OK;
+    }
+
+    // K-means of the columns of Y: k-means++ seeds, nearest-seed groups, their
+    // means (empty groups keep the seed), then Lloyd.
+    respca_status kmeans(const T* Y, int64_t ldy, uint64_t seed, int max_lloyd, T* C,
+                         int32_t*& cur, int32_t*& alt, int& steps) {
+        CKS(ensure(h, h->d2, n * sizeof(double)));
+        CKS(ensure(h, h->chosen, n * sizeof(int32_t)));
+        CKS(ensure(h, h->seeds, c * sizeof(int32_t)));
+        CKS(ensure(h, h->u, c * sizeof(double)));
+        uint64_t state = seed;
+        double* hu = h->hstage + 8;
+        for (int m = 0; m < c; ++m) hu[m] = uniform01(state);
+        int64_t s0 = (int64_t)std::floor(hu[0] * (double)n);
+        if (s0 >= n) s0 = n - 1;
+        int32_t* seeds = (int32_t*)h->seeds.p;
+        int32_t* chosen = (int32_t*)h->chosen.p;
+        int32_t* hi = (int32_t*)(h->hstage + 4);
+        hi[0] = (int32_t)s0;
+        hi[1] = 1;
+        CK(hipMemcpyAsync(h->u.p, hu, c * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_zero_i32(chosen, n, st);
+        CK(hipMemcpyAsync(seeds, &hi[0], sizeof(int32_t), hipMemcpyHostToDevice, st));
+        CK(hipMemcpyAsync(chosen + s0, &hi[1], sizeof(int32_t), hipMemcpyHostToDevice, st));
+        launch_d2<T>(Y, ldy, d, n, seeds, 0, (double*)h->d2.p, st);
+        for (int m = 1; m < c; ++m) {
+            launch_pick((const double*)h->d2.p, n, (const double*)h->u.p, m, seeds, chosen, st);
+            launch_d2<T>(Y, ldy, d, n, seeds, m, (double*)h->d2.p, st);
+        }
+        launch_gather_cols<T>(Y, ldy, d, seeds, c, C, st);
+        launch_zero_i32(cur, n, st);
+        assign(Y, ldy, C, cur, alt);
+        std::swap(cur, alt);
+        sort(cur);
+        group_means(false, Y, ldy, nullptr, 0, nullptr, 0, T(0), C);
+        CKS(lloyd(Y, ldy, C, cur, alt, max_lloyd, steps, nullptr));  // also waits for the pinned stage
+        return RESPCA_OK;
+    }
+
+    // One outer iteration; norms receives the three Frobenius norms.
+    respca_status iterate_once(const Resolved& r, const T* X, int64_t ldx, T* L, int64_t ldl, T* S,
+                               int64_t lds, T* Th, int64_t ldt, T* C, int32_t*& cur, int32_t*& alt,
+                               double rho, double norms[3], int& steps) {
+        const double alpha = rho / (2.0 * r.lambda + rho);
+        const double beta = (2.0 * r.lambda) / (2.0 * r.lambda + rho);
+        const double inv = 1.0 / rho;
+        sort(cur);                                                   // Sec. 4.1: groups of D
+        group_means(true, X, ldx, S, lds, Th, ldt, (T)inv, C);
+        const int np = launch_sweep<T>(X, ldx, L, ldl, S, lds, Th, ldt, C, cur, d, n, alpha, beta,
+                                       rho, inv, (double*)h->normp.p, st);
+        launch_sum_partials((const double*)h->normp.p, np, 3, status, st);
+        double first[4];
+        CKS(lloyd(L, ldl, C, cur, alt, r.max_lloyd, steps, first));  // Sec. 4.2
+        for (int i = 0; i < 3; ++i) norms[i] = std::sqrt(first[i]);
+        return RESPCA_OK;
+    }
+};
+
+template <typename T>
+respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, const T* X,
+                      int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, int32_t* labels,
+                      respca_info* info, hipStream_t st) {
+    Engine<T> e{h, st, d, n, r.c};
+    CKS(e.setup());
+    CKS(ensure(h, h->theta, (size_t)d * n * sizeof(T)));
+    CKS(ensure(h, h->cbuf, (size_t)d * r.c * sizeof(T)));
+    T* Th = (T*)h->theta.p;
+    T* C = (T*)h->cbuf.p;
+    int32_t* cur = (int32_t*)h->lab_a.p;
+    int32_t* alt = (int32_t*)h->lab_b.p;
+
+    double nx2 = 0.0;
+    CKS(e.sumsq(X, ldx, nx2));
+    if (!std::isfinite(nx2)) return fail(h, RESPCA_ERR_NONFINITE, "X contains NaN or Inf");
+    launch_zero2d<T>(L, ldl, d, n, st);
+    launch_zero2d<T>(S, lds, d, n, st);
+    launch_zero2d<T>(Th, d, d, n, st);
+    if (nx2 == 0.0) {
+        if (labels) launch_zero_i32(labels, n, st);
+        CK(hipStreamSynchronize(st));
+        info->status = RESPCA_OK;
+        return RESPCA_OK;
+    }
+    const double nX = std::sqrt(nx2);
+
+    if (r.init_labels) {
+        std::vector<int32_t> hl(n);
+        CK(hipMemcpyAsync(hl.data(), r.init_labels, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (int64_t j = 0; j < n; ++j)
+            if (hl[j] < 0 || hl[j] >= r.c) return fail(h, RESPCA_ERR_INVALID, "init_labels out of range");
+        CK(hipMemcpyAsync(cur, r.init_labels, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        launch_zero2d<T>(C, d, d, r.c, st);
+        e.sort(cur);
+        e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C);
+    } else {
+        int steps = 0;
+        CKS(e.kmeans(X, ldx, r.seed, r.max_lloyd, C, cur, alt, steps));
+        info->init_lloyd = steps;
+    }
+
+    double rho = r.rho0;
+    info->status = RESPCA_NOT_CONVERGED;
+    for (int t = 1; t <= r.max_iter; ++t) {
+        double norms[3];
+        int steps = 0;
+        CKS(e.iterate_once(r, X, ldx, L, ldl, S, lds, Th, d, C, cur, alt, rho, norms, steps));
+        info->lloyd_steps += steps;
+        info->iters = t;
+        info->rho_final = rho;
+        info->primal = norms[0] / nX;
+        info->dL = norms[1] / nX;
+        info->dS = norms[2] / nX;
+        if (r.history) {
+            r.history[3 * (t - 1) + 0] = info->primal;
+            r.history[3 * (t - 1) + 1] = info->dL;
+            r.history[3 * (t - 1) + 2] = info->dS;
+        }
+        const double next = r.kappa * rho;
+        rho = next < r.rho_max ? next : r.rho_max;
+        const double crit = std::fmax(info->primal, std::fmax(info->dL, info->dS));
+        if (crit <= r.tol) {
+            info->status = RESPCA_OK;
+            break;
+        }
+    }
+    if (labels) CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    CK(hipStreamSynchronize(st));
+    return (respca_status)info->status;
+}
+
+template <typename T>
+respca_status iterate_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, const T* X,
+                        int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th, int64_t ldt,
+                        int32_t* labels, T* C, double* rho, int iters, double* norms_out,
+                        respca_info* info, hipStream_t st) {
+    Engine<T> e{h, st, d, n, r.c};
+    CKS(e.setup());
+    int32_t* cur = (int32_t*)h->lab_a.p;
+    int32_t* alt = (int32_t*)h->lab_b.p;
+    {
+        std::vector<int32_t> hl(n);
+        CK(hipMemcpyAsync(hl.data(), labels, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (int64_t j = 0; j < n; ++j)
+            if (hl[j] < 0 || hl[j] >= r.c) return fail(h, RESPCA_ERR_INVALID, "labels out of range");
+    }
+    CK(hipMemcpyAsync(cur, labels, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    double rr = *rho;
+    for (int t = 0; t < iters; ++t) {
+        double norms[3];
+        int steps = 0;
+        CKS(e.iterate_once(r, X, ldx, L, ldl, S, lds, Th, ldt, C, cur, alt, rr, norms, steps));
+        info->lloyd_steps += steps;
+        info->iters = t + 1;
+        info->rho_final = rr;
+        if (norms_out) std::memcpy(norms_out + 3 * t, norms, sizeof(norms));
+        const double next = r.kappa * rr;
+        rr = next < r.rho_max ? next : r.rho_max;
+    }
+    *rho = rr;
+    CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    CK(hipStreamSynchronize(st));
+    info->status = RESPCA_OK;
+    return RESPCA_OK;
+}
+
+template <typename T>
+respca_status kmeans_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, const T* Y,
+                       int64_t ldy, int32_t* labels, T* C, respca_info* info, hipStream_t st) {
+    Engine<T> e{h, st, d, n, r.c};
+    CKS(e.setup());
+    int32_t* cur = (int32_t*)h->lab_a.p;
+    int32_t* alt = (int32_t*)h->lab_b.p;
+    int steps = 0;
+    CKS(e.kmeans(Y, ldy, r.seed, r.max_lloyd, C, cur, alt, steps));
+    info->init_lloyd = steps;
+    CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    CK(hipStreamSynchronize(st));
+    info->status = RESPCA_OK;
+    return RESPCA_OK;
+}
+
+respca_status bind_device(respca_handle h) {
+    CK(hipSetDevice(h->device));
+    return RESPCA_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+respca_status respca_create(respca_handle* out, int32_t device) {
+    if (!out) return RESPCA_ERR_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return RESPCA_ERR_HIP;
+    auto* h = new (std::nothrow) respca_handle_s();
+    if (!h) return RESPCA_ERR_NOMEM;
+    h->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete h;
+        return RESPCA_ERR_HIP;
+    }
+    *out = h;
+    return RESPCA_OK;
+}
+
+void respca_destroy(respca_handle h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
+                      &h->nseg, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b, &h->d2,
+                      &h->chosen, &h->seeds, &h->u, &h->normp, &h->chgp, &h->status};
+    for (DevBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (h->hstage) (void)hipHostFree(h->hstage);
+    delete h;
+}
+
+void respca_params_default(respca_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->lambda = NAN;
+    p->rank = 0;
+    p->tol = 1e-3;
+    p->max_iter = 500;
+    p->rho0 = 1e-4;
+    p->kappa = 1.5;
+    p->rho_max = 1e10;
+    p->max_lloyd = 100;
+    p->seed = 0;
+    p->precision = RESPCA_F32;
+    p->init_labels = nullptr;
+    p->history = nullptr;
+}
+
+const char* respca_status_string(respca_status s) {
+    switch (s) {
+        case RESPCA_OK: return "RESPCA_OK";
+        case RESPCA_NOT_CONVERGED: return "RESPCA_NOT_CONVERGED";
+        case RESPCA_ERR_INVALID: return "RESPCA_ERR_INVALID";
+        case RESPCA_ERR_NONFINITE: return "RESPCA_ERR_NONFINITE";
+        case RESPCA_ERR_NOMEM: return "RESPCA_ERR_NOMEM";
+        case RESPCA_ERR_HIP: return "RESPCA_ERR_HIP";
+        case RESPCA_ERR_UNSUPPORTED: return "RESPCA_ERR_UNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+const char* respca_last_error(respca_handle h) { return h ? h->err.c_str() : "NULL handle"; }
+
+const char* respca_version(void) { return kVersion; }
+
+respca_status respca_solve(respca_handle h, const respca_params* params, int64_t d, int64_t n,
+                           const void* X, int64_t ldx, void* L, int64_t ldl, void* S, int64_t lds,
+                           int32_t* labels, respca_info* info, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    respca_info local{};
+    respca_info* out = info ? info : &local;
+    std::memset(out, 0, sizeof(*out));
+    Resolved r;
+    respca_status s = resolve(h, params, d, n, r);
+    if (s == RESPCA_OK) {
+        const size_t w = r.precision == RESPCA_F64 ? 8 : 4;
+        if (!X || !L || !S) s = fail(h, RESPCA_ERR_INVALID, "X, L and S must be non-NULL");
+        else if (ldx < d || ldl < d || lds < d) s = fail(h, RESPCA_ERR_INVALID, "leading dimension < d");
+        else {
+            Span sx = span_of(X, ldx, d, n, w), sl = span_of(L, ldl, d, n, w), ss = span_of(S, lds, d, n, w);
+            if (overlap(sx, sl) || overlap(sx, ss) || overlap(sl, ss))
+                s = fail(h, RESPCA_ERR_INVALID, "X, L and S must not overlap");
+        }
+    }
+    if (s == RESPCA_OK) s = bind_device(h);
+    if (s == RESPCA_OK) {
+        hipStream_t st = (hipStream_t)stream;
+        if (r.precision == RESPCA_F64)
+            s = solve_t<double>(h, r, d, n, (const double*)X, ldx, (double*)L, ldl, (double*)S, lds,
+                                labels, out, st);
+        else
+            s = solve_t<float>(h, r, d, n, (const float*)X, ldx, (float*)L, ldl, (float*)S, lds,
+                               labels, out, st);
+    }
+    out->status = s;
+    return s;
+}
+
+respca_status respca_iterate(respca_handle h, const respca_params* params, int64_t d, int64_t n,
+                             const void* X, int64_t ldx, void* L, int64_t ldl, void* S, int64_t lds,
+                             void* Theta, int64_t ldt, int32_t* labels, void* C, double* rho,
+                             int32_t iters, double* norms, respca_info* info, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    respca_info local{};
+    respca_info* out = info ? info : &local;
+    std::memset(out, 0, sizeof(*out));
+    Resolved r;
+    respca_status s = resolve(h, params, d, n, r);
+    if (s == RESPCA_OK) {
+        const size_t w = r.precision == RESPCA_F64 ? 8 : 4;
+        if (!X || !L || !S || !Theta || !labels || !C || !rho)
+            s = fail(h, RESPCA_ERR_INVALID, "NULL argument");
+        else if (ldx < d || ldl < d || lds < d || ldt < d)
+            s = fail(h, RESPCA_ERR_INVALID, "leading dimension < d");
+        else if (iters < 0)
+            s = fail(h, RESPCA_ERR_INVALID, "iters must be >= 0");
+        else if (!(*rho > 0.0) || !std::isfinite(*rho))
+            s = fail(h, RESPCA_ERR_INVALID, "rho must be > 0");
+        else {
+            Span sx = span_of(X, ldx, d, n, w), sl = span_of(L, ldl, d, n, w),
+                 ss = span_of(S, lds, d, n, w), sth = span_of(Theta, ldt, d, n, w);
+            if (overlap(sx, sl) || overlap(sx, ss) || overlap(sl, ss) || overlap(sth, sx) ||
+                overlap(sth, sl) || overlap(sth, ss))
+                s = fail(h, RESPCA_ERR_INVALID, "X, L, S and Theta must not overlap");
+        }
+    }
+    if (s == RESPCA_OK) s = bind_device(h);
+    if (s == RESPCA_OK) {
+        hipStream_t st = (hipStream_t)stream;
+        if (r.precision == RESPCA_F64)
+            s = iterate_t<double>(h, r, d, n, (const double*)X, ldx, (double*)L, ldl, (double*)S, lds,
+                                  (double*)Theta, ldt, labels, (double*)C, rho, iters, norms, out, st);
+        else
+            s = iterate_t<float>(h, r, d, n, (const float*)X, ldx, (float*)L, ldl, (float*)S, lds,
+                                 (float*)Theta, ldt, labels, (float*)C, rho, iters, norms, out, st);
+    }
+    out->status = s;
+    return s;
+}
+
+respca_status respca_kmeans(respca_handle h, const respca_params* params, int64_t d, int64_t n,
+                            const void* Y, int64_t ldy, int32_t* labels, void* C,
+                            respca_info* info, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    respca_info local{};
+    respca_info* out = info ? info : &local;
+    std::memset(out, 0, sizeof(*out));
+    Resolved r;
+    respca_status s = resolve(h, params, d, n, r);
+    if (s == RESPCA_OK) {
+        if (!Y || !labels || !C) s = fail(h, RESPCA_ERR_INVALID, "NULL argument");
+        else if (ldy < d) s = fail(h, RESPCA_ERR_INVALID, "leading dimension < d");
+    }
+    if (s == RESPCA_OK) s = bind_device(h);
+    if (s == RESPCA_OK) {
+        hipStream_t st = (hipStream_t)stream;
+        if (r.precision == RESPCA_F64)
+            s = kmeans_t<double>(h, r, d, n, (const double*)Y, ldy, labels, (double*)C, out, st);
+        else
+            s = kmeans_t<float>(h, r, d, n, (const float*)Y, ldy, labels, (float*)C, out, st);
+    }
+    out->status = s;
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+"""Thin ctypes binding of librespca (include/respca.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  torch supplies device memory and streams.  A (d, n) column-major
+matrix is a torch tensor of shape (d, n) whose stride is (1, ld) with ld >= d,
+e.g. ``t.T`` for a contiguous (n, d) tensor ``t``.
+
+The library must be built (``paper_1904_07497_amd.build``); there is no
+fallback, so a missing or unloadable library raises at once.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librespca.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_INVALID, ERR_NONFINITE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
+F64, F32, BF16GEMM_F32 = 0, 1, 2
+
+# Every symbol include/respca.h declares.
+EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_status_string",
+           "respca_last_error", "respca_version", "respca_solve", "respca_iterate",
+           "respca_kmeans")
+
+
+class Params(ct.Structure):
+    _fields_ = [("lam", ct.c_double), ("rank", ct.c_int32), ("tol", ct.c_double),
+                ("max_iter", ct.c_int32), ("rho0", ct.c_double), ("kappa", ct.c_double),
+                ("rho_max", ct.c_double), ("max_lloyd", ct.c_int32), ("seed", ct.c_uint64),
+                ("precision", ct.c_int32), ("init_labels", ct.c_void_p),
+                ("history", ct.POINTER(ct.c_double))]
+
+
+class Info(ct.Structure):
+    _fields_ = [("iters", ct.c_int32), ("lloyd_steps", ct.c_int32), ("init_lloyd", ct.c_int32),
+                ("status", ct.c_int32), ("primal", ct.c_double), ("dL", ct.c_double),
+                ("dS", ct.c_double), ("rho_final", ct.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RespcaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load librespca.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1904_07497_amd.build")
+        L = ct.CDLL(LIB_PATH)
+        vp, i64, i32 = ct.c_void_p, ct.c_int64, ct.c_int32
+        L.respca_create.restype = i32
+        L.respca_create.argtypes = [ct.POINTER(vp), i32]
+        L.respca_destroy.restype = None
+        L.respca_destroy.argtypes = [vp]
+        L.respca_params_default.restype = None
+        L.respca_params_default.argtypes = [ct.POINTER(Params)]
+        L.respca_status_string.restype = ct.c_char_p
+        L.respca_status_string.argtypes = [i32]
+        L.respca_last_error.restype = ct.c_char_p
+        L.respca_last_error.argtypes = [vp]
+        L.respca_version.restype = ct.c_char_p
+        L.respca_version.argtypes = []
+        L.respca_solve.restype = i32
+        L.respca_solve.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, i64, vp, i64,
+                                   vp, ct.POINTER(Info), vp]
+        L.respca_iterate.restype = i32
+        L.respca_iterate.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, i64, vp, i64,
+                                     vp, i64, vp, vp, ct.POINTER(ct.c_double), i32,
+                                     ct.POINTER(ct.c_double), ct.POINTER(Info), vp]
+        L.respca_kmeans.restype = i32
+        L.respca_kmeans.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, vp,
+                                    ct.POINTER(Info), vp]
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().respca_status_string(int(s)).decode()
+
+
+def version() -> str:
+    return lib().respca_version().decode()
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().respca_params_default(ct.byref(p))
+    return p
+
+
+def make_params(rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
+                max_lloyd=100, seed=0, precision=F32) -> Params:
+    p = default_params()
+    p.lam = math.nan if lam is None else float(lam)
+    p.rank, p.tol, p.max_iter = int(rank), float(tol), int(max_iter)
+    p.rho0, p.kappa, p.rho_max = float(rho0), float(kappa), float(rho_max)
+    p.max_lloyd, p.seed, p.precision = int(max_lloyd), int(seed) & (2**64 - 1), int(precision)
+    return p
+
+
+# ------------------------------------------------------------------ handles
+
+class Handle:
+    """Owns a respca_handle (device workspace) for one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ct.c_void_p()
+        s = lib().respca_create(ct.byref(h), int(device))
+        if s != OK:
+            raise RespcaError(s, "respca_create failed")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().respca_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().respca_last_error(self._h).decode()
+
+    def check(self, s: int, allow=(OK, NOT_CONVERGED)):
+        if s not in allow:
+            raise RespcaError(s, self.last_error())
+        return s
+
+
+_handles: dict = {}
+
+
+def handle(device: int = 0) -> Handle:
+    if device not in _handles:
+        _handles[device] = Handle(device)
+    return _handles[device]
+
+
+# -------------------------------------------------------------- marshalling
+
+def _colmajor(t, name):
+    import torch
+    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < t.shape[0]:
+        raise ValueError(f"{name} must be a (d, n) column-major tensor (stride (1, ld), ld >= d)")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    return t.data_ptr(), int(t.stride(1)) if t.shape[1] > 1 else max(int(t.stride(1)), t.shape[0])
+
+
+def _dtype_precision(t, precision):
+    import torch
+    if precision is None:
+        precision = F64 if t.dtype == torch.float64 else F32
+    want = torch.float64 if precision == F64 else torch.float32
+    if t.dtype != want:
+        raise ValueError(f"precision {precision} needs {want}, got {t.dtype}")
+    return precision
+
+
+def empty_colmajor(d, n, dtype, device):
+    import torch
+    return torch.empty((n, d), dtype=dtype, device=device).T
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
+          max_lloyd=100, seed=0, precision=None, init_labels=None, history=False,
+          out=None, stream=None):
+    """RES-PCA of X (d x n column-major tensor).  Returns dict(L, S, labels, info[, history])."""
+    import torch
+    precision = _dtype_precision(X, precision)
+    d, n = X.shape
+    xp, ldx = _colmajor(X, "X")
+    if out is None:
+        L = empty_colmajor(d, n, X.dtype, X.device)
+        S = empty_colmajor(d, n, X.dtype, X.device)
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    else:
+        L, S, labels = out
+    lp, ldl = _colmajor(L, "L")
+    sp, lds = _colmajor(S, "S")
+    p = make_params(rank, lam, tol, max_iter, rho0, kappa, rho_max, max_lloyd, seed, precision)
+    hist = None
+    if history:
+        hist = (ct.c_double * (3 * max_iter))()
+        p.history = ct.cast(hist, ct.POINTER(ct.c_double))
+    il = None
+    if init_labels is not None:
+        il = init_labels.to(device=X.device, dtype=torch.int32).contiguous()
+        p.init_labels = il.data_ptr()
+    info = Info()
+    h = handle(X.device.index or 0)
+    s = lib().respca_solve(h._h, ct.byref(p), d, n, xp, ldx, lp, ldl, sp, lds, labels.data_ptr(),
+                           ct.byref(info), _stream(stream))
+    h.check(s)
+    res = {"L": L, "S": S, "labels": labels, "info": info.as_dict(), "status": s}
+    if hist is not None:
+        import numpy as np
+        res["history"] = np.ctypeslib.as_array(hist)[: 3 * info.iters].reshape(-1, 3).copy()
+    return res
+
+
+def iterate(X, state: dict, iters=1, rank=None, lam=None, max_lloyd=100, kappa=1.5, rho_max=1e10,
+            precision=None, stream=None):
+    """Run ``iters`` outer iterations in place on ``state`` (device tensors L, S,
+    Theta (d x n column-major), labels (int32[n]), C (d x c column-major, ld = d)
+    and float rho).  Returns (norms [iters x 3], info)."""
+    import numpy as np
+    precision = _dtype_precision(X, precision)
+    d, n = X.shape
+    C = state["C"]
+    c = C.shape[1] if rank is None else rank
+    if C.shape != (d, c) or C.stride(0) != 1 or (c > 1 and C.stride(1) != d):
+        raise ValueError("C must be a (d, c) column-major tensor with ld = d")
+    xp, ldx = _colmajor(X, "X")
+    lp, ldl = _colmajor(state["L"], "L")
+    sp, lds = _colmajor(state["S"], "S")
+    tp, ldt = _colmajor(state["Theta"], "Theta")
+    p = make_params(c, lam, 0.0, max(iters, 1), 1e-4, kappa, rho_max, max_lloyd, 0, precision)
+    rho = ct.c_double(float(state["rho"]))
+    norms = (ct.c_double * (3 * max(iters, 1)))()
+    info = Info()
+    h = handle(X.device.index or 0)
+    s = lib().respca_iterate(h._h, ct.byref(p), d, n, xp, ldx, lp, ldl, sp, lds, tp, ldt,
+                             state["labels"].data_ptr(), C.data_ptr(), ct.byref(rho), int(iters),
+                             ct.cast(norms, ct.POINTER(ct.c_double)), ct.byref(info),
+                             _stream(stream))
+    h.check(s)
+    state["rho"] = rho.value
+    return np.ctypeslib.as_array(norms)[: 3 * iters].reshape(-1, 3).copy(), info.as_dict()
+
+
+def kmeans(Y, rank, seed=0, max_lloyd=100, precision=None, stream=None):
+    """k-means++ + Lloyd on the columns of Y.  Returns (labels, C, info)."""
+    import torch
+    precision = _dtype_precision(Y, precision)
+    d, n = Y.shape
+    yp, ldy = _colmajor(Y, "Y")
+    labels = torch.empty(n, dtype=torch.int32, device=Y.device)
+    C = empty_colmajor(d, rank, Y.dtype, Y.device)
+    p = make_params(rank, 1.0, 1e-3, 1, 1e-4, 1.5, 1e10, max_lloyd, seed, precision)
+    info = Info()
+    h = handle(Y.device.index or 0)
+    s = lib().respca_kmeans(h._h, ct.byref(p), d, n, yp, ldy, labels.data_ptr(), C.data_ptr(),
+                            ct.byref(info), _stream(stream))
+    h.check(s)
+    return labels, C, info.as_dict()

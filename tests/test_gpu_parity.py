@@ -1,0 +1,314 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars (relative Frobenius error, denominator the oracle's norm or ||X||_F when
+that is zero): <= 1e-10 for FP64 runs, <= 1e-5 for FP32 runs.  Integer outputs
+(labels, iteration and Lloyd counts) must match exactly wherever the decision
+is well separated; the support of S must match on well-separated entries.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1904_07497_amd import respca as rp  # noqa: E402
+from paper_1904_07497_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL, F32_TOL = 1e-10, 1e-5
+
+
+def dev(a, dtype=None):
+    a = np.asfortranarray(a if dtype is None else np.asarray(a, dtype=dtype))
+    return torch.from_numpy(a).to("cuda")
+
+
+def host(t):
+    return np.asfortranarray(t.detach().cpu().numpy().astype(np.float64))
+
+
+def rel(a, b, scale_fallback):
+    den = np.linalg.norm(b)
+    if den == 0:
+        den = scale_fallback
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / den
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------------ K-means
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("shape", [(300, 500, 6), (1037, 211, 9), (5, 64, 3)])
+def test_kmeans_matches_oracle_on_grouped_data(dtype, shape):
+    d, n, c = shape
+    say(f"kmeans {dtype.__name__} {shape}")
+    X, _, _, g = synth.clustered(d, n, c, seed=d + n, sep=3.0, noise=0.5, frac=0.02, amp=5.0,
+                                 dtype=dtype)
+    prec = rp.F64 if dtype == np.float64 else rp.F32
+    for seed in (0, 7):
+        lab, C, info = rp.kmeans(dev(X), c, seed=seed, precision=prec)
+        ol, oC, osteps = oracle.kmeans(X, c, seed)
+        np.testing.assert_array_equal(lab.cpu().numpy(), ol)
+        assert info["init_lloyd"] == osteps
+        tol = F64_TOL if dtype == np.float64 else F32_TOL
+        assert rel(host(C), oC, 1.0) <= tol
+
+
+def test_kmeans_f64_unstructured_small_config():
+    X, _, _ = synth.config_small(0)
+    lab, C, info = rp.kmeans(dev(X), 25, seed=0, precision=rp.F64)
+    ol, oC, osteps = oracle.kmeans(X, 25, 0)
+    np.testing.assert_array_equal(lab.cpu().numpy(), ol)
+    assert info["init_lloyd"] == osteps
+    assert rel(host(C), oC, 1.0) <= F64_TOL
+
+
+# ------------------------------------------------------------ whole solves
+
+@pytest.mark.parametrize("lam", [1 / np.sqrt(500), np.sqrt(500)])
+def test_solve_f64_small_config(lam):
+    """500 x 500, rank 25, 5 % corruptions in [-50, 50], c = 25, tol 1e-7, FP64."""
+    X, _, _ = synth.config_small(0)
+    say(f"solve f64 500x500 lam={lam}")
+    g = rp.solve(dev(X), rank=25, lam=lam, tol=1e-7, seed=0, precision=rp.F64)
+    o = oracle.solve(X, oracle.make_params(25, lam=lam, tol=1e-7, seed=0))
+    gi, oi = g["info"], o["info"]
+    assert g["status"] == rp.OK and o["status"] == 0
+    assert (gi["iters"], gi["lloyd_steps"], gi["init_lloyd"]) == \
+        (oi["iters"], oi["lloyd_steps"], oi["init_lloyd"])
+    np.testing.assert_array_equal(g["labels"].cpu().numpy(), o["labels"])
+    nX = np.linalg.norm(X)
+    assert rel(host(g["L"]), o["L"], nX) <= F64_TOL
+    assert rel(host(g["S"]), o["S"], nX) <= F64_TOL
+    assert abs(gi["primal"] - oi["primal"]) <= 1e-9 * max(oi["primal"], 1e-12) + 1e-16
+
+
+@pytest.mark.parametrize("shape,lam", [((1037, 777, 5), None), ((2051, 300, 7), 0.3),
+                                       ((64, 1000, 4), None), ((4096, 130, 3), 2.0)])
+def test_solve_f32_grouped_iteration_locked(shape, lam):
+    """FP32 GPU vs FP64 oracle on data with the model's group structure, ragged
+    tails in both dimensions; both run exactly the iteration count the oracle
+    needs for tol 1e-6 (so a stop near the threshold cannot mask a mismatch)."""
+    d, n, c = shape
+    say(f"solve f32 {shape} lam={lam}")
+    X, _, _, _ = synth.clustered(d, n, c, seed=d * 3 + n, sep=4.0, noise=0.5, frac=0.05, amp=10.0,
+                                 dtype=np.float32)
+    lam = float(np.sqrt(max(d, n))) if lam is None else lam
+    o = oracle.solve(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=1))
+    T = o["info"]["iters"]
+    g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=T, seed=1)
+    assert g["status"] == rp.NOT_CONVERGED and g["info"]["iters"] == T
+    np.testing.assert_array_equal(g["labels"].cpu().numpy(), o["labels"])
+    nX = np.linalg.norm(X.astype(np.float64))
+    assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
+    assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+    # free-running: same stopping iteration
+    g2 = rp.solve(dev(X), rank=c, lam=lam, tol=1e-6, seed=1)
+    assert abs(g2["info"]["iters"] - T) <= 1
+
+
+def test_solve_f32_video_clip_matches_oracle_and_table2_counts():
+    """Synthetic 8-bit clip, lambda = sqrt(max(n, d)), tol 1e-3 (the Sec. 5.1
+    setting): the GPU stops at the oracle's iteration (23, as in Table 2)."""
+    X, _, _ = synth.video(n=200, h=48, w=64, seed=2, dtype=np.float32)
+    d, n = X.shape
+    lam = float(np.sqrt(max(d, n)))
+    for c in (1, 2):
+        o = oracle.solve(X, oracle.make_params(c, lam=lam, tol=1e-3))
+        g = rp.solve(dev(X), rank=c, lam=lam, tol=1e-3)
+        assert g["info"]["iters"] == o["info"]["iters"]
+        assert 23 <= g["info"]["iters"] <= 25
+        nX = np.linalg.norm(X.astype(np.float64))
+        assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
+        assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+
+
+def test_warm_start_labels_match_oracle_from_same_init():
+    X, _, _ = synth.config_small(1)
+    init = np.random.default_rng(3).integers(0, 25, 500).astype(np.int32)
+    g = rp.solve(dev(X), rank=25, lam=0.5, tol=1e-7, precision=rp.F64,
+                 init_labels=torch.from_numpy(init))
+    o = oracle.solve(X, oracle.make_params(25, lam=0.5, tol=1e-7), init_labels=init)
+    assert g["info"]["iters"] == o["info"]["iters"] and g["info"]["init_lloyd"] == 0
+    nX = np.linalg.norm(X)
+    assert rel(host(g["L"]), o["L"], nX) <= F64_TOL
+    assert rel(host(g["S"]), o["S"], nX) <= F64_TOL
+
+
+# -------------------------------------------------------- single iterations
+
+def _gpu_state(st, dtype):
+    return {"L": dev(st["L"], dtype), "S": dev(st["S"], dtype), "Theta": dev(st["Theta"], dtype),
+            "labels": torch.from_numpy(st["labels"].copy()).to("cuda"),
+            "C": dev(st["C"], dtype), "rho": st["rho"]}
+
+
+def _support_check(X, L_or, Th_prev, rho, S_gpu, S_or, eps):
+    """Support of S identical on entries where |B| is well away from 1/rho."""
+    B = X - L_or + Th_prev / rho
+    margin = np.abs(np.abs(B) - 1.0 / rho)
+    bound = 64 * eps * (np.abs(X) + np.abs(L_or) + np.abs(Th_prev) / rho + 1.0 / rho)
+    sep = margin > bound
+    assert np.array_equal((S_gpu != 0)[sep], (S_or != 0)[sep])
+    return sep.mean()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("max_lloyd", [1, 100])
+def test_iterate_matches_oracle_steps(dtype, max_lloyd):
+    d, n, c = 2051, 333, 7
+    X, _, _, _ = synth.clustered(d, n, c, seed=99, sep=3.0, noise=1.0, frac=0.1, amp=10.0,
+                                 dtype=dtype)
+    st = synth.random_state(X, c, seed=5, s_frac=0.2, s_amp=2.0)
+    st["rho"] = 0.05
+    lam = 0.8
+    prec = rp.F64 if dtype == np.float64 else rp.F32
+    gs = _gpu_state(st, dtype)
+    ost = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) and v.dtype != np.int32 else v)
+           for k, v in st.items()}
+    p = oracle.make_params(c, lam=lam, max_lloyd=max_lloyd)
+    tol = F64_TOL if dtype == np.float64 else F32_TOL
+    eps = np.finfo(dtype).eps
+    Xo = X.astype(np.float64)
+    nX = np.linalg.norm(Xo)
+    for t in range(3):
+        th_prev = ost["Theta"].copy()
+        rho_t = ost["rho"]
+        norms, info = rp.iterate(dev(X), gs, iters=1, lam=lam, max_lloyd=max_lloyd, precision=prec)
+        ost = oracle.step(p, Xo, ost)
+        np.testing.assert_array_equal(gs["labels"].cpu().numpy(), ost["labels"])
+        assert info["lloyd_steps"] == ost["lloyd"]
+        assert gs["rho"] == pytest.approx(ost["rho"], rel=1e-15)
+        for k in ("L", "S"):
+            assert rel(host(gs[k]), ost[k], nX) <= tol, (t, k)
+        # Theta is checked through what the method uses, Theta / rho
+        assert rel(host(gs["Theta"]) / rho_t, ost["Theta"] / rho_t, nX) <= tol
+        np.testing.assert_allclose(norms[0], ost["norms"], rtol=1e-3 if dtype == np.float32 else 1e-9,
+                                   atol=1e-6 * nX if dtype == np.float32 else 1e-12 * nX)
+        frac = _support_check(Xo, ost["L"], th_prev, rho_t, host(gs["S"]), ost["S"], eps)
+        assert frac > 0.99
+
+
+def test_iterate_full_size_sampled_columns():
+    """10^4 x 10^4, rank 100, 10 % corruptions in [-100, 100], c = 100, FP32: one
+    iteration from an arbitrary state, checked at sampled columns against the
+    oracle (group means over all columns, then per-column outputs)."""
+    d = n = 10000
+    c = 100
+    say("full-size iterate: generating")
+    X, _, _ = synth.config_large(1, np.float32)
+    st = synth.random_state(X, c, seed=8, s_frac=0.1, s_amp=20.0)
+    st["rho"] = 0.3
+    lam = 0.01
+    gs = _gpu_state(st, np.float32)
+    say("full-size iterate: gpu")
+    rp.iterate(dev(X), gs, iters=1, lam=lam, max_lloyd=1)
+    rng = np.random.default_rng(0)
+    sel = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 62, replace=False)]))
+    say("full-size iterate: oracle")
+    o = oracle.step_columns(oracle.make_params(c, lam=lam, max_lloyd=1), X, st, sel)
+    Xo = X[:, sel].astype(np.float64)
+    for k in ("L", "S"):
+        got = host(gs[k][:, torch.from_numpy(sel).cuda()])
+        assert rel(got, o[k], np.linalg.norm(Xo)) <= F32_TOL, k
+    got_t = host(gs["Theta"][:, torch.from_numpy(sel).cuda()])
+    assert rel(got_t / 0.3, o["Theta"] / 0.3, np.linalg.norm(Xo)) <= F32_TOL
+    # labels: identical where the top-2 squared-distance gap is well separated
+    lab = gs["labels"].cpu().numpy()[sel]
+    mu = o["mu"]
+    dist = ((o["L"][:, :, None] - mu[:, None, :]) ** 2).sum(axis=0)
+    srt = np.sort(dist, axis=1)
+    gap = srt[:, 1] - srt[:, 0]
+    cn = np.sqrt((mu ** 2).sum(axis=0)).max()
+    ln = np.sqrt((o["L"] ** 2).sum(axis=0))
+    # FP32 partial dot products over 1024-row slices: worst-case rounding bound
+    bound = 1024 * np.finfo(np.float32).eps * (cn ** 2 + 2 * cn * ln)
+    sep = gap > bound
+    assert sep.mean() > 0.5
+    np.testing.assert_array_equal(lab[sep], o["labels"][sep])
+
+
+# ------------------------------------------------------------- full size
+
+@pytest.mark.parametrize("rank", [100, 5])
+def test_solve_full_size_properties(rank):
+    """10^4 x 10^4 FP32 solve, true rank given (c = 100) and withheld (c = 5):
+    converges, X = L + S to the tolerance, finite outputs, labels in range."""
+    say(f"full-size solve c={rank}: generating")
+    X, _, _ = synth.config_large(1, np.float32)
+    Xd = dev(X)
+    say(f"full-size solve c={rank}: gpu")
+    g = rp.solve(Xd, rank=rank, lam=0.01, tol=1e-6, seed=0)
+    say(f"info {g['info']}")
+    assert g["status"] == rp.OK
+    L, S = g["L"].double(), g["S"].double()
+    r = torch.linalg.norm(Xd.double() - L - S) / torch.linalg.norm(Xd.double())
+    assert float(r) <= 1e-6 * 1.5
+    assert torch.isfinite(L).all() and torch.isfinite(S).all()
+    lab = g["labels"]
+    assert int(lab.min()) >= 0 and int(lab.max()) < rank
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_zero_input_and_error_paths():
+    Z = torch.zeros((40, 30), dtype=torch.float32, device="cuda").T.contiguous().T
+    g = rp.solve(Z, rank=3, lam=1.0)
+    assert g["status"] == rp.OK and g["info"]["iters"] == 0
+    assert not g["L"].any() and not g["S"].any() and not g["labels"].any()
+    X = dev(np.random.default_rng(0).normal(size=(40, 30)), np.float32)
+    with pytest.raises(rp.RespcaError) as e:
+        rp.solve(X, rank=31, lam=1.0)
+    assert e.value.status == rp.ERR_INVALID
+    with pytest.raises(rp.RespcaError) as e:
+        rp.solve(X, rank=3, lam=-1.0)
+    assert e.value.status == rp.ERR_INVALID
+    Xn = X.clone()
+    Xn[3, 4] = float("nan")
+    with pytest.raises(rp.RespcaError) as e:
+        rp.solve(Xn, rank=3, lam=1.0)
+    assert e.value.status == rp.ERR_NONFINITE
+    Xi = X.clone()
+    Xi[0, 0] = float("inf")
+    with pytest.raises(rp.RespcaError) as e:
+        rp.solve(Xi, rank=3, lam=1.0)
+    assert e.value.status == rp.ERR_NONFINITE
+    g = rp.solve(X, rank=3, lam=1.0, max_iter=1)
+    assert g["status"] == rp.NOT_CONVERGED and g["info"]["iters"] == 1
+
+
+def test_degenerate_cases_match_closed_forms():
+    """c = n or lambda = 0: L = X, S = 0, stop at t = 2; d = n = 1."""
+    X = np.random.default_rng(1).normal(size=(7, 40))
+    for c, lam in [(40, 2.0), (3, 0.0)]:
+        g = rp.solve(dev(X), rank=c, lam=lam, tol=1e-12, precision=rp.F64)
+        assert g["info"]["iters"] == 2
+        np.testing.assert_allclose(host(g["L"]), X, atol=1e-15)
+        assert not g["S"].any()
+    one = np.array([[3.5]])
+    g = rp.solve(dev(one), rank=1, lam=1.0, tol=1e-12, precision=rp.F64)
+    assert g["info"]["iters"] == 2 and float(g["L"][0, 0]) == 3.5
+
+
+def test_padded_leading_dimension_and_determinism():
+    d, n, c = 1001, 257, 4
+    X, _, _, _ = synth.clustered(d, n, c, seed=4, sep=4.0, noise=0.5, dtype=np.float32)
+    Xd = dev(X)
+    pad = torch.zeros((n, d + 5), dtype=torch.float32, device="cuda")
+    pad[:, :d] = Xd.T
+    Xp = pad.T[:d]                       # stride (1, d + 5)
+    assert Xp.stride() == (1, d + 5)
+    a = rp.solve(Xd, rank=c, lam=0.7, tol=1e-6, seed=2)
+    b = rp.solve(Xd, rank=c, lam=0.7, tol=1e-6, seed=2)
+    assert torch.equal(a["L"], b["L"]) and torch.equal(a["S"], b["S"])
+    assert torch.equal(a["labels"], b["labels"])
+    p = rp.solve(Xp, rank=c, lam=0.7, tol=1e-6, seed=2)
+    o = oracle.solve(X, oracle.make_params(c, lam=0.7, tol=1e-6, seed=2))
+    nX = np.linalg.norm(X.astype(np.float64))
+    assert p["info"]["iters"] == o["info"]["iters"]
+    assert rel(host(p["L"]), o["L"], nX) <= F32_TOL
+    assert rel(host(p["S"]), o["S"], nX) <= F32_TOL

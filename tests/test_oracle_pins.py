@@ -400,3 +400,19 @@ def test_coarse_agreement_with_convex_rpca_ialm(orc):
     e_ialm = np.linalg.norm(Li - L0) / nL0
     assert e_res < 0.05 and e_ialm < 0.05
     assert np.linalg.norm(r["L"] - Li) / nL0 <= e_res + e_ialm + 1e-9
+
+
+def test_column_restricted_step_agrees_with_full_step(orc):
+    """The column-restricted step used for large checks gives the full step's
+    outputs at the selected columns (single assignment pass)."""
+    X = np.asfortranarray(np.random.default_rng(16).normal(0, 3, (9, 30)))
+    c, lam = 4, 0.7
+    st = _state(X, c, 3)
+    p = orc.make_params(c, lam=lam, max_lloyd=1)
+    full = orc.step(p, X, st)
+    sel = np.array([0, 3, 17, 29])
+    part = orc.step_columns(p, X, st, sel)
+    for k in ("L", "S", "Theta"):
+        np.testing.assert_array_equal(part[k], full[k][:, sel])
+    assign_first = orc.assign(full["L"][:, sel], part["mu"])
+    np.testing.assert_array_equal(part["labels"], assign_first)
