@@ -1,0 +1,200 @@
+"""RES-PCA solves/s on one MI355X, with the sweep's HBM roofline and the FP64
+CPU checker timed beside it.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload large]
+                    [--no-cpu-baseline]
+
+A step is one whole RES-PCA solve (initial K-means of X, then outer ALM
+iterations L -> p -> S -> Theta/rho until the Sec. 5 criterion <= tol) of
+one synthetic input that is already resident in HBM.  The default workload is
+10^4 x 10^4 FP32: X = U V^T (rank 100, U, V iid N(0, 1)) plus 10 % of entries
+uniform in [-100, 100], c = 100 groups, lambda = 0.01, tol = 1e-6.
+
+One JSON line is printed.  `roofline` describes the dominant kernel (the one
+with the largest summed event time), with achieved = algorithmic bytes per
+launch / mean launch time, both measured live by the library's event timing on
+the launch stream over the timed region.  `traffic` comes from the rocprofv3
+counter summary committed under profiles/ when it was taken on the current
+kernel source, else null.  `cpu_baseline` times the FP64 CPU checker on a
+bounded sample of the same workload and scales it to solves/s (see `sample`).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "large": dict(name="RES-PCA FP32 10000x10000 rank-100 + 10% sparse in [-100,100], c=100 (true "
+                       "rank given), lambda=0.01, tol=1e-6", d=10000, n=10000, rank=100, lam=0.01,
+                  tol=1e-6, gen="large"),
+    "large_c5": dict(name="RES-PCA FP32 10000x10000 rank-100 + 10% sparse in [-100,100], c=5 (rank "
+                          "withheld), lambda=0.01, tol=1e-6", d=10000, n=10000, rank=5, lam=0.01,
+                     tol=1e-6, gen="large"),
+    "video": dict(name="RES-PCA FP32 synthetic 240x320x2000 clip (rank-5 background, 4 moving 20x20 "
+                       "squares, 8-bit scale), c=5, lambda=sqrt(76800), tol=1e-6", d=76800, n=2000,
+                  rank=5, lam=None, tol=1e-6, gen="video"),
+}
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1904_07497_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """Per-launch HBM bytes (fetch + write, scaled by the copy-kernel factor)
+    from the committed counter summary, only if taken on the current source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_input(wl, dtype):
+    import numpy as np
+    from paper_1904_07497_amd import synth
+    if wl["gen"] == "large":
+        X, _, _ = synth.config_large(1, np.float32, d=wl["d"], n=wl["n"])
+    else:
+        X, _, _ = synth.video(n=wl["n"], seed=2, dtype=np.float32)
+    return X
+
+
+def cpu_baseline(X, wl, gpu_info):
+    """Time the FP64 CPU checker on one outer iteration of the same workload and
+    scale to one whole solve with the iteration / pass counts of the GPU solve."""
+    import numpy as np
+    import oracle
+    d, n = X.shape
+    c = wl["rank"]
+    lam = wl["lam"] if wl["lam"] is not None else float(np.sqrt(max(d, n)))
+    X64 = np.asfortranarray(X.astype(np.float64))
+    rng = np.random.default_rng(0)
+    st = {"L": np.zeros((d, n), order="F"), "S": np.zeros((d, n), order="F"),
+          "Theta": np.zeros((d, n), order="F"), "labels": rng.integers(0, c, n).astype(np.int32),
+          "C": np.zeros((d, c), order="F"), "rho": 1e-4}
+    p = oracle.make_params(c, lam=lam, max_lloyd=1)
+    t = time.perf_counter()
+    o = oracle.step(p, X64, st)                      # L-step + one assignment + S + Theta
+    t_step = time.perf_counter() - t
+    t = time.perf_counter()
+    lab = oracle.assign(o["L"], o["C"])              # one extra Lloyd assignment pass
+    t_assign = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.group_means(o["L"], lab, c)               # one Lloyd centroid pass
+    t_mean = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.kmeanspp(X64, 2, 0)                       # two k-means++ distance passes
+    t_d2 = (time.perf_counter() - t) / 2
+    it, ll, il = gpu_info["iters"], gpu_info["lloyd_steps"], gpu_info["init_lloyd"]
+    t_solve = (c * t_d2 + (il + 1) * (t_assign + t_mean) + it * t_step
+               + (ll - it) * (t_assign + t_mean))
+    sample = (f"one FP64 outer iteration (L-step, one assignment pass, S-step, Theta update) of the "
+              f"same {d}x{n} c={c} input ({t_step:.2f} s), one assignment pass ({t_assign:.2f} s), "
+              f"one centroid pass ({t_mean:.2f} s), one k-means++ distance pass ({t_d2:.3f} s); "
+              f"solve time = {c}*seed pass + {il + 1} init assignment+centroid passes + {it} "
+              f"iterations + {ll - it} extra Lloyd passes (counts of the GPU solve) = {t_solve:.1f} s")
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": sample}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
+              f"single MI355X; see the sharding notes in the design document)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1904_07497_amd import respca as rp
+
+    wl = WORKLOADS[args.workload]
+    X = make_input(wl, np.float32)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    d, n = X.shape
+    kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0)
+    L = rp.empty_colmajor(d, n, Xd.dtype, Xd.device)
+    S = rp.empty_colmajor(d, n, Xd.dtype, Xd.device)
+    lab = torch.empty(n, dtype=torch.int32, device=Xd.device)
+    out = (L, S, lab)
+
+    for _ in range(args.warmup):
+        r = rp.solve(Xd, out=out, **kw)
+    torch.cuda.synchronize()
+    rp.profile_enable(True)
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = rp.solve(Xd, out=out, **kw)
+        infos.append(r["info"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = rp.profile_query()
+    rp.profile_enable(False)
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    pk = prof[dom]
+    per_launch_bytes = pk["bytes"] / max(pk["launches"], 1)
+    mean_s = pk["ms"] / 1e3 / max(pk["launches"], 1)
+    achieved = per_launch_bytes / mean_s / 1e9 if mean_s > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(dom, args.workload), "kernel": dom,
+                "bytes_per_launch": per_launch_bytes, "mean_launch_ms": round(mean_s * 1e3, 4)}
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None}
+               for k, v in prof.items()}
+    line = {
+        "metric": "RPCA solves/s + sweep HBM GB/s at rel-err<=1e-5 (BF16/learned vs plain FP32)",
+        "value": round(args.steps / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "d": d, "n": n, "c": wl["rank"],
+                   "precision": "plain FP32 (double accumulators)",
+                   "iters": infos[-1]["iters"], "lloyd_steps": infos[-1]["lloyd_steps"],
+                   "init_lloyd": infos[-1]["init_lloyd"]},
+        "sweep_GBps": kernels["sweep"]["GBps"],
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(X, wl, infos[-1])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -149,6 +149,28 @@ respca_status respca_kmeans(respca_handle h, const respca_params *params,
                             int64_t d, int64_t n, const void *Y, int64_t ldy,
                             int32_t *labels, void *C, respca_info *info, void *stream);
 
+/*
+ * Kernel timing.  While enabled, every launch of the kernels listed in
+ * respca_kernel_id is bracketed by HIP events recorded on the stream it is
+ * launched on, and the library accumulates, per kernel, the number of
+ * launches, their summed event time and their summed algorithmic HBM bytes
+ * (the bytes the method must move: every d x n array the kernel reads or
+ * writes once, at the element size of the run).  Enabling (or disabling)
+ * resets the counters.  Timing adds two event records per launch.
+ */
+typedef enum {
+    RESPCA_KERNEL_SWEEP = 0,      /* fused L/S/Theta sweep: reads X, S, Theta, L; writes L, S, Theta */
+    RESPCA_KERNEL_MEANS = 1,      /* group partial sums: reads X, S, Theta (or one array)            */
+    RESPCA_KERNEL_DISTANCE = 2,   /* centroid . column products: reads the d x n operand once       */
+    RESPCA_KERNEL_SEEDING = 3,    /* k-means++ squared distances: reads X once                      */
+    RESPCA_KERNEL_COUNT = 4
+} respca_kernel_id;
+
+respca_status respca_profile_enable(respca_handle h, int32_t enable);
+/* launches, total_ms and bytes are host outputs (any may be NULL). */
+respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t *launches,
+                                   double *total_ms, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

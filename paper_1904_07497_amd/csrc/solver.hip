@@ -24,9 +24,22 @@ struct DevBuf {
 
 }  // namespace
 
+struct ProfPending {
+    int kernel;
+    hipEvent_t a, b;
+    double bytes;
+};
+
 struct respca_handle_s {
     int device = 0;
     std::string err;
+    // kernel timing
+    bool prof_on = false;
+    int64_t prof_launches[RESPCA_KERNEL_COUNT] = {};
+    double prof_ms[RESPCA_KERNEL_COUNT] = {};
+    double prof_bytes[RESPCA_KERNEL_COUNT] = {};
+    std::vector<ProfPending> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
     DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, pmeans, dots, cnorm, lab_a, lab_b, d2,
         chosen, seeds, u, normp, chgp, status;
     double* hstage = nullptr;  // pinned host staging (status readback, uniforms)
@@ -80,6 +93,51 @@ respca_status ensure_host(respca_handle h, size_t bytes) {
 respca_status fail(respca_handle h, respca_status s, const std::string& msg) {
     if (h) h->err = msg;
     return s;
+}
+
+// Event bracket around one launch (no-op unless timing is enabled).
+struct ProfScope {
+    respca_handle h;
+    hipStream_t st;
+    int kernel;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(respca_handle h_, hipStream_t st_, int k, double by) : h(h_), st(st_), kernel(k), bytes(by) {
+        if (!h->prof_on) return;
+        a = take();
+        b = take();
+        if (a && b) (void)hipEventRecord(a, st);
+    }
+    ~ProfScope() {
+        if (!h->prof_on || !a || !b) return;
+        (void)hipEventRecord(b, st);
+        h->prof_pending.push_back({kernel, a, b, bytes});
+    }
+    hipEvent_t take() {
+        if (!h->prof_pool.empty()) {
+            hipEvent_t e = h->prof_pool.back();
+            h->prof_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+// Fold finished event pairs into the counters; call after a stream sync.
+void prof_resolve(respca_handle h) {
+    for (auto& p : h->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            h->prof_launches[p.kernel] += 1;
+            h->prof_ms[p.kernel] += ms;
+            h->prof_bytes[p.kernel] += p.bytes;
+        }
+        h->prof_pool.push_back(p.a);
+        h->prof_pool.push_back(p.b);
+    }
+    h->prof_pending.clear();
 }
 
 uint64_t splitmix64_next(uint64_t& state) {
@@ -187,6 +245,7 @@ struct Engine {
         CK(hipMemcpyAsync(h->hstage, status, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
         for (int i = 0; i < 4; ++i) out[i] = h->hstage[i];
+        prof_resolve(h);
         return RESPCA_OK;
     }
 
@@ -208,9 +267,12 @@ struct Engine {
     // for the groups of the last sort; empty groups keep C[:, k].
     void group_means(bool with_d, const T* A, int64_t lda, const T* S, int64_t lds, const T* Th,
                      int64_t ldt, T inv_rho, T* C) {
-        launch_group_partial<T>(with_d, A, lda, S, lds, Th, ldt, inv_rho, d, n, c, perm(),
+        {
+            ProfScope ps(h, st, RESPCA_KERNEL_MEANS, (with_d ? 3.0 : 1.0) * (double)d * n * sizeof(T));
+            launch_group_partial<T>(with_d, A, lda, S, lds, Th, ldt, inv_rho, d, n, c, perm(),
                                 (const int32_t*)h->segb.p, (const int32_t*)h->segl.p,
                                 (const int32_t*)h->nseg.p, (double*)h->pmeans.p, st);
+        }
         launch_group_finalize<T>((const double*)h->pmeans.p, d, c, counts(),
                                  (const int32_t*)h->segf.p, C, st);
     }
@@ -218,7 +280,10 @@ struct Engine {
     // Assignment pass: new = nearest centroid of every column of Y; status[3] = #changed.
     void assign(const T* Y, int64_t ldy, const T* C, const int32_t* old, int32_t* neu) {
         launch_col_sqnorm<T>(C, d, c, (double*)h->cnorm.p, st);
-        launch_dots<T>(C, d, c, Y, ldy, n, (T*)h->dots.p, st);
+        {
+            ProfScope ps(h, st, RESPCA_KERNEL_DISTANCE, (double)d * n * sizeof(T));
+            launch_dots<T>(C, d, c, Y, ldy, n, (T*)h->dots.p, st);
+        }
         const int g = launch_argmin<T>((const T*)h->dots.p, nrb, c, n, (const double*)h->cnorm.p, old,
                                        neu, (double*)h->chgp.p, st);
         launch_sum_partials((const double*)h->chgp.p, g, 1, status + 3, st);
@@ -265,9 +330,14 @@ struct Engine {
         launch_zero_i32(chosen, n, st);
         CK(hipMemcpyAsync(seeds, &hi[0], sizeof(int32_t), hipMemcpyHostToDevice, st));
         CK(hipMemcpyAsync(chosen + s0, &hi[1], sizeof(int32_t), hipMemcpyHostToDevice, st));
-        launch_d2<T>(Y, ldy, d, n, seeds, 0, (double*)h->d2.p, st);
+        const double pass_bytes = (double)d * n * sizeof(T);
+        {
+            ProfScope ps(h, st, RESPCA_KERNEL_SEEDING, pass_bytes);
+            launch_d2<T>(Y, ldy, d, n, seeds, 0, (double*)h->d2.p, st);
+        }
         for (int m = 1; m < c; ++m) {
             launch_pick((const double*)h->d2.p, n, (const double*)h->u.p, m, seeds, chosen, st);
+            ProfScope ps(h, st, RESPCA_KERNEL_SEEDING, pass_bytes);
             launch_d2<T>(Y, ldy, d, n, seeds, m, (double*)h->d2.p, st);
         }
         launch_gather_cols<T>(Y, ldy, d, seeds, c, C, st);
@@ -289,8 +359,12 @@ struct Engine {
         const double inv = 1.0 / rho;
         sort(cur);                                                   // Sec. 4.1: groups of D
         group_means(true, X, ldx, S, lds, Th, ldt, (T)inv, C);
-        const int np = launch_sweep<T>(X, ldx, L, ldl, S, lds, Th, ldt, C, cur, d, n, alpha, beta,
-                                       rho, inv, (double*)h->normp.p, st);
+        int np = 0;
+        {
+            ProfScope ps(h, st, RESPCA_KERNEL_SWEEP, 7.0 * (double)d * n * sizeof(T));
+            np = launch_sweep<T>(X, ldx, L, ldl, S, lds, Th, ldt, C, cur, d, n, alpha, beta, rho, inv,
+                                 (double*)h->normp.p, st);
+        }
         launch_sum_partials((const double*)h->normp.p, np, 3, status, st);
         double first[4];
         CKS(lloyd(L, ldl, C, cur, alt, r.max_lloyd, steps, first));  // Sec. 4.2
@@ -455,6 +529,11 @@ respca_status respca_create(respca_handle* out, int32_t device) {
 void respca_destroy(respca_handle h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
+    for (auto& p : h->prof_pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
                       &h->nseg, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b, &h->d2,
                       &h->chosen, &h->seeds, &h->u, &h->normp, &h->chgp, &h->status};
@@ -497,6 +576,36 @@ const char* respca_status_string(respca_status s) {
 const char* respca_last_error(respca_handle h) { return h ? h->err.c_str() : "NULL handle"; }
 
 const char* respca_version(void) { return kVersion; }
+
+respca_status respca_profile_enable(respca_handle h, int32_t enable) {
+    if (!h) return RESPCA_ERR_INVALID;
+    if (hipSetDevice(h->device) != hipSuccess) return RESPCA_ERR_HIP;
+    if (!h->prof_pending.empty()) {
+        (void)hipDeviceSynchronize();
+        prof_resolve(h);
+    }
+    h->prof_on = enable != 0;
+    for (int k = 0; k < RESPCA_KERNEL_COUNT; ++k) {
+        h->prof_launches[k] = 0;
+        h->prof_ms[k] = 0.0;
+        h->prof_bytes[k] = 0.0;
+    }
+    return RESPCA_OK;
+}
+
+respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t* launches,
+                                   double* total_ms, double* bytes) {
+    if (!h || kernel < 0 || kernel >= RESPCA_KERNEL_COUNT) return RESPCA_ERR_INVALID;
+    if (!h->prof_pending.empty()) {
+        if (hipSetDevice(h->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return RESPCA_ERR_HIP;
+        prof_resolve(h);
+    }
+    if (launches) *launches = h->prof_launches[kernel];
+    if (total_ms) *total_ms = h->prof_ms[kernel];
+    if (bytes) *bytes = h->prof_bytes[kernel];
+    return RESPCA_OK;
+}
 
 respca_status respca_solve(respca_handle h, const respca_params* params, int64_t d, int64_t n,
                            const void* X, int64_t ldx, void* L, int64_t ldl, void* S, int64_t lds,

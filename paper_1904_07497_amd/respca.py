@@ -24,7 +24,8 @@ F64, F32, BF16GEMM_F32 = 0, 1, 2
 # Every symbol include/respca.h declares.
 EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_status_string",
            "respca_last_error", "respca_version", "respca_solve", "respca_iterate",
-           "respca_kmeans")
+           "respca_kmeans", "respca_profile_enable", "respca_profile_query")
+KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3}
 
 
 class Params(ct.Structure):
@@ -80,6 +81,11 @@ def lib():
         L.respca_iterate.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, i64, vp, i64,
                                      vp, i64, vp, vp, ct.POINTER(ct.c_double), i32,
                                      ct.POINTER(ct.c_double), ct.POINTER(Info), vp]
+        L.respca_profile_enable.restype = i32
+        L.respca_profile_enable.argtypes = [vp, i32]
+        L.respca_profile_query.restype = i32
+        L.respca_profile_query.argtypes = [vp, i32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
+                                           ct.POINTER(ct.c_double)]
         L.respca_kmeans.restype = i32
         L.respca_kmeans.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, vp,
                                     ct.POINTER(Info), vp]
@@ -268,3 +274,21 @@ def kmeans(Y, rank, seed=0, max_lloyd=100, precision=None, stream=None):
                             ct.byref(info), _stream(stream))
     h.check(s)
     return labels, C, info.as_dict()
+
+
+def profile_enable(on: bool = True, device: int = 0):
+    """Turn the library's per-kernel event timing on/off (resets the counters)."""
+    h = handle(device)
+    h.check(lib().respca_profile_enable(h._h, 1 if on else 0), allow=(OK,))
+
+
+def profile_query(device: int = 0) -> dict:
+    """{kernel: {"launches", "ms", "bytes"}} accumulated since profile_enable."""
+    h = handle(device)
+    out = {}
+    for name, kid in KERNELS.items():
+        n, ms, by = ct.c_int64(), ct.c_double(), ct.c_double()
+        h.check(lib().respca_profile_query(h._h, kid, ct.byref(n), ct.byref(ms), ct.byref(by)),
+                allow=(OK,))
+        out[name] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
+    return out
