@@ -47,7 +47,7 @@ WORKLOADS = {
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h"):
+    for f in ("kernels.hip", "kernels.h", "distance.hip"):
         with open(os.path.join(ROOT, "paper_1904_07497_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

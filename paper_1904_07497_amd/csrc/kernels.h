@@ -11,7 +11,6 @@ constexpr int kBlock = 256;          // threads of a streaming workgroup (4 wave
 constexpr int kRowsPerBlock = 1024;  // rows of the d-slice one streaming workgroup covers
 constexpr int kSegCols = 64;         // max columns of one group segment in the means pass
 constexpr int kMaxGroups = 1024;     // c limit (LDS histogram of the label sort)
-constexpr int kSortThreads = 512;    // single-workgroup label sort
 constexpr int kPickThreads = 1024;   // single-workgroup k-means++ draw
 
 inline int row_blocks(int64_t d) { return (int)((d + kRowsPerBlock - 1) / kRowsPerBlock); }
@@ -30,9 +29,11 @@ void launch_sum_partials(const double* partial, int count, int width, double* ou
 
 // Stable counting sort of labels: counts[c], perm[n] (columns grouped by label,
 // increasing index within a group), and the segment table of the means pass.
-void launch_label_sort(const int32_t* labels, int64_t n, int c, int32_t* counts, int32_t* perm,
-                       int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg,
-                       hipStream_t st);
+// `bc` is scratch of sort_scratch_ints(n, c) ints.
+int64_t sort_scratch_ints(int64_t n, int c);
+void launch_label_sort(const int32_t* labels, int64_t n, int c, int32_t* bc, int32_t* counts,
+                       int32_t* perm, int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first,
+                       int32_t* nseg, hipStream_t st);
 
 // Group partial sums: partial[s*d + i] = sum over the columns j of segment s of
 // Y[i, j], where Y = X - S + Theta*inv_rho (with_d = true) or Y = A (with_d = false).
@@ -71,6 +72,17 @@ template <typename T>
 int launch_argmin(const T* part, int nrb, int c, int64_t n, const double* cnorm,
                   const int32_t* old_labels, int32_t* new_labels, double* changed_partial,
                   hipStream_t st);
+
+// Assignment pass: new_labels[j] = argmin_k ||C_k||^2 - 2 C_k . Y_j (ties: lowest
+// k), per-block changed counts into changed_partial; returns the number of
+// count partials.  `work` must hold assign_workspace_bytes<T>(d, n, c).
+template <typename T>
+size_t assign_workspace_bytes(int64_t d, int64_t n, int c);
+template <typename T>
+int launch_assign(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t n,
+                  const double* cnorm, const int32_t* old_labels, int32_t* new_labels, void* work,
+                  double* changed_partial, hipStream_t st);
+inline int64_t assign_partials_max(int64_t n) { return (n + 15) / 16; }
 
 // k-means++ helpers.
 template <typename T>

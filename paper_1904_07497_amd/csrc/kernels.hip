@@ -134,99 +134,84 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, 
 
 // --------------------------------------------------------------- label sort
 
-// Stable counting sort in one workgroup of kSortThreads threads.  Wave w owns
-// a contiguous range of columns; per-(wave, label) counts give every wave its
-// own output offsets, and inside a wave equal labels are ranked with ballots,
-// so the output order is "by label, then by column index".
-__global__ __launch_bounds__(kSortThreads) void k_label_sort(
-    const int32_t* __restrict__ labels, int n, int c, int32_t* counts, int32_t* perm,
-    int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg_out) {
-    constexpr int W = kSortThreads / 64;
-    __shared__ int cnt[W * kMaxGroups];
-    __shared__ int wsum[W];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+// Stable counting sort in three launches.  Chunk b = columns [256b, 256b+256):
+//   hist:    per-chunk label histogram -> bc[b*c + k]
+//   scan:    per label, exclusive offsets over (label, chunk) -> bc in place;
+//            group counts and the segment table (runs of <= kSegCols columns)
+//   scatter: each column's rank among equal labels earlier in its chunk.
+// Output order: by label, then by column index.
+constexpr int kSortChunk = 256;
 
-    for (int e = tid; e < W * c; e += kSortThreads) cnt[e] = 0;
+__global__ __launch_bounds__(kSortChunk) void k_sort_hist(const int32_t* __restrict__ labels, int n,
+                                                          int c, int32_t* __restrict__ bc) {
+    __shared__ int h[kMaxGroups];
+    for (int k = threadIdx.x; k < c; k += kSortChunk) h[k] = 0;
     __syncthreads();
-    const int per = (n + W - 1) / W;
-    const int lo = wave * per, hi = min(n, lo + per);
-    for (int j = lo + lane; j < hi; j += 64) atomicAdd(&cnt[wave * c + labels[j]], 1);
+    const int j = blockIdx.x * kSortChunk + threadIdx.x;
+    if (j < n) atomicAdd(&h[labels[j]], 1);
     __syncthreads();
+    for (int k = threadIdx.x; k < c; k += kSortChunk) bc[(int64_t)blockIdx.x * c + k] = h[k];
+}
 
-    // exclusive scan over groups of (total count) and of (segments), two passes
-    // of a chunked block scan: each thread owns up to 2 consecutive groups.
-    constexpr int GPT = kMaxGroups / kSortThreads;
-    int tot[GPT], nsg[GPT];
-    int my_tot = 0, my_seg = 0;
+__device__ inline int block_exscan_1024(int v, int* wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
 #pragma unroll
-    for (int g = 0; g < GPT; ++g) {
-        const int k = tid * GPT + g;
-        int t = 0;
-        if (k < c)
-            for (int w = 0; w < W; ++w) t += cnt[w * c + k];
-        tot[g] = t;
-        nsg[g] = (t + kSegCols - 1) / kSegCols;
-        my_tot += t;
-        my_seg += nsg[g];
-    }
-    // block exclusive scan of (my_tot, my_seg) packed into two passes
-    auto block_exscan = [&](int v) -> int {
-        int x = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[wave] = x;
-        __syncthreads();
-        int base = 0;
-        for (int w = 0; w < wave; ++w) base += wsum[w];
-        __syncthreads();
-        return base + x - v;
-    };
-    int base_cnt = block_exscan(my_tot);
-    int base_seg = block_exscan(my_seg);
-
-#pragma unroll
-    for (int g = 0; g < GPT; ++g) {
-        const int k = tid * GPT + g;
-        if (k < c) {
-            counts[k] = tot[g];
-            seg_first[k] = base_seg;
-            for (int q = 0; q < nsg[g]; ++q) {
-                seg_begin[base_seg + q] = base_cnt + q * kSegCols;
-                seg_len[base_seg + q] = min(kSegCols, tot[g] - q * kSegCols);
-            }
-            // per-wave output offsets, in place
-            int run = base_cnt;
-            for (int w = 0; w < W; ++w) {
-                const int t = cnt[w * c + k];
-                cnt[w * c + k] = run;
-                run += t;
-            }
-            if (k == c - 1) { seg_first[c] = base_seg + nsg[g]; *nseg_out = base_seg + nsg[g]; }
-        }
-        base_cnt += tot[g];
-        base_seg += nsg[g];
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
     __syncthreads();
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    return base + x - v;
+}
 
-    for (int b0 = lo; b0 < hi; b0 += 64) {
-        const int j = b0 + lane;
-        const bool valid = j < hi;
-        const int lab = valid ? labels[j] : -1;
-        unsigned long long pending = __ballot(valid);
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int L = __shfl(lab, leader);
-            const unsigned long long m = __ballot(valid && lab == L);
-            const int b = cnt[wave * c + L];
-            if (valid && lab == L) perm[b + __popcll(m & ((1ull << lane) - 1ull))] = j;
-            __builtin_amdgcn_wave_barrier();
-            if (lane == leader) cnt[wave * c + L] = b + __popcll(m);
-            __builtin_amdgcn_wave_barrier();
-            pending &= ~m;
+__global__ __launch_bounds__(kMaxGroups) void k_sort_scan(int32_t* __restrict__ bc, int nb, int c,
+                                                         int32_t* counts, int32_t* seg_begin,
+                                                         int32_t* seg_len, int32_t* seg_first,
+                                                         int32_t* nseg_out) {
+    __shared__ int wsum[kMaxGroups / 64];
+    const int k = threadIdx.x;
+    int tot = 0;
+    if (k < c)
+        for (int b = 0; b < nb; ++b) tot += bc[(int64_t)b * c + k];
+    const int nsg = (tot + kSegCols - 1) / kSegCols;
+    const int base = block_exscan_1024(tot, wsum);
+    const int sbase = block_exscan_1024(nsg, wsum);
+    if (k < c) {
+        counts[k] = tot;
+        seg_first[k] = sbase;
+        for (int q = 0; q < nsg; ++q) {
+            seg_begin[sbase + q] = base + q * kSegCols;
+            seg_len[sbase + q] = min(kSegCols, tot - q * kSegCols);
         }
+        int run = base;
+        for (int b = 0; b < nb; ++b) {
+            const int t = bc[(int64_t)b * c + k];
+            bc[(int64_t)b * c + k] = run;
+            run += t;
+        }
+        if (k == c - 1) { seg_first[c] = sbase + nsg; *nseg_out = sbase + nsg; }
+    }
+}
+
+__global__ __launch_bounds__(kSortChunk) void k_sort_scatter(const int32_t* __restrict__ labels,
+                                                             int n, int c,
+                                                             const int32_t* __restrict__ bc,
+                                                             int32_t* __restrict__ perm) {
+    __shared__ int lab[kSortChunk];
+    const int tid = threadIdx.x;
+    const int j = blockIdx.x * kSortChunk + tid;
+    const int my = j < n ? labels[j] : -1;
+    lab[tid] = my;
+    __syncthreads();
+    if (j < n) {
+        int rank = 0;
+        for (int t = 0; t < tid; ++t) rank += (lab[t] == my);
+        perm[bc[(int64_t)blockIdx.x * c + my] + rank] = j;
     }
 }
 
@@ -455,8 +440,9 @@ __global__ __launch_bounds__(kBlock) void k_argmin(const T* __restrict__ part, i
 
 // -------------------------------------------------------------- k-means++
 
-// One wave per column: d2[j] = min(d2[j], ||Y_j - Y_s||^2) in double, s = seeds[m].
-template <typename T>
+// One wave per column: d2[j] = min(d2[j], ||Y_j - Y_s||^2) in double, s = seeds[m]
+// (the differences of the upcast values are taken in double as well).
+template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void k_d2(const T* __restrict__ Y, int64_t ldy, int64_t d,
                                                int64_t n, const int32_t* __restrict__ seeds, int m,
                                                double* __restrict__ d2) {
@@ -464,10 +450,18 @@ __global__ __launch_bounds__(kBlock) void k_d2(const T* __restrict__ Y, int64_t 
     const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (j >= n) return;
     const int64_t s = seeds[m];
+    const T* yj = Y + j * ldy;
+    const T* ys = Y + s * ldy;
     double acc = 0.0;
-    for (int64_t i = lane; i < d; i += 64) {
-        const double t = (double)Y[j * ldy + i] - (double)Y[s * ldy + i];
-        acc += t * t;
+    for (int64_t i = (int64_t)lane * V; i < d; i += 64 * V) {
+        T a[V], b[V];
+        vload<T, V>(yj + i, a);
+        vload<T, V>(ys + i, b);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const double t = (double)a[v] - (double)b[v];
+            acc += t * t;
+        }
     }
     acc = wave_sum(acc);
     if (lane == 0) d2[j] = (m == 0) ? acc : fmin(d2[j], acc);
@@ -579,11 +573,15 @@ void launch_sum_partials(const double* partial, int count, int width, double* ou
     k_sum_partials<<<1, kBlock, 0, st>>>(partial, count, width, out);
 }
 
-void launch_label_sort(const int32_t* labels, int64_t n, int c, int32_t* counts, int32_t* perm,
-                       int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg,
-                       hipStream_t st) {
-    k_label_sort<<<1, kSortThreads, 0, st>>>(labels, (int)n, c, counts, perm, seg_begin, seg_len,
-                                             seg_first, nseg);
+int64_t sort_scratch_ints(int64_t n, int c) { return ((n + kSortChunk - 1) / kSortChunk) * (int64_t)c; }
+
+void launch_label_sort(const int32_t* labels, int64_t n, int c, int32_t* bc, int32_t* counts,
+                       int32_t* perm, int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first,
+                       int32_t* nseg, hipStream_t st) {
+    const int nb = (int)((n + kSortChunk - 1) / kSortChunk);
+    k_sort_hist<<<nb, kSortChunk, 0, st>>>(labels, (int)n, c, bc);
+    k_sort_scan<<<1, kMaxGroups, 0, st>>>(bc, nb, c, counts, seg_begin, seg_len, seg_first, nseg);
+    k_sort_scatter<<<nb, kSortChunk, 0, st>>>(labels, (int)n, c, bc, perm);
 }
 
 template <typename T>
@@ -680,7 +678,12 @@ template <typename T>
 void launch_d2(const T* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* seeds, int m,
                double* d2, hipStream_t st) {
     const int per = kBlock / 64;
-    k_d2<T><<<(unsigned)((n + per - 1) / per), kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2);
+    const unsigned g = (unsigned)((n + per - 1) / per);
+    constexpr int VV = 16 / sizeof(T);
+    if (pick_vec<T>(d, {{Y, ldy}}) == VV)
+        k_d2<T, VV><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2);
+    else
+        k_d2<T, 1><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2);
 }
 
 void launch_pick(const double* d2, int64_t n, const double* u, int m, int32_t* seeds,

@@ -40,8 +40,8 @@ struct respca_handle_s {
     double prof_bytes[RESPCA_KERNEL_COUNT] = {};
     std::vector<ProfPending> prof_pending;
     std::vector<hipEvent_t> prof_pool;
-    DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, pmeans, dots, cnorm, lab_a, lab_b, d2,
-        chosen, seeds, u, normp, chgp, status;
+    DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, sortbc, pmeans, dots, cnorm, lab_a,
+        lab_b, d2, chosen, seeds, u, normp, chgp, status;
     double* hstage = nullptr;  // pinned host staging (status readback, uniforms)
     size_t hstage_bytes = 0;
 };
@@ -223,14 +223,15 @@ struct Engine {
         CKS(ensure(h, h->segf, (c + 1) * sizeof(int32_t)));
         CKS(ensure(h, h->nseg, sizeof(int32_t)));
         CKS(ensure(h, h->pmeans, segs * d * sizeof(double)));
-        CKS(ensure(h, h->dots, (size_t)nrb * c * n * sizeof(T)));
+        CKS(ensure(h, h->sortbc, (size_t)sort_scratch_ints(n, c) * sizeof(int32_t)));
+        CKS(ensure(h, h->dots, assign_workspace_bytes<T>(d, n, c)));
         CKS(ensure(h, h->cnorm, c * sizeof(double)));
         CKS(ensure(h, h->lab_a, n * sizeof(int32_t)));
         CKS(ensure(h, h->lab_b, n * sizeof(int32_t)));
         const size_t np = (size_t)sweep_partials(d, n);
         size_t nsum = (size_t)nrb * (size_t)((n + 15) / 16);
         CKS(ensure(h, h->normp, 3 * (np > nsum ? np : nsum) * sizeof(double)));
-        CKS(ensure(h, h->chgp, ((n + kBlock - 1) / kBlock) * sizeof(double)));
+        CKS(ensure(h, h->chgp, (size_t)assign_partials_max(n) * sizeof(double)));
         CKS(ensure(h, h->status, 8 * sizeof(double)));
         CKS(ensure_host(h, (16 + 2 * (size_t)c) * sizeof(double)));
         status = (double*)h->status.p;
@@ -259,8 +260,8 @@ struct Engine {
     }
 
     void sort(const int32_t* labels) {
-        launch_label_sort(labels, n, c, counts(), perm(), (int32_t*)h->segb.p, (int32_t*)h->segl.p,
-                          (int32_t*)h->segf.p, (int32_t*)h->nseg.p, st);
+        launch_label_sort(labels, n, c, (int32_t*)h->sortbc.p, counts(), perm(), (int32_t*)h->segb.p,
+                          (int32_t*)h->segl.p, (int32_t*)h->segf.p, (int32_t*)h->nseg.p, st);
     }
 
     // C[:, k] <- mean over group k of Y (Y = X - S + Theta*inv_rho when with_d),
@@ -280,12 +281,12 @@ struct Engine {
     // Assignment pass: new = nearest centroid of every column of Y; status[3] = #changed.
     void assign(const T* Y, int64_t ldy, const T* C, const int32_t* old, int32_t* neu) {
         launch_col_sqnorm<T>(C, d, c, (double*)h->cnorm.p, st);
+        int g = 0;
         {
             ProfScope ps(h, st, RESPCA_KERNEL_DISTANCE, (double)d * n * sizeof(T));
-            launch_dots<T>(C, d, c, Y, ldy, n, (T*)h->dots.p, st);
+            g = launch_assign<T>(C, d, c, Y, ldy, n, (const double*)h->cnorm.p, old, neu, h->dots.p,
+                                 (double*)h->chgp.p, st);
         }
-        const int g = launch_argmin<T>((const T*)h->dots.p, nrb, c, n, (const double*)h->cnorm.p, old,
-                                       neu, (double*)h->chgp.p, st);
         launch_sum_partials((const double*)h->chgp.p, g, 1, status + 3, st);
     }
 
@@ -535,7 +536,7 @@ void respca_destroy(respca_handle h) {
     }
     for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
-                      &h->nseg, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b, &h->d2,
+                      &h->nseg, &h->sortbc, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b, &h->d2,
                       &h->chosen, &h->seeds, &h->u, &h->normp, &h->chgp, &h->status};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
