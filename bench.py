@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # dense, per MI355X
 
 WORKLOADS = {
     "large": dict(name="RES-PCA FP32 10000x10000 rank-100 + 10% sparse in [-100,100], c=100 (true "
@@ -120,6 +121,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"],
+                    help="distance contraction: split-bf16 MFMA with exact refinement, or FP32 MFMA")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the other precision in the same run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -136,39 +141,55 @@ def main():
     X = make_input(wl, np.float32)
     Xd = torch.from_numpy(X).to("cuda:0")
     d, n = X.shape
-    kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0)
-    L = rp.empty_colmajor(d, n, Xd.dtype, Xd.device)
-    S = rp.empty_colmajor(d, n, Xd.dtype, Xd.device)
-    lab = torch.empty(n, dtype=torch.int32, device=Xd.device)
-    out = (L, S, lab)
 
-    for _ in range(args.warmup):
-        r = rp.solve(Xd, out=out, **kw)
-    torch.cuda.synchronize()
-    rp.profile_enable(True)
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = rp.solve(Xd, out=out, **kw)
-        infos.append(r["info"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = rp.profile_query()
-    rp.profile_enable(False)
-    elapsed = t1 - t0
+    def timed(precision, steps, warmup, profile):
+        prec = rp.BF16GEMM_F32 if precision == "bf16" else rp.F32
+        kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=prec)
+        out = (rp.empty_colmajor(d, n, Xd.dtype, Xd.device),
+               rp.empty_colmajor(d, n, Xd.dtype, Xd.device),
+               torch.empty(n, dtype=torch.int32, device=Xd.device))
+        for _ in range(warmup):
+            rp.solve(Xd, out=out, **kw)
+        torch.cuda.synchronize()
+        if profile:
+            rp.profile_enable(True)
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos.append(rp.solve(Xd, out=out, **kw)["info"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = rp.profile_query() if profile else None
+        if profile:
+            rp.profile_enable(False)
+        return t1 - t0, infos, prof, out
+
+    elapsed, infos, prof, out = timed(args.precision, args.steps, args.warmup, True)
     ms_per_step = 1e3 * elapsed / args.steps
 
+    def roofline_of(name):
+        k = prof[name]
+        nl = max(k["launches"], 1)
+        secs = k["ms"] / 1e3 / nl
+        bpl, fpl = k["bytes"] / nl, k["flops"] / nl
+        mfma = "bf16" if args.precision == "bf16" else "fp32"
+        ridge = MFMA_PEAK_TFLOPS[mfma] * 1e12 / (HBM_PEAK_GBS * 1e9)
+        if fpl > 0 and fpl / bpl > ridge:
+            ach = fpl / secs / 1e12 if secs > 0 else 0.0
+            return {"bound": "mfma", "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS[mfma],
+                    "unit": "TFLOP/s", "frac": round(ach / MFMA_PEAK_TFLOPS[mfma], 4),
+                    "traffic": load_traffic(name, args.workload), "kernel": name,
+                    "flops_per_launch": fpl, "bytes_per_launch": bpl,
+                    "mean_launch_ms": round(secs * 1e3, 4)}
+        ach = bpl / secs / 1e9 if secs > 0 else 0.0
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(name, args.workload),
+                "kernel": name, "bytes_per_launch": bpl, "mean_launch_ms": round(secs * 1e3, 4)}
+
     dom = max(prof, key=lambda k: prof[k]["ms"])
-    pk = prof[dom]
-    per_launch_bytes = pk["bytes"] / max(pk["launches"], 1)
-    mean_s = pk["ms"] / 1e3 / max(pk["launches"], 1)
-    achieved = per_launch_bytes / mean_s / 1e9 if mean_s > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": load_traffic(dom, args.workload), "kernel": dom,
-                "bytes_per_launch": per_launch_bytes, "mean_launch_ms": round(mean_s * 1e3, 4)}
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None}
+                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
+                   "TFLOPs": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["ms"] > 0 and v["flops"] else None}
                for k, v in prof.items()}
     line = {
         "metric": "RPCA solves/s + sweep HBM GB/s at rel-err<=1e-5 (BF16/learned vs plain FP32)",
@@ -184,13 +205,26 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["name"], "d": d, "n": n, "c": wl["rank"],
-                   "precision": "plain FP32 (double accumulators)",
+                   "precision": ("split-bf16 MFMA distances + exact refinement; FP32 data, double "
+                                 "accumulators") if args.precision == "bf16" else
+                                "FP32 MFMA distances; FP32 data, double accumulators",
                    "iters": infos[-1]["iters"], "lloyd_steps": infos[-1]["lloyd_steps"],
-                   "init_lloyd": infos[-1]["init_lloyd"]},
+                   "init_lloyd": infos[-1]["init_lloyd"], "refined_columns": infos[-1]["refined"]},
         "sweep_GBps": kernels["sweep"]["GBps"],
+        "sweep_roofline": roofline_of("sweep"),
         "kernels": kernels,
-        "roofline": roofline,
+        "roofline": roofline_of(dom),
     }
+    if not args.no_compare:
+        other = "fp32" if args.precision == "bf16" else "bf16"
+        e2, i2, _, out2 = timed(other, args.steps, args.warmup, False)
+        Lr, Sr = out2[0].double(), out2[1].double()
+        line[f"{other}_solves_per_s"] = round(args.steps / e2, 4)
+        line[f"{other}_iters"] = i2[-1]["iters"]
+        line[f"rel_err_L_vs_{other}"] = float(torch.linalg.norm(out[0].double() - Lr) / torch.linalg.norm(Lr))
+        line[f"rel_err_S_vs_{other}"] = float(torch.linalg.norm(out[1].double() - Sr) /
+                                              max(float(torch.linalg.norm(Sr)), 1e-300))
+        line["labels_equal_fraction"] = float((out[2] == out2[2]).double().mean())
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, wl, infos[-1])
     print(json.dumps(line), flush=True)

@@ -81,6 +81,7 @@ typedef struct {
     double  dL;           /* ||L_t - L_{t-1}||_F / ||X||_F                              */
     double  dS;           /* ||S_t - S_{t-1}||_F / ||X||_F                              */
     double  rho_final;    /* rho used by the last iteration                             */
+    int64_t refined;      /* bf16 mode: column decisions re-taken exactly (all passes)   */
 } respca_info;
 
 typedef struct respca_handle_s *respca_handle;
@@ -167,9 +168,11 @@ typedef enum {
 } respca_kernel_id;
 
 respca_status respca_profile_enable(respca_handle h, int32_t enable);
-/* launches, total_ms and bytes are host outputs (any may be NULL). */
+/* launches, total_ms, bytes and flops are host outputs (any may be NULL).
+ * flops counts the algorithmic floating-point operations (the distance
+ * contraction's 2 c d n per pass; zero for the streaming kernels). */
 respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t *launches,
-                                   double *total_ms, double *bytes);
+                                   double *total_ms, double *bytes, double *flops);
 
 #ifdef __cplusplus
 }

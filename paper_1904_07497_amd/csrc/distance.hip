@@ -10,6 +10,17 @@
 // products go to a [slice][column][group] buffer; a second kernel sums the
 // slices in fixed order in double, forms the distances and takes the argmin
 // with 16 lanes per column.  FP64 runs use the VALU contraction in kernels.hip.
+//
+// bf16 mode: the same tiles, but each FP32 operand x is split into
+// x_hi = bf16(x) and x_lo = bf16(x - x_hi), and C.Y is accumulated in FP32 as
+// hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 (one instruction covers a
+// whole 32-row stage).  The dropped lo.lo term and the rounding of x_lo are
+// each below 2^-16 |c||y| per product, so with the FP32 accumulation error a
+// distance carries at most E = (3 * 2^-15 + 2 K 2^-24) ||C_k|| ||Y_j|| error
+// (K = rows summed in FP32).  The kernel also accumulates ||Y_j||^2; the argmin
+// kernel flags every column whose best and runner-up distances are not
+// separated by the bounds, and those columns are re-decided exactly (FP64
+// differences of the FP32 values) by a refinement kernel.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -22,11 +33,15 @@ namespace respca {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxCand = 8;  // candidate groups kept per near-tied column
 
 constexpr int kJT = 128;     // columns per workgroup
 constexpr int kKC = 128;     // groups per workgroup (8 blocks of 16)
 constexpr int kRT = 32;      // rows per LDS stage
 constexpr int kStride = 36;  // padded LDS stride (floats) of one staged column: conflict-free
+constexpr int kStrideH = 40; // padded LDS stride (bf16) of one staged column (80 bytes)
 
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
@@ -34,39 +49,124 @@ __device__ inline double wave_sum_d(double v) {
     return v;
 }
 
-// Stage rows [r, r + 32) of `cols` consecutive columns starting at col0 of a
-// column-major matrix into LDS (column-major, stride kStride); zero outside.
+// A 32-row stage of 128 consecutive columns of a column-major matrix, held in
+// registers between its global load and its LDS store (zero outside the
+// matrix), so that the next stage's loads are in flight during the MFMAs.
 template <bool VEC>
-__device__ inline void stage(float* __restrict__ dst, const float* __restrict__ src, int64_t ld,
-                             int64_t col0, int64_t ncols, int64_t r, int64_t rend) {
-    const int tid = threadIdx.x;
-    if constexpr (VEC) {
+struct StageRegs {
+    float4 v4[VEC ? 4 : 1];
+    float v1[VEC ? 1 : 16];
+
+    __device__ inline void load(const float* __restrict__ src, int64_t ld, int64_t col0,
+                                int64_t ncols, int64_t r, int64_t rend) {
+        const int tid = threadIdx.x;
+        if constexpr (VEC) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int col = p * 32 + (tid >> 3);
-            const int rr = (tid & 7) * 4;
-            const int64_t gj = col0 + col, gi = r + rr;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gj < ncols && gi < rend) v = *reinterpret_cast<const float4*>(src + gj * ld + gi);
-            *reinterpret_cast<float4*>(dst + col * kStride + rr) = v;
-        }
-    } else {
-#pragma unroll 4
-        for (int e = tid; e < 128 * kRT; e += 256) {
-            const int col = e >> 5, rr = e & 31;
-            const int64_t gj = col0 + col, gi = r + rr;
-            dst[col * kStride + rr] = (gj < ncols && gi < rend) ? src[gj * ld + gi] : 0.f;
+            for (int p = 0; p < 4; ++p) {
+                const int col = p * 32 + (tid >> 3);
+                const int rr = (tid & 7) * 4;
+                const int64_t gj = col0 + col, gi = r + rr;
+                v4[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gj < ncols && gi < rend) v4[p] = *reinterpret_cast<const float4*>(src + gj * ld + gi);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int e = tid + 256 * p, col = e >> 5, rr = e & 31;
+                const int64_t gj = col0 + col, gi = r + rr;
+                v1[p] = (gj < ncols && gi < rend) ? src[gj * ld + gi] : 0.f;
+            }
         }
     }
-}
 
-template <bool VEC>
+    // Sum of squares of each staged column's 32 rows, accumulated into acc[]:
+    // VEC: 8 consecutive lanes share a column (acc[p], column p*32 + tid/8, valid
+    // in lanes with tid % 8 == 0); scalar: 32 lanes share a column (acc[p],
+    // column tid/32 + 8p, valid in lanes with tid % 32 == 0).
+    __device__ inline void col_sumsq(float* acc) const {
+        if constexpr (VEC) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                float t = v4[p].x * v4[p].x + v4[p].y * v4[p].y + v4[p].z * v4[p].z + v4[p].w * v4[p].w;
+                t += __shfl_xor(t, 1);
+                t += __shfl_xor(t, 2);
+                t += __shfl_xor(t, 4);
+                acc[p] += t;
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                float t = v1[p] * v1[p];
+#pragma unroll
+                for (int o = 1; o < 32; o <<= 1) t += __shfl_xor(t, o);
+                acc[p] += t;
+            }
+        }
+    }
+
+    // Store as bf16 high and low parts (x = hi + lo + O(2^-16 x)), stride kStrideH.
+    __device__ inline void store_split(__bf16* __restrict__ hi, __bf16* __restrict__ lo) const {
+        const int tid = threadIdx.x;
+        if constexpr (VEC) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int col = p * 32 + (tid >> 3);
+                const int rr = (tid & 7) * 4;
+                const float x[4] = {v4[p].x, v4[p].y, v4[p].z, v4[p].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const __bf16 h = (__bf16)x[e];
+                    hi[col * kStrideH + rr + e] = h;
+                    lo[col * kStrideH + rr + e] = (__bf16)(x[e] - (float)h);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int e = tid + 256 * p, col = e >> 5, rr = e & 31;
+                const __bf16 h = (__bf16)v1[p];
+                hi[col * kStrideH + rr] = h;
+                lo[col * kStrideH + rr] = (__bf16)(v1[p] - (float)h);
+            }
+        }
+    }
+
+    __device__ inline void store(float* __restrict__ dst) const {
+        const int tid = threadIdx.x;
+        if constexpr (VEC) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int col = p * 32 + (tid >> 3);
+                const int rr = (tid & 7) * 4;
+                *reinterpret_cast<float4*>(dst + col * kStride + rr) = v4[p];
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int e = tid + 256 * p, col = e >> 5, rr = e & 31;
+                dst[col * kStride + rr] = v1[p];
+            }
+        }
+    }
+};
+
+template <bool VEC, bool BF16>
 __global__ __launch_bounds__(256) void k_dist_mfma(const float* __restrict__ C, int64_t d, int c,
                                                    int kpad, const float* __restrict__ Y, int64_t ldy,
                                                    int64_t n, int slice_rows,
-                                                   float* __restrict__ part) {
-    __shared__ __attribute__((aligned(16))) float Ys[kJT * kStride];
-    __shared__ __attribute__((aligned(16))) float Cs[kKC * kStride];
+                                                   float* __restrict__ part,
+                                                   float* __restrict__ ynorm_part,
+                                                   int* __restrict__ counters) {
+    // fp32 mode: Ys, Cs as floats; bf16 mode: hi/lo halves of both operands.
+    constexpr size_t kF32Bytes = 2 * kJT * kStride * sizeof(float);
+    constexpr size_t kBf16Bytes = 2 * (kJT + kKC) * kStrideH * sizeof(__bf16);
+    __shared__ __attribute__((aligned(16))) char smem[kF32Bytes > kBf16Bytes ? kF32Bytes : kBf16Bytes];
+    float* Ys = reinterpret_cast<float*>(smem);
+    float* Cs = Ys + kJT * kStride;
+    __bf16* Yh = reinterpret_cast<__bf16*>(smem);
+    __bf16* Yl = Yh + kJT * kStrideH;
+    __bf16* Ch = Yl + kJT * kStrideH;
+    __bf16* Cl = Ch + kKC * kStrideH;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int q = lane & 15, g = lane >> 4;
     const int64_t j0 = (int64_t)blockIdx.x * kJT;
@@ -75,6 +175,12 @@ __global__ __launch_bounds__(256) void k_dist_mfma(const float* __restrict__ C, 
     const int64_t r0 = (int64_t)s * slice_rows;
     const int64_t r1 = r0 + slice_rows < d ? r0 + slice_rows : d;
     const int nkb = (kpad - k0 < kKC ? kpad - k0 : kKC) / 16;
+    if (BF16 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid < 4)
+        counters[tid] = 0;   // refinement list length, its changed count: fresh for this pass
+    constexpr int NCOL = VEC ? 4 : 16;
+    float ycol[NCOL];
+#pragma unroll
+    for (int p = 0; p < NCOL; ++p) ycol[p] = 0.f;
 
     floatx4 acc[2][8];
 #pragma unroll
@@ -82,35 +188,86 @@ __global__ __launch_bounds__(256) void k_dist_mfma(const float* __restrict__ C, 
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    StageRegs<VEC> ry, rc;
+    if (r0 < r1) {
+        ry.load(Y, ldy, j0, n, r0, r1);
+        rc.load(C, d, k0, c, r0, r1);
+    }
     for (int64_t r = r0; r < r1; r += kRT) {
-        stage<VEC>(Ys, Y, ldy, j0, n, r, r1);
-        stage<VEC>(Cs, C, d, k0, c, r, r1);
-        __syncthreads();
-        // MFMA step m: lane group g supplies row 8g + m of the stage (same map for both operands)
-        float a[2][8];
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb) {
-            const float* p = Ys + (wave * 32 + jb * 16 + q) * kStride + g * 8;
-            const float4 u = *reinterpret_cast<const float4*>(p);
-            const float4 w = *reinterpret_cast<const float4*>(p + 4);
-            a[jb][0] = u.x; a[jb][1] = u.y; a[jb][2] = u.z; a[jb][3] = u.w;
-            a[jb][4] = w.x; a[jb][5] = w.y; a[jb][6] = w.z; a[jb][7] = w.w;
+        if constexpr (BF16) {
+            ry.col_sumsq(ycol);
+            ry.store_split(Yh, Yl);
+            rc.store_split(Ch, Cl);
+        } else {
+            ry.store(Ys);
+            rc.store(Cs);
         }
+        __syncthreads();
+        if (r + kRT < r1) {                     // next stage's loads overlap this stage's MFMAs
+            ry.load(Y, ldy, j0, n, r + kRT, r1);
+            rc.load(C, d, k0, c, r + kRT, r1);
+        }
+        if constexpr (BF16) {
+            // one 16x16x32 instruction covers the stage: lane group g holds rows 8g..8g+7
+            bf16x8 ahi[2], alo[2];
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) {
-            if (kb < nkb) {
-                const float* p = Cs + (kb * 16 + q) * kStride + g * 8;
+            for (int jb = 0; jb < 2; ++jb) {
+                const int col = wave * 32 + jb * 16 + q;
+                ahi[jb] = *reinterpret_cast<const bf16x8*>(Yh + col * kStrideH + g * 8);
+                alo[jb] = *reinterpret_cast<const bf16x8*>(Yl + col * kStrideH + g * 8);
+            }
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb) {
+                if (kb < nkb) {
+                    const int row = kb * 16 + q;
+                    const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Ch + row * kStrideH + g * 8);
+                    const bf16x8 blo = *reinterpret_cast<const bf16x8*>(Cl + row * kStrideH + g * 8);
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb) {
+                        acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[jb], bhi, acc[jb][kb], 0, 0, 0);
+                        acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[jb], blo, acc[jb][kb], 0, 0, 0);
+                        acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[jb], bhi, acc[jb][kb], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            // MFMA step m: lane group g supplies row 8g + m of the stage (same map for both operands)
+            float a[2][8];
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) {
+                const float* p = Ys + (wave * 32 + jb * 16 + q) * kStride + g * 8;
                 const float4 u = *reinterpret_cast<const float4*>(p);
                 const float4 w = *reinterpret_cast<const float4*>(p + 4);
-                const float b[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
+                a[jb][0] = u.x; a[jb][1] = u.y; a[jb][2] = u.z; a[jb][3] = u.w;
+                a[jb][4] = w.x; a[jb][5] = w.y; a[jb][6] = w.z; a[jb][7] = w.w;
+            }
 #pragma unroll
-                for (int jb = 0; jb < 2; ++jb)
+            for (int kb = 0; kb < 8; ++kb) {
+                if (kb < nkb) {
+                    const float* p = Cs + (kb * 16 + q) * kStride + g * 8;
+                    const float4 u = *reinterpret_cast<const float4*>(p);
+                    const float4 w = *reinterpret_cast<const float4*>(p + 4);
+                    const float b[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
 #pragma unroll
-                    for (int m = 0; m < 8; ++m)
-                        acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jb][m], b[m], acc[jb][kb], 0, 0, 0);
+                    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                        for (int m = 0; m < 8; ++m)
+                            acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jb][m], b[m], acc[jb][kb], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
+    }
+    if constexpr (BF16) {
+        if (blockIdx.z == 0) {
+#pragma unroll
+            for (int p = 0; p < NCOL; ++p) {
+                const int col = VEC ? p * 32 + (tid >> 3) : (tid >> 5) + 8 * p;
+                const bool owner = VEC ? (tid & 7) == 0 : (tid & 31) == 0;
+                const int64_t j = j0 + col;
+                if (owner && j < n) ynorm_part[(int64_t)s * n + j] = ycol[p];
+            }
+        }
     }
     // lane holds D[column 4g + v][group q] of each 16 x 16 tile
 #pragma unroll
@@ -166,6 +323,184 @@ __global__ __launch_bounds__(256) void k_dist_argmin(const float* __restrict__ p
     if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// bf16 mode: distances with their error bounds.  Lane q of a column's 16
+// lanes takes groups q, q+16, ...  The provisional label is the group with the
+// smallest distance; every group whose distance interval [d - 2E, d + 2E] reaches
+// below the smallest upper end is a candidate.  A column with more than one
+// candidate goes on the refinement list (with up to kMaxCand candidates, or all
+// groups) and its label is decided there; the others count their changes here.
+__global__ __launch_bounds__(256) void k_dist_argmin_bounded(
+    const float* __restrict__ part, const float* __restrict__ ynorm_part, int nslices, int64_t n,
+    int c, int kpad, float eps_rel, const double* __restrict__ cnorm,
+    const int32_t* __restrict__ old_labels, int32_t* __restrict__ new_labels,
+    double* __restrict__ changed_partial, int* __restrict__ counters, int32_t* __restrict__ list,
+    int32_t* __restrict__ cand) {
+    __shared__ double sh[4];
+    const int q = threadIdx.x & 15;
+    const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = j < n;
+    double ynorm = 0.0;
+    if (live)
+        for (int s = 0; s < nslices; ++s) ynorm += (double)ynorm_part[(int64_t)s * n + j];
+    const double ylen = sqrt(ynorm);
+    // pass 1: best distance and the smallest upper bound
+    double bestd = INFINITY, upper = INFINITY;
+    int bestk = INT_MAX;
+    if (live)
+        for (int k = q; k < c; k += 16) {
+            double dot = 0.0;
+            for (int s = 0; s < nslices; ++s) dot += (double)part[((int64_t)s * n + j) * kpad + k];
+            const double dist = cnorm[k] - 2.0 * dot;
+            const double e = 2.0 * eps_rel * sqrt(cnorm[k]) * ylen;
+            if (dist < bestd) { bestd = dist; bestk = k; }
+            upper = fmin(upper, dist + e);
+        }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        const double od = __shfl_xor(bestd, o, 16);
+        const int ok = __shfl_xor(bestk, o, 16);
+        if (od < bestd || (od == bestd && ok < bestk)) { bestd = od; bestk = ok; }
+        upper = fmin(upper, __shfl_xor(upper, o, 16));
+    }
+    // pass 2: candidates (lower end below the smallest upper end)
+    unsigned long long mine = 0;  // bit t: group q + 16 t is a candidate (first 64 per lane)
+    int ncand = 0;
+    if (live)
+        for (int k = q, t = 0; k < c; k += 16, ++t) {
+            double dot = 0.0;
+            for (int s = 0; s < nslices; ++s) dot += (double)part[((int64_t)s * n + j) * kpad + k];
+            const double dist = cnorm[k] - 2.0 * dot;
+            const double e = 2.0 * eps_rel * sqrt(cnorm[k]) * ylen;
+            if (dist - e <= upper) { ++ncand; if (t < 64) mine |= 1ull << t; }
+        }
+    int total = ncand;
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) total += __shfl_xor(total, o, 16);
+    double changed = 0.0;
+    const int lab = bestk == INT_MAX ? 0 : bestk;
+    if (live && total <= 1) {
+        if (q == 0) {
+            new_labels[j] = lab;
+            changed = old_labels[j] != lab ? 1.0 : 0.0;
+        }
+    } else if (live) {
+        // candidate list in increasing group order: rank = candidates of lower groups
+        int slot = 0;
+        if (q == 0) slot = atomicAdd(&counters[0], 1);
+        slot = __shfl(slot, (threadIdx.x & 63) & ~15);
+        if (q == 0) { list[slot] = (int32_t)j; new_labels[j] = lab; }
+        int32_t* cj = cand + (int64_t)j * kMaxCand;
+        if (total > kMaxCand) {
+            if (q == 0) cj[0] = -1;          // refine against every group
+        } else {
+            // groups in increasing order: walk k = 0..c-1, each owned by lane k % 16
+            int before = 0;                  // candidates of this lane's groups already placed
+            for (int k0 = 0; k0 < c; k0 += 16) {
+                const int t = k0 / 16;
+                const bool is = (q + k0 < c) && t < 64 && ((mine >> t) & 1ull);
+                const unsigned long long bal = __ballot(is);
+                const int sub = (threadIdx.x & 63) & ~15;         // this column's 16 lanes
+                const unsigned long long grp = (bal >> sub) & 0xFFFFull;
+                if (is) cj[before + __popcll(grp & ((1ull << q) - 1ull))] = k0 + q;
+                before += __popcll(grp);
+            }
+            if (q == 0 && total < kMaxCand) cj[total] = -2;   // end marker
+        }
+    }
+    changed = wave_sum_d(changed);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = changed;
+    __syncthreads();
+    if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Exact squared distances (double differences of the FP32 values) for the
+// refinement list.  Workgroup (slot, t) takes list items slot, slot + gridDim.x,
+// ... and their t-th candidate; 256 threads x 4 independent loads per step.
+constexpr int kRefineSlots = 256;
+
+__global__ __launch_bounds__(256) void k_refine_dist(const float* __restrict__ C, int64_t d, int c,
+                                                     const float* __restrict__ Y, int64_t ldy,
+                                                     const int* __restrict__ counters,
+                                                     const int32_t* __restrict__ list,
+                                                     const int32_t* __restrict__ cand,
+                                                     double* __restrict__ refdist) {
+    __shared__ double sh[4];
+    const int count = counters[0];
+    const int t = blockIdx.y;
+    for (int item = blockIdx.x; item < count; item += gridDim.x) {
+        const int64_t j = list[item];
+        // entries after the end marker (-2) are stale; -1 (every group) is handled per wave
+        bool valid = true;
+        for (int u = 0; u <= t; ++u) valid = valid && cand[j * kMaxCand + u] >= 0;
+        const int k = valid ? cand[j * kMaxCand + t] : -1;   // uniform across the workgroup
+        if (k < 0 || k >= c) continue;
+        const float* y = Y + j * ldy;
+        const float* ck = C + (int64_t)k * d;
+        double acc = 0.0;
+        for (int64_t i = threadIdx.x; i < d; i += 1024) {
+            double e[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t ii = i + 256 * u;
+                e[u] = ii < d ? (double)y[ii] - (double)ck[ii] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += e[u] * e[u];
+        }
+        acc = wave_sum_d(acc);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) refdist[(int64_t)item * kMaxCand + t] = sh[0] + sh[1] + sh[2] + sh[3];
+    }
+}
+
+// Per list item: smallest exact distance among its candidates (lowest group on
+// ties).  Items with more than kMaxCand candidates are scored against every
+// group by one wave here (rare).
+__global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ C, int64_t d, int c,
+                                                     const float* __restrict__ Y, int64_t ldy,
+                                                     const int* __restrict__ counters,
+                                                     const int32_t* __restrict__ list,
+                                                     const int32_t* __restrict__ cand,
+                                                     const double* __restrict__ refdist,
+                                                     const int32_t* __restrict__ old_labels,
+                                                     int32_t* __restrict__ new_labels,
+                                                     int* __restrict__ changed_count) {
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= counters[0]) return;
+    const int64_t j = list[item];
+    const int32_t* cj = cand + j * kMaxCand;
+    double best = INFINITY;
+    int bestk = INT_MAX;
+    if (cj[0] == -1) {
+        const float* y = Y + j * ldy;
+        for (int k = 0; k < c; ++k) {
+            const float* ck = C + (int64_t)k * d;
+            double acc = 0.0;
+            for (int64_t i = lane; i < d; i += 64) {
+                const double e = (double)y[i] - (double)ck[i];
+                acc += e * e;
+            }
+            acc = wave_sum_d(acc);
+            if (acc < best) { best = acc; bestk = k; }
+        }
+    } else {
+        for (int t = 0; t < kMaxCand; ++t) {
+            const int k = cj[t];
+            if (k < 0) break;
+            const double dist = refdist[(int64_t)item * kMaxCand + t];
+            if (dist < best || (dist == best && k < bestk)) { best = dist; bestk = k; }
+        }
+    }
+    if (lane == 0) {
+        const int lab = bestk == INT_MAX ? 0 : bestk;
+        new_labels[j] = lab;
+        if (old_labels[j] != lab) atomicAdd(changed_count, 1);
+    }
+}
+
 struct DistPlan {
     int kpad, ntiles, nkc, slices, slice_rows;
 };
@@ -190,10 +525,14 @@ DistPlan plan_f32(int64_t d, int64_t n, int c) {
 
 }  // namespace
 
+// Workspace layout (float runs): partial dots [slices][n][kpad] | column norm
+// partials [slices][n] | (256-aligned) counters (int x 4) | refinement list [n] |
+// candidates [n][kMaxCand] | (8-aligned) exact distances [n][kMaxCand] (double).
 template <>
 size_t assign_workspace_bytes<float>(int64_t d, int64_t n, int c) {
     const DistPlan p = plan_f32(d, n, c);
-    return (size_t)p.slices * (size_t)n * (size_t)p.kpad * sizeof(float);
+    return (size_t)p.slices * (size_t)n * (size_t)(p.kpad + 1) * sizeof(float) + 256 + 16 +
+           (size_t)n * (1 + kMaxCand) * sizeof(int32_t) + 8 + (size_t)n * kMaxCand * sizeof(double);
 }
 
 template <>
@@ -204,33 +543,73 @@ size_t assign_workspace_bytes<double>(int64_t d, int64_t n, int c) {
 template <>
 int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64_t ldy, int64_t n,
                          const double* cnorm, const int32_t* old_labels, int32_t* new_labels,
-                         void* work, double* changed_partial, hipStream_t st) {
+                         void* work, double* changed_partial, bool bf16, int* changed_extra,
+                         hipStream_t st) {
     const DistPlan p = plan_f32(d, n, c);
     float* part = (float*)work;
+    float* ynorm = part + (size_t)p.slices * n * p.kpad;
+    char* tail = (char*)(ynorm + (size_t)p.slices * n);
+    tail = (char*)(((uintptr_t)tail + 255) & ~(uintptr_t)255);
+    int* counters = (int*)tail;                       // [0] list length, [1] refined changes
+    int32_t* list = (int32_t*)(tail + 16);
+    int32_t* cand = list + n;
+    double* refdist = (double*)(((uintptr_t)(cand + n * kMaxCand) + 7) & ~(uintptr_t)7);
     const dim3 grid(p.ntiles, p.slices, p.nkc);
     const bool vec = (d % 4 == 0) && (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0) &&
                      (reinterpret_cast<uintptr_t>(C) % 16 == 0);
-    if (vec)
-        k_dist_mfma<true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part);
-    else
-        k_dist_mfma<false><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part);
     const int gb = (int)((n + 15) / 16);
-    k_dist_argmin<<<gb, 256, 0, st>>>(part, p.slices, n, c, p.kpad, cnorm, old_labels, new_labels,
-                                      changed_partial);
+    if (!bf16) {
+        if (vec)
+            k_dist_mfma<true, false><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows,
+                                                           part, ynorm, counters);
+        else
+            k_dist_mfma<false, false><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows,
+                                                            part, ynorm, counters);
+        k_dist_argmin<<<gb, 256, 0, st>>>(part, p.slices, n, c, p.kpad, cnorm, old_labels,
+                                          new_labels, changed_partial);
+        return gb;
+    }
+    if (vec)
+        k_dist_mfma<true, true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
+                                                      ynorm, counters);
+    else
+        k_dist_mfma<false, true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
+                                                       ynorm, counters);
+    // error bound factor (doubled for safety): split products, 3 * 2^-16 per
+    // product, plus FP32 accumulation over one slice of rows
+    const float eps_rel = (float)(2.0 * (3.0 * std::ldexp(1.0, -16) + p.slice_rows * std::ldexp(1.0, -24)));
+    k_dist_argmin_bounded<<<gb, 256, 0, st>>>(part, ynorm, p.slices, n, c, p.kpad, eps_rel, cnorm,
+                                              old_labels, new_labels, changed_partial, counters, list,
+                                              cand);
+    k_refine_dist<<<dim3(kRefineSlots, kMaxCand), 256, 0, st>>>(C, d, c, Y, ldy, counters, list,
+                                                                  cand, refdist);
+    k_refine_pick<<<(unsigned)((n + 3) / 4), 256, 0, st>>>(C, d, c, Y, ldy, counters, list, cand,
+                                                           refdist, old_labels, new_labels,
+                                                           counters + 1);
+    // refined changes are added to the partial list by the caller via changed_extra
+    if (changed_extra) *changed_extra = 1;
     return gb;
+}
+
+int* assign_refine_counters(void* work, int64_t d, int64_t n, int c) {
+    const DistPlan p = plan_f32(d, n, c);
+    float* part = (float*)work;
+    float* ynorm = part + (size_t)p.slices * n * p.kpad;
+    char* tail = (char*)(ynorm + (size_t)p.slices * n);
+    tail = (char*)(((uintptr_t)tail + 255) & ~(uintptr_t)255);
+    return (int*)tail;
 }
 
 template <>
 int launch_assign<double>(const double* C, int64_t d, int c, const double* Y, int64_t ldy,
                           int64_t n, const double* cnorm, const int32_t* old_labels,
-                          int32_t* new_labels, void* work, double* changed_partial,
-                          hipStream_t st) {
+                          int32_t* new_labels, void* work, double* changed_partial, bool,
+                          int* changed_extra, hipStream_t st) {
+    if (changed_extra) *changed_extra = 0;
     double* part = (double*)work;
     launch_dots<double>(C, d, c, Y, ldy, n, part, st);
     return launch_argmin<double>(part, row_blocks(d), c, n, cnorm, old_labels, new_labels,
                                  changed_partial, st);
 }
-
-int assign_partials(int64_t n) { return (int)((n + 15) / 16); }
 
 }  // namespace respca

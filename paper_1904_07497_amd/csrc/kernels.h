@@ -20,6 +20,7 @@ inline int max_segments(int64_t n, int c) { return (int)((n + kSegCols - 1) / kS
 template <typename T>
 void launch_zero2d(T* A, int64_t ld, int64_t d, int64_t n, hipStream_t st);
 void launch_zero_i32(int32_t* a, int64_t count, hipStream_t st);
+void launch_zero_f64(double* a, hipStream_t st);
 
 // Sum of squares of X in double: per-workgroup partials, count returned.
 template <typename T>
@@ -78,10 +79,16 @@ int launch_argmin(const T* part, int nrb, int c, int64_t n, const double* cnorm,
 // count partials.  `work` must hold assign_workspace_bytes<T>(d, n, c).
 template <typename T>
 size_t assign_workspace_bytes(int64_t d, int64_t n, int c);
+// bf16 (float runs only): split-bf16 MFMA contraction with bounded error and
+// exact refinement of near-tied columns; their changes are counted in the int at
+// assign_refine_counters(work)[1] (*changed_extra is set to 1 when that applies).
 template <typename T>
 int launch_assign(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t n,
                   const double* cnorm, const int32_t* old_labels, int32_t* new_labels, void* work,
-                  double* changed_partial, hipStream_t st);
+                  double* changed_partial, bool bf16, int* changed_extra, hipStream_t st);
+int* assign_refine_counters(void* work, int64_t d, int64_t n, int c);
+// out[0] += counter (or out[0] = counter when set), one thread.
+void launch_add_int(const int* counter, double* out, hipStream_t st, bool set = false);
 inline int64_t assign_partials_max(int64_t n) { return (n + 15) / 16; }
 
 // k-means++ helpers.

@@ -555,6 +555,8 @@ void launch_zero2d(T* A, int64_t ld, int64_t d, int64_t n, hipStream_t st) {
     k_zero2d<T><<<grid_cap(d * n, kBlock * 8), kBlock, 0, st>>>(A, ld, d, n);
 }
 
+void launch_zero_f64(double* a, hipStream_t st) { k_zero2d<double><<<1, 64, 0, st>>>(a, 1, 1, 1); }
+
 void launch_zero_i32(int32_t* a, int64_t count, hipStream_t st) {
     k_zero_i32<<<grid_cap(count, kBlock * 8), kBlock, 0, st>>>(a, count);
 }
@@ -566,6 +568,14 @@ int launch_sumsq(const T* X, int64_t ldx, int64_t d, int64_t n, double* partial,
     const int ncb = (int)((n + jc - 1) / jc);
     k_sumsq<T><<<dim3(ncb, nrb), kBlock, 0, st>>>(X, ldx, d, n, jc, partial);
     return nrb * ncb;
+}
+
+__global__ void k_add_int(const int* counter, double* out, int set) {
+    if (threadIdx.x == 0) out[0] = (set ? 0.0 : out[0]) + (double)counter[0];
+}
+
+void launch_add_int(const int* counter, double* out, hipStream_t st, bool set) {
+    k_add_int<<<1, 64, 0, st>>>(counter, out, set ? 1 : 0);
 }
 
 void launch_sum_partials(const double* partial, int count, int width, double* out,

@@ -27,7 +27,7 @@ struct DevBuf {
 struct ProfPending {
     int kernel;
     hipEvent_t a, b;
-    double bytes;
+    double bytes, flops;
 };
 
 struct respca_handle_s {
@@ -38,6 +38,7 @@ struct respca_handle_s {
     int64_t prof_launches[RESPCA_KERNEL_COUNT] = {};
     double prof_ms[RESPCA_KERNEL_COUNT] = {};
     double prof_bytes[RESPCA_KERNEL_COUNT] = {};
+    double prof_flops[RESPCA_KERNEL_COUNT] = {};
     std::vector<ProfPending> prof_pending;
     std::vector<hipEvent_t> prof_pool;
     DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, sortbc, pmeans, dots, cnorm, lab_a,
@@ -100,9 +101,10 @@ struct ProfScope {
     respca_handle h;
     hipStream_t st;
     int kernel;
-    double bytes;
+    double bytes, flops;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(respca_handle h_, hipStream_t st_, int k, double by) : h(h_), st(st_), kernel(k), bytes(by) {
+    ProfScope(respca_handle h_, hipStream_t st_, int k, double by, double fl = 0.0)
+        : h(h_), st(st_), kernel(k), bytes(by), flops(fl) {
         if (!h->prof_on) return;
         a = take();
         b = take();
@@ -111,7 +113,7 @@ struct ProfScope {
     ~ProfScope() {
         if (!h->prof_on || !a || !b) return;
         (void)hipEventRecord(b, st);
-        h->prof_pending.push_back({kernel, a, b, bytes});
+        h->prof_pending.push_back({kernel, a, b, bytes, flops});
     }
     hipEvent_t take() {
         if (!h->prof_pool.empty()) {
@@ -133,6 +135,7 @@ void prof_resolve(respca_handle h) {
             h->prof_launches[p.kernel] += 1;
             h->prof_ms[p.kernel] += ms;
             h->prof_bytes[p.kernel] += p.bytes;
+            h->prof_flops[p.kernel] += p.flops;
         }
         h->prof_pool.push_back(p.a);
         h->prof_pool.push_back(p.b);
@@ -186,8 +189,6 @@ respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_
     if (r.max_lloyd < 1) return fail(h, RESPCA_ERR_INVALID, "max_lloyd must be >= 1");
     if (r.precision != RESPCA_F64 && r.precision != RESPCA_F32 && r.precision != RESPCA_BF16GEMM_F32)
         return fail(h, RESPCA_ERR_INVALID, "unknown precision");
-    if (r.precision == RESPCA_BF16GEMM_F32)
-        return fail(h, RESPCA_ERR_UNSUPPORTED, "bf16 distance path not built");
     return RESPCA_OK;
 }
 
@@ -210,8 +211,10 @@ struct Engine {
     hipStream_t st;
     int64_t d, n;
     int c;
+    bool bf16;       // split-bf16 MFMA distances with exact refinement (float runs)
     int nrb;
-    double* status;  // device: [0..2] norms^2, [3] changed count
+    double* status;  // device: [0..2] norms^2, [3] changed count, [4] refined columns
+    int64_t refined = 0;
 
     respca_status setup() {
         nrb = row_blocks(d);
@@ -243,9 +246,10 @@ struct Engine {
 
     respca_status readback(double out[4]) {
         CK(hipGetLastError());
-        CK(hipMemcpyAsync(h->hstage, status, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(hipMemcpyAsync(h->hstage, status, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
         for (int i = 0; i < 4; ++i) out[i] = h->hstage[i];
+        refined += (int64_t)h->hstage[4];
         prof_resolve(h);
         return RESPCA_OK;
     }
@@ -281,13 +285,21 @@ struct Engine {
     // Assignment pass: new = nearest centroid of every column of Y; status[3] = #changed.
     void assign(const T* Y, int64_t ldy, const T* C, const int32_t* old, int32_t* neu) {
         launch_col_sqnorm<T>(C, d, c, (double*)h->cnorm.p, st);
-        int g = 0;
+        int g = 0, extra = 0;
         {
-            ProfScope ps(h, st, RESPCA_KERNEL_DISTANCE, (double)d * n * sizeof(T));
+            ProfScope ps(h, st, RESPCA_KERNEL_DISTANCE, (double)d * n * sizeof(T),
+                         2.0 * (double)c * (double)d * (double)n);
             g = launch_assign<T>(C, d, c, Y, ldy, n, (const double*)h->cnorm.p, old, neu, h->dots.p,
-                                 (double*)h->chgp.p, st);
+                                 (double*)h->chgp.p, bf16, &extra, st);
         }
         launch_sum_partials((const double*)h->chgp.p, g, 1, status + 3, st);
+        if (extra) {
+            int* cnt = assign_refine_counters(h->dots.p, d, n, c);
+            launch_add_int(cnt + 1, status + 3, st);
+            launch_add_int(cnt, status + 4, st, true);
+        } else {
+            launch_zero_f64(status + 4, st);
+        }
     }
 
     // Lloyd passes on the columns of Y from (cur, C); see oracle_lloyd for the
@@ -378,7 +390,7 @@ template <typename T>
 respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, const T* X,
                       int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, int32_t* labels,
                       respca_info* info, hipStream_t st) {
-    Engine<T> e{h, st, d, n, r.c};
+    Engine<T> e{h, st, d, n, r.c, r.precision == RESPCA_BF16GEMM_F32};
     CKS(e.setup());
     CKS(ensure(h, h->theta, (size_t)d * n * sizeof(T)));
     CKS(ensure(h, h->cbuf, (size_t)d * r.c * sizeof(T)));
@@ -444,6 +456,7 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
     }
     if (labels) CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     CK(hipStreamSynchronize(st));
+    info->refined = e.refined;
     return (respca_status)info->status;
 }
 
@@ -452,7 +465,7 @@ respca_status iterate_t(respca_handle h, const Resolved& r, int64_t d, int64_t n
                         int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th, int64_t ldt,
                         int32_t* labels, T* C, double* rho, int iters, double* norms_out,
                         respca_info* info, hipStream_t st) {
-    Engine<T> e{h, st, d, n, r.c};
+    Engine<T> e{h, st, d, n, r.c, r.precision == RESPCA_BF16GEMM_F32};
     CKS(e.setup());
     int32_t* cur = (int32_t*)h->lab_a.p;
     int32_t* alt = (int32_t*)h->lab_b.p;
@@ -479,6 +492,7 @@ respca_status iterate_t(respca_handle h, const Resolved& r, int64_t d, int64_t n
     *rho = rr;
     CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     CK(hipStreamSynchronize(st));
+    info->refined = e.refined;
     info->status = RESPCA_OK;
     return RESPCA_OK;
 }
@@ -486,7 +500,7 @@ respca_status iterate_t(respca_handle h, const Resolved& r, int64_t d, int64_t n
 template <typename T>
 respca_status kmeans_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, const T* Y,
                        int64_t ldy, int32_t* labels, T* C, respca_info* info, hipStream_t st) {
-    Engine<T> e{h, st, d, n, r.c};
+    Engine<T> e{h, st, d, n, r.c, r.precision == RESPCA_BF16GEMM_F32};
     CKS(e.setup());
     int32_t* cur = (int32_t*)h->lab_a.p;
     int32_t* alt = (int32_t*)h->lab_b.p;
@@ -495,6 +509,7 @@ respca_status kmeans_t(respca_handle h, const Resolved& r, int64_t d, int64_t n,
     info->init_lloyd = steps;
     CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     CK(hipStreamSynchronize(st));
+    info->refined = e.refined;
     info->status = RESPCA_OK;
     return RESPCA_OK;
 }
@@ -590,12 +605,13 @@ respca_status respca_profile_enable(respca_handle h, int32_t enable) {
         h->prof_launches[k] = 0;
         h->prof_ms[k] = 0.0;
         h->prof_bytes[k] = 0.0;
+        h->prof_flops[k] = 0.0;
     }
     return RESPCA_OK;
 }
 
 respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t* launches,
-                                   double* total_ms, double* bytes) {
+                                   double* total_ms, double* bytes, double* flops) {
     if (!h || kernel < 0 || kernel >= RESPCA_KERNEL_COUNT) return RESPCA_ERR_INVALID;
     if (!h->prof_pending.empty()) {
         if (hipSetDevice(h->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
@@ -605,6 +621,7 @@ respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t* lau
     if (launches) *launches = h->prof_launches[kernel];
     if (total_ms) *total_ms = h->prof_ms[kernel];
     if (bytes) *bytes = h->prof_bytes[kernel];
+    if (flops) *flops = h->prof_flops[kernel];
     return RESPCA_OK;
 }
 

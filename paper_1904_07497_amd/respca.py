@@ -39,7 +39,7 @@ class Params(ct.Structure):
 class Info(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("lloyd_steps", ct.c_int32), ("init_lloyd", ct.c_int32),
                 ("status", ct.c_int32), ("primal", ct.c_double), ("dL", ct.c_double),
-                ("dS", ct.c_double), ("rho_final", ct.c_double)]
+                ("dS", ct.c_double), ("rho_final", ct.c_double), ("refined", ct.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -85,7 +85,7 @@ def lib():
         L.respca_profile_enable.argtypes = [vp, i32]
         L.respca_profile_query.restype = i32
         L.respca_profile_query.argtypes = [vp, i32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
-                                           ct.POINTER(ct.c_double)]
+                                           ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
         L.respca_kmeans.restype = i32
         L.respca_kmeans.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, vp,
                                     ct.POINTER(Info), vp]
@@ -283,12 +283,12 @@ def profile_enable(on: bool = True, device: int = 0):
 
 
 def profile_query(device: int = 0) -> dict:
-    """{kernel: {"launches", "ms", "bytes"}} accumulated since profile_enable."""
+    """{kernel: {"launches", "ms", "bytes", "flops"}} accumulated since profile_enable."""
     h = handle(device)
     out = {}
     for name, kid in KERNELS.items():
-        n, ms, by = ct.c_int64(), ct.c_double(), ct.c_double()
-        h.check(lib().respca_profile_query(h._h, kid, ct.byref(n), ct.byref(ms), ct.byref(by)),
-                allow=(OK,))
-        out[name] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
+        n, ms, by, fl = ct.c_int64(), ct.c_double(), ct.c_double(), ct.c_double()
+        h.check(lib().respca_profile_query(h._h, kid, ct.byref(n), ct.byref(ms), ct.byref(by),
+                                           ct.byref(fl)), allow=(OK,))
+        out[name] = {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
     return out

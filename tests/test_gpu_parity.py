@@ -312,3 +312,94 @@ def test_padded_leading_dimension_and_determinism():
     assert p["info"]["iters"] == o["info"]["iters"]
     assert rel(host(p["L"]), o["L"], nX) <= F32_TOL
     assert rel(host(p["S"]), o["S"], nX) <= F32_TOL
+
+
+# ------------------------------------------------------ bf16 distance mode
+
+@pytest.mark.parametrize("shape,lam", [((1037, 777, 5), None), ((2051, 300, 40), 0.3)])
+def test_bf16_solve_matches_oracle(shape, lam):
+    """Split-bf16 MFMA distances with exact refinement: same labels and the FP32
+    bar against the FP64 oracle (iteration-locked), on grouped data."""
+    d, n, c = shape
+    X, _, _, _ = synth.clustered(d, n, c, seed=d * 3 + n, sep=4.0, noise=0.5, frac=0.05, amp=10.0,
+                                 dtype=np.float32)
+    lam = float(np.sqrt(max(d, n))) if lam is None else lam
+    o = oracle.solve(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=1))
+    T = o["info"]["iters"]
+    g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=T, seed=1, precision=rp.BF16GEMM_F32)
+    np.testing.assert_array_equal(g["labels"].cpu().numpy(), o["labels"])
+    assert g["info"]["init_lloyd"] == o["info"]["init_lloyd"]
+    nX = np.linalg.norm(X.astype(np.float64))
+    assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
+    assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+
+
+def test_bf16_kmeans_matches_oracle():
+    X, _, _, _ = synth.clustered(777, 900, 12, seed=5, sep=3.0, noise=0.7, dtype=np.float32)
+    lab, C, info = rp.kmeans(dev(X), 12, seed=4, precision=rp.BF16GEMM_F32)
+    ol, oC, osteps = oracle.kmeans(X, 12, 4)
+    np.testing.assert_array_equal(lab.cpu().numpy(), ol)
+    assert info["init_lloyd"] == osteps
+
+
+@pytest.mark.parametrize("precision", [rp.F32, rp.BF16GEMM_F32])
+def test_exact_ties_go_to_lowest_group(precision):
+    """Two identical centroids (empty groups carried in the state) tie exactly for
+    the columns nearest to them; the lower group must win, as in the oracle.
+    lambda = 0 makes L = X, so the tie is exact in any precision."""
+    d, n, c = 256, 200, 4
+    rng = np.random.default_rng(11)
+    e = np.zeros(d)
+    e[0] = 10.0
+    X = np.empty((d, n))
+    X[:, :90] = e[:, None] + rng.normal(0, 0.1, (d, 90))
+    X[:, 90:180] = -e[:, None] + rng.normal(0, 0.1, (d, 90))
+    X[:, 180:] = rng.normal(0, 0.01, (d, 20))
+    X = np.asfortranarray(X.astype(np.float32))
+    st = synth.random_state(X, c, seed=3, s_frac=0.0)
+    lab = np.zeros(n, dtype=np.int32)
+    lab[90:180] = 3
+    lab[190:] = 3                              # groups 1 and 2 are empty
+    st["labels"] = lab
+    st["C"][:, 1] = 0.0                        # identical centroids at the origin
+    st["C"][:, 2] = 0.0
+    st["Theta"][:] = 0.0
+    st["rho"] = 1e-2
+    gs = _gpu_state(st, np.float32)
+    rp.iterate(dev(X), gs, iters=1, lam=0.0, max_lloyd=1, precision=precision)
+    ost = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) and v.dtype != np.int32 else v)
+           for k, v in st.items()}
+    o = oracle.step(oracle.make_params(c, lam=0.0, max_lloyd=1), X.astype(np.float64), ost)
+    assert np.all(o["labels"][180:] == 1)
+    np.testing.assert_array_equal(gs["labels"].cpu().numpy(), o["labels"])
+
+
+def test_bf16_iterate_full_size_sampled_columns():
+    """Full-size one-iteration check of the bf16 mode (10^4 x 10^4, c = 100)."""
+    d = n = 10000
+    c = 100
+    X, _, _ = synth.config_large(1, np.float32)
+    st = synth.random_state(X, c, seed=8, s_frac=0.1, s_amp=20.0)
+    st["rho"] = 0.3
+    lam = 0.01
+    gs = _gpu_state(st, np.float32)
+    rp.iterate(dev(X), gs, iters=1, lam=lam, max_lloyd=1, precision=rp.BF16GEMM_F32)
+    rng = np.random.default_rng(0)
+    sel = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 62, replace=False)]))
+    o = oracle.step_columns(oracle.make_params(c, lam=lam, max_lloyd=1), X, st, sel)
+    Xo = X[:, sel].astype(np.float64)
+    idx = torch.from_numpy(sel).cuda()
+    for k in ("L", "S"):
+        assert rel(host(gs[k][:, idx]), o[k], np.linalg.norm(Xo)) <= F32_TOL, k
+    lab = gs["labels"].cpu().numpy()[sel]
+    mu = o["mu"]
+    dist = ((o["L"][:, :, None] - mu[:, None, :]) ** 2).sum(axis=0)
+    srt = np.sort(dist, axis=1)
+    gap = srt[:, 1] - srt[:, 0]
+    cn = np.sqrt((mu ** 2).sum(axis=0)).max()
+    ln = np.sqrt((o["L"] ** 2).sum(axis=0))
+    # refined decisions are exact up to double rounding of FP32 inputs
+    bound = 64 * np.finfo(np.float32).eps * (cn ** 2 + 2 * cn * ln)
+    sep = gap > bound
+    assert sep.mean() > 0.9
+    np.testing.assert_array_equal(lab[sep], o["labels"][sep])
