@@ -1,0 +1,164 @@
+// Device helpers and tile bodies shared by the single-solve kernels and the
+// batched persistent kernel.  Every tile works on a slice of kRowsPerBlock
+// consecutive rows of column-major d x n arrays; each wave64 load touches 64
+// consecutive rows of one column, V elements per lane (16-byte vectors when d
+// and the leading dimensions allow it).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace respca {
+
+// ------------------------------------------------------------ small helpers
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sum of 3 values over a 256-thread block; result valid in thread 0.
+__device__ inline void block_sum3(double& a, double& b, double& c) {
+    __shared__ double sh[3][kBlock / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = sh[0][0]; b = sh[1][0]; c = sh[2][0];
+        for (int i = 1; i < kBlock / 64; ++i) { a += sh[0][i]; b += sh[1][i]; c += sh[2][i]; }
+    }
+}
+
+template <typename T, int V> struct Vec;
+template <> struct Vec<float, 4> { using type = float4; };
+template <> struct Vec<double, 2> { using type = double2; };
+
+template <typename T, int V>
+__device__ inline void vload(const T* p, T (&r)[V]) {
+    if constexpr (V == 1) {
+        r[0] = *p;
+    } else {
+        using VT = typename Vec<T, V>::type;
+        VT v = *reinterpret_cast<const VT*>(p);
+        if constexpr (V == 4) { r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w; }
+        else { r[0] = v.x; r[1] = v.y; }
+    }
+}
+
+template <typename T, int V>
+__device__ inline void vstore(T* p, const T (&r)[V]) {
+    if constexpr (V == 1) {
+        *p = r[0];
+    } else {
+        using VT = typename Vec<T, V>::type;
+        VT v;
+        if constexpr (V == 4) { v.x = r[0]; v.y = r[1]; v.z = r[2]; v.w = r[3]; }
+        else { v.x = r[0]; v.y = r[1]; }
+        *reinterpret_cast<VT*>(p) = v;
+    }
+}
+
+// ------------------------------------------------------------- tile bodies
+
+// The fused ALM sweep over columns [j0, j1) of rows [r0, r0 + kRowsPerBlock).
+// Per entry (i, j) with group p = labels[j]:
+//   D  = X - S + Theta/rho                     (matrix the L-step pulls toward)
+//   L  = alpha D + beta C[:, p]                (Sec. 4.1 closed form, C = group mean of D)
+//   B  = X - L + Theta/rho;  S' = sign(B) max(|B| - 1/rho, 0)      (Sec. 4.3)
+//   Theta' = Theta + rho (X - L - S')                              (Sec. 4.4)
+// and adds this thread's squared norms of X - L - S', L - L_prev, S' - S to a0..a2.
+template <typename T, int V>
+__device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __restrict__ L,
+                                  int64_t ldl, T* __restrict__ S, int64_t lds, T* __restrict__ Th,
+                                  int64_t ldt, const T* __restrict__ C,
+                                  const int32_t* __restrict__ labels, int64_t d, int64_t j0,
+                                  int64_t j1, int64_t r0, T alpha, T beta, T rho, T inv_rho,
+                                  double& a0, double& a1, double& a2) {
+    constexpr int NS = kRowsPerBlock / (kBlock * V);
+    for (int64_t j = j0; j < j1; ++j) {
+        const int64_t p = labels[j];
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            if (i >= d) continue;
+            T x[V], s[V], t[V], lp[V], m[V], ln[V], sn[V], tn[V];
+            vload<T, V>(X + j * ldx + i, x);
+            vload<T, V>(S + j * lds + i, s);
+            vload<T, V>(Th + j * ldt + i, t);
+            vload<T, V>(L + j * ldl + i, lp);
+            vload<T, V>(C + p * d + i, m);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const T dv = x[v] - s[v] + t[v] * inv_rho;
+                ln[v] = alpha * dv + beta * m[v];
+                const T b = x[v] - ln[v] + t[v] * inv_rho;
+                const T mag = fabs(b) - inv_rho;
+                sn[v] = mag > T(0) ? copysign(mag, b) : T(0);
+                const T r = x[v] - ln[v] - sn[v];
+                tn[v] = t[v] + rho * r;
+                const double dl = (double)ln[v] - (double)lp[v];
+                const double ds = (double)sn[v] - (double)s[v];
+                a0 += (double)r * (double)r;
+                a1 += dl * dl;
+                a2 += ds * ds;
+            }
+            vstore<T, V>(L + j * ldl + i, ln);
+            vstore<T, V>(S + j * lds + i, sn);
+            vstore<T, V>(Th + j * ldt + i, tn);
+        }
+    }
+}
+
+// Sum over the `len` columns perm[begin..begin+len) (one group segment) of
+// Y = X - S + Theta*inv_rho (WITH_D) or Y = A, rows [r0, r0 + kRowsPerBlock),
+// in double, written to out[i] (out points at this segment's d-vector).
+template <typename T, int V, bool WITH_D>
+__device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
+                                          const T* __restrict__ S, int64_t lds,
+                                          const T* __restrict__ Th, int64_t ldt, T inv_rho,
+                                          int64_t d, const int32_t* __restrict__ perm, int begin,
+                                          int len, int64_t r0, double* __restrict__ out) {
+    constexpr int NS = kRowsPerBlock / (kBlock * V);
+    double acc[NS][V];
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
+    for (int q = 0; q < len; ++q) {
+        const int64_t j = perm[begin + q];
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            if (i < d) {
+                T x[V];
+                vload<T, V>(A + j * lda + i, x);
+                if constexpr (WITH_D) {
+                    T sv[V], tv[V];
+                    vload<T, V>(S + j * lds + i, sv);
+                    vload<T, V>(Th + j * ldt + i, tv);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) x[v] = x[v] - sv[v] + tv[v] * inv_rho;
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[a][v] += (double)x[v];
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+        const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+        if (i < d)
+#pragma unroll
+            for (int v = 0; v < V; ++v) out[i + v] = acc[a][v];
+    }
+}
+
+}  // namespace respca

@@ -1,0 +1,258 @@
+// The MFMA distance tile shared by the single-solve and batched kernels:
+// partial products C^T Y for 128 columns x 128 groups over one slice of rows,
+// staged through LDS 32 rows at a time (FP32 v_mfma_f32_16x16x4f32, or split
+// bf16 hi/lo on v_mfma_f32_16x16x32_bf16).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace respca {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxCand = 8;  // candidate groups kept per near-tied column
+
+constexpr int kJT = 128;     // columns per workgroup
+constexpr int kKC = 128;     // groups per workgroup (8 blocks of 16)
+constexpr int kRT = 32;      // rows per LDS stage
+constexpr int kStride = 36;  // padded LDS stride (floats) of one staged column: conflict-free
+constexpr int kStrideH = 40; // padded LDS stride (bf16) of one staged column (80 bytes)
+
+
+// A 32-row stage of 128 consecutive columns of a column-major matrix, held in
+// registers between its global load and its LDS store (zero outside the
+// matrix), so that the next stage's loads are in flight during the MFMAs.
+template <bool VEC>
+struct StageRegs {
+    float4 v4[VEC ? 4 : 1];
+    float v1[VEC ? 1 : 16];
+
+    __device__ inline void load(const float* __restrict__ src, int64_t ld, int64_t col0,
+                                int64_t ncols, int64_t r, int64_t rend) {
+        const int tid = threadIdx.x;
+        if constexpr (VEC) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int col = p * 32 + (tid >> 3);
+                const int rr = (tid & 7) * 4;
+                const int64_t gj = col0 + col, gi = r + rr;
+                v4[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gj < ncols && gi < rend) v4[p] = *reinterpret_cast<const float4*>(src + gj * ld + gi);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int e = tid + 256 * p, col = e >> 5, rr = e & 31;
+                const int64_t gj = col0 + col, gi = r + rr;
+                v1[p] = (gj < ncols && gi < rend) ? src[gj * ld + gi] : 0.f;
+            }
+        }
+    }
+
+    // Sum of squares of each staged column's 32 rows, accumulated into acc[]:
+    // VEC: 8 consecutive lanes share a column (acc[p], column p*32 + tid/8, valid
+    // in lanes with tid % 8 == 0); scalar: 32 lanes share a column (acc[p],
+    // column tid/32 + 8p, valid in lanes with tid % 32 == 0).
+    __device__ inline void col_sumsq(float* acc) const {
+        if constexpr (VEC) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                float t = v4[p].x * v4[p].x + v4[p].y * v4[p].y + v4[p].z * v4[p].z + v4[p].w * v4[p].w;
+                t += __shfl_xor(t, 1);
+                t += __shfl_xor(t, 2);
+                t += __shfl_xor(t, 4);
+                acc[p] += t;
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                float t = v1[p] * v1[p];
+#pragma unroll
+                for (int o = 1; o < 32; o <<= 1) t += __shfl_xor(t, o);
+                acc[p] += t;
+            }
+        }
+    }
+
+    // Store as bf16 high and low parts (x = hi + lo + O(2^-16 x)), stride kStrideH.
+    __device__ inline void store_split(__bf16* __restrict__ hi, __bf16* __restrict__ lo) const {
+        const int tid = threadIdx.x;
+        if constexpr (VEC) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int col = p * 32 + (tid >> 3);
+                const int rr = (tid & 7) * 4;
+                const float x[4] = {v4[p].x, v4[p].y, v4[p].z, v4[p].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const __bf16 h = (__bf16)x[e];
+                    hi[col * kStrideH + rr + e] = h;
+                    lo[col * kStrideH + rr + e] = (__bf16)(x[e] - (float)h);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int e = tid + 256 * p, col = e >> 5, rr = e & 31;
+                const __bf16 h = (__bf16)v1[p];
+                hi[col * kStrideH + rr] = h;
+                lo[col * kStrideH + rr] = (__bf16)(v1[p] - (float)h);
+            }
+        }
+    }
+
+    __device__ inline void store(float* __restrict__ dst) const {
+        const int tid = threadIdx.x;
+        if constexpr (VEC) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int col = p * 32 + (tid >> 3);
+                const int rr = (tid & 7) * 4;
+                *reinterpret_cast<float4*>(dst + col * kStride + rr) = v4[p];
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int e = tid + 256 * p, col = e >> 5, rr = e & 31;
+                dst[col * kStride + rr] = v1[p];
+            }
+        }
+    }
+};
+
+// One distance tile: columns [j0, j0 + 128) x groups [k0, k0 + 128) over the
+// rows of slice s; writes part[s][j][k] (and, in bf16 mode with write_ynorm,
+// the slice's column sums of squares).  256 threads.
+template <bool VEC, bool BF16>
+__device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, int kpad,
+                                 const float* __restrict__ Y, int64_t ldy, int64_t n, int slice_rows,
+                                 float* __restrict__ part, float* __restrict__ ynorm_part,
+                                 int64_t j0, int s, int k0, bool write_ynorm) {
+    // fp32 mode: Ys, Cs as floats; bf16 mode: hi/lo halves of both operands.
+    constexpr size_t kF32Bytes = 2 * kJT * kStride * sizeof(float);
+    constexpr size_t kBf16Bytes = 2 * (kJT + kKC) * kStrideH * sizeof(__bf16);
+    __shared__ __attribute__((aligned(16))) char smem[kF32Bytes > kBf16Bytes ? kF32Bytes : kBf16Bytes];
+    float* Ys = reinterpret_cast<float*>(smem);
+    float* Cs = Ys + kJT * kStride;
+    __bf16* Yh = reinterpret_cast<__bf16*>(smem);
+    __bf16* Yl = Yh + kJT * kStrideH;
+    __bf16* Ch = Yl + kJT * kStrideH;
+    __bf16* Cl = Ch + kKC * kStrideH;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    __syncthreads();   // the LDS tiles may still be read by a previous tile of this workgroup
+    const int q = lane & 15, g = lane >> 4;
+    const int64_t r0 = (int64_t)s * slice_rows;
+    const int64_t r1 = r0 + slice_rows < d ? r0 + slice_rows : d;
+    const int nkb = (kpad - k0 < kKC ? kpad - k0 : kKC) / 16;
+    constexpr int NCOL = VEC ? 4 : 16;
+    float ycol[NCOL];
+#pragma unroll
+    for (int p = 0; p < NCOL; ++p) ycol[p] = 0.f;
+
+    floatx4 acc[2][8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    StageRegs<VEC> ry, rc;
+    if (r0 < r1) {
+        ry.load(Y, ldy, j0, n, r0, r1);
+        rc.load(C, d, k0, c, r0, r1);
+    }
+    for (int64_t r = r0; r < r1; r += kRT) {
+        if constexpr (BF16) {
+            ry.col_sumsq(ycol);
+            ry.store_split(Yh, Yl);
+            rc.store_split(Ch, Cl);
+        } else {
+            ry.store(Ys);
+            rc.store(Cs);
+        }
+        __syncthreads();
+        if (r + kRT < r1) {                     // next stage's loads overlap this stage's MFMAs
+            ry.load(Y, ldy, j0, n, r + kRT, r1);
+            rc.load(C, d, k0, c, r + kRT, r1);
+        }
+        if constexpr (BF16) {
+            // one 16x16x32 instruction covers the stage: lane group g holds rows 8g..8g+7
+            bf16x8 ahi[2], alo[2];
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) {
+                const int col = wave * 32 + jb * 16 + q;
+                ahi[jb] = *reinterpret_cast<const bf16x8*>(Yh + col * kStrideH + g * 8);
+                alo[jb] = *reinterpret_cast<const bf16x8*>(Yl + col * kStrideH + g * 8);
+            }
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb) {
+                if (kb < nkb) {
+                    const int row = kb * 16 + q;
+                    const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Ch + row * kStrideH + g * 8);
+                    const bf16x8 blo = *reinterpret_cast<const bf16x8*>(Cl + row * kStrideH + g * 8);
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb) {
+                        acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[jb], bhi, acc[jb][kb], 0, 0, 0);
+                        acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[jb], blo, acc[jb][kb], 0, 0, 0);
+                        acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[jb], bhi, acc[jb][kb], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            // MFMA step m: lane group g supplies row 8g + m of the stage (same map for both operands)
+            float a[2][8];
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) {
+                const float* p = Ys + (wave * 32 + jb * 16 + q) * kStride + g * 8;
+                const float4 u = *reinterpret_cast<const float4*>(p);
+                const float4 w = *reinterpret_cast<const float4*>(p + 4);
+                a[jb][0] = u.x; a[jb][1] = u.y; a[jb][2] = u.z; a[jb][3] = u.w;
+                a[jb][4] = w.x; a[jb][5] = w.y; a[jb][6] = w.z; a[jb][7] = w.w;
+            }
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb) {
+                if (kb < nkb) {
+                    const float* p = Cs + (kb * 16 + q) * kStride + g * 8;
+                    const float4 u = *reinterpret_cast<const float4*>(p);
+                    const float4 w = *reinterpret_cast<const float4*>(p + 4);
+                    const float b[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                        for (int m = 0; m < 8; ++m)
+                            acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jb][m], b[m], acc[jb][kb], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (BF16) {
+        if (write_ynorm) {
+#pragma unroll
+            for (int p = 0; p < NCOL; ++p) {
+                const int col = VEC ? p * 32 + (tid >> 3) : (tid >> 5) + 8 * p;
+                const bool owner = VEC ? (tid & 7) == 0 : (tid & 31) == 0;
+                const int64_t j = j0 + col;
+                if (owner && j < n) ynorm_part[(int64_t)s * n + j] = ycol[p];
+            }
+        }
+    }
+    // lane holds D[column 4g + v][group q] of each 16 x 16 tile
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+            if (kb >= nkb) continue;
+            const int k = k0 + kb * 16 + q;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t j = j0 + wave * 32 + jb * 16 + 4 * g + v;
+                if (j < n) part[((int64_t)s * n + j) * kpad + k] = acc[jb][kb][v];
+            }
+        }
+}
+
+
+}  // namespace respca
