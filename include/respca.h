@@ -151,6 +151,44 @@ respca_status respca_kmeans(respca_handle h, const respca_params *params,
                             int32_t *labels, void *C, respca_info *info, void *stream);
 
 /*
+ * Batched solve: `batch` independent RES-PCA problems of uneven size, each run
+ * exactly as respca_solve would run it (its own initial K-means, iteration
+ * count, Lloyd passes and Sec. 5 stopping test), all inside one persistent
+ * kernel launch that is captured once in a hipGraph and replayed when the same
+ * call (same pointers, sizes and parameters) repeats.
+ *   params[i]: per-instance parameters (precision must be RESPCA_F32; the
+ *              history pointer is ignored).  d[i], n[i], ldx[i], ldl[i], lds[i]:
+ *              sizes and leading dimensions.  X[i], L[i], S[i]: device pointers
+ *              (host arrays of them).  labels: nullable host array of nullable
+ *              device int32[n[i]] pointers.  info: host array of `batch` structs.
+ * Tile shapes come from the handle's tuning (respca_autotune_batched) or the
+ * defaults.  Returns RESPCA_OK when every instance converged, otherwise the
+ * first non-OK instance status (each info[i].status has its own).
+ */
+respca_status respca_solve_batched(respca_handle h, const respca_params *params, int32_t batch,
+                                   const int64_t *d, const int64_t *n,
+                                   const void *const *X, const int64_t *ldx,
+                                   void *const *L, const int64_t *ldl,
+                                   void *const *S, const int64_t *lds,
+                                   int32_t *const *labels, respca_info *info, void *stream);
+
+/*
+ * Tile-shape tuner of the batched solver: times respca_solve_batched on the
+ * given batch for each candidate (sweep columns per work item, rows per
+ * distance slice, workgroups per compute unit) and keeps the fastest in the
+ * handle.  With cache_path non-NULL the result is looked up in / appended to
+ * that text file (one "key jc slice_rows blocks_per_cu ms" line per tuned size
+ * bucket) so later processes skip the search.  Outputs are overwritten by the
+ * timing runs.  best_ms (host, nullable) receives the winning time.
+ */
+respca_status respca_autotune_batched(respca_handle h, const respca_params *params, int32_t batch,
+                                      const int64_t *d, const int64_t *n,
+                                      const void *const *X, const int64_t *ldx,
+                                      void *const *L, const int64_t *ldl,
+                                      void *const *S, const int64_t *lds,
+                                      const char *cache_path, double *best_ms, void *stream);
+
+/*
  * Kernel timing.  While enabled, every launch of the kernels listed in
  * respca_kernel_id is bracketed by HIP events recorded on the stream it is
  * launched on, and the library accumulates, per kernel, the number of

@@ -1,0 +1,79 @@
+// Device-side descriptors of the batched persistent solver (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace respca {
+
+// One instance.  The static part is written by the host; the state part is
+// owned by the kernel (initialised in its first phases, read back by the host).
+struct BatchInst {
+    // caller buffers
+    const float* Xc;
+    float* Lc;
+    float* Sc;
+    int32_t* labels_out;       // nullable
+    const int32_t* init_labels;  // nullable
+    int64_t ldx, ldl, lds;
+    // internal copies, zero-padded to dp rows (leading dimension dp)
+    float* X;
+    float* L;
+    float* S;
+    float* Th;
+    float* C;                  // dp x c centroids
+    int32_t* lab[2];
+    int32_t* perm;
+    int32_t* counts;
+    int32_t* segb;
+    int32_t* segl;
+    int32_t* segf;
+    double* pmeans;            // [segment][dp]
+    float* part;               // [slice][n][kpad]
+    double* d2;
+    int32_t* chosen;
+    int32_t* seeds;
+    const double* u;           // k-means++ uniforms (host-drawn from splitmix64(seed))
+    double* cnorm;
+    double* sweep_part;        // 3 per sweep tile
+    int32_t* chg;              // 1 per 16-column argmin item
+    // shape and tiling
+    int d, dp, n, c, kpad, nrb, jc, slices, slice_rows, nkc, n_sweep, n_argmin;
+    // parameters
+    double lambda, tol, rho0, kappa, rho_max;
+    int max_iter, max_lloyd;
+    // state
+    int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, status, nseg;
+    double rho, nx, rho_final, primal, dL, dS;
+};
+
+struct BatchSync {
+    unsigned count;
+    unsigned gen;
+    int abort;
+    int active;
+};
+
+struct BatchArgs {
+    BatchInst* inst;
+    int batch;
+    BatchSync* sync;
+    uint64_t timeout_ticks;
+    int cmax;
+    int max_steps;
+    // prefix tables (batch + 1 entries) of per-instance work items
+    const int32_t* off_tile;   // ceil(n/jc) * nrb   (pack, sweep, unpack)
+    const int32_t* off_d2;     // ceil(n/4)          (k-means++ distances, wave per column)
+    const int32_t* off_kc;     // c                  (seed columns, centroid norms)
+    const int32_t* off_seg;    // (ceil(n/64) + c) * nrb (group partial sums)
+    const int32_t* off_kr;     // c * ceil(dp/256)   (centroid finalisation)
+    const int32_t* off_dist;   // ceil(n/128) * slices * nkc (distance tiles)
+    const int32_t* off_col;    // ceil(n/16)         (argmin)
+};
+
+void launch_batched_reset(BatchSync* s, int batch, hipStream_t st);
+void launch_batched(const BatchArgs& args, int nblocks, hipStream_t st);
+int batched_blocks_per_cu();
+
+}  // namespace respca

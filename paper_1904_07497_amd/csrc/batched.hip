@@ -1,0 +1,587 @@
+// Batched RES-PCA: many independent instances of uneven d, n and c solved by one
+// persistent kernel launch (replayed from a hipGraph).
+//
+// Every instance runs its own copy of the method -- initial K-means, then outer
+// ALM iterations (Sec. 4.1 -> 4.2 -> 4.3 -> 4.4) with its own iteration count,
+// Lloyd passes and Sec. 5 stopping test -- as a small state machine.  The grid
+// walks a fixed sequence of phases; in each phase the work items (instance,
+// tile) of all instances whose state needs that phase are spread over every
+// workgroup, and phases are separated by a grid barrier.  The barrier's wait is
+// bounded by a wall-clock limit: a workgroup that waits too long raises an abort
+// flag that every other wait sees, so the launch always drains and the host
+// reports an error instead of hanging.
+//
+// Instances are stored zero-padded to d' = 4 * ceil(d / 4) rows so every tile
+// takes the 16-byte vector path; the padding rows stay exactly zero through all
+// steps (X, S, Theta, centroids and hence L are zero there), so sums, norms and
+// dot products are those of the unpadded problem.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "batched.h"
+#include "device_common.h"
+#include "dist_tile.h"
+
+namespace respca {
+
+namespace {
+
+enum Mode : int { M_DONE = 0, M_SEED = 1, M_MEANSX = 2, M_KMX = 3, M_ITER = 4, M_LL = 5 };
+
+// ---------------------------------------------------------------- barrier
+
+__device__ bool grid_sync(BatchSync* gs, unsigned nblocks, uint64_t timeout_ticks) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ab = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!ab) {
+            const unsigned g = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            const unsigned arrived =
+                __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived == nblocks - 1) {
+                __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&gs->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                    if (wall_clock64() - t0 > timeout_ticks) {
+                        __hip_atomic_store(&gs->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            __threadfence();
+            ab = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_ok = ab ? 0 : 1;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ------------------------------------------------------------ item lookup
+
+// Largest i with off[i] <= item (off is a prefix table of batch + 1 entries).
+__device__ inline int find_inst(const int32_t* __restrict__ off, int batch, int item) {
+    int lo = 0, hi = batch;   // off[lo] <= item < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline bool needs_groups(int m) { return m == M_MEANSX || m == M_KMX || m == M_ITER || m == M_LL; }
+__device__ inline bool needs_assign(int m) { return m == M_SEED || m == M_KMX || m == M_ITER || m == M_LL; }
+
+// ------------------------------------------------------- per-instance work
+
+// Stable counting sort of one instance's labels by one workgroup, with the
+// segment table of the means pass (runs of <= kSegCols columns of one group).
+__device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab) {
+    __shared__ int hist[kMaxGroups];
+    __shared__ int offs[kMaxGroups];
+    __shared__ int chunk[kBlock];
+    __shared__ int wsum[kBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = B.n, c = B.c;
+    for (int k = tid; k < c; k += kBlock) hist[k] = 0;
+    __syncthreads();
+    for (int j = tid; j < n; j += kBlock) atomicAdd(&hist[lab[j]], 1);
+    __syncthreads();
+    // each thread owns 4 consecutive groups; two block exclusive scans
+    int cnt[4], nsg[4], my_c = 0, my_s = 0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int k = tid * 4 + g;
+        cnt[g] = k < c ? hist[k] : 0;
+        nsg[g] = (cnt[g] + kSegCols - 1) / kSegCols;
+        my_c += cnt[g];
+        my_s += nsg[g];
+    }
+    auto exscan = [&](int v) -> int {
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        __syncthreads();
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        int base = 0;
+        for (int w = 0; w < wave; ++w) base += wsum[w];
+        return base + x - v;
+    };
+    int bc = exscan(my_c);
+    int bs = exscan(my_s);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int k = tid * 4 + g;
+        if (k < c) {
+            offs[k] = bc;
+            B.counts[k] = cnt[g];
+            B.segf[k] = bs;
+            for (int q = 0; q < nsg[g]; ++q) {
+                B.segb[bs + q] = bc + q * kSegCols;
+                B.segl[bs + q] = min(kSegCols, cnt[g] - q * kSegCols);
+            }
+            if (k == c - 1) { B.segf[c] = bs + nsg[g]; B.nseg = bs + nsg[g]; }
+        }
+        bc += cnt[g];
+        bs += nsg[g];
+    }
+    __syncthreads();
+    for (int base = 0; base < n; base += kBlock) {
+        const int j = base + tid;
+        const int my = j < n ? lab[j] : -1;
+        chunk[tid] = my;
+        __syncthreads();
+        int rank = 0, later = 0;
+        if (j < n) {
+            for (int t = 0; t < tid; ++t) rank += (chunk[t] == my);
+            for (int t = tid + 1; t < kBlock; ++t) later += (chunk[t] == my);
+            B.perm[offs[my] + rank] = j;
+        }
+        __syncthreads();
+        if (j < n && later == 0) offs[my] += rank + 1;   // last of its group in this chunk
+        __syncthreads();
+    }
+}
+
+// k-means++ draw of seed m (m >= 1) for one instance by one workgroup; see k_pick.
+__device__ void pick_instance(BatchInst& B, int m) {
+    __shared__ double wtot[kBlock / 64];
+    __shared__ int ish[kBlock / 64];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int n = B.n;
+    const int chunk = (n + kBlock - 1) / kBlock;
+    const int lo = tid * chunk, hi = min(n, lo + chunk);
+    double loc = 0.0;
+    for (int j = lo; j < hi; ++j) loc += B.d2[j];
+    double x = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) wtot[wave] = x;
+    __syncthreads();
+    double pre = 0.0, total = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wave) pre += wtot[w];
+        total += wtot[w];
+    }
+    pre += x - loc;
+    auto bmin = [&](int v) -> int {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+        __syncthreads();
+        if (lane == 0) ish[wave] = v;
+        __syncthreads();
+        int r = ish[0];
+        for (int w = 1; w < kBlock / 64; ++w) r = min(r, ish[w]);
+        return r;
+    };
+    int s;
+    if (total > 0.0) {
+        const double target = B.u[m] * total;
+        int cand = INT_MAX;
+        double run = pre;
+        for (int j = lo; j < hi; ++j) {
+            run += B.d2[j];
+            if (run > target) { cand = j; break; }
+        }
+        s = bmin(cand);
+        if (s == INT_MAX) {
+            int last = INT_MAX;
+            for (int j = hi - 1; j >= lo; --j)
+                if (B.d2[j] > 0.0) { last = -j; break; }
+            s = -bmin(last);
+        }
+    } else {
+        int cand = INT_MAX;
+        for (int j = lo; j < hi; ++j)
+            if (!B.chosen[j]) { cand = j; break; }
+        s = bmin(cand);
+    }
+    if (tid == 0) { B.seeds[m] = s; B.chosen[s] = 1; }
+}
+
+// Control step of one instance (thread 0 of one workgroup).
+__device__ void control_instance(BatchInst& B, int* active) {
+    const int mode = B.mode;
+    if (!needs_assign(mode) && mode != M_MEANSX) return;
+    if (mode == M_MEANSX) { B.mode = M_ITER; return; }
+    int changed = 0;
+    for (int t = 0; t < B.n_argmin; ++t) changed += B.chg[t];
+    if (mode == M_SEED) { B.cur ^= 1; B.mode = M_KMX; return; }
+    if (mode == M_KMX) {
+        B.init_lloyd += 1;
+        if (changed == 0 || B.init_lloyd >= B.max_lloyd) {
+            if (changed) B.cur ^= 1;
+            B.mode = M_ITER;
+        } else {
+            B.cur ^= 1;
+        }
+        return;
+    }
+    if (mode == M_ITER) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int t = 0; t < B.n_sweep; ++t) {
+            a0 += B.sweep_part[3 * t];
+            a1 += B.sweep_part[3 * t + 1];
+            a2 += B.sweep_part[3 * t + 2];
+        }
+        B.iters += 1;
+        B.rho_final = B.rho;
+        B.primal = sqrt(a0) / B.nx;
+        B.dL = sqrt(a1) / B.nx;
+        B.dS = sqrt(a2) / B.nx;
+        B.lloyd_iter = 0;
+    }
+    B.lloyd_iter += 1;
+    B.lloyd_total += 1;
+    if (changed != 0 && B.lloyd_iter < B.max_lloyd) {
+        B.cur ^= 1;
+        B.mode = M_LL;
+        return;
+    }
+    if (changed) B.cur ^= 1;
+    const double next = B.kappa * B.rho;
+    B.rho = next < B.rho_max ? next : B.rho_max;
+    const double crit = fmax(B.primal, fmax(B.dL, B.dS));
+    if (crit <= B.tol) {
+        B.status = 0;
+        B.mode = M_DONE;
+        atomicSub(active, 1);
+    } else if (B.iters >= B.max_iter) {
+        B.status = 1;
+        B.mode = M_DONE;
+        atomicSub(active, 1);
+    } else {
+        B.mode = M_ITER;
+    }
+}
+
+// --------------------------------------------------------------- kernel
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_batched(BatchArgs A) {
+    BatchInst* __restrict__ inst = A.inst;
+    const int batch = A.batch;
+    const unsigned nb = gridDim.x;
+    const uint64_t tmo = A.timeout_ticks;
+    BatchSync* gs = A.sync;
+    int* active = &A.sync->active;
+
+    // ---- phase: copy X into its zero-padded internal copy; zero L, S, Theta;
+    //      sums of squares of X
+    for (int item = blockIdx.x; item < A.off_tile[batch]; item += nb) {
+        const int i = find_inst(A.off_tile, batch, item);
+        BatchInst& B = inst[i];
+        const int local = item - A.off_tile[i];
+        const int cb = local / B.nrb, rb = local % B.nrb;
+        const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
+        const int64_t r0 = (int64_t)rb * kRowsPerBlock;
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int64_t j = j0; j < j1; ++j)
+            for (int64_t r = r0 + threadIdx.x * 4; r < r0 + kRowsPerBlock && r < B.dp; r += kBlock * 4) {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (r + e < B.d) ? B.Xc[j * B.ldx + r + e] : 0.f;
+                const float4 x = make_float4(v[0], v[1], v[2], v[3]);
+                *reinterpret_cast<float4*>(B.X + j * B.dp + r) = x;
+                a += (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z + (double)x.w * x.w;
+                const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                *reinterpret_cast<float4*>(B.L + j * B.dp + r) = z;
+                *reinterpret_cast<float4*>(B.S + j * B.dp + r) = z;
+                *reinterpret_cast<float4*>(B.Th + j * B.dp + r) = z;
+            }
+        block_sum3(a, b, c);
+        if (threadIdx.x == 0) B.sweep_part[3 * local] = a;
+    }
+    if (!grid_sync(gs, nb, tmo)) return;
+
+    // ---- phase: initial state of every instance
+    for (int i = blockIdx.x; i < batch; i += nb) {
+        BatchInst& B = inst[i];
+        __shared__ int s_mode, s_status;
+        if (threadIdx.x == 0) {
+            double nx2 = 0.0;
+            for (int t = 0; t < B.n_sweep; ++t) nx2 += B.sweep_part[3 * t];
+            B.nx = sqrt(nx2);
+            B.cur = 0;
+            B.iters = B.lloyd_total = B.lloyd_iter = B.init_lloyd = 0;
+            B.rho = B.rho0;
+            B.rho_final = 0.0;
+            B.primal = B.dL = B.dS = 0.0;
+            B.nseg = 0;
+            if (!isfinite(nx2)) { B.status = -2; B.mode = M_DONE; atomicSub(active, 1); }
+            else if (nx2 == 0.0) { B.status = 0; B.mode = M_DONE; atomicSub(active, 1); }
+            else { B.status = 1; B.mode = B.init_labels ? M_MEANSX : M_SEED; }
+            s_mode = B.mode;
+            s_status = B.status;
+        }
+        __syncthreads();
+        const int m = s_mode;
+        if (s_status == 0 && m == M_DONE)
+            for (int j = threadIdx.x; j < B.n; j += kBlock) B.lab[0][j] = 0;
+        if (m == M_MEANSX) {
+            for (int j = threadIdx.x; j < B.n; j += kBlock) B.lab[0][j] = B.init_labels[j];
+            for (int64_t e = threadIdx.x; e < (int64_t)B.dp * B.c; e += kBlock) B.C[e] = 0.f;
+        }
+        if (m == M_SEED) {
+            for (int j = threadIdx.x; j < B.n; j += kBlock) B.chosen[j] = 0;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int64_t s0 = (int64_t)floor(B.u[0] * (double)B.n);
+                if (s0 >= B.n) s0 = B.n - 1;
+                B.seeds[0] = (int)s0;
+                B.chosen[s0] = 1;
+            }
+        }
+        __syncthreads();
+    }
+    if (!grid_sync(gs, nb, tmo)) return;
+
+    // ---- k-means++ seeding, seed by seed, for instances in M_SEED
+    for (int m = 0; m < A.cmax; ++m) {
+        for (int item = blockIdx.x; item < A.off_d2[batch]; item += nb) {
+            const int i = find_inst(A.off_d2, batch, item);
+            BatchInst& B = inst[i];
+            if (B.mode != M_SEED || m >= B.c) continue;
+            const int lane = threadIdx.x & 63;
+            const int64_t j = (int64_t)(item - A.off_d2[i]) * 4 + (threadIdx.x >> 6);
+            if (j >= B.n) continue;
+            const float* yj = B.X + j * B.dp;
+            const float* ys = B.X + (int64_t)B.seeds[m] * B.dp;
+            double acc = 0.0;
+            for (int64_t r = lane * 4; r < B.dp; r += 256) {
+                const float4 a = *reinterpret_cast<const float4*>(yj + r);
+                const float4 b = *reinterpret_cast<const float4*>(ys + r);
+                const double e0 = (double)a.x - b.x, e1 = (double)a.y - b.y;
+                const double e2 = (double)a.z - b.z, e3 = (double)a.w - b.w;
+                acc += e0 * e0;
+                acc += e1 * e1;
+                acc += e2 * e2;
+                acc += e3 * e3;
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) B.d2[j] = (m == 0) ? acc : fmin(B.d2[j], acc);
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+        if (m + 1 >= A.cmax) break;
+        for (int i = blockIdx.x; i < batch; i += nb) {
+            BatchInst& B = inst[i];
+            if (B.mode == M_SEED && m + 1 < B.c) pick_instance(B, m + 1);
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+    }
+    // centroids = seed columns
+    for (int item = blockIdx.x; item < A.off_kc[batch]; item += nb) {
+        const int i = find_inst(A.off_kc, batch, item);
+        BatchInst& B = inst[i];
+        if (B.mode != M_SEED) continue;
+        const int k = item - A.off_kc[i];
+        const float* src = B.X + (int64_t)B.seeds[k] * B.dp;
+        for (int64_t r = threadIdx.x; r < B.dp; r += kBlock) B.C[(int64_t)k * B.dp + r] = src[r];
+    }
+    if (!grid_sync(gs, nb, tmo)) return;
+
+    // ---- main loop: one step of every live instance per pass
+    for (int step = 0; step < A.max_steps; ++step) {
+        if (__hip_atomic_load(active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0) break;
+        // A: sort the current labels
+        for (int i = blockIdx.x; i < batch; i += nb) {
+            BatchInst& B = inst[i];
+            if (needs_groups(B.mode)) sort_instance(B, B.lab[B.cur]);
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+        // B: group partial sums (of X, of D = X - S + Theta/rho, or of L)
+        for (int item = blockIdx.x; item < A.off_seg[batch]; item += nb) {
+            const int i = find_inst(A.off_seg, batch, item);
+            BatchInst& B = inst[i];
+            const int mode = B.mode;
+            if (!needs_groups(mode)) continue;
+            const int local = item - A.off_seg[i];
+            const int s = local / B.nrb, rb = local % B.nrb;
+            if (s >= B.nseg) continue;
+            const int64_t r0 = (int64_t)rb * kRowsPerBlock;
+            double* out = B.pmeans + (int64_t)s * B.dp;
+            if (mode == M_ITER)
+                group_partial_tile<float, 4, true>(B.X, B.dp, B.S, B.dp, B.Th, B.dp,
+                                                   (float)(1.0 / B.rho), B.dp, B.perm, B.segb[s],
+                                                   B.segl[s], r0, out);
+            else
+                group_partial_tile<float, 4, false>(mode == M_LL ? B.L : B.X, B.dp, nullptr, 0,
+                                                    nullptr, 0, 0.f, B.dp, B.perm, B.segb[s],
+                                                    B.segl[s], r0, out);
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+        // C: centroids of the non-empty groups
+        for (int item = blockIdx.x; item < A.off_kr[batch]; item += nb) {
+            const int i = find_inst(A.off_kr, batch, item);
+            BatchInst& B = inst[i];
+            if (!needs_groups(B.mode)) continue;
+            const int local = item - A.off_kr[i];
+            const int nrc = (B.dp + kBlock - 1) / kBlock;
+            const int k = local / nrc;
+            const int64_t r = (int64_t)(local % nrc) * kBlock + threadIdx.x;
+            const int nk = B.counts[k];
+            if (nk == 0 || r >= B.dp) continue;
+            double s = 0.0;
+            for (int g = B.segf[k]; g < B.segf[k + 1]; ++g) s += B.pmeans[(int64_t)g * B.dp + r];
+            B.C[(int64_t)k * B.dp + r] = (float)(s / (double)nk);
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+        // D: the fused ALM sweep (instances starting an outer iteration)
+        for (int item = blockIdx.x; item < A.off_tile[batch]; item += nb) {
+            const int i = find_inst(A.off_tile, batch, item);
+            BatchInst& B = inst[i];
+            if (B.mode != M_ITER) continue;
+            const int local = item - A.off_tile[i];
+            const int cb = local / B.nrb, rb = local % B.nrb;
+            const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
+            const double rho = B.rho;
+            const double alpha = rho / (2.0 * B.lambda + rho), beta = (2.0 * B.lambda) / (2.0 * B.lambda + rho);
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            sweep_tile<float, 4>(B.X, B.dp, B.L, B.dp, B.S, B.dp, B.Th, B.dp, B.C, B.lab[B.cur], B.dp,
+                                 j0, j1, (int64_t)rb * kRowsPerBlock, (float)alpha, (float)beta,
+                                 (float)rho, (float)(1.0 / rho), a0, a1, a2);
+            block_sum3(a0, a1, a2);
+            if (threadIdx.x == 0) {
+                B.sweep_part[3 * local] = a0;
+                B.sweep_part[3 * local + 1] = a1;
+                B.sweep_part[3 * local + 2] = a2;
+            }
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+        // E: squared centroid norms
+        for (int item = blockIdx.x; item < A.off_kc[batch]; item += nb) {
+            const int i = find_inst(A.off_kc, batch, item);
+            BatchInst& B = inst[i];
+            if (!needs_assign(B.mode)) continue;
+            const int k = item - A.off_kc[i];
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int64_t r = threadIdx.x; r < B.dp; r += kBlock) {
+                const double x = (double)B.C[(int64_t)k * B.dp + r];
+                a += x * x;
+            }
+            block_sum3(a, b, c);
+            if (threadIdx.x == 0) B.cnorm[k] = a;
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+        // F: distance tiles (columns of X before the iterations, of L after)
+        for (int item = blockIdx.x; item < A.off_dist[batch]; item += nb) {
+            const int i = find_inst(A.off_dist, batch, item);
+            BatchInst& B = inst[i];
+            const int mode = B.mode;
+            if (!needs_assign(mode)) continue;
+            const int local = item - A.off_dist[i];
+            const int kc = local % B.nkc, ts = local / B.nkc;
+            const int tile = ts / B.slices, s = ts % B.slices;
+            const float* Y = (mode == M_ITER || mode == M_LL) ? B.L : B.X;
+            dist_tile<true, false>(B.C, B.dp, B.c, B.kpad, Y, B.dp, B.n, B.slice_rows, B.part, nullptr,
+                                   (int64_t)tile * kJT, s, kc * kKC, false);
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+        // G: reduce slices, argmin (16 lanes per column), changed counts
+        for (int item = blockIdx.x; item < A.off_col[batch]; item += nb) {
+            const int i = find_inst(A.off_col, batch, item);
+            BatchInst& B = inst[i];
+            if (!needs_assign(B.mode)) continue;
+            const int local = item - A.off_col[i];
+            const int q = threadIdx.x & 15;
+            const int64_t j = (int64_t)local * 16 + (threadIdx.x >> 4);
+            double bestd = INFINITY;
+            int bestk = INT_MAX;
+            if (j < B.n)
+                for (int k = q; k < B.c; k += 16) {
+                    double dot = 0.0;
+                    for (int s = 0; s < B.slices; ++s)
+                        dot += (double)B.part[((int64_t)s * B.n + j) * B.kpad + k];
+                    const double dist = B.cnorm[k] - 2.0 * dot;
+                    if (dist < bestd) { bestd = dist; bestk = k; }
+                }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) {
+                const double od = __shfl_xor(bestd, o, 16);
+                const int ok = __shfl_xor(bestk, o, 16);
+                if (od < bestd || (od == bestd && ok < bestk)) { bestd = od; bestk = ok; }
+            }
+            double ch = 0.0;
+            if (j < B.n && q == 0) {
+                const int lab = bestk == INT_MAX ? 0 : bestk;
+                B.lab[B.cur ^ 1][j] = lab;
+                ch = B.lab[B.cur][j] != lab ? 1.0 : 0.0;
+            }
+            double z1 = 0.0, z2 = 0.0;
+            block_sum3(ch, z1, z2);
+            if (threadIdx.x == 0) B.chg[local] = (int)ch;
+        }
+        if (!grid_sync(gs, nb, tmo)) return;
+        // H: control
+        if (threadIdx.x == 0)
+            for (int i = blockIdx.x; i < batch; i += nb) control_instance(inst[i], active);
+        if (!grid_sync(gs, nb, tmo)) return;
+    }
+
+    // ---- results: L, S (first d rows) and labels into the caller's buffers
+    for (int item = blockIdx.x; item < A.off_tile[batch]; item += nb) {
+        const int i = find_inst(A.off_tile, batch, item);
+        BatchInst& B = inst[i];
+        if (B.status < 0) continue;
+        const int local = item - A.off_tile[i];
+        const int cb = local / B.nrb, rb = local % B.nrb;
+        const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
+        const int64_t r0 = (int64_t)rb * kRowsPerBlock;
+        const int64_t r1 = min((int64_t)B.d, r0 + kRowsPerBlock);
+        for (int64_t j = j0; j < j1; ++j)
+            for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
+                B.Lc[j * B.ldl + r] = B.L[j * B.dp + r];
+                B.Sc[j * B.lds + r] = B.S[j * B.dp + r];
+            }
+    }
+    for (int i = blockIdx.x; i < batch; i += nb) {
+        BatchInst& B = inst[i];
+        if (B.labels_out && B.status >= 0) {
+            const int32_t* src = B.lab[B.cur];
+            for (int j = threadIdx.x; j < B.n; j += kBlock) B.labels_out[j] = src[j];
+        }
+    }
+}
+
+__global__ void k_batched_reset(BatchSync* s, int batch) {
+    if (threadIdx.x == 0) {
+        s->count = 0u;
+        s->gen = 0u;
+        s->abort = 0;
+        s->active = batch;
+    }
+}
+
+}  // namespace
+
+void launch_batched_reset(BatchSync* s, int batch, hipStream_t st) {
+    k_batched_reset<<<1, 64, 0, st>>>(s, batch);
+}
+
+void launch_batched(const BatchArgs& args, int nblocks, hipStream_t st) {
+    k_batched<<<nblocks, kBlock, 0, st>>>(args);
+}
+
+int batched_blocks_per_cu() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched, kBlock, 0) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+}  // namespace respca

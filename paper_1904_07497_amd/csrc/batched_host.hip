@@ -1,0 +1,410 @@
+// Host side of the batched solver: per-instance layout and workspace, work
+// tables, hipGraph capture/replay of the persistent launch, and the tile-shape
+// tuner with its on-disk cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/respca.h"
+#include "batched.h"
+#include "handle.h"
+#include "kernels.h"
+
+using namespace respca;
+
+namespace {
+
+constexpr int kTableCount = 7;
+constexpr double kBarrierTimeoutS = 4.0;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Every per-call input that the captured graph depends on lives in this header
+// block (descriptors, work tables, k-means++ uniforms); it is staged in pinned
+// memory and copied to the device by the graph's first node.
+struct Staged {
+    size_t inst_off, sync_off, table_off, u_off, header_bytes;  // device header layout
+    size_t readback_off;                                        // pinned readback area
+    size_t stage_bytes;
+};
+
+struct Call {
+    std::vector<BatchInst> inst;
+    std::vector<int32_t> tables[kTableCount];
+    std::vector<double> u;
+    std::vector<size_t> u_start;
+    size_t array_bytes = 0;  // per-instance arrays after the header
+    int cmax = 0;
+    int64_t max_steps = 0;
+};
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ULL) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+respca_status validate(respca_handle h, const respca_params* params, int32_t batch, const int64_t* d,
+                       const int64_t* n, const void* const* X, const int64_t* ldx, void* const* L,
+                       const int64_t* ldl, void* const* S, const int64_t* lds,
+                       std::vector<Resolved>& res) {
+    if (!params || batch < 1 || !d || !n || !X || !ldx || !L || !ldl || !S || !lds)
+        return fail(h, RESPCA_ERR_INVALID, "NULL argument or empty batch");
+    res.resize(batch);
+    for (int i = 0; i < batch; ++i) {
+        respca_status s = resolve(h, &params[i], d[i], n[i], res[i]);
+        if (s != RESPCA_OK) {
+            h->err = "instance " + std::to_string(i) + ": " + h->err;
+            return s;
+        }
+        if (res[i].precision != RESPCA_F32)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "batched solver runs FP32 instances only");
+        if (!X[i] || !L[i] || !S[i]) return fail(h, RESPCA_ERR_INVALID, "NULL matrix pointer");
+        if (ldx[i] < d[i] || ldl[i] < d[i] || lds[i] < d[i])
+            return fail(h, RESPCA_ERR_INVALID, "leading dimension < d");
+        if ((int64_t)(d[i] + 3) / 4 * 4 * n[i] >= (int64_t)INT32_MAX)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "batched instance too large");
+        if (res[i].init_labels) {
+            std::vector<int32_t> hl(n[i]);
+            CK(hipMemcpy(hl.data(), res[i].init_labels, n[i] * sizeof(int32_t), hipMemcpyDeviceToHost));
+            for (int64_t j = 0; j < n[i]; ++j)
+                if (hl[j] < 0 || hl[j] >= res[i].c)
+                    return fail(h, RESPCA_ERR_INVALID, "init_labels out of range");
+        }
+    }
+    return RESPCA_OK;
+}
+
+// Per-instance tiling and array layout; tables of work items.
+void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t* n,
+          const void* const* X, const int64_t* ldx, void* const* L, const int64_t* ldl,
+          void* const* S, const int64_t* lds, int32_t* const* labels,
+          const std::vector<Resolved>& res, Call& call) {
+    call.inst.assign(batch, BatchInst{});
+    for (auto& t : call.tables) t.assign(batch + 1, 0);
+    call.u.clear();
+    call.u_start.assign(batch, 0);
+    call.cmax = 0;
+    call.max_steps = 0;
+    size_t off = 0;
+    for (int i = 0; i < batch; ++i) {
+        BatchInst& B = call.inst[i];
+        const Resolved& r = res[i];
+        B.Xc = (const float*)X[i];
+        B.Lc = (float*)L[i];
+        B.Sc = (float*)S[i];
+        B.labels_out = labels ? labels[i] : nullptr;
+        B.init_labels = r.init_labels;
+        B.ldx = ldx[i];
+        B.ldl = ldl[i];
+        B.lds = lds[i];
+        B.d = (int)d[i];
+        B.dp = (int)((d[i] + 3) / 4 * 4);
+        B.n = (int)n[i];
+        B.c = r.c;
+        B.kpad = (r.c + 15) / 16 * 16;
+        B.nkc = (B.kpad + 127) / 128;
+        B.nrb = (B.dp + kRowsPerBlock - 1) / kRowsPerBlock;
+        B.jc = tune.jc;
+        int rows = std::max(32, tune.slice_rows / 32 * 32);
+        if (rows > B.dp) rows = (B.dp + 31) / 32 * 32;
+        B.slice_rows = rows;
+        B.slices = (B.dp + rows - 1) / rows;
+        const int ntiles = (B.n + 127) / 128;
+        B.n_sweep = ((B.n + B.jc - 1) / B.jc) * B.nrb;
+        B.n_argmin = (B.n + 15) / 16;
+        const int nseg_max = (B.n + kSegCols - 1) / kSegCols + B.c;
+        B.lambda = r.lambda;
+        B.tol = r.tol;
+        B.rho0 = r.rho0;
+        B.kappa = r.kappa;
+        B.rho_max = r.rho_max;
+        B.max_iter = r.max_iter;
+        B.max_lloyd = r.max_lloyd;
+        // work tables (prefix sums)
+        const int64_t counts[kTableCount] = {B.n_sweep, (B.n + 3) / 4, B.c, (int64_t)nseg_max * B.nrb,
+                                             (int64_t)B.c * ((B.dp + kBlock - 1) / kBlock),
+                                             (int64_t)ntiles * B.slices * B.nkc, B.n_argmin};
+        for (int t = 0; t < kTableCount; ++t)
+            call.tables[t][i + 1] = call.tables[t][i] + (int32_t)counts[t];
+        // arrays: offsets relative to the array area (pointers patched later)
+        const size_t dpn = (size_t)B.dp * B.n * sizeof(float);
+        auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+        B.X = (float*)take(dpn);
+        B.L = (float*)take(dpn);
+        B.S = (float*)take(dpn);
+        B.Th = (float*)take(dpn);
+        B.C = (float*)take((size_t)B.dp * B.c * sizeof(float));
+        B.lab[0] = (int32_t*)take(B.n * sizeof(int32_t));
+        B.lab[1] = (int32_t*)take(B.n * sizeof(int32_t));
+        B.perm = (int32_t*)take(B.n * sizeof(int32_t));
+        B.counts = (int32_t*)take(B.c * sizeof(int32_t));
+        B.segb = (int32_t*)take(nseg_max * sizeof(int32_t));
+        B.segl = (int32_t*)take(nseg_max * sizeof(int32_t));
+        B.segf = (int32_t*)take((B.c + 1) * sizeof(int32_t));
+        B.pmeans = (double*)take((size_t)nseg_max * B.dp * sizeof(double));
+        B.part = (float*)take((size_t)B.slices * B.n * B.kpad * sizeof(float));
+        B.d2 = (double*)take(B.n * sizeof(double));
+        B.chosen = (int32_t*)take(B.n * sizeof(int32_t));
+        B.seeds = (int32_t*)take(B.c * sizeof(int32_t));
+        B.cnorm = (double*)take(B.c * sizeof(double));
+        B.sweep_part = (double*)take(3 * (size_t)B.n_sweep * sizeof(double));
+        B.chg = (int32_t*)take(B.n_argmin * sizeof(int32_t));
+        // k-means++ uniforms from the instance's seed
+        call.u_start[i] = call.u.size();
+        uint64_t state = r.init_labels ? 0 : r.seed;
+        for (int m = 0; m < B.c; ++m) call.u.push_back(uniform01(state));
+        call.cmax = std::max(call.cmax, r.init_labels ? 0 : B.c);
+        call.max_steps += 2 + (int64_t)r.max_lloyd * (1 + (int64_t)r.max_iter);
+    }
+    call.array_bytes = off;
+    if (call.max_steps > 100000000) call.max_steps = 100000000;
+}
+
+Staged layout_of(const Call& call, int32_t batch) {
+    Staged s;
+    size_t o = 0;
+    s.inst_off = o;
+    o = align_up(o + batch * sizeof(BatchInst), 256);
+    s.sync_off = o;
+    o = align_up(o + sizeof(BatchSync), 256);
+    s.table_off = o;
+    o = align_up(o + (size_t)kTableCount * (batch + 1) * sizeof(int32_t), 256);
+    s.u_off = o;
+    o = align_up(o + std::max<size_t>(call.u.size(), 1) * sizeof(double), 256);
+    s.header_bytes = o;
+    s.readback_off = o;
+    s.stage_bytes = o + align_up(batch * sizeof(BatchInst) + 256 + sizeof(BatchSync), 256);
+    return s;
+}
+
+respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, hipStream_t caller,
+                          respca_info* info, double* elapsed_ms) {
+    Call call = call_in;
+    const Staged L = layout_of(call, batch);
+    const size_t total = L.header_bytes + call.array_bytes;
+    CKS(ensure(h, h->bws, total));
+    if (h->bstage_bytes < L.stage_bytes) {
+        if (h->bstage) CK(hipHostFree(h->bstage));
+        h->bstage = nullptr;
+        h->bstage_bytes = 0;
+        CK(hipHostMalloc((void**)&h->bstage, L.stage_bytes, hipHostMallocDefault));
+        h->bstage_bytes = L.stage_bytes;
+    }
+    if (!h->bstream) CK(hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking));
+    if (!h->bev) CK(hipEventCreateWithFlags(&h->bev, hipEventDisableTiming));
+
+    // patch array offsets into device pointers
+    char* base = (char*)h->bws.p;
+    char* arr = base + L.header_bytes;
+    auto fix = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(arr + (size_t)p); };
+    const double* u_dev = (const double*)(base + L.u_off);
+    for (int i = 0; i < batch; ++i) {
+        BatchInst& B = call.inst[i];
+        fix(B.X); fix(B.L); fix(B.S); fix(B.Th); fix(B.C); fix(B.lab[0]); fix(B.lab[1]); fix(B.perm);
+        fix(B.counts); fix(B.segb); fix(B.segl); fix(B.segf); fix(B.pmeans); fix(B.part); fix(B.d2);
+        fix(B.chosen); fix(B.seeds); fix(B.cnorm); fix(B.sweep_part); fix(B.chg);
+        B.u = u_dev + call.u_start[i];
+    }
+    // stage the header
+    char* st = h->bstage;
+    std::memcpy(st + L.inst_off, call.inst.data(), batch * sizeof(BatchInst));
+    std::memset(st + L.sync_off, 0, sizeof(BatchSync));
+    for (int t = 0; t < kTableCount; ++t)
+        std::memcpy(st + L.table_off + (size_t)t * (batch + 1) * sizeof(int32_t), call.tables[t].data(),
+                    (batch + 1) * sizeof(int32_t));
+    if (!call.u.empty()) std::memcpy(st + L.u_off, call.u.data(), call.u.size() * sizeof(double));
+
+    int dev = h->device, cus = 0, rate_khz = 0;
+    CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    const int occ = batched_blocks_per_cu();
+    if (occ < 1) return fail(h, RESPCA_ERR_HIP, "batched kernel cannot be resident");
+    const int nblocks = cus * std::max(1, std::min(occ, h->tune.blocks_per_cu));
+
+    BatchArgs args;
+    args.inst = (BatchInst*)(base + L.inst_off);
+    args.batch = batch;
+    args.sync = (BatchSync*)(base + L.sync_off);
+    args.timeout_ticks = (uint64_t)(kBarrierTimeoutS * (double)rate_khz * 1000.0);
+    args.cmax = call.cmax;
+    args.max_steps = (int)call.max_steps;
+    const int32_t* tb = (const int32_t*)(base + L.table_off);
+    args.off_tile = tb;
+    args.off_d2 = tb + 1 * (batch + 1);
+    args.off_kc = tb + 2 * (batch + 1);
+    args.off_seg = tb + 3 * (batch + 1);
+    args.off_kr = tb + 4 * (batch + 1);
+    args.off_dist = tb + 5 * (batch + 1);
+    args.off_col = tb + 6 * (batch + 1);
+
+    uint64_t sig = fnv1a(st, L.header_bytes);
+    sig = fnv1a(&nblocks, sizeof(nblocks), sig);
+    sig = fnv1a(&args, sizeof(args), sig);
+    if (!(h->bexec && h->bsig == sig)) {
+        if (h->bexec) CK(hipGraphExecDestroy(h->bexec));
+        if (h->bgraph) CK(hipGraphDestroy(h->bgraph));
+        h->bexec = nullptr;
+        h->bgraph = nullptr;
+        CK(hipStreamBeginCapture(h->bstream, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = hipMemcpyAsync(base, st, L.header_bytes, hipMemcpyHostToDevice, h->bstream);
+        launch_batched_reset(args.sync, batch, h->bstream);
+        launch_batched(args, nblocks, h->bstream);
+        hipError_t e2 = hipMemcpyAsync(st + L.readback_off, base + L.inst_off,
+                                       batch * sizeof(BatchInst), hipMemcpyDeviceToHost, h->bstream);
+        hipError_t e3 = hipMemcpyAsync(st + L.readback_off + align_up(batch * sizeof(BatchInst), 256),
+                                       base + L.sync_off, sizeof(BatchSync), hipMemcpyDeviceToHost,
+                                       h->bstream);
+        hipGraph_t g = nullptr;
+        hipError_t e4 = hipStreamEndCapture(h->bstream, &g);
+        CK(e1);
+        CK(e2);
+        CK(e3);
+        CK(e4);
+        h->bgraph = g;
+        CK(hipGraphInstantiate(&h->bexec, h->bgraph, nullptr, nullptr, 0));
+        h->bsig = sig;
+    }
+    // order after the caller's earlier work, replay, wait
+    CK(hipEventRecord(h->bev, caller));
+    CK(hipStreamWaitEvent(h->bstream, h->bev, 0));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (elapsed_ms) {
+        CK(hipEventCreate(&t0));
+        CK(hipEventCreate(&t1));
+        CK(hipEventRecord(t0, h->bstream));
+    }
+    CK(hipGraphLaunch(h->bexec, h->bstream));
+    if (elapsed_ms) CK(hipEventRecord(t1, h->bstream));
+    CK(hipStreamSynchronize(h->bstream));
+    if (elapsed_ms) {
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, t0, t1));
+        *elapsed_ms = ms;
+        CK(hipEventDestroy(t0));
+        CK(hipEventDestroy(t1));
+    }
+    const BatchInst* out = (const BatchInst*)(st + L.readback_off);
+    const BatchSync* sy = (const BatchSync*)(st + L.readback_off + align_up(batch * sizeof(BatchInst), 256));
+    if (sy->abort) return fail(h, RESPCA_ERR_HIP, "batched kernel: grid barrier timed out (aborted)");
+    respca_status worst = RESPCA_OK;
+    for (int i = 0; i < batch; ++i) {
+        const BatchInst& B = out[i];
+        if (info) {
+            respca_info& f = info[i];
+            std::memset(&f, 0, sizeof(f));
+            f.iters = B.iters;
+            f.lloyd_steps = B.lloyd_total;
+            f.init_lloyd = B.init_lloyd;
+            f.status = B.status;
+            f.primal = B.primal;
+            f.dL = B.dL;
+            f.dS = B.dS;
+            f.rho_final = B.rho_final;
+        }
+        if (B.status < 0 && (worst >= 0 || B.status < worst)) worst = (respca_status)B.status;
+        if (B.status == RESPCA_NOT_CONVERGED && worst == RESPCA_OK) worst = RESPCA_NOT_CONVERGED;
+    }
+    if (worst < 0) h->err = "an instance failed (see its info status)";
+    return worst;
+}
+
+std::string bucket_key(int32_t batch, const int64_t* d, const int64_t* n, const std::vector<Resolved>& r,
+                       int device) {
+    std::vector<double> dn(batch);
+    int cmax = 0;
+    for (int i = 0; i < batch; ++i) {
+        dn[i] = (double)d[i] * (double)n[i];
+        cmax = std::max(cmax, r[i].c);
+    }
+    std::nth_element(dn.begin(), dn.begin() + batch / 2, dn.end());
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+    for (auto& ch : arch) if (ch == ' ' || ch == ':') ch = '_';
+    char key[256];
+    std::snprintf(key, sizeof(key), "%s_b%d_dn2^%d_c%d", arch.c_str(), batch,
+                  (int)std::lround(std::log2(std::max(dn[batch / 2], 1.0))), cmax);
+    return key;
+}
+
+}  // namespace
+
+extern "C" {
+
+respca_status respca_solve_batched(respca_handle h, const respca_params* params, int32_t batch,
+                                   const int64_t* d, const int64_t* n, const void* const* X,
+                                   const int64_t* ldx, void* const* L, const int64_t* ldl,
+                                   void* const* S, const int64_t* lds, int32_t* const* labels,
+                                   respca_info* info, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    std::vector<Resolved> res;
+    CKS(validate(h, params, batch, d, n, X, ldx, L, ldl, S, lds, res));
+    CK(hipSetDevice(h->device));
+    Call call;
+    plan(h->tune, batch, d, n, X, ldx, L, ldl, S, lds, labels, res, call);
+    return run_batched(h, call, batch, (hipStream_t)stream, info, nullptr);
+}
+
+respca_status respca_autotune_batched(respca_handle h, const respca_params* params, int32_t batch,
+                                      const int64_t* d, const int64_t* n, const void* const* X,
+                                      const int64_t* ldx, void* const* L, const int64_t* ldl,
+                                      void* const* S, const int64_t* lds, const char* cache_path,
+                                      double* best_ms, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    std::vector<Resolved> res;
+    CKS(validate(h, params, batch, d, n, X, ldx, L, ldl, S, lds, res));
+    CK(hipSetDevice(h->device));
+    const std::string key = bucket_key(batch, d, n, res, h->device);
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char k[256];
+            int jc, rows, bpc;
+            double ms;
+            bool found = false;
+            while (std::fscanf(f, "%255s %d %d %d %lf", k, &jc, &rows, &bpc, &ms) == 5)
+                if (key == k) { h->tune = BatchTune{jc, rows, bpc}; if (best_ms) *best_ms = ms; found = true; }
+            std::fclose(f);
+            if (found) return RESPCA_OK;
+        }
+    }
+    const int jcs[] = {4, 8, 16};
+    const int rows_c[] = {512, 1024, 2048};
+    const int bpcs[] = {1, 2};
+    BatchTune best = h->tune;
+    double best_t = 1e300;
+    std::vector<respca_info> info(batch);
+    for (int bpc : bpcs)
+        for (int rows : rows_c)
+            for (int jc : jcs) {
+                h->tune = BatchTune{jc, rows, bpc};
+                Call call;
+                plan(h->tune, batch, d, n, X, ldx, L, ldl, S, lds, nullptr, res, call);
+                double ms = 0.0;
+                respca_status s = run_batched(h, call, batch, (hipStream_t)stream, info.data(), nullptr);
+                if (s < 0) return s;
+                CKS(run_batched(h, call, batch, (hipStream_t)stream, info.data(), &ms));  // graph replay
+                if (ms < best_t) { best_t = ms; best = h->tune; }
+            }
+    h->tune = best;
+    if (best_ms) *best_ms = best_t;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s %d %d %d %.4f\n", key.c_str(), best.jc, best.slice_rows,
+                         best.blocks_per_cu, best_t);
+            std::fclose(f);
+        }
+    }
+    return RESPCA_OK;
+}
+
+}  // extern "C"

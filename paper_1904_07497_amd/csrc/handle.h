@@ -1,0 +1,128 @@
+// Handle state and host-side helpers shared by the library's host files
+// (internal; not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/respca.h"
+
+namespace respca {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct ProfPending {
+    int kernel;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+
+// Tile shapes of the batched solver (set by the tuner, or these defaults).
+struct BatchTune {
+    int jc = 8;             // columns per sweep / pack work item
+    int slice_rows = 1024;  // rows per distance slice (multiple of 32)
+    int blocks_per_cu = 2;  // persistent workgroups per compute unit
+};
+
+}  // namespace respca
+
+struct respca_handle_s {
+    int device = 0;
+    std::string err;
+    // kernel timing
+    bool prof_on = false;
+    int64_t prof_launches[RESPCA_KERNEL_COUNT] = {};
+    double prof_ms[RESPCA_KERNEL_COUNT] = {};
+    double prof_bytes[RESPCA_KERNEL_COUNT] = {};
+    double prof_flops[RESPCA_KERNEL_COUNT] = {};
+    std::vector<respca::ProfPending> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    respca::DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, sortbc, pmeans, dots, cnorm,
+        lab_a, lab_b, d2, chosen, seeds, u, normp, chgp, status;
+    double* hstage = nullptr;  // pinned host staging (status readback, uniforms)
+    size_t hstage_bytes = 0;
+    // batched solver
+    respca::BatchTune tune;
+    respca::DevBuf bws;             // batched workspace (descriptors, tables, instance arrays)
+    char* bstage = nullptr;         // pinned staging of descriptors/tables/uniforms + readback
+    size_t bstage_bytes = 0;
+    hipStream_t bstream = nullptr;  // internal stream (graph capture needs a non-null stream)
+    hipEvent_t bev = nullptr;
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bexec = nullptr;
+    uint64_t bsig = 0;              // signature of the captured call
+};
+
+#define CK(expr)                                                                            \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            h->err = std::string(#expr) + ": " + hipGetErrorString(e_);                     \
+            return e_ == hipErrorOutOfMemory ? RESPCA_ERR_NOMEM : RESPCA_ERR_HIP;           \
+        }                                                                                   \
+    } while (0)
+
+#define CKS(expr)                                    \
+    do {                                             \
+        respca_status s_ = (expr);                   \
+        if (s_ < 0) return s_;                       \
+    } while (0)
+
+namespace respca {
+
+inline respca_status ensure(respca_handle h, DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return RESPCA_OK;
+    if (b.p) CK(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    CK(hipMalloc(&b.p, bytes));
+    b.bytes = bytes;
+    return RESPCA_OK;
+}
+
+inline respca_status ensure_host(respca_handle h, size_t bytes) {
+    if (h->hstage_bytes >= bytes) return RESPCA_OK;
+    if (h->hstage) CK(hipHostFree(h->hstage));
+    h->hstage = nullptr;
+    h->hstage_bytes = 0;
+    CK(hipHostMalloc((void**)&h->hstage, bytes, hipHostMallocDefault));
+    h->hstage_bytes = bytes;
+    return RESPCA_OK;
+}
+
+inline respca_status fail(respca_handle h, respca_status s, const std::string& msg) {
+    if (h) h->err = msg;
+    return s;
+}
+
+// splitmix64 (Steele, Lea & Flood 2014) and the uniform in [0, 1) from its top 53 bits.
+inline uint64_t splitmix64_next(uint64_t& state) {
+    uint64_t z = (state += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+inline double uniform01(uint64_t& state) {
+    return (double)(splitmix64_next(state) >> 11) * 0x1.0p-53;
+}
+
+// Parameters after defaults are applied.
+struct Resolved {
+    double lambda, tol, rho0, kappa, rho_max;
+    int c, max_iter, max_lloyd, precision;
+    uint64_t seed;
+    const int32_t* init_labels;
+    double* history;
+};
+
+respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_t n, Resolved& r);
+
+}  // namespace respca

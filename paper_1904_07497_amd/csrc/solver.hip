@@ -11,90 +11,14 @@
 #include <vector>
 
 #include "../../include/respca.h"
+#include "handle.h"
 #include "kernels.h"
 
 using namespace respca;
 
 namespace {
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-};
-
-}  // namespace
-
-struct ProfPending {
-    int kernel;
-    hipEvent_t a, b;
-    double bytes, flops;
-};
-
-struct respca_handle_s {
-    int device = 0;
-    std::string err;
-    // kernel timing
-    bool prof_on = false;
-    int64_t prof_launches[RESPCA_KERNEL_COUNT] = {};
-    double prof_ms[RESPCA_KERNEL_COUNT] = {};
-    double prof_bytes[RESPCA_KERNEL_COUNT] = {};
-    double prof_flops[RESPCA_KERNEL_COUNT] = {};
-    std::vector<ProfPending> prof_pending;
-    std::vector<hipEvent_t> prof_pool;
-    DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, sortbc, pmeans, dots, cnorm, lab_a,
-        lab_b, d2, chosen, seeds, u, normp, chgp, status;
-    double* hstage = nullptr;  // pinned host staging (status readback, uniforms)
-    size_t hstage_bytes = 0;
-};
-
-namespace {
-
-const char* kVersion = "librespca 0.1 (gfx950)";
-
-struct HipFail {
-    respca_status code;
-};
-
-#define CK(expr)                                                                            \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess) {                                                             \
-            h->err = std::string(#expr) + ": " + hipGetErrorString(e_);                     \
-            return e_ == hipErrorOutOfMemory ? RESPCA_ERR_NOMEM : RESPCA_ERR_HIP;           \
-        }                                                                                   \
-    } while (0)
-
-#define CKS(expr)                                    \
-    do {                                             \
-        respca_status s_ = (expr);                   \
-        if (s_ < 0) return s_;                       \
-    } while (0)
-
-respca_status ensure(respca_handle h, DevBuf& b, size_t bytes) {
-    if (bytes == 0) bytes = 16;
-    if (b.bytes >= bytes) return RESPCA_OK;
-    if (b.p) CK(hipFree(b.p));
-    b.p = nullptr;
-    b.bytes = 0;
-    CK(hipMalloc(&b.p, bytes));
-    b.bytes = bytes;
-    return RESPCA_OK;
-}
-
-respca_status ensure_host(respca_handle h, size_t bytes) {
-    if (h->hstage_bytes >= bytes) return RESPCA_OK;
-    if (h->hstage) CK(hipHostFree(h->hstage));
-    h->hstage = nullptr;
-    h->hstage_bytes = 0;
-    CK(hipHostMalloc((void**)&h->hstage, bytes, hipHostMallocDefault));
-    h->hstage_bytes = bytes;
-    return RESPCA_OK;
-}
-
-respca_status fail(respca_handle h, respca_status s, const std::string& msg) {
-    if (h) h->err = msg;
-    return s;
-}
+const char* kVersion = "librespca 0.2 (gfx950)";
 
 // Event bracket around one launch (no-op unless timing is enabled).
 struct ProfScope {
@@ -143,25 +67,9 @@ void prof_resolve(respca_handle h) {
     h->prof_pending.clear();
 }
 
-uint64_t splitmix64_next(uint64_t& state) {
-    uint64_t z = (state += 0x9E3779B97F4A7C15ULL);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
+}  // namespace
 
-double uniform01(uint64_t& state) { return (double)(splitmix64_next(state) >> 11) * 0x1.0p-53; }
-
-// Parameters after defaults are applied.
-struct Resolved {
-    double lambda, tol, rho0, kappa, rho_max;
-    int c, max_iter, max_lloyd, precision;
-    uint64_t seed;
-    const int32_t* init_labels;
-    double* history;
-};
-
-respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_t n, Resolved& r) {
+respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d, int64_t n, Resolved& r) {
     if (!p) return fail(h, RESPCA_ERR_INVALID, "params is NULL");
     if (d < 1 || n < 1 || d >= (int64_t)INT32_MAX || n >= (int64_t)INT32_MAX)
         return fail(h, RESPCA_ERR_INVALID, "d and n must be in [1, 2^31)");
@@ -191,6 +99,8 @@ respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_
         return fail(h, RESPCA_ERR_INVALID, "unknown precision");
     return RESPCA_OK;
 }
+
+namespace {
 
 struct Span {
     uintptr_t lo, hi;
@@ -550,6 +460,12 @@ void respca_destroy(respca_handle h) {
         (void)hipEventDestroy(p.b);
     }
     for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
+    if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
+    if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
+    if (h->bev) (void)hipEventDestroy(h->bev);
+    if (h->bstream) (void)hipStreamDestroy(h->bstream);
+    if (h->bws.p) (void)hipFree(h->bws.p);
+    if (h->bstage) (void)hipHostFree(h->bstage);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
                       &h->nseg, &h->sortbc, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b, &h->d2,
                       &h->chosen, &h->seeds, &h->u, &h->normp, &h->chgp, &h->status};

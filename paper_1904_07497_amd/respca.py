@@ -24,7 +24,8 @@ F64, F32, BF16GEMM_F32 = 0, 1, 2
 # Every symbol include/respca.h declares.
 EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_status_string",
            "respca_last_error", "respca_version", "respca_solve", "respca_iterate",
-           "respca_kmeans", "respca_profile_enable", "respca_profile_query")
+           "respca_kmeans", "respca_profile_enable", "respca_profile_query",
+           "respca_solve_batched", "respca_autotune_batched")
 KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3}
 
 
@@ -86,6 +87,14 @@ def lib():
         L.respca_profile_query.restype = i32
         L.respca_profile_query.argtypes = [vp, i32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
                                            ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
+        arr = ct.POINTER(ct.c_void_p)
+        i64p = ct.POINTER(ct.c_int64)
+        L.respca_solve_batched.restype = i32
+        L.respca_solve_batched.argtypes = [vp, ct.POINTER(Params), i32, i64p, i64p, arr, i64p, arr, i64p,
+                                           arr, i64p, arr, ct.POINTER(Info), vp]
+        L.respca_autotune_batched.restype = i32
+        L.respca_autotune_batched.argtypes = [vp, ct.POINTER(Params), i32, i64p, i64p, arr, i64p, arr,
+                                              i64p, arr, i64p, ct.c_char_p, ct.POINTER(ct.c_double), vp]
         L.respca_kmeans.restype = i32
         L.respca_kmeans.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, vp,
                                     ct.POINTER(Info), vp]
@@ -292,3 +301,79 @@ def profile_query(device: int = 0) -> dict:
                                            ct.byref(fl)), allow=(OK,))
         out[name] = {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
     return out
+
+
+# ------------------------------------------------------------------ batched
+
+def _batch_args(Xs, params_list, outs):
+    import torch
+    b = len(Xs)
+    P = (Params * b)(*params_list)
+    d = (ct.c_int64 * b)(*[x.shape[0] for x in Xs])
+    n = (ct.c_int64 * b)(*[x.shape[1] for x in Xs])
+    def ptrs(ts, name):
+        vals, lds = [], []
+        for t in ts:
+            p, ld = _colmajor(t, name)
+            if t.dtype != torch.float32:
+                raise ValueError(f"{name} must be float32")
+            vals.append(p)
+            lds.append(ld)
+        return (ct.c_void_p * b)(*vals), (ct.c_int64 * b)(*lds)
+    Xp, ldx = ptrs(Xs, "X")
+    Lp, ldl = ptrs([o[0] for o in outs], "L")
+    Sp, lds = ptrs([o[1] for o in outs], "S")
+    Lab = (ct.c_void_p * b)(*[o[2].data_ptr() for o in outs])
+    return b, P, d, n, Xp, ldx, Lp, ldl, Sp, lds, Lab
+
+
+def batch_params(ranks, lams=None, tol=1e-6, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
+                 max_lloyd=100, seeds=None, init_labels=None):
+    """Per-instance Params (FP32).  ``rho0`` may be a scalar or a per-instance list;
+    ``init_labels`` a list of device int32 tensors or None entries."""
+    b = len(ranks)
+    out, keep = [], []
+    for i in range(b):
+        r0 = rho0[i] if isinstance(rho0, (list, tuple)) else rho0
+        p = make_params(ranks[i], None if lams is None else lams[i], tol, max_iter, r0, kappa,
+                        rho_max, max_lloyd, 0 if seeds is None else seeds[i], F32)
+        if init_labels is not None and init_labels[i] is not None:
+            p.init_labels = init_labels[i].data_ptr()
+            keep.append(init_labels[i])
+        out.append(p)
+    return out, keep
+
+
+def solve_batched(Xs, params_list, outs=None, stream=None, device=0):
+    """Solve many instances in one persistent launch.  Xs: list of (d, n) float32
+    column-major device tensors; params_list: from batch_params.  Returns
+    (outs [(L, S, labels)], infos [dict], status)."""
+    import torch
+    if outs is None:
+        outs = [(empty_colmajor(x.shape[0], x.shape[1], x.dtype, x.device),
+                 empty_colmajor(x.shape[0], x.shape[1], x.dtype, x.device),
+                 torch.empty(x.shape[1], dtype=torch.int32, device=x.device)) for x in Xs]
+    b, P, d, n, Xp, ldx, Lp, ldl, Sp, lds, Lab = _batch_args(Xs, params_list, outs)
+    info = (Info * b)()
+    h = handle(device)
+    s = lib().respca_solve_batched(h._h, P, b, d, n, Xp, ldx, Lp, ldl, Sp, lds, Lab, info,
+                                   _stream(stream))
+    h.check(s)
+    return outs, [info[i].as_dict() for i in range(b)], s
+
+
+def autotune_batched(Xs, params_list, cache_path=None, outs=None, stream=None, device=0):
+    """Run the batched tile-shape tuner (result kept in the handle); returns best ms."""
+    import torch
+    if outs is None:
+        outs = [(empty_colmajor(x.shape[0], x.shape[1], x.dtype, x.device),
+                 empty_colmajor(x.shape[0], x.shape[1], x.dtype, x.device),
+                 torch.empty(x.shape[1], dtype=torch.int32, device=x.device)) for x in Xs]
+    b, P, d, n, Xp, ldx, Lp, ldl, Sp, lds, _ = _batch_args(Xs, params_list, outs)
+    best = ct.c_double(0.0)
+    h = handle(device)
+    s = lib().respca_autotune_batched(h._h, P, b, d, n, Xp, ldx, Lp, ldl, Sp, lds,
+                                      cache_path.encode() if cache_path else None, ct.byref(best),
+                                      _stream(stream))
+    h.check(s, allow=(OK,))
+    return best.value

@@ -403,3 +403,91 @@ def test_bf16_iterate_full_size_sampled_columns():
     sep = gap > bound
     assert sep.mean() > 0.9
     np.testing.assert_array_equal(lab[sep], o["labels"][sep])
+
+
+# ------------------------------------------------------------ batched solver
+
+def _batch_mix(seed=7):
+    """Grouped instances of uneven, ragged sizes (labels well separated)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(37, 50, 3), (200, 333, 5), (513, 129, 7), (1030, 241, 4), (64, 700, 9),
+              (255, 255, 6), (2049, 97, 3), (321, 1025, 12), (8, 40, 2), (1500, 600, 20)]
+    Xs = []
+    for i, (d, n, c) in enumerate(shapes):
+        X, _, _, _ = synth.clustered(d, n, c, seed=int(rng.integers(1 << 30)), sep=4.0, noise=0.5,
+                                     frac=0.05, amp=8.0, dtype=np.float32, min_size=2)
+        Xs.append(X)
+    return shapes, Xs
+
+
+def test_batched_matches_oracle_per_instance():
+    """Every instance of a ragged batch, solved in one persistent launch, meets the
+    FP32 bar against the oracle run on that instance alone (iteration-locked)."""
+    shapes, Xs = _batch_mix()
+    lams = [0.5 if i % 3 == 0 else float(np.sqrt(max(s[0], s[1]))) for i, s in enumerate(shapes)]
+    T = []
+    for X, (d, n, c), lam, i in zip(Xs, shapes, lams, range(len(shapes))):
+        o = oracle.solve(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=i))
+        T.append(o)
+    plist, keep = rp.batch_params([s[2] for s in shapes], lams, tol=0.0,
+                                  max_iter=0, seeds=list(range(len(shapes))))
+    for p, o in zip(plist, T):
+        p.max_iter = o["info"]["iters"]
+    Xd = [dev(X) for X in Xs]
+    outs, infos, status = rp.solve_batched(Xd, plist)
+    for i, (X, o) in enumerate(zip(Xs, T)):
+        say(f"batched instance {i} {shapes[i]} iters {infos[i]['iters']} / {o['info']['iters']}")
+        assert infos[i]["iters"] == o["info"]["iters"]
+        assert infos[i]["init_lloyd"] == o["info"]["init_lloyd"]
+        np.testing.assert_array_equal(outs[i][2].cpu().numpy(), o["labels"])
+        nX = np.linalg.norm(X.astype(np.float64))
+        assert rel(host(outs[i][0]), o["L"], nX) <= F32_TOL, i
+        assert rel(host(outs[i][1]), o["S"], nX) <= F32_TOL, i
+
+
+def test_batched_special_instances_and_replay():
+    """Zero input, warm start from labels, lambda = 0 and the same call replayed
+    from the captured graph (bitwise identical)."""
+    rng = np.random.default_rng(3)
+    X0 = np.zeros((30, 20), np.float32, order="F")
+    X1, _, _, _ = synth.clustered(100, 80, 4, seed=5, sep=4.0, dtype=np.float32)
+    X2 = np.asfortranarray(rng.normal(size=(17, 23)).astype(np.float32))
+    init = torch.from_numpy(rng.integers(0, 4, 80).astype(np.int32)).cuda()
+    Xd = [dev(X0), dev(X1), dev(X2)]
+    plist, keep = rp.batch_params([2, 4, 3], [1.0, 0.7, 0.0], tol=1e-6,
+                                  init_labels=[None, init, None])
+    outs, infos, status = rp.solve_batched(Xd, plist)
+    assert infos[0]["status"] == 0 and infos[0]["iters"] == 0
+    assert not outs[0][0].any() and not outs[0][1].any()
+    o = oracle.solve(X1, oracle.make_params(4, lam=0.7, tol=1e-6), init_labels=init.cpu().numpy())
+    assert infos[1]["iters"] == o["info"]["iters"] and infos[1]["init_lloyd"] == 0
+    nX = np.linalg.norm(X1.astype(np.float64))
+    assert rel(host(outs[1][0]), o["L"], nX) <= F32_TOL
+    assert infos[2]["iters"] == 2
+    np.testing.assert_allclose(host(outs[2][0]), X2.astype(np.float64), atol=0)
+    snap = [(a.clone(), b.clone(), c.clone()) for a, b, c in outs]
+    outs2, infos2, _ = rp.solve_batched(Xd, plist, outs=outs)
+    for (a, b, c), (a2, b2, c2) in zip(snap, outs2):
+        assert torch.equal(a, a2) and torch.equal(b, b2) and torch.equal(c, c2)
+    assert infos2 == infos
+
+
+def test_batched_size_mix_converges():
+    """The 256-instance size mix (d, n log-uniform in [200, 4000], rank 5-50,
+    1-20 % corruptions in [-50, 50], c = rank, lambda = 1/sqrt(max(d, n)),
+    tol 1e-6) in one launch: every instance converges and X = L + S to tol."""
+    Xs, ranks, lams = [], [], []
+    for i in range(256):
+        X, r, meta = synth.batch_instance(i)
+        Xs.append(dev(X))
+        ranks.append(r)
+        lams.append(1.0 / np.sqrt(max(meta["d"], meta["n"])))
+    say("batched size mix: solving")
+    plist, _ = rp.batch_params(ranks, lams, tol=1e-6)
+    outs, infos, status = rp.solve_batched(Xs, plist)
+    assert status == rp.OK
+    for i, (X, (L, S, lab)) in enumerate(zip(Xs, outs)):
+        assert infos[i]["status"] == 0
+        r = torch.linalg.norm(X.double() - L.double() - S.double()) / torch.linalg.norm(X.double())
+        assert float(r) <= 1.5e-6, (i, float(r))
+        assert int(lab.min()) >= 0 and int(lab.max()) < ranks[i]
