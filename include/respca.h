@@ -162,7 +162,7 @@ respca_status respca_kmeans(respca_handle h, const respca_params *params,
  *              (host arrays of them).  labels: nullable host array of nullable
  *              device int32[n[i]] pointers.  info: host array of `batch` structs.
  * Tile shapes come from the handle's tuning (respca_autotune_batched) or the
- * defaults.  Returns RESPCA_OK when every instance converged, otherwise the
+ * defaults.  At most 1024 instances per call (RESPCA_ERR_UNSUPPORTED beyond).  Returns RESPCA_OK when every instance converged, otherwise the
  * first non-OK instance status (each info[i].status has its own).
  */
 respca_status respca_solve_batched(respca_handle h, const respca_params *params, int32_t batch,
@@ -202,7 +202,11 @@ typedef enum {
     RESPCA_KERNEL_MEANS = 1,      /* group partial sums: reads X, S, Theta (or one array)            */
     RESPCA_KERNEL_DISTANCE = 2,   /* centroid . column products: reads the d x n operand once       */
     RESPCA_KERNEL_SEEDING = 3,    /* k-means++ squared distances: reads X once                      */
-    RESPCA_KERNEL_COUNT = 4
+    RESPCA_KERNEL_BATCHED = 4,    /* one persistent batched launch (graph replay); bytes = the
+                                     method's passes of every instance: 1 (||X||) + c (seeding)
+                                     + 1 + 2 per initial Lloyd pass + 11 per outer iteration
+                                     + 2 per extra Lloyd pass, times d n 4                          */
+    RESPCA_KERNEL_COUNT = 5
 } respca_kernel_id;
 
 respca_status respca_profile_enable(respca_handle h, int32_t enable);
@@ -211,6 +215,14 @@ respca_status respca_profile_enable(respca_handle h, int32_t enable);
  * contraction's 2 c d n per pass; zero for the streaming kernels). */
 respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t *launches,
                                    double *total_ms, double *bytes, double *flops);
+
+/* Phase breakdown of the last batched launch: ms[p] for the phases
+ * pack, init, seed-distance, seed-draw, seed-gather, sort, means, finalize,
+ * sweep, centroid-norms, distance, argmin, control (count <= 13 entries are
+ * written; each is the wall time one workgroup spent in that phase including its
+ * barrier wait), and *steps the number of state-machine steps.  Host outputs. */
+respca_status respca_profile_batched_phases(respca_handle h, double *ms, int32_t count,
+                                            int64_t *steps);
 
 #ifdef __cplusplus
 }

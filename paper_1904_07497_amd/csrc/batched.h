@@ -7,6 +7,8 @@
 
 namespace respca {
 
+constexpr int kMaxBatch = 1024;   // instances per batched call (LDS-cached work tables)
+
 // One instance.  The static part is written by the host; the state part is
 // owned by the kernel (initialised in its first phases, read back by the host).
 struct BatchInst {
@@ -48,11 +50,19 @@ struct BatchInst {
     double rho, nx, rho_final, primal, dL, dS;
 };
 
+// Phases of the persistent kernel, for its per-phase timing.
+enum BatchPhase : int {
+    BP_PACK = 0, BP_INIT, BP_SEED_D2, BP_SEED_PICK, BP_GATHER, BP_SORT, BP_MEANS, BP_FINALIZE,
+    BP_SWEEP, BP_CNORM, BP_DIST, BP_ARGMIN, BP_CONTROL, BP_COUNT
+};
+
 struct BatchSync {
     unsigned count;
     unsigned gen;
     int abort;
     int active;
+    uint64_t phase_ticks[BP_COUNT];  // wall-clock ticks per phase, measured by workgroup 0
+    uint64_t steps;
 };
 
 struct BatchArgs {

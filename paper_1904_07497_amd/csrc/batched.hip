@@ -32,7 +32,8 @@ enum Mode : int { M_DONE = 0, M_SEED = 1, M_MEANSX = 2, M_KMX = 3, M_ITER = 4, M
 
 // ---------------------------------------------------------------- barrier
 
-__device__ bool grid_sync(BatchSync* gs, unsigned nblocks, uint64_t timeout_ticks) {
+__device__ bool grid_sync(BatchSync* gs, unsigned nblocks, uint64_t timeout_ticks, int phase,
+                          uint64_t& t_prev) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -60,6 +61,11 @@ __device__ bool grid_sync(BatchSync* gs, unsigned nblocks, uint64_t timeout_tick
             ab = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         s_ok = ab ? 0 : 1;
+        if (blockIdx.x == 0) {   // phase time as seen by one workgroup: its work plus the wait
+            const uint64_t t = wall_clock64();
+            gs->phase_ticks[phase] += t - t_prev;
+            t_prev = t;
+        }
     }
     __syncthreads();
     return s_ok != 0;
@@ -215,13 +221,31 @@ __device__ void pick_instance(BatchInst& B, int m) {
     if (tid == 0) { B.seeds[m] = s; B.chosen[s] = 1; }
 }
 
-// Control step of one instance (thread 0 of one workgroup).
+// Control step of one instance: the workgroup sums the changed counts and (for
+// an outer iteration) the sweep's norm partials in fixed order, then thread 0
+// updates the state.
 __device__ void control_instance(BatchInst& B, int* active) {
-    const int mode = B.mode;
-    if (!needs_assign(mode) && mode != M_MEANSX) return;
+    __shared__ int s_mode;
+    if (threadIdx.x == 0) s_mode = B.mode;
+    __syncthreads();
+    const int mode0 = s_mode;
+    if (!needs_assign(mode0) && mode0 != M_MEANSX) return;
+    double ch = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0, z = 0.0;
+    if (mode0 != M_MEANSX) {
+        for (int t = threadIdx.x; t < B.n_argmin; t += kBlock) ch += (double)B.chg[t];
+        if (mode0 == M_ITER)
+            for (int t = threadIdx.x; t < B.n_sweep; t += kBlock) {
+                a0 += B.sweep_part[3 * t];
+                a1 += B.sweep_part[3 * t + 1];
+                a2 += B.sweep_part[3 * t + 2];
+            }
+    }
+    block_sum3(ch, z, z);
+    block_sum3(a0, a1, a2);
+    if (threadIdx.x != 0) return;
+    const int mode = mode0;
     if (mode == M_MEANSX) { B.mode = M_ITER; return; }
-    int changed = 0;
-    for (int t = 0; t < B.n_argmin; ++t) changed += B.chg[t];
+    const int changed = (int)ch;
     if (mode == M_SEED) { B.cur ^= 1; B.mode = M_KMX; return; }
     if (mode == M_KMX) {
         B.init_lloyd += 1;
@@ -234,12 +258,6 @@ __device__ void control_instance(BatchInst& B, int* active) {
         return;
     }
     if (mode == M_ITER) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int t = 0; t < B.n_sweep; ++t) {
-            a0 += B.sweep_part[3 * t];
-            a1 += B.sweep_part[3 * t + 1];
-            a2 += B.sweep_part[3 * t + 2];
-        }
         B.iters += 1;
         B.rho_final = B.rho;
         B.primal = sqrt(a0) / B.nx;
@@ -273,6 +291,27 @@ __device__ void control_instance(BatchInst& B, int* active) {
 
 // --------------------------------------------------------------- kernel
 
+// Work-item walk of one phase: items item = blockIdx.x + k * gridDim.x of the
+// prefix table `tab` (cached in LDS), instance found by a forward scan; an
+// instance whose mode does not need the phase is skipped in one step.
+template <typename Need, typename Body>
+__device__ inline void for_items(int batch, const int* tab, const int* modes, Need need, Body body) {
+    const unsigned nb = gridDim.x;
+    const int total = tab[batch];
+    int i = 0;
+    int item = blockIdx.x;
+    while (item < total) {
+        while (tab[i + 1] <= item) ++i;
+        if (!need(modes[i])) {
+            const int next = tab[i + 1];
+            item = next + (int)((blockIdx.x + nb - (unsigned)next % nb) % nb);
+            continue;
+        }
+        body(i, item - tab[i]);
+        item += nb;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_batched(BatchArgs A) {
     BatchInst* __restrict__ inst = A.inst;
     const int batch = A.batch;
@@ -280,13 +319,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const uint64_t tmo = A.timeout_ticks;
     BatchSync* gs = A.sync;
     int* active = &A.sync->active;
+    uint64_t tclk = wall_clock64();
+    __shared__ int s_tab[kMaxBatch + 1];
+    __shared__ int s_mode[kMaxBatch];
+    __shared__ int s_nseg[kMaxBatch];
+    auto load_tab = [&](const int32_t* off) {
+        __syncthreads();
+        for (int t = threadIdx.x; t <= batch; t += kBlock) s_tab[t] = off[t];
+        __syncthreads();
+    };
+    auto load_modes = [&]() {
+        __syncthreads();
+        for (int t = threadIdx.x; t < batch; t += kBlock)
+            s_mode[t] = __hip_atomic_load(&inst[t].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    };
+    auto any = [](int) { return true; };
 
     // ---- phase: copy X into its zero-padded internal copy; zero L, S, Theta;
     //      sums of squares of X
-    for (int item = blockIdx.x; item < A.off_tile[batch]; item += nb) {
-        const int i = find_inst(A.off_tile, batch, item);
+    load_tab(A.off_tile);
+    for (int t = threadIdx.x; t < batch; t += kBlock) s_mode[t] = 1;
+    __syncthreads();
+    for_items(batch, s_tab, s_mode, any, [&](int i, int local) {
         BatchInst& B = inst[i];
-        const int local = item - A.off_tile[i];
         const int cb = local / B.nrb, rb = local % B.nrb;
         const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
         const int64_t r0 = (int64_t)rb * kRowsPerBlock;
@@ -306,16 +362,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             }
         block_sum3(a, b, c);
         if (threadIdx.x == 0) B.sweep_part[3 * local] = a;
-    }
-    if (!grid_sync(gs, nb, tmo)) return;
+    });
+    if (!grid_sync(gs, nb, tmo, BP_PACK, tclk)) return;
 
     // ---- phase: initial state of every instance
     for (int i = blockIdx.x; i < batch; i += nb) {
         BatchInst& B = inst[i];
-        __shared__ int s_mode, s_status;
+        __shared__ int s_m, s_status;
+        double nx2 = 0.0, z1 = 0.0, z2 = 0.0;
+        for (int t = threadIdx.x; t < B.n_sweep; t += kBlock) nx2 += B.sweep_part[3 * t];
+        block_sum3(nx2, z1, z2);
         if (threadIdx.x == 0) {
-            double nx2 = 0.0;
-            for (int t = 0; t < B.n_sweep; ++t) nx2 += B.sweep_part[3 * t];
             B.nx = sqrt(nx2);
             B.cur = 0;
             B.iters = B.lloyd_total = B.lloyd_iter = B.init_lloyd = 0;
@@ -326,11 +383,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             if (!isfinite(nx2)) { B.status = -2; B.mode = M_DONE; atomicSub(active, 1); }
             else if (nx2 == 0.0) { B.status = 0; B.mode = M_DONE; atomicSub(active, 1); }
             else { B.status = 1; B.mode = B.init_labels ? M_MEANSX : M_SEED; }
-            s_mode = B.mode;
+            s_m = B.mode;
             s_status = B.status;
         }
         __syncthreads();
-        const int m = s_mode;
+        const int m = s_m;
         if (s_status == 0 && m == M_DONE)
             for (int j = threadIdx.x; j < B.n; j += kBlock) B.lab[0][j] = 0;
         if (m == M_MEANSX) {
@@ -349,70 +406,82 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         }
         __syncthreads();
     }
-    if (!grid_sync(gs, nb, tmo)) return;
+    if (!grid_sync(gs, nb, tmo, BP_INIT, tclk)) return;
+    load_modes();
 
     // ---- k-means++ seeding, seed by seed, for instances in M_SEED
+    auto is_seed = [](int m) { return m == M_SEED; };
     for (int m = 0; m < A.cmax; ++m) {
-        for (int item = blockIdx.x; item < A.off_d2[batch]; item += nb) {
-            const int i = find_inst(A.off_d2, batch, item);
+        load_tab(A.off_d2);
+        for_items(batch, s_tab, s_mode, is_seed, [&](int i, int local) {
             BatchInst& B = inst[i];
-            if (B.mode != M_SEED || m >= B.c) continue;
+            if (m >= B.c) return;
             const int lane = threadIdx.x & 63;
-            const int64_t j = (int64_t)(item - A.off_d2[i]) * 4 + (threadIdx.x >> 6);
-            if (j >= B.n) continue;
+            const int64_t j = (int64_t)local * 4 + (threadIdx.x >> 6);
+            if (j >= B.n) return;
             const float* yj = B.X + j * B.dp;
             const float* ys = B.X + (int64_t)B.seeds[m] * B.dp;
-            double acc = 0.0;
-            for (int64_t r = lane * 4; r < B.dp; r += 256) {
-                const float4 a = *reinterpret_cast<const float4*>(yj + r);
-                const float4 b = *reinterpret_cast<const float4*>(ys + r);
-                const double e0 = (double)a.x - b.x, e1 = (double)a.y - b.y;
-                const double e2 = (double)a.z - b.z, e3 = (double)a.w - b.w;
-                acc += e0 * e0;
-                acc += e1 * e1;
-                acc += e2 * e2;
-                acc += e3 * e3;
+            double acc0 = 0.0, acc1 = 0.0;
+            int64_t r = lane * 4;
+            for (; r + 256 < B.dp; r += 512) {        // two rows groups in flight
+                const float4 a0 = *reinterpret_cast<const float4*>(yj + r);
+                const float4 b0 = *reinterpret_cast<const float4*>(ys + r);
+                const float4 a1 = *reinterpret_cast<const float4*>(yj + r + 256);
+                const float4 b1 = *reinterpret_cast<const float4*>(ys + r + 256);
+                const double e0 = (double)a0.x - b0.x, e1 = (double)a0.y - b0.y;
+                const double e2 = (double)a0.z - b0.z, e3 = (double)a0.w - b0.w;
+                const double f0 = (double)a1.x - b1.x, f1 = (double)a1.y - b1.y;
+                const double f2 = (double)a1.z - b1.z, f3 = (double)a1.w - b1.w;
+                acc0 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+                acc1 += f0 * f0 + f1 * f1 + f2 * f2 + f3 * f3;
             }
-            acc = wave_sum(acc);
+            if (r < B.dp) {
+                const float4 a0 = *reinterpret_cast<const float4*>(yj + r);
+                const float4 b0 = *reinterpret_cast<const float4*>(ys + r);
+                const double e0 = (double)a0.x - b0.x, e1 = (double)a0.y - b0.y;
+                const double e2 = (double)a0.z - b0.z, e3 = (double)a0.w - b0.w;
+                acc0 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+            }
+            double acc = wave_sum(acc0 + acc1);
             if (lane == 0) B.d2[j] = (m == 0) ? acc : fmin(B.d2[j], acc);
-        }
-        if (!grid_sync(gs, nb, tmo)) return;
+        });
+        if (!grid_sync(gs, nb, tmo, BP_SEED_D2, tclk)) return;
         if (m + 1 >= A.cmax) break;
         for (int i = blockIdx.x; i < batch; i += nb) {
             BatchInst& B = inst[i];
-            if (B.mode == M_SEED && m + 1 < B.c) pick_instance(B, m + 1);
+            if (s_mode[i] == M_SEED && m + 1 < B.c) pick_instance(B, m + 1);
         }
-        if (!grid_sync(gs, nb, tmo)) return;
+        if (!grid_sync(gs, nb, tmo, BP_SEED_PICK, tclk)) return;
     }
     // centroids = seed columns
-    for (int item = blockIdx.x; item < A.off_kc[batch]; item += nb) {
-        const int i = find_inst(A.off_kc, batch, item);
+    load_tab(A.off_kc);
+    for_items(batch, s_tab, s_mode, is_seed, [&](int i, int k) {
         BatchInst& B = inst[i];
-        if (B.mode != M_SEED) continue;
-        const int k = item - A.off_kc[i];
         const float* src = B.X + (int64_t)B.seeds[k] * B.dp;
         for (int64_t r = threadIdx.x; r < B.dp; r += kBlock) B.C[(int64_t)k * B.dp + r] = src[r];
-    }
-    if (!grid_sync(gs, nb, tmo)) return;
+    });
+    if (!grid_sync(gs, nb, tmo, BP_GATHER, tclk)) return;
 
     // ---- main loop: one step of every live instance per pass
     for (int step = 0; step < A.max_steps; ++step) {
         if (__hip_atomic_load(active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0) break;
+        load_modes();
         // A: sort the current labels
         for (int i = blockIdx.x; i < batch; i += nb) {
             BatchInst& B = inst[i];
-            if (needs_groups(B.mode)) sort_instance(B, B.lab[B.cur]);
+            if (needs_groups(s_mode[i])) sort_instance(B, B.lab[B.cur]);
         }
-        if (!grid_sync(gs, nb, tmo)) return;
+        if (!grid_sync(gs, nb, tmo, BP_SORT, tclk)) return;
+        for (int t = threadIdx.x; t < batch; t += kBlock)
+            s_nseg[t] = needs_groups(s_mode[t]) ? __hip_atomic_load(&inst[t].nseg, __ATOMIC_RELAXED,
+                                                                    __HIP_MEMORY_SCOPE_AGENT) : 0;
         // B: group partial sums (of X, of D = X - S + Theta/rho, or of L)
-        for (int item = blockIdx.x; item < A.off_seg[batch]; item += nb) {
-            const int i = find_inst(A.off_seg, batch, item);
+        load_tab(A.off_seg);
+        for_items(batch, s_tab, s_mode, needs_groups, [&](int i, int local) {
             BatchInst& B = inst[i];
-            const int mode = B.mode;
-            if (!needs_groups(mode)) continue;
-            const int local = item - A.off_seg[i];
+            const int mode = s_mode[i];
             const int s = local / B.nrb, rb = local % B.nrb;
-            if (s >= B.nseg) continue;
+            if (s >= s_nseg[i]) return;
             const int64_t r0 = (int64_t)rb * kRowsPerBlock;
             double* out = B.pmeans + (int64_t)s * B.dp;
             if (mode == M_ITER)
@@ -423,30 +492,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 group_partial_tile<float, 4, false>(mode == M_LL ? B.L : B.X, B.dp, nullptr, 0,
                                                     nullptr, 0, 0.f, B.dp, B.perm, B.segb[s],
                                                     B.segl[s], r0, out);
-        }
-        if (!grid_sync(gs, nb, tmo)) return;
+        });
+        if (!grid_sync(gs, nb, tmo, BP_MEANS, tclk)) return;
         // C: centroids of the non-empty groups
-        for (int item = blockIdx.x; item < A.off_kr[batch]; item += nb) {
-            const int i = find_inst(A.off_kr, batch, item);
+        load_tab(A.off_kr);
+        for_items(batch, s_tab, s_mode, needs_groups, [&](int i, int local) {
             BatchInst& B = inst[i];
-            if (!needs_groups(B.mode)) continue;
-            const int local = item - A.off_kr[i];
             const int nrc = (B.dp + kBlock - 1) / kBlock;
             const int k = local / nrc;
             const int64_t r = (int64_t)(local % nrc) * kBlock + threadIdx.x;
             const int nk = B.counts[k];
-            if (nk == 0 || r >= B.dp) continue;
+            if (nk == 0 || r >= B.dp) return;
             double s = 0.0;
             for (int g = B.segf[k]; g < B.segf[k + 1]; ++g) s += B.pmeans[(int64_t)g * B.dp + r];
             B.C[(int64_t)k * B.dp + r] = (float)(s / (double)nk);
-        }
-        if (!grid_sync(gs, nb, tmo)) return;
+        });
+        if (!grid_sync(gs, nb, tmo, BP_FINALIZE, tclk)) return;
         // D: the fused ALM sweep (instances starting an outer iteration)
-        for (int item = blockIdx.x; item < A.off_tile[batch]; item += nb) {
-            const int i = find_inst(A.off_tile, batch, item);
+        load_tab(A.off_tile);
+        for_items(batch, s_tab, s_mode, [](int m) { return m == M_ITER; }, [&](int i, int local) {
             BatchInst& B = inst[i];
-            if (B.mode != M_ITER) continue;
-            const int local = item - A.off_tile[i];
             const int cb = local / B.nrb, rb = local % B.nrb;
             const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
             const double rho = B.rho;
@@ -461,14 +526,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 B.sweep_part[3 * local + 1] = a1;
                 B.sweep_part[3 * local + 2] = a2;
             }
-        }
-        if (!grid_sync(gs, nb, tmo)) return;
+        });
+        if (!grid_sync(gs, nb, tmo, BP_SWEEP, tclk)) return;
         // E: squared centroid norms
-        for (int item = blockIdx.x; item < A.off_kc[batch]; item += nb) {
-            const int i = find_inst(A.off_kc, batch, item);
+        load_tab(A.off_kc);
+        for_items(batch, s_tab, s_mode, needs_assign, [&](int i, int k) {
             BatchInst& B = inst[i];
-            if (!needs_assign(B.mode)) continue;
-            const int k = item - A.off_kc[i];
             double a = 0.0, b = 0.0, c = 0.0;
             for (int64_t r = threadIdx.x; r < B.dp; r += kBlock) {
                 const double x = (double)B.C[(int64_t)k * B.dp + r];
@@ -476,28 +539,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             }
             block_sum3(a, b, c);
             if (threadIdx.x == 0) B.cnorm[k] = a;
-        }
-        if (!grid_sync(gs, nb, tmo)) return;
+        });
+        if (!grid_sync(gs, nb, tmo, BP_CNORM, tclk)) return;
         // F: distance tiles (columns of X before the iterations, of L after)
-        for (int item = blockIdx.x; item < A.off_dist[batch]; item += nb) {
-            const int i = find_inst(A.off_dist, batch, item);
+        load_tab(A.off_dist);
+        for_items(batch, s_tab, s_mode, needs_assign, [&](int i, int local) {
             BatchInst& B = inst[i];
-            const int mode = B.mode;
-            if (!needs_assign(mode)) continue;
-            const int local = item - A.off_dist[i];
+            const int mode = s_mode[i];
             const int kc = local % B.nkc, ts = local / B.nkc;
             const int tile = ts / B.slices, s = ts % B.slices;
             const float* Y = (mode == M_ITER || mode == M_LL) ? B.L : B.X;
             dist_tile<true, false>(B.C, B.dp, B.c, B.kpad, Y, B.dp, B.n, B.slice_rows, B.part, nullptr,
                                    (int64_t)tile * kJT, s, kc * kKC, false);
-        }
-        if (!grid_sync(gs, nb, tmo)) return;
+        });
+        if (!grid_sync(gs, nb, tmo, BP_DIST, tclk)) return;
         // G: reduce slices, argmin (16 lanes per column), changed counts
-        for (int item = blockIdx.x; item < A.off_col[batch]; item += nb) {
-            const int i = find_inst(A.off_col, batch, item);
+        load_tab(A.off_col);
+        for_items(batch, s_tab, s_mode, needs_assign, [&](int i, int local) {
             BatchInst& B = inst[i];
-            if (!needs_assign(B.mode)) continue;
-            const int local = item - A.off_col[i];
             const int q = threadIdx.x & 15;
             const int64_t j = (int64_t)local * 16 + (threadIdx.x >> 4);
             double bestd = INFINITY;
@@ -525,20 +584,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             double z1 = 0.0, z2 = 0.0;
             block_sum3(ch, z1, z2);
             if (threadIdx.x == 0) B.chg[local] = (int)ch;
-        }
-        if (!grid_sync(gs, nb, tmo)) return;
+        });
+        if (!grid_sync(gs, nb, tmo, BP_ARGMIN, tclk)) return;
         // H: control
-        if (threadIdx.x == 0)
-            for (int i = blockIdx.x; i < batch; i += nb) control_instance(inst[i], active);
-        if (!grid_sync(gs, nb, tmo)) return;
+        for (int i = blockIdx.x; i < batch; i += nb) {
+            control_instance(inst[i], active);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && blockIdx.x == 0) gs->steps += 1;
+        if (!grid_sync(gs, nb, tmo, BP_CONTROL, tclk)) return;
     }
 
     // ---- results: L, S (first d rows) and labels into the caller's buffers
-    for (int item = blockIdx.x; item < A.off_tile[batch]; item += nb) {
-        const int i = find_inst(A.off_tile, batch, item);
+    load_tab(A.off_tile);
+    for (int t = threadIdx.x; t < batch; t += kBlock) s_mode[t] = 1;
+    __syncthreads();
+    for_items(batch, s_tab, s_mode, any, [&](int i, int local) {
         BatchInst& B = inst[i];
-        if (B.status < 0) continue;
-        const int local = item - A.off_tile[i];
+        if (B.status < 0) return;
         const int cb = local / B.nrb, rb = local % B.nrb;
         const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
         const int64_t r0 = (int64_t)rb * kRowsPerBlock;
@@ -548,7 +611,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 B.Lc[j * B.ldl + r] = B.L[j * B.dp + r];
                 B.Sc[j * B.lds + r] = B.S[j * B.dp + r];
             }
-    }
+    });
     for (int i = blockIdx.x; i < batch; i += nb) {
         BatchInst& B = inst[i];
         if (B.labels_out && B.status >= 0) {
@@ -564,7 +627,9 @@ __global__ void k_batched_reset(BatchSync* s, int batch) {
         s->gen = 0u;
         s->abort = 0;
         s->active = batch;
+        s->steps = 0;
     }
+    if (threadIdx.x < BP_COUNT) s->phase_ticks[threadIdx.x] = 0;
 }
 
 }  // namespace

@@ -59,6 +59,7 @@ respca_status validate(respca_handle h, const respca_params* params, int32_t bat
                        std::vector<Resolved>& res) {
     if (!params || batch < 1 || !d || !n || !X || !ldx || !L || !ldl || !S || !lds)
         return fail(h, RESPCA_ERR_INVALID, "NULL argument or empty batch");
+    if (batch > kMaxBatch) return fail(h, RESPCA_ERR_UNSUPPORTED, "batch above 1024 instances");
     res.resize(batch);
     for (int i = 0; i < batch; ++i) {
         respca_status s = resolve(h, &params[i], d[i], n[i], res[i]);
@@ -278,6 +279,8 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     CK(hipEventRecord(h->bev, caller));
     CK(hipStreamWaitEvent(h->bstream, h->bev, 0));
     hipEvent_t t0 = nullptr, t1 = nullptr;
+    double prof_ms = 0.0;
+    if (!elapsed_ms && h->prof_on) elapsed_ms = &prof_ms;
     if (elapsed_ms) {
         CK(hipEventCreate(&t0));
         CK(hipEventCreate(&t1));
@@ -295,10 +298,20 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     }
     const BatchInst* out = (const BatchInst*)(st + L.readback_off);
     const BatchSync* sy = (const BatchSync*)(st + L.readback_off + align_up(batch * sizeof(BatchInst), 256));
+    for (int p = 0; p < BP_COUNT; ++p) h->bphase_ms[p] = (double)sy->phase_ticks[p] / (double)rate_khz;
+    h->bsteps = (int64_t)sy->steps;
     if (sy->abort) return fail(h, RESPCA_ERR_HIP, "batched kernel: grid barrier timed out (aborted)");
     respca_status worst = RESPCA_OK;
+    double alg_bytes = 0.0;
     for (int i = 0; i < batch; ++i) {
         const BatchInst& B = out[i];
+        if (B.status >= 0 && B.nx > 0.0)
+            // ||X|| pass; seeding (c passes) + nearest-seed assignment, or the means of X
+            // for a warm start; 2 per Lloyd pass on X; 3 + 7 + 1 per outer iteration
+            // (means of D, sweep, assignment); 2 per extra Lloyd pass on L
+            alg_bytes += (double)B.d * B.n * sizeof(float) *
+                         (1.0 + (call.inst[i].init_labels ? 1.0 : (double)B.c + 1.0) +
+                          2.0 * B.init_lloyd + 11.0 * B.iters + 2.0 * (B.lloyd_total - B.iters));
         if (info) {
             respca_info& f = info[i];
             std::memset(&f, 0, sizeof(f));
@@ -313,6 +326,11 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
         }
         if (B.status < 0 && (worst >= 0 || B.status < worst)) worst = (respca_status)B.status;
         if (B.status == RESPCA_NOT_CONVERGED && worst == RESPCA_OK) worst = RESPCA_NOT_CONVERGED;
+    }
+    if (h->prof_on) {
+        h->prof_launches[RESPCA_KERNEL_BATCHED] += 1;
+        h->prof_ms[RESPCA_KERNEL_BATCHED] += *elapsed_ms;
+        h->prof_bytes[RESPCA_KERNEL_BATCHED] += alg_bytes;
     }
     if (worst < 0) h->err = "an instance failed (see its info status)";
     return worst;
@@ -404,6 +422,15 @@ respca_status respca_autotune_batched(respca_handle h, const respca_params* para
             std::fclose(f);
         }
     }
+    return RESPCA_OK;
+}
+
+respca_status respca_profile_batched_phases(respca_handle h, double* ms, int32_t count,
+                                            int64_t* steps) {
+    if (!h || count < 0) return RESPCA_ERR_INVALID;
+    for (int p = 0; p < count && p < BP_COUNT; ++p)
+        if (ms) ms[p] = h->bphase_ms[p];
+    if (steps) *steps = h->bsteps;
     return RESPCA_OK;
 }
 

@@ -22,13 +22,15 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Sum of 3 values over a 256-thread block; result valid in thread 0.
+// Sum of 3 values over a 256-thread block; result valid in thread 0.  Safe to
+// call repeatedly; every thread of the block must call it.
 __device__ inline void block_sum3(double& a, double& b, double& c) {
     __shared__ double sh[3][kBlock / 64];
     a = wave_sum(a);
     b = wave_sum(b);
     c = wave_sum(c);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();   // a previous call's readers are done with sh
     if (lane == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -83,18 +85,36 @@ __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __res
                                   int64_t j1, int64_t r0, T alpha, T beta, T rho, T inv_rho,
                                   double& a0, double& a1, double& a2) {
     constexpr int NS = kRowsPerBlock / (kBlock * V);
-    for (int64_t j = j0; j < j1; ++j) {
-        const int64_t p = labels[j];
+    constexpr int U = 2;   // columns in flight per thread (columns are independent)
+    for (int64_t jb = j0; jb < j1; jb += U) {
+        int64_t pp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pp[u] = (jb + u < j1) ? labels[jb + u] : 0;
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
             const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
             if (i >= d) continue;
-            T x[V], s[V], t[V], lp[V], m[V], ln[V], sn[V], tn[V];
-            vload<T, V>(X + j * ldx + i, x);
-            vload<T, V>(S + j * lds + i, s);
-            vload<T, V>(Th + j * ldt + i, t);
-            vload<T, V>(L + j * ldl + i, lp);
-            vload<T, V>(C + p * d + i, m);
+            T xs[U][V], ss[U][V], ts[U][V], lps[U][V], ms[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (jb + u >= j1) continue;
+                const int64_t j = jb + u;
+                vload<T, V>(X + j * ldx + i, xs[u]);
+                vload<T, V>(S + j * lds + i, ss[u]);
+                vload<T, V>(Th + j * ldt + i, ts[u]);
+                vload<T, V>(L + j * ldl + i, lps[u]);
+                vload<T, V>(C + pp[u] * d + i, ms[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+            if (jb + u >= j1) continue;
+            const int64_t j = jb + u;
+            const T (&x)[V] = xs[u];
+            const T (&s)[V] = ss[u];
+            const T (&t)[V] = ts[u];
+            const T (&lp)[V] = lps[u];
+            const T (&m)[V] = ms[u];
+            T ln[V], sn[V], tn[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const T dv = x[v] - s[v] + t[v] * inv_rho;
@@ -113,6 +133,7 @@ __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __res
             vstore<T, V>(L + j * ldl + i, ln);
             vstore<T, V>(S + j * lds + i, sn);
             vstore<T, V>(Th + j * ldt + i, tn);
+            }
         }
     }
 }
@@ -127,26 +148,49 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
                                           int64_t d, const int32_t* __restrict__ perm, int begin,
                                           int len, int64_t r0, double* __restrict__ out) {
     constexpr int NS = kRowsPerBlock / (kBlock * V);
+    constexpr int U = 4;   // columns in flight per thread; the summation order is unchanged
     double acc[NS][V];
 #pragma unroll
     for (int a = 0; a < NS; ++a)
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
-    for (int q = 0; q < len; ++q) {
+    auto value = [&](int64_t j, int64_t i, T (&x)[V]) {
+        vload<T, V>(A + j * lda + i, x);
+        if constexpr (WITH_D) {
+            T sv[V], tv[V];
+            vload<T, V>(S + j * lds + i, sv);
+            vload<T, V>(Th + j * ldt + i, tv);
+#pragma unroll
+            for (int v = 0; v < V; ++v) x[v] = x[v] - sv[v] + tv[v] * inv_rho;
+        }
+    };
+    int q = 0;
+    for (; q + U <= len; q += U) {
+        int64_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jj[u] = perm[begin + q + u];
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            if (i < d) {
+                T x[U][V];
+#pragma unroll
+                for (int u = 0; u < U; ++u) value(jj[u], i, x[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[a][v] += (double)x[u][v];
+            }
+        }
+    }
+    for (; q < len; ++q) {
         const int64_t j = perm[begin + q];
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
             const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
             if (i < d) {
                 T x[V];
-                vload<T, V>(A + j * lda + i, x);
-                if constexpr (WITH_D) {
-                    T sv[V], tv[V];
-                    vload<T, V>(S + j * lds + i, sv);
-                    vload<T, V>(Th + j * ldt + i, tv);
-#pragma unroll
-                    for (int v = 0; v < V; ++v) x[v] = x[v] - sv[v] + tv[v] * inv_rho;
-                }
+                value(j, i, x);
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[a][v] += (double)x[v];
             }

@@ -57,6 +57,8 @@ struct respca_handle_s {
     hipGraph_t bgraph = nullptr;
     hipGraphExec_t bexec = nullptr;
     uint64_t bsig = 0;              // signature of the captured call
+    double bphase_ms[16] = {};      // phase times of the last batched launch
+    int64_t bsteps = 0;
 };
 
 #define CK(expr)                                                                            \

@@ -25,8 +25,10 @@ F64, F32, BF16GEMM_F32 = 0, 1, 2
 EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_status_string",
            "respca_last_error", "respca_version", "respca_solve", "respca_iterate",
            "respca_kmeans", "respca_profile_enable", "respca_profile_query",
-           "respca_solve_batched", "respca_autotune_batched")
-KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3}
+           "respca_solve_batched", "respca_autotune_batched", "respca_profile_batched_phases")
+BATCH_PHASES = ("pack", "init", "seed_distance", "seed_draw", "seed_gather", "sort", "means",
+                "finalize", "sweep", "centroid_norms", "distance", "argmin", "control")
+KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3, "batched": 4}
 
 
 class Params(ct.Structure):
@@ -95,6 +97,9 @@ def lib():
         L.respca_autotune_batched.restype = i32
         L.respca_autotune_batched.argtypes = [vp, ct.POINTER(Params), i32, i64p, i64p, arr, i64p, arr,
                                               i64p, arr, i64p, ct.c_char_p, ct.POINTER(ct.c_double), vp]
+        L.respca_profile_batched_phases.restype = i32
+        L.respca_profile_batched_phases.argtypes = [vp, ct.POINTER(ct.c_double), i32,
+                                                    ct.POINTER(ct.c_int64)]
         L.respca_kmeans.restype = i32
         L.respca_kmeans.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, vp,
                                     ct.POINTER(Info), vp]
@@ -377,3 +382,15 @@ def autotune_batched(Xs, params_list, cache_path=None, outs=None, stream=None, d
                                       _stream(stream))
     h.check(s, allow=(OK,))
     return best.value
+
+
+def batched_phases(device: int = 0) -> dict:
+    """Per-phase milliseconds (and step count) of the last batched launch."""
+    h = handle(device)
+    ms = (ct.c_double * len(BATCH_PHASES))()
+    steps = ct.c_int64()
+    h.check(lib().respca_profile_batched_phases(h._h, ms, len(BATCH_PHASES), ct.byref(steps)),
+            allow=(OK,))
+    out = {k: round(ms[i], 3) for i, k in enumerate(BATCH_PHASES)}
+    out["steps"] = steps.value
+    return out
