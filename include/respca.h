@@ -216,6 +216,52 @@ respca_status respca_profile_enable(respca_handle h, int32_t enable);
 respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t *launches,
                                    double *total_ms, double *bytes, double *flops);
 
+/*
+ * Learned warm start (an addition to the paper's method; all FP32, device
+ * pointers unless marked host).  A per-column network with dims
+ * [68, hidden, hidden, hidden, 65] (ReLU between layers; parameters one flat
+ * vector, layer by layer W (out x in, row-major) then b) maps each column's
+ * normalised sketch and instance features to the normalised sketch of its group
+ * centroid (64 outputs) and a log threshold (1 output).
+ */
+/* Number of network parameters (host).  Needs no device. */
+int64_t       respca_mlp_param_count(int32_t hidden);
+/* Floats of the activation buffer a forward pass for `batch` rows needs; the
+ * network output (batch x 65, row-major) is its last block. Needs no device. */
+int64_t       respca_mlp_act_count(int32_t hidden, int32_t batch);
+/* Column sketch Y (65 x n, leading dimension 65): rows 0..63 are R X_j with
+ * R[k][i] = +-1/8 from bit k of the i-th splitmix64(seed) output, row 64 ||X_j||. */
+respca_status respca_sketch(respca_handle h, int64_t d, int64_t n, const void *X, int64_t ldx,
+                            uint64_t seed, void *Y, void *stream);
+/* Network inputs F (n x 68, row-major) from a sketch Y of a d x n matrix with c groups:
+ * y_j / (s sqrt(d) / 8), log(||X_j|| / (s sqrt(d))), log(d)/8, log(n)/8, c/50 with
+ * s = ||X||_F / sqrt(d n). */
+respca_status respca_features(respca_handle h, int64_t d, int64_t n, int32_t c, const void *Y,
+                              void *F, void *stream);
+/* Forward pass over `batch` rows x (batch x 68); acts receives the activations. */
+respca_status respca_mlp_forward(respca_handle h, int32_t hidden, const void *params, int32_t batch,
+                                 const void *x, void *acts, void *stream);
+/* Gradient (flat, like params) of sum(dy * output) given a forward pass's acts. */
+respca_status respca_mlp_backward(respca_handle h, int32_t hidden, const void *params,
+                                  int32_t batch, const void *x, const void *acts, const void *dy,
+                                  void *grad, void *stream);
+/* Loss (1/B) sum_j [sum_{k<64} (y - t)^2 + w_last (y_64 - t_64)^2] (host *loss) and dy. */
+respca_status respca_mlp_loss(respca_handle h, int32_t batch, const void *y, const void *t,
+                              float w_last, void *dy, double *loss, void *stream);
+/* One Adam step (Kingma & Ba 2015, bias-corrected; step counts from 1). */
+respca_status respca_mlp_adam(respca_handle h, int64_t count, void *params, const void *grad,
+                              void *m, void *v, float lr, float beta1, float beta2, float eps,
+                              int32_t step, void *stream);
+/* Warm start of one d x n FP32 problem with c groups: sketch -> features ->
+ * network -> initial labels = K-means (seed kmeans_seed) of the predicted centroid
+ * sketches, rho0 (host) = exp(mean predicted log threshold) / s.  If the network's
+ * threshold is not a finite positive number *fallback (host) is set to 1 and
+ * *rho0 to 1e-4 (the default); the labels are always valid. */
+respca_status respca_warmstart(respca_handle h, int32_t hidden, const void *params, int64_t d,
+                               int64_t n, int32_t c, const void *X, int64_t ldx,
+                               uint64_t sketch_seed, uint64_t kmeans_seed, int32_t *init_labels,
+                               double *rho0, int32_t *fallback, void *stream);
+
 /* Phase breakdown of the last batched launch: ms[p] for the phases
  * pack, init, seed-distance, seed-draw, seed-gather, sort, means, finalize,
  * sweep, centroid-norms, distance, argmin, control (count <= 13 entries are

@@ -62,6 +62,9 @@ def lib():
         L.oracle_splitmix64_next.argtypes = [P(ct.c_uint64)]
         L.oracle_uniform01.restype = f64
         L.oracle_uniform01.argtypes = [P(ct.c_uint64)]
+        L.oracle_splitmix64_at.restype = ct.c_uint64
+        L.oracle_splitmix64_at.argtypes = [ct.c_uint64, ct.c_uint64]
+        L.oracle_sketch.argtypes = [i64, i64, dp, ct.c_uint64, dp]
         L.oracle_group_means.argtypes = [i64, i64, i32, dp, ip, dp, lp]
         L.oracle_l_step.argtypes = [i64, i64, i32, f64, f64, dp, dp, dp, ip, dp, dp]
         L.oracle_assign.argtypes = [i64, i64, i32, dp, dp, ip]
@@ -122,6 +125,19 @@ def splitmix64(seed: int, count: int) -> list[int]:
 def uniform01(seed: int, count: int) -> list[float]:
     st = ct.c_uint64(seed)
     return [float(lib().oracle_uniform01(ct.byref(st))) for _ in range(count)]
+
+
+def splitmix64_at(seed: int, t: int) -> int:
+    return int(lib().oracle_splitmix64_at(seed & 0xFFFFFFFFFFFFFFFF, t))
+
+
+def sketch(X, seed):
+    """65 x n column sketch (64 Rademacher projections, then the column norm)."""
+    X = _f64(X)
+    d, n = X.shape
+    Y = np.zeros((65, n), order="F")
+    lib().oracle_sketch(d, n, _dp(X), int(seed) & 0xFFFFFFFFFFFFFFFF, _dp(Y))
+    return Y
 
 
 def group_means(Y, labels, c, mean_init=None):

@@ -27,6 +27,29 @@ double oracle_uniform01(uint64_t *state)
     return (double)(oracle_splitmix64_next(state) >> 11) * 0x1.0p-53;
 }
 
+uint64_t oracle_splitmix64_at(uint64_t seed, uint64_t t)
+{
+    uint64_t state = seed + t * 0x9E3779B97F4A7C15ULL;
+    return oracle_splitmix64_next(&state);
+}
+
+/* ------------------------------------------------------------ sketch --- */
+
+void oracle_sketch(int64_t d, int64_t n, const double *X, uint64_t seed, double *Y)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        double *y = Y + j * 65;
+        for (int k = 0; k < 65; ++k) y[k] = 0.0;
+        for (int64_t i = 0; i < d; ++i) {
+            uint64_t bits = oracle_splitmix64_at(seed, (uint64_t)i);
+            double x = X[j * d + i];
+            for (int k = 0; k < 64; ++k) y[k] += ((bits >> k) & 1ULL) ? -0.125 * x : 0.125 * x;
+            y[64] += x * x;
+        }
+        y[64] = sqrt(y[64]);
+    }
+}
+
 /* ------------------------------------------------------------ helpers --- */
 
 static double sq_dist(int64_t d, const double *a, const double *b)

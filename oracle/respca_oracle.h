@@ -62,6 +62,14 @@ typedef struct {
 uint64_t oracle_splitmix64_next(uint64_t *state);
 /* Uniform double in [0, 1): the top 53 bits of the next output times 2^-53. */
 double oracle_uniform01(uint64_t *state);
+/* Counter-based access: the (t+1)-th output of splitmix64 started from `seed`. */
+uint64_t oracle_splitmix64_at(uint64_t seed, uint64_t t);
+
+/* Column sketch used by the learned warm start (not part of the paper's method):
+ * Y (65 x n, leading dimension 65): rows 0..63 are R X_j with R[k][i] = +1/8 if
+ * bit k of oracle_splitmix64_at(seed, i) is 0 and -1/8 otherwise (a Rademacher
+ * random projection), row 64 is ||X_j||_2. */
+void oracle_sketch(int64_t d, int64_t n, const double *X, uint64_t seed, double *Y);
 
 /* Group means: for every k with n_k > 0, mean[:, k] = (1/n_k) sum_{labels[j]=k} Y[:, j].
  * Columns of empty groups are left untouched.  counts[k] = n_k. */

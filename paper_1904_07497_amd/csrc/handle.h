@@ -59,6 +59,8 @@ struct respca_handle_s {
     uint64_t bsig = 0;              // signature of the captured call
     double bphase_ms[16] = {};      // phase times of the last batched launch
     int64_t bsteps = 0;
+    // warm start
+    respca::DevBuf wsk, wfeat, wacts, wscratch, wred, wcent;
 };
 
 #define CK(expr)                                                                            \
@@ -126,5 +128,11 @@ struct Resolved {
 };
 
 respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_t n, Resolved& r);
+
+// K-means (k-means++ from splitmix64(seed), then Lloyd) of the columns of a
+// float d x n matrix; labels (device) and C (device d x c) out; enqueued on st.
+respca_status kmeans_f32(respca_handle h, int64_t d, int64_t n, int c, const float* Y, int64_t ldy,
+                         uint64_t seed, int max_lloyd, int32_t* labels, float* C, hipStream_t st,
+                         int* steps);
 
 }  // namespace respca

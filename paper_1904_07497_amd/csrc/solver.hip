@@ -424,6 +424,24 @@ respca_status kmeans_t(respca_handle h, const Resolved& r, int64_t d, int64_t n,
     return RESPCA_OK;
 }
 
+}  // namespace
+
+respca_status respca::kmeans_f32(respca_handle h, int64_t d, int64_t n, int c, const float* Y,
+                                 int64_t ldy, uint64_t seed, int max_lloyd, int32_t* labels, float* C,
+                                 hipStream_t st, int* steps) {
+    Engine<float> e{h, st, d, n, c, false};
+    CKS(e.setup());
+    int32_t* cur = (int32_t*)h->lab_a.p;
+    int32_t* alt = (int32_t*)h->lab_b.p;
+    int s = 0;
+    CKS(e.kmeans(Y, ldy, seed, max_lloyd, C, cur, alt, s));
+    if (steps) *steps = s;
+    CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    return RESPCA_OK;
+}
+
+namespace {
+
 respca_status bind_device(respca_handle h) {
     CK(hipSetDevice(h->device));
     return RESPCA_OK;
@@ -466,6 +484,9 @@ void respca_destroy(respca_handle h) {
     if (h->bstream) (void)hipStreamDestroy(h->bstream);
     if (h->bws.p) (void)hipFree(h->bws.p);
     if (h->bstage) (void)hipHostFree(h->bstage);
+    respca::DevBuf* wbufs[] = {&h->wsk, &h->wfeat, &h->wacts, &h->wscratch, &h->wred, &h->wcent};
+    for (respca::DevBuf* b : wbufs)
+        if (b->p) (void)hipFree(b->p);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
                       &h->nseg, &h->sortbc, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b, &h->d2,
                       &h->chosen, &h->seeds, &h->u, &h->normp, &h->chgp, &h->status};

@@ -1,0 +1,305 @@
+// Learned warm start (an addition to the paper's method): column sketches, a
+// per-column multilayer perceptron with hand-written forward / backward / Adam
+// kernels, and the feature map between them.
+//
+// Sketch: y_j = R X_j with R[k][i] = +-1/8 taken from bit k of the i-th
+// counter-based splitmix64 output (Rademacher projection to 64 dimensions),
+// plus ||X_j||.  Network: dims [68, h, h, h, 65], ReLU between layers; inputs
+// are the normalised sketch and instance features, outputs the normalised
+// sketch of the column's group centroid (64) and a log-threshold (1).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_common.h"
+#include "warmstart.h"
+
+namespace respca {
+
+namespace {
+
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t t) {
+    uint64_t z = seed + (t + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// One wave per column: 64 projections accumulated per lane over its rows, then
+// a butterfly exchange halves the values each lane holds at every stage so that
+// lane k ends with the full sum of projection k.
+__global__ __launch_bounds__(256) void k_sketch(const float* __restrict__ X, int64_t ldx, int64_t d,
+                                                int64_t n, uint64_t seed, float* __restrict__ Y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const float* x = X + j * ldx;
+    float v[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) v[k] = 0.f;
+    double nrm = 0.0;
+    for (int64_t i = lane; i < d; i += 64) {
+        const float xi = x[i];
+        const uint64_t bits = splitmix64_at(seed, (uint64_t)i);
+        const float p = 0.125f * xi;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) v[k] += ((bits >> k) & 1ull) ? -p : p;
+        nrm += (double)xi * xi;
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const bool up = (lane & s) != 0;
+#pragma unroll
+        for (int k = 0; k < s; ++k) {
+            const float send = up ? v[k] : v[k + s];
+            const float keep = up ? v[k + s] : v[k];
+            v[k] = keep + __shfl_xor(send, s);
+        }
+    }
+    nrm = wave_sum(nrm);
+    Y[j * 65 + lane] = v[0];
+    if (lane == 0) Y[j * 65 + 64] = (float)sqrt(nrm);
+}
+
+// sum_j Y[j][64]^2 (= ||X||_F^2) in double, one workgroup.
+__global__ __launch_bounds__(256) void k_sketch_total(const float* __restrict__ Y, int64_t n,
+                                                      double* __restrict__ out) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const double t = Y[j * 65 + 64];
+        a += t * t;
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) out[0] = a;
+}
+
+// Network inputs of column j: y_j / (s sqrt(d) / 8) (64), log(||X_j|| / (s sqrt(d))),
+// log(d) / 8, log(n) / 8, c / 50 with s = ||X||_F / sqrt(d n).
+__global__ __launch_bounds__(256) void k_features(const float* __restrict__ Y, int64_t d, int64_t n,
+                                                  int c, const double* __restrict__ total,
+                                                  float* __restrict__ F) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * kWarmIn) return;
+    const int64_t j = e / kWarmIn;
+    const int k = (int)(e % kWarmIn);
+    const double s = sqrt(total[0] / ((double)d * (double)n));
+    const double col = s * sqrt((double)d);
+    double f;
+    if (k < 64) f = (col > 0.0) ? Y[j * 65 + k] / (0.125 * col) : 0.0;
+    else if (k == 64) f = log((double)Y[j * 65 + 64] / (col > 0.0 ? col : 1.0) + 1e-12);
+    else if (k == 65) f = log((double)d) / 8.0;
+    else if (k == 66) f = log((double)n) / 8.0;
+    else f = (double)c / 50.0;
+    F[e] = (float)f;
+}
+
+// C(m, n) [+]= sum_k A(m, k) B(k, n) (+ bias[n]) with A(m, k) = A[m*as0 + k*as1],
+// B(k, n) = B[k*bs0 + n*bs1], C row-major (ldc).  EPI: 0 none, 1 ReLU, 2 multiply by
+// (mask(m, n) > 0) with the mask laid out like C.  64 x 64 tiles, 16-deep K steps
+// through LDS, 4 x 4 outputs per thread.
+template <bool BIAS, int EPI, bool ACCUM>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* __restrict__ A,
+                                              int64_t as0, int64_t as1, const float* __restrict__ B,
+                                              int64_t bs0, int64_t bs1, const float* __restrict__ bias,
+                                              const float* __restrict__ mask, float* __restrict__ C,
+                                              int64_t ldc) {
+    __shared__ float As[16][64 + 1];
+    __shared__ float Bs[16][64 + 1];
+    const int tid = threadIdx.x, tm = tid >> 4, tn = tid & 15;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int e = tid + 256 * p;        // 1024 = 16 x 64
+            const int kk = e >> 6, mm = e & 63;
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk][mm] = (gm < M && gk < K) ? A[(int64_t)gm * as0 + (int64_t)gk * as1] : 0.f;
+            const int gn = n0 + mm;
+            Bs[kk][mm] = (gn < N && gk < K) ? B[(int64_t)gk * bs0 + (int64_t)gn * bs1] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a[q] = As[kk][tm * 4 + q]; b[q] = Bs[kk][tn * 4 + q]; }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const int m = m0 + tm * 4 + x;
+        if (m >= M) continue;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int nn = n0 + tn * 4 + y;
+            if (nn >= N) continue;
+            float v = acc[x][y];
+            if (BIAS) v += bias[nn];
+            if (EPI == 1) v = v > 0.f ? v : 0.f;
+            if (EPI == 2) v = mask[(int64_t)m * ldc + nn] > 0.f ? v : 0.f;
+            float* c = C + (int64_t)m * ldc + nn;
+            *c = ACCUM ? *c + v : v;
+        }
+    }
+}
+
+// out[n] = sum_m A[m * lda + n] (fixed order), one thread per column.
+__global__ __launch_bounds__(256) void k_colsum(int M, int N, const float* __restrict__ A, int64_t lda,
+                                                float* __restrict__ out) {
+    const int nn = blockIdx.x * 256 + threadIdx.x;
+    if (nn >= N) return;
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) s += A[(int64_t)m * lda + nn];
+    out[nn] = (float)s;
+}
+
+// dY = 2 w (Y - T) / B (w = 1 except w_last on the last output), loss partials.
+__global__ __launch_bounds__(256) void k_loss(int64_t count, int out_dim, int batch, float w_last,
+                                              const float* __restrict__ Y, const float* __restrict__ T,
+                                              float* __restrict__ dY, double* __restrict__ partial) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+        const float w = (e % out_dim == out_dim - 1) ? w_last : 1.f;
+        const float r = Y[e] - T[e];
+        dY[e] = 2.f * w * r / (float)batch;
+        a += (double)w * r * r;
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a / batch;
+}
+
+__global__ __launch_bounds__(256) void k_adam(int64_t count, float* __restrict__ p,
+                                              const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    const float gi = g[e];
+    const float mi = b1 * m[e] + (1.f - b1) * gi;
+    const float vi = b2 * v[e] + (1.f - b2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    p[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// mean_j out[j * 65 + 64] in double, one workgroup.
+__global__ __launch_bounds__(256) void k_pool_last(const float* __restrict__ out, int64_t n,
+                                                   double* __restrict__ res) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) a += out[j * kWarmOut + kWarmOut - 1];
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) res[0] = a / (double)n;
+}
+
+void gemm(int M, int N, int K, const float* A, int64_t as0, int64_t as1, const float* B, int64_t bs0,
+          int64_t bs1, const float* bias, int epi, const float* mask, bool accum, float* C,
+          int64_t ldc, hipStream_t st) {
+    const dim3 grid((N + 63) / 64, (M + 63) / 64);
+    if (bias && epi == 1 && !accum)
+        k_gemm<true, 1, false><<<grid, 256, 0, st>>>(M, N, K, A, as0, as1, B, bs0, bs1, bias, mask, C, ldc);
+    else if (bias && epi == 0 && !accum)
+        k_gemm<true, 0, false><<<grid, 256, 0, st>>>(M, N, K, A, as0, as1, B, bs0, bs1, bias, mask, C, ldc);
+    else if (!bias && epi == 2 && !accum)
+        k_gemm<false, 2, false><<<grid, 256, 0, st>>>(M, N, K, A, as0, as1, B, bs0, bs1, bias, mask, C, ldc);
+    else
+        k_gemm<false, 0, false><<<grid, 256, 0, st>>>(M, N, K, A, as0, as1, B, bs0, bs1, bias, mask, C, ldc);
+}
+
+}  // namespace
+
+int64_t mlp_param_count(int hidden) {
+    const int dims[5] = {kWarmIn, hidden, hidden, hidden, kWarmOut};
+    int64_t t = 0;
+    for (int l = 0; l < 4; ++l) t += (int64_t)dims[l] * dims[l + 1] + dims[l + 1];
+    return t;
+}
+
+int64_t mlp_act_count(int hidden, int batch) { return (int64_t)batch * (3 * hidden + kWarmOut); }
+
+void launch_sketch(const float* X, int64_t ldx, int64_t d, int64_t n, uint64_t seed, float* Y,
+                   hipStream_t st) {
+    k_sketch<<<(unsigned)((n + 3) / 4), 256, 0, st>>>(X, ldx, d, n, seed, Y);
+}
+
+void launch_features(const float* Y, int64_t d, int64_t n, int c, double* total, float* F,
+                     hipStream_t st) {
+    k_sketch_total<<<1, 256, 0, st>>>(Y, n, total);
+    k_features<<<(unsigned)((n * kWarmIn + 255) / 256), 256, 0, st>>>(Y, d, n, c, total, F);
+}
+
+// acts: [a1 (B x h) | a2 (B x h) | a3 (B x h) | y (B x 65)], y is the network output.
+void launch_mlp_forward(const float* P, int hidden, int batch, const float* x, float* acts,
+                        hipStream_t st) {
+    const int dims[5] = {kWarmIn, hidden, hidden, hidden, kWarmOut};
+    const float* a = x;
+    const float* w = P;
+    float* out = acts;
+    for (int l = 0; l < 4; ++l) {
+        const int in = dims[l], o = dims[l + 1];
+        const float* b = w + (int64_t)in * o;
+        gemm(batch, o, in, a, in, 1, w, 1, in, b, l < 3 ? 1 : 0, nullptr, false, out, o, st);
+        a = out;
+        out += (int64_t)batch * o;
+        w = b + o;
+    }
+}
+
+void launch_mlp_backward(const float* P, int hidden, int batch, const float* x, const float* acts,
+                         const float* dy, float* grad, float* scratch, hipStream_t st) {
+    const int dims[5] = {kWarmIn, hidden, hidden, hidden, kWarmOut};
+    int64_t woff[4], act_off[4];
+    int64_t o = 0;
+    for (int l = 0; l < 4; ++l) { woff[l] = o; o += (int64_t)dims[l] * dims[l + 1] + dims[l + 1]; }
+    act_off[0] = 0;
+    for (int l = 1; l < 4; ++l) act_off[l] = act_off[l - 1] + (int64_t)batch * dims[l];
+    // scratch holds two B x h buffers for dZ
+    float* dz_a = scratch;
+    float* dz_b = scratch + (int64_t)batch * hidden;
+    const float* dz = dy;
+    for (int l = 3; l >= 0; --l) {
+        const int in = dims[l], out = dims[l + 1];
+        const float* a_in = l == 0 ? x : acts + act_off[l - 1];
+        float* gW = grad + woff[l];
+        float* gb = gW + (int64_t)in * out;
+        // gW (out x in) = dz^T (out x B) * a_in (B x in)
+        gemm(out, in, batch, dz, 1, out, a_in, in, 1, nullptr, 0, nullptr, false, gW, in, st);
+        k_colsum<<<(out + 255) / 256, 256, 0, st>>>(batch, out, dz, out, gb);
+        if (l > 0) {
+            // dz_prev (B x in) = (dz (B x out) * W (out x in)) masked by a_in > 0
+            float* nxt = (dz == dz_a) ? dz_b : dz_a;
+            gemm(batch, in, out, dz, out, 1, P + woff[l], in, 1, nullptr, 2, a_in, false, nxt, in, st);
+            dz = nxt;
+        }
+    }
+}
+
+int launch_loss(int batch, const float* y, const float* t, float w_last, float* dy, double* partial,
+                hipStream_t st) {
+    const int64_t count = (int64_t)batch * kWarmOut;
+    int g = (int)((count + 255) / 256);
+    if (g > 1024) g = 1024;
+    k_loss<<<g, 256, 0, st>>>(count, kWarmOut, batch, w_last, y, t, dy, partial);
+    return g;
+}
+
+void launch_adam(int64_t count, float* p, const float* g, float* m, float* v, float lr, float b1,
+                 float b2, float eps, int step, hipStream_t st) {
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    k_adam<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(count, p, g, m, v, lr, b1, b2, eps, c1, c2);
+}
+
+void launch_pool_last(const float* out, int64_t n, double* res, hipStream_t st) {
+    k_pool_last<<<1, 256, 0, st>>>(out, n, res);
+}
+
+}  // namespace respca

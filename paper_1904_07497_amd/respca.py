@@ -25,7 +25,11 @@ F64, F32, BF16GEMM_F32 = 0, 1, 2
 EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_status_string",
            "respca_last_error", "respca_version", "respca_solve", "respca_iterate",
            "respca_kmeans", "respca_profile_enable", "respca_profile_query",
-           "respca_solve_batched", "respca_autotune_batched", "respca_profile_batched_phases")
+           "respca_solve_batched", "respca_autotune_batched", "respca_profile_batched_phases",
+           "respca_mlp_param_count", "respca_mlp_act_count", "respca_sketch", "respca_features",
+           "respca_mlp_forward", "respca_mlp_backward", "respca_mlp_loss", "respca_mlp_adam",
+           "respca_warmstart")
+WARM_IN, WARM_OUT = 68, 65
 BATCH_PHASES = ("pack", "init", "seed_distance", "seed_draw", "seed_gather", "sort", "means",
                 "finalize", "sweep", "centroid_norms", "distance", "argmin", "control")
 KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3, "batched": 4}
@@ -100,6 +104,26 @@ def lib():
         L.respca_profile_batched_phases.restype = i32
         L.respca_profile_batched_phases.argtypes = [vp, ct.POINTER(ct.c_double), i32,
                                                     ct.POINTER(ct.c_int64)]
+        L.respca_mlp_param_count.restype = i64
+        L.respca_mlp_param_count.argtypes = [i32]
+        L.respca_mlp_act_count.restype = i64
+        L.respca_mlp_act_count.argtypes = [i32, i32]
+        L.respca_sketch.restype = i32
+        L.respca_sketch.argtypes = [vp, i64, i64, vp, i64, ct.c_uint64, vp, vp]
+        L.respca_features.restype = i32
+        L.respca_features.argtypes = [vp, i64, i64, i32, vp, vp, vp]
+        L.respca_mlp_forward.restype = i32
+        L.respca_mlp_forward.argtypes = [vp, i32, vp, i32, vp, vp, vp]
+        L.respca_mlp_backward.restype = i32
+        L.respca_mlp_backward.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp]
+        L.respca_mlp_loss.restype = i32
+        L.respca_mlp_loss.argtypes = [vp, i32, vp, vp, ct.c_float, vp, ct.POINTER(ct.c_double), vp]
+        L.respca_mlp_adam.restype = i32
+        L.respca_mlp_adam.argtypes = [vp, i64, vp, vp, vp, vp, ct.c_float, ct.c_float, ct.c_float,
+                                      ct.c_float, i32, vp]
+        L.respca_warmstart.restype = i32
+        L.respca_warmstart.argtypes = [vp, i32, vp, i64, i64, i32, vp, i64, ct.c_uint64, ct.c_uint64,
+                                       vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int32), vp]
         L.respca_kmeans.restype = i32
         L.respca_kmeans.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, vp,
                                     ct.POINTER(Info), vp]
@@ -394,3 +418,90 @@ def batched_phases(device: int = 0) -> dict:
     out = {k: round(ms[i], 3) for i, k in enumerate(BATCH_PHASES)}
     out["steps"] = steps.value
     return out
+
+
+# ------------------------------------------------------------- warm start
+
+def mlp_param_count(hidden: int) -> int:
+    return int(lib().respca_mlp_param_count(hidden))
+
+
+def mlp_act_count(hidden: int, batch: int) -> int:
+    return int(lib().respca_mlp_act_count(hidden, batch))
+
+
+def sketch(X, seed=0, stream=None):
+    """65 x n float32 sketch (returned as an (n, 65) row-major tensor)."""
+    import torch
+    d, n = X.shape
+    xp, ldx = _colmajor(X, "X")
+    Y = torch.empty((n, 65), dtype=torch.float32, device=X.device)
+    h = handle(X.device.index or 0)
+    h.check(lib().respca_sketch(h._h, d, n, xp, ldx, int(seed) & (2**64 - 1), Y.data_ptr(),
+                                _stream(stream)), allow=(OK,))
+    return Y
+
+
+def features(Y, d, c, stream=None):
+    """(n, 68) network inputs from an (n, 65) sketch of a d x n matrix with c groups."""
+    import torch
+    n = Y.shape[0]
+    F = torch.empty((n, WARM_IN), dtype=torch.float32, device=Y.device)
+    h = handle(Y.device.index or 0)
+    h.check(lib().respca_features(h._h, d, n, c, Y.data_ptr(), F.data_ptr(), _stream(stream)),
+            allow=(OK,))
+    return F
+
+
+def mlp_forward(params, hidden, x, stream=None):
+    """Returns (output (B, 65) view, acts buffer)."""
+    import torch
+    B = x.shape[0]
+    acts = torch.empty(mlp_act_count(hidden, B), dtype=torch.float32, device=x.device)
+    h = handle(x.device.index or 0)
+    h.check(lib().respca_mlp_forward(h._h, hidden, params.data_ptr(), B, x.data_ptr(),
+                                     acts.data_ptr(), _stream(stream)), allow=(OK,))
+    return acts[3 * B * hidden:].view(B, WARM_OUT), acts
+
+
+def mlp_backward(params, hidden, x, acts, dy, stream=None):
+    import torch
+    grad = torch.empty_like(params)
+    h = handle(x.device.index or 0)
+    h.check(lib().respca_mlp_backward(h._h, hidden, params.data_ptr(), x.shape[0], x.data_ptr(),
+                                      acts.data_ptr(), dy.data_ptr(), grad.data_ptr(),
+                                      _stream(stream)), allow=(OK,))
+    return grad
+
+
+def mlp_loss(y, t, w_last, stream=None):
+    import torch
+    dy = torch.empty_like(y)
+    loss = ct.c_double()
+    h = handle(y.device.index or 0)
+    h.check(lib().respca_mlp_loss(h._h, y.shape[0], y.data_ptr(), t.data_ptr(), float(w_last),
+                                  dy.data_ptr(), ct.byref(loss), _stream(stream)), allow=(OK,))
+    return loss.value, dy
+
+
+def mlp_adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    h = handle(params.device.index or 0)
+    h.check(lib().respca_mlp_adam(h._h, params.numel(), params.data_ptr(), grad.data_ptr(),
+                                  m.data_ptr(), v.data_ptr(), float(lr), float(beta1), float(beta2),
+                                  float(eps), int(step), _stream(stream)), allow=(OK,))
+
+
+def warmstart(X, rank, params, hidden, sketch_seed=0, kmeans_seed=0, stream=None):
+    """Initial labels (device int32[n]), rho0 and the fallback flag for X."""
+    import torch
+    d, n = X.shape
+    xp, ldx = _colmajor(X, "X")
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    rho0 = ct.c_double()
+    fb = ct.c_int32()
+    h = handle(X.device.index or 0)
+    h.check(lib().respca_warmstart(h._h, hidden, params.data_ptr(), d, n, rank, xp, ldx,
+                                   int(sketch_seed) & (2**64 - 1), int(kmeans_seed) & (2**64 - 1),
+                                   labels.data_ptr(), ct.byref(rho0), ct.byref(fb), _stream(stream)),
+            allow=(OK,))
+    return labels, rho0.value, bool(fb.value)

@@ -491,3 +491,53 @@ def test_batched_size_mix_converges():
         r = torch.linalg.norm(X.double() - L.double() - S.double()) / torch.linalg.norm(X.double())
         assert float(r) <= 1.5e-6, (i, float(r))
         assert int(lab.min()) >= 0 and int(lab.max()) < ranks[i]
+
+
+# ------------------------------------------------------- warm-start kernels
+
+def test_sketch_and_features_match_oracle():
+    from oracle import mlp as omlp
+    rng = np.random.default_rng(31)
+    d, n, c = 1037, 311, 7
+    X = np.asfortranarray(rng.normal(0, 3, (d, n)).astype(np.float32))
+    Y = rp.sketch(dev(X), seed=77)                       # (n, 65)
+    Yo = oracle.sketch(X, 77)                            # (65, n)
+    Yg = Y.cpu().numpy().astype(np.float64).T
+    assert rel(Yg, Yo, 1.0) <= 2e-6
+    F = rp.features(Y, d, c).cpu().numpy().astype(np.float64)
+    Fo = omlp.features(Yo, d, c)
+    assert np.abs(F - Fo).max() <= 1e-4
+
+
+@pytest.mark.parametrize("hidden,batch", [(32, 300), (256, 1000)])
+def test_mlp_forward_backward_adam_match_oracle(hidden, batch):
+    """The hand-written network kernels against the FP64 reference: outputs,
+    loss and its gradient, parameter gradients, one Adam step."""
+    from oracle import mlp as omlp
+    dims = [68, hidden, hidden, hidden, 65]
+    rng = np.random.default_rng(hidden + batch)
+    p = (omlp.init_params(dims, 5) + 0.01 * rng.normal(size=omlp.layer_slices(dims)[1])).astype(np.float32)
+    x = rng.normal(size=(batch, 68)).astype(np.float32)
+    t = rng.normal(size=(batch, 65)).astype(np.float32)
+    P = torch.from_numpy(p).cuda()
+    Xg = torch.from_numpy(x).cuda()
+    Tg = torch.from_numpy(t).cuda()
+    out, acts = rp.mlp_forward(P, hidden, Xg)
+    yo, acts_o = omlp.forward(p.astype(np.float64), dims, x.astype(np.float64))
+    assert rel(out.cpu().numpy(), yo, 1.0) <= 2e-5
+    loss, dy = rp.mlp_loss(out, Tg, 4.0)
+    lo, dyo = omlp.loss_grad(out.cpu().numpy().astype(np.float64), t, 4.0)
+    assert loss == pytest.approx(lo, rel=1e-6)
+    np.testing.assert_allclose(dy.cpu().numpy(), dyo, rtol=1e-5, atol=1e-9)
+    g = rp.mlp_backward(P, hidden, Xg, acts, dy)
+    go = omlp.backward(p.astype(np.float64), dims, acts_o, dyo)
+    assert rel(g.cpu().numpy(), go, 1.0) <= 1e-4
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    P2 = P.clone()
+    rp.mlp_adam(P2, g, m, v, 1e-3, 1)
+    rp.mlp_adam(P2, g, m, v, 1e-3, 2)
+    po, mo, vo = omlp.adam(p.astype(np.float64), g.cpu().numpy().astype(np.float64), 0.0, 0.0,
+                           1e-3, 0.9, 0.999, 1e-8, 1)
+    po, mo, vo = omlp.adam(po, g.cpu().numpy().astype(np.float64), mo, vo, 1e-3, 0.9, 0.999, 1e-8, 2)
+    np.testing.assert_allclose(P2.cpu().numpy(), po, rtol=0, atol=2e-6)

@@ -416,3 +416,61 @@ def test_column_restricted_step_agrees_with_full_step(orc):
         np.testing.assert_array_equal(part[k], full[k][:, sel])
     assign_first = orc.assign(full["L"][:, sel], part["mu"])
     np.testing.assert_array_equal(part["labels"], assign_first)
+
+
+# ------------------------------------------------------- warm-start sketch --
+
+def test_splitmix64_counter_access_matches_stream(orc):
+    seq = orc.splitmix64(1234567, 6)
+    assert [orc.splitmix64_at(1234567, t) for t in range(6)] == seq
+
+
+def test_sketch_is_a_scaled_sign_projection(orc):
+    """Rows 0..63: R X with R[k][i] = +-1/8 from bit k of the i-th counter output
+    (built here from the published splitmix64 vectors' generator, independently of
+    the oracle's loop), row 64: column norms; R R^T / d -> I/64."""
+    rng = np.random.default_rng(17)
+    d, n, seed = 37, 5, 99
+    X = np.asfortranarray(rng.normal(size=(d, n)))
+    Y = orc.sketch(X, seed)
+    R = np.empty((64, d))
+    for i in range(d):
+        bits = orc.splitmix64_at(seed, i)
+        for k in range(64):
+            R[k, i] = -0.125 if (bits >> k) & 1 else 0.125
+    np.testing.assert_allclose(Y[:64], R @ X, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Y[64], np.linalg.norm(X, axis=0), rtol=1e-14)
+    Rb = np.array([[-0.125 if (orc.splitmix64_at(5, i) >> k) & 1 else 0.125 for i in range(4000)]
+                   for k in range(64)])
+    G = Rb @ Rb.T / 4000 * 64
+    assert np.abs(np.diag(G) - 1).max() < 1e-12
+    assert np.abs(G - np.diag(np.diag(G))).max() < 0.08   # near-orthogonal rows
+
+
+# ----------------------------------------------------- warm-start network --
+
+def test_mlp_backward_matches_central_differences():
+    from oracle import mlp
+    dims = [6, 9, 9, 9, 4]
+    rng = np.random.default_rng(21)
+    p = mlp.init_params(dims, 3) + 0.01 * rng.normal(size=mlp.layer_slices(dims)[1])
+    x = rng.normal(size=(5, 6))
+    t = rng.normal(size=(5, 4))
+    y, acts = mlp.forward(p, dims, x)
+    loss, dy = mlp.loss_grad(y, t, 3.0)
+    g = mlp.backward(p, dims, acts, dy)
+    h = 1e-6
+    for idx in rng.choice(p.size, 40, replace=False):
+        e = np.zeros_like(p)
+        e[idx] = h
+        lp = mlp.loss_grad(mlp.forward(p + e, dims, x)[0], t, 3.0)[0]
+        lm = mlp.loss_grad(mlp.forward(p - e, dims, x)[0], t, 3.0)[0]
+        assert g[idx] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-8)
+
+
+def test_adam_first_step_is_lr_times_sign():
+    """With bias correction the first Adam step is lr * g / (|g| + eps)."""
+    from oracle import mlp
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    p1, m, v = mlp.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 0.01, 0.9, 0.999, 1e-8, 1)
+    np.testing.assert_allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
