@@ -70,6 +70,14 @@ typedef struct {
                              instead of k-means++ + Lloyd on X (warm start); NULL = none   */
     double  *history;     /* optional HOST double[3 * max_iter]: per iteration the three
                              relative criterion terms (primal, dL, dS); NULL = none        */
+    const void *init_embedding; /* optional device FP32 matrix, init_embedding_rows x n with
+                             leading dimension init_embedding_ld: its columns are clustered
+                             (k-means++ from seed, then Lloyd) instead of the columns of X
+                             to obtain the initial groups; the iterations then start as
+                             with init_labels.  Ignored when init_labels is set; not for
+                             RESPCA_F64.  NULL = none                                       */
+    int64_t  init_embedding_ld;
+    int32_t  init_embedding_rows;
 } respca_params;
 
 typedef struct {
@@ -261,6 +269,21 @@ respca_status respca_warmstart(respca_handle h, int32_t hidden, const void *para
                                int64_t n, int32_t c, const void *X, int64_t ldx,
                                uint64_t sketch_seed, uint64_t kmeans_seed, int32_t *init_labels,
                                double *rho0, int32_t *fallback, void *stream);
+
+/* Warm start of a batch of instances (the learned initialisation above, Sec. 4
+ * groups and Sec. 4.4 rho, for every instance with one network pass over all
+ * their columns).  Instance i is d[i] x n[i] (FP32, device, leading dimension
+ * ldx[i]) with c[i] groups.  Writes `embedding` (device FP32, caller-allocated,
+ * 65 x sum(n) column-major with leading dimension 65): the columns of instance i
+ * start at column sum_{i' < i} n[i'], rows 0..63 hold the predicted centroid
+ * sketches, to be passed as init_embedding (64 rows, leading dimension 65), row
+ * 64 the predicted log-thresholds.  rho0[i] and fallback[i] (host arrays) as for
+ * respca_warmstart.  At most 1024 instances; synchronises `stream`. */
+respca_status respca_warmstart_batched(respca_handle h, int32_t hidden, const void *params,
+                                       int32_t batch, const int64_t *d, const int64_t *n,
+                                       const int32_t *c, const void *const *X, const int64_t *ldx,
+                                       uint64_t sketch_seed, void *embedding, double *rho0,
+                                       int32_t *fallback, void *stream);
 
 /* Phase breakdown of the last batched launch: ms[p] for the phases
  * pack, init, seed-distance, seed-draw, seed-gather, sort, means, finalize,

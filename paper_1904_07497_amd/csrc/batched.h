@@ -18,20 +18,22 @@ struct BatchInst {
     float* Sc;
     int32_t* labels_out;       // nullable
     const int32_t* init_labels;  // nullable
-    int64_t ldx, ldl, lds;
+    const float* Ec;           // nullable: er x n embedding whose columns are clustered first
+    int64_t ldx, ldl, lds, lde;
     // internal copies, zero-padded to dp rows (leading dimension dp)
     float* X;
     float* L;
     float* S;
     float* Th;
-    float* C;                  // dp x c centroids
+    float* Z;                  // embedding copy zero-padded to kdp rows (null without one)
+    float* C;                  // centroids, leading dimension = rows of the current K-means matrix
     int32_t* lab[2];
     int32_t* perm;
     int32_t* counts;
     int32_t* segb;
     int32_t* segl;
     int32_t* segf;
-    double* pmeans;            // [segment][dp]
+    double* pmeans;            // [segment][rows of the current K-means matrix]
     float* part;               // [slice][n][kpad]
     double* d2;
     int32_t* chosen;
@@ -40,8 +42,11 @@ struct BatchInst {
     double* cnorm;
     double* sweep_part;        // 3 per sweep tile
     int32_t* chg;              // 1 per 16-column argmin item
-    // shape and tiling
+    // shape and tiling.  The initial K-means runs on the columns of X (kdp = dp) or of
+    // the embedding (kdp = 4 * ceil(er / 4)); mrows = max(dp, kdp) and mrb row blocks
+    // of kRowsPerBlock cover both.
     int d, dp, n, c, kpad, nrb, jc, slices, slice_rows, nkc, n_sweep, n_argmin;
+    int er, kdp, mrows, mrb;
     // parameters
     double lambda, tol, rho0, kappa, rho_max;
     int max_iter, max_lloyd;
@@ -76,8 +81,8 @@ struct BatchArgs {
     const int32_t* off_tile;   // ceil(n/jc) * nrb   (pack, sweep, unpack)
     const int32_t* off_d2;     // ceil(n/4)          (k-means++ distances, wave per column)
     const int32_t* off_kc;     // c                  (seed columns, centroid norms)
-    const int32_t* off_seg;    // (ceil(n/64) + c) * nrb (group partial sums)
-    const int32_t* off_kr;     // c * ceil(dp/256)   (centroid finalisation)
+    const int32_t* off_seg;    // (ceil(n/64) + c) * mrb (group partial sums)
+    const int32_t* off_kr;     // c * ceil(mrows/256) (centroid finalisation)
     const int32_t* off_dist;   // ceil(n/128) * slices * nkc (distance tiles)
     const int32_t* off_col;    // ceil(n/16)         (argmin)
 };

@@ -11,6 +11,11 @@
 // flag that every other wait sees, so the launch always drains and the host
 // reports an error instead of hanging.
 //
+// An instance given an embedding (a few rows per column, e.g. a learned warm
+// start's predicted sketches) runs its initial K-means on the embedding's
+// columns instead of X's, then takes the means of X over the resulting groups
+// (empty groups at zero) and starts the iterations from there.
+//
 // Instances are stored zero-padded to d' = 4 * ceil(d / 4) rows so every tile
 // takes the 16-byte vector path; the padding rows stay exactly zero through all
 // steps (X, S, Theta, centroids and hence L are zero there), so sums, norms and
@@ -85,6 +90,17 @@ __device__ inline int find_inst(const int32_t* __restrict__ off, int batch, int 
 
 __device__ inline bool needs_groups(int m) { return m == M_MEANSX || m == M_KMX || m == M_ITER || m == M_LL; }
 __device__ inline bool needs_assign(int m) { return m == M_SEED || m == M_KMX || m == M_ITER || m == M_LL; }
+
+// Matrix whose columns the current mode clusters, and its row count (= its
+// leading dimension and that of the centroids).
+__device__ inline const float* kmeans_matrix(const BatchInst& B, int m) {
+    if (m == M_ITER || m == M_LL) return B.L;
+    if (m == M_MEANSX) return B.X;
+    return B.Z ? B.Z : B.X;
+}
+__device__ inline int mode_rows(const BatchInst& B, int m) {
+    return (m == M_SEED || m == M_KMX) ? B.kdp : B.dp;
+}
 
 // ------------------------------------------------------- per-instance work
 
@@ -251,7 +267,7 @@ __device__ void control_instance(BatchInst& B, int* active) {
         B.init_lloyd += 1;
         if (changed == 0 || B.init_lloyd >= B.max_lloyd) {
             if (changed) B.cur ^= 1;
-            B.mode = M_ITER;
+            B.mode = B.Z ? M_MEANSX : M_ITER;   // embedding groups: means of X next
         } else {
             B.cur ^= 1;
         }
@@ -360,6 +376,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 *reinterpret_cast<float4*>(B.S + j * B.dp + r) = z;
                 *reinterpret_cast<float4*>(B.Th + j * B.dp + r) = z;
             }
+        if (B.Z && rb == 0)
+            for (int64_t j = j0; j < j1; ++j)
+                for (int64_t r = threadIdx.x * 4; r < B.kdp; r += kBlock * 4) {
+                    float v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = (r + e < B.er) ? B.Ec[j * B.lde + r + e] : 0.f;
+                    *reinterpret_cast<float4*>(B.Z + j * B.kdp + r) = make_float4(v[0], v[1], v[2], v[3]);
+                }
         block_sum3(a, b, c);
         if (threadIdx.x == 0) B.sweep_part[3 * local] = a;
     });
@@ -390,10 +414,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         const int m = s_m;
         if (s_status == 0 && m == M_DONE)
             for (int j = threadIdx.x; j < B.n; j += kBlock) B.lab[0][j] = 0;
-        if (m == M_MEANSX) {
+        if (m == M_MEANSX)
             for (int j = threadIdx.x; j < B.n; j += kBlock) B.lab[0][j] = B.init_labels[j];
-            for (int64_t e = threadIdx.x; e < (int64_t)B.dp * B.c; e += kBlock) B.C[e] = 0.f;
-        }
         if (m == M_SEED) {
             for (int j = threadIdx.x; j < B.n; j += kBlock) B.chosen[j] = 0;
             __syncthreads();
@@ -419,11 +441,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             const int lane = threadIdx.x & 63;
             const int64_t j = (int64_t)local * 4 + (threadIdx.x >> 6);
             if (j >= B.n) return;
-            const float* yj = B.X + j * B.dp;
-            const float* ys = B.X + (int64_t)B.seeds[m] * B.dp;
+            const float* Y = B.Z ? B.Z : B.X;
+            const int rows = B.kdp;
+            const float* yj = Y + j * rows;
+            const float* ys = Y + (int64_t)B.seeds[m] * rows;
             double acc0 = 0.0, acc1 = 0.0;
             int64_t r = lane * 4;
-            for (; r + 256 < B.dp; r += 512) {        // two rows groups in flight
+            for (; r + 256 < rows; r += 512) {        // two rows groups in flight
                 const float4 a0 = *reinterpret_cast<const float4*>(yj + r);
                 const float4 b0 = *reinterpret_cast<const float4*>(ys + r);
                 const float4 a1 = *reinterpret_cast<const float4*>(yj + r + 256);
@@ -435,7 +459,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 acc0 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
                 acc1 += f0 * f0 + f1 * f1 + f2 * f2 + f3 * f3;
             }
-            if (r < B.dp) {
+            if (r < rows) {
                 const float4 a0 = *reinterpret_cast<const float4*>(yj + r);
                 const float4 b0 = *reinterpret_cast<const float4*>(ys + r);
                 const double e0 = (double)a0.x - b0.x, e1 = (double)a0.y - b0.y;
@@ -457,8 +481,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     load_tab(A.off_kc);
     for_items(batch, s_tab, s_mode, is_seed, [&](int i, int k) {
         BatchInst& B = inst[i];
-        const float* src = B.X + (int64_t)B.seeds[k] * B.dp;
-        for (int64_t r = threadIdx.x; r < B.dp; r += kBlock) B.C[(int64_t)k * B.dp + r] = src[r];
+        const float* src = (B.Z ? B.Z : B.X) + (int64_t)B.seeds[k] * B.kdp;
+        for (int64_t r = threadIdx.x; r < B.kdp; r += kBlock) B.C[(int64_t)k * B.kdp + r] = src[r];
     });
     if (!grid_sync(gs, nb, tmo, BP_GATHER, tclk)) return;
 
@@ -480,17 +504,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         for_items(batch, s_tab, s_mode, needs_groups, [&](int i, int local) {
             BatchInst& B = inst[i];
             const int mode = s_mode[i];
-            const int s = local / B.nrb, rb = local % B.nrb;
+            const int s = local / B.mrb, rb = local % B.mrb;
             if (s >= s_nseg[i]) return;
+            const int rows = mode_rows(B, mode);
             const int64_t r0 = (int64_t)rb * kRowsPerBlock;
-            double* out = B.pmeans + (int64_t)s * B.dp;
+            if (r0 >= rows) return;
+            double* out = B.pmeans + (int64_t)s * rows;
             if (mode == M_ITER)
                 group_partial_tile<float, 4, true>(B.X, B.dp, B.S, B.dp, B.Th, B.dp,
                                                    (float)(1.0 / B.rho), B.dp, B.perm, B.segb[s],
                                                    B.segl[s], r0, out);
             else
-                group_partial_tile<float, 4, false>(mode == M_LL ? B.L : B.X, B.dp, nullptr, 0,
-                                                    nullptr, 0, 0.f, B.dp, B.perm, B.segb[s],
+                group_partial_tile<float, 4, false>(kmeans_matrix(B, mode), rows, nullptr, 0,
+                                                    nullptr, 0, 0.f, rows, B.perm, B.segb[s],
                                                     B.segl[s], r0, out);
         });
         if (!grid_sync(gs, nb, tmo, BP_MEANS, tclk)) return;
@@ -498,14 +524,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         load_tab(A.off_kr);
         for_items(batch, s_tab, s_mode, needs_groups, [&](int i, int local) {
             BatchInst& B = inst[i];
-            const int nrc = (B.dp + kBlock - 1) / kBlock;
+            const int mode = s_mode[i];
+            const int rows = mode_rows(B, mode);
+            const int nrc = (B.mrows + kBlock - 1) / kBlock;
             const int k = local / nrc;
             const int64_t r = (int64_t)(local % nrc) * kBlock + threadIdx.x;
+            if (r >= rows) return;
             const int nk = B.counts[k];
-            if (nk == 0 || r >= B.dp) return;
+            if (nk == 0) {   // an empty group keeps its centroid, except the means of X from given groups
+                if (mode == M_MEANSX) B.C[(int64_t)k * rows + r] = 0.f;
+                return;
+            }
             double s = 0.0;
-            for (int g = B.segf[k]; g < B.segf[k + 1]; ++g) s += B.pmeans[(int64_t)g * B.dp + r];
-            B.C[(int64_t)k * B.dp + r] = (float)(s / (double)nk);
+            for (int g = B.segf[k]; g < B.segf[k + 1]; ++g) s += B.pmeans[(int64_t)g * rows + r];
+            B.C[(int64_t)k * rows + r] = (float)(s / (double)nk);
         });
         if (!grid_sync(gs, nb, tmo, BP_FINALIZE, tclk)) return;
         // D: the fused ALM sweep (instances starting an outer iteration)
@@ -532,9 +564,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         load_tab(A.off_kc);
         for_items(batch, s_tab, s_mode, needs_assign, [&](int i, int k) {
             BatchInst& B = inst[i];
+            const int rows = mode_rows(B, s_mode[i]);
             double a = 0.0, b = 0.0, c = 0.0;
-            for (int64_t r = threadIdx.x; r < B.dp; r += kBlock) {
-                const double x = (double)B.C[(int64_t)k * B.dp + r];
+            for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
+                const double x = (double)B.C[(int64_t)k * rows + r];
                 a += x * x;
             }
             block_sum3(a, b, c);
@@ -548,9 +581,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             const int mode = s_mode[i];
             const int kc = local % B.nkc, ts = local / B.nkc;
             const int tile = ts / B.slices, s = ts % B.slices;
-            const float* Y = (mode == M_ITER || mode == M_LL) ? B.L : B.X;
-            dist_tile<true, false>(B.C, B.dp, B.c, B.kpad, Y, B.dp, B.n, B.slice_rows, B.part, nullptr,
-                                   (int64_t)tile * kJT, s, kc * kKC, false);
+            const int rows = mode_rows(B, mode);
+            dist_tile<true, false>(B.C, rows, B.c, B.kpad, kmeans_matrix(B, mode), rows, B.n,
+                                   B.slice_rows, B.part, nullptr, (int64_t)tile * kJT, s, kc * kKC,
+                                   false);
         });
         if (!grid_sync(gs, nb, tmo, BP_DIST, tclk)) return;
         // G: reduce slices, argmin (16 lanes per column), changed counts

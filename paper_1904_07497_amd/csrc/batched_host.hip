@@ -74,6 +74,8 @@ respca_status validate(respca_handle h, const respca_params* params, int32_t bat
             return fail(h, RESPCA_ERR_INVALID, "leading dimension < d");
         if ((int64_t)(d[i] + 3) / 4 * 4 * n[i] >= (int64_t)INT32_MAX)
             return fail(h, RESPCA_ERR_UNSUPPORTED, "batched instance too large");
+        if (res[i].init_embedding && (int64_t)(res[i].emb_rows + 3) / 4 * 4 * n[i] >= (int64_t)INT32_MAX)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "batched embedding too large");
         if (res[i].init_labels) {
             std::vector<int32_t> hl(n[i]);
             CK(hipMemcpy(hl.data(), res[i].init_labels, n[i] * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -105,6 +107,8 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.Sc = (float*)S[i];
         B.labels_out = labels ? labels[i] : nullptr;
         B.init_labels = r.init_labels;
+        B.Ec = r.init_embedding;
+        B.lde = r.emb_ld;
         B.ldx = ldx[i];
         B.ldl = ldl[i];
         B.lds = lds[i];
@@ -115,11 +119,15 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.kpad = (r.c + 15) / 16 * 16;
         B.nkc = (B.kpad + 127) / 128;
         B.nrb = (B.dp + kRowsPerBlock - 1) / kRowsPerBlock;
+        B.er = B.Ec ? r.emb_rows : 0;
+        B.kdp = B.Ec ? (B.er + 3) / 4 * 4 : B.dp;
+        B.mrows = std::max(B.dp, B.kdp);
+        B.mrb = (B.mrows + kRowsPerBlock - 1) / kRowsPerBlock;
         B.jc = tune.jc;
         int rows = std::max(32, tune.slice_rows / 32 * 32);
-        if (rows > B.dp) rows = (B.dp + 31) / 32 * 32;
+        if (rows > B.mrows) rows = (B.mrows + 31) / 32 * 32;
         B.slice_rows = rows;
-        B.slices = (B.dp + rows - 1) / rows;
+        B.slices = (B.mrows + rows - 1) / rows;
         const int ntiles = (B.n + 127) / 128;
         B.n_sweep = ((B.n + B.jc - 1) / B.jc) * B.nrb;
         B.n_argmin = (B.n + 15) / 16;
@@ -132,8 +140,8 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.max_iter = r.max_iter;
         B.max_lloyd = r.max_lloyd;
         // work tables (prefix sums)
-        const int64_t counts[kTableCount] = {B.n_sweep, (B.n + 3) / 4, B.c, (int64_t)nseg_max * B.nrb,
-                                             (int64_t)B.c * ((B.dp + kBlock - 1) / kBlock),
+        const int64_t counts[kTableCount] = {B.n_sweep, (B.n + 3) / 4, B.c, (int64_t)nseg_max * B.mrb,
+                                             (int64_t)B.c * ((B.mrows + kBlock - 1) / kBlock),
                                              (int64_t)ntiles * B.slices * B.nkc, B.n_argmin};
         for (int t = 0; t < kTableCount; ++t)
             call.tables[t][i + 1] = call.tables[t][i] + (int32_t)counts[t];
@@ -144,7 +152,8 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.L = (float*)take(dpn);
         B.S = (float*)take(dpn);
         B.Th = (float*)take(dpn);
-        B.C = (float*)take((size_t)B.dp * B.c * sizeof(float));
+        B.Z = B.Ec ? (float*)take((size_t)B.kdp * B.n * sizeof(float)) : nullptr;
+        B.C = (float*)take((size_t)B.mrows * B.c * sizeof(float));
         B.lab[0] = (int32_t*)take(B.n * sizeof(int32_t));
         B.lab[1] = (int32_t*)take(B.n * sizeof(int32_t));
         B.perm = (int32_t*)take(B.n * sizeof(int32_t));
@@ -152,7 +161,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.segb = (int32_t*)take(nseg_max * sizeof(int32_t));
         B.segl = (int32_t*)take(nseg_max * sizeof(int32_t));
         B.segf = (int32_t*)take((B.c + 1) * sizeof(int32_t));
-        B.pmeans = (double*)take((size_t)nseg_max * B.dp * sizeof(double));
+        B.pmeans = (double*)take((size_t)nseg_max * B.mrows * sizeof(double));
         B.part = (float*)take((size_t)B.slices * B.n * B.kpad * sizeof(float));
         B.d2 = (double*)take(B.n * sizeof(double));
         B.chosen = (int32_t*)take(B.n * sizeof(int32_t));
@@ -214,6 +223,7 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
         fix(B.X); fix(B.L); fix(B.S); fix(B.Th); fix(B.C); fix(B.lab[0]); fix(B.lab[1]); fix(B.perm);
         fix(B.counts); fix(B.segb); fix(B.segl); fix(B.segf); fix(B.pmeans); fix(B.part); fix(B.d2);
         fix(B.chosen); fix(B.seeds); fix(B.cnorm); fix(B.sweep_part); fix(B.chg);
+        if (B.Ec) fix(B.Z);
         B.u = u_dev + call.u_start[i];
     }
     // stage the header

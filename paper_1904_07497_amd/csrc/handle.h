@@ -60,7 +60,7 @@ struct respca_handle_s {
     double bphase_ms[16] = {};      // phase times of the last batched launch
     int64_t bsteps = 0;
     // warm start
-    respca::DevBuf wsk, wfeat, wacts, wscratch, wred, wcent;
+    respca::DevBuf wsk, wfeat, wacts, wscratch, wred, wcent, embl, embc;
 };
 
 #define CK(expr)                                                                            \
@@ -125,6 +125,9 @@ struct Resolved {
     uint64_t seed;
     const int32_t* init_labels;
     double* history;
+    const float* init_embedding;
+    int64_t emb_ld;
+    int emb_rows;
 };
 
 respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_t n, Resolved& r);

@@ -85,6 +85,15 @@ respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d
     r.seed = p->seed;
     r.init_labels = p->init_labels;
     r.history = p->history;
+    r.init_embedding = p->init_labels ? nullptr : (const float*)p->init_embedding;
+    r.emb_ld = p->init_embedding_ld;
+    r.emb_rows = p->init_embedding_rows;
+    if (r.init_embedding) {
+        if (r.emb_rows < 1 || r.emb_ld < r.emb_rows)
+            return fail(h, RESPCA_ERR_INVALID, "init_embedding rows/leading dimension invalid");
+        if (p->precision == RESPCA_F64)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "init_embedding needs an FP32 precision");
+    }
     if (!(r.lambda >= 0.0) || !std::isfinite(2.0 * r.lambda))
         return fail(h, RESPCA_ERR_INVALID, "lambda must be finite and >= 0");
     if (r.c < 1 || (int64_t)r.c > n) return fail(h, RESPCA_ERR_INVALID, "rank must be in [1, n]");
@@ -323,7 +332,20 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
     }
     const double nX = std::sqrt(nx2);
 
-    if (r.init_labels) {
+    if (r.init_embedding) {
+        // groups from K-means of the embedding's columns, then as with init labels
+        CKS(ensure(h, h->embl, n * sizeof(int32_t)));
+        CKS(ensure(h, h->embc, (size_t)r.emb_rows * r.c * sizeof(float)));
+        int steps = 0;
+        CKS(kmeans_f32(h, r.emb_rows, n, r.c, r.init_embedding, r.emb_ld, r.seed, r.max_lloyd,
+                       (int32_t*)h->embl.p, (float*)h->embc.p, st, &steps));
+        info->init_lloyd = steps;
+        CKS(e.setup());
+        CK(hipMemcpyAsync(cur, h->embl.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        launch_zero2d<T>(C, d, d, r.c, st);
+        e.sort(cur);
+        e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C);
+    } else if (r.init_labels) {
         std::vector<int32_t> hl(n);
         CK(hipMemcpyAsync(hl.data(), r.init_labels, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
@@ -484,7 +506,8 @@ void respca_destroy(respca_handle h) {
     if (h->bstream) (void)hipStreamDestroy(h->bstream);
     if (h->bws.p) (void)hipFree(h->bws.p);
     if (h->bstage) (void)hipHostFree(h->bstage);
-    respca::DevBuf* wbufs[] = {&h->wsk, &h->wfeat, &h->wacts, &h->wscratch, &h->wred, &h->wcent};
+    respca::DevBuf* wbufs[] = {&h->wsk, &h->wfeat, &h->wacts, &h->wscratch, &h->wred, &h->wcent,
+                               &h->embl, &h->embc};
     for (respca::DevBuf* b : wbufs)
         if (b->p) (void)hipFree(b->p);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
@@ -511,6 +534,9 @@ void respca_params_default(respca_params* p) {
     p->precision = RESPCA_F32;
     p->init_labels = nullptr;
     p->history = nullptr;
+    p->init_embedding = nullptr;
+    p->init_embedding_ld = 0;
+    p->init_embedding_rows = 0;
 }
 
 const char* respca_status_string(respca_status s) {

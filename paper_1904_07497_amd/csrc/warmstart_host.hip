@@ -131,18 +131,74 @@ respca_status respca_warmstart(respca_handle h, int32_t hidden, const void* para
     const float* out = A + (int64_t)3 * n * hidden;      // n x 65
     launch_pool_last(out, n, red + 1, st);
     CK(hipMemcpyAsync(h->hstage, red, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    // read before the K-means below, which reuses the host staging area
+    const double total = h->hstage[0], tmean = h->hstage[1];
     // initial groups: K-means of the predicted centroid sketches (column j = out row j, ld 65)
     int steps = 0;
     CKS(kmeans_f32(h, 64, n, c, out, kWarmOut, kmeans_seed, 100, init_labels, (float*)h->wcent.p, st,
                    &steps));
     CK(hipStreamSynchronize(st));
-    const double total = h->hstage[0], tmean = h->hstage[1];
     const double s = std::sqrt(total / ((double)d * (double)n));
     double r = (s > 0.0) ? std::exp(tmean) / s : NAN;
     int fb = 0;
     if (!(r > 0.0) || !std::isfinite(r) || r > 1e10) { r = 1e-4; fb = 1; }
     *rho0 = r;
     if (fallback) *fallback = fb;
+    return RESPCA_OK;
+}
+
+respca_status respca_warmstart_batched(respca_handle h, int32_t hidden, const void* params,
+                                       int32_t batch, const int64_t* d, const int64_t* n,
+                                       const int32_t* c, const void* const* X, const int64_t* ldx,
+                                       uint64_t sketch_seed, void* embedding, double* rho0,
+                                       int32_t* fallback, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    if (!hidden_ok(hidden) || !params || batch < 1 || batch > 1024 || !d || !n || !c || !X || !ldx ||
+        !embedding || !rho0)
+        return fail(h, RESPCA_ERR_INVALID, "bad batched warm-start arguments");
+    int64_t total = 0;
+    for (int i = 0; i < batch; ++i) {
+        if (!X[i] || d[i] < 1 || n[i] < 1 || ldx[i] < d[i] || c[i] < 1 || c[i] > n[i])
+            return fail(h, RESPCA_ERR_INVALID, "bad batched warm-start instance");
+        total += n[i];
+    }
+    if (total >= INT32_MAX / kWarmOut) return fail(h, RESPCA_ERR_UNSUPPORTED, "too many columns");
+    CK(hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    CKS(ensure(h, h->wsk, (size_t)65 * total * sizeof(float)));
+    CKS(ensure(h, h->wfeat, (size_t)kWarmIn * total * sizeof(float)));
+    CKS(ensure(h, h->wacts, (size_t)mlp_act_count(hidden, (int)total) * sizeof(float)));
+    CKS(ensure(h, h->wred, (size_t)2 * batch * sizeof(double)));
+    CKS(ensure_host(h, (size_t)2 * batch * sizeof(double)));
+    float* Y = (float*)h->wsk.p;
+    float* F = (float*)h->wfeat.p;
+    float* A = (float*)h->wacts.p;
+    double* red = (double*)h->wred.p;
+    int64_t off = 0;
+    for (int i = 0; i < batch; ++i) {   // per instance: sketch and features (own Frobenius scale)
+        launch_sketch((const float*)X[i], ldx[i], d[i], n[i], sketch_seed, Y + 65 * off, st);
+        launch_features(Y + 65 * off, d[i], n[i], c[i], red + 2 * i, F + (int64_t)kWarmIn * off, st);
+        off += n[i];
+    }
+    launch_mlp_forward((const float*)params, hidden, (int)total, F, A, st);
+    const float* out = A + (int64_t)3 * total * hidden;   // total x 65
+    off = 0;
+    for (int i = 0; i < batch; ++i) {
+        launch_pool_last(out + (int64_t)kWarmOut * off, n[i], red + 2 * i + 1, st);
+        off += n[i];
+    }
+    CK(hipMemcpyAsync(embedding, out, (size_t)kWarmOut * total * sizeof(float), hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(h->hstage, red, 2 * (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    for (int i = 0; i < batch; ++i) {
+        const double s = std::sqrt(h->hstage[2 * i] / ((double)d[i] * (double)n[i]));
+        double r = (s > 0.0) ? std::exp(h->hstage[2 * i + 1]) / s : NAN;
+        int fb = 0;
+        if (!(r > 0.0) || !std::isfinite(r) || r > 1e10) { r = 1e-4; fb = 1; }
+        rho0[i] = r;
+        if (fallback) fallback[i] = fb;
+    }
     return RESPCA_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_s
            "respca_solve_batched", "respca_autotune_batched", "respca_profile_batched_phases",
            "respca_mlp_param_count", "respca_mlp_act_count", "respca_sketch", "respca_features",
            "respca_mlp_forward", "respca_mlp_backward", "respca_mlp_loss", "respca_mlp_adam",
-           "respca_warmstart")
+           "respca_warmstart", "respca_warmstart_batched")
 WARM_IN, WARM_OUT = 68, 65
 BATCH_PHASES = ("pack", "init", "seed_distance", "seed_draw", "seed_gather", "sort", "means",
                 "finalize", "sweep", "centroid_norms", "distance", "argmin", "control")
@@ -40,7 +40,8 @@ class Params(ct.Structure):
                 ("max_iter", ct.c_int32), ("rho0", ct.c_double), ("kappa", ct.c_double),
                 ("rho_max", ct.c_double), ("max_lloyd", ct.c_int32), ("seed", ct.c_uint64),
                 ("precision", ct.c_int32), ("init_labels", ct.c_void_p),
-                ("history", ct.POINTER(ct.c_double))]
+                ("history", ct.POINTER(ct.c_double)), ("init_embedding", ct.c_void_p),
+                ("init_embedding_ld", ct.c_int64), ("init_embedding_rows", ct.c_int32)]
 
 
 class Info(ct.Structure):
@@ -124,6 +125,10 @@ def lib():
         L.respca_warmstart.restype = i32
         L.respca_warmstart.argtypes = [vp, i32, vp, i64, i64, i32, vp, i64, ct.c_uint64, ct.c_uint64,
                                        vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int32), vp]
+        L.respca_warmstart_batched.restype = i32
+        L.respca_warmstart_batched.argtypes = [vp, i32, vp, i32, i64p, i64p, ct.POINTER(ct.c_int32),
+                                               arr, i64p, ct.c_uint64, vp, ct.POINTER(ct.c_double),
+                                               ct.POINTER(ct.c_int32), vp]
         L.respca_kmeans.restype = i32
         L.respca_kmeans.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, vp,
                                     ct.POINTER(Info), vp]
@@ -232,7 +237,7 @@ def _stream(stream):
 
 def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
           max_lloyd=100, seed=0, precision=None, init_labels=None, history=False,
-          out=None, stream=None):
+          out=None, stream=None, init_embedding=None):
     """RES-PCA of X (d x n column-major tensor).  Returns dict(L, S, labels, info[, history])."""
     import torch
     precision = _dtype_precision(X, precision)
@@ -255,6 +260,12 @@ def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho
     if init_labels is not None:
         il = init_labels.to(device=X.device, dtype=torch.int32).contiguous()
         p.init_labels = il.data_ptr()
+    if init_embedding is not None:
+        if init_embedding.dtype != torch.float32:
+            raise ValueError("init_embedding must be float32")
+        ep, eld = _colmajor(init_embedding, "init_embedding")
+        p.init_embedding, p.init_embedding_ld = ep, eld
+        p.init_embedding_rows = init_embedding.shape[0]
     info = Info()
     h = handle(X.device.index or 0)
     s = lib().respca_solve(h._h, ct.byref(p), d, n, xp, ldx, lp, ldl, sp, lds, labels.data_ptr(),
@@ -357,9 +368,11 @@ def _batch_args(Xs, params_list, outs):
 
 
 def batch_params(ranks, lams=None, tol=1e-6, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
-                 max_lloyd=100, seeds=None, init_labels=None):
+                 max_lloyd=100, seeds=None, init_labels=None, init_embeddings=None):
     """Per-instance Params (FP32).  ``rho0`` may be a scalar or a per-instance list;
-    ``init_labels`` a list of device int32 tensors or None entries."""
+    ``init_labels`` a list of device int32 tensors or None entries; ``init_embeddings``
+    a list of (rows, n) column-major float32 device tensors or None entries."""
+    import torch
     b = len(ranks)
     out, keep = [], []
     for i in range(b):
@@ -369,6 +382,13 @@ def batch_params(ranks, lams=None, tol=1e-6, max_iter=500, rho0=1e-4, kappa=1.5,
         if init_labels is not None and init_labels[i] is not None:
             p.init_labels = init_labels[i].data_ptr()
             keep.append(init_labels[i])
+        if init_embeddings is not None and init_embeddings[i] is not None:
+            e = init_embeddings[i]
+            if e.dtype != torch.float32:
+                raise ValueError("init_embedding must be float32")
+            ep, eld = _colmajor(e, "init_embedding")
+            p.init_embedding, p.init_embedding_ld, p.init_embedding_rows = ep, eld, e.shape[0]
+            keep.append(e)
         out.append(p)
     return out, keep
 
@@ -474,14 +494,17 @@ def mlp_backward(params, hidden, x, acts, dy, stream=None):
     return grad
 
 
-def mlp_loss(y, t, w_last, stream=None):
+def mlp_loss(y, t, w_last, stream=None, read=True):
+    """(loss, dy); with read=False the loss is not read back (no host synchronisation)
+    and None is returned in its place."""
     import torch
     dy = torch.empty_like(y)
     loss = ct.c_double()
     h = handle(y.device.index or 0)
     h.check(lib().respca_mlp_loss(h._h, y.shape[0], y.data_ptr(), t.data_ptr(), float(w_last),
-                                  dy.data_ptr(), ct.byref(loss), _stream(stream)), allow=(OK,))
-    return loss.value, dy
+                                  dy.data_ptr(), ct.byref(loss) if read else None, _stream(stream)),
+            allow=(OK,))
+    return (loss.value if read else None), dy
 
 
 def mlp_adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
@@ -505,3 +528,34 @@ def warmstart(X, rank, params, hidden, sketch_seed=0, kmeans_seed=0, stream=None
                                    labels.data_ptr(), ct.byref(rho0), ct.byref(fb), _stream(stream)),
             allow=(OK,))
     return labels, rho0.value, bool(fb.value)
+
+
+def warmstart_batched(Xs, ranks, params, hidden, sketch_seed=0, stream=None):
+    """Warm start of a batch: returns (embeddings, rho0s, fallbacks) where embeddings[i]
+    is the (64, n_i) column-major view (leading dimension 65) of the predicted centroid
+    sketches of instance i, ready for ``init_embeddings``."""
+    import torch
+    b = len(Xs)
+    dev = Xs[0].device
+    ns = [int(X.shape[1]) for X in Xs]
+    ptrs, lds = [], []
+    for X in Xs:
+        if X.dtype != torch.float32:
+            raise ValueError("warm start needs float32 instances")
+        p, ld = _colmajor(X, "X")
+        ptrs.append(p)
+        lds.append(ld)
+    emb = torch.empty(sum(ns), WARM_OUT, dtype=torch.float32, device=dev)
+    rho0 = (ct.c_double * b)()
+    fb = (ct.c_int32 * b)()
+    h = handle(dev.index or 0)
+    h.check(lib().respca_warmstart_batched(
+        h._h, hidden, params.data_ptr(), b, (ct.c_int64 * b)(*[int(X.shape[0]) for X in Xs]),
+        (ct.c_int64 * b)(*ns), (ct.c_int32 * b)(*[int(r) for r in ranks]),
+        (ct.c_void_p * b)(*ptrs), (ct.c_int64 * b)(*lds), int(sketch_seed) & (2**64 - 1),
+        emb.data_ptr(), rho0, fb, _stream(stream)), allow=(OK,))
+    views, off = [], 0
+    for n in ns:
+        views.append(emb[off:off + n, :WARM_OUT - 1].t())
+        off += n
+    return views, list(rho0), [bool(x) for x in fb]

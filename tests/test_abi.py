@@ -1,6 +1,8 @@
 """The C-ABI library loads and exports every symbol include/respca.h declares;
 host-only entry points work without a GPU."""
 import math
+
+import numpy as np
 import os
 import re
 
@@ -38,3 +40,15 @@ def test_null_handle_is_rejected_without_touching_a_device():
     p = rp.default_params()
     assert lib.respca_solve(None, p, 4, 4, None, 4, None, 4, None, 4, None, None, None) == rp.ERR_INVALID
     assert lib.respca_last_error(None) == b"NULL handle"
+
+
+def test_warmstart_module_host_logic():
+    """Training-instance shapes follow the batched size-mix recipe; the initial
+    parameters have the library's layout size and are reproducible."""
+    from paper_1904_07497_amd import synth
+    from paper_1904_07497_amd import warmstart as ws
+    for i, (d, n, r) in enumerate(synth.batch_shapes(5, ws.TRAIN_BASE)):
+        assert ws.instance_meta(ws.TRAIN_BASE + i)[:3] == (d, n, r)
+    a = ws.init_params(32, 3)
+    assert a.size == 68 * 32 + 32 + 2 * (32 * 32 + 32) + 32 * 65 + 65
+    assert np.array_equal(a, ws.init_params(32, 3))

@@ -541,3 +541,146 @@ def test_mlp_forward_backward_adam_match_oracle(hidden, batch):
                            1e-3, 0.9, 0.999, 1e-8, 1)
     po, mo, vo = omlp.adam(po, g.cpu().numpy().astype(np.float64), mo, vo, 1e-3, 0.9, 0.999, 1e-8, 2)
     np.testing.assert_allclose(P2.cpu().numpy(), po, rtol=0, atol=2e-6)
+
+
+# --------------------------------------------------- embedding initialisation
+
+def _embedding_cases():
+    """(X, embedding view, c, lam) with embedding rows 13 (ld 16), 64 (> d) and 8."""
+    cases = []
+    for (d, n, c, er, ld, seed) in [(300, 200, 5, 13, 16, 41), (10, 150, 4, 64, 64, 42),
+                                    (1030, 241, 4, 8, 9, 43)]:
+        X, _, _, _ = synth.clustered(d, n, c, seed=seed, sep=4.0, noise=0.5, frac=0.05, amp=8.0,
+                                     dtype=np.float32, min_size=2)
+        E, _, _, _ = synth.clustered(er, n, c, seed=seed + 100, sep=6.0, noise=0.3, frac=0.0,
+                                     amp=1.0, dtype=np.float32, min_size=2)
+        buf = np.zeros((ld, n), np.float32, order="F")
+        buf[:er] = E
+        Ed = dev(buf)[:er]
+        cases.append((X, E, Ed, c, 0.5 if seed % 2 else float(np.sqrt(max(d, n)))))
+    return cases
+
+
+def _oracle_from_embedding(X, E, c, lam, seed, **kw):
+    lab, _, steps = oracle.kmeans(E, c, seed, 100)
+    o = oracle.solve(X, oracle.make_params(c, lam=lam, seed=seed, **kw), init_labels=lab)
+    return o, steps
+
+
+def test_init_embedding_single_solve_matches_oracle():
+    """Groups from K-means of an embedding's columns, then the iterations from the
+    means of X over them: identical to the oracle given the embedding's labels."""
+    for i, (X, E, Ed, c, lam) in enumerate(_embedding_cases()):
+        o, steps = _oracle_from_embedding(X, E, c, lam, seed=i + 3, tol=1e-6)
+        g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=o["info"]["iters"], seed=i + 3,
+                     precision=rp.F32, init_embedding=Ed)
+        say(f"embedding case {i} {X.shape} iters {g['info']['iters']} init_lloyd "
+            f"{g['info']['init_lloyd']} / {steps}")
+        assert g["info"]["init_lloyd"] == steps
+        np.testing.assert_array_equal(g["labels"].cpu().numpy(), o["labels"])
+        nX = np.linalg.norm(X.astype(np.float64))
+        assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
+        assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+    with pytest.raises(rp.RespcaError):
+        rp.solve(dev(X, np.float64), rank=c, precision=rp.F64, init_embedding=Ed)
+
+
+def test_init_embedding_batched_matches_oracle():
+    """Embedding, label and cold instances side by side in one persistent launch."""
+    cases = _embedding_cases()
+    shapes, Xs = _batch_mix()
+    X_lab, X_cold = Xs[1], Xs[2]
+    lab0 = np.random.default_rng(5).integers(0, shapes[1][2], X_lab.shape[1]).astype(np.int32)
+    Xall = [cs[0] for cs in cases] + [X_lab, X_cold]
+    ranks = [cs[3] for cs in cases] + [shapes[1][2], shapes[2][2]]
+    lams = [cs[4] for cs in cases] + [0.7, 0.4]
+    seeds = [11, 12, 13, 14, 15]
+    T = []
+    for i, (X, r, lam, sd) in enumerate(zip(Xall, ranks, lams, seeds)):
+        if i < len(cases):
+            o, steps = _oracle_from_embedding(X, cases[i][1], r, lam, sd, tol=1e-6)
+            o["emb_steps"] = steps
+        elif i == len(cases):
+            o = oracle.solve(X, oracle.make_params(r, lam=lam, tol=1e-6, seed=sd), init_labels=lab0)
+        else:
+            o = oracle.solve(X, oracle.make_params(r, lam=lam, tol=1e-6, seed=sd))
+        T.append(o)
+    emb = [cs[2] for cs in cases] + [None, None]
+    labs = [None] * len(cases) + [torch.from_numpy(lab0).cuda(), None]
+    plist, keep = rp.batch_params(ranks, lams, tol=0.0, max_iter=0, seeds=seeds, init_labels=labs,
+                                  init_embeddings=emb)
+    for p, o in zip(plist, T):
+        p.max_iter = o["info"]["iters"]
+    outs, infos, status = rp.solve_batched([dev(X) for X in Xall], plist)
+    for i, (X, o) in enumerate(zip(Xall, T)):
+        say(f"batched embedding instance {i} {X.shape} iters {infos[i]['iters']} / {o['info']['iters']}")
+        assert infos[i]["iters"] == o["info"]["iters"]
+        want_init = o["emb_steps"] if "emb_steps" in o else o["info"]["init_lloyd"]
+        assert infos[i]["init_lloyd"] == want_init
+        np.testing.assert_array_equal(outs[i][2].cpu().numpy(), o["labels"])
+        nX = np.linalg.norm(X.astype(np.float64))
+        assert rel(host(outs[i][0]), o["L"], nX) <= F32_TOL, i
+        assert rel(host(outs[i][1]), o["S"], nX) <= F32_TOL, i
+
+
+def test_warmstart_batched_matches_oracle_network():
+    """Batched warm start: every instance's predicted sketches and rho0 against the
+    FP64 sketch -> features -> network chain, and against the one-instance call."""
+    from oracle import mlp as omlp
+    hidden = 32
+    dims = [68, hidden, hidden, hidden, 65]
+    p = omlp.init_params(dims, 9).astype(np.float32)
+    P = torch.from_numpy(p).cuda()
+    rng = np.random.default_rng(8)
+    shapes = [(300, 200, 5), (17, 90, 3), (1030, 411, 8)]
+    Xs = [np.asfortranarray(rng.normal(0, 2, (d, n)).astype(np.float32)) for d, n, _ in shapes]
+    views, rho0s, fbs = rp.warmstart_batched([dev(X) for X in Xs], [s[2] for s in shapes], P, hidden,
+                                             sketch_seed=21)
+    for X, (d, n, c), v, r0, fb in zip(Xs, shapes, views, rho0s, fbs):
+        Yo = oracle.sketch(X, 21)
+        yo, _ = omlp.forward(p.astype(np.float64), dims, omlp.features(Yo, d, c))
+        assert v.shape == (64, n) and v.stride() == (1, 65)
+        assert rel(v.cpu().numpy().astype(np.float64).T, yo[:, :64], 1.0) <= 5e-4
+        s = np.linalg.norm(X.astype(np.float64)) / np.sqrt(d * n)
+        assert not fb
+        assert r0 == pytest.approx(np.exp(yo[:, 64].mean()) / s, rel=1e-3)
+        _, r1, _ = rp.warmstart(dev(X), c, P, hidden, sketch_seed=21)
+        assert r0 == pytest.approx(r1, rel=1e-6)
+
+
+def test_warm_started_batched_solve_matches_oracle_chain():
+    """Whole warm-started path (sketch -> network -> K-means of the predicted sketches ->
+    iterations from rho0) against the same chain on the oracle side, for a network
+    with fixed random weights: labels equal, L and S within the FP32 bar."""
+    from oracle import mlp as omlp
+    hidden = 64
+    dims = [68, hidden, hidden, hidden, 65]
+    p = omlp.init_params(dims, 17).astype(np.float32)
+    P = torch.from_numpy(p).cuda()
+    shapes = [(400, 300, 4), (90, 500, 6)]
+    Xs = [synth.clustered(d, n, c, seed=60 + i, sep=4.0, noise=0.3, frac=0.05, amp=8.0,
+                          dtype=np.float32, min_size=3)[0] for i, (d, n, c) in enumerate(shapes)]
+    views, rho0s, _ = rp.warmstart_batched([dev(X) for X in Xs], [s[2] for s in shapes], P, hidden,
+                                           sketch_seed=5)
+    T = []
+    for X, (d, n, c), r0 in zip(Xs, shapes, rho0s):
+        yo, _ = omlp.forward(p.astype(np.float64), dims, omlp.features(oracle.sketch(X, 5), d, c))
+        s = np.linalg.norm(X.astype(np.float64)) / np.sqrt(d * n)
+        rho0_o = float(np.exp(yo[:, 64].mean()) / s)
+        assert r0 == pytest.approx(rho0_o, rel=1e-4)
+        lab, _, steps = oracle.kmeans(np.asfortranarray(yo[:, :64].T), c, 0, 100)
+        o = oracle.solve(X, oracle.make_params(c, lam=0.5, tol=1e-6, rho0=rho0_o), init_labels=lab)
+        o["emb_steps"] = steps
+        T.append(o)
+    plist, keep = rp.batch_params([s[2] for s in shapes], [0.5, 0.5], tol=0.0, max_iter=0, rho0=rho0s,
+                                  init_embeddings=views)
+    for pp, o in zip(plist, T):
+        pp.max_iter = o["info"]["iters"]
+    outs, infos, _ = rp.solve_batched([dev(X) for X in Xs], plist)
+    for i, (X, o) in enumerate(zip(Xs, T)):
+        say(f"warm chain instance {i}: iters {infos[i]['iters']} init_lloyd {infos[i]['init_lloyd']}")
+        assert infos[i]["init_lloyd"] == o["emb_steps"]
+        np.testing.assert_array_equal(outs[i][2].cpu().numpy(), o["labels"])
+        nX = np.linalg.norm(X.astype(np.float64))
+        assert rel(host(outs[i][0]), o["L"], nX) <= F32_TOL
+        assert rel(host(outs[i][1]), o["S"], nX) <= F32_TOL
