@@ -8,6 +8,7 @@
 namespace respca {
 
 constexpr int kMaxBatch = 1024;   // instances per batched call (LDS-cached work tables)
+constexpr int kBatchRows = 256;   // rows per tile (one wave covers them, 4 per lane)
 
 // One instance.  The static part is written by the host; the state part is
 // owned by the kernel (initialised in its first phases, read back by the host).
@@ -44,7 +45,7 @@ struct BatchInst {
     int32_t* chg;              // 1 per 16-column argmin item
     // shape and tiling.  The initial K-means runs on the columns of X (kdp = dp) or of
     // the embedding (kdp = 4 * ceil(er / 4)); mrows = max(dp, kdp) and mrb row blocks
-    // of kRowsPerBlock cover both.
+    // of kBatchRows cover both.
     int d, dp, n, c, kpad, nrb, jc, slices, slice_rows, nkc, n_sweep, n_argmin;
     int er, kdp, mrows, mrb;
     // parameters
@@ -62,12 +63,13 @@ enum BatchPhase : int {
 };
 
 struct BatchSync {
-    unsigned count;
-    unsigned gen;
+    unsigned count;                  // top-level barrier arrivals (one per group)
+    unsigned gen;                    // barrier generation
     int abort;
     int active;
     uint64_t phase_ticks[BP_COUNT];  // wall-clock ticks per phase, measured by workgroup 0
     uint64_t steps;
+    unsigned group_count[8 * 64];    // per-group barrier arrivals, one 256-byte line each
 };
 
 struct BatchArgs {
@@ -78,7 +80,7 @@ struct BatchArgs {
     int cmax;
     int max_steps;
     // prefix tables (batch + 1 entries) of per-instance work items
-    const int32_t* off_tile;   // ceil(n/jc) * nrb   (pack, sweep, unpack)
+    const int32_t* off_tile;   // ceil(n/jc) * nrb   (pack, sweep, unpack; nrb = ceil(dp/256))
     const int32_t* off_d2;     // ceil(n/4)          (k-means++ distances, wave per column)
     const int32_t* off_kc;     // c                  (seed columns, centroid norms)
     const int32_t* off_seg;    // (ceil(n/64) + c) * mrb (group partial sums)

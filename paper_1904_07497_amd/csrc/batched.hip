@@ -37,23 +37,43 @@ enum Mode : int { M_DONE = 0, M_SEED = 1, M_MEANSX = 2, M_KMX = 3, M_ITER = 4, M
 
 // ---------------------------------------------------------------- barrier
 
+// Two-level grid barrier.  Workgroups arrive on one of eight group counters
+// (workgroup index mod 8, each on its own cache line), the last arrival of each
+// group on the top counter, and the last top arrival bumps the generation the
+// others poll.  Memory ordering uses fences instead of ordered atomics: one
+// agent-scope release fence before arriving, an acquire-release fence in every
+// last arrival (which passes the earlier arrivals' writes on), relaxed polling
+// and one acquire fence after it -- so each wait costs one cache write-back and
+// one invalidate instead of one per poll.  Every wait is bounded by a wall-clock
+// limit; a workgroup that waits too long raises the abort flag, which ends every
+// other wait, and all workgroups then leave the kernel.
 __device__ bool grid_sync(BatchSync* gs, unsigned nblocks, uint64_t timeout_ticks, int phase,
                           uint64_t& t_prev) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
-        int ab = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (!ab) {
+        if (!__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             const unsigned g = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            const unsigned arrived =
-                __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (arrived == nblocks - 1) {
-                __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&gs->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned grp = blockIdx.x & 7u;
+            unsigned* gc = &gs->group_count[grp * 64];
+            const unsigned members = (nblocks - grp + 7u) / 8u;
+            bool waiter = true;
+            if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+                __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                const unsigned groups = nblocks < 8u ? nblocks : 8u;
+                if (__hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                    groups - 1) {
+                    __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                    __hip_atomic_fetch_add(&gs->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    waiter = false;
+                }
+            }
+            if (waiter) {
                 const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                while (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                     if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
                     if (wall_clock64() - t0 > timeout_ticks) {
                         __hip_atomic_store(&gs->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -62,10 +82,9 @@ __device__ bool grid_sync(BatchSync* gs, unsigned nblocks, uint64_t timeout_tick
                     __builtin_amdgcn_s_sleep(2);
                 }
             }
-            __threadfence();
-            ab = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        s_ok = ab ? 0 : 1;
+        s_ok = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 0 : 1;
         if (blockIdx.x == 0) {   // phase time as seen by one workgroup: its work plus the wait
             const uint64_t t = wall_clock64();
             gs->phase_ticks[phase] += t - t_prev;
@@ -109,7 +128,6 @@ __device__ inline int mode_rows(const BatchInst& B, int m) {
 __device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab) {
     __shared__ int hist[kMaxGroups];
     __shared__ int offs[kMaxGroups];
-    __shared__ int chunk[kBlock];
     __shared__ int wsum[kBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = B.n, c = B.c;
@@ -160,21 +178,32 @@ __device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab) {
         bs += nsg[g];
     }
     __syncthreads();
-    for (int base = 0; base < n; base += kBlock) {
-        const int j = base + tid;
-        const int my = j < n ? lab[j] : -1;
-        chunk[tid] = my;
-        __syncthreads();
-        int rank = 0, later = 0;
-        if (j < n) {
-            for (int t = 0; t < tid; ++t) rank += (chunk[t] == my);
-            for (int t = tid + 1; t < kBlock; ++t) later += (chunk[t] == my);
-            B.perm[offs[my] + rank] = j;
+    // stable scatter by wave 0, 64 columns at a time: the lanes holding the same
+    // label are found with one ballot per label bit; a lane's rank among them is
+    // the count of such lanes below it, and the lowest of them advances the offset.
+    if (wave == 0) {
+        int nbits = 0;
+        while ((1 << nbits) < c) ++nbits;
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        for (int base = 0; base < n; base += 64) {
+            const int j = base + lane;
+            const bool valid = j < n;
+            const int my = valid ? lab[j] : 0;
+            uint64_t same = __ballot(valid);
+            for (int b = 0; b < nbits; ++b) {
+                const bool bit = (my >> b) & 1;
+                const uint64_t m = __ballot(bit);
+                same &= bit ? m : ~m;
+            }
+            const int rank = __popcll(same & below);
+            const int base_off = offs[my];
+            if (valid) {
+                B.perm[base_off + rank] = j;
+                if (rank == 0) offs[my] = base_off + __popcll(same);
+            }
         }
-        __syncthreads();
-        if (j < n && later == 0) offs[my] += rank + 1;   // last of its group in this chunk
-        __syncthreads();
     }
+    __syncthreads();   // the tables are reused by the next instance of this workgroup
 }
 
 // k-means++ draw of seed m (m >= 1) for one instance by one workgroup; see k_pick.
@@ -361,10 +390,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         BatchInst& B = inst[i];
         const int cb = local / B.nrb, rb = local % B.nrb;
         const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
-        const int64_t r0 = (int64_t)rb * kRowsPerBlock;
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wave per column, 4 rows per lane
+        const int64_t r = (int64_t)rb * kBatchRows + lane * 4;
         double a = 0.0, b = 0.0, c = 0.0;
-        for (int64_t j = j0; j < j1; ++j)
-            for (int64_t r = r0 + threadIdx.x * 4; r < r0 + kRowsPerBlock && r < B.dp; r += kBlock * 4) {
+        if (r < B.dp)
+            for (int64_t j = j0 + w; j < j1; j += kBlock / 64) {
                 float v[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[e] = (r + e < B.d) ? B.Xc[j * B.ldx + r + e] : 0.f;
@@ -377,12 +407,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 *reinterpret_cast<float4*>(B.Th + j * B.dp + r) = z;
             }
         if (B.Z && rb == 0)
-            for (int64_t j = j0; j < j1; ++j)
-                for (int64_t r = threadIdx.x * 4; r < B.kdp; r += kBlock * 4) {
+            for (int64_t j = j0 + w; j < j1; j += kBlock / 64)
+                for (int64_t q = lane * 4; q < B.kdp; q += 256) {
                     float v[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = (r + e < B.er) ? B.Ec[j * B.lde + r + e] : 0.f;
-                    *reinterpret_cast<float4*>(B.Z + j * B.kdp + r) = make_float4(v[0], v[1], v[2], v[3]);
+                    for (int e = 0; e < 4; ++e) v[e] = (q + e < B.er) ? B.Ec[j * B.lde + q + e] : 0.f;
+                    *reinterpret_cast<float4*>(B.Z + j * B.kdp + q) = make_float4(v[0], v[1], v[2], v[3]);
                 }
         block_sum3(a, b, c);
         if (threadIdx.x == 0) B.sweep_part[3 * local] = a;
@@ -507,17 +537,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             const int s = local / B.mrb, rb = local % B.mrb;
             if (s >= s_nseg[i]) return;
             const int rows = mode_rows(B, mode);
-            const int64_t r0 = (int64_t)rb * kRowsPerBlock;
+            const int64_t r0 = (int64_t)rb * kBatchRows;
             if (r0 >= rows) return;
             double* out = B.pmeans + (int64_t)s * rows;
             if (mode == M_ITER)
-                group_partial_tile<float, 4, true>(B.X, B.dp, B.S, B.dp, B.Th, B.dp,
-                                                   (float)(1.0 / B.rho), B.dp, B.perm, B.segb[s],
-                                                   B.segl[s], r0, out);
+                group_partial_tile<float, 4, true, kBatchRows, 4>(
+                    B.X, B.dp, B.S, B.dp, B.Th, B.dp, (float)(1.0 / B.rho), B.dp, B.perm, B.segb[s],
+                    B.segl[s], r0, out);
             else
-                group_partial_tile<float, 4, false>(kmeans_matrix(B, mode), rows, nullptr, 0,
-                                                    nullptr, 0, 0.f, rows, B.perm, B.segb[s],
-                                                    B.segl[s], r0, out);
+                group_partial_tile<float, 4, false, kBatchRows, 4>(
+                    kmeans_matrix(B, mode), rows, nullptr, 0, nullptr, 0, 0.f, rows, B.perm,
+                    B.segb[s], B.segl[s], r0, out);
         });
         if (!grid_sync(gs, nb, tmo, BP_MEANS, tclk)) return;
         // C: centroids of the non-empty groups
@@ -549,8 +579,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             const double rho = B.rho;
             const double alpha = rho / (2.0 * B.lambda + rho), beta = (2.0 * B.lambda) / (2.0 * B.lambda + rho);
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            sweep_tile<float, 4>(B.X, B.dp, B.L, B.dp, B.S, B.dp, B.Th, B.dp, B.C, B.lab[B.cur], B.dp,
-                                 j0, j1, (int64_t)rb * kRowsPerBlock, (float)alpha, (float)beta,
+            sweep_tile<float, 4, kBatchRows, 4>(B.X, B.dp, B.L, B.dp, B.S, B.dp, B.Th, B.dp, B.C,
+                                 B.lab[B.cur], B.dp, j0, j1, (int64_t)rb * kBatchRows, (float)alpha, (float)beta,
                                  (float)rho, (float)(1.0 / rho), a0, a1, a2);
             block_sum3(a0, a1, a2);
             if (threadIdx.x == 0) {
@@ -638,10 +668,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         if (B.status < 0) return;
         const int cb = local / B.nrb, rb = local % B.nrb;
         const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
-        const int64_t r0 = (int64_t)rb * kRowsPerBlock;
-        const int64_t r1 = min((int64_t)B.d, r0 + kRowsPerBlock);
-        for (int64_t j = j0; j < j1; ++j)
-            for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
+        const int64_t r0 = (int64_t)rb * kBatchRows;
+        const int64_t r1 = min((int64_t)B.d, r0 + kBatchRows);
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wave per column
+        for (int64_t j = j0 + w; j < j1; j += kBlock / 64)
+            for (int64_t r = r0 + lane; r < r1; r += 64) {
                 B.Lc[j * B.ldl + r] = B.L[j * B.dp + r];
                 B.Sc[j * B.lds + r] = B.S[j * B.dp + r];
             }
@@ -664,6 +695,7 @@ __global__ void k_batched_reset(BatchSync* s, int batch) {
         s->steps = 0;
     }
     if (threadIdx.x < BP_COUNT) s->phase_ticks[threadIdx.x] = 0;
+    for (int t = threadIdx.x; t < 8 * 64; t += blockDim.x) s->group_count[t] = 0u;
 }
 
 }  // namespace

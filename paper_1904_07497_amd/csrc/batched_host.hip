@@ -118,11 +118,11 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.c = r.c;
         B.kpad = (r.c + 15) / 16 * 16;
         B.nkc = (B.kpad + 127) / 128;
-        B.nrb = (B.dp + kRowsPerBlock - 1) / kRowsPerBlock;
+        B.nrb = (B.dp + kBatchRows - 1) / kBatchRows;
         B.er = B.Ec ? r.emb_rows : 0;
         B.kdp = B.Ec ? (B.er + 3) / 4 * 4 : B.dp;
         B.mrows = std::max(B.dp, B.kdp);
-        B.mrb = (B.mrows + kRowsPerBlock - 1) / kRowsPerBlock;
+        B.mrb = (B.mrows + kBatchRows - 1) / kBatchRows;
         B.jc = tune.jc;
         int rows = std::max(32, tune.slice_rows / 32 * 32);
         if (rows > B.mrows) rows = (B.mrows + 31) / 32 * 32;
@@ -405,7 +405,7 @@ respca_status respca_autotune_batched(respca_handle h, const respca_params* para
             if (found) return RESPCA_OK;
         }
     }
-    const int jcs[] = {4, 8, 16};
+    const int jcs[] = {4, 8, 16, 32};
     const int rows_c[] = {512, 1024, 2048};
     const int bpcs[] = {1, 2};
     BatchTune best = h->tune;

@@ -70,35 +70,40 @@ __device__ inline void vstore(T* p, const T (&r)[V]) {
 
 // ------------------------------------------------------------- tile bodies
 
-// The fused ALM sweep over columns [j0, j1) of rows [r0, r0 + kRowsPerBlock).
+// The fused ALM sweep over columns [j0, j1) of rows [r0, r0 + ROWS).  The block's
+// threads form CG column groups of kBlock / CG threads; group g takes columns
+// j0 + g, j0 + g + CG, ... (CG > 1 keeps all lanes busy when d is small).
 // Per entry (i, j) with group p = labels[j]:
 //   D  = X - S + Theta/rho                     (matrix the L-step pulls toward)
 //   L  = alpha D + beta C[:, p]                (Sec. 4.1 closed form, C = group mean of D)
 //   B  = X - L + Theta/rho;  S' = sign(B) max(|B| - 1/rho, 0)      (Sec. 4.3)
 //   Theta' = Theta + rho (X - L - S')                              (Sec. 4.4)
 // and adds this thread's squared norms of X - L - S', L - L_prev, S' - S to a0..a2.
-template <typename T, int V>
+template <typename T, int V, int ROWS = kRowsPerBlock, int CG = 1>
 __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __restrict__ L,
                                   int64_t ldl, T* __restrict__ S, int64_t lds, T* __restrict__ Th,
                                   int64_t ldt, const T* __restrict__ C,
                                   const int32_t* __restrict__ labels, int64_t d, int64_t j0,
                                   int64_t j1, int64_t r0, T alpha, T beta, T rho, T inv_rho,
                                   double& a0, double& a1, double& a2) {
-    constexpr int NS = kRowsPerBlock / (kBlock * V);
+    constexpr int TPC = kBlock / CG;   // threads per column group
+    constexpr int NS = ROWS / (TPC * V);
+    static_assert(NS >= 1 && NS * TPC * V == ROWS, "row block must tile the column group");
     constexpr int U = 2;   // columns in flight per thread (columns are independent)
-    for (int64_t jb = j0; jb < j1; jb += U) {
+    const int cg = (int)threadIdx.x / TPC, tl = (int)threadIdx.x % TPC;
+    for (int64_t jb = j0 + cg; jb < j1; jb += (int64_t)U * CG) {
         int64_t pp[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) pp[u] = (jb + u < j1) ? labels[jb + u] : 0;
+        for (int u = 0; u < U; ++u) pp[u] = (jb + u * CG < j1) ? labels[jb + u * CG] : 0;
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
-            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
             if (i >= d) continue;
             T xs[U][V], ss[U][V], ts[U][V], lps[U][V], ms[U][V];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (jb + u >= j1) continue;
-                const int64_t j = jb + u;
+                if (jb + u * CG >= j1) continue;
+                const int64_t j = jb + u * CG;
                 vload<T, V>(X + j * ldx + i, xs[u]);
                 vload<T, V>(S + j * lds + i, ss[u]);
                 vload<T, V>(Th + j * ldt + i, ts[u]);
@@ -107,8 +112,8 @@ __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __res
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-            if (jb + u >= j1) continue;
-            const int64_t j = jb + u;
+            if (jb + u * CG >= j1) continue;
+            const int64_t j = jb + u * CG;
             const T (&x)[V] = xs[u];
             const T (&s)[V] = ss[u];
             const T (&t)[V] = ts[u];
@@ -138,17 +143,30 @@ __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __res
     }
 }
 
+// LDS buffer for the column groups' partial sums below, shared by every
+// instantiation (one allocation per kernel).
+constexpr int kGroupRedDoubles = 1024;
+__device__ inline double* group_red_lds() {
+    __shared__ double red[kGroupRedDoubles];
+    return red;
+}
+
 // Sum over the `len` columns perm[begin..begin+len) (one group segment) of
-// Y = X - S + Theta*inv_rho (WITH_D) or Y = A, rows [r0, r0 + kRowsPerBlock),
-// in double, written to out[i] (out points at this segment's d-vector).
-template <typename T, int V, bool WITH_D>
+// Y = X - S + Theta*inv_rho (WITH_D) or Y = A, rows [r0, r0 + ROWS), in double,
+// written to out[i] (out points at this segment's d-vector).  With CG column
+// groups, group g sums the segment's columns g, g + CG, ... and the CG partial
+// sums are added in group order at the end; the order of every sum is fixed.
+template <typename T, int V, bool WITH_D, int ROWS = kRowsPerBlock, int CG = 1>
 __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
                                           const T* __restrict__ S, int64_t lds,
                                           const T* __restrict__ Th, int64_t ldt, T inv_rho,
                                           int64_t d, const int32_t* __restrict__ perm, int begin,
                                           int len, int64_t r0, double* __restrict__ out) {
-    constexpr int NS = kRowsPerBlock / (kBlock * V);
+    constexpr int TPC = kBlock / CG;
+    constexpr int NS = ROWS / (TPC * V);
+    static_assert(NS >= 1 && NS * TPC * V == ROWS, "row block must tile the column group");
     constexpr int U = 4;   // columns in flight per thread; the summation order is unchanged
+    const int cg = (int)threadIdx.x / TPC, tl = (int)threadIdx.x % TPC;
     double acc[NS][V];
 #pragma unroll
     for (int a = 0; a < NS; ++a)
@@ -164,14 +182,14 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
             for (int v = 0; v < V; ++v) x[v] = x[v] - sv[v] + tv[v] * inv_rho;
         }
     };
-    int q = 0;
-    for (; q + U <= len; q += U) {
+    int q = cg;
+    for (; q + (U - 1) * CG < len; q += U * CG) {
         int64_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = perm[begin + q + u];
+        for (int u = 0; u < U; ++u) jj[u] = perm[begin + q + u * CG];
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
-            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
             if (i < d) {
                 T x[U][V];
 #pragma unroll
@@ -183,11 +201,11 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
             }
         }
     }
-    for (; q < len; ++q) {
+    for (; q < len; q += CG) {
         const int64_t j = perm[begin + q];
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
-            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
             if (i < d) {
                 T x[V];
                 value(j, i, x);
@@ -196,12 +214,31 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
             }
         }
     }
+    if constexpr (CG == 1) {
 #pragma unroll
-    for (int a = 0; a < NS; ++a) {
-        const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
-        if (i < d)
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
+            if (i < d)
 #pragma unroll
-            for (int v = 0; v < V; ++v) out[i + v] = acc[a][v];
+                for (int v = 0; v < V; ++v) out[i + v] = acc[a][v];
+        }
+    } else {
+        static_assert(CG * ROWS <= kGroupRedDoubles, "partial-sum buffer too small");
+        double* red = group_red_lds();
+#pragma unroll
+        for (int a = 0; a < NS; ++a)
+#pragma unroll
+            for (int v = 0; v < V; ++v) red[cg * ROWS + (a * TPC + tl) * V + v] = acc[a][v];
+        __syncthreads();
+        for (int e = threadIdx.x; e < ROWS; e += kBlock) {
+            if (r0 + e < d) {
+                double t = red[e];
+#pragma unroll
+                for (int g = 1; g < CG; ++g) t += red[g * ROWS + e];
+                out[r0 + e] = t;
+            }
+        }
+        __syncthreads();   // red is reused by the next call
     }
 }
 
