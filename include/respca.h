@@ -72,9 +72,12 @@ typedef struct {
                              relative criterion terms (primal, dL, dS); NULL = none        */
     const void *init_embedding; /* optional device FP32 matrix, init_embedding_rows x n with
                              leading dimension init_embedding_ld: its columns are clustered
-                             (k-means++ from seed, then Lloyd) instead of the columns of X
-                             to obtain the initial groups; the iterations then start as
-                             with init_labels.  Ignored when init_labels is set; not for
+                             (k-means++ from seed, then Lloyd) in place of the seeding on X;
+                             from the means of X over those groups (empty groups at zero)
+                             Lloyd then runs on the columns of X (same rule as the p-step,
+                             at most max_lloyd passes), and the iterations start as with
+                             init_labels from the resulting groups.  info.init_lloyd counts
+                             the passes of both.  Ignored when init_labels is set; not for
                              RESPCA_F64.  NULL = none                                       */
     int64_t  init_embedding_ld;
     int32_t  init_embedding_rows;

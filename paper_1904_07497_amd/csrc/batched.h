@@ -52,7 +52,7 @@ struct BatchInst {
     double lambda, tol, rho0, kappa, rho_max;
     int max_iter, max_lloyd;
     // state
-    int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, status, nseg;
+    int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, ref_lloyd, status, nseg;
     double rho, nx, rho_final, primal, dL, dS;
 };
 

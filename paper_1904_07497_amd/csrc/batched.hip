@@ -33,7 +33,11 @@ namespace respca {
 
 namespace {
 
-enum Mode : int { M_DONE = 0, M_SEED = 1, M_MEANSX = 2, M_KMX = 3, M_ITER = 4, M_LL = 5 };
+// M_SEED / M_KMX: k-means++ and Lloyd on X, or on the embedding when given one;
+// M_MEANSX: centroids = means of X over given groups (empty groups at zero);
+// M_REFX: Lloyd on X from the embedding's groups; M_ITER: an outer iteration with
+// its first Lloyd pass on L; M_LL: further Lloyd passes on L.
+enum Mode : int { M_DONE = 0, M_SEED = 1, M_MEANSX = 2, M_KMX = 3, M_ITER = 4, M_LL = 5, M_REFX = 6 };
 
 // ---------------------------------------------------------------- barrier
 
@@ -107,14 +111,18 @@ __device__ inline int find_inst(const int32_t* __restrict__ off, int batch, int 
     return lo;
 }
 
-__device__ inline bool needs_groups(int m) { return m == M_MEANSX || m == M_KMX || m == M_ITER || m == M_LL; }
-__device__ inline bool needs_assign(int m) { return m == M_SEED || m == M_KMX || m == M_ITER || m == M_LL; }
+__device__ inline bool needs_groups(int m) {
+    return m == M_MEANSX || m == M_KMX || m == M_ITER || m == M_LL || m == M_REFX;
+}
+__device__ inline bool needs_assign(int m) {
+    return m == M_SEED || m == M_KMX || m == M_ITER || m == M_LL || m == M_REFX;
+}
 
 // Matrix whose columns the current mode clusters, and its row count (= its
 // leading dimension and that of the centroids).
 __device__ inline const float* kmeans_matrix(const BatchInst& B, int m) {
     if (m == M_ITER || m == M_LL) return B.L;
-    if (m == M_MEANSX) return B.X;
+    if (m == M_MEANSX || m == M_REFX) return B.X;
     return B.Z ? B.Z : B.X;
 }
 __device__ inline int mode_rows(const BatchInst& B, int m) {
@@ -289,7 +297,10 @@ __device__ void control_instance(BatchInst& B, int* active) {
     block_sum3(a0, a1, a2);
     if (threadIdx.x != 0) return;
     const int mode = mode0;
-    if (mode == M_MEANSX) { B.mode = M_ITER; return; }
+    if (mode == M_MEANSX) {   // embedding groups: Lloyd on X next, once; then the iterations
+        if (B.Z && B.ref_lloyd == 0) { B.mode = M_REFX; } else { B.mode = M_ITER; }
+        return;
+    }
     const int changed = (int)ch;
     if (mode == M_SEED) { B.cur ^= 1; B.mode = M_KMX; return; }
     if (mode == M_KMX) {
@@ -300,6 +311,13 @@ __device__ void control_instance(BatchInst& B, int* active) {
         } else {
             B.cur ^= 1;
         }
+        return;
+    }
+    if (mode == M_REFX) {
+        B.init_lloyd += 1;
+        B.ref_lloyd += 1;
+        if (changed) B.cur ^= 1;
+        if (changed == 0 || B.ref_lloyd >= B.max_lloyd) B.mode = M_MEANSX;   // means over the final groups
         return;
     }
     if (mode == M_ITER) {
@@ -429,7 +447,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         if (threadIdx.x == 0) {
             B.nx = sqrt(nx2);
             B.cur = 0;
-            B.iters = B.lloyd_total = B.lloyd_iter = B.init_lloyd = 0;
+            B.iters = B.lloyd_total = B.lloyd_iter = B.init_lloyd = B.ref_lloyd = 0;
             B.rho = B.rho0;
             B.rho_final = 0.0;
             B.primal = B.dL = B.dS = 0.0;

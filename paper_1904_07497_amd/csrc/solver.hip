@@ -339,9 +339,16 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
         int steps = 0;
         CKS(kmeans_f32(h, r.emb_rows, n, r.c, r.init_embedding, r.emb_ld, r.seed, r.max_lloyd,
                        (int32_t*)h->embl.p, (float*)h->embc.p, st, &steps));
-        info->init_lloyd = steps;
         CKS(e.setup());
         CK(hipMemcpyAsync(cur, h->embl.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        // Lloyd on the columns of X from the means of X over those groups (empty at zero)
+        launch_zero2d<T>(C, d, d, r.c, st);
+        e.sort(cur);
+        e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C);
+        int ref = 0;
+        CKS(e.lloyd(X, ldx, C, cur, alt, r.max_lloyd, ref, nullptr));
+        info->init_lloyd = steps + ref;
+        // then as with given initial labels
         launch_zero2d<T>(C, d, d, r.c, st);
         e.sort(cur);
         e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C);

@@ -14,10 +14,14 @@ calls and moves tensors.  For every column the network predicts
   columns gives the instance's rho0 (larger rho0 = fewer of the schedule's
   geometric steps, each a factor kappa).
 
-rho0* of a training instance is the largest value on the grid 1e-4 * 2.25^k
+rho0* of a training instance is the largest value on the grid 1e-4 * 1.5^k
 whose run, started from the cold run's groups, still converges to the same
 error against the planted L as the cold run (within 1 %).  The solver stays
 the judge: whatever the network predicts, the iterations run to tolerance.
+
+At inference the predicted sketches are clustered (64 coordinates instead of d),
+Lloyd on X refines those groups, and the iterations start from them with the
+predicted rho0 (the init_embedding path of the solvers).
 
 Instances follow the batched size mix: d, n log-uniform in [200, 4000], rank
 uniform in 5..50, X = U V^T + S0 with U, V iid N(0, 1) and a fraction uniform in
@@ -40,7 +44,7 @@ HIDDEN = 256
 SKETCH_SEED = 0x5EED5EED
 TRAIN_BASE, HELDOUT_BASE = 4_000_000, 5_000_000
 COLD_RHO0 = 1e-4
-GRID_STEP = 1.5 ** 2
+GRID_STEP = 1.5
 TOL = 1e-6
 
 

@@ -561,15 +561,23 @@ def _embedding_cases():
     return cases
 
 
+def _refine_on_x(X, lab, c, max_lloyd=100):
+    """Groups of an embedding refined on X: Lloyd from the means of X over them."""
+    C0, _ = oracle.group_means(X, lab, c)
+    lab2, _, steps = oracle.lloyd(X, C0, lab, max_lloyd)
+    return lab2, steps
+
+
 def _oracle_from_embedding(X, E, c, lam, seed, **kw):
     lab, _, steps = oracle.kmeans(E, c, seed, 100)
-    o = oracle.solve(X, oracle.make_params(c, lam=lam, seed=seed, **kw), init_labels=lab)
-    return o, steps
+    lab2, ref = _refine_on_x(X, lab, c)
+    o = oracle.solve(X, oracle.make_params(c, lam=lam, seed=seed, **kw), init_labels=lab2)
+    return o, steps + ref
 
 
 def test_init_embedding_single_solve_matches_oracle():
-    """Groups from K-means of an embedding's columns, then the iterations from the
-    means of X over them: identical to the oracle given the embedding's labels."""
+    """Groups from K-means of an embedding's columns, refined by Lloyd on X, then the
+    iterations: identical to the oracle's chain from the same embedding."""
     for i, (X, E, Ed, c, lam) in enumerate(_embedding_cases()):
         o, steps = _oracle_from_embedding(X, E, c, lam, seed=i + 3, tol=1e-6)
         g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=o["info"]["iters"], seed=i + 3,
@@ -669,8 +677,9 @@ def test_warm_started_batched_solve_matches_oracle_chain():
         rho0_o = float(np.exp(yo[:, 64].mean()) / s)
         assert r0 == pytest.approx(rho0_o, rel=1e-4)
         lab, _, steps = oracle.kmeans(np.asfortranarray(yo[:, :64].T), c, 0, 100)
-        o = oracle.solve(X, oracle.make_params(c, lam=0.5, tol=1e-6, rho0=rho0_o), init_labels=lab)
-        o["emb_steps"] = steps
+        lab2, ref = _refine_on_x(X, lab, c)
+        o = oracle.solve(X, oracle.make_params(c, lam=0.5, tol=1e-6, rho0=rho0_o), init_labels=lab2)
+        o["emb_steps"] = steps + ref
         T.append(o)
     plist, keep = rp.batch_params([s[2] for s in shapes], [0.5, 0.5], tol=0.0, max_iter=0, rho0=rho0s,
                                   init_embeddings=views)
