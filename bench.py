@@ -2,7 +2,8 @@
 CPU checker timed beside it.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload large]
-                    [--no-cpu-baseline]
+                    [--precision bf16|fp32] [--no-compare] [--no-cpu-baseline]
+                    [--tune-cache FILE] [--calibrate-copy]
 
 A step is one whole RES-PCA solve (initial K-means of X, then outer ALM
 iterations L -> p -> S -> Theta/rho until the Sec. 5 criterion <= tol) of
@@ -44,6 +45,11 @@ WORKLOADS = {
                          "uniform in 5..50, 1-20% sparse in [-50,50], c=rank, lambda=1/sqrt(max(d,n)), "
                          "tol=1e-6; one persistent launch replayed from a hipGraph", batch=256,
                     tol=1e-6, gen="batched"),
+    "warmstart": dict(name="learned warm start vs cold start, RES-PCA FP32: 1024 held-out instances "
+                           "of the batched size mix (d, n log-uniform in [200, 4000], rank 5..50, "
+                           "1-20% sparse in [-50,50]) drawn on the device, c=rank, "
+                           "lambda=1/sqrt(max(d,n)), tol=1e-6; launches of 256 instances, network "
+                           "pass included", instances=1024, chunk=256, tol=1e-6, gen="warmstart"),
     "video": dict(name="RES-PCA FP32 synthetic 240x320x2000 clip (rank-5 background, 4 moving 20x20 "
                        "squares, 8-bit scale), c=5, lambda=sqrt(76800), tol=1e-6", d=76800, n=2000,
                   rank=5, lam=None, tol=1e-6, gen="video"),
@@ -51,10 +57,15 @@ WORKLOADS = {
 
 
 def kernel_source_sha() -> str:
+    """Hash of every kernel source file (a counter summary is used only if taken on
+    exactly this source)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h", "distance.hip"):
-        with open(os.path.join(ROOT, "paper_1904_07497_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    src = os.path.join(ROOT, "paper_1904_07497_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(src, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -119,12 +130,62 @@ def cpu_baseline(X, wl, gpu_info):
             "sample": sample}
 
 
+def batched_cpu_baseline(Xh_median, c_median, lam_median, shapes, ranks, infos, count):
+    """FP64 oracle on the median instance, scaled per instance by its size and the
+    GPU run's pass counts; returns the cpu_baseline object for `count` solves."""
+    import numpy as np
+    import oracle
+    X64 = np.asfortranarray(Xh_median.astype(np.float64))
+    d, n = X64.shape
+    c = c_median
+    rng = np.random.default_rng(0)
+    st = {"L": np.zeros((d, n), order="F"), "S": np.zeros((d, n), order="F"),
+          "Theta": np.zeros((d, n), order="F"), "labels": rng.integers(0, c, n).astype(np.int32),
+          "C": np.zeros((d, c), order="F"), "rho": 1e-4}
+    t = time.perf_counter(); o = oracle.step(oracle.make_params(c, lam=lam_median, max_lloyd=1), X64, st)
+    t_step = time.perf_counter() - t
+    t = time.perf_counter(); lab = oracle.assign(o["L"], o["C"]); t_assign = time.perf_counter() - t
+    t = time.perf_counter(); oracle.group_means(o["L"], lab, c); t_mean = time.perf_counter() - t
+    t = time.perf_counter(); oracle.kmeanspp(X64, 2, 0); t_d2 = (time.perf_counter() - t) / 2
+    base = t_step - t_assign
+    total = 0.0
+    for (di, ni), ci, f in zip(shapes, ranks, infos):
+        sz = di * ni / (d * n)
+        ta = t_assign * sz * ci / c
+        tm, tb, td = t_mean * sz, base * sz, t_d2 * sz
+        total += (ci * td + (f["init_lloyd"] + 1) * (ta + tm) + f["iters"] * (tb + ta)
+                  + (f["lloyd_steps"] - f["iters"]) * (ta + tm))
+    return {"value": count / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle on the median instance ({d}x{n}, c={c}): one outer iteration "
+                       f"{t_step:.3f} s, one assignment pass {t_assign:.3f} s, one centroid pass "
+                       f"{t_mean:.4f} s, one k-means++ distance pass {t_d2:.4f} s; every instance's "
+                       f"solve time = these costs scaled by its d*n (and c for assignments) times the "
+                       f"pass counts of its cold GPU solve (seeding, initial Lloyd, iterations, Lloyd); "
+                       f"total {total:.1f} s for {count} solves")}
+
+
+def batched_roofline(prof, workload):
+    nl = max(prof["launches"], 1)
+    secs = prof["ms"] / 1e3 / nl
+    bpl = prof["bytes"] / nl
+    ach = bpl / secs / 1e9 if secs > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic("batched", workload),
+            "kernel": "batched (persistent launch)", "bytes_per_launch": bpl,
+            "mean_launch_ms": round(secs * 1e3, 3)}
+
+
+def tune(rp, Xs, plist, outs, cache):
+    t = time.perf_counter()
+    ms = rp.autotune_batched(Xs, plist, cache_path=cache, outs=outs)
+    return ms, time.perf_counter() - t
+
+
 def bench_batched(args, wl):
     """256 uneven instances per step, one persistent launch (graph replay)."""
     import numpy as np
     import torch
 
-    import oracle
     from paper_1904_07497_amd import respca as rp
     from paper_1904_07497_amd import synth
 
@@ -139,9 +200,7 @@ def bench_batched(args, wl):
     outs = [(rp.empty_colmajor(x.shape[0], x.shape[1], x.dtype, x.device),
              rp.empty_colmajor(x.shape[0], x.shape[1], x.dtype, x.device),
              torch.empty(x.shape[1], dtype=torch.int32, device=x.device)) for x in Xs]
-    t = time.perf_counter()
-    tuned_ms = rp.autotune_batched(Xs, plist, outs=outs)
-    tune_s = time.perf_counter() - t
+    tuned_ms, tune_s = tune(rp, Xs, plist, outs, args.tune_cache)
     for _ in range(max(args.warmup, 1)):
         _, infos, _ = rp.solve_batched(Xs, plist, outs=outs)
     torch.cuda.synchronize()
@@ -155,10 +214,6 @@ def bench_batched(args, wl):
     rp.profile_enable(False)
     phases = rp.batched_phases()
     elapsed = t1 - t0
-    nl = max(prof["launches"], 1)
-    secs = prof["ms"] / 1e3 / nl
-    bpl = prof["bytes"] / nl
-    ach = bpl / secs / 1e9 if secs > 0 else 0.0
     iters = [f["iters"] for f in infos]
     line = {
         "metric": "RPCA solves/s + sweep HBM GB/s at rel-err<=1e-5 (BF16/learned vs plain FP32)",
@@ -178,44 +233,136 @@ def bench_batched(args, wl):
                    "iters_min_median_max": [min(iters), int(np.median(iters)), max(iters)],
                    "all_converged": all(f["status"] == 0 for f in infos),
                    "tuner_seconds": round(tune_s, 2), "tuned_launch_ms": round(tuned_ms, 3)},
-        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic("batched", "batched"),
-                     "kernel": "batched (persistent launch)", "bytes_per_launch": bpl,
-                     "mean_launch_ms": round(secs * 1e3, 3)},
+        "roofline": batched_roofline(prof, "batched"),
         "phases_ms": phases,
     }
     if not args.no_cpu_baseline:
-        # oracle on the median-size instance, scaled per instance by its size and pass counts
         dn = [x.shape[0] * x.shape[1] for x in Xh]
         im = int(np.argsort(dn)[len(dn) // 2])
-        X64 = np.asfortranarray(Xh[im].astype(np.float64))
-        d, n = X64.shape
-        c = ranks[im]
-        rng = np.random.default_rng(0)
-        st = {"L": np.zeros((d, n), order="F"), "S": np.zeros((d, n), order="F"),
-              "Theta": np.zeros((d, n), order="F"), "labels": rng.integers(0, c, n).astype(np.int32),
-              "C": np.zeros((d, c), order="F"), "rho": 1e-4}
-        t = time.perf_counter(); o = oracle.step(oracle.make_params(c, lam=lams[im], max_lloyd=1), X64, st)
-        t_step = time.perf_counter() - t
-        t = time.perf_counter(); lab = oracle.assign(o["L"], o["C"]); t_assign = time.perf_counter() - t
-        t = time.perf_counter(); oracle.group_means(o["L"], lab, c); t_mean = time.perf_counter() - t
-        t = time.perf_counter(); oracle.kmeanspp(X64, 2, 0); t_d2 = (time.perf_counter() - t) / 2
-        base = t_step - t_assign
-        total = 0.0
-        for i, f in enumerate(infos):
-            sz = dn[i] / (d * n)
-            ta = t_assign * sz * ranks[i] / c
-            tm, tb, td = t_mean * sz, base * sz, t_d2 * sz
-            total += (ranks[i] * td + (f["init_lloyd"] + 1) * (ta + tm) + f["iters"] * (tb + ta)
-                      + (f["lloyd_steps"] - f["iters"]) * (ta + tm))
-        line["cpu_baseline"] = {
-            "value": wl["batch"] / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 oracle on the median instance ({d}x{n}, c={c}): one outer iteration "
-                       f"{t_step:.3f} s, one assignment pass {t_assign:.3f} s, one centroid pass "
-                       f"{t_mean:.4f} s, one k-means++ distance pass {t_d2:.4f} s; every instance's "
-                       f"solve time = these costs scaled by its d*n (and c for assignments) times its "
-                       f"GPU pass counts; batch total {total:.1f} s")}
+        line["cpu_baseline"] = batched_cpu_baseline(Xh[im], ranks[im], lams[im],
+                                                    [x.shape for x in Xh], ranks, infos, wl["batch"])
     print(json.dumps(line), flush=True)
+
+
+def bench_warmstart(args, wl):
+    """Held-out instances solved from the learned warm start (network pass, then
+    the batched solver from the predicted groups and rho0) against the cold start
+    on the same instances; a step is one pass over all of them."""
+    import numpy as np
+    import torch
+
+    from paper_1904_07497_amd import respca as rp
+    from paper_1904_07497_amd import warmstart as ws
+
+    P, hidden, sseed = ws.load_model()
+    inst = [ws.make_instance(ws.HELDOUT_BASE + i) for i in range(wl["instances"])]
+    chunk = wl["chunk"]
+    chunks = []
+    for c0 in range(0, len(inst), chunk):
+        part = inst[c0:c0 + chunk]
+        Xs = [x for x, _, _ in part]
+        ranks = [m[2] for _, _, m in part]
+        lams = [ws.lam_of(*x.shape) for x in Xs]
+        outs = [(rp.empty_colmajor(x.shape[0], x.shape[1], x.dtype, x.device),
+                 rp.empty_colmajor(x.shape[0], x.shape[1], x.dtype, x.device),
+                 torch.empty(x.shape[1], dtype=torch.int32, device=x.device)) for x in Xs]
+        chunks.append((Xs, ranks, lams, outs))
+    cold_p = [rp.batch_params(r, l, tol=wl["tol"])[0] for _, r, l, _ in chunks]
+    tuned_ms, tune_s = tune(rp, chunks[0][0], cold_p[0], chunks[0][3], args.tune_cache)
+
+    def warm_pass():
+        infos, keep = [], []
+        for Xs, ranks, lams, outs in chunks:
+            emb, rho0s, fbs = rp.warmstart_batched(Xs, ranks, P, hidden, sseed)
+            plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s, init_embeddings=emb)
+            infos += rp.solve_batched(Xs, plist, outs=outs)[1]
+            keep.append((emb, k, fbs))
+        return infos, keep
+
+    def cold_pass():
+        infos = []
+        for (Xs, _, _, outs), plist in zip(chunks, cold_p):
+            infos += rp.solve_batched(Xs, plist, outs=outs)[1]
+        return infos
+
+    def errors():
+        out = []
+        for ci, (_, _, _, outs) in enumerate(chunks):
+            for k, o in enumerate(outs):
+                out.append(ws.rel_err(o[0], inst[ci * chunk + k][1]))
+        return out
+
+    for _ in range(max(args.warmup, 1)):
+        cold_pass()
+        warm_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cold = cold_pass()
+    torch.cuda.synchronize()
+    cold_s = time.perf_counter() - t0
+    cold_err = errors()
+    rp.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        warm, keep = warm_pass()
+    torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t0
+    prof = rp.profile_query()["batched"]
+    rp.profile_enable(False)
+    warm_err = errors()
+    fallbacks = sum(sum(k[2]) for k in keep)
+    ratio = np.array(warm_err) / np.array(cold_err)
+    count = len(inst)
+    line = {
+        "metric": "RPCA solves/s + sweep HBM GB/s at rel-err<=1e-5 (BF16/learned vs plain FP32)",
+        "value": round(count * args.steps / warm_s, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(args.warmup, 1),
+        "ms_per_step": round(1e3 * warm_s / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "instances": count, "per_launch": chunk,
+                   "model": f"MLP 68-{hidden}-{hidden}-{hidden}-65 (stored weights)",
+                   "warm_iters_mean": round(float(np.mean([f["iters"] for f in warm])), 3),
+                   "cold_iters_mean": round(float(np.mean([f["iters"] for f in cold])), 3),
+                   "warm_converged": sum(f["status"] == 0 for f in warm),
+                   "cold_converged": sum(f["status"] == 0 for f in cold),
+                   "fallbacks": int(fallbacks),
+                   "err_vs_planted_ratio_warm_over_cold": {
+                       "median": round(float(np.median(ratio)), 5), "max": round(float(ratio.max()), 5)},
+                   "tuner_seconds": round(tune_s, 2)},
+        "cold_solves_per_s": round(count * args.steps / cold_s, 2),
+        "speedup_vs_cold": round(cold_s / warm_s, 4),
+        "roofline": batched_roofline(prof, "warmstart"),
+    }
+    if not args.no_cpu_baseline:
+        shapes = [tuple(x.shape) for x, _, _ in inst]
+        ranks = [m[2] for _, _, m in inst]
+        dn = [a * b for a, b in shapes]
+        im = int(np.argsort(dn)[len(dn) // 2])
+        line["cpu_baseline"] = batched_cpu_baseline(inst[im][0].cpu().numpy(), ranks[im],
+                                                    ws.lam_of(*shapes[im]), shapes, ranks, cold, count)
+    print(json.dumps(line), flush=True)
+
+
+def calibrate_copy(args):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters: prints the bytes each launch reads and writes."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(max(args.steps, 1)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                      "launches": max(args.steps, 1)}), flush=True)
 
 
 def main():
@@ -229,6 +376,10 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the other precision in the same run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="batched tile-shape cache file (read if it holds the shape bucket, else written)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
@@ -240,9 +391,15 @@ def main():
 
     from paper_1904_07497_amd import respca as rp
 
+    if args.calibrate_copy:
+        calibrate_copy(args)
+        return
     wl = WORKLOADS[args.workload]
     if wl["gen"] == "batched":
         bench_batched(args, wl)
+        return
+    if wl["gen"] == "warmstart":
+        bench_warmstart(args, wl)
         return
     X = make_input(wl, np.float32)
     Xd = torch.from_numpy(X).to("cuda:0")

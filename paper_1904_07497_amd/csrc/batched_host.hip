@@ -315,13 +315,20 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     double alg_bytes = 0.0;
     for (int i = 0; i < batch; ++i) {
         const BatchInst& B = out[i];
-        if (B.status >= 0 && B.nx > 0.0)
-            // ||X|| pass; seeding (c passes) + nearest-seed assignment, or the means of X
-            // for a warm start; 2 per Lloyd pass on X; 3 + 7 + 1 per outer iteration
-            // (means of D, sweep, assignment); 2 per extra Lloyd pass on L
-            alg_bytes += (double)B.d * B.n * sizeof(float) *
-                         (1.0 + (call.inst[i].init_labels ? 1.0 : (double)B.c + 1.0) +
-                          2.0 * B.init_lloyd + 11.0 * B.iters + 2.0 * (B.lloyd_total - B.iters));
+        if (B.status >= 0 && B.nx > 0.0) {
+            // passes over X: ||X||; 3 + 7 + 1 per outer iteration (means of D, sweep,
+            // assignment); 2 per extra Lloyd pass on L; and the start: the means of X for
+            // given labels, seeding (c passes) + nearest-seed assignment + 2 per Lloyd
+            // pass for a cold start, or for an embedding 2 per Lloyd pass on X plus two
+            // means of X, with its seeding and Lloyd passes counted on the embedding
+            double px = 1.0 + 11.0 * B.iters + 2.0 * (B.lloyd_total - B.iters), pz = 0.0;
+            if (call.inst[i].init_labels) px += 1.0;
+            else if (B.Z) {
+                px += 2.0 + 2.0 * B.ref_lloyd;
+                pz = (double)B.c + 1.0 + 2.0 * (B.init_lloyd - B.ref_lloyd);
+            } else px += (double)B.c + 1.0 + 2.0 * B.init_lloyd;
+            alg_bytes += (double)B.n * sizeof(float) * ((double)B.d * px + (double)B.er * pz);
+        }
         if (info) {
             respca_info& f = info[i];
             std::memset(&f, 0, sizeof(f));
