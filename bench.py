@@ -56,28 +56,36 @@ WORKLOADS = {
 }
 
 
-def kernel_source_sha() -> str:
-    """Hash of every kernel source file (a counter summary is used only if taken on
-    exactly this source)."""
+# source files whose kernels make up each profiled unit
+KERNEL_SOURCES = {
+    "sweep": ("kernels.hip", "kernels.h", "device_common.h"),
+    "means": ("kernels.hip", "kernels.h", "device_common.h"),
+    "seeding": ("kernels.hip", "kernels.h", "device_common.h"),
+    "distance": ("distance.hip", "dist_tile.h", "kernels.hip", "kernels.h", "device_common.h"),
+    "batched": ("batched.hip", "batched.h", "dist_tile.h", "device_common.h", "kernels.h"),
+}
+
+
+def kernel_source_sha(kernel: str) -> str:
+    """Hash of the source files of one profiled unit (a counter summary is used only
+    if it was taken on exactly this source)."""
     h = hashlib.sha256()
-    src = os.path.join(ROOT, "paper_1904_07497_amd", "csrc")
-    for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(src, f), "rb") as fh:
-                h.update(f.encode())
-                h.update(fh.read())
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1904_07497_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel: str, workload: str):
-    """Per-launch HBM bytes (fetch + write, scaled by the copy-kernel factor)
+    """Per-launch HBM bytes (fetch + write, each scaled by the copy-kernel factor)
     from the committed counter summary, only if taken on the current source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha") != kernel_source_sha():
+    if rec.get("kernel_source_sha") != kernel_source_sha(kernel):
         return None
     return rec.get("bytes_per_launch")
 
