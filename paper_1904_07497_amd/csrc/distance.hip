@@ -181,6 +181,102 @@ __global__ __launch_bounds__(256) void k_dist_argmin_bounded(
     if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// Same decisions as k_dist_argmin_bounded for c <= 16 T, in one pass over the
+// partial dot products: a lane keeps the distances and bounds of its T groups in
+// registers (the slices are summed in the same order, so every value is
+// bitwise the same).
+template <int T>
+__global__ __launch_bounds__(256) void k_dist_argmin_bounded_r(
+    const float* __restrict__ part, const float* __restrict__ ynorm_part, int nslices, int64_t n,
+    int c, int kpad, float eps_rel, const double* __restrict__ cnorm,
+    const int32_t* __restrict__ old_labels, int32_t* __restrict__ new_labels,
+    double* __restrict__ changed_partial, int* __restrict__ counters, int32_t* __restrict__ list,
+    int32_t* __restrict__ cand) {
+    __shared__ double sh[4];
+    const int q = threadIdx.x & 15;
+    const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = j < n;
+    double ynorm = 0.0;
+    double dot[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) dot[t] = 0.0;
+    if (live)
+        for (int s = 0; s < nslices; ++s) {
+            const float* p = part + ((int64_t)s * n + j) * kpad;
+            float v[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) v[t] = (q + 16 * t < c) ? p[q + 16 * t] : 0.f;
+#pragma unroll
+            for (int t = 0; t < T; ++t) dot[t] += (double)v[t];
+            ynorm += (double)ynorm_part[(int64_t)s * n + j];
+        }
+    const double ylen = sqrt(ynorm);
+    double dist[T], err[T];
+    double bestd = INFINITY, upper = INFINITY;
+    int bestk = INT_MAX;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int k = q + 16 * t;
+        dist[t] = INFINITY;
+        err[t] = 0.0;
+        if (live && k < c) {
+            const double cn = cnorm[k];
+            dist[t] = cn - 2.0 * dot[t];
+            err[t] = 2.0 * eps_rel * sqrt(cn) * ylen;
+            if (dist[t] < bestd) { bestd = dist[t]; bestk = k; }
+            upper = fmin(upper, dist[t] + err[t]);
+        }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        const double od = __shfl_xor(bestd, o, 16);
+        const int ok = __shfl_xor(bestk, o, 16);
+        if (od < bestd || (od == bestd && ok < bestk)) { bestd = od; bestk = ok; }
+        upper = fmin(upper, __shfl_xor(upper, o, 16));
+    }
+    unsigned mine = 0;   // bit t: group q + 16 t is a candidate
+    int ncand = 0;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+        if (live && q + 16 * t < c && dist[t] - err[t] <= upper) { ++ncand; mine |= 1u << t; }
+    int total = ncand;
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) total += __shfl_xor(total, o, 16);
+    double changed = 0.0;
+    const int lab = bestk == INT_MAX ? 0 : bestk;
+    if (live && total <= 1) {
+        if (q == 0) {
+            new_labels[j] = lab;
+            changed = old_labels[j] != lab ? 1.0 : 0.0;
+        }
+    } else if (live) {
+        int slot = 0;
+        if (q == 0) slot = atomicAdd(&counters[0], 1);
+        slot = __shfl(slot, (threadIdx.x & 63) & ~15);
+        if (q == 0) { list[slot] = (int32_t)j; new_labels[j] = lab; }
+        int32_t* cj = cand + (int64_t)j * kMaxCand;
+        if (total > kMaxCand) {
+            if (q == 0) cj[0] = -1;          // refine against every group
+        } else {
+            int before = 0;                  // candidates of lower groups already placed
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const bool is = (mine >> t) & 1u;
+                const unsigned long long bal = __ballot(is);
+                const int sub = (threadIdx.x & 63) & ~15;
+                const unsigned long long grp = (bal >> sub) & 0xFFFFull;
+                if (is) cj[before + __popcll(grp & ((1ull << q) - 1ull))] = 16 * t + q;
+                before += __popcll(grp);
+            }
+            if (q == 0 && total < kMaxCand) cj[total] = -2;   // end marker
+        }
+    }
+    changed = wave_sum_d(changed);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = changed;
+    __syncthreads();
+    if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
 // Exact squared distances (double differences of the FP32 values) for the
 // refinement list.  Workgroup (slot, t) takes list items slot, slot + gridDim.x,
 // ... and their t-th candidate; 256 threads x 4 independent loads per step.
@@ -346,9 +442,19 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
     // error bound factor (doubled for safety): split products, 3 * 2^-16 per
     // product, plus FP32 accumulation over one slice of rows
     const float eps_rel = (float)(2.0 * (3.0 * std::ldexp(1.0, -16) + p.slice_rows * std::ldexp(1.0, -24)));
-    k_dist_argmin_bounded<<<gb, 256, 0, st>>>(part, ynorm, p.slices, n, c, p.kpad, eps_rel, cnorm,
-                                              old_labels, new_labels, changed_partial, counters, list,
-                                              cand);
+#define RESPCA_ARGMIN_R(TT)                                                                    \
+    k_dist_argmin_bounded_r<TT><<<gb, 256, 0, st>>>(part, ynorm, p.slices, n, c, p.kpad, eps_rel,  \
+                                                    cnorm, old_labels, new_labels, changed_partial, \
+                                                    counters, list, cand)
+    if (c <= 16) RESPCA_ARGMIN_R(1);
+    else if (c <= 32) RESPCA_ARGMIN_R(2);
+    else if (c <= 64) RESPCA_ARGMIN_R(4);
+    else if (c <= 128) RESPCA_ARGMIN_R(8);
+    else
+        k_dist_argmin_bounded<<<gb, 256, 0, st>>>(part, ynorm, p.slices, n, c, p.kpad, eps_rel, cnorm,
+                                                  old_labels, new_labels, changed_partial, counters,
+                                                  list, cand);
+#undef RESPCA_ARGMIN_R
     k_refine_dist<<<dim3(kRefineSlots, kMaxCand), 256, 0, st>>>(C, d, c, Y, ldy, counters, list,
                                                                   cand, refdist);
     k_refine_pick<<<(unsigned)((n + 3) / 4), 256, 0, st>>>(C, d, c, Y, ldy, counters, list, cand,

@@ -88,6 +88,10 @@ int launch_assign(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t
                   double* changed_partial, bool bf16, int* changed_extra, hipStream_t st);
 int* assign_refine_counters(void* work, int64_t d, int64_t n, int c);
 // out[0] += counter (or out[0] = counter when set), one thread.
+// out[0] = sum of `count` changed-count partials plus counters[1]; out[1] =
+// counters[0] (counters may be null: refinement counts then read as zero).
+void launch_assign_finish(const double* partial, int count, const int* counters, double* out,
+                          hipStream_t st);
 void launch_add_int(const int* counter, double* out, hipStream_t st, bool set = false);
 inline int64_t assign_partials_max(int64_t n) { return (n + 15) / 16; }
 

@@ -449,6 +449,24 @@ int launch_sumsq(const T* X, int64_t ldx, int64_t d, int64_t n, double* partial,
     return nrb * ncb;
 }
 
+// End of an assignment pass: out[0] = changed labels (partials + refined), out[1]
+// = refined columns (0 without a refinement list).
+__global__ __launch_bounds__(kBlock) void k_assign_finish(const double* partial, int count,
+                                                          const int* counters, double* out) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int r = threadIdx.x; r < count; r += kBlock) a += partial[r];
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        out[0] = a + (counters ? (double)counters[1] : 0.0);
+        out[1] = counters ? (double)counters[0] : 0.0;
+    }
+}
+
+void launch_assign_finish(const double* partial, int count, const int* counters, double* out,
+                          hipStream_t st) {
+    k_assign_finish<<<1, kBlock, 0, st>>>(partial, count, counters, out);
+}
+
 __global__ void k_add_int(const int* counter, double* out, int set) {
     if (threadIdx.x == 0) out[0] = (set ? 0.0 : out[0]) + (double)counter[0];
 }

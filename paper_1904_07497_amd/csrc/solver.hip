@@ -211,14 +211,9 @@ struct Engine {
             g = launch_assign<T>(C, d, c, Y, ldy, n, (const double*)h->cnorm.p, old, neu, h->dots.p,
                                  (double*)h->chgp.p, bf16, &extra, st);
         }
-        launch_sum_partials((const double*)h->chgp.p, g, 1, status + 3, st);
-        if (extra) {
-            int* cnt = assign_refine_counters(h->dots.p, d, n, c);
-            launch_add_int(cnt + 1, status + 3, st);
-            launch_add_int(cnt, status + 4, st, true);
-        } else {
-            launch_zero_f64(status + 4, st);
-        }
+        launch_assign_finish((const double*)h->chgp.p, g,
+                             extra ? assign_refine_counters(h->dots.p, d, n, c) : nullptr, status + 3,
+                             st);
     }
 
     // Lloyd passes on the columns of Y from (cur, C); see oracle_lloyd for the
