@@ -55,6 +55,18 @@ void launch_col_sqnorm(const T* C, int64_t d, int c, double* out, hipStream_t st
 
 // One ALM sweep over every entry: L-step, S-step, multiplier update, and the
 // three squared-norm partials (returns the number of partial triples).
+// The sweep walked in group order (segments of the last label sort); also writes
+// the group partial sums of D' = X - S' + Theta' * inv_rho_next to next_partial
+// (layout of the means pass).  Returns the number of norm partials (slots past
+// the segment count contribute zeros).
+int sweep_seg_partials(int64_t d, int64_t n, int c);
+template <typename T>
+int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th,
+                     int64_t ldt, const T* C, const int32_t* labels, const int32_t* perm,
+                     const int32_t* seg_begin, const int32_t* seg_len, const int32_t* nseg,
+                     int64_t d, int64_t n, int c, double alpha, double beta, double rho,
+                     double inv_rho, double inv_rho_next, double* norm_partial,
+                     double* next_partial, hipStream_t st);
 template <typename T>
 int launch_sweep(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th,
                  int64_t ldt, const T* C, const int32_t* labels, int64_t d, int64_t n,

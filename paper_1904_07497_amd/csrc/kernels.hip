@@ -228,6 +228,96 @@ __global__ __launch_bounds__(kBlock) void k_sweep(
     }
 }
 
+// The same sweep walked in group order: workgroup (s, rb) takes segment s of the
+// label sort (at most kSegCols columns of one group) over one row block.  Beside
+// L, S, Theta and the norms it sums D' = X - S' + Theta' / rho_next over the
+// segment's columns, in the order and arithmetic of the means pass: these are the
+// group sums the next iteration's L-step needs (at rho_next) whenever the p-step
+// keeps every label, so that iteration can skip its means pass.  Slots past the
+// segment count write zero norms.
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void k_sweep_seg(
+    const T* __restrict__ X, int64_t ldx, T* __restrict__ L, int64_t ldl, T* __restrict__ S,
+    int64_t lds, T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
+    const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ seg_begin, const int32_t* __restrict__ seg_len,
+    const int32_t* __restrict__ nseg, int64_t d, T alpha, T beta, T rho, T inv_rho,
+    T inv_rho_next, double* __restrict__ norm_partial, double* __restrict__ next_partial) {
+    constexpr int NS = kRowsPerBlock / (kBlock * V);
+    constexpr int U = 2;   // columns in flight per thread
+    const int sg = blockIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (sg < *nseg) {
+        const int begin = seg_begin[sg], len = seg_len[sg];
+        const int64_t p = labels[perm[begin]];
+        double acc[NS][V];
+#pragma unroll
+        for (int a = 0; a < NS; ++a)
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
+        for (int q0 = 0; q0 < len; q0 += U) {
+            int64_t jj[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) jj[u] = q0 + u < len ? perm[begin + q0 + u] : -1;
+#pragma unroll
+            for (int a = 0; a < NS; ++a) {
+                const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+                if (i >= d) continue;
+                T xs[U][V], ss[U][V], ts[U][V], lps[U][V], m[V];
+                vload<T, V>(C + p * d + i, m);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (jj[u] < 0) continue;
+                    vload<T, V>(X + jj[u] * ldx + i, xs[u]);
+                    vload<T, V>(S + jj[u] * lds + i, ss[u]);
+                    vload<T, V>(Th + jj[u] * ldt + i, ts[u]);
+                    vload<T, V>(L + jj[u] * ldl + i, lps[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (jj[u] < 0) continue;
+                    const int64_t j = jj[u];
+                    T ln[V], sn[V], tn[V];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const T x = xs[u][v], sv = ss[u][v], t = ts[u][v];
+                        const T dv = x - sv + t * inv_rho;
+                        ln[v] = alpha * dv + beta * m[v];
+                        const T b = x - ln[v] + t * inv_rho;
+                        const T mag = fabs(b) - inv_rho;
+                        sn[v] = mag > T(0) ? copysign(mag, b) : T(0);
+                        const T rr = x - ln[v] - sn[v];
+                        tn[v] = t + rho * rr;
+                        const double dl = (double)ln[v] - (double)lps[u][v];
+                        const double ds = (double)sn[v] - (double)sv;
+                        a0 += (double)rr * (double)rr;
+                        a1 += dl * dl;
+                        a2 += ds * ds;
+                        acc[a][v] += (double)(x - sn[v] + tn[v] * inv_rho_next);
+                    }
+                    vstore<T, V>(L + j * ldl + i, ln);
+                    vstore<T, V>(S + j * lds + i, sn);
+                    vstore<T, V>(Th + j * ldt + i, tn);
+                }
+            }
+        }
+        double* out = next_partial + (int64_t)sg * d;
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
+            if (i < d)
+#pragma unroll
+                for (int v = 0; v < V; ++v) out[i + v] = acc[a][v];
+        }
+    }
+    block_sum3(a0, a1, a2);
+    if (threadIdx.x == 0) {
+        double* o = norm_partial + 3 * ((int64_t)blockIdx.x * gridDim.y + blockIdx.y);
+        o[0] = a0; o[1] = a1; o[2] = a2;
+    }
+}
+
 // -------------------------------------------------------------------- dots
 
 // Tile: 64 columns x CT = 16*KB groups, over one kRowsPerBlock slice of rows,
@@ -559,6 +649,31 @@ int launch_sweep(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, 
     return (int)(grid.x * grid.y);
 }
 
+int sweep_seg_partials(int64_t d, int64_t n, int c) { return max_segments(n, c) * row_blocks(d); }
+
+template <typename T>
+int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th,
+                     int64_t ldt, const T* C, const int32_t* labels, const int32_t* perm,
+                     const int32_t* seg_begin, const int32_t* seg_len, const int32_t* nseg,
+                     int64_t d, int64_t n, int c, double alpha, double beta, double rho,
+                     double inv_rho, double inv_rho_next, double* norm_partial,
+                     double* next_partial, hipStream_t st) {
+    const dim3 grid(max_segments(n, c), row_blocks(d));
+    constexpr int VV = 16 / sizeof(T);
+    const int v = pick_vec<T>(d, {{X, ldx}, {L, ldl}, {S, lds}, {Th, ldt}, {C, d}});
+    if (v == VV)
+        k_sweep_seg<T, VV><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, perm,
+                                                    seg_begin, seg_len, nseg, d, (T)alpha, (T)beta,
+                                                    (T)rho, (T)inv_rho, (T)inv_rho_next,
+                                                    norm_partial, next_partial);
+    else
+        k_sweep_seg<T, 1><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, perm,
+                                                   seg_begin, seg_len, nseg, d, (T)alpha, (T)beta,
+                                                   (T)rho, (T)inv_rho, (T)inv_rho_next, norm_partial,
+                                                   next_partial);
+    return (int)(grid.x * grid.y);
+}
+
 template <typename T>
 void launch_dots(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t n, T* part,
                  hipStream_t st) {
@@ -620,6 +735,11 @@ void launch_gather_cols(const T* Y, int64_t ldy, int64_t d, const int32_t* idx, 
     template int launch_sweep<T>(const T*, int64_t, T*, int64_t, T*, int64_t, T*, int64_t,        \
                                  const T*, const int32_t*, int64_t, int64_t, double, double,       \
                                  double, double, double*, hipStream_t);                            \
+    template int launch_sweep_seg<T>(const T*, int64_t, T*, int64_t, T*, int64_t, T*, int64_t,    \
+                                     const T*, const int32_t*, const int32_t*, const int32_t*,     \
+                                     const int32_t*, const int32_t*, int64_t, int64_t, int,        \
+                                     double, double, double, double, double, double*, double*,     \
+                                     hipStream_t);                                                 \
     template void launch_dots<T>(const T*, int64_t, int, const T*, int64_t, int64_t, T*,           \
                                  hipStream_t);                                                     \
     template int launch_argmin<T>(const T*, int, int, int64_t, const double*, const int32_t*,     \

@@ -134,6 +134,7 @@ struct Engine {
     int nrb;
     double* status;  // device: [0..2] norms^2, [3] changed count, [4] refined columns
     int64_t refined = 0;
+    bool next_ready = false;   // pmeans / sort tables hold the next L-step's group sums of D
 
     respca_status setup() {
         nrb = row_blocks(d);
@@ -150,9 +151,12 @@ struct Engine {
         CKS(ensure(h, h->cnorm, c * sizeof(double)));
         CKS(ensure(h, h->lab_a, n * sizeof(int32_t)));
         CKS(ensure(h, h->lab_b, n * sizeof(int32_t)));
-        const size_t np = (size_t)sweep_partials(d, n);
-        size_t nsum = (size_t)nrb * (size_t)((n + 15) / 16);
-        CKS(ensure(h, h->normp, 3 * (np > nsum ? np : nsum) * sizeof(double)));
+        size_t np = (size_t)sweep_partials(d, n);
+        const size_t nsum = (size_t)nrb * (size_t)((n + 15) / 16);
+        const size_t nseg_sweep = (size_t)sweep_seg_partials(d, n, c);
+        if (nsum > np) np = nsum;
+        if (nseg_sweep > np) np = nseg_sweep;
+        CKS(ensure(h, h->normp, 3 * np * sizeof(double)));
         CKS(ensure(h, h->chgp, (size_t)assign_partials_max(n) * sizeof(double)));
         CKS(ensure(h, h->status, 8 * sizeof(double)));
         CKS(ensure_host(h, (16 + 2 * (size_t)c) * sizeof(double)));
@@ -284,18 +288,30 @@ struct Engine {
         const double alpha = rho / (2.0 * r.lambda + rho);
         const double beta = (2.0 * r.lambda) / (2.0 * r.lambda + rho);
         const double inv = 1.0 / rho;
-        sort(cur);                                                   // Sec. 4.1: groups of D
-        group_means(true, X, ldx, S, lds, Th, ldt, (T)inv, C);
+        const double next = r.kappa * rho;                           // Sec. 4.4 schedule
+        const double inv_next = 1.0 / (next < r.rho_max ? next : r.rho_max);
+        if (next_ready) {
+            // the previous sweep summed D over these same groups at this rho
+            launch_group_finalize<T>((const double*)h->pmeans.p, d, c, counts(),
+                                     (const int32_t*)h->segf.p, C, st);
+        } else {
+            sort(cur);                                               // Sec. 4.1: groups of D
+            group_means(true, X, ldx, S, lds, Th, ldt, (T)inv, C);
+        }
         int np = 0;
         {
             ProfScope ps(h, st, RESPCA_KERNEL_SWEEP, 7.0 * (double)d * n * sizeof(T));
-            np = launch_sweep<T>(X, ldx, L, ldl, S, lds, Th, ldt, C, cur, d, n, alpha, beta, rho, inv,
-                                 (double*)h->normp.p, st);
+            np = launch_sweep_seg<T>(X, ldx, L, ldl, S, lds, Th, ldt, C, cur, perm(),
+                                     (const int32_t*)h->segb.p, (const int32_t*)h->segl.p,
+                                     (const int32_t*)h->nseg.p, d, n, c, alpha, beta, rho, inv,
+                                     inv_next, (double*)h->normp.p, (double*)h->pmeans.p, st);
         }
         launch_sum_partials((const double*)h->normp.p, np, 3, status, st);
         double first[4];
         CKS(lloyd(L, ldl, C, cur, alt, r.max_lloyd, steps, first));  // Sec. 4.2
         for (int i = 0; i < 3; ++i) norms[i] = std::sqrt(first[i]);
+        // unchanged labels: the sort tables and the sweep's sums stay valid
+        next_ready = (first[3] == 0.0);
         return RESPCA_OK;
     }
 };
