@@ -67,12 +67,7 @@ int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t l
                      int64_t d, int64_t n, int c, double alpha, double beta, double rho,
                      double inv_rho, double inv_rho_next, double* norm_partial,
                      double* next_partial, hipStream_t st);
-template <typename T>
-int launch_sweep(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th,
-                 int64_t ldt, const T* C, const int32_t* labels, int64_t d, int64_t n,
-                 double alpha, double beta, double rho, double inv_rho, double* norm_partial,
-                 hipStream_t st);
-int sweep_partials(int64_t d, int64_t n);
+
 
 // Split-d centroid/column dot products: part[(rb*c + k)*n + j] = sum_{i in slice rb} C[i,k] Y[i,j].
 template <typename T>

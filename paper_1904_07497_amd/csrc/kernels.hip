@@ -172,11 +172,11 @@ __global__ __launch_bounds__(kBlock) void k_group_partial(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ S, int64_t lds,
     const T* __restrict__ Th, int64_t ldt, T inv_rho, int64_t d, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ seg_begin, const int32_t* __restrict__ seg_len,
-    const int32_t* __restrict__ nseg, double* __restrict__ partial) {
-    const int s = blockIdx.x;
+    const int32_t* __restrict__ nseg, int nrb, double* __restrict__ partial) {
+    const int s = (int)(blockIdx.x / nrb);   // row blocks vary fastest
     if (s >= *nseg) return;
     group_partial_tile<T, V, WITH_D>(A, lda, S, lds, Th, ldt, inv_rho, d, perm, seg_begin[s],
-                                     seg_len[s], (int64_t)blockIdx.y * kRowsPerBlock,
+                                     seg_len[s], (int64_t)(blockIdx.x % nrb) * kRowsPerBlock,
                                      partial + (int64_t)s * d);
 }
 
@@ -209,27 +209,8 @@ __global__ __launch_bounds__(kBlock) void k_col_sqnorm(const T* C, int64_t d, do
 
 // The fused ALM sweep (tile body in device_common.h): one workgroup per
 // (column chunk, row slice), per-workgroup norm partials.
-template <typename T, int V>
-__global__ __launch_bounds__(kBlock) void k_sweep(
-    const T* __restrict__ X, int64_t ldx, T* __restrict__ L, int64_t ldl, T* __restrict__ S,
-    int64_t lds, T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
-    const int32_t* __restrict__ labels, int64_t d, int64_t n, int jc, T alpha, T beta, T rho,
-    T inv_rho, double* __restrict__ norm_partial) {
-    const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
-    const int64_t j0 = (int64_t)blockIdx.x * jc;
-    const int64_t j1 = j0 + jc < n ? j0 + jc : n;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    sweep_tile<T, V>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, d, j0, j1, r0, alpha, beta, rho,
-                     inv_rho, a0, a1, a2);
-    block_sum3(a0, a1, a2);
-    if (threadIdx.x == 0) {
-        double* o = norm_partial + 3 * ((int64_t)blockIdx.x * gridDim.y + blockIdx.y);
-        o[0] = a0; o[1] = a1; o[2] = a2;
-    }
-}
-
-// The same sweep walked in group order: workgroup (s, rb) takes segment s of the
-// label sort (at most kSegCols columns of one group) over one row block.  Beside
+// The fused ALM sweep (body as sweep_tile) walked in group order: workgroup
+// (s, rb) takes segment s of the label sort (at most kSegCols columns of one group) over one row block.  Beside
 // L, S, Theta and the norms it sums D' = X - S' + Theta' / rho_next over the
 // segment's columns, in the order and arithmetic of the means pass: these are the
 // group sums the next iteration's L-step needs (at rho_next) whenever the p-step
@@ -241,13 +222,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     int64_t lds, T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
     const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ seg_begin, const int32_t* __restrict__ seg_len,
-    const int32_t* __restrict__ nseg, int64_t d, T alpha, T beta, T rho, T inv_rho,
+    const int32_t* __restrict__ nseg, int64_t d, int nrb, T alpha, T beta, T rho, T inv_rho,
     T inv_rho_next, double* __restrict__ norm_partial, double* __restrict__ next_partial) {
     constexpr int NS = kRowsPerBlock / (kBlock * V);
-    constexpr int U = 2;   // columns in flight per thread
-    const int sg = blockIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    constexpr int U = 4;   // columns in flight per thread
+    const int sg = (int)(blockIdx.x / nrb);             // row blocks vary fastest: the
+    const int64_t r0 = (int64_t)(blockIdx.x % nrb) * kRowsPerBlock;   // resident workgroups
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;                // share a band of segments
     if (sg < *nseg) {
         const int begin = seg_begin[sg], len = seg_len[sg];
         const int64_t p = labels[perm[begin]];
@@ -313,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     }
     block_sum3(a0, a1, a2);
     if (threadIdx.x == 0) {
-        double* o = norm_partial + 3 * ((int64_t)blockIdx.x * gridDim.y + blockIdx.y);
+        double* o = norm_partial + 3 * (int64_t)blockIdx.x;
         o[0] = a0; o[1] = a1; o[2] = a2;
     }
 }
@@ -422,7 +403,24 @@ __global__ __launch_bounds__(kBlock) void k_d2(const T* __restrict__ Y, int64_t 
     const T* yj = Y + j * ldy;
     const T* ys = Y + s * ldy;
     double acc = 0.0;
-    for (int64_t i = (int64_t)lane * V; i < d; i += 64 * V) {
+    constexpr int U = 4;   // loads in flight per lane; the summation order is unchanged
+    int64_t i = (int64_t)lane * V;
+    for (; i + (int64_t)64 * V * (U - 1) < d; i += (int64_t)64 * V * U) {
+        T a[U][V], b[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vload<T, V>(yj + i + (int64_t)64 * V * u, a[u]);
+            vload<T, V>(ys + i + (int64_t)64 * V * u, b[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const double t = (double)a[u][v] - (double)b[u][v];
+                acc += t * t;
+            }
+    }
+    for (; i < d; i += 64 * V) {
         T a[V], b[V];
         vload<T, V>(yj + i, a);
         vload<T, V>(ys + i, b);
@@ -586,23 +584,28 @@ void launch_group_partial(bool with_d, const T* A, int64_t lda, const T* S, int6
                           const T* Th, int64_t ldt, T inv_rho, int64_t d, int64_t n, int c,
                           const int32_t* perm, const int32_t* seg_begin, const int32_t* seg_len,
                           const int32_t* nseg, double* partial, hipStream_t st) {
-    const dim3 grid(max_segments(n, c), row_blocks(d));
+    const int nrb = row_blocks(d);
+    const unsigned grid = (unsigned)max_segments(n, c) * (unsigned)nrb;
     int v = with_d ? pick_vec<T>(d, {{A, lda}, {S, lds}, {Th, ldt}}) : pick_vec<T>(d, {{A, lda}});
     constexpr int VV = 16 / sizeof(T);
     if (with_d) {
         if (v == VV)
             k_group_partial<T, VV, true><<<grid, kBlock, 0, st>>>(A, lda, S, lds, Th, ldt, inv_rho, d,
-                                                                  perm, seg_begin, seg_len, nseg, partial);
+                                                                  perm, seg_begin, seg_len, nseg, nrb,
+                                                                  partial);
         else
             k_group_partial<T, 1, true><<<grid, kBlock, 0, st>>>(A, lda, S, lds, Th, ldt, inv_rho, d,
-                                                                 perm, seg_begin, seg_len, nseg, partial);
+                                                                 perm, seg_begin, seg_len, nseg, nrb,
+                                                                 partial);
     } else {
         if (v == VV)
             k_group_partial<T, VV, false><<<grid, kBlock, 0, st>>>(A, lda, A, lda, A, lda, inv_rho, d,
-                                                                   perm, seg_begin, seg_len, nseg, partial);
+                                                                   perm, seg_begin, seg_len, nseg, nrb,
+                                                                   partial);
         else
             k_group_partial<T, 1, false><<<grid, kBlock, 0, st>>>(A, lda, A, lda, A, lda, inv_rho, d,
-                                                                  perm, seg_begin, seg_len, nseg, partial);
+                                                                  perm, seg_begin, seg_len, nseg, nrb,
+                                                                  partial);
     }
 }
 
@@ -618,37 +621,6 @@ void launch_col_sqnorm(const T* C, int64_t d, int c, double* out, hipStream_t st
     k_col_sqnorm<T><<<c, kBlock, 0, st>>>(C, d, out);
 }
 
-static int sweep_cols(int64_t d, int64_t n) {
-    const int64_t nrb = row_blocks(d);
-    int64_t jc = (nrb * n) / 4096;
-    if (jc < 1) jc = 1;
-    if (jc > 64) jc = 64;
-    return (int)jc;
-}
-
-int sweep_partials(int64_t d, int64_t n) {
-    const int jc = sweep_cols(d, n);
-    return row_blocks(d) * (int)((n + jc - 1) / jc);
-}
-
-template <typename T>
-int launch_sweep(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t lds, T* Th,
-                 int64_t ldt, const T* C, const int32_t* labels, int64_t d, int64_t n,
-                 double alpha, double beta, double rho, double inv_rho, double* norm_partial,
-                 hipStream_t st) {
-    const int jc = sweep_cols(d, n);
-    const dim3 grid((unsigned)((n + jc - 1) / jc), row_blocks(d));
-    constexpr int VV = 16 / sizeof(T);
-    const int v = pick_vec<T>(d, {{X, ldx}, {L, ldl}, {S, lds}, {Th, ldt}, {C, d}});
-    if (v == VV)
-        k_sweep<T, VV><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, d, n, jc,
-                                                (T)alpha, (T)beta, (T)rho, (T)inv_rho, norm_partial);
-    else
-        k_sweep<T, 1><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, d, n, jc,
-                                               (T)alpha, (T)beta, (T)rho, (T)inv_rho, norm_partial);
-    return (int)(grid.x * grid.y);
-}
-
 int sweep_seg_partials(int64_t d, int64_t n, int c) { return max_segments(n, c) * row_blocks(d); }
 
 template <typename T>
@@ -658,20 +630,21 @@ int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t l
                      int64_t d, int64_t n, int c, double alpha, double beta, double rho,
                      double inv_rho, double inv_rho_next, double* norm_partial,
                      double* next_partial, hipStream_t st) {
-    const dim3 grid(max_segments(n, c), row_blocks(d));
+    const int nrb = row_blocks(d);
+    const unsigned grid = (unsigned)max_segments(n, c) * (unsigned)nrb;
     constexpr int VV = 16 / sizeof(T);
     const int v = pick_vec<T>(d, {{X, ldx}, {L, ldl}, {S, lds}, {Th, ldt}, {C, d}});
     if (v == VV)
         k_sweep_seg<T, VV><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, perm,
-                                                    seg_begin, seg_len, nseg, d, (T)alpha, (T)beta,
-                                                    (T)rho, (T)inv_rho, (T)inv_rho_next,
+                                                    seg_begin, seg_len, nseg, d, nrb, (T)alpha,
+                                                    (T)beta, (T)rho, (T)inv_rho, (T)inv_rho_next,
                                                     norm_partial, next_partial);
     else
         k_sweep_seg<T, 1><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, perm,
-                                                   seg_begin, seg_len, nseg, d, (T)alpha, (T)beta,
-                                                   (T)rho, (T)inv_rho, (T)inv_rho_next, norm_partial,
-                                                   next_partial);
-    return (int)(grid.x * grid.y);
+                                                   seg_begin, seg_len, nseg, d, nrb, (T)alpha,
+                                                   (T)beta, (T)rho, (T)inv_rho, (T)inv_rho_next,
+                                                   norm_partial, next_partial);
+    return (int)grid;
 }
 
 template <typename T>
@@ -732,9 +705,6 @@ void launch_gather_cols(const T* Y, int64_t ldy, int64_t d, const int32_t* idx, 
     template void launch_group_finalize<T>(const double*, int64_t, int, const int32_t*,            \
                                            const int32_t*, T*, hipStream_t);                       \
     template void launch_col_sqnorm<T>(const T*, int64_t, int, double*, hipStream_t);              \
-    template int launch_sweep<T>(const T*, int64_t, T*, int64_t, T*, int64_t, T*, int64_t,        \
-                                 const T*, const int32_t*, int64_t, int64_t, double, double,       \
-                                 double, double, double*, hipStream_t);                            \
     template int launch_sweep_seg<T>(const T*, int64_t, T*, int64_t, T*, int64_t, T*, int64_t,    \
                                      const T*, const int32_t*, const int32_t*, const int32_t*,     \
                                      const int32_t*, const int32_t*, int64_t, int64_t, int,        \

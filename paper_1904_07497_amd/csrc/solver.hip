@@ -151,11 +151,9 @@ struct Engine {
         CKS(ensure(h, h->cnorm, c * sizeof(double)));
         CKS(ensure(h, h->lab_a, n * sizeof(int32_t)));
         CKS(ensure(h, h->lab_b, n * sizeof(int32_t)));
-        size_t np = (size_t)sweep_partials(d, n);
+        size_t np = (size_t)sweep_seg_partials(d, n, c);
         const size_t nsum = (size_t)nrb * (size_t)((n + 15) / 16);
-        const size_t nseg_sweep = (size_t)sweep_seg_partials(d, n, c);
         if (nsum > np) np = nsum;
-        if (nseg_sweep > np) np = nseg_sweep;
         CKS(ensure(h, h->normp, 3 * np * sizeof(double)));
         CKS(ensure(h, h->chgp, (size_t)assign_partials_max(n) * sizeof(double)));
         CKS(ensure(h, h->status, 8 * sizeof(double)));
