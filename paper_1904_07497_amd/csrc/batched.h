@@ -41,18 +41,19 @@ struct BatchInst {
     int32_t* seeds;
     const double* u;           // k-means++ uniforms (host-drawn from splitmix64(seed))
     double* cnorm;
-    double* sweep_part;        // 3 per sweep tile
+    double* sweep_part;        // 3 per sweep item (segment x row block), 1 per pack tile
     int32_t* chg;              // 1 per 16-column argmin item
     // shape and tiling.  The initial K-means runs on the columns of X (kdp = dp) or of
     // the embedding (kdp = 4 * ceil(er / 4)); mrows = max(dp, kdp) and mrb row blocks
     // of kBatchRows cover both.
-    int d, dp, n, c, kpad, nrb, jc, slices, slice_rows, nkc, n_sweep, n_argmin;
+    int d, dp, n, c, kpad, nrb, jc, slices, slice_rows, nkc, n_sweep, n_tile, n_argmin;
     int er, kdp, mrows, mrb;
     // parameters
     double lambda, tol, rho0, kappa, rho_max;
     int max_iter, max_lloyd;
     // state
     int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, ref_lloyd, status, nseg;
+    int next_ready;            // pmeans and the sort tables hold the next L-step's group sums
     double rho, nx, rho_final, primal, dL, dS;
 };
 
@@ -80,10 +81,10 @@ struct BatchArgs {
     int cmax;
     int max_steps;
     // prefix tables (batch + 1 entries) of per-instance work items
-    const int32_t* off_tile;   // ceil(n/jc) * nrb   (pack, sweep, unpack; nrb = ceil(dp/256))
+    const int32_t* off_tile;   // ceil(n/jc) * nrb   (pack, unpack; nrb = ceil(dp/256))
     const int32_t* off_d2;     // ceil(n/4)          (k-means++ distances, wave per column)
     const int32_t* off_kc;     // c                  (seed columns, centroid norms)
-    const int32_t* off_seg;    // (ceil(n/64) + c) * mrb (group partial sums)
+    const int32_t* off_seg;    // (ceil(n/64) + c) * mrb (group partial sums, sweep)
     const int32_t* off_kr;     // c * ceil(mrows/256) (centroid finalisation)
     const int32_t* off_dist;   // ceil(n/128) * slices * nkc (distance tiles)
     const int32_t* off_col;    // ceil(n/16)         (argmin)

@@ -330,6 +330,9 @@ __device__ void control_instance(BatchInst& B, int* active) {
     }
     B.lloyd_iter += 1;
     B.lloyd_total += 1;
+    // an outer iteration whose first assignment kept every label leaves the next
+    // L-step's group sums (summed by this step's sweep) and the sort tables valid
+    B.next_ready = (mode == M_ITER && changed == 0) ? 1 : 0;
     if (changed != 0 && B.lloyd_iter < B.max_lloyd) {
         B.cur ^= 1;
         B.mode = M_LL;
@@ -356,7 +359,8 @@ __device__ void control_instance(BatchInst& B, int* active) {
 
 // Work-item walk of one phase: items item = blockIdx.x + k * gridDim.x of the
 // prefix table `tab` (cached in LDS), instance found by a forward scan; an
-// instance whose mode does not need the phase is skipped in one step.
+// instance that does not need the phase (need(mode, instance) false) is skipped
+// in one step.
 template <typename Need, typename Body>
 __device__ inline void for_items(int batch, const int* tab, const int* modes, Need need, Body body) {
     const unsigned nb = gridDim.x;
@@ -365,7 +369,7 @@ __device__ inline void for_items(int batch, const int* tab, const int* modes, Ne
     int item = blockIdx.x;
     while (item < total) {
         while (tab[i + 1] <= item) ++i;
-        if (!need(modes[i])) {
+        if (!need(modes[i], i)) {
             const int next = tab[i + 1];
             item = next + (int)((blockIdx.x + nb - (unsigned)next % nb) % nb);
             continue;
@@ -386,6 +390,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     __shared__ int s_tab[kMaxBatch + 1];
     __shared__ int s_mode[kMaxBatch];
     __shared__ int s_nseg[kMaxBatch];
+    __shared__ int s_ready[kMaxBatch];   // the instance skips its sort and means this step
     auto load_tab = [&](const int32_t* off) {
         __syncthreads();
         for (int t = threadIdx.x; t <= batch; t += kBlock) s_tab[t] = off[t];
@@ -393,11 +398,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     };
     auto load_modes = [&]() {
         __syncthreads();
-        for (int t = threadIdx.x; t < batch; t += kBlock)
-            s_mode[t] = __hip_atomic_load(&inst[t].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int t = threadIdx.x; t < batch; t += kBlock) {
+            const int m = __hip_atomic_load(&inst[t].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_mode[t] = m;
+            s_ready[t] = m == M_ITER && __hip_atomic_load(&inst[t].next_ready, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
     };
-    auto any = [](int) { return true; };
+    auto any = [](int, int) { return true; };
+    auto groups = [](int m, int) { return needs_groups(m); };
+    auto assigns = [](int m, int) { return needs_assign(m); };
 
     // ---- phase: copy X into its zero-padded internal copy; zero L, S, Theta;
     //      sums of squares of X
@@ -442,12 +453,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         BatchInst& B = inst[i];
         __shared__ int s_m, s_status;
         double nx2 = 0.0, z1 = 0.0, z2 = 0.0;
-        for (int t = threadIdx.x; t < B.n_sweep; t += kBlock) nx2 += B.sweep_part[3 * t];
+        for (int t = threadIdx.x; t < B.n_tile; t += kBlock) nx2 += B.sweep_part[3 * t];
         block_sum3(nx2, z1, z2);
         if (threadIdx.x == 0) {
             B.nx = sqrt(nx2);
             B.cur = 0;
             B.iters = B.lloyd_total = B.lloyd_iter = B.init_lloyd = B.ref_lloyd = 0;
+            B.next_ready = 0;
             B.rho = B.rho0;
             B.rho_final = 0.0;
             B.primal = B.dL = B.dS = 0.0;
@@ -480,7 +492,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     load_modes();
 
     // ---- k-means++ seeding, seed by seed, for instances in M_SEED
-    auto is_seed = [](int m) { return m == M_SEED; };
+    auto is_seed = [](int m, int) { return m == M_SEED; };
     for (int m = 0; m < A.cmax; ++m) {
         load_tab(A.off_d2);
         for_items(batch, s_tab, s_mode, is_seed, [&](int i, int local) {
@@ -541,7 +553,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         // A: sort the current labels
         for (int i = blockIdx.x; i < batch; i += nb) {
             BatchInst& B = inst[i];
-            if (needs_groups(s_mode[i])) sort_instance(B, B.lab[B.cur]);
+            if (needs_groups(s_mode[i]) && !s_ready[i]) sort_instance(B, B.lab[B.cur]);
         }
         if (!grid_sync(gs, nb, tmo, BP_SORT, tclk)) return;
         for (int t = threadIdx.x; t < batch; t += kBlock)
@@ -549,7 +561,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                                                                     __HIP_MEMORY_SCOPE_AGENT) : 0;
         // B: group partial sums (of X, of D = X - S + Theta/rho, or of L)
         load_tab(A.off_seg);
-        for_items(batch, s_tab, s_mode, needs_groups, [&](int i, int local) {
+        for_items(batch, s_tab, s_mode, [&](int m, int i) { return needs_groups(m) && !s_ready[i]; }, [&](int i, int local) {
             BatchInst& B = inst[i];
             const int mode = s_mode[i];
             const int s = local / B.mrb, rb = local % B.mrb;
@@ -570,7 +582,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         if (!grid_sync(gs, nb, tmo, BP_MEANS, tclk)) return;
         // C: centroids of the non-empty groups
         load_tab(A.off_kr);
-        for_items(batch, s_tab, s_mode, needs_groups, [&](int i, int local) {
+        for_items(batch, s_tab, s_mode, groups, [&](int i, int local) {
             BatchInst& B = inst[i];
             const int mode = s_mode[i];
             const int rows = mode_rows(B, mode);
@@ -588,18 +600,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             B.C[(int64_t)k * rows + r] = (float)(s / (double)nk);
         });
         if (!grid_sync(gs, nb, tmo, BP_FINALIZE, tclk)) return;
-        // D: the fused ALM sweep (instances starting an outer iteration)
-        load_tab(A.off_tile);
-        for_items(batch, s_tab, s_mode, [](int m) { return m == M_ITER; }, [&](int i, int local) {
+        // D: the fused ALM sweep (instances starting an outer iteration), walked over
+        //    the group segments; it also leaves the next L-step's group sums in pmeans
+        load_tab(A.off_seg);
+        for_items(batch, s_tab, s_mode, [](int m, int) { return m == M_ITER; }, [&](int i, int local) {
             BatchInst& B = inst[i];
-            const int cb = local / B.nrb, rb = local % B.nrb;
-            const int64_t j0 = (int64_t)cb * B.jc, j1 = min((int64_t)B.n, j0 + B.jc);
-            const double rho = B.rho;
-            const double alpha = rho / (2.0 * B.lambda + rho), beta = (2.0 * B.lambda) / (2.0 * B.lambda + rho);
+            const int sg = local / B.mrb, rb = local % B.mrb;
+            const int64_t r0 = (int64_t)rb * kBatchRows;
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            sweep_tile<float, 4, kBatchRows, 4>(B.X, B.dp, B.L, B.dp, B.S, B.dp, B.Th, B.dp, B.C,
-                                 B.lab[B.cur], B.dp, j0, j1, (int64_t)rb * kBatchRows, (float)alpha, (float)beta,
-                                 (float)rho, (float)(1.0 / rho), a0, a1, a2);
+            if (sg < s_nseg[i] && r0 < B.dp) {
+                const double rho = B.rho;
+                const double alpha = rho / (2.0 * B.lambda + rho);
+                const double beta = (2.0 * B.lambda) / (2.0 * B.lambda + rho);
+                const double next = B.kappa * rho;
+                const double inv_next = 1.0 / (next < B.rho_max ? next : B.rho_max);
+                const int begin = B.segb[sg];
+                seg_sweep_tile<float, 4, kBatchRows, 4, 2>(
+                    B.X, B.dp, B.L, B.dp, B.S, B.dp, B.Th, B.dp, B.C, B.lab[B.cur][B.perm[begin]], B.dp,
+                    B.perm, begin, B.segl[sg], r0, (float)alpha, (float)beta, (float)rho,
+                    (float)(1.0 / rho), (float)inv_next, a0, a1, a2, B.pmeans + (int64_t)sg * B.dp);
+            }
             block_sum3(a0, a1, a2);
             if (threadIdx.x == 0) {
                 B.sweep_part[3 * local] = a0;
@@ -610,7 +630,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         if (!grid_sync(gs, nb, tmo, BP_SWEEP, tclk)) return;
         // E: squared centroid norms
         load_tab(A.off_kc);
-        for_items(batch, s_tab, s_mode, needs_assign, [&](int i, int k) {
+        for_items(batch, s_tab, s_mode, assigns, [&](int i, int k) {
             BatchInst& B = inst[i];
             const int rows = mode_rows(B, s_mode[i]);
             double a = 0.0, b = 0.0, c = 0.0;
@@ -624,7 +644,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         if (!grid_sync(gs, nb, tmo, BP_CNORM, tclk)) return;
         // F: distance tiles (columns of X before the iterations, of L after)
         load_tab(A.off_dist);
-        for_items(batch, s_tab, s_mode, needs_assign, [&](int i, int local) {
+        for_items(batch, s_tab, s_mode, assigns, [&](int i, int local) {
             BatchInst& B = inst[i];
             const int mode = s_mode[i];
             const int kc = local % B.nkc, ts = local / B.nkc;
@@ -637,7 +657,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         if (!grid_sync(gs, nb, tmo, BP_DIST, tclk)) return;
         // G: reduce slices, argmin (16 lanes per column), changed counts
         load_tab(A.off_col);
-        for_items(batch, s_tab, s_mode, needs_assign, [&](int i, int local) {
+        for_items(batch, s_tab, s_mode, assigns, [&](int i, int local) {
             BatchInst& B = inst[i];
             const int q = threadIdx.x & 15;
             const int64_t j = (int64_t)local * 16 + (threadIdx.x >> 4);

@@ -129,9 +129,10 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.slice_rows = rows;
         B.slices = (B.mrows + rows - 1) / rows;
         const int ntiles = (B.n + 127) / 128;
-        B.n_sweep = ((B.n + B.jc - 1) / B.jc) * B.nrb;
+        B.n_tile = ((B.n + B.jc - 1) / B.jc) * B.nrb;
         B.n_argmin = (B.n + 15) / 16;
         const int nseg_max = (B.n + kSegCols - 1) / kSegCols + B.c;
+        B.n_sweep = nseg_max * B.mrb;
         B.lambda = r.lambda;
         B.tol = r.tol;
         B.rho0 = r.rho0;
@@ -140,7 +141,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.max_iter = r.max_iter;
         B.max_lloyd = r.max_lloyd;
         // work tables (prefix sums)
-        const int64_t counts[kTableCount] = {B.n_sweep, (B.n + 3) / 4, B.c, (int64_t)nseg_max * B.mrb,
+        const int64_t counts[kTableCount] = {B.n_tile, (B.n + 3) / 4, B.c, (int64_t)nseg_max * B.mrb,
                                              (int64_t)B.c * ((B.mrows + kBlock - 1) / kBlock),
                                              (int64_t)ntiles * B.slices * B.nkc, B.n_argmin};
         for (int t = 0; t < kTableCount; ++t)
@@ -167,7 +168,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.chosen = (int32_t*)take(B.n * sizeof(int32_t));
         B.seeds = (int32_t*)take(B.c * sizeof(int32_t));
         B.cnorm = (double*)take(B.c * sizeof(double));
-        B.sweep_part = (double*)take(3 * (size_t)B.n_sweep * sizeof(double));
+        B.sweep_part = (double*)take(3 * (size_t)std::max(B.n_sweep, B.n_tile) * sizeof(double));
         B.chg = (int32_t*)take(B.n_argmin * sizeof(int32_t));
         // k-means++ uniforms from the instance's seed
         call.u_start[i] = call.u.size();

@@ -68,6 +68,14 @@ __device__ inline void vstore(T* p, const T (&r)[V]) {
     }
 }
 
+// LDS buffer for the column groups' partial sums below, shared by every
+// instantiation (one allocation per kernel).
+constexpr int kGroupRedDoubles = 1024;
+__device__ inline double* group_red_lds() {
+    __shared__ double red[kGroupRedDoubles];
+    return red;
+}
+
 // ------------------------------------------------------------- tile bodies
 
 // The fused ALM sweep over columns [j0, j1) of rows [r0, r0 + ROWS).  The block's
@@ -143,12 +151,102 @@ __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __res
     }
 }
 
-// LDS buffer for the column groups' partial sums below, shared by every
-// instantiation (one allocation per kernel).
-constexpr int kGroupRedDoubles = 1024;
-__device__ inline double* group_red_lds() {
-    __shared__ double red[kGroupRedDoubles];
-    return red;
+// The fused sweep over one group segment: the `len` columns perm[begin..) (all in
+// group p) over rows [r0, r0 + ROWS), CG column groups of kBlock / CG threads
+// (group g takes the segment's columns g, g + CG, ...), U columns in flight.  Per
+// entry it does what sweep_tile does and also sums D' = X - S' + Theta' * inv_rho_next
+// over the segment's columns -- the group sums of the next L-step when the p-step
+// keeps every label -- in the order and arithmetic of group_partial_tile (column
+// groups added in group order), written to out[i] (this segment's d-vector).
+template <typename T, int V, int ROWS, int CG, int U>
+__device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* __restrict__ L,
+                                      int64_t ldl, T* __restrict__ S, int64_t lds,
+                                      T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
+                                      int64_t p, int64_t d, const int32_t* __restrict__ perm,
+                                      int begin, int len, int64_t r0, T alpha, T beta, T rho,
+                                      T inv_rho, T inv_rho_next, double& a0, double& a1, double& a2,
+                                      double* __restrict__ out) {
+    constexpr int TPC = kBlock / CG;
+    constexpr int NS = ROWS / (TPC * V);
+    static_assert(NS >= 1 && NS * TPC * V == ROWS, "row block must tile the column group");
+    const int cg = (int)threadIdx.x / TPC, tl = (int)threadIdx.x % TPC;
+    double acc[NS][V];
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
+    for (int q0 = cg; q0 < len; q0 += U * CG) {
+        int64_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jj[u] = q0 + u * CG < len ? perm[begin + q0 + u * CG] : -1;
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
+            if (i >= d) continue;
+            T xs[U][V], ss[U][V], ts[U][V], lps[U][V], m[V];
+            vload<T, V>(C + p * d + i, m);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (jj[u] < 0) continue;
+                vload<T, V>(X + jj[u] * ldx + i, xs[u]);
+                vload<T, V>(S + jj[u] * lds + i, ss[u]);
+                vload<T, V>(Th + jj[u] * ldt + i, ts[u]);
+                vload<T, V>(L + jj[u] * ldl + i, lps[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (jj[u] < 0) continue;
+                const int64_t j = jj[u];
+                T ln[V], sn[V], tn[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T x = xs[u][v], sv = ss[u][v], t = ts[u][v];
+                    const T dv = x - sv + t * inv_rho;
+                    ln[v] = alpha * dv + beta * m[v];
+                    const T b = x - ln[v] + t * inv_rho;
+                    const T mag = fabs(b) - inv_rho;
+                    sn[v] = mag > T(0) ? copysign(mag, b) : T(0);
+                    const T rr = x - ln[v] - sn[v];
+                    tn[v] = t + rho * rr;
+                    const double dl = (double)ln[v] - (double)lps[u][v];
+                    const double ds = (double)sn[v] - (double)sv;
+                    a0 += (double)rr * (double)rr;
+                    a1 += dl * dl;
+                    a2 += ds * ds;
+                    acc[a][v] += (double)(x - sn[v] + tn[v] * inv_rho_next);
+                }
+                vstore<T, V>(L + j * ldl + i, ln);
+                vstore<T, V>(S + j * lds + i, sn);
+                vstore<T, V>(Th + j * ldt + i, tn);
+            }
+        }
+    }
+    if constexpr (CG == 1) {
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
+            if (i < d)
+#pragma unroll
+                for (int v = 0; v < V; ++v) out[i + v] = acc[a][v];
+        }
+    } else {
+        static_assert(CG * ROWS <= kGroupRedDoubles, "partial-sum buffer too small");
+        double* red = group_red_lds();
+#pragma unroll
+        for (int a = 0; a < NS; ++a)
+#pragma unroll
+            for (int v = 0; v < V; ++v) red[cg * ROWS + (a * TPC + tl) * V + v] = acc[a][v];
+        __syncthreads();
+        for (int e = threadIdx.x; e < ROWS; e += kBlock) {
+            if (r0 + e < d) {
+                double t = red[e];
+#pragma unroll
+                for (int g = 1; g < CG; ++g) t += red[g * ROWS + e];
+                out[r0 + e] = t;
+            }
+        }
+        __syncthreads();   // red is reused by the next call
+    }
 }
 
 // Sum over the `len` columns perm[begin..begin+len) (one group segment) of

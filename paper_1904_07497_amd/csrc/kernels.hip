@@ -207,15 +207,13 @@ __global__ __launch_bounds__(kBlock) void k_col_sqnorm(const T* C, int64_t d, do
 
 // ------------------------------------------------------------------- sweep
 
-// The fused ALM sweep (tile body in device_common.h): one workgroup per
-// (column chunk, row slice), per-workgroup norm partials.
-// The fused ALM sweep (body as sweep_tile) walked in group order: workgroup
-// (s, rb) takes segment s of the label sort (at most kSegCols columns of one group) over one row block.  Beside
-// L, S, Theta and the norms it sums D' = X - S' + Theta' / rho_next over the
-// segment's columns, in the order and arithmetic of the means pass: these are the
-// group sums the next iteration's L-step needs (at rho_next) whenever the p-step
-// keeps every label, so that iteration can skip its means pass.  Slots past the
-// segment count write zero norms.
+// The fused ALM sweep walked in group order (tile body seg_sweep_tile):
+// workgroup (s, rb) takes segment s of the label sort (at most kSegCols columns
+// of one group) over one row block, row blocks varying fastest so that resident
+// workgroups share a band of segments.  Beside L, S, Theta and the norm partials
+// it writes the group sums of D at the next penalty, which let the next
+// iteration skip its means pass when the p-step keeps every label.  Slots past
+// the segment count write zero norms.
 template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     const T* __restrict__ X, int64_t ldx, T* __restrict__ L, int64_t ldl, T* __restrict__ S,
@@ -224,73 +222,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     const int32_t* __restrict__ seg_begin, const int32_t* __restrict__ seg_len,
     const int32_t* __restrict__ nseg, int64_t d, int nrb, T alpha, T beta, T rho, T inv_rho,
     T inv_rho_next, double* __restrict__ norm_partial, double* __restrict__ next_partial) {
-    constexpr int NS = kRowsPerBlock / (kBlock * V);
-    constexpr int U = 4;   // columns in flight per thread
-    const int sg = (int)(blockIdx.x / nrb);             // row blocks vary fastest: the
-    const int64_t r0 = (int64_t)(blockIdx.x % nrb) * kRowsPerBlock;   // resident workgroups
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;                // share a band of segments
+    const int sg = (int)(blockIdx.x / nrb);
+    const int64_t r0 = (int64_t)(blockIdx.x % nrb) * kRowsPerBlock;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (sg < *nseg) {
-        const int begin = seg_begin[sg], len = seg_len[sg];
-        const int64_t p = labels[perm[begin]];
-        double acc[NS][V];
-#pragma unroll
-        for (int a = 0; a < NS; ++a)
-#pragma unroll
-            for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
-        for (int q0 = 0; q0 < len; q0 += U) {
-            int64_t jj[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) jj[u] = q0 + u < len ? perm[begin + q0 + u] : -1;
-#pragma unroll
-            for (int a = 0; a < NS; ++a) {
-                const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
-                if (i >= d) continue;
-                T xs[U][V], ss[U][V], ts[U][V], lps[U][V], m[V];
-                vload<T, V>(C + p * d + i, m);
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (jj[u] < 0) continue;
-                    vload<T, V>(X + jj[u] * ldx + i, xs[u]);
-                    vload<T, V>(S + jj[u] * lds + i, ss[u]);
-                    vload<T, V>(Th + jj[u] * ldt + i, ts[u]);
-                    vload<T, V>(L + jj[u] * ldl + i, lps[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (jj[u] < 0) continue;
-                    const int64_t j = jj[u];
-                    T ln[V], sn[V], tn[V];
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        const T x = xs[u][v], sv = ss[u][v], t = ts[u][v];
-                        const T dv = x - sv + t * inv_rho;
-                        ln[v] = alpha * dv + beta * m[v];
-                        const T b = x - ln[v] + t * inv_rho;
-                        const T mag = fabs(b) - inv_rho;
-                        sn[v] = mag > T(0) ? copysign(mag, b) : T(0);
-                        const T rr = x - ln[v] - sn[v];
-                        tn[v] = t + rho * rr;
-                        const double dl = (double)ln[v] - (double)lps[u][v];
-                        const double ds = (double)sn[v] - (double)sv;
-                        a0 += (double)rr * (double)rr;
-                        a1 += dl * dl;
-                        a2 += ds * ds;
-                        acc[a][v] += (double)(x - sn[v] + tn[v] * inv_rho_next);
-                    }
-                    vstore<T, V>(L + j * ldl + i, ln);
-                    vstore<T, V>(S + j * lds + i, sn);
-                    vstore<T, V>(Th + j * ldt + i, tn);
-                }
-            }
-        }
-        double* out = next_partial + (int64_t)sg * d;
-#pragma unroll
-        for (int a = 0; a < NS; ++a) {
-            const int64_t i = r0 + (int64_t)(a * kBlock + threadIdx.x) * V;
-            if (i < d)
-#pragma unroll
-                for (int v = 0; v < V; ++v) out[i + v] = acc[a][v];
-        }
+        const int begin = seg_begin[sg];
+        seg_sweep_tile<T, V, kRowsPerBlock, 1, 4>(X, ldx, L, ldl, S, lds, Th, ldt, C,
+                                                  labels[perm[begin]], d, perm, begin, seg_len[sg],
+                                                  r0, alpha, beta, rho, inv_rho, inv_rho_next, a0,
+                                                  a1, a2, next_partial + (int64_t)sg * d);
     }
     block_sum3(a0, a1, a2);
     if (threadIdx.x == 0) {
