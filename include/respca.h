@@ -289,8 +289,8 @@ respca_status respca_warmstart_batched(respca_handle h, int32_t hidden, const vo
                                        int32_t *fallback, void *stream);
 
 /* Phase breakdown of the last batched launch: ms[p] for the phases
- * pack, init, seed-distance, seed-draw, seed-gather, sort, means, finalize,
- * sweep, centroid-norms, distance, argmin, control (count <= 13 entries are
+ * pack, init, seed-distance, seed-draw, seed-gather, sort, means, centroids
+ * (with their norms), sweep, distance, argmin, control (count <= 12 entries are
  * written; each is the wall time one workgroup spent in that phase including its
  * barrier wait), and *steps the number of state-machine steps.  Host outputs. */
 respca_status respca_profile_batched_phases(respca_handle h, double *ms, int32_t count,

@@ -9,6 +9,7 @@ namespace respca {
 
 constexpr int kMaxBatch = 1024;   // instances per batched call (LDS-cached work tables)
 constexpr int kBatchRows = 256;   // rows per tile (one wave covers them, 4 per lane)
+constexpr int kBatchSegCols = 64; // max columns of one group segment (means and sweep items)
 
 // One instance.  The static part is written by the host; the state part is
 // owned by the kernel (initialised in its first phases, read back by the host).
@@ -60,7 +61,7 @@ struct BatchInst {
 // Phases of the persistent kernel, for its per-phase timing.
 enum BatchPhase : int {
     BP_PACK = 0, BP_INIT, BP_SEED_D2, BP_SEED_PICK, BP_GATHER, BP_SORT, BP_MEANS, BP_FINALIZE,
-    BP_SWEEP, BP_CNORM, BP_DIST, BP_ARGMIN, BP_CONTROL, BP_COUNT
+    BP_SWEEP, BP_DIST, BP_ARGMIN, BP_CONTROL, BP_COUNT
 };
 
 struct BatchSync {
@@ -83,9 +84,8 @@ struct BatchArgs {
     // prefix tables (batch + 1 entries) of per-instance work items
     const int32_t* off_tile;   // ceil(n/jc) * nrb   (pack, unpack; nrb = ceil(dp/256))
     const int32_t* off_d2;     // ceil(n/4)          (k-means++ distances, wave per column)
-    const int32_t* off_kc;     // c                  (seed columns, centroid norms)
+    const int32_t* off_kc;     // c                  (seed columns, centroids and their norms)
     const int32_t* off_seg;    // (ceil(n/64) + c) * mrb (group partial sums, sweep)
-    const int32_t* off_kr;     // c * ceil(mrows/256) (centroid finalisation)
     const int32_t* off_dist;   // ceil(n/128) * slices * nkc (distance tiles)
     const int32_t* off_col;    // ceil(n/16)         (argmin)
 };

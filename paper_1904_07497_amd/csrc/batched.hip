@@ -132,7 +132,7 @@ __device__ inline int mode_rows(const BatchInst& B, int m) {
 // ------------------------------------------------------- per-instance work
 
 // Stable counting sort of one instance's labels by one workgroup, with the
-// segment table of the means pass (runs of <= kSegCols columns of one group).
+// segment table of the means pass (runs of <= kBatchSegCols columns of one group).
 __device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab) {
     __shared__ int hist[kMaxGroups];
     __shared__ int offs[kMaxGroups];
@@ -149,7 +149,7 @@ __device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab) {
     for (int g = 0; g < 4; ++g) {
         const int k = tid * 4 + g;
         cnt[g] = k < c ? hist[k] : 0;
-        nsg[g] = (cnt[g] + kSegCols - 1) / kSegCols;
+        nsg[g] = (cnt[g] + kBatchSegCols - 1) / kBatchSegCols;
         my_c += cnt[g];
         my_s += nsg[g];
     }
@@ -177,8 +177,8 @@ __device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab) {
             B.counts[k] = cnt[g];
             B.segf[k] = bs;
             for (int q = 0; q < nsg[g]; ++q) {
-                B.segb[bs + q] = bc + q * kSegCols;
-                B.segl[bs + q] = min(kSegCols, cnt[g] - q * kSegCols);
+                B.segb[bs + q] = bc + q * kBatchSegCols;
+                B.segl[bs + q] = min(kBatchSegCols, cnt[g] - q * kBatchSegCols);
             }
             if (k == c - 1) { B.segf[c] = bs + nsg[g]; B.nseg = bs + nsg[g]; }
         }
@@ -580,24 +580,49 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                     B.segb[s], B.segl[s], r0, out);
         });
         if (!grid_sync(gs, nb, tmo, BP_MEANS, tclk)) return;
-        // C: centroids of the non-empty groups
-        load_tab(A.off_kr);
-        for_items(batch, s_tab, s_mode, groups, [&](int i, int local) {
+        // C: centroids (group means; an empty group keeps its centroid, except the
+        //    means of X over given groups, where it is zero) and their squared norms,
+        //    one workgroup per (instance, group)
+        load_tab(A.off_kc);
+        for_items(batch, s_tab, s_mode, [](int m, int) { return needs_groups(m) || needs_assign(m); },
+                  [&](int i, int k) {
             BatchInst& B = inst[i];
             const int mode = s_mode[i];
             const int rows = mode_rows(B, mode);
-            const int nrc = (B.mrows + kBlock - 1) / kBlock;
-            const int k = local / nrc;
-            const int64_t r = (int64_t)(local % nrc) * kBlock + threadIdx.x;
-            if (r >= rows) return;
-            const int nk = B.counts[k];
-            if (nk == 0) {   // an empty group keeps its centroid, except the means of X from given groups
-                if (mode == M_MEANSX) B.C[(int64_t)k * rows + r] = 0.f;
-                return;
+            float* Ck = B.C + (int64_t)k * rows;
+            double a = 0.0, zb = 0.0, zc = 0.0;
+            if (needs_groups(mode)) {
+                const int nk = B.counts[k];
+                const int g0 = B.segf[k], g1 = B.segf[k + 1];
+                for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
+                    float v;
+                    if (nk == 0) {
+                        v = mode == M_MEANSX ? 0.f : Ck[r];
+                        if (mode == M_MEANSX) Ck[r] = 0.f;
+                    } else {
+                        double sum = 0.0;
+                        int g = g0;
+                        for (; g + 4 <= g1; g += 4) {   // four loads in flight, added in order
+                            const double v0 = B.pmeans[(int64_t)g * rows + r];
+                            const double v1 = B.pmeans[(int64_t)(g + 1) * rows + r];
+                            const double v2 = B.pmeans[(int64_t)(g + 2) * rows + r];
+                            const double v3 = B.pmeans[(int64_t)(g + 3) * rows + r];
+                            sum += v0; sum += v1; sum += v2; sum += v3;
+                        }
+                        for (; g < g1; ++g) sum += B.pmeans[(int64_t)g * rows + r];
+                        v = (float)(sum / (double)nk);
+                        Ck[r] = v;
+                    }
+                    a += (double)v * (double)v;
+                }
+            } else {
+                for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
+                    const double x = (double)Ck[r];
+                    a += x * x;
+                }
             }
-            double s = 0.0;
-            for (int g = B.segf[k]; g < B.segf[k + 1]; ++g) s += B.pmeans[(int64_t)g * rows + r];
-            B.C[(int64_t)k * rows + r] = (float)(s / (double)nk);
+            block_sum3(a, zb, zc);
+            if (threadIdx.x == 0) B.cnorm[k] = a;
         });
         if (!grid_sync(gs, nb, tmo, BP_FINALIZE, tclk)) return;
         // D: the fused ALM sweep (instances starting an outer iteration), walked over
@@ -628,20 +653,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             }
         });
         if (!grid_sync(gs, nb, tmo, BP_SWEEP, tclk)) return;
-        // E: squared centroid norms
-        load_tab(A.off_kc);
-        for_items(batch, s_tab, s_mode, assigns, [&](int i, int k) {
-            BatchInst& B = inst[i];
-            const int rows = mode_rows(B, s_mode[i]);
-            double a = 0.0, b = 0.0, c = 0.0;
-            for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
-                const double x = (double)B.C[(int64_t)k * rows + r];
-                a += x * x;
-            }
-            block_sum3(a, b, c);
-            if (threadIdx.x == 0) B.cnorm[k] = a;
-        });
-        if (!grid_sync(gs, nb, tmo, BP_CNORM, tclk)) return;
         // F: distance tiles (columns of X before the iterations, of L after)
         load_tab(A.off_dist);
         for_items(batch, s_tab, s_mode, assigns, [&](int i, int local) {

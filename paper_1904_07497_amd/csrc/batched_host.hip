@@ -20,7 +20,7 @@ using namespace respca;
 
 namespace {
 
-constexpr int kTableCount = 7;
+constexpr int kTableCount = 6;
 constexpr double kBarrierTimeoutS = 4.0;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -131,7 +131,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         const int ntiles = (B.n + 127) / 128;
         B.n_tile = ((B.n + B.jc - 1) / B.jc) * B.nrb;
         B.n_argmin = (B.n + 15) / 16;
-        const int nseg_max = (B.n + kSegCols - 1) / kSegCols + B.c;
+        const int nseg_max = (B.n + kBatchSegCols - 1) / kBatchSegCols + B.c;
         B.n_sweep = nseg_max * B.mrb;
         B.lambda = r.lambda;
         B.tol = r.tol;
@@ -142,7 +142,6 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.max_lloyd = r.max_lloyd;
         // work tables (prefix sums)
         const int64_t counts[kTableCount] = {B.n_tile, (B.n + 3) / 4, B.c, (int64_t)nseg_max * B.mrb,
-                                             (int64_t)B.c * ((B.mrows + kBlock - 1) / kBlock),
                                              (int64_t)ntiles * B.slices * B.nkc, B.n_argmin};
         for (int t = 0; t < kTableCount; ++t)
             call.tables[t][i + 1] = call.tables[t][i] + (int32_t)counts[t];
@@ -255,9 +254,8 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     args.off_d2 = tb + 1 * (batch + 1);
     args.off_kc = tb + 2 * (batch + 1);
     args.off_seg = tb + 3 * (batch + 1);
-    args.off_kr = tb + 4 * (batch + 1);
-    args.off_dist = tb + 5 * (batch + 1);
-    args.off_col = tb + 6 * (batch + 1);
+    args.off_dist = tb + 4 * (batch + 1);
+    args.off_col = tb + 5 * (batch + 1);
 
     uint64_t sig = fnv1a(st, L.header_bytes);
     sig = fnv1a(&nblocks, sizeof(nblocks), sig);

@@ -189,7 +189,16 @@ __global__ __launch_bounds__(kBlock) void k_group_finalize(const double* __restr
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (nk == 0 || i >= d) return;
     double s = 0.0;
-    for (int g = seg_first[k]; g < seg_first[k + 1]; ++g) s += partial[(int64_t)g * d + i];
+    const int g1 = seg_first[k + 1];
+    int g = seg_first[k];
+    for (; g + 4 <= g1; g += 4) {   // four loads in flight, added in segment order
+        const double v0 = partial[(int64_t)g * d + i];
+        const double v1 = partial[(int64_t)(g + 1) * d + i];
+        const double v2 = partial[(int64_t)(g + 2) * d + i];
+        const double v3 = partial[(int64_t)(g + 3) * d + i];
+        s += v0; s += v1; s += v2; s += v3;
+    }
+    for (; g < g1; ++g) s += partial[(int64_t)g * d + i];
     C[(int64_t)k * d + i] = (T)(s / (double)nk);
 }
 

@@ -31,7 +31,7 @@ EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_s
            "respca_warmstart", "respca_warmstart_batched")
 WARM_IN, WARM_OUT = 68, 65
 BATCH_PHASES = ("pack", "init", "seed_distance", "seed_draw", "seed_gather", "sort", "means",
-                "finalize", "sweep", "centroid_norms", "distance", "argmin", "control")
+                "finalize", "sweep", "distance", "argmin", "control")
 KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3, "batched": 4}
 
 
