@@ -12,6 +12,7 @@ namespace respca {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxCand = 8;  // candidate groups kept per near-tied column
 
@@ -86,12 +87,15 @@ struct StageRegs {
                 const int col = p * 32 + (tid >> 3);
                 const int rr = (tid & 7) * 4;
                 const float x[4] = {v4[p].x, v4[p].y, v4[p].z, v4[p].w};
+                bf16x4 h, l;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const __bf16 h = (__bf16)x[e];
-                    hi[col * kStrideH + rr + e] = h;
-                    lo[col * kStrideH + rr + e] = (__bf16)(x[e] - (float)h);
+                    h[e] = (__bf16)x[e];
+                    l[e] = (__bf16)(x[e] - (float)h[e]);
                 }
+                // one 8-byte LDS store per part (rr * 2 bytes is 8-byte aligned)
+                *reinterpret_cast<bf16x4*>(hi + col * kStrideH + rr) = h;
+                *reinterpret_cast<bf16x4*>(lo + col * kStrideH + rr) = l;
             }
         } else {
 #pragma unroll
