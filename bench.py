@@ -244,6 +244,19 @@ def bench_batched(args, wl):
         "roofline": batched_roofline(prof, "batched"),
         "phases_ms": phases,
     }
+    if not args.no_compare:
+        # the plain FP32 method one instance at a time (same parameters) on the first
+        # 64 instances of the mix, for the batching gain
+        m = min(64, len(Xs))
+        for i in range(2):
+            rp.solve(Xs[i], rank=ranks[i], lam=lams[i], tol=wl["tol"], precision=rp.F32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(m):
+            rp.solve(Xs[i], rank=ranks[i], lam=lams[i], tol=wl["tol"], precision=rp.F32)
+        torch.cuda.synchronize()
+        line["sequential_fp32_solves_per_s"] = round(m / (time.perf_counter() - t0), 2)
+        line["sequential_sample"] = f"first {m} instances of the batch, one respca_solve each"
     if not args.no_cpu_baseline:
         dn = [x.shape[0] * x.shape[1] for x in Xh]
         im = int(np.argsort(dn)[len(dn) // 2])

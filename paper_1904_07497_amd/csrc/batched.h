@@ -55,6 +55,7 @@ struct BatchInst {
     // state
     int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, ref_lloyd, status, nseg;
     int next_ready;            // pmeans and the sort tables hold the next L-step's group sums
+    int meansd;                // outer iterations that ran the means pass over X, S, Theta
     double rho, nx, rho_final, primal, dL, dS;
 };
 

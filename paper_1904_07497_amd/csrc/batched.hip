@@ -321,6 +321,7 @@ __device__ void control_instance(BatchInst& B, int* active) {
         return;
     }
     if (mode == M_ITER) {
+        if (!B.next_ready) B.meansd += 1;   // this step's L-step summed D in the means phase
         B.iters += 1;
         B.rho_final = B.rho;
         B.primal = sqrt(a0) / B.nx;
@@ -460,6 +461,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             B.cur = 0;
             B.iters = B.lloyd_total = B.lloyd_iter = B.init_lloyd = B.ref_lloyd = 0;
             B.next_ready = 0;
+            B.meansd = 0;
             B.rho = B.rho0;
             B.rho_final = 0.0;
             B.primal = B.dL = B.dS = 0.0;

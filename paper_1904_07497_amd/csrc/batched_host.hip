@@ -315,12 +315,14 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     for (int i = 0; i < batch; ++i) {
         const BatchInst& B = out[i];
         if (B.status >= 0 && B.nx > 0.0) {
-            // passes over X: ||X||; 3 + 7 + 1 per outer iteration (means of D, sweep,
-            // assignment); 2 per extra Lloyd pass on L; and the start: the means of X for
-            // given labels, seeding (c passes) + nearest-seed assignment + 2 per Lloyd
-            // pass for a cold start, or for an embedding 2 per Lloyd pass on X plus two
-            // means of X, with its seeding and Lloyd passes counted on the embedding
-            double px = 1.0 + 11.0 * B.iters + 2.0 * (B.lloyd_total - B.iters), pz = 0.0;
+            // passes over X: ||X||; 7 + 1 per outer iteration (sweep, assignment) and 3
+            // more for each that ran the means pass (the others had the group sums from
+            // the previous sweep); 2 per extra Lloyd pass on L; and the start: the means
+            // of X for given labels, seeding (c passes) + nearest-seed assignment + 2 per
+            // Lloyd pass for a cold start, or for an embedding 2 per Lloyd pass on X plus
+            // two means of X, with its seeding and Lloyd passes counted on the embedding
+            double px = 1.0 + 8.0 * B.iters + 3.0 * B.meansd + 2.0 * (B.lloyd_total - B.iters);
+            double pz = 0.0;
             if (call.inst[i].init_labels) px += 1.0;
             else if (B.Z) {
                 px += 2.0 + 2.0 * B.ref_lloyd;
