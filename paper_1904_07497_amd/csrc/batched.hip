@@ -29,6 +29,8 @@
 #include "device_common.h"
 #include "dist_tile.h"
 
+static_assert(respca::kBatchSegCols <= respca::kMaxSegCols, "segments must fit the LDS column list");
+
 namespace respca {
 
 namespace {

@@ -68,6 +68,19 @@ __device__ inline void vstore(T* p, const T (&r)[V]) {
     }
 }
 
+// The column indices of one group segment (at most kMaxSegCols), copied from the
+// sort permutation into LDS once per tile so that the column loop does not wait
+// on a global load before each batch of columns.  Every thread must call it.
+constexpr int kMaxSegCols = 64;
+__device__ inline const int32_t* stage_segment_cols(const int32_t* __restrict__ perm, int begin,
+                                                    int len) {
+    __shared__ int32_t cols[kMaxSegCols];
+    __syncthreads();   // the previous tile's readers are done
+    for (int q = threadIdx.x; q < len; q += kBlock) cols[q] = perm[begin + q];
+    __syncthreads();
+    return cols;
+}
+
 // LDS buffer for the column groups' partial sums below, shared by every
 // instantiation (one allocation per kernel).
 constexpr int kGroupRedDoubles = 1024;
@@ -170,6 +183,7 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
     constexpr int NS = ROWS / (TPC * V);
     static_assert(NS >= 1 && NS * TPC * V == ROWS, "row block must tile the column group");
     const int cg = (int)threadIdx.x / TPC, tl = (int)threadIdx.x % TPC;
+    const int32_t* cols = stage_segment_cols(perm, begin, len);
     double acc[NS][V];
 #pragma unroll
     for (int a = 0; a < NS; ++a)
@@ -178,7 +192,7 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
     for (int q0 = cg; q0 < len; q0 += U * CG) {
         int64_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = q0 + u * CG < len ? perm[begin + q0 + u * CG] : -1;
+        for (int u = 0; u < U; ++u) jj[u] = q0 + u * CG < len ? cols[q0 + u * CG] : -1;
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
             const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
@@ -280,11 +294,12 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
             for (int v = 0; v < V; ++v) x[v] = x[v] - sv[v] + tv[v] * inv_rho;
         }
     };
+    const int32_t* cols = stage_segment_cols(perm, begin, len);
     int q = cg;
     for (; q + (U - 1) * CG < len; q += U * CG) {
         int64_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = perm[begin + q + u * CG];
+        for (int u = 0; u < U; ++u) jj[u] = cols[q + u * CG];
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
             const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
@@ -300,7 +315,7 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
         }
     }
     for (; q < len; q += CG) {
-        const int64_t j = perm[begin + q];
+        const int64_t j = cols[q];
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
             const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;

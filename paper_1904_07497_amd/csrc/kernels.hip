@@ -9,6 +9,8 @@
 #include "kernels.h"
 #include "device_common.h"
 
+static_assert(respca::kSegCols <= respca::kMaxSegCols, "segments must fit the LDS column list");
+
 #include <hip/hip_runtime.h>
 
 #include <climits>
