@@ -30,6 +30,37 @@ template <bool VEC>
 struct StageRegs {
     float4 v4[VEC ? 4 : 1];
     float v1[VEC ? 1 : 16];
+    const float* ptr[VEC ? 4 : 1];   // VEC: this thread's four columns at row 0 of the tile's rows
+    unsigned ok = 0;                 // VEC: bit p set when column p lies inside the matrix
+
+    // VEC: fix this thread's four column pointers once per tile (they only move by
+    // rows from stage to stage).
+    __device__ inline void init(const float* __restrict__ src, int64_t ld, int64_t col0,
+                                int64_t ncols) {
+        const int tid = threadIdx.x;
+        ok = 0;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int64_t gj = col0 + p * 32 + (tid >> 3);
+            ptr[p] = src + (tid & 7) * 4;
+            if (gj < ncols) {
+                ok |= 1u << p;
+                ptr[p] += gj * ld;
+            }
+        }
+    }
+
+    // VEC: rows [r, r + 32) of the four columns fixed by init (zero past rend).
+    __device__ inline void load_rows(int64_t r, int64_t rend) {
+        const int64_t rr = (threadIdx.x & 7) * 4;
+        const bool full = r + kRT <= rend;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            v4[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (((ok >> p) & 1u) && (full || r + rr < rend))
+                v4[p] = *reinterpret_cast<const float4*>(ptr[p] + r);
+        }
+    }
 
     __device__ inline void load(const float* __restrict__ src, int64_t ld, int64_t col0,
                                 int64_t ncols, int64_t r, int64_t rend) {
@@ -129,8 +160,10 @@ struct StageRegs {
 
 // One distance tile: columns [j0, j0 + 128) x groups [k0, k0 + 128) over the
 // rows of slice s; writes part[s][j][k] (and, in bf16 mode with write_ynorm,
-// the slice's column sums of squares).  256 threads.
-template <bool VEC, bool BF16>
+// the slice's column sums of squares).  256 threads.  DB: two LDS stage
+// buffers, so a stage's MFMAs and the staging of the next one share one barrier
+// and can overlap (twice the LDS).
+template <bool VEC, bool BF16, bool DB = false>
 __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, int kpad,
                                  const float* __restrict__ Y, int64_t ldy, int64_t n, int slice_rows,
                                  float* __restrict__ part, float* __restrict__ ynorm_part,
@@ -138,13 +171,8 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
     // fp32 mode: Ys, Cs as floats; bf16 mode: hi/lo halves of both operands.
     constexpr size_t kF32Bytes = 2 * kJT * kStride * sizeof(float);
     constexpr size_t kBf16Bytes = 2 * (kJT + kKC) * kStrideH * sizeof(__bf16);
-    __shared__ __attribute__((aligned(16))) char smem[kF32Bytes > kBf16Bytes ? kF32Bytes : kBf16Bytes];
-    float* Ys = reinterpret_cast<float*>(smem);
-    float* Cs = Ys + kJT * kStride;
-    __bf16* Yh = reinterpret_cast<__bf16*>(smem);
-    __bf16* Yl = Yh + kJT * kStrideH;
-    __bf16* Ch = Yl + kJT * kStrideH;
-    __bf16* Cl = Ch + kKC * kStrideH;
+    constexpr size_t kStage = kF32Bytes > kBf16Bytes ? kF32Bytes : kBf16Bytes;
+    __shared__ __attribute__((aligned(16))) char smem[(DB ? 2 : 1) * kStage];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     __syncthreads();   // the LDS tiles may still be read by a previous tile of this workgroup
     const int q = lane & 15, g = lane >> 4;
@@ -163,25 +191,44 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
         for (int b = 0; b < 8; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     StageRegs<VEC> ry, rc;
-    if (r0 < r1) {
-        ry.load(Y, ldy, j0, n, r0, r1);
-        rc.load(C, d, k0, c, r0, r1);
+    if constexpr (VEC) {
+        ry.init(Y, ldy, j0, n);
+        rc.init(C, d, k0, c);
     }
-    for (int64_t r = r0; r < r1; r += kRT) {
+    auto load_stage = [&](int64_t r) {
+        if constexpr (VEC) {
+            ry.load_rows(r, r1);
+            rc.load_rows(r, r1);
+        } else {
+            ry.load(Y, ldy, j0, n, r, r1);
+            rc.load(C, d, k0, c, r, r1);
+        }
+    };
+    // registers -> LDS buffer b (bf16: split into hi/lo, and the columns' sums of squares)
+    auto store_stage = [&](int b) {
+        char* base = smem + (DB ? b * kStage : 0);
         if constexpr (BF16) {
+            __bf16* Yh = reinterpret_cast<__bf16*>(base);
+            __bf16* Yl = Yh + kJT * kStrideH;
+            __bf16* Ch = Yl + kJT * kStrideH;
+            __bf16* Cl = Ch + kKC * kStrideH;
             ry.col_sumsq(ycol);
             ry.store_split(Yh, Yl);
             rc.store_split(Ch, Cl);
         } else {
+            float* Ys = reinterpret_cast<float*>(base);
             ry.store(Ys);
-            rc.store(Cs);
+            rc.store(Ys + kJT * kStride);
         }
-        __syncthreads();
-        if (r + kRT < r1) {                     // next stage's loads overlap this stage's MFMAs
-            ry.load(Y, ldy, j0, n, r + kRT, r1);
-            rc.load(C, d, k0, c, r + kRT, r1);
-        }
+    };
+    // the MFMAs of the stage held in LDS buffer b
+    auto mfma_stage = [&](int b) {
+        const char* base = smem + (DB ? b * kStage : 0);
         if constexpr (BF16) {
+            const __bf16* Yh = reinterpret_cast<const __bf16*>(base);
+            const __bf16* Yl = Yh + kJT * kStrideH;
+            const __bf16* Ch = Yl + kJT * kStrideH;
+            const __bf16* Cl = Ch + kKC * kStrideH;
             // one 16x16x32 instruction covers the stage: lane group g holds rows 8g..8g+7
             bf16x8 ahi[2], alo[2];
 #pragma unroll
@@ -205,6 +252,8 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
                 }
             }
         } else {
+            const float* Ys = reinterpret_cast<const float*>(base);
+            const float* Cs = Ys + kJT * kStride;
             // MFMA step m: lane group g supplies row 8g + m of the stage (same map for both operands)
             float a[2][8];
 #pragma unroll
@@ -221,16 +270,39 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
                     const float* p = Cs + (kb * 16 + q) * kStride + g * 8;
                     const float4 u = *reinterpret_cast<const float4*>(p);
                     const float4 w = *reinterpret_cast<const float4*>(p + 4);
-                    const float b[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
+                    const float b8[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
 #pragma unroll
                     for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
                         for (int m = 0; m < 8; ++m)
-                            acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jb][m], b[m], acc[jb][kb], 0, 0, 0);
+                            acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jb][m], b8[m], acc[jb][kb], 0, 0, 0);
                 }
             }
         }
-        __syncthreads();
+    };
+    if constexpr (DB) {
+        if (r0 < r1) {
+            load_stage(r0);
+            store_stage(0);
+            __syncthreads();
+        }
+        int b = 0;
+        for (int64_t r = r0; r < r1; r += kRT, b ^= 1) {
+            const bool more = r + kRT < r1;
+            if (more) load_stage(r + kRT);      // global loads in flight during the MFMAs
+            mfma_stage(b);
+            if (more) store_stage(b ^ 1);       // the other buffer was released by the last barrier
+            __syncthreads();
+        }
+    } else {
+        if (r0 < r1) load_stage(r0);
+        for (int64_t r = r0; r < r1; r += kRT) {
+            store_stage(0);
+            __syncthreads();
+            if (r + kRT < r1) load_stage(r + kRT);  // next stage's loads overlap this stage's MFMAs
+            mfma_stage(0);
+            __syncthreads();
+        }
     }
     if constexpr (BF16) {
         if (write_ynorm) {

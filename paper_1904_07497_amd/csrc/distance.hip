@@ -40,7 +40,7 @@ __device__ inline double wave_sum_d(double v) {
 }
 
 template <bool VEC, bool BF16>
-__global__ __launch_bounds__(256) void k_dist_mfma(const float* __restrict__ C, int64_t d, int c,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dist_mfma(const float* __restrict__ C, int64_t d, int c,
                                                    int kpad, const float* __restrict__ Y, int64_t ldy,
                                                    int64_t n, int slice_rows,
                                                    float* __restrict__ part,
@@ -48,8 +48,9 @@ __global__ __launch_bounds__(256) void k_dist_mfma(const float* __restrict__ C, 
                                                    int* __restrict__ counters) {
     if (BF16 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < 4)
         counters[threadIdx.x] = 0;   // refinement list length, its changed count: fresh for this pass
-    dist_tile<VEC, BF16>(C, d, c, kpad, Y, ldy, n, slice_rows, part, ynorm_part,
-                         (int64_t)blockIdx.x * kJT, blockIdx.y, blockIdx.z * kKC, blockIdx.z == 0);
+    dist_tile<VEC, BF16, true>(C, d, c, kpad, Y, ldy, n, slice_rows, part, ynorm_part,
+                               (int64_t)blockIdx.x * kJT, blockIdx.y, blockIdx.z * kKC,
+                               blockIdx.z == 0);
 }
 
 // 16 lanes per column: lane q takes groups q, q+16, ...; slices summed in order
