@@ -26,4 +26,17 @@ void launch_adam(int64_t count, float* p, const float* g, float* m, float* v, fl
                  float b2, float eps, int step, hipStream_t st);
 void launch_pool_last(const float* out, int64_t n, double* res, hipStream_t st);
 
+// One instance of a batched warm start: its columns are [off, off + n) of the
+// concatenated sketch / feature / output arrays (entry batch holds off = total).
+struct WarmDesc {
+    const float* X;
+    int64_t ldx, d, n, off, c;
+};
+// Sketch, squared-norm totals (res[2 i]) and features of every instance's columns.
+void launch_sketch_batched(const WarmDesc* D, int batch, int64_t total, uint64_t seed, float* Y,
+                           double* res, float* F, hipStream_t st);
+// Mean of each instance's last network output (res[2 i + 1]).
+void launch_pool_last_batched(const WarmDesc* D, int batch, const float* out, double* res,
+                              hipStream_t st);
+
 }  // namespace respca

@@ -27,13 +27,10 @@ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t t) {
 
 // One wave per column: 64 projections accumulated per lane over its rows, then
 // a butterfly exchange halves the values each lane holds at every stage so that
-// lane k ends with the full sum of projection k.
-__global__ __launch_bounds__(256) void k_sketch(const float* __restrict__ X, int64_t ldx, int64_t d,
-                                                int64_t n, uint64_t seed, float* __restrict__ Y) {
+// lane k ends with the full sum of projection k.  Writes the column's 65 values.
+__device__ inline void sketch_column(const float* __restrict__ x, int64_t d, uint64_t seed,
+                                     float* __restrict__ yj) {
     const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= n) return;
-    const float* x = X + j * ldx;
     float v[64];
 #pragma unroll
     for (int k = 0; k < 64; ++k) v[k] = 0.f;
@@ -57,8 +54,35 @@ __global__ __launch_bounds__(256) void k_sketch(const float* __restrict__ X, int
         }
     }
     nrm = wave_sum(nrm);
-    Y[j * 65 + lane] = v[0];
-    if (lane == 0) Y[j * 65 + 64] = (float)sqrt(nrm);
+    yj[lane] = v[0];
+    if (lane == 0) yj[64] = (float)sqrt(nrm);
+}
+
+__global__ __launch_bounds__(256) void k_sketch(const float* __restrict__ X, int64_t ldx, int64_t d,
+                                                int64_t n, uint64_t seed, float* __restrict__ Y) {
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    sketch_column(X + j * ldx, d, seed, Y + j * 65);
+}
+
+// Instance table of the batched warm start: instance i owns the sketch / feature
+// columns [off, off + n) of the concatenation of all instances.
+__device__ inline int find_instance(const WarmDesc* __restrict__ D, int batch, int64_t col) {
+    int lo = 0, hi = batch;   // D[lo].off <= col < D[hi].off (D[batch].off = total)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (D[mid].off <= col) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_sketch_b(const WarmDesc* __restrict__ D, int batch,
+                                                  int64_t total, uint64_t seed,
+                                                  float* __restrict__ Y) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= total) return;
+    const WarmDesc& w = D[find_instance(D, batch, g)];
+    sketch_column(w.X + (g - w.off) * w.ldx, w.d, seed, Y + g * 65);
 }
 
 // sum_j Y[j][64]^2 (= ||X||_F^2) in double, one workgroup.
@@ -75,22 +99,64 @@ __global__ __launch_bounds__(256) void k_sketch_total(const float* __restrict__ 
 
 // Network inputs of column j: y_j / (s sqrt(d) / 8) (64), log(||X_j|| / (s sqrt(d))),
 // log(d) / 8, log(n) / 8, c / 50 with s = ||X||_F / sqrt(d n).
+__device__ inline float feature_value(const float* __restrict__ yj, int k, int64_t d, int64_t n,
+                                      int64_t c, double total) {
+    const double s = sqrt(total / ((double)d * (double)n));
+    const double col = s * sqrt((double)d);
+    double f;
+    if (k < 64) f = (col > 0.0) ? yj[k] / (0.125 * col) : 0.0;
+    else if (k == 64) f = log((double)yj[64] / (col > 0.0 ? col : 1.0) + 1e-12);
+    else if (k == 65) f = log((double)d) / 8.0;
+    else if (k == 66) f = log((double)n) / 8.0;
+    else f = (double)c / 50.0;
+    return (float)f;
+}
+
 __global__ __launch_bounds__(256) void k_features(const float* __restrict__ Y, int64_t d, int64_t n,
                                                   int c, const double* __restrict__ total,
                                                   float* __restrict__ F) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= n * kWarmIn) return;
     const int64_t j = e / kWarmIn;
-    const int k = (int)(e % kWarmIn);
-    const double s = sqrt(total[0] / ((double)d * (double)n));
-    const double col = s * sqrt((double)d);
-    double f;
-    if (k < 64) f = (col > 0.0) ? Y[j * 65 + k] / (0.125 * col) : 0.0;
-    else if (k == 64) f = log((double)Y[j * 65 + 64] / (col > 0.0 ? col : 1.0) + 1e-12);
-    else if (k == 65) f = log((double)d) / 8.0;
-    else if (k == 66) f = log((double)n) / 8.0;
-    else f = (double)c / 50.0;
-    F[e] = (float)f;
+    F[e] = feature_value(Y + j * 65, (int)(e % kWarmIn), d, n, c, total[0]);
+}
+
+// Batched: one workgroup per instance sums its columns' squared norms (res[2 i]).
+__global__ __launch_bounds__(256) void k_sketch_total_b(const WarmDesc* __restrict__ D,
+                                                        const float* __restrict__ Y,
+                                                        double* __restrict__ res) {
+    const WarmDesc& w = D[blockIdx.x];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t j = threadIdx.x; j < w.n; j += 256) {
+        const double t = Y[(w.off + j) * 65 + 64];
+        a += t * t;
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) res[2 * blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(256) void k_features_b(const WarmDesc* __restrict__ D, int batch,
+                                                    int64_t total, const float* __restrict__ Y,
+                                                    const double* __restrict__ res,
+                                                    float* __restrict__ F) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total * kWarmIn) return;
+    const int64_t g = e / kWarmIn;
+    const int i = find_instance(D, batch, g);
+    const WarmDesc& w = D[i];
+    F[e] = feature_value(Y + g * 65, (int)(e % kWarmIn), w.d, w.n, w.c, res[2 * i]);
+}
+
+// Batched: one workgroup per instance, mean of its columns' last network output
+// (res[2 i + 1]).
+__global__ __launch_bounds__(256) void k_pool_last_b(const WarmDesc* __restrict__ D,
+                                                     const float* __restrict__ out,
+                                                     double* __restrict__ res) {
+    const WarmDesc& w = D[blockIdx.x];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t j = threadIdx.x; j < w.n; j += 256) a += out[(w.off + j) * kWarmOut + kWarmOut - 1];
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) res[2 * blockIdx.x + 1] = a / (double)w.n;
 }
 
 // C(m, n) [+]= sum_k A(m, k) B(k, n) (+ bias[n]) with A(m, k) = A[m*as0 + k*as1],
@@ -300,6 +366,18 @@ void launch_adam(int64_t count, float* p, const float* g, float* m, float* v, fl
 
 void launch_pool_last(const float* out, int64_t n, double* res, hipStream_t st) {
     k_pool_last<<<1, 256, 0, st>>>(out, n, res);
+}
+
+void launch_sketch_batched(const WarmDesc* D, int batch, int64_t total, uint64_t seed, float* Y,
+                           double* res, float* F, hipStream_t st) {
+    k_sketch_b<<<(unsigned)((total + 3) / 4), 256, 0, st>>>(D, batch, total, seed, Y);
+    k_sketch_total_b<<<batch, 256, 0, st>>>(D, Y, res);
+    k_features_b<<<(unsigned)((total * kWarmIn + 255) / 256), 256, 0, st>>>(D, batch, total, Y, res, F);
+}
+
+void launch_pool_last_batched(const WarmDesc* D, int batch, const float* out, double* res,
+                              hipStream_t st) {
+    k_pool_last_b<<<batch, 256, 0, st>>>(D, out, res);
 }
 
 }  // namespace respca

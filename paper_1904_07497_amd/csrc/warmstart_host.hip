@@ -2,6 +2,7 @@
 // and the one-call inference that returns initial labels and rho0.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -170,24 +171,26 @@ respca_status respca_warmstart_batched(respca_handle h, int32_t hidden, const vo
     CKS(ensure(h, h->wfeat, (size_t)kWarmIn * total * sizeof(float)));
     CKS(ensure(h, h->wacts, (size_t)mlp_act_count(hidden, (int)total) * sizeof(float)));
     CKS(ensure(h, h->wred, (size_t)2 * batch * sizeof(double)));
-    CKS(ensure_host(h, (size_t)2 * batch * sizeof(double)));
+    CKS(ensure(h, h->wdesc, (size_t)batch * sizeof(WarmDesc)));
+    const size_t desc_bytes = (size_t)batch * sizeof(WarmDesc);
+    CKS(ensure_host(h, std::max(desc_bytes, (size_t)2 * batch * sizeof(double))));
     float* Y = (float*)h->wsk.p;
     float* F = (float*)h->wfeat.p;
     float* A = (float*)h->wacts.p;
     double* red = (double*)h->wred.p;
+    // instance table, staged through pinned memory (one launch per stage for all instances)
+    WarmDesc* hd = reinterpret_cast<WarmDesc*>(h->hstage);
     int64_t off = 0;
-    for (int i = 0; i < batch; ++i) {   // per instance: sketch and features (own Frobenius scale)
-        launch_sketch((const float*)X[i], ldx[i], d[i], n[i], sketch_seed, Y + 65 * off, st);
-        launch_features(Y + 65 * off, d[i], n[i], c[i], red + 2 * i, F + (int64_t)kWarmIn * off, st);
+    for (int i = 0; i < batch; ++i) {
+        hd[i] = WarmDesc{(const float*)X[i], ldx[i], d[i], n[i], off, c[i]};
         off += n[i];
     }
+    const WarmDesc* D = (const WarmDesc*)h->wdesc.p;
+    CK(hipMemcpyAsync(h->wdesc.p, hd, desc_bytes, hipMemcpyHostToDevice, st));
+    launch_sketch_batched(D, batch, total, sketch_seed, Y, red, F, st);
     launch_mlp_forward((const float*)params, hidden, (int)total, F, A, st);
     const float* out = A + (int64_t)3 * total * hidden;   // total x 65
-    off = 0;
-    for (int i = 0; i < batch; ++i) {
-        launch_pool_last(out + (int64_t)kWarmOut * off, n[i], red + 2 * i + 1, st);
-        off += n[i];
-    }
+    launch_pool_last_batched(D, batch, out, red, st);
     CK(hipMemcpyAsync(embedding, out, (size_t)kWarmOut * total * sizeof(float), hipMemcpyDeviceToDevice, st));
     CK(hipMemcpyAsync(h->hstage, red, 2 * (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
