@@ -693,3 +693,27 @@ def test_warm_started_batched_solve_matches_oracle_chain():
         nX = np.linalg.norm(X.astype(np.float64))
         assert rel(host(outs[i][0]), o["L"], nX) <= F32_TOL
         assert rel(host(outs[i][1]), o["S"], nX) <= F32_TOL
+
+
+def test_embedding_and_batched_warm_start_error_paths():
+    """Invalid embedding shapes and warm-start batches are rejected with clear codes."""
+    X, _, _, _ = synth.clustered(40, 30, 3, seed=1, dtype=np.float32)
+    Xd = dev(X)
+    bad_ld = torch.zeros((8, 30), dtype=torch.float32, device="cuda")[:8]
+    p = rp.make_params(3, 0.5, 1e-6, 50, 1e-4, 1.5, 1e10, 100, 0, rp.F32)
+    p.init_embedding = bad_ld.data_ptr()
+    p.init_embedding_ld = 4          # below the row count
+    p.init_embedding_rows = 8
+    L = rp.empty_colmajor(40, 30, torch.float32, Xd.device)
+    S = rp.empty_colmajor(40, 30, torch.float32, Xd.device)
+    info = rp.Info()
+    h = rp.handle(0)
+    st = rp.lib().respca_solve(h._h, rp.ct.byref(p), 40, 30, Xd.data_ptr(), 40, L.data_ptr(), 40,
+                               S.data_ptr(), 40, None, rp.ct.byref(info), rp._stream(None))
+    assert st == rp.ERR_INVALID
+    from oracle import mlp as omlp
+    P = torch.from_numpy(omlp.init_params([68, 8, 8, 8, 65], 1).astype(np.float32)).cuda()
+    with pytest.raises(rp.RespcaError):
+        rp.warmstart_batched([Xd], [31], P, 8)            # more groups than columns
+    with pytest.raises(rp.RespcaError):
+        rp.warmstart_batched([Xd] * 1025, [3] * 1025, P, 8)   # above the batch limit
