@@ -178,15 +178,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+    // loads run along whichever index is contiguous in memory (uniform choice)
+    const bool a_k_contig = as1 == 1, b_k_contig = bs0 == 1;
     for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int e = tid + 256 * p;        // 1024 = 16 x 64
-            const int kk = e >> 6, mm = e & 63;
-            const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < K) ? A[(int64_t)gm * as0 + (int64_t)gk * as1] : 0.f;
-            const int gn = n0 + mm;
-            Bs[kk][mm] = (gn < N && gk < K) ? B[(int64_t)gk * bs0 + (int64_t)gn * bs1] : 0.f;
+            {
+                const int kk = a_k_contig ? (e & 15) : (e >> 6);
+                const int mm = a_k_contig ? (e >> 4) : (e & 63);
+                const int gm = m0 + mm, gk = k0 + kk;
+                As[kk][mm] = (gm < M && gk < K) ? A[(int64_t)gm * as0 + (int64_t)gk * as1] : 0.f;
+            }
+            {
+                const int kk = b_k_contig ? (e & 15) : (e >> 6);
+                const int nn = b_k_contig ? (e >> 4) : (e & 63);
+                const int gn = n0 + nn, gk = k0 + kk;
+                Bs[kk][nn] = (gn < N && gk < K) ? B[(int64_t)gk * bs0 + (int64_t)gn * bs1] : 0.f;
+            }
         }
         __syncthreads();
 #pragma unroll
