@@ -60,7 +60,7 @@ struct respca_handle_s {
     double bphase_ms[16] = {};      // phase times of the last batched launch
     int64_t bsteps = 0;
     // warm start
-    respca::DevBuf wsk, wfeat, wacts, wscratch, wred, wcent, embl, embc, wdesc;
+    respca::DevBuf wsk, wfeat, wacts, wscratch, wred, wcent, embl, embc, wdesc, whash;
 };
 
 #define CK(expr)                                                                            \

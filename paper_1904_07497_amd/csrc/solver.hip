@@ -523,7 +523,7 @@ void respca_destroy(respca_handle h) {
     if (h->bws.p) (void)hipFree(h->bws.p);
     if (h->bstage) (void)hipHostFree(h->bstage);
     respca::DevBuf* wbufs[] = {&h->wsk, &h->wfeat, &h->wacts, &h->wscratch, &h->wred, &h->wcent,
-                               &h->embl, &h->embc, &h->wdesc};
+                               &h->embl, &h->embc, &h->wdesc, &h->whash};
     for (respca::DevBuf* b : wbufs)
         if (b->p) (void)hipFree(b->p);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,

@@ -31,10 +31,13 @@ void launch_pool_last(const float* out, int64_t n, double* res, hipStream_t st);
 struct WarmDesc {
     const float* X;
     int64_t ldx, d, n, off, c;
+    int64_t toff;   // first of the instance's ceil(n / 16) sketch tiles
 };
-// Sketch, squared-norm totals (res[2 i]) and features of every instance's columns.
-void launch_sketch_batched(const WarmDesc* D, int batch, int64_t total, uint64_t seed, float* Y,
-                           double* res, float* F, hipStream_t st);
+// Sketch, squared-norm totals (res[2 i]) and features of every instance's columns;
+// `hash` is scratch for max_d row hashes (max_d = the largest d).
+void launch_sketch_batched(const WarmDesc* D, int batch, int64_t total, int64_t ntiles,
+                           int64_t max_d, uint64_t* hash, uint64_t seed, float* Y, double* res,
+                           float* F, hipStream_t st);
 // Mean of each instance's last network output (res[2 i + 1]).
 void launch_pool_last_batched(const WarmDesc* D, int batch, const float* out, double* res,
                               hipStream_t st);

@@ -76,13 +76,84 @@ __device__ inline int find_instance(const WarmDesc* __restrict__ D, int batch, i
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_sketch_b(const WarmDesc* __restrict__ D, int batch,
-                                                  int64_t total, uint64_t seed,
-                                                  float* __restrict__ Y) {
-    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (g >= total) return;
-    const WarmDesc& w = D[find_instance(D, batch, g)];
-    sketch_column(w.X + (g - w.off) * w.ldx, w.d, seed, Y + g * 65);
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// h[i] = the i-th counter-based splitmix64 output (the signs of sketch row i).
+__global__ __launch_bounds__(256) void k_row_hash(uint64_t seed, int64_t rows,
+                                                  uint64_t* __restrict__ h) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < rows) h[i] = splitmix64_at(seed, (uint64_t)i);
+}
+
+// Batched sketch on the matrix cores: one wave per tile of 16 columns of one
+// instance computes Y = R X for all 64 sketch rows with v_mfma_f32_16x16x4f32.
+// Lane l (q = l % 16, g = l / 16) feeds column q and, at step e of each 16-row
+// chunk, row i0 + 4 g + e: its B value is that entry of X and its A values are
+// the signs +-1/8 of sketch rows 16 kb + q for that row (bit 16 kb + q of the row's
+// hash); the four lane groups fill the instruction's four K slots.  Column norms
+// are summed in double beside the products.
+__global__ __launch_bounds__(256) void k_sketch_mfma_b(const WarmDesc* __restrict__ D, int batch,
+                                                       int64_t ntiles,
+                                                       const uint64_t* __restrict__ hash,
+                                                       float* __restrict__ Y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    int lo = 0, hi = batch;   // D[lo].toff <= tile < D[hi].toff
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (D[mid].toff <= tile) lo = mid; else hi = mid;
+    }
+    const WarmDesc& w = D[lo];
+    const int q = lane & 15, g = lane >> 4;
+    const int64_t jl = (tile - w.toff) * 16 + q;   // this lane's column in the instance
+    const bool colok = jl < w.n;
+    const float* x = w.X + (colok ? jl : 0) * w.ldx;
+    const bool vec = (w.ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(w.X) & 15) == 0);
+    f32x4 acc[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    double nrm = 0.0;
+    for (int64_t i0 = 0; i0 < w.d; i0 += 16) {
+        const int64_t r = i0 + 4 * g;
+        float xv[4] = {0.f, 0.f, 0.f, 0.f};
+        uint64_t hv[4] = {0, 0, 0, 0};
+        if (vec && r + 4 <= w.d) {
+            if (colok) {
+                const float4 t = *reinterpret_cast<const float4*>(x + r);
+                xv[0] = t.x; xv[1] = t.y; xv[2] = t.z; xv[3] = t.w;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) hv[e] = hash[r + e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (r + e < w.d) {
+                    xv[e] = colok ? x[r + e] : 0.f;
+                    hv[e] = hash[r + e];
+                }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) nrm += (double)xv[e] * (double)xv[e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const float a = ((hv[e] >> (16 * kb + q)) & 1ull) ? -0.125f : 0.125f;
+                acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xv[e], acc[kb], 0, 0, 0);
+            }
+    }
+    nrm += __shfl_xor(nrm, 16);
+    nrm += __shfl_xor(nrm, 32);
+    if (colok) {
+        float* yj = Y + (w.off + jl) * 65;
+        // lane holds rows 4 g + v of each 16 x 16 output block kb, column q
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) yj[16 * kb + 4 * g + v] = acc[kb][v];
+        if (g == 0) yj[64] = (float)sqrt(nrm);
+    }
 }
 
 // sum_j Y[j][64]^2 (= ||X||_F^2) in double, one workgroup.
@@ -377,9 +448,11 @@ void launch_pool_last(const float* out, int64_t n, double* res, hipStream_t st) 
     k_pool_last<<<1, 256, 0, st>>>(out, n, res);
 }
 
-void launch_sketch_batched(const WarmDesc* D, int batch, int64_t total, uint64_t seed, float* Y,
-                           double* res, float* F, hipStream_t st) {
-    k_sketch_b<<<(unsigned)((total + 3) / 4), 256, 0, st>>>(D, batch, total, seed, Y);
+void launch_sketch_batched(const WarmDesc* D, int batch, int64_t total, int64_t ntiles,
+                           int64_t max_d, uint64_t* hash, uint64_t seed, float* Y, double* res,
+                           float* F, hipStream_t st) {
+    k_row_hash<<<(unsigned)((max_d + 255) / 256), 256, 0, st>>>(seed, max_d, hash);
+    k_sketch_mfma_b<<<(unsigned)((ntiles + 3) / 4), 256, 0, st>>>(D, batch, ntiles, hash, Y);
     k_sketch_total_b<<<batch, 256, 0, st>>>(D, Y, res);
     k_features_b<<<(unsigned)((total * kWarmIn + 255) / 256), 256, 0, st>>>(D, batch, total, Y, res, F);
 }

@@ -180,14 +180,18 @@ respca_status respca_warmstart_batched(respca_handle h, int32_t hidden, const vo
     double* red = (double*)h->wred.p;
     // instance table, staged through pinned memory (one launch per stage for all instances)
     WarmDesc* hd = reinterpret_cast<WarmDesc*>(h->hstage);
-    int64_t off = 0;
+    int64_t off = 0, toff = 0, max_d = 1;
     for (int i = 0; i < batch; ++i) {
-        hd[i] = WarmDesc{(const float*)X[i], ldx[i], d[i], n[i], off, c[i]};
+        hd[i] = WarmDesc{(const float*)X[i], ldx[i], d[i], n[i], off, c[i], toff};
         off += n[i];
+        toff += (n[i] + 15) / 16;
+        max_d = std::max(max_d, d[i]);
     }
+    CKS(ensure(h, h->whash, (size_t)max_d * sizeof(uint64_t)));
     const WarmDesc* D = (const WarmDesc*)h->wdesc.p;
     CK(hipMemcpyAsync(h->wdesc.p, hd, desc_bytes, hipMemcpyHostToDevice, st));
-    launch_sketch_batched(D, batch, total, sketch_seed, Y, red, F, st);
+    launch_sketch_batched(D, batch, total, toff, max_d, (uint64_t*)h->whash.p, sketch_seed, Y, red, F,
+                          st);
     launch_mlp_forward((const float*)params, hidden, (int)total, F, A, st);
     const float* out = A + (int64_t)3 * total * hidden;   // total x 65
     launch_pool_last_batched(D, batch, out, red, st);

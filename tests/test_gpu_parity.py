@@ -653,7 +653,7 @@ def test_warmstart_batched_matches_oracle_network():
         assert not fb
         assert r0 == pytest.approx(np.exp(yo[:, 64].mean()) / s, rel=1e-3)
         _, r1, _ = rp.warmstart(dev(X), c, P, hidden, sketch_seed=21)
-        assert r0 == pytest.approx(r1, rel=1e-6)
+        assert r0 == pytest.approx(r1, rel=1e-4)   # batched sketch sums on the matrix cores
 
 
 def test_warm_started_batched_solve_matches_oracle_chain():
