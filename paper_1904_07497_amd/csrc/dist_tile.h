@@ -84,29 +84,29 @@ struct StageRegs {
         }
     }
 
-    // Sum of squares of each staged column's 32 rows, accumulated into acc[]:
-    // VEC: 8 consecutive lanes share a column (acc[p], column p*32 + tid/8, valid
-    // in lanes with tid % 8 == 0); scalar: 32 lanes share a column (acc[p],
-    // column tid/32 + 8p, valid in lanes with tid % 32 == 0).
+    // This thread's share of the sum of squares of each staged column, added to
+    // acc[] (VEC: acc[p] for column p*32 + tid/8, 4 rows per lane; scalar: acc[p]
+    // for column tid/32 + 8p, one row per lane); col_sumsq_reduce completes the
+    // sums across the lanes that share a column once all stages are in.
     __device__ inline void col_sumsq(float* acc) const {
         if constexpr (VEC) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                float t = v4[p].x * v4[p].x + v4[p].y * v4[p].y + v4[p].z * v4[p].z + v4[p].w * v4[p].w;
-                t += __shfl_xor(t, 1);
-                t += __shfl_xor(t, 2);
-                t += __shfl_xor(t, 4);
-                acc[p] += t;
-            }
+            for (int p = 0; p < 4; ++p)
+                acc[p] += v4[p].x * v4[p].x + v4[p].y * v4[p].y + v4[p].z * v4[p].z + v4[p].w * v4[p].w;
         } else {
 #pragma unroll
-            for (int p = 0; p < 16; ++p) {
-                float t = v1[p] * v1[p];
-#pragma unroll
-                for (int o = 1; o < 32; o <<= 1) t += __shfl_xor(t, o);
-                acc[p] += t;
-            }
+            for (int p = 0; p < 16; ++p) acc[p] += v1[p] * v1[p];
         }
+    }
+
+    // Sums the per-lane shares: VEC over the 8 lanes of a column (valid in lanes
+    // with tid % 8 == 0), scalar over its 32 lanes (valid where tid % 32 == 0).
+    static __device__ inline void col_sumsq_reduce(float* acc) {
+        constexpr int kLanes = VEC ? 8 : 32;
+#pragma unroll
+        for (int p = 0; p < (VEC ? 4 : 16); ++p)
+#pragma unroll
+            for (int o = 1; o < kLanes; o <<= 1) acc[p] += __shfl_xor(acc[p], o);
     }
 
     // Store as bf16 high and low parts (x = hi + lo + O(2^-16 x)), stride kStrideH.
@@ -158,16 +158,60 @@ struct StageRegs {
     }
 };
 
+// Centroids already split into bf16 parts: element (k, g) of the [kpad][ldq]
+// array holds rows 4g..4g+3 of group k as {hi[4], lo[4]} (16 bytes), zero past
+// the last row, so a stage is a plain copy into the LDS hi/lo tiles.
+struct SplitStage {
+    uint4 v[4];
+    const uint4* ptr[4];
+    unsigned ok = 0;   // bit p set when group column p lies below kpad
+
+    __device__ inline void init(const uint4* __restrict__ Csp, int64_t ldq, int k0, int kpad) {
+        const int tid = threadIdx.x;
+        ok = 0;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int gk = k0 + p * 32 + (tid >> 3);
+            ptr[p] = Csp + (tid & 7);
+            if (gk < kpad) {
+                ok |= 1u << p;
+                ptr[p] += (int64_t)gk * ldq;
+            }
+        }
+    }
+    // rows [r, r + 32) (r a multiple of 32; the padded rows read as zero)
+    __device__ inline void load_rows(int64_t r) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            v[p] = make_uint4(0u, 0u, 0u, 0u);
+            if ((ok >> p) & 1u) v[p] = ptr[p][r >> 2];
+        }
+    }
+    __device__ inline void store(__bf16* __restrict__ hi, __bf16* __restrict__ lo) const {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int col = p * 32 + (tid >> 3);
+            const int rr = (tid & 7) * 4;
+            *reinterpret_cast<uint2*>(hi + col * kStrideH + rr) = make_uint2(v[p].x, v[p].y);
+            *reinterpret_cast<uint2*>(lo + col * kStrideH + rr) = make_uint2(v[p].z, v[p].w);
+        }
+    }
+};
+
 // One distance tile: columns [j0, j0 + 128) x groups [k0, k0 + 128) over the
 // rows of slice s; writes part[s][j][k] (and, in bf16 mode with write_ynorm,
 // the slice's column sums of squares).  256 threads.  DB: two LDS stage
 // buffers, so a stage's MFMAs and the staging of the next one share one barrier
-// and can overlap (twice the LDS).
-template <bool VEC, bool BF16, bool DB = false>
+// and can overlap (twice the LDS).  CS (bf16 only): the centroids come pre-split
+// from Csp (SplitStage layout, ldq row groups per group) instead of C.
+template <bool VEC, bool BF16, bool DB = false, bool CS = false>
 __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, int kpad,
                                  const float* __restrict__ Y, int64_t ldy, int64_t n, int slice_rows,
                                  float* __restrict__ part, float* __restrict__ ynorm_part,
-                                 int64_t j0, int s, int k0, bool write_ynorm) {
+                                 int64_t j0, int s, int k0, bool write_ynorm,
+                                 const uint4* __restrict__ Csp = nullptr, int64_t ldq = 0) {
+    static_assert(!CS || BF16, "pre-split centroids are bf16 parts");
     // fp32 mode: Ys, Cs as floats; bf16 mode: hi/lo halves of both operands.
     constexpr size_t kF32Bytes = 2 * kJT * kStride * sizeof(float);
     constexpr size_t kBf16Bytes = 2 * (kJT + kKC) * kStrideH * sizeof(__bf16);
@@ -190,19 +234,18 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    StageRegs<VEC> ry, rc;
-    if constexpr (VEC) {
-        ry.init(Y, ldy, j0, n);
-        rc.init(C, d, k0, c);
-    }
+    StageRegs<VEC> ry;
+    StageRegs<VEC> rc;   // unused with CS
+    SplitStage rs;
+    if constexpr (VEC) ry.init(Y, ldy, j0, n);
+    if constexpr (CS) rs.init(Csp, ldq, k0, kpad);
+    else if constexpr (VEC) rc.init(C, d, k0, c);
     auto load_stage = [&](int64_t r) {
-        if constexpr (VEC) {
-            ry.load_rows(r, r1);
-            rc.load_rows(r, r1);
-        } else {
-            ry.load(Y, ldy, j0, n, r, r1);
-            rc.load(C, d, k0, c, r, r1);
-        }
+        if constexpr (VEC) ry.load_rows(r, r1);
+        else ry.load(Y, ldy, j0, n, r, r1);
+        if constexpr (CS) rs.load_rows(r);
+        else if constexpr (VEC) rc.load_rows(r, r1);
+        else rc.load(C, d, k0, c, r, r1);
     };
     // registers -> LDS buffer b (bf16: split into hi/lo, and the columns' sums of squares)
     auto store_stage = [&](int b) {
@@ -214,7 +257,8 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
             __bf16* Cl = Ch + kKC * kStrideH;
             ry.col_sumsq(ycol);
             ry.store_split(Yh, Yl);
-            rc.store_split(Ch, Cl);
+            if constexpr (CS) rs.store(Ch, Cl);
+            else rc.store_split(Ch, Cl);
         } else {
             float* Ys = reinterpret_cast<float*>(base);
             ry.store(Ys);
@@ -306,6 +350,7 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
     }
     if constexpr (BF16) {
         if (write_ynorm) {
+            StageRegs<VEC>::col_sumsq_reduce(ycol);
 #pragma unroll
             for (int p = 0; p < NCOL; ++p) {
                 const int col = VEC ? p * 32 + (tid >> 3) : (tid >> 5) + 8 * p;

@@ -45,12 +45,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                    int64_t n, int slice_rows,
                                                    float* __restrict__ part,
                                                    float* __restrict__ ynorm_part,
-                                                   int* __restrict__ counters) {
+                                                   int* __restrict__ counters,
+                                                   const uint4* __restrict__ Csp, int64_t ldq) {
     if (BF16 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < 4)
         counters[threadIdx.x] = 0;   // refinement list length, its changed count: fresh for this pass
-    dist_tile<VEC, BF16, true>(C, d, c, kpad, Y, ldy, n, slice_rows, part, ynorm_part,
-                               (int64_t)blockIdx.x * kJT, blockIdx.y, blockIdx.z * kKC,
-                               blockIdx.z == 0);
+    dist_tile<VEC, BF16, true, BF16>(C, d, c, kpad, Y, ldy, n, slice_rows, part, ynorm_part,
+                                     (int64_t)blockIdx.x * kJT, blockIdx.y, blockIdx.z * kKC,
+                                     blockIdx.z == 0, Csp, ldq);
+}
+
+// bf16 mode, once per pass: every centroid split into its bf16 parts in the
+// layout the distance tile stages from (rows 4g..4g+3 of group k as {hi[4],
+// lo[4]} at Csp[k * ldq + g], zero past row d and for the padding groups
+// c..kpad-1), and cnorm[k] = ||C_k||^2 in double.  One workgroup per group.
+__global__ __launch_bounds__(1024) void k_split_centroids(const float* __restrict__ C, int64_t d,
+                                                          int c, int64_t ldq, bool vec,
+                                                          uint4* __restrict__ Csp,
+                                                          double* __restrict__ cnorm) {
+    const int k = blockIdx.x;
+    const float* ck = C + (int64_t)k * d;
+    double a = 0.0;
+    for (int64_t g = threadIdx.x; g < ldq; g += 1024) {
+        float x[4] = {0.f, 0.f, 0.f, 0.f};
+        if (k < c && 4 * g < d) {
+            if (vec) {   // d % 4 == 0 and C 16-byte aligned: one load per row group
+                const float4 t = *reinterpret_cast<const float4*>(ck + 4 * g);
+                x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (4 * g + e < d) x[e] = ck[4 * g + e];
+            }
+        }
+        bf16x4 h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            h[e] = (__bf16)x[e];
+            l[e] = (__bf16)(x[e] - (float)h[e]);
+            a += (double)x[e] * (double)x[e];
+        }
+        uint4 v;
+        const uint2 hb = *reinterpret_cast<const uint2*>(&h), lb = *reinterpret_cast<const uint2*>(&l);
+        v.x = hb.x; v.y = hb.y; v.z = lb.x; v.w = lb.y;
+        Csp[(int64_t)k * ldq + g] = v;
+    }
+    a = wave_sum_d(a);
+    __shared__ double sh[16];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0 && k < c) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += sh[w];
+        cnorm[k] = t;
+    }
 }
 
 // 16 lanes per column: lane q takes groups q, q+16, ...; slices summed in order
@@ -392,12 +439,20 @@ DistPlan plan_f32(int64_t d, int64_t n, int c) {
 
 // Workspace layout (float runs): partial dots [slices][n][kpad] | column norm
 // partials [slices][n] | (256-aligned) counters (int x 4) | refinement list [n] |
-// candidates [n][kMaxCand] | (8-aligned) exact distances [n][kMaxCand] (double).
-template <>
-size_t assign_workspace_bytes<float>(int64_t d, int64_t n, int c) {
+// candidates [n][kMaxCand] | (8-aligned) exact distances [n][kMaxCand] (double) |
+// (256-aligned) split centroids [kpad][ldq] x 16 bytes, ldq = ceil(d / 32) * 8.
+int64_t split_ldq(int64_t d) { return (d + kRT - 1) / kRT * (kRT / 4); }
+
+size_t assign_tail_bytes(int64_t d, int64_t n, int c) {
     const DistPlan p = plan_f32(d, n, c);
     return (size_t)p.slices * (size_t)n * (size_t)(p.kpad + 1) * sizeof(float) + 256 + 16 +
            (size_t)n * (1 + kMaxCand) * sizeof(int32_t) + 8 + (size_t)n * kMaxCand * sizeof(double);
+}
+
+template <>
+size_t assign_workspace_bytes<float>(int64_t d, int64_t n, int c) {
+    const DistPlan p = plan_f32(d, n, c);
+    return assign_tail_bytes(d, n, c) + 256 + (size_t)p.kpad * (size_t)split_ldq(d) * sizeof(uint4);
 }
 
 template <>
@@ -407,7 +462,7 @@ size_t assign_workspace_bytes<double>(int64_t d, int64_t n, int c) {
 
 template <>
 int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64_t ldy, int64_t n,
-                         const double* cnorm, const int32_t* old_labels, int32_t* new_labels,
+                         double* cnorm, const int32_t* old_labels, int32_t* new_labels,
                          void* work, double* changed_partial, bool bf16, int* changed_extra,
                          hipStream_t st) {
     const DistPlan p = plan_f32(d, n, c);
@@ -419,27 +474,32 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
     int32_t* list = (int32_t*)(tail + 16);
     int32_t* cand = list + n;
     double* refdist = (double*)(((uintptr_t)(cand + n * kMaxCand) + 7) & ~(uintptr_t)7);
+    uint4* csp = (uint4*)(((uintptr_t)work + assign_tail_bytes(d, n, c) + 255) & ~(uintptr_t)255);
+    const int64_t ldq = split_ldq(d);
     const dim3 grid(p.ntiles, p.slices, p.nkc);
-    const bool vec = (d % 4 == 0) && (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0) &&
-                     (reinterpret_cast<uintptr_t>(C) % 16 == 0);
+    const bool vecy = (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+    const bool vec = vecy && (d % 4 == 0) && (reinterpret_cast<uintptr_t>(C) % 16 == 0);
     const int gb = (int)((n + 15) / 16);
     if (!bf16) {
         if (vec)
             k_dist_mfma<true, false><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows,
-                                                           part, ynorm, counters);
+                                                           part, ynorm, counters, nullptr, 0);
         else
             k_dist_mfma<false, false><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows,
-                                                            part, ynorm, counters);
+                                                            part, ynorm, counters, nullptr, 0);
         k_dist_argmin<<<gb, 256, 0, st>>>(part, p.slices, n, c, p.kpad, cnorm, old_labels,
                                           new_labels, changed_partial);
         return gb;
     }
-    if (vec)
+    // the pre-split centroids replace C in the tiles, so only Y's layout picks the path
+    k_split_centroids<<<p.kpad, 1024, 0, st>>>(
+        C, d, c, ldq, (d % 4 == 0) && (reinterpret_cast<uintptr_t>(C) % 16 == 0), csp, cnorm);
+    if (vecy && d % 4 == 0)
         k_dist_mfma<true, true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
-                                                      ynorm, counters);
+                                                      ynorm, counters, csp, ldq);
     else
         k_dist_mfma<false, true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
-                                                       ynorm, counters);
+                                                       ynorm, counters, csp, ldq);
     // error bound factor (doubled for safety): split products, 3 * 2^-16 per
     // product, plus FP32 accumulation over one slice of rows
     const float eps_rel = (float)(2.0 * (3.0 * std::ldexp(1.0, -16) + p.slice_rows * std::ldexp(1.0, -24)));
@@ -477,7 +537,7 @@ int* assign_refine_counters(void* work, int64_t d, int64_t n, int c) {
 
 template <>
 int launch_assign<double>(const double* C, int64_t d, int c, const double* Y, int64_t ldy,
-                          int64_t n, const double* cnorm, const int32_t* old_labels,
+                          int64_t n, double* cnorm, const int32_t* old_labels,
                           int32_t* new_labels, void* work, double* changed_partial, bool,
                           int* changed_extra, hipStream_t st) {
     if (changed_extra) *changed_extra = 0;

@@ -89,9 +89,11 @@ size_t assign_workspace_bytes(int64_t d, int64_t n, int c);
 // bf16 (float runs only): split-bf16 MFMA contraction with bounded error and
 // exact refinement of near-tied columns; their changes are counted in the int at
 // assign_refine_counters(work)[1] (*changed_extra is set to 1 when that applies).
+// cnorm (||C_k||^2 in double) is an input, except in bf16 mode, where the pass
+// computes it while splitting the centroids.
 template <typename T>
 int launch_assign(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t n,
-                  const double* cnorm, const int32_t* old_labels, int32_t* new_labels, void* work,
+                  double* cnorm, const int32_t* old_labels, int32_t* new_labels, void* work,
                   double* changed_partial, bool bf16, int* changed_extra, hipStream_t st);
 int* assign_refine_counters(void* work, int64_t d, int64_t n, int c);
 // out[0] += counter (or out[0] = counter when set), one thread.

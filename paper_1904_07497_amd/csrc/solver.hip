@@ -205,12 +205,12 @@ struct Engine {
 
     // Assignment pass: new = nearest centroid of every column of Y; status[3] = #changed.
     void assign(const T* Y, int64_t ldy, const T* C, const int32_t* old, int32_t* neu) {
-        launch_col_sqnorm<T>(C, d, c, (double*)h->cnorm.p, st);
+        if (!bf16) launch_col_sqnorm<T>(C, d, c, (double*)h->cnorm.p, st);   // bf16: in the pass
         int g = 0, extra = 0;
         {
             ProfScope ps(h, st, RESPCA_KERNEL_DISTANCE, (double)d * n * sizeof(T),
                          2.0 * (double)c * (double)d * (double)n);
-            g = launch_assign<T>(C, d, c, Y, ldy, n, (const double*)h->cnorm.p, old, neu, h->dots.p,
+            g = launch_assign<T>(C, d, c, Y, ldy, n, (double*)h->cnorm.p, old, neu, h->dots.p,
                                  (double*)h->chgp.p, bf16, &extra, st);
         }
         launch_assign_finish((const double*)h->chgp.p, g,
