@@ -45,6 +45,7 @@ struct respca_handle_s {
     std::vector<hipEvent_t> prof_pool;
     respca::DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, sortbc, pmeans, dots, cnorm,
         lab_a, lab_b, d2, chosen, seeds, u, normp, chgp, status;
+    respca::DevBuf zcopy, zsc, ynorm;   // fp16 copy, column scales and norms for bounded seeding
     double* hstage = nullptr;  // pinned host staging (status readback, uniforms)
     size_t hstage_bytes = 0;
     // batched solver

@@ -108,6 +108,16 @@ inline int64_t assign_partials_max(int64_t n) { return (n + 15) / 16; }
 template <typename T>
 void launch_d2(const T* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* seeds, int m,
                double* d2, hipStream_t st);
+// Bounded k-means++ seeding for float runs: launch_d2_first does the m = 0
+// pass and fills the fp16 copy Z (d2_copy_ld(d) rows per column), its column
+// scales zsc[n] and the column norms ynorm[n]; launch_d2_bounded then does pass
+// m >= 1 with the same results as launch_d2.
+int64_t d2_copy_ld(int64_t d);
+void launch_d2_first(const float* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* seeds,
+                     double* d2, _Float16* Z, float* zsc, double* ynorm, hipStream_t st);
+void launch_d2_bounded(const float* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* seeds,
+                       int m, double* d2, const _Float16* Z, const float* zsc, const double* ynorm,
+                       hipStream_t st);
 void launch_pick(const double* d2, int64_t n, const double* u, int m, int32_t* seeds,
                  int32_t* chosen, hipStream_t st);
 template <typename T>

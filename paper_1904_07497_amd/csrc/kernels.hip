@@ -343,18 +343,21 @@ __global__ __launch_bounds__(kBlock) void k_argmin(const T* __restrict__ part, i
 
 // One wave per column: d2[j] = min(d2[j], ||Y_j - Y_s||^2) in double, s = seeds[m]
 // (the differences of the upcast values are taken in double as well).
-template <typename T, int V>
-__global__ __launch_bounds__(kBlock) void k_d2(const T* __restrict__ Y, int64_t ldy, int64_t d,
-                                               int64_t n, const int32_t* __restrict__ seeds, int m,
-                                               double* __restrict__ d2) {
-    const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (j >= n) return;
-    const int64_t s = seeds[m];
-    const T* yj = Y + j * ldy;
-    const T* ys = Y + s * ldy;
+// ||y_j - y_s||^2 in double, one wave: lane partials over a fixed row order
+// (U loads in flight per lane), then the wave sum.  Every seeding kernel uses
+// this order, so a distance has the same value whichever kernel computes it.
+// STATS: also this lane's share of ||y_j||^2 (nn) and max |y_j| (mx).
+template <typename T, int V, bool STATS = false>
+__device__ inline double d2_column(const T* __restrict__ yj, const T* __restrict__ ys, int64_t d,
+                                   int lane, double* nn = nullptr, float* mx = nullptr) {
     double acc = 0.0;
-    constexpr int U = 4;   // loads in flight per lane; the summation order is unchanged
+    constexpr int U = 4;
+    auto stats = [&](T a) {
+        if constexpr (STATS) {
+            *nn += (double)a * (double)a;
+            *mx = fmaxf(*mx, fabsf((float)a));
+        }
+    };
     int64_t i = (int64_t)lane * V;
     for (; i + (int64_t)64 * V * (U - 1) < d; i += (int64_t)64 * V * U) {
         T a[U][V], b[U][V];
@@ -369,6 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_d2(const T* __restrict__ Y, int64_t 
             for (int v = 0; v < V; ++v) {
                 const double t = (double)a[u][v] - (double)b[u][v];
                 acc += t * t;
+                stats(a[u][v]);
             }
     }
     for (; i < d; i += 64 * V) {
@@ -379,10 +383,128 @@ __global__ __launch_bounds__(kBlock) void k_d2(const T* __restrict__ Y, int64_t 
         for (int v = 0; v < V; ++v) {
             const double t = (double)a[v] - (double)b[v];
             acc += t * t;
+            stats(a[v]);
         }
     }
-    acc = wave_sum(acc);
+    return wave_sum(acc);
+}
+
+// k-means++ D^2 update (Sec. 4.2 initialisation): d2[j] = min(d2[j], ||y_j - y_s||^2)
+// for the newest seed s = seeds[m] (m = 0: the first distances).  One wave per column.
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void k_d2(const T* __restrict__ Y, int64_t ldy, int64_t d,
+                                               int64_t n, const int32_t* __restrict__ seeds, int m,
+                                               double* __restrict__ d2) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const double acc = d2_column<T, V>(Y + j * ldy, Y + (int64_t)seeds[m] * ldy, d, lane);
     if (lane == 0) d2[j] = (m == 0) ? acc : fmin(d2[j], acc);
+}
+
+// Half-precision copy for bounded seeding (float runs).  Column j is stored as
+// z = y_j / sc_j in fp16, sc_j the power of two that puts max |y_j| in
+// [2^14, 2^15) (at least 2^-126), so |z sc_j - y_j| <= 2^-11 |y_j| + 2^-25 sc_j
+// per element; Z has ldz >= d rows, zero past row d.  This first pass also
+// computes the exact distances to seed 0 and the column norms.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_d2_first(const float* __restrict__ Y, int64_t ldy,
+                                                     int64_t d, int64_t n,
+                                                     const int32_t* __restrict__ seeds,
+                                                     double* __restrict__ d2, _Float16* __restrict__ Z,
+                                                     int64_t ldz, float* __restrict__ zsc,
+                                                     double* __restrict__ ynorm) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const float* yj = Y + j * ldy;
+    double nn = 0.0;
+    float mx = 0.f;
+    const double acc = d2_column<float, V, true>(yj, Y + (int64_t)seeds[0] * ldy, d, lane, &nn, &mx);
+    nn = wave_sum(nn);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    int e = mx > 0.f ? ilogbf(mx) - 14 : 0;
+    if (e < -126) e = -126;
+    const float inv = ldexpf(1.f, -e);   // exact: z = y * 2^-e
+    _Float16* zj = Z + j * ldz;
+    typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+    for (int64_t i = (int64_t)lane * 4; i < ldz; i += 256) {   // ldz % 8 == 0: 8-byte stores
+        float x[4];
+        if (V == 4 && i + 4 <= d) {
+            vload<float, 4>(yj + i, x);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[e] = i + e < d ? yj[i + e] : 0.f;
+        }
+        half4 z;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) z[e] = (_Float16)(x[e] * inv);
+        *reinterpret_cast<half4*>(zj + i) = z;
+    }
+    if (lane == 0) {
+        d2[j] = acc;
+        ynorm[j] = sqrt(nn);
+        zsc[j] = ldexpf(1.f, e);
+    }
+}
+
+// Bounded D^2 update for seeds m >= 1 (float runs).  A lower bound on
+// ||y_j - y_s|| comes from the fp16 copy of y_j and the FP32 seed column:
+// sqrt(A / (1 + eta)) - E_j, with A the FP32 sum of (z_i sc_j - y_s,i)^2 (relative
+// error at most eta) and E_j = 2^-10 ||y_j|| + 2^-24 sc_j sqrt(d) the copy's error
+// bound (twice the rounding bound).  When the bound already exceeds d2[j] the
+// minimum cannot change and the exact distance is skipped; otherwise it is
+// computed exactly as in k_d2, so d2 holds the same values either way.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_d2_bounded(const float* __restrict__ Y, int64_t ldy,
+                                                       int64_t d, int64_t n,
+                                                       const int32_t* __restrict__ seeds, int m,
+                                                       double* __restrict__ d2,
+                                                       const _Float16* __restrict__ Z, int64_t ldz,
+                                                       const float* __restrict__ zsc,
+                                                       const double* __restrict__ ynorm, float eta) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const float* ys = Y + (int64_t)seeds[m] * ldy;
+    const _Float16* zj = Z + j * ldz;
+    const float sc = zsc[j];
+    typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+    float acc = 0.f;
+    for (int64_t i = (int64_t)lane * 8; i < d; i += 512) {   // ldz % 8 == 0: 16-byte loads
+        const half8 z = *reinterpret_cast<const half8*>(zj + i);
+        float y[8];
+        if (i + 8 <= d) {
+            if constexpr (V == 4) {
+                const float4 a = *reinterpret_cast<const float4*>(ys + i);
+                const float4 b = *reinterpret_cast<const float4*>(ys + i + 4);
+                y[0] = a.x; y[1] = a.y; y[2] = a.z; y[3] = a.w;
+                y[4] = b.x; y[5] = b.y; y[6] = b.z; y[7] = b.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) y[e] = ys[i + e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) y[e] = i + e < d ? ys[i + e] : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float t = fmaf((float)z[e], sc, -y[e]);
+            acc = fmaf(t, t, acc);
+        }
+    }
+    // A less the largest total of underflowed squares (2^-148 per term), then the
+    // relative error; an infinite or NaN A never skips
+    const double A = wave_sum((double)acc) - (double)d * ldexp(1.0, -148);
+    const double E = (ldexp(1.0, -10) * ynorm[j] + ldexp(1.0, -24) * (double)sc * sqrt((double)d)) *
+                     (1.0 + 1e-6);
+    const double lb = sqrt(fmax(A, 0.0) / (1.0 + (double)eta)) - E;
+    const double cur = d2[j];
+    if (isfinite(A) && lb > 0.0 && lb * lb * (1.0 - 1e-9) > cur) return;   // the minimum stays cur
+    const double ex = d2_column<float, V>(Y + j * ldy, ys, d, lane);
+    if (lane == 0) d2[j] = fmin(cur, ex);
 }
 
 __device__ inline int block_min_i(int v, int* sh) {
@@ -630,6 +752,35 @@ void launch_d2(const T* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* see
         k_d2<T, VV><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2);
     else
         k_d2<T, 1><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2);
+}
+
+int64_t d2_copy_ld(int64_t d) { return (d + 7) / 8 * 8; }
+
+void launch_d2_first(const float* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* seeds,
+                     double* d2, _Float16* Z, float* zsc, double* ynorm, hipStream_t st) {
+    const int per = kBlock / 64;
+    const unsigned g = (unsigned)((n + per - 1) / per);
+    const int64_t ldz = d2_copy_ld(d);
+    if (pick_vec<float>(d, {{Y, ldy}}) == 4)
+        k_d2_first<4><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, d2, Z, ldz, zsc, ynorm);
+    else
+        k_d2_first<1><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, d2, Z, ldz, zsc, ynorm);
+}
+
+void launch_d2_bounded(const float* Y, int64_t ldy, int64_t d, int64_t n, const int32_t* seeds,
+                       int m, double* d2, const _Float16* Z, const float* zsc, const double* ynorm,
+                       hipStream_t st) {
+    const int per = kBlock / 64;
+    const unsigned g = (unsigned)((n + per - 1) / per);
+    // FP32 error of A: per-term rounding (3 units) plus at most 8 ceil(d / 512) lane
+    // additions, doubled
+    const float eta = (float)(2.0 * (3.0 + 8.0 * (double)((d + 511) / 512)) * std::ldexp(1.0, -24));
+    if (pick_vec<float>(d, {{Y, ldy}}) == 4)
+        k_d2_bounded<4><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2, Z, d2_copy_ld(d), zsc,
+                                              ynorm, eta);
+    else
+        k_d2_bounded<1><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2, Z, d2_copy_ld(d), zsc,
+                                              ynorm, eta);
 }
 
 void launch_pick(const double* d2, int64_t n, const double* u, int m, int32_t* seeds,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -260,14 +261,44 @@ struct Engine {
         CK(hipMemcpyAsync(seeds, &hi[0], sizeof(int32_t), hipMemcpyHostToDevice, st));
         CK(hipMemcpyAsync(chosen + s0, &hi[1], sizeof(int32_t), hipMemcpyHostToDevice, st));
         const double pass_bytes = (double)d * n * sizeof(T);
-        {
-            ProfScope ps(h, st, RESPCA_KERNEL_SEEDING, pass_bytes);
-            launch_d2<T>(Y, ldy, d, n, seeds, 0, (double*)h->d2.p, st);
+        // float runs with more than 8 seeds: bounded passes over an fp16 copy of Y
+        // (same D^2 values; the copy costs one extra pass, so few seeds skip it).
+        // Without memory for the copy the plain passes run.
+        bool bounded = false;
+        if constexpr (std::is_same<T, float>::value) {
+            if (c > 8) {
+                bounded = ensure(h, h->zcopy, (size_t)d2_copy_ld(d) * n * sizeof(_Float16)) == RESPCA_OK;
+                if (!bounded) {
+                    (void)hipGetLastError();
+                    h->err.clear();
+                }
+            }
         }
-        for (int m = 1; m < c; ++m) {
-            launch_pick((const double*)h->d2.p, n, (const double*)h->u.p, m, seeds, chosen, st);
-            ProfScope ps(h, st, RESPCA_KERNEL_SEEDING, pass_bytes);
-            launch_d2<T>(Y, ldy, d, n, seeds, m, (double*)h->d2.p, st);
+        if (bounded) {
+            CKS(ensure(h, h->zsc, n * sizeof(float)));
+            CKS(ensure(h, h->ynorm, n * sizeof(double)));
+            {
+                ProfScope ps(h, st, RESPCA_KERNEL_SEEDING, pass_bytes + (double)d * n * sizeof(_Float16));
+                launch_d2_first((const float*)Y, ldy, d, n, seeds, (double*)h->d2.p,
+                                (_Float16*)h->zcopy.p, (float*)h->zsc.p, (double*)h->ynorm.p, st);
+            }
+            for (int m = 1; m < c; ++m) {
+                launch_pick((const double*)h->d2.p, n, (const double*)h->u.p, m, seeds, chosen, st);
+                ProfScope ps(h, st, RESPCA_KERNEL_SEEDING, (double)d * n * sizeof(_Float16));
+                launch_d2_bounded((const float*)Y, ldy, d, n, seeds, m, (double*)h->d2.p,
+                                  (const _Float16*)h->zcopy.p, (const float*)h->zsc.p,
+                                  (const double*)h->ynorm.p, st);
+            }
+        } else {
+            {
+                ProfScope ps(h, st, RESPCA_KERNEL_SEEDING, pass_bytes);
+                launch_d2<T>(Y, ldy, d, n, seeds, 0, (double*)h->d2.p, st);
+            }
+            for (int m = 1; m < c; ++m) {
+                launch_pick((const double*)h->d2.p, n, (const double*)h->u.p, m, seeds, chosen, st);
+                ProfScope ps(h, st, RESPCA_KERNEL_SEEDING, pass_bytes);
+                launch_d2<T>(Y, ldy, d, n, seeds, m, (double*)h->d2.p, st);
+            }
         }
         launch_gather_cols<T>(Y, ldy, d, seeds, c, C, st);
         launch_zero_i32(cur, n, st);
@@ -528,6 +559,7 @@ void respca_destroy(respca_handle h) {
         if (b->p) (void)hipFree(b->p);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
                       &h->nseg, &h->sortbc, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b, &h->d2,
+                      &h->zcopy, &h->zsc, &h->ynorm,
                       &h->chosen, &h->seeds, &h->u, &h->normp, &h->chgp, &h->status};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
