@@ -139,6 +139,85 @@ __global__ __launch_bounds__(256) void k_dist_argmin(const float* __restrict__ p
     if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// dot[t] = sum over the slices, in slice order, of part[s][j][q + 16 t] (zero for
+// groups >= c), and (YN) ynorm = the same sum of ynorm_part[s][j].
+// Four slices' loads are issued before their additions; the loads are
+// unconditional (indices clamped into the buffer, unwanted values zeroed after
+// the load) so that they are not serialised behind branches.
+template <int T, bool YN>
+__device__ inline void sum_slices(const float* __restrict__ part,
+                                  const float* __restrict__ ynorm_part, int nslices, int64_t n,
+                                  int64_t j, int c, int kpad, int q, double (&dot)[T],
+                                  double& ynorm) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) dot[t] = 0.0;
+    ynorm = 0.0;
+    for (int s = 0; s < nslices; s += 4) {
+        float v[4][T], yn[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int su = s + u < nslices ? s + u : nslices - 1;
+            const float* p = part + ((int64_t)su * n + j) * kpad;
+#pragma unroll
+            for (int t = 0; t < T; ++t) v[u][t] = p[q + 16 * t < kpad ? q + 16 * t : kpad - 1];
+            yn[u] = YN ? ynorm_part[(int64_t)su * n + j] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = s + u < nslices;
+#pragma unroll
+            for (int t = 0; t < T; ++t) dot[t] += (ok && q + 16 * t < c) ? (double)v[u][t] : 0.0;
+            ynorm += ok ? (double)yn[u] : 0.0;
+        }
+    }
+}
+
+// FP32 mode, c <= 16 T: the same minimum with each lane's T group sums held in
+// registers (slices summed in the same order).
+template <int T>
+__global__ __launch_bounds__(256) void k_dist_argmin_r(const float* __restrict__ part, int nslices,
+                                                       int64_t n, int c, int kpad,
+                                                       const double* __restrict__ cnorm,
+                                                       const int32_t* __restrict__ old_labels,
+                                                       int32_t* __restrict__ new_labels,
+                                                       double* __restrict__ changed_partial) {
+    __shared__ double sh[4];
+    const int q = threadIdx.x & 15;
+    const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = j < n;
+    double dot[T], ynorm;
+    sum_slices<T, false>(part, nullptr, live ? nslices : 0, n, j, c, kpad, q, dot, ynorm);
+    double bestd = INFINITY;
+    int bestk = INT_MAX;
+    double cn[T];   // loaded unconditionally (clamped), used only below c
+#pragma unroll
+    for (int t = 0; t < T; ++t) cn[t] = cnorm[q + 16 * t < c ? q + 16 * t : c - 1];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int k = q + 16 * t;
+        if (live && k < c) {
+            const double dist = cn[t] - 2.0 * dot[t];
+            if (dist < bestd) { bestd = dist; bestk = k; }
+        }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        const double od = __shfl_xor(bestd, o, 16);
+        const int ok = __shfl_xor(bestk, o, 16);
+        if (od < bestd || (od == bestd && ok < bestk)) { bestd = od; bestk = ok; }
+    }
+    double changed = 0.0;
+    if (live && q == 0) {
+        const int lab = bestk == INT_MAX ? 0 : bestk;
+        new_labels[j] = lab;
+        changed = old_labels[j] != lab ? 1.0 : 0.0;
+    }
+    changed = wave_sum_d(changed);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = changed;
+    __syncthreads();
+    if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
 // bf16 mode: distances with their error bounds.  Lane q of a column's 16
 // lanes takes groups q, q+16, ...  The provisional label is the group with the
 // smallest distance; every group whose distance interval [d - 2E, d + 2E] reaches
@@ -246,29 +325,21 @@ __global__ __launch_bounds__(256) void k_dist_argmin_bounded_r(
     const bool live = j < n;
     double ynorm = 0.0;
     double dot[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) dot[t] = 0.0;
-    if (live)
-        for (int s = 0; s < nslices; ++s) {
-            const float* p = part + ((int64_t)s * n + j) * kpad;
-            float v[T];
-#pragma unroll
-            for (int t = 0; t < T; ++t) v[t] = (q + 16 * t < c) ? p[q + 16 * t] : 0.f;
-#pragma unroll
-            for (int t = 0; t < T; ++t) dot[t] += (double)v[t];
-            ynorm += (double)ynorm_part[(int64_t)s * n + j];
-        }
+    sum_slices<T, true>(part, ynorm_part, live ? nslices : 0, n, j, c, kpad, q, dot, ynorm);
     const double ylen = sqrt(ynorm);
     double dist[T], err[T];
     double bestd = INFINITY, upper = INFINITY;
     int bestk = INT_MAX;
+    double cnv[T];   // loaded unconditionally (clamped), used only below c
+#pragma unroll
+    for (int t = 0; t < T; ++t) cnv[t] = cnorm[q + 16 * t < c ? q + 16 * t : c - 1];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int k = q + 16 * t;
         dist[t] = INFINITY;
         err[t] = 0.0;
         if (live && k < c) {
-            const double cn = cnorm[k];
+            const double cn = cnv[t];
             dist[t] = cn - 2.0 * dot[t];
             err[t] = 2.0 * eps_rel * sqrt(cn) * ylen;
             if (dist[t] < bestd) { bestd = dist[t]; bestk = k; }
@@ -487,8 +558,17 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
         else
             k_dist_mfma<false, false><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows,
                                                             part, ynorm, counters, nullptr, 0);
-        k_dist_argmin<<<gb, 256, 0, st>>>(part, p.slices, n, c, p.kpad, cnorm, old_labels,
-                                          new_labels, changed_partial);
+#define RESPCA_ARGMIN_F(TT)                                                                    \
+    k_dist_argmin_r<TT><<<gb, 256, 0, st>>>(part, p.slices, n, c, p.kpad, cnorm, old_labels,     \
+                                            new_labels, changed_partial)
+        if (c <= 16) RESPCA_ARGMIN_F(1);
+        else if (c <= 32) RESPCA_ARGMIN_F(2);
+        else if (c <= 64) RESPCA_ARGMIN_F(4);
+        else if (c <= 128) RESPCA_ARGMIN_F(8);
+        else
+            k_dist_argmin<<<gb, 256, 0, st>>>(part, p.slices, n, c, p.kpad, cnorm, old_labels,
+                                              new_labels, changed_partial);
+#undef RESPCA_ARGMIN_F
         return gb;
     }
     // the pre-split centroids replace C in the tiles, so only Y's layout picks the path

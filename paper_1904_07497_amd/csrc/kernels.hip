@@ -126,9 +126,16 @@ __global__ __launch_bounds__(kMaxGroups) void k_sort_scan(int32_t* __restrict__ 
                                                          int32_t* nseg_out) {
     __shared__ int wsum[kMaxGroups / 64];
     const int k = threadIdx.x;
+    constexpr int U = 8;   // block counts loaded per step (independent loads in flight)
     int tot = 0;
     if (k < c)
-        for (int b = 0; b < nb; ++b) tot += bc[(int64_t)b * c + k];
+        for (int b = 0; b < nb; b += U) {
+            int v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = b + u < nb ? bc[(int64_t)(b + u) * c + k] : 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) tot += v[u];
+        }
     const int nsg = (tot + kSegCols - 1) / kSegCols;
     const int base = block_exscan_1024(tot, wsum);
     const int sbase = block_exscan_1024(nsg, wsum);
@@ -140,10 +147,15 @@ __global__ __launch_bounds__(kMaxGroups) void k_sort_scan(int32_t* __restrict__ 
             seg_len[sbase + q] = min(kSegCols, tot - q * kSegCols);
         }
         int run = base;
-        for (int b = 0; b < nb; ++b) {
-            const int t = bc[(int64_t)b * c + k];
-            bc[(int64_t)b * c + k] = run;
-            run += t;
+        for (int b = 0; b < nb; b += U) {
+            int v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = b + u < nb ? bc[(int64_t)(b + u) * c + k] : 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (b + u < nb) bc[(int64_t)(b + u) * c + k] = run;
+                run += v[u];
+            }
         }
         if (k == c - 1) { seg_first[c] = sbase + nsg; *nseg_out = sbase + nsg; }
     }
