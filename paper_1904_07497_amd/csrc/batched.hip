@@ -507,30 +507,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             if (j >= B.n) return;
             const float* Y = B.Z ? B.Z : B.X;
             const int rows = B.kdp;
-            const float* yj = Y + j * rows;
-            const float* ys = Y + (int64_t)B.seeds[m] * rows;
-            double acc0 = 0.0, acc1 = 0.0;
-            int64_t r = lane * 4;
-            for (; r + 256 < rows; r += 512) {        // two rows groups in flight
-                const float4 a0 = *reinterpret_cast<const float4*>(yj + r);
-                const float4 b0 = *reinterpret_cast<const float4*>(ys + r);
-                const float4 a1 = *reinterpret_cast<const float4*>(yj + r + 256);
-                const float4 b1 = *reinterpret_cast<const float4*>(ys + r + 256);
-                const double e0 = (double)a0.x - b0.x, e1 = (double)a0.y - b0.y;
-                const double e2 = (double)a0.z - b0.z, e3 = (double)a0.w - b0.w;
-                const double f0 = (double)a1.x - b1.x, f1 = (double)a1.y - b1.y;
-                const double f2 = (double)a1.z - b1.z, f3 = (double)a1.w - b1.w;
-                acc0 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
-                acc1 += f0 * f0 + f1 * f1 + f2 * f2 + f3 * f3;
-            }
-            if (r < rows) {
-                const float4 a0 = *reinterpret_cast<const float4*>(yj + r);
-                const float4 b0 = *reinterpret_cast<const float4*>(ys + r);
-                const double e0 = (double)a0.x - b0.x, e1 = (double)a0.y - b0.y;
-                const double e2 = (double)a0.z - b0.z, e3 = (double)a0.w - b0.w;
-                acc0 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
-            }
-            double acc = wave_sum(acc0 + acc1);
+            // rows is a multiple of 4 (zero padded): four row groups of float4 in flight
+            const double acc = d2_column<float, 4>(Y + j * rows, Y + (int64_t)B.seeds[m] * rows, rows, lane);
             if (lane == 0) B.d2[j] = (m == 0) ? acc : fmin(B.d2[j], acc);
         });
         if (!grid_sync(gs, nb, tmo, BP_SEED_D2, tclk)) return;
@@ -605,15 +583,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                         if (mode == M_MEANSX) Ck[r] = 0.f;
                     } else {
                         double sum = 0.0;
-                        int g = g0;
-                        for (; g + 4 <= g1; g += 4) {   // four loads in flight, added in order
-                            const double v0 = B.pmeans[(int64_t)g * rows + r];
-                            const double v1 = B.pmeans[(int64_t)(g + 1) * rows + r];
-                            const double v2 = B.pmeans[(int64_t)(g + 2) * rows + r];
-                            const double v3 = B.pmeans[(int64_t)(g + 3) * rows + r];
-                            sum += v0; sum += v1; sum += v2; sum += v3;
+                        for (int g = g0; g < g1; g += 4) {   // four loads in flight, added in order
+                            double v[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)      // clamped: no branch per load
+                                v[u] = B.pmeans[(int64_t)(g + u < g1 ? g + u : g1 - 1) * rows + r];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (g + u < g1) sum += v[u];
                         }
-                        for (; g < g1; ++g) sum += B.pmeans[(int64_t)g * rows + r];
                         v = (float)(sum / (double)nk);
                         Ck[r] = v;
                     }
@@ -678,14 +656,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             const int64_t j = (int64_t)local * 16 + (threadIdx.x >> 4);
             double bestd = INFINITY;
             int bestk = INT_MAX;
-            if (j < B.n)
-                for (int k = q; k < B.c; k += 16) {
-                    double dot = 0.0;
-                    for (int s = 0; s < B.slices; ++s)
-                        dot += (double)B.part[((int64_t)s * B.n + j) * B.kpad + k];
-                    const double dist = B.cnorm[k] - 2.0 * dot;
-                    if (dist < bestd) { bestd = dist; bestk = k; }
+            // 64 groups per chunk: each lane's four slice sums come from batched loads
+            for (int k0 = 0; k0 < B.c; k0 += 64) {
+                double dot[4], yn;
+                sum_slices<4, false>(B.part, nullptr, j < B.n ? B.slices : 0, B.n, j, B.c, B.kpad,
+                                     k0 + q, dot, yn);
+                double cn[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = k0 + q + 16 * t;
+                    cn[t] = B.cnorm[k < B.c ? k : B.c - 1];
                 }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = k0 + q + 16 * t;
+                    if (j < B.n && k < B.c) {
+                        const double dist = cn[t] - 2.0 * dot[t];
+                        if (dist < bestd) { bestd = dist; bestk = k; }
+                    }
+                }
+            }
 #pragma unroll
             for (int o = 8; o > 0; o >>= 1) {
                 const double od = __shfl_xor(bestd, o, 16);

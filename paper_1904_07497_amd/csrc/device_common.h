@@ -68,6 +68,52 @@ __device__ inline void vstore(T* p, const T (&r)[V]) {
     }
 }
 
+// ||y_j - y_s||^2 in double, one wave: lane partials over a fixed row order
+// (U loads in flight per lane), then the wave sum.  Every seeding kernel uses
+// this order, so a distance has the same value whichever kernel computes it.
+// STATS: also this lane's share of ||y_j||^2 (nn) and max |y_j| (mx).
+template <typename T, int V, bool STATS = false>
+__device__ inline double d2_column(const T* __restrict__ yj, const T* __restrict__ ys, int64_t d,
+                                   int lane, double* nn = nullptr, float* mx = nullptr) {
+    double acc = 0.0;
+    constexpr int U = 4;
+    auto stats = [&](T a) {
+        if constexpr (STATS) {
+            *nn += (double)a * (double)a;
+            *mx = fmaxf(*mx, fabsf((float)a));
+        }
+    };
+    int64_t i = (int64_t)lane * V;
+    for (; i + (int64_t)64 * V * (U - 1) < d; i += (int64_t)64 * V * U) {
+        T a[U][V], b[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vload<T, V>(yj + i + (int64_t)64 * V * u, a[u]);
+            vload<T, V>(ys + i + (int64_t)64 * V * u, b[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const double t = (double)a[u][v] - (double)b[u][v];
+                acc += t * t;
+                stats(a[u][v]);
+            }
+    }
+    for (; i < d; i += 64 * V) {
+        T a[V], b[V];
+        vload<T, V>(yj + i, a);
+        vload<T, V>(ys + i, b);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const double t = (double)a[v] - (double)b[v];
+            acc += t * t;
+            stats(a[v]);
+        }
+    }
+    return wave_sum(acc);
+}
+
 // The column indices of one group segment (at most kMaxSegCols), copied from the
 // sort permutation into LDS once per tile so that the column loop does not wait
 // on a global load before each batch of columns.  Every thread must call it.

@@ -376,4 +376,39 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
 }
 
 
+// dot[t] = sum over the slices, in slice order, of part[s][j][q + 16 t] (zero for
+// groups >= c; q may include a group offset), and (YN) ynorm = the same sum of
+// ynorm_part[s][j].
+// Four slices' loads are issued before their additions; the loads are
+// unconditional (indices clamped into the buffer, unwanted values zeroed after
+// the load) so that they are not serialised behind branches.
+template <int T, bool YN>
+__device__ inline void sum_slices(const float* __restrict__ part,
+                                  const float* __restrict__ ynorm_part, int nslices, int64_t n,
+                                  int64_t j, int c, int kpad, int q, double (&dot)[T],
+                                  double& ynorm) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) dot[t] = 0.0;
+    ynorm = 0.0;
+    for (int s = 0; s < nslices; s += 4) {
+        float v[4][T], yn[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int su = s + u < nslices ? s + u : nslices - 1;
+            const float* p = part + ((int64_t)su * n + j) * kpad;
+#pragma unroll
+            for (int t = 0; t < T; ++t) v[u][t] = p[q + 16 * t < kpad ? q + 16 * t : kpad - 1];
+            yn[u] = YN ? ynorm_part[(int64_t)su * n + j] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = s + u < nslices;
+#pragma unroll
+            for (int t = 0; t < T; ++t) dot[t] += (ok && q + 16 * t < c) ? (double)v[u][t] : 0.0;
+            ynorm += ok ? (double)yn[u] : 0.0;
+        }
+    }
+}
+
+
 }  // namespace respca

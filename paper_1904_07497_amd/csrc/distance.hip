@@ -139,39 +139,6 @@ __global__ __launch_bounds__(256) void k_dist_argmin(const float* __restrict__ p
     if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// dot[t] = sum over the slices, in slice order, of part[s][j][q + 16 t] (zero for
-// groups >= c), and (YN) ynorm = the same sum of ynorm_part[s][j].
-// Four slices' loads are issued before their additions; the loads are
-// unconditional (indices clamped into the buffer, unwanted values zeroed after
-// the load) so that they are not serialised behind branches.
-template <int T, bool YN>
-__device__ inline void sum_slices(const float* __restrict__ part,
-                                  const float* __restrict__ ynorm_part, int nslices, int64_t n,
-                                  int64_t j, int c, int kpad, int q, double (&dot)[T],
-                                  double& ynorm) {
-#pragma unroll
-    for (int t = 0; t < T; ++t) dot[t] = 0.0;
-    ynorm = 0.0;
-    for (int s = 0; s < nslices; s += 4) {
-        float v[4][T], yn[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int su = s + u < nslices ? s + u : nslices - 1;
-            const float* p = part + ((int64_t)su * n + j) * kpad;
-#pragma unroll
-            for (int t = 0; t < T; ++t) v[u][t] = p[q + 16 * t < kpad ? q + 16 * t : kpad - 1];
-            yn[u] = YN ? ynorm_part[(int64_t)su * n + j] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool ok = s + u < nslices;
-#pragma unroll
-            for (int t = 0; t < T; ++t) dot[t] += (ok && q + 16 * t < c) ? (double)v[u][t] : 0.0;
-            ynorm += ok ? (double)yn[u] : 0.0;
-        }
-    }
-}
-
 // FP32 mode, c <= 16 T: the same minimum with each lane's T group sums held in
 // registers (slices summed in the same order).
 template <int T>
@@ -410,25 +377,37 @@ __global__ __launch_bounds__(256) void k_refine_dist(const float* __restrict__ C
     __shared__ double sh[4];
     const int count = counters[0];
     const int t = blockIdx.y;
+    static_assert(kMaxCand == 8, "candidate rows are read as two int4");
     for (int item = blockIdx.x; item < count; item += gridDim.x) {
         const int64_t j = list[item];
         // entries after the end marker (-2) are stale; -1 (every group) is handled per wave
+        const int4* row = reinterpret_cast<const int4*>(cand + j * kMaxCand);
+        const int4 c0 = row[0], c1 = row[1];
+        const int cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
         bool valid = true;
-        for (int u = 0; u <= t; ++u) valid = valid && cand[j * kMaxCand + u] >= 0;
-        const int k = valid ? cand[j * kMaxCand + t] : -1;   // uniform across the workgroup
+#pragma unroll
+        for (int u = 0; u < 8; ++u) valid = valid && (u > t || cv[u] >= 0);
+        int k = -1;   // uniform across the workgroup
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (u == t && valid) k = cv[u];
         if (k < 0 || k >= c) continue;
         const float* y = Y + j * ldy;
         const float* ck = C + (int64_t)k * d;
         double acc = 0.0;
         for (int64_t i = threadIdx.x; i < d; i += 1024) {
-            double e[4];
+            float a[4], b[4];   // loads clamped into the column, tails zeroed after
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int64_t ii = i + 256 * u;
-                e[u] = ii < d ? (double)y[ii] - (double)ck[ii] : 0.0;
+                const int64_t ii = i + 256 * u < d ? i + 256 * u : d - 1;
+                a[u] = y[ii];
+                b[u] = ck[ii];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc += e[u] * e[u];
+            for (int u = 0; u < 4; ++u) {
+                const double e = i + 256 * u < d ? (double)a[u] - (double)b[u] : 0.0;
+                acc += e * e;
+            }
         }
         acc = wave_sum_d(acc);
         __syncthreads();
@@ -470,11 +449,16 @@ __global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ C
             if (acc < best) { best = acc; bestk = k; }
         }
     } else {
-        for (int t = 0; t < kMaxCand; ++t) {
-            const int k = cj[t];
-            if (k < 0) break;
-            const double dist = refdist[(int64_t)item * kMaxCand + t];
-            if (dist < best || (dist == best && k < bestk)) { best = dist; bestk = k; }
+        const int4 c0 = reinterpret_cast<const int4*>(cj)[0], c1 = reinterpret_cast<const int4*>(cj)[1];
+        const int cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+        double dv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) dv[t] = refdist[(int64_t)item * kMaxCand + t];
+        bool live = true;   // candidates up to the first end marker
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            live = live && cv[t] >= 0;
+            if (live && (dv[t] < best || (dv[t] == best && cv[t] < bestk))) { best = dv[t]; bestk = cv[t]; }
         }
     }
     if (lane == 0) {
@@ -510,14 +494,15 @@ DistPlan plan_f32(int64_t d, int64_t n, int c) {
 
 // Workspace layout (float runs): partial dots [slices][n][kpad] | column norm
 // partials [slices][n] | (256-aligned) counters (int x 4) | refinement list [n] |
-// candidates [n][kMaxCand] | (8-aligned) exact distances [n][kMaxCand] (double) |
+// (16-aligned) candidates [n][kMaxCand] | (8-aligned) exact distances [n][kMaxCand] (double) |
 // (256-aligned) split centroids [kpad][ldq] x 16 bytes, ldq = ceil(d / 32) * 8.
 int64_t split_ldq(int64_t d) { return (d + kRT - 1) / kRT * (kRT / 4); }
 
 size_t assign_tail_bytes(int64_t d, int64_t n, int c) {
     const DistPlan p = plan_f32(d, n, c);
     return (size_t)p.slices * (size_t)n * (size_t)(p.kpad + 1) * sizeof(float) + 256 + 16 +
-           (size_t)n * (1 + kMaxCand) * sizeof(int32_t) + 8 + (size_t)n * kMaxCand * sizeof(double);
+           (size_t)n * (1 + kMaxCand) * sizeof(int32_t) + 16 + 8 +
+           (size_t)n * kMaxCand * sizeof(double);
 }
 
 template <>
@@ -543,7 +528,7 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
     tail = (char*)(((uintptr_t)tail + 255) & ~(uintptr_t)255);
     int* counters = (int*)tail;                       // [0] list length, [1] refined changes
     int32_t* list = (int32_t*)(tail + 16);
-    int32_t* cand = list + n;
+    int32_t* cand = (int32_t*)(((uintptr_t)(list + n) + 15) & ~(uintptr_t)15);   // rows read as int4
     double* refdist = (double*)(((uintptr_t)(cand + n * kMaxCand) + 7) & ~(uintptr_t)7);
     uint4* csp = (uint4*)(((uintptr_t)work + assign_tail_bytes(d, n, c) + 255) & ~(uintptr_t)255);
     const int64_t ldq = split_ldq(d);

@@ -204,15 +204,15 @@ __global__ __launch_bounds__(kBlock) void k_group_finalize(const double* __restr
     if (nk == 0 || i >= d) return;
     double s = 0.0;
     const int g1 = seg_first[k + 1];
-    int g = seg_first[k];
-    for (; g + 4 <= g1; g += 4) {   // four loads in flight, added in segment order
-        const double v0 = partial[(int64_t)g * d + i];
-        const double v1 = partial[(int64_t)(g + 1) * d + i];
-        const double v2 = partial[(int64_t)(g + 2) * d + i];
-        const double v3 = partial[(int64_t)(g + 3) * d + i];
-        s += v0; s += v1; s += v2; s += v3;
+    for (int g = seg_first[k]; g < g1; g += 4) {   // four loads in flight, added in segment order
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)                  // clamped: no branch per load
+            v[u] = partial[(int64_t)(g + u < g1 ? g + u : g1 - 1) * d + i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (g + u < g1) s += v[u];
     }
-    for (; g < g1; ++g) s += partial[(int64_t)g * d + i];
     C[(int64_t)k * d + i] = (T)(s / (double)nk);
 }
 
@@ -355,52 +355,6 @@ __global__ __launch_bounds__(kBlock) void k_argmin(const T* __restrict__ part, i
 
 // One wave per column: d2[j] = min(d2[j], ||Y_j - Y_s||^2) in double, s = seeds[m]
 // (the differences of the upcast values are taken in double as well).
-// ||y_j - y_s||^2 in double, one wave: lane partials over a fixed row order
-// (U loads in flight per lane), then the wave sum.  Every seeding kernel uses
-// this order, so a distance has the same value whichever kernel computes it.
-// STATS: also this lane's share of ||y_j||^2 (nn) and max |y_j| (mx).
-template <typename T, int V, bool STATS = false>
-__device__ inline double d2_column(const T* __restrict__ yj, const T* __restrict__ ys, int64_t d,
-                                   int lane, double* nn = nullptr, float* mx = nullptr) {
-    double acc = 0.0;
-    constexpr int U = 4;
-    auto stats = [&](T a) {
-        if constexpr (STATS) {
-            *nn += (double)a * (double)a;
-            *mx = fmaxf(*mx, fabsf((float)a));
-        }
-    };
-    int64_t i = (int64_t)lane * V;
-    for (; i + (int64_t)64 * V * (U - 1) < d; i += (int64_t)64 * V * U) {
-        T a[U][V], b[U][V];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            vload<T, V>(yj + i + (int64_t)64 * V * u, a[u]);
-            vload<T, V>(ys + i + (int64_t)64 * V * u, b[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const double t = (double)a[u][v] - (double)b[u][v];
-                acc += t * t;
-                stats(a[u][v]);
-            }
-    }
-    for (; i < d; i += 64 * V) {
-        T a[V], b[V];
-        vload<T, V>(yj + i, a);
-        vload<T, V>(ys + i, b);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const double t = (double)a[v] - (double)b[v];
-            acc += t * t;
-            stats(a[v]);
-        }
-    }
-    return wave_sum(acc);
-}
-
 // k-means++ D^2 update (Sec. 4.2 initialisation): d2[j] = min(d2[j], ||y_j - y_s||^2)
 // for the newest seed s = seeds[m] (m = 0: the first distances).  One wave per column.
 template <typename T, int V>
