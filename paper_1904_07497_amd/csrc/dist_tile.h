@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace respca {
 
@@ -31,34 +32,44 @@ struct StageRegs {
     float4 v4[VEC ? 4 : 1];
     float v1[VEC ? 1 : 16];
     const float* ptr[VEC ? 4 : 1];   // VEC: this thread's four columns at row 0 of the tile's rows
-    unsigned ok = 0;                 // VEC: bit p set when column p lies inside the matrix
 
     // VEC: fix this thread's four column pointers once per tile (they only move by
-    // rows from stage to stage).
+    // rows from stage to stage).  Columns past the matrix are clamped to its last
+    // column: their products only reach outputs of those columns, which nobody
+    // reads, and every load stays unconditional (no branch splits the count of
+    // loads in flight).
     __device__ inline void init(const float* __restrict__ src, int64_t ld, int64_t col0,
                                 int64_t ncols) {
         const int tid = threadIdx.x;
-        ok = 0;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const int64_t gj = col0 + p * 32 + (tid >> 3);
-            ptr[p] = src + (tid & 7) * 4;
-            if (gj < ncols) {
-                ok |= 1u << p;
-                ptr[p] += gj * ld;
-            }
+            int64_t gj = col0 + p * 32 + (tid >> 3);
+            if (gj >= ncols) gj = ncols - 1;
+            ptr[p] = src + (tid & 7) * 4 + gj * ld;
         }
     }
 
-    // VEC: rows [r, r + 32) of the four columns fixed by init (zero past rend).
-    __device__ inline void load_rows(int64_t r, int64_t rend) {
-        const int64_t rr = (threadIdx.x & 7) * 4;
-        const bool full = r + kRT <= rend;
+    // VEC: rows [r, r + 32) of the four columns fixed by init (zero past rend;
+    // rend and the row offsets are multiples of 4).  A full stage loads without
+    // conditions; the last partial stage reads row 0 in place of the rows past
+    // rend and zeroes them.
+    // VEC: a stage known to lie inside the rows (r + 32 <= rend).
+    __device__ inline void load_rows_full(int64_t r) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            v4[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (((ok >> p) & 1u) && (full || r + rr < rend))
-                v4[p] = *reinterpret_cast<const float4*>(ptr[p] + r);
+        for (int p = 0; p < 4; ++p) v4[p] = *reinterpret_cast<const float4*>(ptr[p] + r);
+    }
+
+    __device__ inline void load_rows(int64_t r, int64_t rend) {
+        if (r + kRT <= rend) {
+            load_rows_full(r);
+        } else {
+            const int64_t rr = (threadIdx.x & 7) * 4;
+            const bool in = r + rr < rend;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const float4 t = *reinterpret_cast<const float4*>(in ? ptr[p] + r : ptr[p] - rr);
+                v4[p] = in ? t : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
     }
 
@@ -161,38 +172,41 @@ struct StageRegs {
 // Centroids already split into bf16 parts: element (k, g) of the [kpad][ldq]
 // array holds rows 4g..4g+3 of group k as {hi[4], lo[4]} (16 bytes), zero past
 // the last row, so a stage is a plain copy into the LDS hi/lo tiles.
+// NT threads share the stage: thread t takes row group t % 8 of group columns
+// t / 8 + (NT / 8) p, p < 1024 / NT.
+template <int NT = 256>
 struct SplitStage {
-    uint4 v[4];
-    const uint4* ptr[4];
-    unsigned ok = 0;   // bit p set when group column p lies below kpad
+    static constexpr int P = 1024 / NT;
+    static_assert(P >= 1 && P * NT == 1024, "128 groups x 8 row groups per stage");
+    uint4 v[P];
+    const uint4* ptr[P];
 
+    // group columns past kpad are clamped to the last one (no MFMA reads them)
     __device__ inline void init(const uint4* __restrict__ Csp, int64_t ldq, int k0, int kpad) {
         const int tid = threadIdx.x;
-        ok = 0;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int gk = k0 + p * 32 + (tid >> 3);
-            ptr[p] = Csp + (tid & 7);
-            if (gk < kpad) {
-                ok |= 1u << p;
-                ptr[p] += (int64_t)gk * ldq;
-            }
+        for (int p = 0; p < P; ++p) {
+            int gk = k0 + p * (NT / 8) + (tid >> 3);
+            if (gk >= kpad) gk = kpad - 1;
+            ptr[p] = Csp + (tid & 7) + (int64_t)gk * ldq;
         }
     }
     // rows [r, r + 32) (r a multiple of 32; the padded rows read as zero)
     __device__ inline void load_rows(int64_t r) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            v[p] = make_uint4(0u, 0u, 0u, 0u);
-            if ((ok >> p) & 1u) v[p] = ptr[p][r >> 2];
-        }
+        for (int p = 0; p < P; ++p) v[p] = ptr[p][r >> 2];
     }
+    // PERM: row group rg (rows 4rg..4rg+3) goes to position 8 (rg % 4) + 4 (rg / 4),
+    // so that the 8 values at 8g..8g+7 are rows 4g..4g+3 and 16+4g..16+4g+3
+    // (the row order of the direct tile's K slots).
+    template <bool PERM = false>
     __device__ inline void store(__bf16* __restrict__ hi, __bf16* __restrict__ lo) const {
         const int tid = threadIdx.x;
+        const int rg = tid & 7;
+        const int rr = PERM ? 8 * (rg & 3) + 4 * (rg >> 2) : 4 * rg;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int col = p * 32 + (tid >> 3);
-            const int rr = (tid & 7) * 4;
+        for (int p = 0; p < P; ++p) {
+            const int col = p * (NT / 8) + (tid >> 3);
             *reinterpret_cast<uint2*>(hi + col * kStrideH + rr) = make_uint2(v[p].x, v[p].y);
             *reinterpret_cast<uint2*>(lo + col * kStrideH + rr) = make_uint2(v[p].z, v[p].w);
         }
@@ -234,35 +248,56 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    StageRegs<VEC> ry;
-    StageRegs<VEC> rc;   // unused with CS
-    SplitStage rs;
-    if constexpr (VEC) ry.init(Y, ldy, j0, n);
-    if constexpr (CS) rs.init(Csp, ldq, k0, kpad);
-    else if constexpr (VEC) rc.init(C, d, k0, c);
-    auto load_stage = [&](int64_t r) {
-        if constexpr (VEC) ry.load_rows(r, r1);
-        else ry.load(Y, ldy, j0, n, r, r1);
-        if constexpr (CS) rs.load_rows(r);
-        else if constexpr (VEC) rc.load_rows(r, r1);
-        else rc.load(C, d, k0, c, r, r1);
+    // Two register sets (PF2: VEC with two LDS buffers) so that a stage's loads can
+    // be issued two stages ahead; otherwise only set 0 is used.
+    constexpr bool PF2 = DB && VEC;
+    StageRegs<VEC> ry[PF2 ? 2 : 1];
+    StageRegs<VEC> rc[PF2 ? 2 : 1];   // unused with CS
+    SplitStage<> rs[PF2 ? 2 : 1];
+    if constexpr (VEC) ry[0].init(Y, ldy, j0, n);
+    if constexpr (CS) rs[0].init(Csp, ldq, k0, kpad);
+    else if constexpr (VEC) rc[0].init(C, d, k0, c);
+    if constexpr (PF2) {
+        ry[1] = ry[0];
+        rc[1] = rc[0];
+        rs[1] = rs[0];
+    }
+    using Set0 = std::integral_constant<int, 0>;
+    using Set1 = std::integral_constant<int, PF2 ? 1 : 0>;
+    auto load_stage = [&](auto set, int64_t r) {
+        constexpr int S = decltype(set)::value;
+        if constexpr (VEC) ry[S].load_rows(r, r1);
+        else ry[S].load(Y, ldy, j0, n, r, r1);
+        if constexpr (CS) rs[S].load_rows(r);
+        else if constexpr (VEC) rc[S].load_rows(r, r1);
+        else rc[S].load(C, d, k0, c, r, r1);
+    };
+    // VEC, a stage inside the rows: loads without any branch
+    auto load_full = [&](auto set, int64_t r) {
+        constexpr int S = decltype(set)::value;
+        if constexpr (VEC) {
+            ry[S].load_rows_full(r);
+            if constexpr (CS) rs[S].load_rows(r);
+            else rc[S].load_rows_full(r);
+        }
     };
     // registers -> LDS buffer b (bf16: split into hi/lo, and the columns' sums of squares)
-    auto store_stage = [&](int b) {
+    auto store_stage = [&](auto set, int b) {
+        constexpr int S = decltype(set)::value;
         char* base = smem + (DB ? b * kStage : 0);
         if constexpr (BF16) {
             __bf16* Yh = reinterpret_cast<__bf16*>(base);
             __bf16* Yl = Yh + kJT * kStrideH;
             __bf16* Ch = Yl + kJT * kStrideH;
             __bf16* Cl = Ch + kKC * kStrideH;
-            ry.col_sumsq(ycol);
-            ry.store_split(Yh, Yl);
-            if constexpr (CS) rs.store(Ch, Cl);
-            else rc.store_split(Ch, Cl);
+            ry[S].col_sumsq(ycol);
+            ry[S].store_split(Yh, Yl);
+            if constexpr (CS) rs[S].store(Ch, Cl);
+            else rc[S].store_split(Ch, Cl);
         } else {
             float* Ys = reinterpret_cast<float*>(base);
-            ry.store(Ys);
-            rc.store(Ys + kJT * kStride);
+            ry[S].store(Ys);
+            rc[S].store(Ys + kJT * kStride);
         }
     };
     // the MFMAs of the stage held in LDS buffer b
@@ -324,26 +359,63 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
             }
         }
     };
-    if constexpr (DB) {
+    if constexpr (PF2) {
+        // Buffer 0 holds stage r and set 1 holds (or is loading) stage r + 32 at the
+        // top of each pass.  A half-step loads stage r + 64 into the free set, runs
+        // the MFMAs of the buffered stage, then stores the older set into the other
+        // buffer; its loads had a whole half-step to arrive.
         if (r0 < r1) {
-            load_stage(r0);
-            store_stage(0);
+            load_stage(Set0{}, r0);
+            store_stage(Set0{}, 0);
+            if (r0 + kRT < r1) load_stage(Set1{}, r0 + kRT);
+            __syncthreads();
+        }
+        int64_t r = r0;
+        // steady state (both loaded stages inside the rows): every load
+        // unconditional, so the waits before each store leave the newest set's loads
+        // in flight
+        for (; r + 4 * kRT <= r1; r += 2 * kRT) {
+            load_full(Set0{}, r + 2 * kRT);
+            mfma_stage(0);
+            store_stage(Set1{}, 1);
+            __syncthreads();
+            load_full(Set1{}, r + 3 * kRT);
+            mfma_stage(1);
+            store_stage(Set0{}, 0);
+            __syncthreads();
+        }
+        // the last one to three stages
+        for (; r < r1; r += 2 * kRT) {
+            if (r + 2 * kRT < r1) load_stage(Set0{}, r + 2 * kRT);
+            mfma_stage(0);
+            if (r + kRT < r1) store_stage(Set1{}, 1);
+            __syncthreads();
+            if (r + kRT >= r1) break;
+            if (r + 3 * kRT < r1) load_stage(Set1{}, r + 3 * kRT);
+            mfma_stage(1);
+            if (r + 2 * kRT < r1) store_stage(Set0{}, 0);
+            __syncthreads();
+        }
+    } else if constexpr (DB) {
+        if (r0 < r1) {
+            load_stage(Set0{}, r0);
+            store_stage(Set0{}, 0);
             __syncthreads();
         }
         int b = 0;
         for (int64_t r = r0; r < r1; r += kRT, b ^= 1) {
             const bool more = r + kRT < r1;
-            if (more) load_stage(r + kRT);      // global loads in flight during the MFMAs
+            if (more) load_stage(Set0{}, r + kRT);   // global loads in flight during the MFMAs
             mfma_stage(b);
-            if (more) store_stage(b ^ 1);       // the other buffer was released by the last barrier
+            if (more) store_stage(Set0{}, b ^ 1);    // the other buffer was released by the last barrier
             __syncthreads();
         }
     } else {
-        if (r0 < r1) load_stage(r0);
+        if (r0 < r1) load_stage(Set0{}, r0);
         for (int64_t r = r0; r < r1; r += kRT) {
-            store_stage(0);
+            store_stage(Set0{}, 0);
             __syncthreads();
-            if (r + kRT < r1) load_stage(r + kRT);  // next stage's loads overlap this stage's MFMAs
+            if (r + kRT < r1) load_stage(Set0{}, r + kRT);  // next stage's loads overlap this stage's MFMAs
             mfma_stage(0);
             __syncthreads();
         }
@@ -365,6 +437,172 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
     for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
+            if (kb >= nkb) continue;
+            const int k = k0 + kb * 16 + q;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t j = j0 + wave * 32 + jb * 16 + 4 * g + v;
+                if (j < n) part[((int64_t)s * n + j) * kpad + k] = acc[jb][kb][v];
+            }
+        }
+}
+
+
+// bf16 distance tile with the column operand read straight into registers
+// (VEC layout, pre-split centroids): the products of dist_tile<true, true, true,
+// true> for 32 WAVES columns, each wave loading its own 32 columns in MFMA operand order and
+// splits them in registers, so only the centroids pass through LDS.  The K slots
+// of lane group g are rows 4g..4g+3 and 16+4g..16+4g+3 of the stage (two 16-byte
+// loads per column, 64 contiguous bytes per four lanes), and the centroid tiles
+// are stored in LDS in that row order.  NKB group blocks of 16 (fixed at compile
+// time; blocks past the tile's groups compute on clamped copies and are not
+// written): all centroid operands of a stage are read from LDS first, then the
+// MFMAs run product by product over every (block, column half), so that 2 NKB
+// independent accumulators separate two updates of the same one.
+template <int NKB, int WAVES>
+__device__ inline void dist_tile_ydirect(int64_t d, int kpad, const float* __restrict__ Y,
+                                         int64_t ldy, int64_t n, int slice_rows,
+                                         float* __restrict__ part,
+                                         float* __restrict__ ynorm_part, int64_t j0, int s,
+                                         int k0, bool write_ynorm,
+                                         const uint4* __restrict__ Csp, int64_t ldq) {
+    static_assert(NKB >= 1 && NKB <= kKC / 16, "group blocks per tile");
+    constexpr size_t kCBuf = 2 * kKC * kStrideH * sizeof(__bf16);   // hi and lo of one stage
+    __shared__ __attribute__((aligned(16))) char smem[2 * kCBuf];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    __syncthreads();   // a previous tile of this workgroup may still read the LDS
+    const int q = lane & 15, g = lane >> 4;
+    const int64_t r0 = (int64_t)s * slice_rows;
+    const int64_t r1 = r0 + slice_rows < d ? r0 + slice_rows : d;
+    const int nkb = (kpad - k0 < kKC ? kpad - k0 : kKC) / 16;   // blocks written out
+
+    floatx4 acc[2][NKB];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NKB; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float ycol[2] = {0.f, 0.f};   // this lane's share of its two columns' squared norms
+
+    // this lane's two columns (clamped into the matrix: their outputs are dropped)
+    const float* yp[2];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+        int64_t col = j0 + wave * 32 + jb * 16 + q;
+        if (col >= n) col = n - 1;
+        yp[jb] = Y + col * ldy + 4 * g;
+    }
+    float4 yv[2][2];   // [jb][half] of the next stage
+    SplitStage<64 * WAVES> rs;
+    rs.init(Csp, ldq, k0, kpad);
+    // a stage inside the rows: unconditional loads
+    auto load_full = [&](int64_t r) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) yv[jb][h] = *reinterpret_cast<const float4*>(yp[jb] + r + 16 * h);
+        rs.load_rows(r);
+    };
+    // any stage: rows past r1 read row 0 of the column and are zeroed
+    auto load_any = [&](int64_t r) {
+        if (r + kRT <= r1) {
+            load_full(r);
+            return;
+        }
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bool in = r + 4 * g + 16 * h < r1;
+                const float4 t = *reinterpret_cast<const float4*>(in ? yp[jb] + r + 16 * h : yp[jb] - 4 * g);
+                yv[jb][h] = in ? t : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        rs.load_rows(r);
+    };
+    auto store_c = [&](int b) {
+        __bf16* Ch = reinterpret_cast<__bf16*>(smem + b * kCBuf);
+        rs.template store<true>(Ch, Ch + kKC * kStrideH);
+    };
+    // the loaded column values as A operands (and their squares)
+    auto split = [&](bf16x8 (&ahi)[2], bf16x8 (&alo)[2]) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+            const float x[8] = {yv[jb][0].x, yv[jb][0].y, yv[jb][0].z, yv[jb][0].w,
+                                yv[jb][1].x, yv[jb][1].y, yv[jb][1].z, yv[jb][1].w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const __bf16 h = (__bf16)x[e];
+                ahi[jb][e] = h;
+                alo[jb][e] = (__bf16)(x[e] - (float)h);
+                ycol[jb] += x[e] * x[e];
+            }
+        }
+    };
+    auto mfma_stage = [&](int b, const bf16x8 (&ahi)[2], const bf16x8 (&alo)[2]) {
+        const __bf16* Ch = reinterpret_cast<const __bf16*>(smem + b * kCBuf);
+        const __bf16* Cl = Ch + kKC * kStrideH;
+        bf16x8 bhi[NKB], blo[NKB];
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            const int row = kb * 16 + q;
+            bhi[kb] = *reinterpret_cast<const bf16x8*>(Ch + row * kStrideH + g * 8);
+            blo[kb] = *reinterpret_cast<const bf16x8*>(Cl + row * kStrideH + g * 8);
+        }
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+                acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[jb], bhi[kb], acc[jb][kb], 0, 0, 0);
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+                acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[jb], blo[kb], acc[jb][kb], 0, 0, 0);
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+                acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[jb], bhi[kb], acc[jb][kb], 0, 0, 0);
+    };
+    // At the top of each pass LDS buffer b holds the centroids of stage r and the
+    // registers its column values; the next stage's loads run during the MFMAs.
+    if (r0 < r1) {
+        load_any(r0);
+        store_c(0);
+        __syncthreads();
+    }
+    bf16x8 ahi[2], alo[2];
+    int b = 0;
+    int64_t r = r0;
+    for (; r + 2 * kRT <= r1; r += kRT, b ^= 1) {   // the next stage lies inside the rows
+        split(ahi, alo);
+        load_full(r + kRT);
+        mfma_stage(b, ahi, alo);
+        store_c(b ^ 1);
+        __syncthreads();
+    }
+    for (; r < r1; r += kRT, b ^= 1) {              // the last stage (or the next one partial)
+        split(ahi, alo);
+        const bool more = r + kRT < r1;
+        if (more) load_any(r + kRT);
+        mfma_stage(b, ahi, alo);
+        if (more) store_c(b ^ 1);
+        __syncthreads();
+    }
+    if (write_ynorm) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+            float t = ycol[jb];
+            t += __shfl_xor(t, 16);
+            t += __shfl_xor(t, 32);
+            const int64_t j = j0 + wave * 32 + jb * 16 + q;
+            if (g == 0 && j < n) ynorm_part[(int64_t)s * n + j] = t;
+        }
+    }
+    // lane holds D[column 4g + v][group q] of each 16 x 16 tile
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
             if (kb >= nkb) continue;
             const int k = k0 + kb * 16 + q;
 #pragma unroll

@@ -23,6 +23,7 @@
 // differences of the FP32 values) by a refinement kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -37,6 +38,23 @@ __device__ inline double wave_sum_d(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
+}
+
+// bf16, VEC: the direct tile, 8 waves x 32 columns and NKB group blocks per
+// workgroup (one workgroup per CU: the 256 columns share each centroid stage).
+constexpr int kDirectWaves = 8;
+constexpr int kJD = 32 * kDirectWaves;   // columns per direct workgroup
+
+template <int NKB>
+__global__ __launch_bounds__(64 * kDirectWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dist_mfma_direct(
+    int64_t d, int c, int kpad, const float* __restrict__ Y, int64_t ldy, int64_t n, int slice_rows,
+    float* __restrict__ part, float* __restrict__ ynorm_part, int* __restrict__ counters,
+    const uint4* __restrict__ Csp, int64_t ldq) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < 4)
+        counters[threadIdx.x] = 0;   // refinement list length, its changed count: fresh for this pass
+    dist_tile_ydirect<NKB, kDirectWaves>(d, kpad, Y, ldy, n, slice_rows, part, ynorm_part,
+                                         (int64_t)blockIdx.x * kJD, blockIdx.y, blockIdx.z * kKC,
+                                         blockIdx.z == 0, Csp, ldq);
 }
 
 template <bool VEC, bool BF16>
@@ -472,6 +490,8 @@ struct DistPlan {
     int kpad, ntiles, nkc, slices, slice_rows;
 };
 
+// Staged tile (dist_tile): 128 columns per workgroup, slices chosen for at
+// least 1024 workgroups.
 DistPlan plan_f32(int64_t d, int64_t n, int c) {
     DistPlan p;
     p.kpad = (c + 15) / 16 * 16;
@@ -490,25 +510,84 @@ DistPlan plan_f32(int64_t d, int64_t n, int c) {
     return p;
 }
 
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    return cus;
+}
+
+// Direct tile: kJD columns per workgroup, one workgroup per CU.  The slice count
+// minimises the time in units of one stage of every CU: (rounds of workgroups) x
+// (stages per slice), plus the partial sums each slice writes and the argmin
+// reads back (2 n kpad floats against the CUs' kJD x 32 floats per stage).
+DistPlan plan_direct(int64_t d, int64_t n, int c) {
+    DistPlan p;
+    p.kpad = (c + 15) / 16 * 16;
+    p.ntiles = (int)((n + kJD - 1) / kJD);
+    p.nkc = (p.kpad + kKC - 1) / kKC;
+    const int64_t per = (int64_t)p.ntiles * p.nkc, slots = device_cus();
+    const int64_t stages = (d + kRT - 1) / kRT;
+    const double slice_cost = 2.0 * (double)n * p.kpad / ((double)slots * kJD * kRT);
+    int64_t best = 1;
+    double best_cost = 1e300;
+    for (int64_t sl = 1; sl <= 64 && sl <= stages; ++sl) {
+        const double cost = (double)(((per * sl + slots - 1) / slots) * ((stages + sl - 1) / sl)) +
+                            slice_cost * (double)sl;
+        if (cost < best_cost) { best_cost = cost; best = sl; }
+    }
+    const int64_t rows = (stages + best - 1) / best * kRT;
+    p.slice_rows = (int)rows;
+    p.slices = (int)((d + rows - 1) / rows);
+    return p;
+}
+
+bool use_direct(int64_t d, const float* Y, int64_t ldy, bool bf16) {
+    return bf16 && d % 4 == 0 && ldy % 4 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
+}
+
 }  // namespace
 
-// Workspace layout (float runs): partial dots [slices][n][kpad] | column norm
-// partials [slices][n] | (256-aligned) counters (int x 4) | refinement list [n] |
-// (16-aligned) candidates [n][kMaxCand] | (8-aligned) exact distances [n][kMaxCand] (double) |
-// (256-aligned) split centroids [kpad][ldq] x 16 bytes, ldq = ceil(d / 32) * 8.
+// Workspace layout (float runs): counters (int x 4, padded to 256 bytes) |
+// refinement list [n] | (16-aligned) candidates [n][kMaxCand] | (8-aligned) exact
+// distances [n][kMaxCand] (double) | (256-aligned) split centroids [kpad][ldq] x 16
+// bytes, ldq = ceil(d / 32) * 8 | (256-aligned) partial dots [slices][n][kpad] |
+// column norm partials [slices][n], sized for the larger slice count of the two
+// tile plans.
 int64_t split_ldq(int64_t d) { return (d + kRT - 1) / kRT * (kRT / 4); }
 
-size_t assign_tail_bytes(int64_t d, int64_t n, int c) {
-    const DistPlan p = plan_f32(d, n, c);
-    return (size_t)p.slices * (size_t)n * (size_t)(p.kpad + 1) * sizeof(float) + 256 + 16 +
-           (size_t)n * (1 + kMaxCand) * sizeof(int32_t) + 16 + 8 +
-           (size_t)n * kMaxCand * sizeof(double);
+struct WorkLayout {
+    int* counters;
+    int32_t* list;
+    int32_t* cand;
+    double* refdist;
+    uint4* csp;
+    float* part;
+    float* ynorm;
+};
+
+inline uintptr_t align_up(uintptr_t v, uintptr_t a) { return (v + a - 1) & ~(a - 1); }
+
+WorkLayout work_layout(void* work, int64_t d, int64_t n, int c, int slices) {
+    WorkLayout w;
+    const uintptr_t base = (uintptr_t)work;
+    w.counters = (int*)base;
+    w.list = (int32_t*)(base + 256);
+    w.cand = (int32_t*)align_up((uintptr_t)(w.list + n), 16);
+    w.refdist = (double*)align_up((uintptr_t)(w.cand + n * kMaxCand), 8);
+    w.csp = (uint4*)align_up((uintptr_t)(w.refdist + n * kMaxCand), 256);
+    const int kpad = (c + 15) / 16 * 16;
+    w.part = (float*)align_up((uintptr_t)(w.csp + (int64_t)kpad * split_ldq(d)), 256);
+    w.ynorm = w.part + (size_t)slices * n * kpad;
+    return w;
 }
 
 template <>
 size_t assign_workspace_bytes<float>(int64_t d, int64_t n, int c) {
-    const DistPlan p = plan_f32(d, n, c);
-    return assign_tail_bytes(d, n, c) + 256 + (size_t)p.kpad * (size_t)split_ldq(d) * sizeof(uint4);
+    const int slices = std::max(plan_f32(d, n, c).slices, plan_direct(d, n, c).slices);
+    const WorkLayout w = work_layout(nullptr, d, n, c, slices);
+    return (size_t)(uintptr_t)(w.ynorm + (size_t)slices * n);
 }
 
 template <>
@@ -521,16 +600,16 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
                          double* cnorm, const int32_t* old_labels, int32_t* new_labels,
                          void* work, double* changed_partial, bool bf16, int* changed_extra,
                          hipStream_t st) {
-    const DistPlan p = plan_f32(d, n, c);
-    float* part = (float*)work;
-    float* ynorm = part + (size_t)p.slices * n * p.kpad;
-    char* tail = (char*)(ynorm + (size_t)p.slices * n);
-    tail = (char*)(((uintptr_t)tail + 255) & ~(uintptr_t)255);
-    int* counters = (int*)tail;                       // [0] list length, [1] refined changes
-    int32_t* list = (int32_t*)(tail + 16);
-    int32_t* cand = (int32_t*)(((uintptr_t)(list + n) + 15) & ~(uintptr_t)15);   // rows read as int4
-    double* refdist = (double*)(((uintptr_t)(cand + n * kMaxCand) + 7) & ~(uintptr_t)7);
-    uint4* csp = (uint4*)(((uintptr_t)work + assign_tail_bytes(d, n, c) + 255) & ~(uintptr_t)255);
+    const bool direct = use_direct(d, Y, ldy, bf16);
+    const DistPlan p = direct ? plan_direct(d, n, c) : plan_f32(d, n, c);
+    const WorkLayout w = work_layout(work, d, n, c, p.slices);
+    int* counters = w.counters;                       // [0] list length, [1] refined changes
+    int32_t* list = w.list;
+    int32_t* cand = w.cand;
+    double* refdist = w.refdist;
+    uint4* csp = w.csp;
+    float* part = w.part;
+    float* ynorm = w.ynorm;
     const int64_t ldq = split_ldq(d);
     const dim3 grid(p.ntiles, p.slices, p.nkc);
     const bool vecy = (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
@@ -559,10 +638,19 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
     // the pre-split centroids replace C in the tiles, so only Y's layout picks the path
     k_split_centroids<<<p.kpad, 1024, 0, st>>>(
         C, d, c, ldq, (d % 4 == 0) && (reinterpret_cast<uintptr_t>(C) % 16 == 0), csp, cnorm);
-    if (vecy && d % 4 == 0)
-        k_dist_mfma<true, true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
-                                                      ynorm, counters, csp, ldq);
-    else
+    if (direct) {
+        switch (std::min(p.kpad / 16, kKC / 16)) {
+#define RESPCA_DIRECT(NB)                                                                            \
+    case NB:                                                                                         \
+        k_dist_mfma_direct<NB><<<grid, 64 * kDirectWaves, 0, st>>>(d, c, p.kpad, Y, ldy, n,          \
+                                                                   p.slice_rows, part, ynorm,        \
+                                                                   counters, csp, ldq);              \
+        break;
+            RESPCA_DIRECT(1) RESPCA_DIRECT(2) RESPCA_DIRECT(3) RESPCA_DIRECT(4)
+            RESPCA_DIRECT(5) RESPCA_DIRECT(6) RESPCA_DIRECT(7) RESPCA_DIRECT(8)
+#undef RESPCA_DIRECT
+        }
+    } else
         k_dist_mfma<false, true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
                                                        ynorm, counters, csp, ldq);
     // error bound factor (doubled for safety): split products, 3 * 2^-16 per
@@ -591,14 +679,7 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
     return gb;
 }
 
-int* assign_refine_counters(void* work, int64_t d, int64_t n, int c) {
-    const DistPlan p = plan_f32(d, n, c);
-    float* part = (float*)work;
-    float* ynorm = part + (size_t)p.slices * n * p.kpad;
-    char* tail = (char*)(ynorm + (size_t)p.slices * n);
-    tail = (char*)(((uintptr_t)tail + 255) & ~(uintptr_t)255);
-    return (int*)tail;
-}
+int* assign_refine_counters(void* work, int64_t, int64_t, int) { return (int*)work; }
 
 template <>
 int launch_assign<double>(const double* C, int64_t d, int c, const double* Y, int64_t ldy,
