@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cmath>
 #include <cstdint>
 
@@ -235,10 +237,13 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
     for (int a = 0; a < NS; ++a)
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
-    for (int q0 = cg; q0 < len; q0 += U * CG) {
+    // One step: U columns of the segment (FULL: all inside it, so no load sits
+    // behind a branch and the waits before each column's stores stay exact).
+    auto step = [&](int q0, auto full) {
+        constexpr bool FULL = decltype(full)::value;
         int64_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = q0 + u * CG < len ? cols[q0 + u * CG] : -1;
+        for (int u = 0; u < U; ++u) jj[u] = (FULL || q0 + u * CG < len) ? cols[q0 + u * CG] : -1;
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
             const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
@@ -247,7 +252,7 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
             vload<T, V>(C + p * d + i, m);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (jj[u] < 0) continue;
+                if (!FULL && jj[u] < 0) continue;
                 vload<T, V>(X + jj[u] * ldx + i, xs[u]);
                 vload<T, V>(S + jj[u] * lds + i, ss[u]);
                 vload<T, V>(Th + jj[u] * ldt + i, ts[u]);
@@ -255,7 +260,7 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (jj[u] < 0) continue;
+                if (!FULL && jj[u] < 0) continue;
                 const int64_t j = jj[u];
                 T ln[V], sn[V], tn[V];
 #pragma unroll
@@ -280,7 +285,10 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
                 vstore<T, V>(Th + j * ldt + i, tn);
             }
         }
-    }
+    };
+    int q0 = cg;
+    for (; q0 + (U - 1) * CG < len; q0 += U * CG) step(q0, std::true_type{});
+    if (q0 < len) step(q0, std::false_type{});   // the segment's last, partial step
     if constexpr (CG == 1) {
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
@@ -323,7 +331,9 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
     constexpr int TPC = kBlock / CG;
     constexpr int NS = ROWS / (TPC * V);
     static_assert(NS >= 1 && NS * TPC * V == ROWS, "row block must tile the column group");
-    constexpr int U = 4;   // columns in flight per thread; the summation order is unchanged
+    // columns in flight per thread (each a load of A, and of S and Theta with D);
+    // the summation order is unchanged
+    constexpr int U = WITH_D ? 4 : 8;
     const int cg = (int)threadIdx.x / TPC, tl = (int)threadIdx.x % TPC;
     double acc[NS][V];
 #pragma unroll
@@ -341,11 +351,12 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
         }
     };
     const int32_t* cols = stage_segment_cols(perm, begin, len);
-    int q = cg;
-    for (; q + (U - 1) * CG < len; q += U * CG) {
+    // U columns per step; past the segment's end the last column is loaded again
+    // (unconditional loads) and its values are not added
+    for (int q = cg; q < len; q += U * CG) {
         int64_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = cols[q + u * CG];
+        for (int u = 0; u < U; ++u) jj[u] = cols[q + u * CG < len ? q + u * CG : len - 1];
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
             const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
@@ -355,21 +366,9 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
                 for (int u = 0; u < U; ++u) value(jj[u], i, x[u]);
 #pragma unroll
                 for (int u = 0; u < U; ++u)
+                    if (q + u * CG < len)
 #pragma unroll
-                    for (int v = 0; v < V; ++v) acc[a][v] += (double)x[u][v];
-            }
-        }
-    }
-    for (; q < len; q += CG) {
-        const int64_t j = cols[q];
-#pragma unroll
-        for (int a = 0; a < NS; ++a) {
-            const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
-            if (i < d) {
-                T x[V];
-                value(j, i, x);
-#pragma unroll
-                for (int v = 0; v < V; ++v) acc[a][v] += (double)x[v];
+                        for (int v = 0; v < V; ++v) acc[a][v] += (double)x[u][v];
             }
         }
     }
