@@ -172,12 +172,13 @@ struct StageRegs {
 // Centroids already split into bf16 parts: element (k, g) of the [kpad][ldq]
 // array holds rows 4g..4g+3 of group k as {hi[4], lo[4]} (16 bytes), zero past
 // the last row, so a stage is a plain copy into the LDS hi/lo tiles.
-// NT threads share the stage: thread t takes row group t % 8 of group columns
-// t / 8 + (NT / 8) p, p < 1024 / NT.
-template <int NT = 256>
+// NT threads share the stage of the first GROUPS group columns (rounded up to
+// whole passes of NT / 8 columns): thread t takes row group t % 8 of group
+// columns t / 8 + (NT / 8) p.
+template <int NT = 256, int GROUPS = kKC>
 struct SplitStage {
-    static constexpr int P = 1024 / NT;
-    static_assert(P >= 1 && P * NT == 1024, "128 groups x 8 row groups per stage");
+    static constexpr int P = (GROUPS * 8 + NT - 1) / NT;
+    static_assert(P >= 1 && P * (NT / 8) <= kKC, "at most 128 groups per stage");
     uint4 v[P];
     const uint4* ptr[P];
 
@@ -214,12 +215,12 @@ struct SplitStage {
 };
 
 // One distance tile: columns [j0, j0 + 128) x groups [k0, k0 + 128) over the
-// rows of slice s; writes part[s][j][k] (and, in bf16 mode with write_ynorm,
+// rows of slice s; writes part[s][j][k] (and, with YN and write_ynorm,
 // the slice's column sums of squares).  256 threads.  DB: two LDS stage
 // buffers, so a stage's MFMAs and the staging of the next one share one barrier
 // and can overlap (twice the LDS).  CS (bf16 only): the centroids come pre-split
 // from Csp (SplitStage layout, ldq row groups per group) instead of C.
-template <bool VEC, bool BF16, bool DB = false, bool CS = false>
+template <bool VEC, bool BF16, bool DB = false, bool CS = false, bool YN = BF16>
 __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, int kpad,
                                  const float* __restrict__ Y, int64_t ldy, int64_t n, int slice_rows,
                                  float* __restrict__ part, float* __restrict__ ynorm_part,
@@ -296,6 +297,7 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
             else rc[S].store_split(Ch, Cl);
         } else {
             float* Ys = reinterpret_cast<float*>(base);
+            if constexpr (YN) ry[S].col_sumsq(ycol);
             ry[S].store(Ys);
             rc[S].store(Ys + kJT * kStride);
         }
@@ -420,7 +422,7 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
             __syncthreads();
         }
     }
-    if constexpr (BF16) {
+    if constexpr (YN) {
         if (write_ynorm) {
             StageRegs<VEC>::col_sumsq_reduce(ycol);
 #pragma unroll
@@ -492,7 +494,7 @@ __device__ inline void dist_tile_ydirect(int64_t d, int kpad, const float* __res
         yp[jb] = Y + col * ldy + 4 * g;
     }
     float4 yv[2][2];   // [jb][half] of the next stage
-    SplitStage<64 * WAVES> rs;
+    SplitStage<64 * WAVES, 16 * NKB> rs;   // only the groups the MFMAs read
     rs.init(Csp, ldq, k0, kpad);
     // a stage inside the rows: unconditional loads
     auto load_full = [&](int64_t r) {

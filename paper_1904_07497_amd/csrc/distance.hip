@@ -20,7 +20,10 @@
 // (K = rows summed in FP32).  The kernel also accumulates ||Y_j||^2; the argmin
 // kernel flags every column whose best and runner-up distances are not
 // separated by the bounds, and those columns are re-decided exactly (FP64
-// differences of the FP32 values) by a refinement kernel.
+// differences of the FP32 values) by a refinement kernel.  With at most 32
+// groups this bounded mode runs the FP32 MFMA tile instead (few MFMAs, no split
+// work; E = 2 (K + 2) 2^-24 ||C_k|| ||Y_j|| from the FP32 products and sums) with
+// the same argmin and refinement, so its labels are exact as well.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,8 +48,12 @@ __device__ inline double wave_sum_d(double v) {
 constexpr int kDirectWaves = 8;
 constexpr int kJD = 32 * kDirectWaves;   // columns per direct workgroup
 
+// Up to three group blocks the registers fit two workgroups per CU (four waves
+// per SIMD); more blocks take one.
+constexpr int direct_wgs_per_cu(int nkb) { return nkb <= 3 ? 2 : 1; }
+
 template <int NKB>
-__global__ __launch_bounds__(64 * kDirectWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dist_mfma_direct(
+__global__ __launch_bounds__(64 * kDirectWaves) __attribute__((amdgpu_waves_per_eu(2 * direct_wgs_per_cu(NKB), 2 * direct_wgs_per_cu(NKB)))) void k_dist_mfma_direct(
     int64_t d, int c, int kpad, const float* __restrict__ Y, int64_t ldy, int64_t n, int slice_rows,
     float* __restrict__ part, float* __restrict__ ynorm_part, int* __restrict__ counters,
     const uint4* __restrict__ Csp, int64_t ldq) {
@@ -55,6 +62,20 @@ __global__ __launch_bounds__(64 * kDirectWaves) __attribute__((amdgpu_waves_per_
     dist_tile_ydirect<NKB, kDirectWaves>(d, kpad, Y, ldy, n, slice_rows, part, ynorm_part,
                                          (int64_t)blockIdx.x * kJD, blockIdx.y, blockIdx.z * kKC,
                                          blockIdx.z == 0, Csp, ldq);
+}
+
+// Bounded mode at small c: the FP32 MFMA tile with the columns' norms, decided by
+// the same bounded argmin and exact refinement as the split-bf16 tiles.
+template <bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dist_mfma_f32b(
+    const float* __restrict__ C, int64_t d, int c, int kpad, const float* __restrict__ Y, int64_t ldy,
+    int64_t n, int slice_rows, float* __restrict__ part, float* __restrict__ ynorm_part,
+    int* __restrict__ counters) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < 4)
+        counters[threadIdx.x] = 0;   // refinement list length, its changed count: fresh for this pass
+    dist_tile<VEC, false, true, false, true>(C, d, c, kpad, Y, ldy, n, slice_rows, part, ynorm_part,
+                                             (int64_t)blockIdx.x * kJT, blockIdx.y, blockIdx.z * kKC,
+                                             blockIdx.z == 0);
 }
 
 template <bool VEC, bool BF16>
@@ -435,21 +456,15 @@ __global__ __launch_bounds__(256) void k_refine_dist(const float* __restrict__ C
     }
 }
 
-// Per list item: smallest exact distance among its candidates (lowest group on
-// ties).  Items with more than kMaxCand candidates are scored against every
-// group by one wave here (rare).
-__global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ C, int64_t d, int c,
-                                                     const float* __restrict__ Y, int64_t ldy,
-                                                     const int* __restrict__ counters,
-                                                     const int32_t* __restrict__ list,
-                                                     const int32_t* __restrict__ cand,
-                                                     const double* __restrict__ refdist,
-                                                     const int32_t* __restrict__ old_labels,
-                                                     int32_t* __restrict__ new_labels,
-                                                     int* __restrict__ changed_count) {
-    const int lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (item >= counters[0]) return;
+// One list item, one wave.
+__device__ inline void refine_pick_item(const float* __restrict__ C, int64_t d, int c,
+                                        const float* __restrict__ Y, int64_t ldy,
+                                        const int32_t* __restrict__ list,
+                                        const int32_t* __restrict__ cand,
+                                        const double* __restrict__ refdist,
+                                        const int32_t* __restrict__ old_labels,
+                                        int32_t* __restrict__ new_labels,
+                                        int* __restrict__ changed_count, int item, int lane) {
     const int64_t j = list[item];
     const int32_t* cj = cand + j * kMaxCand;
     double best = INFINITY;
@@ -486,6 +501,26 @@ __global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ C
     }
 }
 
+// Per list item: smallest exact distance among its candidates (lowest group on
+// ties).  Items with more than kMaxCand candidates are scored against every
+// group by one wave here (rare).
+__global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ C, int64_t d, int c,
+                                                     const float* __restrict__ Y, int64_t ldy,
+                                                     const int* __restrict__ counters,
+                                                     const int32_t* __restrict__ list,
+                                                     const int32_t* __restrict__ cand,
+                                                     const double* __restrict__ refdist,
+                                                     const int32_t* __restrict__ old_labels,
+                                                     int32_t* __restrict__ new_labels,
+                                                     int* __restrict__ changed_count) {
+    const int lane = threadIdx.x & 63;
+    const int count = counters[0];
+    for (int item = blockIdx.x * 4 + (threadIdx.x >> 6); item < count; item += gridDim.x * 4)
+        refine_pick_item(C, d, c, Y, ldy, list, cand, refdist, old_labels, new_labels, changed_count,
+                         item, lane);
+}
+
+
 struct DistPlan {
     int kpad, ntiles, nkc, slices, slice_rows;
 };
@@ -518,7 +553,7 @@ int device_cus() {
     return cus;
 }
 
-// Direct tile: kJD columns per workgroup, one workgroup per CU.  The slice count
+// Direct tile: kJD columns per workgroup, one or two workgroups per CU.  The slice count
 // minimises the time in units of one stage of every CU: (rounds of workgroups) x
 // (stages per slice), plus the partial sums each slice writes and the argmin
 // reads back (2 n kpad floats against the CUs' kJD x 32 floats per stage).
@@ -527,7 +562,8 @@ DistPlan plan_direct(int64_t d, int64_t n, int c) {
     p.kpad = (c + 15) / 16 * 16;
     p.ntiles = (int)((n + kJD - 1) / kJD);
     p.nkc = (p.kpad + kKC - 1) / kKC;
-    const int64_t per = (int64_t)p.ntiles * p.nkc, slots = device_cus();
+    const int64_t per = (int64_t)p.ntiles * p.nkc;
+    const int64_t slots = (int64_t)device_cus() * direct_wgs_per_cu(std::min(p.kpad / 16, kKC / 16));
     const int64_t stages = (d + kRT - 1) / kRT;
     const double slice_cost = 2.0 * (double)n * p.kpad / ((double)slots * kJD * kRT);
     int64_t best = 1;
@@ -543,8 +579,13 @@ DistPlan plan_direct(int64_t d, int64_t n, int c) {
     return p;
 }
 
-bool use_direct(int64_t d, const float* Y, int64_t ldy, bool bf16) {
-    return bf16 && d % 4 == 0 && ldy % 4 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
+// Bounded mode with at most 32 groups runs the FP32 MFMA tile (few MFMAs, no
+// split work); above that the split-bf16 tiles.
+constexpr int kF32BoundedMaxC = 32;
+
+bool use_direct(int64_t d, int c, const float* Y, int64_t ldy, bool bf16) {
+    return bf16 && c > kF32BoundedMaxC && d % 4 == 0 && ldy % 4 == 0 &&
+           reinterpret_cast<uintptr_t>(Y) % 16 == 0;
 }
 
 }  // namespace
@@ -600,7 +641,7 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
                          double* cnorm, const int32_t* old_labels, int32_t* new_labels,
                          void* work, double* changed_partial, bool bf16, int* changed_extra,
                          hipStream_t st) {
-    const bool direct = use_direct(d, Y, ldy, bf16);
+    const bool direct = use_direct(d, c, Y, ldy, bf16);
     const DistPlan p = direct ? plan_direct(d, n, c) : plan_f32(d, n, c);
     const WorkLayout w = work_layout(work, d, n, c, p.slices);
     int* counters = w.counters;                       // [0] list length, [1] refined changes
@@ -635,10 +676,19 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
 #undef RESPCA_ARGMIN_F
         return gb;
     }
-    // the pre-split centroids replace C in the tiles, so only Y's layout picks the path
+    // the pre-split centroids replace C in the split tiles, so only Y's layout picks
+    // their path; the split pass also leaves the centroid norms
     k_split_centroids<<<p.kpad, 1024, 0, st>>>(
         C, d, c, ldq, (d % 4 == 0) && (reinterpret_cast<uintptr_t>(C) % 16 == 0), csp, cnorm);
-    if (direct) {
+    const bool f32b = c <= kF32BoundedMaxC;
+    if (f32b) {
+        if (vec)
+            k_dist_mfma_f32b<true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
+                                                         ynorm, counters);
+        else
+            k_dist_mfma_f32b<false><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
+                                                          ynorm, counters);
+    } else if (direct) {
         switch (std::min(p.kpad / 16, kKC / 16)) {
 #define RESPCA_DIRECT(NB)                                                                            \
     case NB:                                                                                         \
@@ -653,9 +703,11 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
     } else
         k_dist_mfma<false, true><<<grid, 256, 0, st>>>(C, d, c, p.kpad, Y, ldy, n, p.slice_rows, part,
                                                        ynorm, counters, csp, ldq);
-    // error bound factor (doubled for safety): split products, 3 * 2^-16 per
-    // product, plus FP32 accumulation over one slice of rows
-    const float eps_rel = (float)(2.0 * (3.0 * std::ldexp(1.0, -16) + p.slice_rows * std::ldexp(1.0, -24)));
+    // error bound factor (doubled for safety): FP32 accumulation over one slice of
+    // rows, plus (split tiles) 3 * 2^-16 per product for the bf16 parts, or (FP32
+    // tile) the products' own rounding
+    const double acc_err = (p.slice_rows + 2.0) * std::ldexp(1.0, -24);
+    const float eps_rel = (float)(2.0 * (f32b ? acc_err : 3.0 * std::ldexp(1.0, -16) + acc_err));
 #define RESPCA_ARGMIN_R(TT)                                                                    \
     k_dist_argmin_bounded_r<TT><<<gb, 256, 0, st>>>(part, ynorm, p.slices, n, c, p.kpad, eps_rel,  \
                                                     cnorm, old_labels, new_labels, changed_partial, \
@@ -671,7 +723,7 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
 #undef RESPCA_ARGMIN_R
     k_refine_dist<<<dim3(kRefineSlots, kMaxCand), 256, 0, st>>>(C, d, c, Y, ldy, counters, list,
                                                                   cand, refdist);
-    k_refine_pick<<<(unsigned)((n + 3) / 4), 256, 0, st>>>(C, d, c, Y, ldy, counters, list, cand,
+    k_refine_pick<<<kRefineSlots / 4, 256, 0, st>>>(C, d, c, Y, ldy, counters, list, cand,
                                                            refdist, old_labels, new_labels,
                                                            counters + 1);
     // refined changes are added to the partial list by the caller via changed_extra
