@@ -342,6 +342,27 @@ def test_bf16_kmeans_matches_oracle():
     assert info["init_lloyd"] == osteps
 
 
+@pytest.mark.parametrize("d,n,c,pad", [
+    (1024, 900, 40, 0),     # direct tile, three group blocks (two workgroups per CU)
+    (512, 1300, 70, 0),     # direct tile, five group blocks
+    (1020, 600, 20, 8),     # at most 32 groups: FP32 MFMA tile with bounds, padded ld
+    (2048, 300, 130, 4),    # two group tiles (c > 128), padded ld
+])
+def test_bf16_kmeans_tile_variants_match_oracle(d, n, c, pad):
+    """Every bounded-distance tile variant (chosen by c and the column layout) gives
+    the oracle's labels and Lloyd count on grouped data, also with ld > d."""
+    X, _, _, _ = synth.clustered(d, n, c, seed=d + c, sep=3.0, noise=0.7, dtype=np.float32)
+    buf = rp.empty_colmajor(d + pad, n, torch.float32, torch.device("cuda:0"))
+    buf.zero_()
+    Xv = buf[:d]
+    Xv.copy_(torch.from_numpy(X))
+    say(f"tile variant d={d} n={n} c={c} ld={Xv.stride(1)}")
+    lab, C, info = rp.kmeans(Xv, c, seed=7, precision=rp.BF16GEMM_F32)
+    ol, oC, osteps = oracle.kmeans(X, c, 7)
+    np.testing.assert_array_equal(lab.cpu().numpy(), ol)
+    assert info["init_lloyd"] == osteps
+
+
 @pytest.mark.parametrize("precision", [rp.F32, rp.BF16GEMM_F32])
 def test_exact_ties_go_to_lowest_group(precision):
     """Two identical centroids (empty groups carried in the state) tie exactly for
