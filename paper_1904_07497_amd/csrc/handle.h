@@ -46,6 +46,8 @@ struct respca_handle_s {
     respca::DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, sortbc, pmeans, dots, cnorm,
         lab_a, lab_b, d2, chosen, seeds, u, normp, chgp, status;
     respca::DevBuf zcopy, zsc, ynorm;   // fp16 copy, column scales and norms for bounded seeding
+    // incremental Lloyd means: group sums, next counts, the moved-column sort and its partials
+    respca::DevBuf gsum, cnt2, cbc, cperm, csegb, csegl, csegf, cnseg, cpart;
     double* hstage = nullptr;  // pinned host staging (status readback, uniforms)
     size_t hstage_bytes = 0;
     // batched solver

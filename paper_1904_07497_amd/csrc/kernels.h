@@ -42,12 +42,30 @@ template <typename T>
 void launch_group_partial(bool with_d, const T* A, int64_t lda, const T* S, int64_t lds,
                           const T* Th, int64_t ldt, T inv_rho, int64_t d, int64_t n, int c,
                           const int32_t* perm, const int32_t* seg_begin, const int32_t* seg_len,
-                          const int32_t* nseg, double* partial, hipStream_t st);
+                          const int32_t* nseg, double* partial, hipStream_t st, int max_seg = -1);
 
-// C[:, k] = (sum of the segment partials of group k) / n_k for non-empty groups.
+// C[:, k] = (sum of the segment partials of group k) / n_k for non-empty groups;
+// with gsum, also gsum[:, k] = that sum in double (zero for empty groups).
 template <typename T>
 void launch_group_finalize(const double* partial, int64_t d, int c, const int32_t* counts,
-                           const int32_t* seg_first, T* C, hipStream_t st);
+                           const int32_t* seg_first, T* C, hipStream_t st, double* gsum = nullptr);
+
+// Incremental group means after an assignment pass (see kernels.hip): a
+// counting sort of the moved columns under 2c keys (entering new label, leaving
+// old label), the new group counts, and its segment table; then, after the
+// group partials of those segments, the update of the group sums and means.
+// `bc` holds changed_sort_scratch_ints(n, c) ints; perm 2n entries; seg_begin and
+// seg_len max_seg entries (enough: changed_max_segments(moved, c)), seg_first
+// 2c + 1.
+int64_t changed_sort_scratch_ints(int64_t n, int c);
+int changed_max_segments(int64_t moved, int c);
+void launch_changed_sort(const int32_t* new_labels, const int32_t* old_labels, int64_t n, int c,
+                         int32_t* bc, const int32_t* counts_old, int32_t* counts_new, int32_t* perm,
+                         int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg,
+                         int max_seg, hipStream_t st);
+template <typename T>
+void launch_group_update(const double* partial, int64_t d, int c, const int32_t* counts_new,
+                         const int32_t* seg_first, double* gsum, T* C, hipStream_t st);
 
 // out[k] = ||C[:, k]||^2 in double.
 template <typename T>

@@ -14,6 +14,7 @@ static_assert(respca::kSegCols <= respca::kMaxSegCols, "segments must fit the LD
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <algorithm>
 #include <cmath>
 
 namespace respca {
@@ -197,11 +198,16 @@ __global__ __launch_bounds__(kBlock) void k_group_partial(
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_group_finalize(const double* __restrict__ partial,
                                                            int64_t d, const int32_t* counts,
-                                                           const int32_t* seg_first, T* C) {
+                                                           const int32_t* seg_first, T* C,
+                                                           double* __restrict__ gsum) {
     const int k = blockIdx.y;
     const int nk = counts[k];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (nk == 0 || i >= d) return;
+    if (i >= d) return;
+    if (nk == 0) {
+        if (gsum) gsum[(int64_t)k * d + i] = 0.0;   // an empty group's sum is exactly zero
+        return;
+    }
     double s = 0.0;
     const int g1 = seg_first[k + 1];
     for (int g = seg_first[k]; g < g1; g += 4) {   // four loads in flight, added in segment order
@@ -213,7 +219,156 @@ __global__ __launch_bounds__(kBlock) void k_group_finalize(const double* __restr
         for (int u = 0; u < 4; ++u)
             if (g + u < g1) s += v[u];
     }
+    if (gsum) gsum[(int64_t)k * d + i] = s;
     C[(int64_t)k * d + i] = (T)(s / (double)nk);
+}
+
+// -------------------------------------------------- incremental group means
+//
+// After an assignment pass that moved few columns, the group sums of Y follow
+// from the previous ones: column j with new label b != old label a is listed
+// under key b (entering b) and key c + a (leaving a).  A counting sort of these
+// entries (keys in order, columns in order within a key) gives segments for the
+// group-partial kernel, and the update adds each group's entering partials and
+// subtracts its leaving partials, segment by segment in order.
+
+__global__ __launch_bounds__(kSortChunk) void k_chg_hist(const int32_t* __restrict__ nl,
+                                                         const int32_t* __restrict__ ol, int n,
+                                                         int c, int32_t* __restrict__ bc) {
+    __shared__ int h[2 * kMaxGroups];
+    const int K = 2 * c;
+    for (int k = threadIdx.x; k < K; k += kSortChunk) h[k] = 0;
+    __syncthreads();
+    const int j = blockIdx.x * kSortChunk + threadIdx.x;
+    if (j < n) {
+        const int a = ol[j], b = nl[j];
+        if (a != b) {
+            atomicAdd(&h[b], 1);
+            atomicAdd(&h[c + a], 1);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kSortChunk) bc[(int64_t)blockIdx.x * K + k] = h[k];
+}
+
+// One workgroup of kMaxGroups threads, thread t owns keys 2t and 2t + 1 (of 2c):
+// key totals, exclusive offsets (bc in place), the segment table (seg_first has
+// 2c + 1 entries) and the new group counts counts_new[k] = counts_old[k] +
+// entering(k) - leaving(k).
+// Segments past max_seg (more moved columns than the tables were sized for) are
+// not written and seg_first is clamped to max_seg.
+__global__ __launch_bounds__(kMaxGroups) void k_chg_scan(int32_t* __restrict__ bc, int nb, int c,
+                                                        const int32_t* __restrict__ counts_old,
+                                                        int32_t* __restrict__ counts_new,
+                                                        int32_t* __restrict__ seg_begin,
+                                                        int32_t* __restrict__ seg_len,
+                                                        int32_t* __restrict__ seg_first,
+                                                        int32_t* __restrict__ nseg_out, int max_seg) {
+    __shared__ int wsum[kMaxGroups / 64];
+    __shared__ int tots[2 * kMaxGroups];
+    const int K = 2 * c;
+    const int t = threadIdx.x;
+    constexpr int U = 8;
+    int tot[2] = {0, 0};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int key = 2 * t + e;
+        if (key < K)
+            for (int b = 0; b < nb; b += U) {
+                int v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = b + u < nb ? bc[(int64_t)(b + u) * K + key] : 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) tot[e] += v[u];
+            }
+    }
+    const int nsg[2] = {(tot[0] + kSegCols - 1) / kSegCols, (tot[1] + kSegCols - 1) / kSegCols};
+    const int base = block_exscan_1024(tot[0] + tot[1], wsum);
+    const int sbase = block_exscan_1024(nsg[0] + nsg[1], wsum);
+    int off = base, soff = sbase;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int key = 2 * t + e;
+        if (key < K) {
+            tots[key] = tot[e];
+            seg_first[key] = min(soff, max_seg);
+            for (int q = 0; q < nsg[e] && soff + q < max_seg; ++q) {
+                seg_begin[soff + q] = off + q * kSegCols;
+                seg_len[soff + q] = min(kSegCols, tot[e] - q * kSegCols);
+            }
+            int run = off;
+            for (int b = 0; b < nb; b += U) {
+                int v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = b + u < nb ? bc[(int64_t)(b + u) * K + key] : 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (b + u < nb) bc[(int64_t)(b + u) * K + key] = run;
+                    run += v[u];
+                }
+            }
+            if (key == K - 1) {
+                seg_first[K] = min(soff + nsg[e], max_seg);
+                *nseg_out = min(soff + nsg[e], max_seg);
+            }
+        }
+        off += tot[e];
+        soff += nsg[e];
+    }
+    __syncthreads();
+    for (int k = t; k < c; k += kMaxGroups) counts_new[k] = counts_old[k] + tots[k] - tots[c + k];
+}
+
+__global__ __launch_bounds__(kSortChunk) void k_chg_scatter(const int32_t* __restrict__ nl,
+                                                            const int32_t* __restrict__ ol, int n,
+                                                            int c, const int32_t* __restrict__ bc,
+                                                            int32_t* __restrict__ perm) {
+    __shared__ int ek[kSortChunk], lk[kSortChunk];   // entering / leaving key, -1 if unchanged
+    const int tid = threadIdx.x;
+    const int j = blockIdx.x * kSortChunk + tid;
+    const int a = j < n ? ol[j] : 0, b = j < n ? nl[j] : 0;
+    const bool moved = j < n && a != b;
+    ek[tid] = moved ? b : -1;
+    lk[tid] = moved ? c + a : -1;
+    __syncthreads();
+    if (moved) {
+        const int K = 2 * c;
+        int re = 0, rl = 0;
+        for (int t = 0; t < tid; ++t) {
+            re += (ek[t] == b);
+            rl += (lk[t] == c + a);
+        }
+        perm[bc[(int64_t)blockIdx.x * K + b] + re] = j;
+        perm[bc[(int64_t)blockIdx.x * K + c + a] + rl] = j;
+    }
+}
+
+// gsum[:, k] += (entering partials) - (leaving partials) for every group with
+// moved columns; C[:, k] = gsum[:, k] / n_k (an emptied group keeps C[:, k] and
+// its sum becomes exactly zero).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_group_update(const double* __restrict__ partial,
+                                                         int64_t d, int c,
+                                                         const int32_t* __restrict__ counts_new,
+                                                         const int32_t* __restrict__ seg_first,
+                                                         double* __restrict__ gsum, T* C) {
+    const int k = blockIdx.y;
+    const int e0 = seg_first[k], e1 = seg_first[k + 1];
+    const int l0 = seg_first[c + k], l1 = seg_first[c + k + 1];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if ((e0 == e1 && l0 == l1) || i >= d) return;   // no column entered or left group k
+    const int nk = counts_new[k];
+    double* gk = gsum + (int64_t)k * d;
+    if (nk == 0) {
+        gk[i] = 0.0;
+        return;
+    }
+    double add = 0.0, sub = 0.0;
+    for (int g = e0; g < e1; ++g) add += partial[(int64_t)g * d + i];
+    for (int g = l0; g < l1; ++g) sub += partial[(int64_t)g * d + i];
+    const double sum = gk[i] + (add - sub);
+    gk[i] = sum;
+    C[(int64_t)k * d + i] = (T)(sum / (double)nk);
 }
 
 template <typename T>
@@ -622,9 +777,10 @@ template <typename T>
 void launch_group_partial(bool with_d, const T* A, int64_t lda, const T* S, int64_t lds,
                           const T* Th, int64_t ldt, T inv_rho, int64_t d, int64_t n, int c,
                           const int32_t* perm, const int32_t* seg_begin, const int32_t* seg_len,
-                          const int32_t* nseg, double* partial, hipStream_t st) {
+                          const int32_t* nseg, double* partial, hipStream_t st, int max_seg) {
     const int nrb = row_blocks(d);
-    const unsigned grid = (unsigned)max_segments(n, c) * (unsigned)nrb;
+    const unsigned grid = (unsigned)(max_seg >= 0 ? max_seg : max_segments(n, c)) * (unsigned)nrb;
+    if (grid == 0) return;
     int v = with_d ? pick_vec<T>(d, {{A, lda}, {S, lds}, {Th, ldt}}) : pick_vec<T>(d, {{A, lda}});
     constexpr int VV = 16 / sizeof(T);
     if (with_d) {
@@ -650,9 +806,36 @@ void launch_group_partial(bool with_d, const T* A, int64_t lda, const T* S, int6
 
 template <typename T>
 void launch_group_finalize(const double* partial, int64_t d, int c, const int32_t* counts,
-                           const int32_t* seg_first, T* C, hipStream_t st) {
+                           const int32_t* seg_first, T* C, hipStream_t st, double* gsum) {
     k_group_finalize<T><<<dim3((unsigned)((d + kBlock - 1) / kBlock), c), kBlock, 0, st>>>(
-        partial, d, counts, seg_first, C);
+        partial, d, counts, seg_first, C, gsum);
+}
+
+int64_t changed_sort_scratch_ints(int64_t n, int c) {
+    return ((n + kSortChunk - 1) / kSortChunk) * (int64_t)(2 * c);
+}
+
+int changed_max_segments(int64_t moved, int c) {
+    const int64_t entries = 2 * moved;
+    return (int)((entries + kSegCols - 1) / kSegCols + std::min<int64_t>(2 * (int64_t)c, entries));
+}
+
+void launch_changed_sort(const int32_t* new_labels, const int32_t* old_labels, int64_t n, int c,
+                         int32_t* bc, const int32_t* counts_old, int32_t* counts_new, int32_t* perm,
+                         int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg,
+                         int max_seg, hipStream_t st) {
+    const int nb = (int)((n + kSortChunk - 1) / kSortChunk);
+    k_chg_hist<<<nb, kSortChunk, 0, st>>>(new_labels, old_labels, (int)n, c, bc);
+    k_chg_scan<<<1, kMaxGroups, 0, st>>>(bc, nb, c, counts_old, counts_new, seg_begin, seg_len,
+                                         seg_first, nseg, max_seg);
+    k_chg_scatter<<<nb, kSortChunk, 0, st>>>(new_labels, old_labels, (int)n, c, bc, perm);
+}
+
+template <typename T>
+void launch_group_update(const double* partial, int64_t d, int c, const int32_t* counts_new,
+                         const int32_t* seg_first, double* gsum, T* C, hipStream_t st) {
+    k_group_update<T><<<dim3((unsigned)((d + kBlock - 1) / kBlock), c), kBlock, 0, st>>>(
+        partial, d, c, counts_new, seg_first, gsum, C);
 }
 
 template <typename T>
@@ -769,9 +952,11 @@ void launch_gather_cols(const T* Y, int64_t ldy, int64_t d, const int32_t* idx, 
     template void launch_group_partial<T>(bool, const T*, int64_t, const T*, int64_t, const T*,     \
                                           int64_t, T, int64_t, int64_t, int, const int32_t*,       \
                                           const int32_t*, const int32_t*, const int32_t*, double*, \
-                                          hipStream_t);                                            \
+                                          hipStream_t, int);                                       \
     template void launch_group_finalize<T>(const double*, int64_t, int, const int32_t*,            \
-                                           const int32_t*, T*, hipStream_t);                       \
+                                           const int32_t*, T*, hipStream_t, double*);              \
+    template void launch_group_update<T>(const double*, int64_t, int, const int32_t*,              \
+                                         const int32_t*, double*, T*, hipStream_t);                \
     template void launch_col_sqnorm<T>(const T*, int64_t, int, double*, hipStream_t);              \
     template int launch_sweep_seg<T>(const T*, int64_t, T*, int64_t, T*, int64_t, T*, int64_t,    \
                                      const T*, const int32_t*, const int32_t*, const int32_t*,     \

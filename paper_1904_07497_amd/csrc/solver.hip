@@ -191,9 +191,10 @@ struct Engine {
     }
 
     // C[:, k] <- mean over group k of Y (Y = X - S + Theta*inv_rho when with_d),
-    // for the groups of the last sort; empty groups keep C[:, k].
+    // for the groups of the last sort; empty groups keep C[:, k].  With gsum the
+    // group sums (double) are kept for incremental updates.
     void group_means(bool with_d, const T* A, int64_t lda, const T* S, int64_t lds, const T* Th,
-                     int64_t ldt, T inv_rho, T* C) {
+                     int64_t ldt, T inv_rho, T* C, double* gsum = nullptr) {
         {
             ProfScope ps(h, st, RESPCA_KERNEL_MEANS, (with_d ? 3.0 : 1.0) * (double)d * n * sizeof(T));
             launch_group_partial<T>(with_d, A, lda, S, lds, Th, ldt, inv_rho, d, n, c, perm(),
@@ -201,7 +202,50 @@ struct Engine {
                                 (const int32_t*)h->nseg.p, (double*)h->pmeans.p, st);
         }
         launch_group_finalize<T>((const double*)h->pmeans.p, d, c, counts(),
-                                 (const int32_t*)h->segf.p, C, st);
+                                 (const int32_t*)h->segf.p, C, st, gsum);
+    }
+
+    // Columns an assignment pass may move for the incremental means (more: a
+    // full means pass).
+    int64_t moved_cap() const { return n / 8; }
+
+    // Group sums (double, d x c) kept by the full means passes of Lloyd.
+    respca_status group_sums(double*& out) {
+        CKS(ensure(h, h->gsum, (size_t)c * d * sizeof(double)));
+        out = (double*)h->gsum.p;
+        return RESPCA_OK;
+    }
+
+    // C and the group sums for labels `neu` from those for labels `old`, moving
+    // only the `moved` columns whose label changed (moved <= moved_cap()); the
+    // group counts follow.  The sort tables are left as they were (the caller
+    // re-sorts before it needs them).
+    respca_status update_means(const T* Y, int64_t ldy, const int32_t* neu, const int32_t* old,
+                               int64_t moved, T* C) {
+        const int maxs = changed_max_segments(moved_cap(), c);
+        CKS(ensure(h, h->cnt2, c * sizeof(int32_t)));
+        CKS(ensure(h, h->cbc, (size_t)changed_sort_scratch_ints(n, c) * sizeof(int32_t)));
+        CKS(ensure(h, h->cperm, 2 * (size_t)n * sizeof(int32_t)));
+        CKS(ensure(h, h->csegb, (size_t)maxs * sizeof(int32_t)));
+        CKS(ensure(h, h->csegl, (size_t)maxs * sizeof(int32_t)));
+        CKS(ensure(h, h->csegf, (2 * (size_t)c + 1) * sizeof(int32_t)));
+        CKS(ensure(h, h->cnseg, sizeof(int32_t)));
+        CKS(ensure(h, h->cpart, (size_t)maxs * d * sizeof(double)));
+        int32_t* cnt2 = (int32_t*)h->cnt2.p;
+        launch_changed_sort(neu, old, n, c, (int32_t*)h->cbc.p, counts(), cnt2, (int32_t*)h->cperm.p,
+                            (int32_t*)h->csegb.p, (int32_t*)h->csegl.p, (int32_t*)h->csegf.p,
+                            (int32_t*)h->cnseg.p, maxs, st);
+        {
+            ProfScope ps(h, st, RESPCA_KERNEL_MEANS, 2.0 * (double)moved * d * sizeof(T));
+            launch_group_partial<T>(false, Y, ldy, nullptr, 0, nullptr, 0, T(0), d, n, c,
+                                    (const int32_t*)h->cperm.p, (const int32_t*)h->csegb.p,
+                                    (const int32_t*)h->csegl.p, (const int32_t*)h->cnseg.p,
+                                    (double*)h->cpart.p, st, changed_max_segments(moved, c));
+        }
+        launch_group_update<T>((const double*)h->cpart.p, d, c, cnt2, (const int32_t*)h->csegf.p,
+                               (double*)h->gsum.p, C, st);
+        CK(hipMemcpyAsync(counts(), cnt2, c * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        return RESPCA_OK;
     }
 
     // Assignment pass: new = nearest centroid of every column of Y; status[3] = #changed.
@@ -220,10 +264,14 @@ struct Engine {
     }
 
     // Lloyd passes on the columns of Y from (cur, C); see oracle_lloyd for the
-    // exact rule.  `first` receives the status of the first pass.
+    // exact rule.  `first` receives the status of the first pass.  sums_valid:
+    // the group sums hold those of Y for the labels in cur (left by the caller's
+    // means pass); then, and after each full means pass here, a pass that moved
+    // few columns updates the means from the moved columns only.
     respca_status lloyd(const T* Y, int64_t ldy, T* C, int32_t*& cur, int32_t*& alt, int max_lloyd,
-                        int& steps, double first[4]) {
+                        int& steps, double first[4], bool sums_valid = false) {
         steps = 0;
+        bool have = sums_valid;
         while (steps < max_lloyd) {
             assign(Y, ldy, C, cur, alt);
             double s[4];
@@ -232,8 +280,16 @@ struct Engine {
             ++steps;
             if (s[3] == 0.0) break;
             std::swap(cur, alt);
-            sort(cur);
-            group_means(false, Y, ldy, nullptr, 0, nullptr, 0, T(0), C);
+            const int64_t moved = (int64_t)s[3];
+            if (have && moved <= moved_cap()) {
+                CKS(update_means(Y, ldy, cur, alt, moved, C));
+            } else {
+                double* gs = nullptr;
+                CKS(group_sums(gs));
+                sort(cur);
+                group_means(false, Y, ldy, nullptr, 0, nullptr, 0, T(0), C, gs);
+                have = true;
+            }
         }
         return RESPCA_OK;
     }
@@ -304,9 +360,11 @@ struct Engine {
         launch_zero_i32(cur, n, st);
         assign(Y, ldy, C, cur, alt);
         std::swap(cur, alt);
+        double* gs = nullptr;
+        CKS(group_sums(gs));
         sort(cur);
-        group_means(false, Y, ldy, nullptr, 0, nullptr, 0, T(0), C);
-        CKS(lloyd(Y, ldy, C, cur, alt, max_lloyd, steps, nullptr));  // also waits for the pinned stage
+        group_means(false, Y, ldy, nullptr, 0, nullptr, 0, T(0), C, gs);
+        CKS(lloyd(Y, ldy, C, cur, alt, max_lloyd, steps, nullptr, true));  // also waits for the pinned stage
         return RESPCA_OK;
     }
 
@@ -383,10 +441,12 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
         CK(hipMemcpyAsync(cur, h->embl.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
         // Lloyd on the columns of X from the means of X over those groups (empty at zero)
         launch_zero2d<T>(C, d, d, r.c, st);
+        double* gs = nullptr;
+        CKS(e.group_sums(gs));
         e.sort(cur);
-        e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C);
+        e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C, gs);
         int ref = 0;
-        CKS(e.lloyd(X, ldx, C, cur, alt, r.max_lloyd, ref, nullptr));
+        CKS(e.lloyd(X, ldx, C, cur, alt, r.max_lloyd, ref, nullptr, true));
         info->init_lloyd = steps + ref;
         // then as with given initial labels
         launch_zero2d<T>(C, d, d, r.c, st);
@@ -559,7 +619,8 @@ void respca_destroy(respca_handle h) {
         if (b->p) (void)hipFree(b->p);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
                       &h->nseg, &h->sortbc, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b, &h->d2,
-                      &h->zcopy, &h->zsc, &h->ynorm,
+                      &h->zcopy, &h->zsc, &h->ynorm, &h->gsum, &h->cnt2, &h->cbc, &h->cperm,
+                      &h->csegb, &h->csegl, &h->csegf, &h->cnseg, &h->cpart,
                       &h->chosen, &h->seeds, &h->u, &h->normp, &h->chgp, &h->status};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
