@@ -42,6 +42,7 @@ struct BatchInst {
     int32_t* seeds;
     const double* u;           // k-means++ uniforms (host-drawn from splitmix64(seed))
     double* cnorm;
+    double* gsum;              // [group][rows]: group sums (double) of the last Lloyd-family means
     double* sweep_part;        // 3 per sweep item (segment x row block), 1 per pack tile
     int32_t* chg;              // 1 per 16-column argmin item
     // shape and tiling.  The initial K-means runs on the columns of X (kdp = dp) or of
@@ -56,6 +57,11 @@ struct BatchInst {
     int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, ref_lloyd, status, nseg;
     int next_ready;            // pmeans and the sort tables hold the next L-step's group sums
     int meansd;                // outer iterations that ran the means pass over X, S, Theta
+    int pmode;                 // mode of the previous step
+    int moved;                 // columns whose label the previous step's assignment changed
+    int inc;                   // this step's means are the incremental update (moved columns only)
+    int inc_steps[2];          // incremental means steps on the d-row matrices [0] / the embedding [1]
+    int64_t inc_cols[2];       // columns those steps read (two per moved column)
     double rho, nx, rho_final, primal, dL, dS;
 };
 

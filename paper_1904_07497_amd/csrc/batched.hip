@@ -120,6 +120,17 @@ __device__ inline bool needs_assign(int m) {
     return m == M_SEED || m == M_KMX || m == M_ITER || m == M_LL || m == M_REFX;
 }
 
+// Modes whose means pass is a Lloyd step on an unchanged matrix (the sums can be
+// carried from one step to the next).
+__device__ inline bool lloyd_family(int m) { return m == M_KMX || m == M_LL || m == M_REFX; }
+
+// Segments of the moved-column sort for `moved` columns (2 entries each, at most
+// 2c keys), as in changed_max_segments.
+__device__ inline int moved_segments(int moved, int c) {
+    const int e = 2 * moved;
+    return (e + kBatchSegCols - 1) / kBatchSegCols + min(2 * c, e);
+}
+
 // Matrix whose columns the current mode clusters, and its row count (= its
 // leading dimension and that of the centroids).
 __device__ inline const float* kmeans_matrix(const BatchInst& B, int m) {
@@ -135,22 +146,38 @@ __device__ inline int mode_rows(const BatchInst& B, int m) {
 
 // Stable counting sort of one instance's labels by one workgroup, with the
 // segment table of the means pass (runs of <= kBatchSegCols columns of one group).
-__device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab) {
+// With old labels (2c <= kMaxGroups) it sorts only the moved columns instead:
+// column j with old[j] = a != lab[j] = b is listed under key b (entering) and key
+// c + a (leaving), keys in order and columns in order within a key; the segment
+// table then has 2c + 1 entries in segf and the counts become those of lab.
+__device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab,
+                              const int32_t* __restrict__ old = nullptr) {
     __shared__ int hist[kMaxGroups];
     __shared__ int offs[kMaxGroups];
     __shared__ int wsum[kBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = B.n, c = B.c;
-    for (int k = tid; k < c; k += kBlock) hist[k] = 0;
+    const int K = old ? 2 * c : c;   // keys
+    for (int k = tid; k < K; k += kBlock) hist[k] = 0;
     __syncthreads();
-    for (int j = tid; j < n; j += kBlock) atomicAdd(&hist[lab[j]], 1);
+    if (old) {
+        for (int j = tid; j < n; j += kBlock) {
+            const int a = old[j], b = lab[j];
+            if (a != b) {
+                atomicAdd(&hist[b], 1);
+                atomicAdd(&hist[c + a], 1);
+            }
+        }
+    } else {
+        for (int j = tid; j < n; j += kBlock) atomicAdd(&hist[lab[j]], 1);
+    }
     __syncthreads();
     // each thread owns 4 consecutive groups; two block exclusive scans
     int cnt[4], nsg[4], my_c = 0, my_s = 0;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int k = tid * 4 + g;
-        cnt[g] = k < c ? hist[k] : 0;
+        cnt[g] = k < K ? hist[k] : 0;
         nsg[g] = (cnt[g] + kBatchSegCols - 1) / kBatchSegCols;
         my_c += cnt[g];
         my_s += nsg[g];
@@ -174,44 +201,59 @@ __device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab) {
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int k = tid * 4 + g;
-        if (k < c) {
+        if (k < K) {
             offs[k] = bc;
-            B.counts[k] = cnt[g];
+            if (!old) B.counts[k] = cnt[g];
             B.segf[k] = bs;
             for (int q = 0; q < nsg[g]; ++q) {
                 B.segb[bs + q] = bc + q * kBatchSegCols;
                 B.segl[bs + q] = min(kBatchSegCols, cnt[g] - q * kBatchSegCols);
             }
-            if (k == c - 1) { B.segf[c] = bs + nsg[g]; B.nseg = bs + nsg[g]; }
+            if (k == K - 1) { B.segf[K] = bs + nsg[g]; B.nseg = bs + nsg[g]; }
         }
         bc += cnt[g];
         bs += nsg[g];
     }
+    if (old)   // counts of the new labels: entering minus leaving
+        for (int k = tid; k < c; k += kBlock) B.counts[k] += hist[k] - hist[c + k];
     __syncthreads();
     // stable scatter by wave 0, 64 columns at a time: the lanes holding the same
     // label are found with one ballot per label bit; a lane's rank among them is
     // the count of such lanes below it, and the lowest of them advances the offset.
     if (wave == 0) {
         int nbits = 0;
-        while ((1 << nbits) < c) ++nbits;
+        while ((1 << nbits) < K) ++nbits;
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        for (int base = 0; base < n; base += 64) {
-            const int j = base + lane;
-            const bool valid = j < n;
-            const int my = valid ? lab[j] : 0;
-            uint64_t same = __ballot(valid);
-            for (int b = 0; b < nbits; ++b) {
-                const bool bit = (my >> b) & 1;
-                const uint64_t m = __ballot(bit);
-                same &= bit ? m : ~m;
+        // pass 0: every column under its label, or (old) the entering keys; pass 1
+        // (old only): the leaving keys
+        for (int pass = 0; pass < (old ? 2 : 1); ++pass)
+            for (int base = 0; base < n; base += 64) {
+                const int j = base + lane;
+                bool valid = j < n;
+                int my = 0;
+                if (valid) {
+                    if (!old) {
+                        my = lab[j];
+                    } else {
+                        const int a = old[j], b = lab[j];
+                        valid = a != b;
+                        my = pass == 0 ? b : c + a;
+                    }
+                }
+                uint64_t same = __ballot(valid);
+                if (same == 0) continue;   // nothing of this pass in these 64 columns
+                for (int b = 0; b < nbits; ++b) {
+                    const bool bit = (my >> b) & 1;
+                    const uint64_t m = __ballot(bit);
+                    same &= bit ? m : ~m;
+                }
+                const int rank = __popcll(same & below);
+                const int base_off = offs[my];
+                if (valid) {
+                    B.perm[base_off + rank] = j;
+                    if (rank == 0) offs[my] = base_off + __popcll(same);
+                }
             }
-            const int rank = __popcll(same & below);
-            const int base_off = offs[my];
-            if (valid) {
-                B.perm[base_off + rank] = j;
-                if (rank == 0) offs[my] = base_off + __popcll(same);
-            }
-        }
     }
     __syncthreads();   // the tables are reused by the next instance of this workgroup
 }
@@ -299,11 +341,13 @@ __device__ void control_instance(BatchInst& B, int* active) {
     block_sum3(a0, a1, a2);
     if (threadIdx.x != 0) return;
     const int mode = mode0;
+    B.pmode = mode;
     if (mode == M_MEANSX) {   // embedding groups: Lloyd on X next, once; then the iterations
         if (B.Z && B.ref_lloyd == 0) { B.mode = M_REFX; } else { B.mode = M_ITER; }
         return;
     }
     const int changed = (int)ch;
+    B.moved = changed;
     if (mode == M_SEED) { B.cur ^= 1; B.mode = M_KMX; return; }
     if (mode == M_KMX) {
         B.init_lloyd += 1;
@@ -464,6 +508,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             B.iters = B.lloyd_total = B.lloyd_iter = B.init_lloyd = B.ref_lloyd = 0;
             B.next_ready = 0;
             B.meansd = 0;
+            B.pmode = M_DONE;
+            B.moved = 0;
+            B.inc = 0;
+            B.inc_steps[0] = B.inc_steps[1] = 0;
+            B.inc_cols[0] = B.inc_cols[1] = 0;
             B.rho = B.rho0;
             B.rho_final = 0.0;
             B.primal = B.dL = B.dS = 0.0;
@@ -535,7 +584,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         // A: sort the current labels
         for (int i = blockIdx.x; i < batch; i += nb) {
             BatchInst& B = inst[i];
-            if (needs_groups(s_mode[i]) && !s_ready[i]) sort_instance(B, B.lab[B.cur]);
+            const int m = s_mode[i];
+            // a Lloyd-family step after one of the same mode that moved few columns
+            // updates the previous step's sums from the moved columns only
+            const bool inc = needs_groups(m) && !s_ready[i] && lloyd_family(m) && B.pmode == m &&
+                             2 * B.c <= kMaxGroups && B.moved <= B.n / 8 &&
+                             moved_segments(B.moved, B.c) <= (B.n + kBatchSegCols - 1) / kBatchSegCols + B.c;
+            if (needs_groups(m) && !s_ready[i])
+                sort_instance(B, B.lab[B.cur], inc ? B.lab[B.cur ^ 1] : nullptr);
+            if (threadIdx.x == 0) {
+                B.inc = inc ? 1 : 0;
+                if (inc) {
+                    const int z = (m == M_KMX && B.Z) ? 1 : 0;
+                    B.inc_steps[z] += 1;
+                    B.inc_cols[z] += 2 * (int64_t)B.moved;
+                }
+            }
         }
         if (!grid_sync(gs, nb, tmo, BP_SORT, tclk)) return;
         for (int t = threadIdx.x; t < batch; t += kBlock)
@@ -572,15 +636,39 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             const int mode = s_mode[i];
             const int rows = mode_rows(B, mode);
             float* Ck = B.C + (int64_t)k * rows;
+            double* Gk = B.gsum + (int64_t)k * rows;
             double a = 0.0, zb = 0.0, zc = 0.0;
-            if (needs_groups(mode)) {
+            if (needs_groups(mode) && B.inc) {
+                // incremental: sums plus entering minus leaving partials, in segment order
+                const int e0 = B.segf[k], e1 = B.segf[k + 1];
+                const int l0 = B.segf[B.c + k], l1 = B.segf[B.c + k + 1];
+                if (e0 == e1 && l0 == l1) return;   // no column entered or left: C and its norm stay
+                const int nk = B.counts[k];
+                for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
+                    float v = Ck[r];
+                    if (nk == 0) {
+                        Gk[r] = 0.0;   // emptied: the centroid stays, its sum is exactly zero
+                    } else {
+                        double add = 0.0, sub = 0.0;
+                        for (int g = e0; g < e1; ++g) add += B.pmeans[(int64_t)g * rows + r];
+                        for (int g = l0; g < l1; ++g) sub += B.pmeans[(int64_t)g * rows + r];
+                        const double sum = Gk[r] + (add - sub);
+                        Gk[r] = sum;
+                        v = (float)(sum / (double)nk);
+                        Ck[r] = v;
+                    }
+                    a += (double)v * (double)v;
+                }
+            } else if (needs_groups(mode)) {
                 const int nk = B.counts[k];
                 const int g0 = B.segf[k], g1 = B.segf[k + 1];
+                const bool keep = lloyd_family(mode);   // sums carried to the next Lloyd step
                 for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
                     float v;
                     if (nk == 0) {
                         v = mode == M_MEANSX ? 0.f : Ck[r];
                         if (mode == M_MEANSX) Ck[r] = 0.f;
+                        if (keep) Gk[r] = 0.0;
                     } else {
                         double sum = 0.0;
                         for (int g = g0; g < g1; g += 4) {   // four loads in flight, added in order
@@ -592,6 +680,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                             for (int u = 0; u < 4; ++u)
                                 if (g + u < g1) sum += v[u];
                         }
+                        if (keep) Gk[r] = sum;
                         v = (float)(sum / (double)nk);
                         Ck[r] = v;
                     }

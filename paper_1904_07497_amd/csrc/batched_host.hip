@@ -160,13 +160,14 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.counts = (int32_t*)take(B.c * sizeof(int32_t));
         B.segb = (int32_t*)take(nseg_max * sizeof(int32_t));
         B.segl = (int32_t*)take(nseg_max * sizeof(int32_t));
-        B.segf = (int32_t*)take((B.c + 1) * sizeof(int32_t));
+        B.segf = (int32_t*)take((2 * (size_t)B.c + 1) * sizeof(int32_t));   // 2c keys when incremental
         B.pmeans = (double*)take((size_t)nseg_max * B.mrows * sizeof(double));
         B.part = (float*)take((size_t)B.slices * B.n * B.kpad * sizeof(float));
         B.d2 = (double*)take(B.n * sizeof(double));
         B.chosen = (int32_t*)take(B.n * sizeof(int32_t));
         B.seeds = (int32_t*)take(B.c * sizeof(int32_t));
         B.cnorm = (double*)take(B.c * sizeof(double));
+        B.gsum = (double*)take((size_t)B.mrows * B.c * sizeof(double));
         B.sweep_part = (double*)take(3 * (size_t)std::max(B.n_sweep, B.n_tile) * sizeof(double));
         B.chg = (int32_t*)take(B.n_argmin * sizeof(int32_t));
         // k-means++ uniforms from the instance's seed
@@ -222,7 +223,7 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
         BatchInst& B = call.inst[i];
         fix(B.X); fix(B.L); fix(B.S); fix(B.Th); fix(B.C); fix(B.lab[0]); fix(B.lab[1]); fix(B.perm);
         fix(B.counts); fix(B.segb); fix(B.segl); fix(B.segf); fix(B.pmeans); fix(B.part); fix(B.d2);
-        fix(B.chosen); fix(B.seeds); fix(B.cnorm); fix(B.sweep_part); fix(B.chg);
+        fix(B.chosen); fix(B.seeds); fix(B.cnorm); fix(B.gsum); fix(B.sweep_part); fix(B.chg);
         if (B.Ec) fix(B.Z);
         B.u = u_dev + call.u_start[i];
     }
@@ -328,6 +329,9 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
                 px += 2.0 + 2.0 * B.ref_lloyd;
                 pz = (double)B.c + 1.0 + 2.0 * (B.init_lloyd - B.ref_lloyd);
             } else px += (double)B.c + 1.0 + 2.0 * B.init_lloyd;
+            // a means step done incrementally read only the moved columns (twice each)
+            px -= (double)B.inc_steps[0] - (double)B.inc_cols[0] / (double)B.n;
+            pz -= (double)B.inc_steps[1] - (double)B.inc_cols[1] / (double)B.n;
             alg_bytes += (double)B.n * sizeof(float) * ((double)B.d * px + (double)B.er * pz);
         }
         if (info) {
