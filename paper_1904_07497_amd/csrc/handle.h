@@ -48,7 +48,9 @@ struct respca_handle_s {
     respca::DevBuf zcopy, zsc, ynorm;   // fp16 copy, column scales and norms for bounded seeding
     // incremental Lloyd means: group sums, next counts, the moved-column sort and its partials
     respca::DevBuf gsum, cnt2, cbc, cperm, csegb, csegl, csegf, cnseg, cpart;
-    double* hstage = nullptr;  // pinned host staging (status readback, uniforms)
+    double* hstage = nullptr;  // pinned host staging (uniforms, small copies)
+    double* hstatus = nullptr;      // pinned host status words the kernels write directly
+    double* hstatus_dev = nullptr;  // the same memory as the device sees it
     size_t hstage_bytes = 0;
     // batched solver
     respca::BatchTune tune;

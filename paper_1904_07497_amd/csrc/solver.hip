@@ -133,7 +133,7 @@ struct Engine {
     int c;
     bool bf16;       // split-bf16 MFMA distances with exact refinement (float runs)
     int nrb;
-    double* status;  // device: [0..2] norms^2, [3] changed count, [4] refined columns
+    double* status;  // pinned host words (device view): [0..2] norms^2, [3] changed count, [4] refined columns
     int64_t refined = 0;
     bool next_ready = false;   // pmeans / sort tables hold the next L-step's group sums of D
 
@@ -157,9 +157,12 @@ struct Engine {
         if (nsum > np) np = nsum;
         CKS(ensure(h, h->normp, 3 * np * sizeof(double)));
         CKS(ensure(h, h->chgp, (size_t)assign_partials_max(n) * sizeof(double)));
-        CKS(ensure(h, h->status, 8 * sizeof(double)));
         CKS(ensure_host(h, (16 + 2 * (size_t)c) * sizeof(double)));
-        status = (double*)h->status.p;
+        if (!h->hstatus) {   // status words in pinned host memory: no copy before each readback
+            CK(hipHostMalloc((void**)&h->hstatus, 8 * sizeof(double), hipHostMallocMapped));
+            CK(hipHostGetDevicePointer((void**)&h->hstatus_dev, h->hstatus, 0));
+        }
+        status = h->hstatus_dev;
         return RESPCA_OK;
     }
 
@@ -168,10 +171,10 @@ struct Engine {
 
     respca_status readback(double out[4]) {
         CK(hipGetLastError());
-        CK(hipMemcpyAsync(h->hstage, status, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
-        for (int i = 0; i < 4; ++i) out[i] = h->hstage[i];
-        refined += (int64_t)h->hstage[4];
+        CK(hipStreamSynchronize(st));   // the kernels wrote the words themselves
+        const volatile double* w = h->hstatus;
+        for (int i = 0; i < 4; ++i) out[i] = w[i];
+        refined += (int64_t)w[4];
         prof_resolve(h);
         return RESPCA_OK;
     }
@@ -625,6 +628,7 @@ void respca_destroy(respca_handle h) {
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (h->hstage) (void)hipHostFree(h->hstage);
+    if (h->hstatus) (void)hipHostFree(h->hstatus);
     delete h;
 }
 
