@@ -73,25 +73,17 @@ struct StageRegs {
         }
     }
 
+    // Scalar layout: rows [r, r + 32) of columns [col0, col0 + 128), zero outside the
+    // matrix (the VEC layout loads through init / load_rows).
     __device__ inline void load(const float* __restrict__ src, int64_t ld, int64_t col0,
                                 int64_t ncols, int64_t r, int64_t rend) {
+        static_assert(!VEC, "the VEC layout loads through init / load_rows");
         const int tid = threadIdx.x;
-        if constexpr (VEC) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int col = p * 32 + (tid >> 3);
-                const int rr = (tid & 7) * 4;
-                const int64_t gj = col0 + col, gi = r + rr;
-                v4[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (gj < ncols && gi < rend) v4[p] = *reinterpret_cast<const float4*>(src + gj * ld + gi);
-            }
-        } else {
-#pragma unroll
-            for (int p = 0; p < 16; ++p) {
-                const int e = tid + 256 * p, col = e >> 5, rr = e & 31;
-                const int64_t gj = col0 + col, gi = r + rr;
-                v1[p] = (gj < ncols && gi < rend) ? src[gj * ld + gi] : 0.f;
-            }
+        for (int p = 0; p < 16; ++p) {
+            const int e = tid + 256 * p, col = e >> 5, rr = e & 31;
+            const int64_t gj = col0 + col, gi = r + rr;
+            v1[p] = (gj < ncols && gi < rend) ? src[gj * ld + gi] : 0.f;
         }
     }
 
