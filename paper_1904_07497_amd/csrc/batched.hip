@@ -703,8 +703,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             BatchInst& B = inst[i];
             const int sg = local / B.mrb, rb = local % B.mrb;
             const int64_t r0 = (int64_t)rb * kBatchRows;
+            if (sg >= s_nseg[i] || r0 >= B.dp) {   // no segment or rows here: zero partials only
+                if (threadIdx.x < 3) B.sweep_part[3 * local + threadIdx.x] = 0.0;
+                return;
+            }
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            if (sg < s_nseg[i] && r0 < B.dp) {
+            {
                 const double rho = B.rho;
                 const double alpha = rho / (2.0 * B.lambda + rho);
                 const double beta = (2.0 * B.lambda) / (2.0 * B.lambda + rho);
