@@ -90,7 +90,7 @@ struct BatchArgs {
     int max_steps;
     // prefix tables (batch + 1 entries) of per-instance work items
     const int32_t* off_tile;   // ceil(n/jc) * nrb   (pack, unpack; nrb = ceil(dp/256))
-    const int32_t* off_d2;     // ceil(n/4)          (k-means++ distances, wave per column)
+    const int32_t* off_d2;     // ceil(n/16)         (k-means++ distances, four columns per wave)
     const int32_t* off_kc;     // c                  (seed columns, centroids and their norms)
     const int32_t* off_seg;    // (ceil(n/64) + c) * mrb (group partial sums, sweep)
     const int32_t* off_dist;   // ceil(n/128) * slices * nkc (distance tiles)

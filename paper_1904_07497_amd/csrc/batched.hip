@@ -548,17 +548,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     auto is_seed = [](int m, int) { return m == M_SEED; };
     for (int m = 0; m < A.cmax; ++m) {
         load_tab(A.off_d2);
-        for_items(batch, s_tab, s_mode, is_seed, [&](int i, int local) {
+        // instances with fewer seeds than m + 1 are skipped whole
+        auto seeds_m = [&](int mode, int i) { return mode == M_SEED && m < inst[i].c; };
+        for_items(batch, s_tab, s_mode, seeds_m, [&](int i, int local) {
             BatchInst& B = inst[i];
-            if (m >= B.c) return;
             const int lane = threadIdx.x & 63;
-            const int64_t j = (int64_t)local * 4 + (threadIdx.x >> 6);
-            if (j >= B.n) return;
             const float* Y = B.Z ? B.Z : B.X;
             const int rows = B.kdp;
-            // rows is a multiple of 4 (zero padded): four row groups of float4 in flight
-            const double acc = d2_column<float, 4>(Y + j * rows, Y + (int64_t)B.seeds[m] * rows, rows, lane);
-            if (lane == 0) B.d2[j] = (m == 0) ? acc : fmin(B.d2[j], acc);
+            const float* ys = Y + (int64_t)B.seeds[m] * rows;
+            // 16 columns per item, four per wave in turn
+            for (int t = 0; t < 4; ++t) {
+                const int64_t j = (int64_t)local * 16 + (threadIdx.x >> 6) * 4 + t;
+                if (j >= B.n) break;
+                // rows is a multiple of 4 (zero padded): four row groups of float4 in flight
+                const double acc = d2_column<float, 4>(Y + j * rows, ys, rows, lane);
+                if (lane == 0) B.d2[j] = (m == 0) ? acc : fmin(B.d2[j], acc);
+            }
         });
         if (!grid_sync(gs, nb, tmo, BP_SEED_D2, tclk)) return;
         if (m + 1 >= A.cmax) break;

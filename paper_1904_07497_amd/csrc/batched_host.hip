@@ -141,7 +141,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.max_iter = r.max_iter;
         B.max_lloyd = r.max_lloyd;
         // work tables (prefix sums)
-        const int64_t counts[kTableCount] = {B.n_tile, (B.n + 3) / 4, B.c, (int64_t)nseg_max * B.mrb,
+        const int64_t counts[kTableCount] = {B.n_tile, (B.n + 15) / 16, B.c, (int64_t)nseg_max * B.mrb,
                                              (int64_t)ntiles * B.slices * B.nkc, B.n_argmin};
         for (int t = 0; t < kTableCount; ++t)
             call.tables[t][i + 1] = call.tables[t][i] + (int32_t)counts[t];
