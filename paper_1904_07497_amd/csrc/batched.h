@@ -44,7 +44,7 @@ struct BatchInst {
     double* cnorm;
     double* gsum;              // [group][rows]: group sums (double) of the last Lloyd-family means
     double* sweep_part;        // 3 per sweep item (segment x row block), 1 per pack tile
-    int32_t* chg;              // 1 per 16-column argmin item
+    int32_t* chg;              // 1 per wave of each 16-column argmin item
     // shape and tiling.  The initial K-means runs on the columns of X (kdp = dp) or of
     // the embedding (kdp = 4 * ceil(er / 4)); mrows = max(dp, kdp) and mrb row blocks
     // of kBatchRows cover both.

@@ -329,7 +329,7 @@ __device__ void control_instance(BatchInst& B, int* active) {
     if (!needs_assign(mode0) && mode0 != M_MEANSX) return;
     double ch = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0, z = 0.0;
     if (mode0 != M_MEANSX) {
-        for (int t = threadIdx.x; t < B.n_argmin; t += kBlock) ch += (double)B.chg[t];
+        for (int t = threadIdx.x; t < 4 * B.n_argmin; t += kBlock) ch += (double)B.chg[t];
         if (mode0 == M_ITER)
             for (int t = threadIdx.x; t < B.n_sweep; t += kBlock) {
                 a0 += B.sweep_part[3 * t];
@@ -780,15 +780,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 const int ok = __shfl_xor(bestk, o, 16);
                 if (od < bestd || (od == bestd && ok < bestk)) { bestd = od; bestk = ok; }
             }
-            double ch = 0.0;
+            bool moved = false;
             if (j < B.n && q == 0) {
                 const int lab = bestk == INT_MAX ? 0 : bestk;
                 B.lab[B.cur ^ 1][j] = lab;
-                ch = B.lab[B.cur][j] != lab ? 1.0 : 0.0;
+                moved = B.lab[B.cur][j] != lab;
             }
-            double z1 = 0.0, z2 = 0.0;
-            block_sum3(ch, z1, z2);
-            if (threadIdx.x == 0) B.chg[local] = (int)ch;
+            // changed count per wave (no workgroup barrier): chg[4 item + wave]
+            const int wch = __popcll(__ballot(moved));
+            if ((threadIdx.x & 63) == 0) B.chg[4 * local + (threadIdx.x >> 6)] = wch;
         });
         if (!grid_sync(gs, nb, tmo, BP_ARGMIN, tclk)) return;
         // H: control

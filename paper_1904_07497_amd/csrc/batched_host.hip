@@ -169,7 +169,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.cnorm = (double*)take(B.c * sizeof(double));
         B.gsum = (double*)take((size_t)B.mrows * B.c * sizeof(double));
         B.sweep_part = (double*)take(3 * (size_t)std::max(B.n_sweep, B.n_tile) * sizeof(double));
-        B.chg = (int32_t*)take(B.n_argmin * sizeof(int32_t));
+        B.chg = (int32_t*)take(4 * (size_t)B.n_argmin * sizeof(int32_t));   // one per argmin wave
         // k-means++ uniforms from the instance's seed
         call.u_start[i] = call.u.size();
         uint64_t state = r.init_labels ? 0 : r.seed;
