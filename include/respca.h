@@ -206,7 +206,9 @@ respca_status respca_autotune_batched(respca_handle h, const respca_params *para
  * launches, their summed event time and their summed algorithmic HBM bytes
  * (the bytes the method must move: every d x n array the kernel reads or
  * writes once, at the element size of the run).  Enabling (or disabling)
- * resets the counters.  Timing adds two event records per launch.
+ * resets the counters.  Timing adds two event records per timed launch, and
+ * each record can leave the device idle for a few microseconds, so a caller
+ * timing a whole solve may time only the unit it reports.
  */
 typedef enum {
     RESPCA_KERNEL_SWEEP = 0,      /* fused L/S/Theta sweep: reads X, S, Theta, L; writes L, S, Theta */
@@ -220,6 +222,9 @@ typedef enum {
     RESPCA_KERNEL_COUNT = 5
 } respca_kernel_id;
 
+/* enable: 0 turns timing off; otherwise bit k (1 << k) times the launches of
+ * respca_kernel_id k, and RESPCA_PROFILE_ALL times every unit. */
+#define RESPCA_PROFILE_ALL (-1)
 respca_status respca_profile_enable(respca_handle h, int32_t enable);
 /* launches, total_ms, bytes and flops are host outputs (any may be NULL).
  * flops counts the algorithmic floating-point operations (the distance

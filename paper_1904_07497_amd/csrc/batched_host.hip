@@ -290,7 +290,8 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     CK(hipStreamWaitEvent(h->bstream, h->bev, 0));
     hipEvent_t t0 = nullptr, t1 = nullptr;
     double prof_ms = 0.0;
-    if (!elapsed_ms && h->prof_on) elapsed_ms = &prof_ms;
+    const bool timed = (h->prof_mask >> RESPCA_KERNEL_BATCHED) & 1u;
+    if (!elapsed_ms && timed) elapsed_ms = &prof_ms;
     if (elapsed_ms) {
         CK(hipEventCreate(&t0));
         CK(hipEventCreate(&t1));
@@ -349,7 +350,7 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
         if (B.status < 0 && (worst >= 0 || B.status < worst)) worst = (respca_status)B.status;
         if (B.status == RESPCA_NOT_CONVERGED && worst == RESPCA_OK) worst = RESPCA_NOT_CONVERGED;
     }
-    if (h->prof_on) {
+    if (timed) {
         h->prof_launches[RESPCA_KERNEL_BATCHED] += 1;
         h->prof_ms[RESPCA_KERNEL_BATCHED] += *elapsed_ms;
         h->prof_bytes[RESPCA_KERNEL_BATCHED] += alg_bytes;

@@ -20,10 +20,12 @@
 // (K = rows summed in FP32).  The kernel also accumulates ||Y_j||^2; the argmin
 // kernel flags every column whose best and runner-up distances are not
 // separated by the bounds, and those columns are re-decided exactly (FP64
-// differences of the FP32 values) by a refinement kernel.  With at most 32
+// differences of the FP32 values) by a refinement kernel.  With 17 to 32
 // groups this bounded mode runs the FP32 MFMA tile instead (few MFMAs, no split
 // work; E = 2 (K + 2) 2^-24 ||C_k|| ||Y_j|| from the FP32 products and sums) with
-// the same argmin and refinement, so its labels are exact as well.
+// the same argmin and refinement, so its labels are exact as well.  With at most
+// 16 groups it accumulates the products in FP64 on the vector units (the FP64
+// tile below): the distances are then FP64 ones and nothing is refined.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -520,6 +522,224 @@ __global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ C
                          item, lane);
 }
 
+// ---- bounded mode with at most 16 groups: FP64 dot products on the vector units
+//
+// Every product of two FP32 values is exact in FP64, so C_k . Y_j accumulated in
+// FP64 carries a relative error of about (K + 16) 2^-53 of sum |c_i y_i| (K rows
+// summed per lane): the labels are those of the FP64 distances, as the
+// refinement's are, and nothing needs refining.  At c <= 16 the FP64 FMAs stay
+// below the time of reading Y once.
+//
+// A workgroup is 16 lane groups of 16 lanes; group q owns G adjacent columns and
+// the workgroup one slice of rows, whose centroid rows it first copies to LDS.
+// Lane r of a group holds rows 4r..4r+3 of every 64-row step (16 lanes read 256
+// contiguous bytes of a column), loads the next step's rows of its G columns
+// before it multiplies the current ones with the centroids from LDS, and keeps
+// G x NC FP64 sums; a 16-lane butterfly ends the slice and the per-slice sums go
+// to part[slice][column][group].  The workgroups of column block 0 also leave the
+// slice's share of ||C_k||^2.
+constexpr int kF64MaxC = 16;
+constexpr int kF64Step = 64;   // rows per step of a lane group
+
+// Columns per lane group: at most 6, and G x NC sums of at most 24 doubles.
+constexpr int f64_cols(int nc) { return 24 / nc < 1 ? 1 : (24 / nc > 6 ? 6 : 24 / nc); }
+// Steps of Y in flight per lane: the current one and kF64Ahead - 1 ahead.
+constexpr int kF64Ahead = 3;
+// Longest slice: its centroid rows take at most 32 KB of LDS.
+constexpr int f64_max_rows(int nc) { return nc <= 8 ? 1024 : 512; }
+
+// Rows rw..rw+3 of column p (VEC: p + rw 16-byte aligned).  FULL: all four rows are
+// below lim.  Otherwise rows at or past lim read row lim - 1 and become zero.
+template <bool VEC, bool FULL>
+__device__ inline float4 load_rows4(const float* __restrict__ p, int64_t rw, int64_t lim) {
+    if (VEC) {
+        const bool ok = FULL || rw < lim;   // lim is a multiple of 4 here
+        float4 v = *reinterpret_cast<const float4*>(p + (ok ? rw : lim - 4));
+        if (!ok) v = make_float4(0.f, 0.f, 0.f, 0.f);
+        return v;
+    }
+    float x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const bool ok = FULL || rw + e < lim;
+        x[e] = p[ok ? rw + e : lim - 1];
+        if (!ok) x[e] = 0.f;
+    }
+    return make_float4(x[0], x[1], x[2], x[3]);
+}
+
+template <int G, bool VEC, bool FULL>
+__device__ inline void f64_load(const float* const (&yc)[G], int64_t rw, int64_t lim, float4 (&y)[G]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) y[g] = load_rows4<VEC, FULL>(yc[g], rw, lim);
+}
+
+// acc[g][k] += rows rl..rl+3 of column g times the same rows of centroid k (LDS,
+// rows of centroid k at sC[k * R / 4 ...]).
+template <int NC, int G, int R>
+__device__ inline void f64_fma(const float4 (&y)[G], const float4* sC, int rl, double (&acc)[G][NC]) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const float4 cv = sC[k * (R / 4) + (rl >> 2)];
+        const double c0 = cv.x, c1 = cv.y, c2 = cv.z, c3 = cv.w;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double a = acc[g][k];
+            a = fma((double)y[g].x, c0, a);
+            a = fma((double)y[g].y, c1, a);
+            a = fma((double)y[g].z, c2, a);
+            a = fma((double)y[g].w, c3, a);
+            acc[g][k] = a;
+        }
+    }
+}
+
+template <int NC, bool VEC>
+__global__ __launch_bounds__(256) void k_dist_f64(const float* __restrict__ C, int64_t d,
+                                                  const float* __restrict__ Y, int64_t ldy, int64_t n,
+                                                  int slice_rows, double* __restrict__ part,
+                                                  double* __restrict__ cn_part,
+                                                  int* __restrict__ counters) {
+    constexpr int G = f64_cols(NC);
+    constexpr int R = f64_max_rows(NC);   // slice_rows <= R, a multiple of kF64Step
+    __shared__ float4 sC[NC * (R / 4)];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4)
+        counters[threadIdx.x] = 0;   // no refinement list in this mode
+    const int r = threadIdx.x & 15;
+    const int64_t j0 = (int64_t)blockIdx.x * (16 * G) + (int64_t)(threadIdx.x >> 4) * G;
+    const int64_t r0 = (int64_t)blockIdx.y * slice_rows;
+    const int64_t r1 = r0 + slice_rows < d ? r0 + slice_rows : d;
+    const int nfull = (int)((r1 - r0) / kF64Step);              // whole steps
+    const int nsteps = (int)((r1 - r0 + kF64Step - 1) / kF64Step);
+    // the slice's centroid rows, zero from row r1 to the end of its last step
+    const int nq = nsteps * (kF64Step / 4);
+    for (int i = threadIdx.x; i < NC * nq; i += 256) {
+        const int k = i / nq, q = i - k * nq;
+        sC[k * (R / 4) + q] = load_rows4<VEC, false>(C + (int64_t)k * d, r0 + 4 * q, r1);
+    }
+    __syncthreads();
+    const float* yc[G];   // columns past n read column n - 1 and are not written
+#pragma unroll
+    for (int g = 0; g < G; ++g) yc[g] = Y + (j0 + g < n ? j0 + g : n - 1) * ldy;
+    double acc[G][NC];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[g][k] = 0.0;
+    const int rl0 = 4 * r;
+    if (nfull > 0) {
+        // ring of kF64Ahead steps: step t is multiplied while steps t + 1 ..
+        // t + kF64Ahead - 1 are in flight; loads past the last whole step re-read it
+        // (in bounds, from cache) so that no load sits under a branch
+        constexpr int P = kF64Ahead;
+        float4 y[P][G];
+#pragma unroll
+        for (int p = 0; p + 1 < P; ++p)
+            f64_load<G, VEC, true>(yc, r0 + rl0 + (int64_t)(p < nfull ? p : nfull - 1) * kF64Step, r1, y[p]);
+        int t = 0;
+        for (; t + P <= nfull; t += P) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int nx = t + p + P - 1;
+                f64_load<G, VEC, true>(yc, r0 + rl0 + (int64_t)(nx < nfull ? nx : nfull - 1) * kF64Step, r1,
+                                       y[(p + P - 1) % P]);
+                // keep the loads ahead of this step's multiplies (the scheduler would
+                // otherwise sink them below, leaving nothing in flight)
+                __builtin_amdgcn_sched_barrier(0);
+                f64_fma<NC, G, R>(y[p], sC, rl0 + (t + p) * kF64Step, acc);
+            }
+        }
+        // fewer than P steps left, already loaded into y[0 ..]
+#pragma unroll
+        for (int p = 0; p + 1 < P; ++p)
+            if (t + p < nfull) f64_fma<NC, G, R>(y[p], sC, rl0 + (t + p) * kF64Step, acc);
+    }
+    if (nfull < nsteps) {   // ragged last step: rows from r1 on read as zero
+        float4 y[G];
+        f64_load<G, VEC, false>(yc, r0 + rl0 + (int64_t)nfull * kF64Step, r1, y);
+        f64_fma<NC, G, R>(y, sC, rl0 + nfull * kF64Step, acc);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) acc[g][k] += __shfl_xor(acc[g][k], o, 16);
+    // every lane of the group now holds the same sums; lane r writes group r
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double v = acc[g][0];
+#pragma unroll
+        for (int k = 1; k < NC; ++k)
+            if (r == k) v = acc[g][k];
+        if (r < NC && j0 + g < n) part[((int64_t)blockIdx.y * n + j0 + g) * NC + r] = v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 64) {   // this slice's share of ||C_k||^2
+        const int lane = threadIdx.x;
+#pragma unroll 1
+        for (int k = 0; k < NC; ++k) {
+            double a = 0.0;
+            for (int q = lane; q < nq; q += 64) {
+                const float4 v = sC[k * (R / 4) + q];
+                a = fma((double)v.x, (double)v.x, a);
+                a = fma((double)v.y, (double)v.y, a);
+                a = fma((double)v.z, (double)v.z, a);
+                a = fma((double)v.w, (double)v.w, a);
+            }
+            a = wave_sum_d(a);
+            if (lane == 0) cn_part[(int64_t)blockIdx.y * NC + k] = a;
+        }
+    }
+}
+
+// One thread per column: slices summed in order, distance ||C_k||^2 - 2 C_k . Y_j
+// in FP64, smallest first (lowest group on ties); block 0 also stores ||C_k||^2.
+template <int NC>
+__global__ __launch_bounds__(256) void k_argmin_f64(const double* __restrict__ part,
+                                                    const double* __restrict__ cn_part, int nslices,
+                                                    int64_t n, double* __restrict__ cnorm,
+                                                    const int32_t* __restrict__ old_labels,
+                                                    int32_t* __restrict__ new_labels,
+                                                    double* __restrict__ changed_partial) {
+    __shared__ double scn[NC];
+    __shared__ double sh[4];
+    if (threadIdx.x < NC) {
+        double a = 0.0;
+        for (int s = 0; s < nslices; ++s) a += cn_part[(int64_t)s * NC + threadIdx.x];
+        scn[threadIdx.x] = a;
+        if (blockIdx.x == 0) cnorm[threadIdx.x] = a;
+    }
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = j < n;
+    const int64_t jj = live ? j : n - 1;
+    double dot[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) dot[k] = 0.0;
+#pragma unroll 4
+    for (int s = 0; s < nslices; ++s) {
+        const double* p = part + ((int64_t)s * n + jj) * NC;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) dot[k] += p[k];
+    }
+    double bestd = INFINITY;
+    int bestk = 0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const double dist = scn[k] - 2.0 * dot[k];
+        if (dist < bestd) { bestd = dist; bestk = k; }
+    }
+    double changed = 0.0;
+    if (live) {
+        new_labels[j] = bestk;
+        changed = old_labels[j] != bestk ? 1.0 : 0.0;
+    }
+    changed = wave_sum_d(changed);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = changed;
+    __syncthreads();
+    if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
 
 struct DistPlan {
     int kpad, ntiles, nkc, slices, slice_rows;
@@ -579,8 +799,56 @@ DistPlan plan_direct(int64_t d, int64_t n, int c) {
     return p;
 }
 
-// Bounded mode with at most 32 groups runs the FP32 MFMA tile (few MFMAs, no
-// split work); above that the split-bf16 tiles.
+// FP64 tile: 16 G columns per workgroup; row slices of whole 64-row steps, at most
+// f64_max_rows(c) rows, as many as fill the last round of the workgroups the CUs
+// hold at once (per_cu each).
+struct F64Plan {
+    int ncb, slices, slice_rows;
+};
+
+F64Plan plan_f64(int64_t d, int64_t n, int c, int per_cu) {
+    F64Plan p;
+    const int64_t cols = 16 * (int64_t)f64_cols(c);
+    p.ncb = (int)((n + cols - 1) / cols);
+    const int64_t steps = (d + kF64Step - 1) / kF64Step;
+    const int64_t max_steps = f64_max_rows(c) / kF64Step;
+    const int64_t sl_min = (steps + max_steps - 1) / max_steps;
+    const int64_t round = (int64_t)device_cus() * per_cu;
+    const int64_t rounds = (p.ncb * sl_min + round - 1) / round;
+    int64_t sl = std::max<int64_t>(sl_min, rounds * round / p.ncb);
+    sl = std::min<int64_t>(sl, steps);
+    const int64_t rows = (steps + sl - 1) / sl * kF64Step;
+    p.slice_rows = (int)rows;
+    p.slices = (int)((d + rows - 1) / rows);
+    return p;
+}
+
+// Upper bound of plan_f64(d, n, c, per_cu).slices for every per_cu <= 8.
+int64_t f64_max_slices(int64_t d, int64_t n, int c) {
+    const int64_t cols = 16 * (int64_t)f64_cols(c);
+    const int64_t ncb = (n + cols - 1) / cols;
+    const int64_t steps = (d + kF64Step - 1) / kF64Step;
+    const int64_t max_steps = f64_max_rows(c) / kF64Step;
+    const int64_t sl_min = (steps + max_steps - 1) / max_steps;
+    return std::min<int64_t>(steps, sl_min + ((int64_t)device_cus() * 8 + ncb - 1) / ncb);
+}
+
+// Workgroups of one FP64 tile instance a CU holds at once (from its register use;
+// asked once per instance).
+template <int NC, bool VEC>
+int f64_blocks_per_cu() {
+    static const int v = [] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_dist_f64<NC, VEC>, 256, 0) !=
+                hipSuccess || nb < 1)
+            nb = 2;
+        return std::min(nb, 8);
+    }();
+    return v;
+}
+
+// Bounded mode: at most 16 groups the FP64 tile; at most 32 the FP32 MFMA tile
+// with bounds (few MFMAs, no split work); above that the split-bf16 tiles.
 constexpr int kF32BoundedMaxC = 32;
 
 bool use_direct(int64_t d, int c, const float* Y, int64_t ldy, bool bf16) {
@@ -624,11 +892,18 @@ WorkLayout work_layout(void* work, int64_t d, int64_t n, int c, int slices) {
     return w;
 }
 
+// The FP64 tile (c <= 16) puts its double partials [slices][n][c] and the centroid
+// norm partials [slices][c] where the float partials start.
 template <>
 size_t assign_workspace_bytes<float>(int64_t d, int64_t n, int c) {
     const int slices = std::max(plan_f32(d, n, c).slices, plan_direct(d, n, c).slices);
     const WorkLayout w = work_layout(nullptr, d, n, c, slices);
-    return (size_t)(uintptr_t)(w.ynorm + (size_t)slices * n);
+    size_t bytes = (size_t)(uintptr_t)(w.ynorm + (size_t)slices * n);
+    if (c <= kF64MaxC) {
+        const size_t sf = (size_t)f64_max_slices(d, n, c);
+        bytes = std::max(bytes, (size_t)(uintptr_t)w.part + sf * ((size_t)n + 1) * c * sizeof(double));
+    }
+    return bytes;
 }
 
 template <>
@@ -641,6 +916,32 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
                          double* cnorm, const int32_t* old_labels, int32_t* new_labels,
                          void* work, double* changed_partial, bool bf16, int* changed_extra,
                          hipStream_t st) {
+    if (bf16 && c <= kF64MaxC) {
+        const WorkLayout w = work_layout(work, d, n, c, 0);
+        double* dpart = reinterpret_cast<double*>(w.part);
+        const bool vec = (d % 4 == 0) && (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0) &&
+                         (reinterpret_cast<uintptr_t>(C) % 16 == 0);
+        const int ga = (int)((n + 255) / 256);
+        switch (c) {
+#define RESPCA_F64(NC)                                                                                \
+    case NC: {                                                                                        \
+        const auto kern = vec ? k_dist_f64<NC, true> : k_dist_f64<NC, false>;                         \
+        const F64Plan pf =                                                                            \
+            plan_f64(d, n, c, vec ? f64_blocks_per_cu<NC, true>() : f64_blocks_per_cu<NC, false>());  \
+        double* cnp = dpart + (size_t)pf.slices * n * c;                                              \
+        kern<<<dim3(pf.ncb, pf.slices), 256, 0, st>>>(C, d, Y, ldy, n, pf.slice_rows, dpart, cnp,     \
+                                                      w.counters);                                    \
+        k_argmin_f64<NC><<<ga, 256, 0, st>>>(dpart, cnp, pf.slices, n, cnorm, old_labels, new_labels, \
+                                             changed_partial);                                        \
+        break;                                                                                        \
+    }
+            RESPCA_F64(1) RESPCA_F64(2) RESPCA_F64(3) RESPCA_F64(4) RESPCA_F64(5) RESPCA_F64(6)
+            RESPCA_F64(7) RESPCA_F64(8) RESPCA_F64(9) RESPCA_F64(10) RESPCA_F64(11) RESPCA_F64(12)
+            RESPCA_F64(13) RESPCA_F64(14) RESPCA_F64(15) RESPCA_F64(16)
+#undef RESPCA_F64
+        }
+        return ga;
+    }
     const bool direct = use_direct(d, c, Y, ldy, bf16);
     const DistPlan p = direct ? plan_direct(d, n, c) : plan_f32(d, n, c);
     const WorkLayout w = work_layout(work, d, n, c, p.slices);

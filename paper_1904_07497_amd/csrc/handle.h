@@ -36,7 +36,8 @@ struct respca_handle_s {
     int device = 0;
     std::string err;
     // kernel timing
-    bool prof_on = false;
+    bool prof_on = false;     // some unit is timed
+    uint32_t prof_mask = 0;   // bit k: launches of kernel id k are timed
     int64_t prof_launches[RESPCA_KERNEL_COUNT] = {};
     double prof_ms[RESPCA_KERNEL_COUNT] = {};
     double prof_bytes[RESPCA_KERNEL_COUNT] = {};

@@ -104,9 +104,11 @@ int launch_argmin(const T* part, int nrb, int c, int64_t n, const double* cnorm,
 // count partials.  `work` must hold assign_workspace_bytes<T>(d, n, c).
 template <typename T>
 size_t assign_workspace_bytes(int64_t d, int64_t n, int c);
-// bf16 (float runs only): split-bf16 MFMA contraction with bounded error and
-// exact refinement of near-tied columns; their changes are counted in the int at
-// assign_refine_counters(work)[1] (*changed_extra is set to 1 when that applies).
+// bf16 (float runs only): labels of the FP64 distances of the FP32 values.  Above
+// 16 groups a bounded-error MFMA contraction (split-bf16, or FP32 up to 32 groups)
+// with exact refinement of near-tied columns, whose changes are counted in the int
+// at assign_refine_counters(work)[1] (*changed_extra is set to 1 when that
+// applies); at most 16 groups an FP64 contraction with nothing to refine.
 // cnorm (||C_k||^2 in double) is an input, except in bf16 mode, where the pass
 // computes it while splitting the centroids.
 template <typename T>

@@ -30,13 +30,13 @@ struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
     ProfScope(respca_handle h_, hipStream_t st_, int k, double by, double fl = 0.0)
         : h(h_), st(st_), kernel(k), bytes(by), flops(fl) {
-        if (!h->prof_on) return;
+        if (!((h->prof_mask >> kernel) & 1u)) return;
         a = take();
         b = take();
         if (a && b) (void)hipEventRecord(a, st);
     }
     ~ProfScope() {
-        if (!h->prof_on || !a || !b) return;
+        if (!a || !b) return;
         (void)hipEventRecord(b, st);
         h->prof_pending.push_back({kernel, a, b, bytes, flops});
     }
@@ -676,6 +676,7 @@ respca_status respca_profile_enable(respca_handle h, int32_t enable) {
         (void)hipDeviceSynchronize();
         prof_resolve(h);
     }
+    h->prof_mask = (uint32_t)enable;
     h->prof_on = enable != 0;
     for (int k = 0; k < RESPCA_KERNEL_COUNT; ++k) {
         h->prof_launches[k] = 0;

@@ -325,10 +325,12 @@ def kmeans(Y, rank, seed=0, max_lloyd=100, precision=None, stream=None):
     return labels, C, info.as_dict()
 
 
-def profile_enable(on: bool = True, device: int = 0):
-    """Turn the library's per-kernel event timing on/off (resets the counters)."""
+def profile_enable(on: bool = True, units=None, device: int = 0):
+    """Turn the library's per-kernel event timing on/off (resets the counters).
+    units: names from KERNELS to time (default: all of them)."""
     h = handle(device)
-    h.check(lib().respca_profile_enable(h._h, 1 if on else 0), allow=(OK,))
+    mask = 0 if not on else (-1 if units is None else sum(1 << KERNELS[u] for u in set(units)))
+    h.check(lib().respca_profile_enable(h._h, mask), allow=(OK,))
 
 
 def profile_query(device: int = 0) -> dict:

@@ -347,6 +347,10 @@ def test_bf16_kmeans_matches_oracle():
     (512, 1300, 70, 0),     # direct tile, five group blocks
     (1020, 600, 20, 8),     # at most 32 groups: FP32 MFMA tile with bounds, padded ld
     (2048, 300, 130, 4),    # two group tiles (c > 128), padded ld
+    (1000, 777, 5, 0),      # at most 16 groups: FP64 tile, 6 columns per lane group
+    (1022, 513, 16, 6),     # FP64 tile, scalar loads (d % 4 != 0), padded ld
+    (260, 1500, 9, 4),      # FP64 tile, 16-byte loads with ld > d
+    (3000, 100, 1, 0),      # one group
 ])
 def test_bf16_kmeans_tile_variants_match_oracle(d, n, c, pad):
     """Every bounded-distance tile variant (chosen by c and the column layout) gives
@@ -361,6 +365,32 @@ def test_bf16_kmeans_tile_variants_match_oracle(d, n, c, pad):
     ol, oC, osteps = oracle.kmeans(X, c, 7)
     np.testing.assert_array_equal(lab.cpu().numpy(), ol)
     assert info["init_lloyd"] == osteps
+
+
+@pytest.mark.parametrize("d,n,c", [(1500, 1234, 5), (1023, 777, 16), (4096, 300, 1), (644, 2100, 9)])
+def test_bounded_small_c_iterations_unstructured(d, n, c):
+    """At most 16 groups the bounded mode sums its dot products in FP64: on data with
+    no group structure, three iterations with up to 100 Lloyd passes each give the
+    oracle's labels and Lloyd counts, and L, S to the FP32 bar."""
+    rng = np.random.default_rng(d + c)
+    X = np.asfortranarray(rng.standard_normal((d, n)).astype(np.float32))
+    st = synth.random_state(X, c, seed=c, s_frac=0.1, s_amp=1.0)
+    st["rho"] = 0.05
+    lam = 0.5
+    gs = _gpu_state(st, np.float32)
+    ost = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) and v.dtype != np.int32 else v)
+           for k, v in st.items()}
+    p = oracle.make_params(c, lam=lam, max_lloyd=100)
+    Xo = X.astype(np.float64)
+    nX = np.linalg.norm(Xo)
+    say(f"bounded small c d={d} n={n} c={c}")
+    for t in range(3):
+        _, info = rp.iterate(dev(X), gs, iters=1, lam=lam, max_lloyd=100, precision=rp.BF16GEMM_F32)
+        ost = oracle.step(p, Xo, ost)
+        np.testing.assert_array_equal(gs["labels"].cpu().numpy(), ost["labels"])
+        assert info["lloyd_steps"] == ost["lloyd"]
+        for k in ("L", "S"):
+            assert rel(host(gs[k]), ost[k], nX) <= F32_TOL, (t, k)
 
 
 @pytest.mark.parametrize("precision", [rp.F32, rp.BF16GEMM_F32])
