@@ -452,8 +452,11 @@ __device__ inline void dist_tile(const float* __restrict__ C, int64_t d, int c, 
 // time; blocks past the tile's groups compute on clamped copies and are not
 // written): all centroid operands of a stage are read from LDS first, then the
 // MFMAs run product by product over every (block, column half), so that 2 NKB
-// independent accumulators separate two updates of the same one.
-template <int NKB, int WAVES>
+// independent accumulators separate two updates of the same one.  AHEAD: stages
+// of column values in flight beyond the one being multiplied (1 or 2; with 2 a
+// step issues the next stage's centroid loads before the values two stages
+// ahead, so that the centroid wait at its end leaves those in flight).
+template <int NKB, int WAVES, int AHEAD>
 __device__ inline void dist_tile_ydirect(int64_t d, int kpad, const float* __restrict__ Y,
                                          int64_t ldy, int64_t n, int slice_rows,
                                          float* __restrict__ part,
@@ -485,21 +488,25 @@ __device__ inline void dist_tile_ydirect(int64_t d, int kpad, const float* __res
         if (col >= n) col = n - 1;
         yp[jb] = Y + col * ldy + 4 * g;
     }
-    float4 yv[2][2];   // [jb][half] of the next stage
+    static_assert(AHEAD == 1 || AHEAD == 2, "stages in flight");
+    float4 ya[2][2], yb[2][2];   // [jb][half]: column values of stage r and (AHEAD 2) r + kRT
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) yb[jb][h] = make_float4(0.f, 0.f, 0.f, 0.f);
     SplitStage<64 * WAVES, 16 * NKB> rs;   // only the groups the MFMAs read
     rs.init(Csp, ldq, k0, kpad);
     // a stage inside the rows: unconditional loads
-    auto load_full = [&](int64_t r) {
+    auto load_y_full = [&](int64_t r, float4 (&yv)[2][2]) {
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
             for (int h = 0; h < 2; ++h) yv[jb][h] = *reinterpret_cast<const float4*>(yp[jb] + r + 16 * h);
-        rs.load_rows(r);
     };
     // any stage: rows past r1 read row 0 of the column and are zeroed
-    auto load_any = [&](int64_t r) {
+    auto load_y_any = [&](int64_t r, float4 (&yv)[2][2]) {
         if (r + kRT <= r1) {
-            load_full(r);
+            load_y_full(r, yv);
             return;
         }
 #pragma unroll
@@ -510,14 +517,13 @@ __device__ inline void dist_tile_ydirect(int64_t d, int kpad, const float* __res
                 const float4 t = *reinterpret_cast<const float4*>(in ? yp[jb] + r + 16 * h : yp[jb] - 4 * g);
                 yv[jb][h] = in ? t : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-        rs.load_rows(r);
     };
     auto store_c = [&](int b) {
         __bf16* Ch = reinterpret_cast<__bf16*>(smem + b * kCBuf);
         rs.template store<true>(Ch, Ch + kKC * kStrideH);
     };
     // the loaded column values as A operands (and their squares)
-    auto split = [&](bf16x8 (&ahi)[2], bf16x8 (&alo)[2]) {
+    auto split = [&](const float4 (&yv)[2][2], bf16x8 (&ahi)[2], bf16x8 (&alo)[2]) {
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb) {
             const float x[8] = {yv[jb][0].x, yv[jb][0].y, yv[jb][0].z, yv[jb][0].w,
@@ -557,30 +563,109 @@ __device__ inline void dist_tile_ydirect(int64_t d, int kpad, const float* __res
             for (int jb = 0; jb < 2; ++jb)
                 acc[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[jb], bhi[kb], acc[jb][kb], 0, 0, 0);
     };
-    // At the top of each pass LDS buffer b holds the centroids of stage r and the
-    // registers its column values; the next stage's loads run during the MFMAs.
-    if (r0 < r1) {
-        load_any(r0);
-        store_c(0);
-        __syncthreads();
-    }
+    auto copy_y = [&](float4 (&dst)[2][2], const float4 (&src)[2][2]) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) dst[jb][h] = src[jb][h];
+    };
     bf16x8 ahi[2], alo[2];
     int b = 0;
     int64_t r = r0;
-    for (; r + 2 * kRT <= r1; r += kRT, b ^= 1) {   // the next stage lies inside the rows
-        split(ahi, alo);
-        load_full(r + kRT);
-        mfma_stage(b, ahi, alo);
-        store_c(b ^ 1);
-        __syncthreads();
-    }
-    for (; r < r1; r += kRT, b ^= 1) {              // the last stage (or the next one partial)
-        split(ahi, alo);
-        const bool more = r + kRT < r1;
-        if (more) load_any(r + kRT);
-        mfma_stage(b, ahi, alo);
-        if (more) store_c(b ^ 1);
-        __syncthreads();
+    if constexpr (AHEAD == 1) {
+        // At the top of each pass LDS buffer b holds the centroids of stage r and
+        // ya its column values; the next stage's loads run during the MFMAs.
+        if (r0 < r1) {
+            load_y_any(r0, ya);
+            rs.load_rows(r0);
+            store_c(0);
+            __syncthreads();
+        }
+        for (; r + 2 * kRT <= r1; r += kRT, b ^= 1) {   // the next stage lies inside the rows
+            split(ya, ahi, alo);
+            load_y_full(r + kRT, ya);
+            rs.load_rows(r + kRT);
+            mfma_stage(b, ahi, alo);
+            store_c(b ^ 1);
+            __syncthreads();
+        }
+        for (; r < r1; r += kRT, b ^= 1) {              // the last stage (or the next one partial)
+            split(ya, ahi, alo);
+            const bool more = r + kRT < r1;
+            if (more) {
+                load_y_any(r + kRT, ya);
+                rs.load_rows(r + kRT);
+            }
+            mfma_stage(b, ahi, alo);
+            if (more) store_c(b ^ 1);
+            __syncthreads();
+        }
+    } else {
+        // Loads complete in issue order, so a step issues the centroids and the
+        // column values of stage r + 2 kRT together: waiting for the centroids of
+        // stage r + kRT (loaded a step earlier) then leaves both later stages in
+        // flight.  At the top of each pass LDS buffer b holds the centroids of stage
+        // r, ya (or yb) the column values of stage r and the other set those of
+        // stage r + kRT, and rsb (or rsa) the centroids of stage r + kRT.
+        SplitStage<64 * WAVES, 16 * NKB> rsb = rs;
+        if (r0 < r1) {
+            rs.load_rows(r0);
+            load_y_any(r0, ya);
+            if (r0 + kRT < r1) {
+                rsb.load_rows(r0 + kRT);
+                load_y_any(r0 + kRT, yb);
+            }
+            store_c(0);
+            __syncthreads();
+        }
+        auto store_from = [&](const SplitStage<64 * WAVES, 16 * NKB>& src, int bb) {
+            __bf16* Ch = reinterpret_cast<__bf16*>(smem + bb * kCBuf);
+            src.template store<true>(Ch, Ch + kKC * kStrideH);
+        };
+        // stages up to r + 2 kRT inside the rows
+        auto step = [&](float4 (&cur)[2][2], SplitStage<64 * WAVES, 16 * NKB>& ld,
+                        const SplitStage<64 * WAVES, 16 * NKB>& st) {
+            // (the barriers keep each stage's work in its own step: hoisting the next
+            // stage's split here would wait on values still in flight)
+            __builtin_amdgcn_sched_barrier(0);
+            split(cur, ahi, alo);
+            __builtin_amdgcn_sched_barrier(0);
+            ld.load_rows(r + 2 * kRT);
+            load_y_full(r + 2 * kRT, cur);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_stage(b, ahi, alo);
+            store_from(st, b ^ 1);
+            __syncthreads();
+            r += kRT;
+            b ^= 1;
+        };
+        for (; r + 4 * kRT <= r1;) {   // two steps per pass: the sets trade roles in place
+            step(ya, rs, rsb);
+            step(yb, rsb, rs);
+        }
+        if (r + 3 * kRT <= r1) {   // one more whole step leaves stage r in yb: swap the sets
+            step(ya, rs, rsb);
+            float4 t[2][2];
+            copy_y(t, ya);
+            copy_y(ya, yb);
+            copy_y(yb, t);
+            const SplitStage<64 * WAVES, 16 * NKB> u = rs;
+            rs = rsb;
+            rsb = u;
+        }
+        for (; r < r1; r += kRT, b ^= 1) {   // at most three stages left
+            split(ya, ahi, alo);
+            const bool more = r + kRT < r1;
+            copy_y(ya, yb);
+            if (r + 2 * kRT < r1) {
+                rs.load_rows(r + 2 * kRT);
+                load_y_any(r + 2 * kRT, yb);
+            }
+            mfma_stage(b, ahi, alo);
+            if (more) store_from(rsb, b ^ 1);
+            __syncthreads();
+            rsb = rs;
+        }
     }
     if (write_ynorm) {
 #pragma unroll

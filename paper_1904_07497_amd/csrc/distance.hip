@@ -61,9 +61,11 @@ __global__ __launch_bounds__(64 * kDirectWaves) __attribute__((amdgpu_waves_per_
     const uint4* __restrict__ Csp, int64_t ldq) {
     if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < 4)
         counters[threadIdx.x] = 0;   // refinement list length, its changed count: fresh for this pass
-    dist_tile_ydirect<NKB, kDirectWaves>(d, kpad, Y, ldy, n, slice_rows, part, ynorm_part,
-                                         (int64_t)blockIdx.x * kJD, blockIdx.y, blockIdx.z * kKC,
-                                         blockIdx.z == 0, Csp, ldq);
+    // one workgroup per CU: two stages of column values in flight per wave (eight
+    // group blocks leave no registers for the second)
+    dist_tile_ydirect<NKB, kDirectWaves, direct_wgs_per_cu(NKB) == 1 && NKB < 8 ? 2 : 1>(
+        d, kpad, Y, ldy, n, slice_rows, part, ynorm_part, (int64_t)blockIdx.x * kJD, blockIdx.y,
+        blockIdx.z * kKC, blockIdx.z == 0, Csp, ldq);
 }
 
 // Bounded mode at small c: the FP32 MFMA tile with the columns' norms, decided by

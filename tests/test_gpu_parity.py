@@ -345,6 +345,8 @@ def test_bf16_kmeans_matches_oracle():
 @pytest.mark.parametrize("d,n,c,pad", [
     (1024, 900, 40, 0),     # direct tile, three group blocks (two workgroups per CU)
     (512, 1300, 70, 0),     # direct tile, five group blocks
+    (1028, 700, 70, 0),     # direct tile, two stages in flight, ragged last stage
+    (2340, 400, 100, 4),    # direct tile, seven group blocks, ragged last stage, padded ld
     (1020, 600, 20, 8),     # at most 32 groups: FP32 MFMA tile with bounds, padded ld
     (2048, 300, 130, 4),    # two group tiles (c > 128), padded ld
     (1000, 777, 5, 0),      # at most 16 groups: FP64 tile, 6 columns per lane group
