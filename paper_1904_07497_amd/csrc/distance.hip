@@ -541,7 +541,9 @@ __global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ C
 // to part[slice][column][group].  The workgroups of column block 0 also leave the
 // slice's share of ||C_k||^2.
 constexpr int kF64MaxC = 16;
-constexpr int kF64Step = 64;   // rows per step of a lane group
+constexpr int kF64Lanes = 16;                 // lanes per column group
+constexpr int kF64Groups = 256 / kF64Lanes;     // column groups per workgroup
+constexpr int kF64Step = 4 * kF64Lanes;         // rows per step of a lane group
 
 // Columns per lane group: at most 6, and G x NC sums of at most 24 doubles.
 constexpr int f64_cols(int nc) { return 24 / nc < 1 ? 1 : (24 / nc > 6 ? 6 : 24 / nc); }
@@ -607,8 +609,8 @@ __global__ __launch_bounds__(256) void k_dist_f64(const float* __restrict__ C, i
     __shared__ float4 sC[NC * (R / 4)];
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4)
         counters[threadIdx.x] = 0;   // no refinement list in this mode
-    const int r = threadIdx.x & 15;
-    const int64_t j0 = (int64_t)blockIdx.x * (16 * G) + (int64_t)(threadIdx.x >> 4) * G;
+    const int r = threadIdx.x & (kF64Lanes - 1);
+    const int64_t j0 = (int64_t)blockIdx.x * (kF64Groups * G) + (int64_t)(threadIdx.x / kF64Lanes) * G;
     const int64_t r0 = (int64_t)blockIdx.y * slice_rows;
     const int64_t r1 = r0 + slice_rows < d ? r0 + slice_rows : d;
     const int nfull = (int)((r1 - r0) / kF64Step);              // whole steps
@@ -666,7 +668,7 @@ __global__ __launch_bounds__(256) void k_dist_f64(const float* __restrict__ C, i
 #pragma unroll
         for (int k = 0; k < NC; ++k)
 #pragma unroll
-            for (int o = 8; o > 0; o >>= 1) acc[g][k] += __shfl_xor(acc[g][k], o, 16);
+            for (int o = kF64Lanes / 2; o > 0; o >>= 1) acc[g][k] += __shfl_xor(acc[g][k], o, kF64Lanes);
     // every lane of the group now holds the same sums; lane r writes group r
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -810,7 +812,7 @@ struct F64Plan {
 
 F64Plan plan_f64(int64_t d, int64_t n, int c, int per_cu) {
     F64Plan p;
-    const int64_t cols = 16 * (int64_t)f64_cols(c);
+    const int64_t cols = kF64Groups * (int64_t)f64_cols(c);
     p.ncb = (int)((n + cols - 1) / cols);
     const int64_t steps = (d + kF64Step - 1) / kF64Step;
     const int64_t max_steps = f64_max_rows(c) / kF64Step;
@@ -827,7 +829,7 @@ F64Plan plan_f64(int64_t d, int64_t n, int c, int per_cu) {
 
 // Upper bound of plan_f64(d, n, c, per_cu).slices for every per_cu <= 8.
 int64_t f64_max_slices(int64_t d, int64_t n, int c) {
-    const int64_t cols = 16 * (int64_t)f64_cols(c);
+    const int64_t cols = kF64Groups * (int64_t)f64_cols(c);
     const int64_t ncb = (n + cols - 1) / cols;
     const int64_t steps = (d + kF64Step - 1) / kF64Step;
     const int64_t max_steps = f64_max_rows(c) / kF64Step;
