@@ -593,7 +593,33 @@ __global__ __launch_bounds__(kBlock) void k_d2_bounded(const float* __restrict__
     const float sc = zsc[j];
     typedef _Float16 half8 __attribute__((ext_vector_type(8)));
     float acc = 0.f;
-    for (int64_t i = (int64_t)lane * 8; i < d; i += 512) {   // ldz % 8 == 0: 16-byte loads
+    int64_t i = (int64_t)lane * 8;
+    if constexpr (V == 4) {
+        // whole 512-row passes, four at a time: their loads are issued before any of
+        // their arithmetic (the same additions in the same order as below)
+        constexpr int U = 4;
+        const int64_t nfull = d / 512;
+        for (int64_t t = 0; t + U <= nfull; t += U, i += 512 * U) {
+            half8 z[U];
+            float4 a[U], b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                z[u] = *reinterpret_cast<const half8*>(zj + i + 512 * u);
+                a[u] = *reinterpret_cast<const float4*>(ys + i + 512 * u);
+                b[u] = *reinterpret_cast<const float4*>(ys + i + 512 * u + 4);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float y[8] = {a[u].x, a[u].y, a[u].z, a[u].w, b[u].x, b[u].y, b[u].z, b[u].w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float t2 = fmaf((float)z[u][e], sc, -y[e]);
+                    acc = fmaf(t2, t2, acc);
+                }
+            }
+        }
+    }
+    for (; i < d; i += 512) {   // ldz % 8 == 0: 16-byte loads
         const half8 z = *reinterpret_cast<const half8*>(zj + i);
         float y[8];
         if (i + 8 <= d) {
