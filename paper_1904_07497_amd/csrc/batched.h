@@ -10,6 +10,7 @@ namespace respca {
 constexpr int kMaxBatch = 1024;   // instances per batched call (LDS-cached work tables)
 constexpr int kBatchRows = 256;   // rows per tile (one wave covers them, 4 per lane)
 constexpr int kBatchSegCols = 64; // max columns of one group segment (means and sweep items)
+constexpr int kArgminCols = 64;   // columns per argmin item (16 lanes each, 4 per lane group)
 
 // One instance.  The static part is written by the host; the state part is
 // owned by the kernel (initialised in its first phases, read back by the host).
@@ -44,7 +45,7 @@ struct BatchInst {
     double* cnorm;
     double* gsum;              // [group][rows]: group sums (double) of the last Lloyd-family means
     double* sweep_part;        // 3 per sweep item (segment x row block), 1 per pack tile
-    int32_t* chg;              // 1 per wave of each 16-column argmin item
+    int32_t* chg;              // 1 per wave of each argmin item
     // shape and tiling.  The initial K-means runs on the columns of X (kdp = dp) or of
     // the embedding (kdp = 4 * ceil(er / 4)); mrows = max(dp, kdp) and mrb row blocks
     // of kBatchRows cover both.
@@ -94,7 +95,7 @@ struct BatchArgs {
     const int32_t* off_kc;     // c                  (seed columns, centroids and their norms)
     const int32_t* off_seg;    // (ceil(n/64) + c) * mrb (group partial sums, sweep)
     const int32_t* off_dist;   // ceil(n/128) * slices * nkc (distance tiles)
-    const int32_t* off_col;    // ceil(n/16)         (argmin)
+    const int32_t* off_col;    // ceil(n/kArgminCols) (argmin)
 };
 
 void launch_batched_reset(BatchSync* s, int batch, hipStream_t st);

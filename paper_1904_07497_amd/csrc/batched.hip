@@ -649,47 +649,101 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 const int l0 = B.segf[B.c + k], l1 = B.segf[B.c + k + 1];
                 if (e0 == e1 && l0 == l1) return;   // no column entered or left: C and its norm stay
                 const int nk = B.counts[k];
-                for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
-                    float v = Ck[r];
-                    if (nk == 0) {
-                        Gk[r] = 0.0;   // emptied: the centroid stays, its sum is exactly zero
-                    } else {
-                        double add = 0.0, sub = 0.0;
-                        for (int g = e0; g < e1; ++g) add += B.pmeans[(int64_t)g * rows + r];
-                        for (int g = l0; g < l1; ++g) sub += B.pmeans[(int64_t)g * rows + r];
-                        const double sum = Gk[r] + (add - sub);
-                        Gk[r] = sum;
-                        v = (float)(sum / (double)nk);
-                        Ck[r] = v;
+                // four rows per thread at a time (loads clamped into the rows); each
+                // row's partials added in segment order, the squares in row order
+                constexpr int RU = 4;
+                for (int64_t r0 = threadIdx.x; r0 < rows; r0 += RU * kBlock) {
+                    float cv[RU];
+                    double gk[RU], add[RU], sub[RU];
+#pragma unroll
+                    for (int q = 0; q < RU; ++q) {
+                        const int64_t r = r0 + q * kBlock < rows ? r0 + q * kBlock : rows - 1;
+                        cv[q] = Ck[r];
+                        gk[q] = Gk[r];
+                        add[q] = 0.0;
+                        sub[q] = 0.0;
                     }
-                    a += (double)v * (double)v;
+                    if (nk != 0) {
+                        for (int g = e0; g < e1; ++g) {
+                            double t[RU];
+#pragma unroll
+                            for (int q = 0; q < RU; ++q)
+                                t[q] = B.pmeans[(int64_t)g * rows +
+                                                (r0 + q * kBlock < rows ? r0 + q * kBlock : rows - 1)];
+#pragma unroll
+                            for (int q = 0; q < RU; ++q) add[q] += t[q];
+                        }
+                        for (int g = l0; g < l1; ++g) {
+                            double t[RU];
+#pragma unroll
+                            for (int q = 0; q < RU; ++q)
+                                t[q] = B.pmeans[(int64_t)g * rows +
+                                                (r0 + q * kBlock < rows ? r0 + q * kBlock : rows - 1)];
+#pragma unroll
+                            for (int q = 0; q < RU; ++q) sub[q] += t[q];
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < RU; ++q) {
+                        const int64_t r = r0 + q * kBlock;
+                        if (r >= rows) break;
+                        float v = cv[q];
+                        if (nk == 0) {
+                            Gk[r] = 0.0;   // emptied: the centroid stays, its sum is exactly zero
+                        } else {
+                            const double sum = gk[q] + (add[q] - sub[q]);
+                            Gk[r] = sum;
+                            v = (float)(sum / (double)nk);
+                            Ck[r] = v;
+                        }
+                        a += (double)v * (double)v;
+                    }
                 }
             } else if (needs_groups(mode)) {
                 const int nk = B.counts[k];
                 const int g0 = B.segf[k], g1 = B.segf[k + 1];
                 const bool keep = lloyd_family(mode);   // sums carried to the next Lloyd step
-                for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
-                    float v;
-                    if (nk == 0) {
-                        v = mode == M_MEANSX ? 0.f : Ck[r];
+                if (nk == 0) {
+                    for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
+                        const float v = mode == M_MEANSX ? 0.f : Ck[r];
                         if (mode == M_MEANSX) Ck[r] = 0.f;
                         if (keep) Gk[r] = 0.0;
-                    } else {
-                        double sum = 0.0;
-                        for (int g = g0; g < g1; g += 4) {   // four loads in flight, added in order
-                            double v[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u)      // clamped: no branch per load
-                                v[u] = B.pmeans[(int64_t)(g + u < g1 ? g + u : g1 - 1) * rows + r];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u)
-                                if (g + u < g1) sum += v[u];
-                        }
-                        if (keep) Gk[r] = sum;
-                        v = (float)(sum / (double)nk);
-                        Ck[r] = v;
+                        a += (double)v * (double)v;
                     }
-                    a += (double)v * (double)v;
+                } else {
+                    // four rows per thread at a time, each with four segments' loads in
+                    // flight (clamped: no branch per load); every row's segments are
+                    // added in order and the rows' squares in row order
+                    constexpr int RU = 4;
+                    for (int64_t r0 = threadIdx.x; r0 < rows; r0 += RU * kBlock) {
+                        double sum[RU];
+#pragma unroll
+                        for (int q = 0; q < RU; ++q) sum[q] = 0.0;
+                        for (int g = g0; g < g1; g += 4) {
+                            double v[RU][4];
+#pragma unroll
+                            for (int q = 0; q < RU; ++q) {
+                                const int64_t r = r0 + q * kBlock < rows ? r0 + q * kBlock : rows - 1;
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    v[q][u] = B.pmeans[(int64_t)(g + u < g1 ? g + u : g1 - 1) * rows + r];
+                            }
+#pragma unroll
+                            for (int q = 0; q < RU; ++q)
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    if (g + u < g1) sum[q] += v[q][u];
+                        }
+#pragma unroll
+                        for (int q = 0; q < RU; ++q) {
+                            const int64_t r = r0 + q * kBlock;
+                            if (r >= rows) break;
+                            if (keep) Gk[r] = sum[q];
+                            const float v = (float)(sum[q] / (double)nk);
+                            Ck[r] = v;
+                            a += (double)v * (double)v;
+                        }
+                    }
                 }
             } else {
                 for (int64_t r = threadIdx.x; r < rows; r += kBlock) {
@@ -746,19 +800,54 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                                    false);
         });
         if (!grid_sync(gs, nb, tmo, BP_DIST, tclk)) return;
-        // G: reduce slices, argmin (16 lanes per column), changed counts
+        // G: reduce slices, argmin (16 lanes per column; lane group g of an item takes
+        //    its columns g, g + 16, ...), changed counts
         load_tab(A.off_col);
         for_items(batch, s_tab, s_mode, assigns, [&](int i, int local) {
             BatchInst& B = inst[i];
             const int q = threadIdx.x & 15;
-            const int64_t j = (int64_t)local * 16 + (threadIdx.x >> 4);
-            double bestd = INFINITY;
-            int bestk = INT_MAX;
-            // 64 groups per chunk: each lane's four slice sums come from batched loads
+            constexpr int NJ = kArgminCols / 16;
+            int64_t j[NJ], jc[NJ];   // jc: clamped into the matrix (results past n dropped)
+#pragma unroll
+            for (int c2 = 0; c2 < NJ; ++c2) {
+                j[c2] = (int64_t)local * (16 * NJ) + 16 * c2 + (threadIdx.x >> 4);
+                jc[c2] = j[c2] < B.n ? j[c2] : B.n - 1;
+            }
+            double bestd[NJ];
+            int bestk[NJ];
+#pragma unroll
+            for (int c2 = 0; c2 < NJ; ++c2) { bestd[c2] = INFINITY; bestk[c2] = INT_MAX; }
+            const int ns = B.slices;
+            // 64 groups per chunk; every column's loads of four slices are issued
+            // before their additions (each column's slices added in slice order)
             for (int k0 = 0; k0 < B.c; k0 += 64) {
-                double dot[4], yn;
-                sum_slices<4, false>(B.part, nullptr, j < B.n ? B.slices : 0, B.n, j, B.c, B.kpad,
-                                     k0 + q, dot, yn);
+                double dot[NJ][4];
+#pragma unroll
+                for (int c2 = 0; c2 < NJ; ++c2)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) dot[c2][t] = 0.0;
+                for (int s0 = 0; s0 < ns; s0 += 4) {
+                    float v[NJ][4][4];
+#pragma unroll
+                    for (int c2 = 0; c2 < NJ; ++c2)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int su = s0 + u < ns ? s0 + u : ns - 1;
+                            const float* pp = B.part + ((int64_t)su * B.n + jc[c2]) * B.kpad;
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                const int k = k0 + q + 16 * t;
+                                v[c2][u][t] = pp[k < B.kpad ? k : B.kpad - 1];
+                            }
+                        }
+#pragma unroll
+                    for (int c2 = 0; c2 < NJ; ++c2)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int t = 0; t < 4; ++t)
+                                dot[c2][t] += (s0 + u < ns && k0 + q + 16 * t < B.c) ? (double)v[c2][u][t] : 0.0;
+                }
                 double cn[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -766,28 +855,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                     cn[t] = B.cnorm[k < B.c ? k : B.c - 1];
                 }
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int k = k0 + q + 16 * t;
-                    if (j < B.n && k < B.c) {
-                        const double dist = cn[t] - 2.0 * dot[t];
-                        if (dist < bestd) { bestd = dist; bestk = k; }
-                    }
-                }
-            }
+                for (int c2 = 0; c2 < NJ; ++c2)
 #pragma unroll
-            for (int o = 8; o > 0; o >>= 1) {
-                const double od = __shfl_xor(bestd, o, 16);
-                const int ok = __shfl_xor(bestk, o, 16);
-                if (od < bestd || (od == bestd && ok < bestk)) { bestd = od; bestk = ok; }
+                    for (int t = 0; t < 4; ++t) {
+                        const int k = k0 + q + 16 * t;
+                        if (k < B.c) {
+                            const double dist = cn[t] - 2.0 * dot[c2][t];
+                            if (dist < bestd[c2]) { bestd[c2] = dist; bestk[c2] = k; }
+                        }
+                    }
             }
-            bool moved = false;
-            if (j < B.n && q == 0) {
-                const int lab = bestk == INT_MAX ? 0 : bestk;
-                B.lab[B.cur ^ 1][j] = lab;
-                moved = B.lab[B.cur][j] != lab;
+            int wch = 0;
+#pragma unroll
+            for (int c2 = 0; c2 < NJ; ++c2) {
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) {
+                    const double od = __shfl_xor(bestd[c2], o, 16);
+                    const int ok = __shfl_xor(bestk[c2], o, 16);
+                    if (od < bestd[c2] || (od == bestd[c2] && ok < bestk[c2])) { bestd[c2] = od; bestk[c2] = ok; }
+                }
+                bool moved = false;
+                if (j[c2] < B.n && q == 0) {
+                    const int lab = bestk[c2] == INT_MAX ? 0 : bestk[c2];
+                    B.lab[B.cur ^ 1][j[c2]] = lab;
+                    moved = B.lab[B.cur][j[c2]] != lab;
+                }
+                wch += __popcll(__ballot(moved));
             }
             // changed count per wave (no workgroup barrier): chg[4 item + wave]
-            const int wch = __popcll(__ballot(moved));
             if ((threadIdx.x & 63) == 0) B.chg[4 * local + (threadIdx.x >> 6)] = wch;
         });
         if (!grid_sync(gs, nb, tmo, BP_ARGMIN, tclk)) return;

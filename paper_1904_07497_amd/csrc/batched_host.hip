@@ -130,7 +130,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.slices = (B.mrows + rows - 1) / rows;
         const int ntiles = (B.n + 127) / 128;
         B.n_tile = ((B.n + B.jc - 1) / B.jc) * B.nrb;
-        B.n_argmin = (B.n + 15) / 16;
+        B.n_argmin = (B.n + kArgminCols - 1) / kArgminCols;
         const int nseg_max = (B.n + kBatchSegCols - 1) / kBatchSegCols + B.c;
         B.n_sweep = nseg_max * B.mrb;
         B.lambda = r.lambda;
