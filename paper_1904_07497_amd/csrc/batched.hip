@@ -556,14 +556,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             const float* Y = B.Z ? B.Z : B.X;
             const int rows = B.kdp;
             const float* ys = Y + (int64_t)B.seeds[m] * rows;
-            // 16 columns per item, four per wave in turn
-            for (int t = 0; t < 4; ++t) {
-                const int64_t j = (int64_t)local * 16 + (threadIdx.x >> 6) * 4 + t;
-                if (j >= B.n) break;
-                // rows is a multiple of 4 (zero padded): four row groups of float4 in flight
-                const double acc = d2_column<float, 4>(Y + j * rows, ys, rows, lane);
-                if (lane == 0) B.d2[j] = (m == 0) ? acc : fmin(B.d2[j], acc);
+            // 16 columns per item, four per wave together: each 512-row pass loads
+            // the seed rows once and the four columns' rows beside them (rows is a
+            // multiple of 4, zero padded; columns past n read column n - 1)
+            constexpr int NC4 = 4;
+            int64_t j[NC4];
+            const float* yj[NC4];
+#pragma unroll
+            for (int t = 0; t < NC4; ++t) {
+                j[t] = (int64_t)local * 16 + (threadIdx.x >> 6) * NC4 + t;
+                yj[t] = Y + (j[t] < B.n ? j[t] : B.n - 1) * rows;
             }
+            double acc[NC4];
+            d2_columns<NC4>(yj, ys, rows, lane, acc);
+#pragma unroll
+            for (int t = 0; t < NC4; ++t)
+                if (lane == 0 && j[t] < B.n) B.d2[j[t]] = (m == 0) ? acc[t] : fmin(B.d2[j[t]], acc[t]);
         });
         if (!grid_sync(gs, nb, tmo, BP_SEED_D2, tclk)) return;
         if (m + 1 >= A.cmax) break;

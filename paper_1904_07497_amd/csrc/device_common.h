@@ -116,6 +116,53 @@ __device__ inline double d2_column(const T* __restrict__ yj, const T* __restrict
     return wave_sum(acc);
 }
 
+// d2_column<float, 4> of NC columns against the same seed column, computed
+// together: every 512-row pass issues the seed's loads once and all the columns'
+// loads before any arithmetic.  Each lane visits its rows in the same order as
+// d2_column, so every result is bitwise that of d2_column.  d % 4 == 0.
+template <int NC>
+__device__ inline void d2_columns(const float* const (&yj)[NC], const float* __restrict__ ys,
+                                  int64_t d, int lane, double (&out)[NC]) {
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    constexpr int U = 2;
+    int64_t i = (int64_t)lane * 4;
+    for (; i + 256 * (U - 1) < d; i += 256 * U) {
+        float b[U][4], a[NC][U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) vload<float, 4>(ys + i + 256 * u, b[u]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int u = 0; u < U; ++u) vload<float, 4>(yj[c] + i + 256 * u, a[c][u]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double t = (double)a[c][u][v] - (double)b[u][v];
+                    acc[c] += t * t;
+                }
+    }
+    for (; i < d; i += 256) {
+        float b[4], a[NC][4];
+        vload<float, 4>(ys + i, b);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) vload<float, 4>(yj[c] + i, a[c]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double t = (double)a[c][v] - (double)b[v];
+                acc[c] += t * t;
+            }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = wave_sum(acc[c]);
+}
+
 // The column indices of one group segment (at most kMaxSegCols), copied from the
 // sort permutation into LDS once per tile so that the column loop does not wait
 // on a global load before each batch of columns.  Every thread must call it.
