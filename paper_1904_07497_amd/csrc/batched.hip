@@ -469,19 +469,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wave per column, 4 rows per lane
         const int64_t r = (int64_t)rb * kBatchRows + lane * 4;
         double a = 0.0, b = 0.0, c = 0.0;
-        if (r < B.dp)
-            for (int64_t j = j0 + w; j < j1; j += kBlock / 64) {
-                float v[4];
+        if (r < B.dp) {
+            // up to four of the wave's columns at a time: every load (clamped into the
+            // matrix, values past row d zeroed after) issued before the stores, the
+            // columns' squares added in column order
+            constexpr int PJ = 4, WS = kBlock / 64;
+            for (int64_t jb = j0 + w; jb < j1; jb += PJ * WS) {
+                float v[PJ][4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = (r + e < B.d) ? B.Xc[j * B.ldx + r + e] : 0.f;
-                const float4 x = make_float4(v[0], v[1], v[2], v[3]);
-                *reinterpret_cast<float4*>(B.X + j * B.dp + r) = x;
-                a += (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z + (double)x.w * x.w;
-                const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-                *reinterpret_cast<float4*>(B.L + j * B.dp + r) = z;
-                *reinterpret_cast<float4*>(B.S + j * B.dp + r) = z;
-                *reinterpret_cast<float4*>(B.Th + j * B.dp + r) = z;
+                for (int u = 0; u < PJ; ++u) {
+                    const int64_t j = jb + u * WS < j1 ? jb + u * WS : j1 - 1;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float t = B.Xc[j * B.ldx + (r + e < B.d ? r + e : B.d - 1)];
+                        v[u][e] = r + e < B.d ? t : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < PJ; ++u) {
+                    const int64_t j = jb + u * WS;
+                    if (j >= j1) break;
+                    const float4 x = make_float4(v[u][0], v[u][1], v[u][2], v[u][3]);
+                    *reinterpret_cast<float4*>(B.X + j * B.dp + r) = x;
+                    a += (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z + (double)x.w * x.w;
+                    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                    *reinterpret_cast<float4*>(B.L + j * B.dp + r) = z;
+                    *reinterpret_cast<float4*>(B.S + j * B.dp + r) = z;
+                    *reinterpret_cast<float4*>(B.Th + j * B.dp + r) = z;
+                }
             }
+        }
         if (B.Z && rb == 0)
             for (int64_t j = j0 + w; j < j1; j += kBlock / 64)
                 for (int64_t q = lane * 4; q < B.kdp; q += 256) {
