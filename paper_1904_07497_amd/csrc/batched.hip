@@ -226,18 +226,34 @@ __device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab,
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         // pass 0: every column under its label, or (old) the entering keys; pass 1
         // (old only): the leaving keys
-        for (int pass = 0; pass < (old ? 2 : 1); ++pass)
-            for (int base = 0; base < n; base += 64) {
-                const int j = base + lane;
+        // the labels of the next PF chunks are loaded while a chunk is placed
+        // (loads clamped into the columns, no branch around them)
+        constexpr int PF = 4;
+        const int nch = (n + 63) / 64;
+        int la[PF], lo[PF];
+        auto fetch = [&](int ch, int slot) {
+            const int jj = min(min(ch, nch - 1) * 64 + lane, n - 1);
+            la[slot] = lab[jj];
+            lo[slot] = old ? old[jj] : 0;
+        };
+        for (int pass = 0; pass < (old ? 2 : 1); ++pass) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) fetch(q, q);
+            for (int ch0 = 0; ch0 < nch; ch0 += PF)
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                if (ch0 + q >= nch) break;
+                const int j = (ch0 + q) * 64 + lane;
+                const int lb = la[q], lold = lo[q];
+                fetch(ch0 + q + PF, q);
                 bool valid = j < n;
                 int my = 0;
                 if (valid) {
                     if (!old) {
-                        my = lab[j];
+                        my = lb;
                     } else {
-                        const int a = old[j], b = lab[j];
-                        valid = a != b;
-                        my = pass == 0 ? b : c + a;
+                        valid = lold != lb;
+                        my = pass == 0 ? lb : c + lold;
                     }
                 }
                 uint64_t same = __ballot(valid);
@@ -254,6 +270,7 @@ __device__ void sort_instance(BatchInst& B, const int32_t* __restrict__ lab,
                     if (rank == 0) offs[my] = base_off + __popcll(same);
                 }
             }
+        }
     }
     __syncthreads();   // the tables are reused by the next instance of this workgroup
 }
