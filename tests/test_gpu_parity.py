@@ -234,15 +234,17 @@ def test_iterate_full_size_sampled_columns():
 
 # ------------------------------------------------------------- full size
 
+@pytest.mark.parametrize("precision", [rp.F32, rp.BF16GEMM_F32])
 @pytest.mark.parametrize("rank", [100, 5])
-def test_solve_full_size_properties(rank):
-    """10^4 x 10^4 FP32 solve, true rank given (c = 100) and withheld (c = 5):
-    converges, X = L + S to the tolerance, finite outputs, labels in range."""
-    say(f"full-size solve c={rank}: generating")
+def test_solve_full_size_properties(rank, precision):
+    """10^4 x 10^4 FP32-data solve, true rank given (c = 100) and withheld (c = 5),
+    FP32 and bounded distances: converges, X = L + S to the tolerance, finite
+    outputs, labels in range."""
+    say(f"full-size solve c={rank} precision={precision}: generating")
     X, _, _ = synth.config_large(1, np.float32)
     Xd = dev(X)
     say(f"full-size solve c={rank}: gpu")
-    g = rp.solve(Xd, rank=rank, lam=0.01, tol=1e-6, seed=0)
+    g = rp.solve(Xd, rank=rank, lam=0.01, tol=1e-6, seed=0, precision=precision)
     say(f"info {g['info']}")
     assert g["status"] == rp.OK
     L, S = g["L"].double(), g["S"].double()
@@ -427,10 +429,11 @@ def test_exact_ties_go_to_lowest_group(precision):
     np.testing.assert_array_equal(gs["labels"].cpu().numpy(), o["labels"])
 
 
-def test_bf16_iterate_full_size_sampled_columns():
-    """Full-size one-iteration check of the bf16 mode (10^4 x 10^4, c = 100)."""
+@pytest.mark.parametrize("c", [100, 5])
+def test_bf16_iterate_full_size_sampled_columns(c):
+    """Full-size one-iteration check of the bounded mode at 10^4 x 10^4: c = 100 on
+    the split-bf16 direct tile, c = 5 on the FP64 tile."""
     d = n = 10000
-    c = 100
     X, _, _ = synth.config_large(1, np.float32)
     st = synth.random_state(X, c, seed=8, s_frac=0.1, s_amp=20.0)
     st["rho"] = 0.3
