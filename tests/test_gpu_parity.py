@@ -461,6 +461,39 @@ def test_bf16_iterate_full_size_sampled_columns(c):
     np.testing.assert_array_equal(lab[sep], o["labels"][sep])
 
 
+def test_bounded_iterate_clip_shape_sampled_columns():
+    """The bounded mode's FP64 tile at the clip shape (76800 x 2000, c = 5: many row
+    slices per column): one iteration from a random state, sampled columns against
+    the oracle, labels equal wherever the two nearest distances are separated."""
+    X, _, _ = synth.video(n=2000, h=240, w=320, seed=2, dtype=np.float32)
+    d, n = X.shape
+    c = 5
+    st = synth.random_state(X, c, seed=9, s_frac=0.1, s_amp=20.0)
+    st["rho"] = 0.05
+    lam = float(np.sqrt(max(d, n)))
+    say(f"bounded iterate clip shape d={d} n={n}")
+    gs = _gpu_state(st, np.float32)
+    rp.iterate(dev(X), gs, iters=1, lam=lam, max_lloyd=1, precision=rp.BF16GEMM_F32)
+    rng = np.random.default_rng(1)
+    sel = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 62, replace=False)]))
+    o = oracle.step_columns(oracle.make_params(c, lam=lam, max_lloyd=1), X, st, sel)
+    Xo = X[:, sel].astype(np.float64)
+    idx = torch.from_numpy(sel).cuda()
+    for k in ("L", "S"):
+        assert rel(host(gs[k][:, idx]), o[k], np.linalg.norm(Xo)) <= F32_TOL, k
+    lab = gs["labels"].cpu().numpy()[sel]
+    mu = o["mu"]
+    dist = ((o["L"][:, :, None] - mu[:, None, :]) ** 2).sum(axis=0)
+    srt = np.sort(dist, axis=1)
+    gap = srt[:, 1] - srt[:, 0]
+    cn = np.sqrt((mu ** 2).sum(axis=0)).max()
+    ln = np.sqrt((o["L"] ** 2).sum(axis=0))
+    bound = 64 * np.finfo(np.float32).eps * (cn ** 2 + 2 * cn * ln)
+    sep = gap > bound
+    assert sep.mean() > 0.9
+    np.testing.assert_array_equal(lab[sep], o["labels"][sep])
+
+
 # ------------------------------------------------------------ batched solver
 
 def _batch_mix(seed=7):
