@@ -355,6 +355,8 @@ def test_bf16_kmeans_matches_oracle():
     (1022, 513, 16, 6),     # FP64 tile, scalar loads (d % 4 != 0), padded ld
     (260, 1500, 9, 4),      # FP64 tile, 16-byte loads with ld > d
     (3000, 100, 1, 0),      # one group
+    (7, 40, 3, 1),          # FP64 tile, fewer rows than one step, scalar loads
+    (64, 9, 4, 0),          # FP64 tile, fewer columns than one lane group's share
 ])
 def test_bf16_kmeans_tile_variants_match_oracle(d, n, c, pad):
     """Every bounded-distance tile variant (chosen by c and the column layout) gives
