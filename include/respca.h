@@ -50,8 +50,11 @@ typedef enum {
 typedef enum {
     RESPCA_F64 = 0,              /* everything in double                              */
     RESPCA_F32 = 1,              /* float data and arithmetic, double accumulators    */
-    RESPCA_BF16GEMM_F32 = 2      /* as F32, but K-means distances on bf16 MFMA with an
-                                    exact FP32 re-check of close calls               */
+    RESPCA_BF16GEMM_F32 = 2      /* as F32, but K-means labels from FP64 distances of
+                                    the FP32 values: above 32 groups split-bf16 MFMA
+                                    with bounds and an exact re-check of close calls,
+                                    17-32 groups FP32 MFMA with bounds and the same
+                                    re-check, at most 16 groups FP64 dot products    */
 } respca_precision;
 
 typedef struct {
@@ -92,7 +95,8 @@ typedef struct {
     double  dL;           /* ||L_t - L_{t-1}||_F / ||X||_F                              */
     double  dS;           /* ||S_t - S_{t-1}||_F / ||X||_F                              */
     double  rho_final;    /* rho used by the last iteration                             */
-    int64_t refined;      /* bf16 mode: column decisions re-taken exactly (all passes)   */
+    int64_t refined;      /* bf16 mode: column decisions re-taken exactly (all passes;
+                             zero at most 16 groups, where nothing is re-taken)          */
 } respca_info;
 
 typedef struct respca_handle_s *respca_handle;
