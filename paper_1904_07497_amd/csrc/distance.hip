@@ -549,8 +549,11 @@ constexpr int kF64Step = 4 * kF64Lanes;         // rows per step of a lane group
 constexpr int f64_cols(int nc) { return 24 / nc < 1 ? 1 : (24 / nc > 6 ? 6 : 24 / nc); }
 // Steps of Y in flight per lane: the current one and kF64Ahead - 1 ahead.
 constexpr int kF64Ahead = 3;
-// Longest slice: its centroid rows take at most 32 KB of LDS.
-constexpr int f64_max_rows(int nc) { return nc <= 8 ? 1024 : 512; }
+// Longest slice: its centroid rows take at most 40 KB of LDS (whole 64-row steps,
+// at most 2048 rows).
+constexpr int f64_max_rows(int nc) {
+    return (40960 / (4 * nc)) / 64 * 64 < 2048 ? (40960 / (4 * nc)) / 64 * 64 : 2048;
+}
 
 // Rows rw..rw+3 of column p (VEC: p + rw 16-byte aligned).  FULL: all four rows are
 // below lim.  Otherwise rows at or past lim read row lim - 1 and become zero.
