@@ -53,6 +53,15 @@ WORKLOADS = {
     "video": dict(name="RES-PCA FP32 synthetic 240x320x2000 clip (rank-5 background, 4 moving 20x20 "
                        "squares, 8-bit scale), c=5, lambda=sqrt(76800), tol=1e-6", d=76800, n=2000,
                   rank=5, lam=None, tol=1e-6, gen="video"),
+    "large_lloyd1": dict(name="RES-PCA FP32 10000x10000 rank-100 + 10% sparse in [-100,100], c=100, "
+                              "lambda=0.01, tol=1e-6, p-step = one Lloyd assignment per outer "
+                              "iteration (instead of K-means to convergence)", d=10000, n=10000,
+                         rank=100, lam=0.01, tol=1e-6, gen="large", max_lloyd=1),
+    "scaling": dict(name="scalability (Sec. 5): seeded random subsets of the synthetic 240x320x2000 "
+                         "clip at ratios 1/8, 1/4, 1/2, 1 of n (all d) and of d (all n), c=5, "
+                         "lambda=sqrt(max(d,n)), 30 outer iterations (no tolerance), 10 runs each",
+                    d=76800, n=2000, rank=5, iters=30, runs=10, ratios=(0.125, 0.25, 0.5, 1.0),
+                    gen="scaling"),
 }
 
 
@@ -422,15 +431,19 @@ def main():
     if wl["gen"] == "warmstart":
         bench_warmstart(args, wl)
         return
+    if wl["gen"] == "scaling":
+        bench_scaling(args, wl)
+        return
     X = make_input(wl, np.float32)
     Xd = torch.from_numpy(X).to("cuda:0")
     d, n = X.shape
 
-    def timed(precision, steps, warmup, units):
+    def timed(precision, steps, warmup, units, max_lloyd=None):
         """Solves timed end to end; the library's event timing covers `units` only
         (each event pair can idle the device for microseconds)."""
         prec = rp.BF16GEMM_F32 if precision == "bf16" else rp.F32
-        kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=prec)
+        kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=prec,
+                  max_lloyd=max_lloyd if max_lloyd is not None else wl.get("max_lloyd", 100))
         out = (rp.empty_colmajor(d, n, Xd.dtype, Xd.device),
                rp.empty_colmajor(d, n, Xd.dtype, Xd.device),
                torch.empty(n, dtype=torch.int32, device=Xd.device))
@@ -515,8 +528,105 @@ def main():
         line[f"rel_err_S_vs_{other}"] = float(torch.linalg.norm(out[1].double() - Sr) /
                                               max(float(torch.linalg.norm(Sr)), 1e-300))
         line["labels_equal_fraction"] = float((out[2] == out2[2]).double().mean())
+    if wl.get("max_lloyd", 100) != 100:
+        # the same workload with the method's p-step (K-means to convergence)
+        e3, i3, _, out3 = timed(args.precision, 1, 0, units, max_lloyd=100)
+        Lr = out3[0].double()
+        line["full_kmeans_solves_per_s"] = round(1.0 / e3, 4)
+        line["full_kmeans_iters"] = i3[-1]["iters"]
+        line["full_kmeans_lloyd_steps"] = i3[-1]["lloyd_steps"]
+        line["rel_diff_L_vs_full_kmeans"] = float(torch.linalg.norm(out[0].double() - Lr) /
+                                                  torch.linalg.norm(Lr))
+        line["config"]["max_lloyd"] = wl["max_lloyd"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, wl, infos[-1])
+    print(json.dumps(line), flush=True)
+
+
+def bench_scaling(args, wl):
+    """Sec. 5 scalability: time of a fixed number of outer iterations on subsets of
+    the clip, sampled in n (all rows) and in d (all columns); mean of `runs` solves
+    per subset, and least-squares lines of time against n and against d."""
+    import numpy as np
+    import torch
+    from paper_1904_07497_amd import respca as rp
+    from paper_1904_07497_amd import synth
+
+    X, _, _ = synth.video(n=wl["n"], seed=2, dtype=np.float32)
+    d, n = X.shape
+    rng = np.random.default_rng(0)
+    prec = rp.BF16GEMM_F32 if args.precision == "bf16" else rp.F32
+
+    def subset(nr, dr):
+        cols = np.sort(rng.choice(n, int(round(n * nr)), replace=False)) if nr < 1 else np.arange(n)
+        rows = np.sort(rng.choice(d, int(round(d * dr)), replace=False)) if dr < 1 else np.arange(d)
+        return torch.from_numpy(np.asfortranarray(X[np.ix_(rows, cols)])).to("cuda:0")
+
+    def run(Xd, profile=False):
+        dd, nn = Xd.shape
+        kw = dict(rank=wl["rank"], lam=float(np.sqrt(max(dd, nn))), tol=0.0, max_iter=wl["iters"],
+                  seed=0, precision=prec)
+        out = (rp.empty_colmajor(dd, nn, Xd.dtype, Xd.device),
+               rp.empty_colmajor(dd, nn, Xd.dtype, Xd.device),
+               torch.empty(nn, dtype=torch.int32, device=Xd.device))
+        for _ in range(max(args.warmup, 1)):
+            rp.solve(Xd, out=out, **kw)
+        torch.cuda.synchronize()
+        rp.profile_enable(profile, units=["sweep"] if profile else None)
+        ts = []
+        for _ in range(wl["runs"]):
+            t0 = time.perf_counter()
+            info = rp.solve(Xd, out=out, **kw)["info"]
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            assert info["iters"] == wl["iters"]
+        prof = rp.profile_query()["sweep"] if profile else None
+        rp.profile_enable(False)
+        return float(np.mean(ts)), prof
+
+    def fit(xs, ys):
+        a, b = np.polyfit(xs, ys, 1)
+        pred = a * np.asarray(xs) + b
+        ss = float(np.sum((np.asarray(ys) - pred) ** 2))
+        st = float(np.sum((np.asarray(ys) - np.mean(ys)) ** 2))
+        return {"ms_per_unit": a * 1e3, "intercept_ms": b * 1e3, "r2": 1.0 - ss / st if st > 0 else 1.0}
+
+    full_s, prof = run(subset(1.0, 1.0), profile=True)
+    by_n, by_d = [], []
+    for r in wl["ratios"]:
+        t = full_s if r == 1.0 else run(subset(r, 1.0))[0]
+        by_n.append({"n": int(round(n * r)), "d": d, "ms": round(t * 1e3, 3)})
+    for r in wl["ratios"]:
+        t = full_s if r == 1.0 else run(subset(1.0, r))[0]
+        by_d.append({"n": n, "d": int(round(d * r)), "ms": round(t * 1e3, 3)})
+    fn = fit([e["n"] for e in by_n], [e["ms"] / 1e3 for e in by_n])
+    fd = fit([e["d"] for e in by_d], [e["ms"] / 1e3 for e in by_d])
+    nl = max(prof["launches"], 1)
+    secs = prof["ms"] / 1e3 / nl
+    ach = prof["bytes"] / nl / secs / 1e9 if secs > 0 else 0.0
+    line = {
+        "metric": "RPCA solves/s + sweep HBM GB/s at rel-err<=1e-5 (BF16/learned vs plain FP32)",
+        "value": round(1.0 / full_s, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": wl["runs"],
+        "warmup": max(args.warmup, 1),
+        "ms_per_step": round(full_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "d": d, "n": n, "c": wl["rank"], "iters": wl["iters"],
+                   "precision": args.precision},
+        "time_vs_n": by_n,
+        "time_vs_d": by_d,
+        "linear_fit_n": {k: round(v, 6) for k, v in fn.items()},
+        "linear_fit_d": {k: round(v, 9) for k, v in fd.items()},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "sweep",
+                     "bytes_per_launch": prof["bytes"] / nl, "mean_launch_ms": round(secs * 1e3, 4)},
+    }
     print(json.dumps(line), flush=True)
 
 

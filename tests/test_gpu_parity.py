@@ -111,6 +111,28 @@ def test_solve_f32_grouped_iteration_locked(shape, lam):
     assert abs(g2["info"]["iters"] - T) <= 1
 
 
+@pytest.mark.parametrize("precision", [rp.F32, rp.BF16GEMM_F32])
+def test_solve_single_lloyd_step_matches_oracle(precision):
+    """p-step of one Lloyd assignment per outer iteration (max_lloyd = 1, also for
+    the initial K-means): iteration-locked whole solve against the oracle run with
+    the same option (labels, iteration and Lloyd counts, L and S)."""
+    d, n, c = 1500, 900, 12
+    X, _, _, _ = synth.clustered(d, n, c, seed=77, sep=3.0, noise=0.8, frac=0.05, amp=10.0,
+                                 dtype=np.float32)
+    lam = float(np.sqrt(max(d, n)))
+    o = oracle.solve(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=3, max_lloyd=1))
+    T = o["info"]["iters"]
+    say(f"single-Lloyd-step solve T={T} precision={precision}")
+    g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=T, seed=3, max_lloyd=1,
+                 precision=precision)
+    assert g["info"]["iters"] == T
+    np.testing.assert_array_equal(g["labels"].cpu().numpy(), o["labels"])
+    assert g["info"]["init_lloyd"] == o["info"]["init_lloyd"]
+    nX = np.linalg.norm(X.astype(np.float64))
+    assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
+    assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+
+
 def test_solve_f32_video_clip_matches_oracle_and_table2_counts():
     """Synthetic 8-bit clip, lambda = sqrt(max(n, d)), tol 1e-3 (the Sec. 5.1
     setting): the GPU stops at the oracle's iteration (23, as in Table 2)."""
