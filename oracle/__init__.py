@@ -34,7 +34,8 @@ def build() -> str:
 class Params(ct.Structure):
     _fields_ = [("lam", ct.c_double), ("c", ct.c_int32), ("tol", ct.c_double),
                 ("max_iter", ct.c_int32), ("rho0", ct.c_double), ("kappa", ct.c_double),
-                ("rho_max", ct.c_double), ("max_lloyd", ct.c_int32), ("seed", ct.c_uint64)]
+                ("rho_max", ct.c_double), ("max_lloyd", ct.c_int32), ("seed", ct.c_uint64),
+                ("sparse_norm", ct.c_int32)]
 
 
 class Info(ct.Structure):
@@ -74,6 +75,7 @@ def lib():
         L.oracle_kmeans.restype = i32
         L.oracle_kmeans.argtypes = [i64, i64, i32, dp, ct.c_uint64, i32, ip, dp]
         L.oracle_s_step.argtypes = [i64, i64, f64, dp, dp, dp, dp]
+        L.oracle_s_step_l21.argtypes = [i64, i64, f64, dp, dp, dp, dp]
         L.oracle_theta_step.argtypes = [i64, i64, f64, dp, dp, dp, dp]
         L.oracle_step.restype = i32
         L.oracle_step.argtypes = [P(Params), i64, i64, dp, dp, dp, dp, ip, dp, dp, dp]
@@ -108,13 +110,13 @@ def _lp(a: np.ndarray):
 
 
 def make_params(c, lam=None, d=None, n=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5,
-                rho_max=1e10, max_lloyd=100, seed=0) -> Params:
+                rho_max=1e10, max_lloyd=100, seed=0, sparse_norm=0) -> Params:
     """Defaults follow Sec. 5 (tol 1e-3, 500 iterations, rho0 1e-4, kappa 1.5) and
     lambda = sqrt(max(n, d)) (Sec. 5.1) when ``lam`` is None."""
     if lam is None:
         lam = float(np.sqrt(max(d, n)))
     return Params(float(lam), int(c), float(tol), int(max_iter), float(rho0), float(kappa),
-                  float(rho_max), int(max_lloyd), int(seed) & 0xFFFFFFFFFFFFFFFF)
+                  float(rho_max), int(max_lloyd), int(seed) & 0xFFFFFFFFFFFFFFFF, int(sparse_norm))
 
 
 def splitmix64(seed: int, count: int) -> list[int]:
@@ -198,11 +200,13 @@ def kmeans(Y, c, seed, max_lloyd=100):
     return lab, C, int(steps)
 
 
-def s_step(X, L, Theta, rho):
+def s_step(X, L, Theta, rho, sparse_norm=0):
+    """Sec. 4.3 S-step; sparse_norm 1: its column-wise l2,1 form."""
     X, L, Theta = _f64(X), _f64(L), _f64(Theta)
     d, n = X.shape
     S = np.zeros((d, n), order="F")
-    lib().oracle_s_step(d, n, float(rho), _dp(X), _dp(L), _dp(Theta), _dp(S))
+    f = lib().oracle_s_step_l21 if sparse_norm == 1 else lib().oracle_s_step
+    f(d, n, float(rho), _dp(X), _dp(L), _dp(Theta), _dp(S))
     return S
 
 

@@ -220,6 +220,23 @@ void oracle_s_step(int64_t d, int64_t n, double rho, const double *X,
     }
 }
 
+void oracle_s_step_l21(int64_t d, int64_t n, double rho, const double *X,
+                       const double *L, const double *Theta, double *S)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        const double *x = X + j * d, *l = L + j * d, *t = Theta + j * d;
+        double *s = S + j * d;
+        double nb2 = 0.0;
+        for (int64_t i = 0; i < d; ++i) {
+            double b = x[i] - l[i] + t[i] / rho;
+            nb2 += b * b;
+        }
+        double nb = sqrt(nb2);
+        double f = (rho * nb > 1.0) ? 1.0 - 1.0 / (rho * nb) : 0.0;
+        for (int64_t i = 0; i < d; ++i) s[i] = f * (x[i] - l[i] + t[i] / rho);
+    }
+}
+
 void oracle_theta_step(int64_t d, int64_t n, double rho, const double *X,
                        const double *L, const double *S, double *Theta)
 {
@@ -242,8 +259,9 @@ int32_t oracle_step(const oracle_params *p, int64_t d, int64_t n, const double *
     oracle_l_step(d, n, p->c, p->lambda, r, X, S, Theta, labels, Lnew, C);
     /* Sec. 4.2: p-step = K-means of the columns of L, from the current groups */
     int32_t steps = oracle_lloyd(d, n, p->c, Lnew, C, labels, p->max_lloyd);
-    /* Sec. 4.3: S-step */
-    oracle_s_step(d, n, r, X, Lnew, Theta, Snew);
+    /* Sec. 4.3: S-step (or its l2,1 form) */
+    if (p->sparse_norm == 1) oracle_s_step_l21(d, n, r, X, Lnew, Theta, Snew);
+    else oracle_s_step(d, n, r, X, Lnew, Theta, Snew);
     /* Sec. 4.4: multiplier and penalty */
     oracle_theta_step(d, n, r, X, Lnew, Snew, Theta);
 
@@ -292,7 +310,8 @@ void oracle_step_columns(const oracle_params *p, int64_t d, int64_t n, const dou
         double *Lq = L_out + q * d;
         for (int64_t i = 0; i < d; ++i) Lq[i] = alpha * D[j * d + i] + beta * mu[k * d + i];
         oracle_assign(d, 1, c, Lq, mu, labels_out + q);
-        oracle_s_step(d, 1, rho, X + j * d, Lq, Theta + j * d, S_out + q * d);
+        if (p->sparse_norm == 1) oracle_s_step_l21(d, 1, rho, X + j * d, Lq, Theta + j * d, S_out + q * d);
+        else oracle_s_step(d, 1, rho, X + j * d, Lq, Theta + j * d, S_out + q * d);
         memcpy(Theta_out + q * d, Theta + j * d, (size_t)d * sizeof(double));
         oracle_theta_step(d, 1, rho, X + j * d, Lq, S_out + q * d, Theta_out + q * d);
     }
@@ -313,6 +332,7 @@ static int params_valid(const oracle_params *p, int64_t d, int64_t n)
     if (!(p->kappa > 1.0) || !isfinite(p->kappa)) return 0;
     if (!(p->rho_max >= p->rho0)) return 0;
     if (!(p->tol >= 0.0)) return 0;
+    if (p->sparse_norm != 0 && p->sparse_norm != 1) return 0;
     if (p->max_iter < 1 || p->max_lloyd < 1) return 0;
     return 1;
 }

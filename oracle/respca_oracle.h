@@ -39,6 +39,9 @@ typedef struct {
     double   rho_max;    /* cap on rho (not in the paper)                                   */
     int32_t  max_lloyd;  /* cap on Lloyd assignment passes per K-means call                 */
     uint64_t seed;       /* k-means++ seeding stream                                        */
+    int32_t  sparse_norm;/* penalty on S: 0 the l1 norm of eq_obj (Sec. 3), 1 the column-wise
+                            l2,1 norm named as the alternative after eq_obj (Sec. 3); the
+                            norm is defined with eq_rpca_l21 (Sec. 2); other values invalid */
 } oracle_params;
 
 typedef struct {
@@ -115,6 +118,10 @@ int32_t oracle_kmeans(int64_t d, int64_t n, int32_t c, const double *Y,
 /* S-step, Sec. 4.3: B = X - L + Theta/rho, S = sign(B) max(|B| - 1/rho, 0). */
 void oracle_s_step(int64_t d, int64_t n, double rho, const double *X,
                    const double *L, const double *Theta, double *S);
+/* S-step with the l2,1 norm: column j of S is B_j max(0, 1 - 1/(rho ||B_j||)),
+ * B = X - L + Theta/rho (the proximal map of (1/rho)||.||_2 per column). */
+void oracle_s_step_l21(int64_t d, int64_t n, double rho, const double *X,
+                       const double *L, const double *Theta, double *S);
 
 /* Multiplier update, Sec. 4.4: Theta <- Theta + rho (X - L - S). */
 void oracle_theta_step(int64_t d, int64_t n, double rho, const double *X,

@@ -111,8 +111,16 @@ def soft(B, t):
     return np.sign(B) * np.maximum(np.abs(B) - t, 0.0)
 
 
+def block_soft(B, t):
+    """Proximal map of t * sum_j ||B_j||_2, by the Moreau identity: B minus its
+    column-wise projection onto the ball of radius t."""
+    nb = np.linalg.norm(B, axis=0)
+    proj = B * np.minimum(1.0, t / np.where(nb > 0, nb, 1.0))
+    return B - proj
+
+
 def solve(X, c, lam, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
-          max_lloyd=100, seed=0):
+          max_lloyd=100, seed=0, sparse_norm=0):
     X = np.asarray(X, dtype=np.float64)
     nX = np.linalg.norm(X)
     d, n = X.shape
@@ -126,7 +134,8 @@ def solve(X, c, lam, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
     for it in range(1, max_iter + 1):
         L, C = l_step_dense(X, S, Th, labels, c, lam, rho, C)
         labels, C, _ = lloyd(L, C, labels, max_lloyd)
-        Sn = soft(X - L + Th / rho, 1.0 / rho)
+        prox = block_soft if sparse_norm == 1 else soft
+        Sn = prox(X - L + Th / rho, 1.0 / rho)
         Th = Th + rho * (X - L - Sn)
         crit = max(np.linalg.norm(X - L - Sn), np.linalg.norm(L - Lp), np.linalg.norm(Sn - S)) / nX
         S, Lp = Sn, L

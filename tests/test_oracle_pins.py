@@ -239,6 +239,132 @@ def test_theta_update_is_clipped_scaled_residual(orc):
     np.testing.assert_allclose(T2[nz], np.sign(S[nz]), atol=1e-13)
 
 
+# ------------------------------------------------- l2,1 sparse term --
+# The column-wise alternative to the l1 penalty (Sec. 3, after eq_obj; the
+# norm is the one of eq_rpca_l21 in Sec. 2).
+
+def _l21_inputs(seed, d, n):
+    """B columns spread over scales so that both the zero band ||B_j|| <= 1/rho
+    and the shrink branch occur."""
+    rng = np.random.default_rng(seed)
+    scales = np.geomspace(0.02, 6.0, n)
+    X = np.asfortranarray(rng.normal(0, 1, (d, n)) * scales)
+    L = np.asfortranarray(rng.normal(0, 0.05, (d, n)))
+    Th = np.asfortranarray(rng.uniform(-1, 1, (d, n)) / np.sqrt(d))
+    return X, L, Th
+
+
+def aug_lagrangian_l21(X, L, S, Theta, labels, c, lam, rho):
+    return (lam * trace_term(L, labels, c) + np.linalg.norm(S, axis=0).sum()
+            + 0.5 * rho * np.sum((X - L - S + Theta / rho) ** 2))
+
+
+def test_l21_s_step_minimises_column_problem(orc):
+    """Column j of S minimises (1/rho)||s||_2 + ||s - B_j||^2 / 2: checked against a
+    general-purpose minimiser and against random perturbations (the problem is
+    strongly convex, so a point no nearby point improves on is the minimiser)."""
+    from scipy.optimize import minimize
+    d, n = 4, 8
+    X, L, Th = _l21_inputs(20, d, n)
+    rng = np.random.default_rng(21)
+    seen_zero = seen_shrunk = False
+    for rho in [0.5, 1.0, 4.0]:
+        S = orc.s_step(X, L, Th, rho, sparse_norm=1)
+        B = X - L + Th / rho
+        for j in range(n):
+            b = B[:, j]
+
+            def f(s):
+                return np.linalg.norm(s) / rho + 0.5 * np.sum((s - b) ** 2)
+            r = minimize(f, b + 0.1, method="Nelder-Mead",
+                         options={"xatol": 1e-11, "fatol": 1e-15, "maxiter": 40000,
+                                  "maxfev": 80000})
+            fs = f(S[:, j])
+            assert fs <= r.fun + 1e-12
+            np.testing.assert_allclose(S[:, j], r.x, atol=1e-5)
+            for _ in range(20):
+                assert fs <= f(S[:, j] + rng.normal(0, 1e-3, d)) + 1e-15
+            if np.linalg.norm(b) <= 1 / rho:
+                assert np.all(S[:, j] == 0.0)
+                seen_zero = True
+            else:
+                seen_shrunk = True
+    assert seen_zero and seen_shrunk
+
+
+def test_l21_s_step_with_one_row_is_the_l1_step(orc):
+    """With d = 1 the l2,1 norm is the l1 norm, so both S-steps coincide."""
+    X, L, Th = _l21_inputs(22, 1, 40)
+    for rho in [0.3, 2.0]:
+        np.testing.assert_allclose(orc.s_step(X, L, Th, rho, sparse_norm=1),
+                                   orc.s_step(X, L, Th, rho), atol=1e-15)
+
+
+def test_l21_theta_is_a_subgradient_of_the_column_norms(orc):
+    """After the multiplier update Theta' = Theta + rho (X - L - S'), column j of
+    Theta' is S'_j / ||S'_j|| where S'_j != 0 and has norm <= 1 where S'_j = 0:
+    the optimality condition of the S-subproblem."""
+    d, n = 6, 12
+    X, L, Th = _l21_inputs(23, d, n)
+    rho = 1.3
+    S = orc.s_step(X, L, Th, rho, sparse_norm=1)
+    T2 = orc.theta_step(X, L, S, Th, rho)
+    nS = np.linalg.norm(S, axis=0)
+    nT = np.linalg.norm(T2, axis=0)
+    assert (nS > 0).any() and (nS == 0).any()
+    for j in range(n):
+        if nS[j] > 0:
+            np.testing.assert_allclose(T2[:, j], S[:, j] / nS[j], atol=1e-13)
+        else:
+            assert nT[j] <= 1 + 1e-13
+
+
+def test_l21_step_identities_and_lagrangian_decrease(orc):
+    """One outer iteration with the l2,1 S-step keeps the L-step identity, the
+    multiplier identity and column norms of Theta <= 1; the S-step does not
+    increase the l2,1 augmented Lagrangian; the invalid value 2 is rejected."""
+    X = np.asfortranarray(np.random.default_rng(24).normal(0, 3, (7, 15)))
+    c, lam = 3, 0.9
+    p = orc.make_params(c, lam=lam, max_lloyd=1, sparse_norm=1)
+    st = _state(X, c, 1)
+    rho = st["rho"]
+    D = X - st["S"] + st["Theta"] / rho
+    mu, _ = orc.group_means(D, st["labels"], c)
+    out = orc.step(p, X, st)
+    lhs = 2 * lam * (out["L"] - mu[:, st["labels"]]) - out["Theta"]
+    np.testing.assert_allclose(lhs, rho * (out["S"] - st["S"]), atol=1e-12)
+    np.testing.assert_allclose(X - out["L"] - out["S"], (out["Theta"] - st["Theta"]) / rho,
+                               atol=1e-12)
+    assert np.linalg.norm(out["Theta"], axis=0).max() <= 1 + 1e-12
+    lab = out["labels"]
+    f_before = aug_lagrangian_l21(X, out["L"], st["S"], st["Theta"], lab, c, lam, rho)
+    f_after = aug_lagrangian_l21(X, out["L"], out["S"], st["Theta"], lab, c, lam, rho)
+    assert f_after <= f_before + 1e-12
+    sel = np.array([0, 4, 14])
+    part = orc.step_columns(p, X, st, sel)
+    for k in ("L", "S", "Theta"):
+        np.testing.assert_array_equal(part[k], out[k][:, sel])
+    bad = orc.make_params(c, lam=lam, sparse_norm=2)
+    assert orc.solve(X, bad)["status"] == -1
+
+
+@pytest.mark.parametrize("seed,c,lam", [(0, 2, 0.3), (1, 3, 2.0)])
+def test_l21_whole_solve_matches_independent_numpy_implementation(orc, seed, c, lam):
+    """The numpy solve takes the column shrink through the Moreau identity (B minus
+    its projection onto the ball of radius 1/rho), a different route to the
+    same proximal map."""
+    X, _, _, _ = synth.clustered(7, 10, c, seed=seed, sep=4.0, noise=0.5, frac=0.1, amp=6.0,
+                                 min_size=1)
+    r = orc.solve(X, orc.make_params(c, lam=lam, tol=1e-8, seed=seed, sparse_norm=1))
+    q = npr.solve(X, c, lam, tol=1e-8, seed=seed, sparse_norm=1)
+    assert r["status"] == 0
+    assert r["info"]["iters"] == q["iters"]
+    np.testing.assert_array_equal(r["labels"], q["labels"])
+    sc = np.linalg.norm(X)
+    assert np.linalg.norm(r["L"] - q["L"]) / sc < 1e-12
+    assert np.linalg.norm(r["S"] - q["S"]) / sc < 1e-12
+
+
 # -------------------------------------------------------- iteration pins --
 
 def _state(X, c, seed):
