@@ -57,6 +57,10 @@ WORKLOADS = {
                               "lambda=0.01, tol=1e-6, p-step = one Lloyd assignment per outer "
                               "iteration (instead of K-means to convergence)", d=10000, n=10000,
                          rank=100, lam=0.01, tol=1e-6, gen="large", max_lloyd=1),
+    "large_l21": dict(name="RES-PCA FP32 10000x10000 rank-100 + 10% sparse in [-100,100], c=100, "
+                           "lambda=0.01, tol=1e-6, column-wise l2,1 penalty on S (the alternative "
+                           "norm of Sec. 3) in place of l1", d=10000, n=10000, rank=100, lam=0.01,
+                      tol=1e-6, gen="large", sparse_norm=1),
     "scaling": dict(name="scalability (Sec. 5): seeded random subsets of the synthetic 240x320x2000 "
                          "clip at ratios 1/8, 1/4, 1/2, 1 of n (all d) and of d (all n), c=5, "
                          "lambda=sqrt(max(d,n)), 30 outer iterations (no tolerance), 10 runs each",
@@ -72,6 +76,7 @@ KERNEL_SOURCES = {
     "seeding": ("kernels.hip", "kernels.h", "device_common.h"),
     "distance": ("distance.hip", "dist_tile.h", "kernels.hip", "kernels.h", "device_common.h"),
     "batched": ("batched.hip", "batched.h", "dist_tile.h", "device_common.h", "kernels.h"),
+    "colnorm": ("kernels.hip", "kernels.h", "device_common.h"),
 }
 
 
@@ -122,7 +127,7 @@ def cpu_baseline(X, wl, gpu_info):
     st = {"L": np.zeros((d, n), order="F"), "S": np.zeros((d, n), order="F"),
           "Theta": np.zeros((d, n), order="F"), "labels": rng.integers(0, c, n).astype(np.int32),
           "C": np.zeros((d, c), order="F"), "rho": 1e-4}
-    p = oracle.make_params(c, lam=lam, max_lloyd=1)
+    p = oracle.make_params(c, lam=lam, max_lloyd=1, sparse_norm=wl.get("sparse_norm", 0))
     t = time.perf_counter()
     o = oracle.step(p, X64, st)                      # L-step + one assignment + S + Theta
     t_step = time.perf_counter() - t
@@ -443,7 +448,8 @@ def main():
         (each event pair can idle the device for microseconds)."""
         prec = rp.BF16GEMM_F32 if precision == "bf16" else rp.F32
         kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=prec,
-                  max_lloyd=max_lloyd if max_lloyd is not None else wl.get("max_lloyd", 100))
+                  max_lloyd=max_lloyd if max_lloyd is not None else wl.get("max_lloyd", 100),
+                  sparse_norm=wl.get("sparse_norm", 0))
         out = (rp.empty_colmajor(d, n, Xd.dtype, Xd.device),
                rp.empty_colmajor(d, n, Xd.dtype, Xd.device),
                torch.empty(n, dtype=torch.int32, device=Xd.device))
@@ -466,7 +472,7 @@ def main():
     _, _, prof_all, _ = timed(args.precision, 1, args.warmup, None)
     prof_all = {k: v for k, v in prof_all.items() if v["launches"] > 0}
     dom = max(prof_all, key=lambda k: prof_all[k]["ms"])
-    units = sorted({dom, "sweep"})
+    units = sorted({dom, "sweep"} | ({"colnorm"} if "colnorm" in prof_all else set()))
     elapsed, infos, prof, out = timed(args.precision, args.steps, 0, units)
     ms_per_step = 1e3 * elapsed / args.steps
 
@@ -538,6 +544,9 @@ def main():
         line["rel_diff_L_vs_full_kmeans"] = float(torch.linalg.norm(out[0].double() - Lr) /
                                                   torch.linalg.norm(Lr))
         line["config"]["max_lloyd"] = wl["max_lloyd"]
+    if wl.get("sparse_norm", 0):
+        line["config"]["sparse_norm"] = "l2,1"
+        line["colnorm_roofline"] = roofline_of("colnorm")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, wl, infos[-1])
     print(json.dumps(line), flush=True)

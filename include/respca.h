@@ -57,6 +57,18 @@ typedef enum {
                                     re-check, at most 16 groups FP64 dot products    */
 } respca_precision;
 
+/* Penalty on the sparse term S.  L1 is the entrywise l1 norm of eq_obj (Sec. 3;
+ * S-step of Sec. 4.3: entrywise soft threshold at 1/rho).  L21 is the column-wise
+ * l2,1 norm named after eq_obj as the alternative (norm of eq_rpca_l21, Sec. 2):
+ * the S-step becomes S_j = B_j max(0, 1 - 1/(rho ||B_j||_2)) per column j, with
+ * B = X - L + Theta/rho, and needs one extra read of X, S and Theta per iteration
+ * for the column norms.  The solver and iterate entry points take both; the
+ * batched solver takes L1 only (RESPCA_ERR_UNSUPPORTED otherwise). */
+typedef enum {
+    RESPCA_SPARSE_L1 = 0,
+    RESPCA_SPARSE_L21 = 1
+} respca_sparse_norm;
+
 typedef struct {
     double   lambda;      /* weight of the group-variance term of eq_obj (Sec. 3); must be
                              >= 0.  NaN selects sqrt(max(d, n)), the value of Sec. 5.1.   */
@@ -84,6 +96,8 @@ typedef struct {
                              RESPCA_F64.  NULL = none                                       */
     int64_t  init_embedding_ld;
     int32_t  init_embedding_rows;
+    int32_t  sparse_norm; /* respca_sparse_norm; default RESPCA_SPARSE_L1; other values
+                             RESPCA_ERR_INVALID                                             */
 } respca_params;
 
 typedef struct {
@@ -223,7 +237,8 @@ typedef enum {
                                      method's passes of every instance: 1 (||X||) + c (seeding)
                                      + 1 + 2 per initial Lloyd pass + 11 per outer iteration
                                      + 2 per extra Lloyd pass, times d n 4                          */
-    RESPCA_KERNEL_COUNT = 5
+    RESPCA_KERNEL_COLNORM = 5,    /* l2,1 S-step column norms: reads X, S, Theta                     */
+    RESPCA_KERNEL_COUNT = 6
 } respca_kernel_id;
 
 /* enable: 0 turns timing off; otherwise bit k (1 << k) times the launches of

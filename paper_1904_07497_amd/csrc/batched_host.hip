@@ -69,6 +69,8 @@ respca_status validate(respca_handle h, const respca_params* params, int32_t bat
         }
         if (res[i].precision != RESPCA_F32)
             return fail(h, RESPCA_ERR_UNSUPPORTED, "batched solver runs FP32 instances only");
+        if (res[i].sparse_norm != RESPCA_SPARSE_L1)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "batched solver runs the l1 penalty only");
         if (!X[i] || !L[i] || !S[i]) return fail(h, RESPCA_ERR_INVALID, "NULL matrix pointer");
         if (ldx[i] < d[i] || ldl[i] < d[i] || lds[i] < d[i])
             return fail(h, RESPCA_ERR_INVALID, "leading dimension < d");

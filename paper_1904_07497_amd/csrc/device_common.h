@@ -266,14 +266,17 @@ __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __res
 // over the segment's columns -- the group sums of the next L-step when the p-step
 // keeps every label -- in the order and arithmetic of group_partial_tile (column
 // groups added in group order), written to out[i] (this segment's d-vector).
-template <typename T, int V, int ROWS, int CG, int U>
+// L21: the column-wise (l2,1) S-step, S_j = fac[j] B_j with the per-column factor
+// max(0, 1 - 1/(rho ||B_j||)) computed beforehand over the whole column.
+template <typename T, int V, int ROWS, int CG, int U, bool L21 = false>
 __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* __restrict__ L,
                                       int64_t ldl, T* __restrict__ S, int64_t lds,
                                       T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
                                       int64_t p, int64_t d, const int32_t* __restrict__ perm,
                                       int begin, int len, int64_t r0, T alpha, T beta, T rho,
                                       T inv_rho, T inv_rho_next, double& a0, double& a1, double& a2,
-                                      double* __restrict__ out) {
+                                      double* __restrict__ out,
+                                      const double* __restrict__ fac = nullptr) {
     constexpr int TPC = kBlock / CG;
     constexpr int NS = ROWS / (TPC * V);
     static_assert(NS >= 1 && NS * TPC * V == ROWS, "row block must tile the column group");
@@ -291,6 +294,11 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
         int64_t jj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) jj[u] = (FULL || q0 + u * CG < len) ? cols[q0 + u * CG] : -1;
+        T fu[U];
+        if constexpr (L21) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) fu[u] = (FULL || jj[u] >= 0) ? (T)fac[jj[u]] : T(0);
+        }
 #pragma unroll
         for (int a = 0; a < NS; ++a) {
             const int64_t i = r0 + (int64_t)(a * TPC + tl) * V;
@@ -316,8 +324,12 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
                     const T dv = x - sv + t * inv_rho;
                     ln[v] = alpha * dv + beta * m[v];
                     const T b = x - ln[v] + t * inv_rho;
-                    const T mag = fabs(b) - inv_rho;
-                    sn[v] = mag > T(0) ? copysign(mag, b) : T(0);
+                    if constexpr (L21) {
+                        sn[v] = fu[u] * b;
+                    } else {
+                        const T mag = fabs(b) - inv_rho;
+                        sn[v] = mag > T(0) ? copysign(mag, b) : T(0);
+                    }
                     const T rr = x - ln[v] - sn[v];
                     tn[v] = t + rho * rr;
                     const double dl = (double)ln[v] - (double)lps[u][v];

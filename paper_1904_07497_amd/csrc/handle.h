@@ -46,6 +46,7 @@ struct respca_handle_s {
     std::vector<hipEvent_t> prof_pool;
     respca::DevBuf theta, cbuf, perm, counts, segb, segl, segf, nseg, sortbc, pmeans, dots, cnorm,
         lab_a, lab_b, d2, chosen, seeds, u, normp, chgp, status;
+    respca::DevBuf l21f;                // per-column l2,1 S-step factors (n doubles)
     respca::DevBuf zcopy, zsc, ynorm;   // fp16 copy, column scales and norms for bounded seeding
     // incremental Lloyd means: group sums, next counts, the moved-column sort and its partials
     respca::DevBuf gsum, cnt2, cbc, cperm, csegb, csegl, csegf, cnseg, cpart;
@@ -127,7 +128,7 @@ inline double uniform01(uint64_t& state) {
 // Parameters after defaults are applied.
 struct Resolved {
     double lambda, tol, rho0, kappa, rho_max;
-    int c, max_iter, max_lloyd, precision;
+    int c, max_iter, max_lloyd, precision, sparse_norm;
     uint64_t seed;
     const int32_t* init_labels;
     double* history;

@@ -84,7 +84,16 @@ int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t l
                      const int32_t* seg_begin, const int32_t* seg_len, const int32_t* nseg,
                      int64_t d, int64_t n, int c, double alpha, double beta, double rho,
                      double inv_rho, double inv_rho_next, double* norm_partial,
-                     double* next_partial, hipStream_t st);
+                     double* next_partial, hipStream_t st, const double* l21_fac = nullptr);
+
+// Column-wise (l2,1) S-step factors: fac[j] = max(0, 1 - 1/(rho ||B_j||)) with
+// B = X - L + Theta * inv_rho and L the L-step's alpha D + beta C[:, labels[j]]
+// (D = X - S + Theta * inv_rho), evaluated as the sweep evaluates it.  Passing
+// fac to launch_sweep_seg then makes its S-step S_j = fac[j] B_j.
+template <typename T>
+void launch_l21_factor(const T* X, int64_t ldx, const T* S, int64_t lds, const T* Th, int64_t ldt,
+                       const T* C, const int32_t* labels, int64_t d, int64_t n, double alpha,
+                       double beta, double rho, double inv_rho, double* fac, hipStream_t st);
 
 
 // Split-d centroid/column dot products: part[(rb*c + k)*n + j] = sum_{i in slice rb} C[i,k] Y[i,j].

@@ -391,29 +391,72 @@ __global__ __launch_bounds__(kBlock) void k_col_sqnorm(const T* C, int64_t d, do
 // workgroups share a band of segments.  Beside L, S, Theta and the norm partials
 // it writes the group sums of D at the next penalty, which let the next
 // iteration skip its means pass when the p-step keeps every label.  Slots past
-// the segment count write zero norms.
-template <typename T, int V>
+// the segment count write zero norms.  L21: column-wise S-step from fac.
+template <typename T, int V, bool L21>
 __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     const T* __restrict__ X, int64_t ldx, T* __restrict__ L, int64_t ldl, T* __restrict__ S,
     int64_t lds, T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
     const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ seg_begin, const int32_t* __restrict__ seg_len,
     const int32_t* __restrict__ nseg, int64_t d, int nrb, T alpha, T beta, T rho, T inv_rho,
-    T inv_rho_next, double* __restrict__ norm_partial, double* __restrict__ next_partial) {
+    T inv_rho_next, double* __restrict__ norm_partial, double* __restrict__ next_partial,
+    const double* __restrict__ fac) {
     const int sg = (int)(blockIdx.x / nrb);
     const int64_t r0 = (int64_t)(blockIdx.x % nrb) * kRowsPerBlock;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (sg < *nseg) {
         const int begin = seg_begin[sg];
-        seg_sweep_tile<T, V, kRowsPerBlock, 1, 4>(X, ldx, L, ldl, S, lds, Th, ldt, C,
-                                                  labels[perm[begin]], d, perm, begin, seg_len[sg],
-                                                  r0, alpha, beta, rho, inv_rho, inv_rho_next, a0,
-                                                  a1, a2, next_partial + (int64_t)sg * d);
+        seg_sweep_tile<T, V, kRowsPerBlock, 1, 4, L21>(X, ldx, L, ldl, S, lds, Th, ldt, C,
+                                                       labels[perm[begin]], d, perm, begin,
+                                                       seg_len[sg], r0, alpha, beta, rho, inv_rho,
+                                                       inv_rho_next, a0, a1, a2,
+                                                       next_partial + (int64_t)sg * d, fac);
     }
     block_sum3(a0, a1, a2);
     if (threadIdx.x == 0) {
         double* o = norm_partial + 3 * (int64_t)blockIdx.x;
         o[0] = a0; o[1] = a1; o[2] = a2;
+    }
+}
+
+// ---------------------------------------------------------- l2,1 factors
+
+// Column-wise S-step (l2,1 penalty), first half: a workgroup per column (grid
+// stride over the columns) sums ||B_j||^2 in
+// double over the column (fixed order: thread stride, then the block sum), with
+// B_j formed in T exactly as the sweep forms it, and stores the block soft
+// threshold factor max(0, 1 - 1/(rho ||B_j||)).
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void k_l21_factor(
+    const T* __restrict__ X, int64_t ldx, const T* __restrict__ S, int64_t lds,
+    const T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
+    const int32_t* __restrict__ labels, int64_t d, int64_t n, T alpha, T beta, T inv_rho,
+    double rho, double* __restrict__ fac) {
+    for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const T* x = X + j * ldx;
+        const T* s = S + j * lds;
+        const T* t = Th + j * ldt;
+        const T* m = C + (int64_t)labels[j] * d;
+        double a = 0.0, b0 = 0.0, c0 = 0.0;
+        for (int64_t i = (int64_t)threadIdx.x * V; i < d; i += (int64_t)kBlock * V) {
+            T xs[V], ss[V], ts[V], ms[V];
+            vload<T, V>(x + i, xs);
+            vload<T, V>(s + i, ss);
+            vload<T, V>(t + i, ts);
+            vload<T, V>(m + i, ms);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const T dv = xs[v] - ss[v] + ts[v] * inv_rho;
+                const T ln = alpha * dv + beta * ms[v];
+                const T b = xs[v] - ln + ts[v] * inv_rho;
+                a += (double)b * (double)b;
+            }
+        }
+        block_sum3(a, b0, c0);   // uniform over the block; safe to repeat per column
+        if (threadIdx.x == 0) {
+            const double nb = sqrt(a);
+            fac[j] = rho * nb > 1.0 ? 1.0 - 1.0 / (rho * nb) : 0.0;
+        }
     }
 }
 
@@ -877,22 +920,40 @@ int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t l
                      const int32_t* seg_begin, const int32_t* seg_len, const int32_t* nseg,
                      int64_t d, int64_t n, int c, double alpha, double beta, double rho,
                      double inv_rho, double inv_rho_next, double* norm_partial,
-                     double* next_partial, hipStream_t st) {
+                     double* next_partial, hipStream_t st, const double* l21_fac) {
     const int nrb = row_blocks(d);
     const unsigned grid = (unsigned)max_segments(n, c) * (unsigned)nrb;
     constexpr int VV = 16 / sizeof(T);
     const int v = pick_vec<T>(d, {{X, ldx}, {L, ldl}, {S, lds}, {Th, ldt}, {C, d}});
-    if (v == VV)
-        k_sweep_seg<T, VV><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, perm,
-                                                    seg_begin, seg_len, nseg, d, nrb, (T)alpha,
-                                                    (T)beta, (T)rho, (T)inv_rho, (T)inv_rho_next,
-                                                    norm_partial, next_partial);
-    else
-        k_sweep_seg<T, 1><<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, perm,
-                                                   seg_begin, seg_len, nseg, d, nrb, (T)alpha,
-                                                   (T)beta, (T)rho, (T)inv_rho, (T)inv_rho_next,
-                                                   norm_partial, next_partial);
+    auto go = [&](auto kern) {
+        kern<<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, perm, seg_begin,
+                                      seg_len, nseg, d, nrb, (T)alpha, (T)beta, (T)rho,
+                                      (T)inv_rho, (T)inv_rho_next, norm_partial, next_partial,
+                                      l21_fac);
+    };
+    if (l21_fac) {
+        if (v == VV) go(k_sweep_seg<T, VV, true>);
+        else go(k_sweep_seg<T, 1, true>);
+    } else {
+        if (v == VV) go(k_sweep_seg<T, VV, false>);
+        else go(k_sweep_seg<T, 1, false>);
+    }
     return (int)grid;
+}
+
+template <typename T>
+void launch_l21_factor(const T* X, int64_t ldx, const T* S, int64_t lds, const T* Th, int64_t ldt,
+                       const T* C, const int32_t* labels, int64_t d, int64_t n, double alpha,
+                       double beta, double rho, double inv_rho, double* fac, hipStream_t st) {
+    constexpr int VV = 16 / sizeof(T);
+    const int v = pick_vec<T>(d, {{X, ldx}, {S, lds}, {Th, ldt}, {C, d}});
+    const unsigned grid = (unsigned)(n < 65536 ? n : 65536);
+    if (v == VV)
+        k_l21_factor<T, VV><<<grid, kBlock, 0, st>>>(X, ldx, S, lds, Th, ldt, C, labels, d, n,
+                                                     (T)alpha, (T)beta, (T)inv_rho, rho, fac);
+    else
+        k_l21_factor<T, 1><<<grid, kBlock, 0, st>>>(X, ldx, S, lds, Th, ldt, C, labels, d, n,
+                                                    (T)alpha, (T)beta, (T)inv_rho, rho, fac);
 }
 
 template <typename T>
@@ -988,7 +1049,10 @@ void launch_gather_cols(const T* Y, int64_t ldy, int64_t d, const int32_t* idx, 
                                      const T*, const int32_t*, const int32_t*, const int32_t*,     \
                                      const int32_t*, const int32_t*, int64_t, int64_t, int,        \
                                      double, double, double, double, double, double*, double*,     \
-                                     hipStream_t);                                                 \
+                                     hipStream_t, const double*);                                  \
+    template void launch_l21_factor<T>(const T*, int64_t, const T*, int64_t, const T*, int64_t,   \
+                                       const T*, const int32_t*, int64_t, int64_t, double, double,  \
+                                       double, double, double*, hipStream_t);                      \
     template void launch_dots<T>(const T*, int64_t, int, const T*, int64_t, int64_t, T*,           \
                                  hipStream_t);                                                     \
     template int launch_argmin<T>(const T*, int, int, int64_t, const double*, const int32_t*,     \

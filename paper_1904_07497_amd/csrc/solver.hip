@@ -83,6 +83,7 @@ respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d
     r.rho_max = p->rho_max;
     r.max_lloyd = p->max_lloyd;
     r.precision = p->precision;
+    r.sparse_norm = p->sparse_norm;
     r.seed = p->seed;
     r.init_labels = p->init_labels;
     r.history = p->history;
@@ -100,6 +101,8 @@ respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d
     if (r.c < 1 || (int64_t)r.c > n) return fail(h, RESPCA_ERR_INVALID, "rank must be in [1, n]");
     if (r.c > kMaxGroups) return fail(h, RESPCA_ERR_UNSUPPORTED, "rank above 1024 is not supported");
     if (!(r.tol >= 0.0)) return fail(h, RESPCA_ERR_INVALID, "tol must be >= 0");
+    if (r.sparse_norm != RESPCA_SPARSE_L1 && r.sparse_norm != RESPCA_SPARSE_L21)
+        return fail(h, RESPCA_ERR_INVALID, "sparse_norm must be RESPCA_SPARSE_L1 or RESPCA_SPARSE_L21");
     if (r.max_iter < 1) return fail(h, RESPCA_ERR_INVALID, "max_iter must be >= 1");
     if (!(r.rho0 > 0.0) || !std::isfinite(r.rho0)) return fail(h, RESPCA_ERR_INVALID, "rho0 must be > 0");
     if (!(r.kappa > 1.0) || !std::isfinite(r.kappa)) return fail(h, RESPCA_ERR_INVALID, "kappa must be > 1");
@@ -388,13 +391,22 @@ struct Engine {
             sort(cur);                                               // Sec. 4.1: groups of D
             group_means(true, X, ldx, S, lds, Th, ldt, (T)inv, C);
         }
+        const double* fac = nullptr;
+        if (r.sparse_norm == RESPCA_SPARSE_L21) {
+            // Sec. 3 alternative penalty: the S-step needs ||B_j|| over the whole column
+            CKS(ensure(h, h->l21f, (size_t)n * sizeof(double)));
+            ProfScope ps(h, st, RESPCA_KERNEL_COLNORM, 3.0 * (double)d * n * sizeof(T));
+            launch_l21_factor<T>(X, ldx, S, lds, Th, ldt, C, cur, d, n, alpha, beta, rho, inv,
+                                 (double*)h->l21f.p, st);
+            fac = (const double*)h->l21f.p;
+        }
         int np = 0;
         {
             ProfScope ps(h, st, RESPCA_KERNEL_SWEEP, 7.0 * (double)d * n * sizeof(T));
             np = launch_sweep_seg<T>(X, ldx, L, ldl, S, lds, Th, ldt, C, cur, perm(),
                                      (const int32_t*)h->segb.p, (const int32_t*)h->segl.p,
                                      (const int32_t*)h->nseg.p, d, n, c, alpha, beta, rho, inv,
-                                     inv_next, (double*)h->normp.p, (double*)h->pmeans.p, st);
+                                     inv_next, (double*)h->normp.p, (double*)h->pmeans.p, st, fac);
         }
         launch_sum_partials((const double*)h->normp.p, np, 3, status, st);
         double first[4];
@@ -645,6 +657,7 @@ void respca_params_default(respca_params* p) {
     p->max_lloyd = 100;
     p->seed = 0;
     p->precision = RESPCA_F32;
+    p->sparse_norm = RESPCA_SPARSE_L1;
     p->init_labels = nullptr;
     p->history = nullptr;
     p->init_embedding = nullptr;

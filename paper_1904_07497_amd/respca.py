@@ -32,7 +32,7 @@ EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_s
 WARM_IN, WARM_OUT = 68, 65
 BATCH_PHASES = ("pack", "init", "seed_distance", "seed_draw", "seed_gather", "sort", "means",
                 "finalize", "sweep", "distance", "argmin", "control")
-KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3, "batched": 4}
+KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3, "batched": 4, "colnorm": 5}
 
 
 class Params(ct.Structure):
@@ -41,7 +41,8 @@ class Params(ct.Structure):
                 ("rho_max", ct.c_double), ("max_lloyd", ct.c_int32), ("seed", ct.c_uint64),
                 ("precision", ct.c_int32), ("init_labels", ct.c_void_p),
                 ("history", ct.POINTER(ct.c_double)), ("init_embedding", ct.c_void_p),
-                ("init_embedding_ld", ct.c_int64), ("init_embedding_rows", ct.c_int32)]
+                ("init_embedding_ld", ct.c_int64), ("init_embedding_rows", ct.c_int32),
+                ("sparse_norm", ct.c_int32)]
 
 
 class Info(ct.Structure):
@@ -151,12 +152,13 @@ def default_params() -> Params:
 
 
 def make_params(rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
-                max_lloyd=100, seed=0, precision=F32) -> Params:
+                max_lloyd=100, seed=0, precision=F32, sparse_norm=0) -> Params:
     p = default_params()
     p.lam = math.nan if lam is None else float(lam)
     p.rank, p.tol, p.max_iter = int(rank), float(tol), int(max_iter)
     p.rho0, p.kappa, p.rho_max = float(rho0), float(kappa), float(rho_max)
     p.max_lloyd, p.seed, p.precision = int(max_lloyd), int(seed) & (2**64 - 1), int(precision)
+    p.sparse_norm = int(sparse_norm)
     return p
 
 
@@ -237,8 +239,9 @@ def _stream(stream):
 
 def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
           max_lloyd=100, seed=0, precision=None, init_labels=None, history=False,
-          out=None, stream=None, init_embedding=None):
-    """RES-PCA of X (d x n column-major tensor).  Returns dict(L, S, labels, info[, history])."""
+          out=None, stream=None, init_embedding=None, sparse_norm=0):
+    """RES-PCA of X (d x n column-major tensor).  Returns dict(L, S, labels, info[, history]).
+    sparse_norm: 0 the l1 penalty on S, 1 the column-wise l2,1 penalty."""
     import torch
     precision = _dtype_precision(X, precision)
     d, n = X.shape
@@ -251,7 +254,8 @@ def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho
         L, S, labels = out
     lp, ldl = _colmajor(L, "L")
     sp, lds = _colmajor(S, "S")
-    p = make_params(rank, lam, tol, max_iter, rho0, kappa, rho_max, max_lloyd, seed, precision)
+    p = make_params(rank, lam, tol, max_iter, rho0, kappa, rho_max, max_lloyd, seed, precision,
+                    sparse_norm)
     hist = None
     if history:
         hist = (ct.c_double * (3 * max_iter))()
@@ -279,7 +283,7 @@ def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho
 
 
 def iterate(X, state: dict, iters=1, rank=None, lam=None, max_lloyd=100, kappa=1.5, rho_max=1e10,
-            precision=None, stream=None):
+            precision=None, stream=None, sparse_norm=0):
     """Run ``iters`` outer iterations in place on ``state`` (device tensors L, S,
     Theta (d x n column-major), labels (int32[n]), C (d x c column-major, ld = d)
     and float rho).  Returns (norms [iters x 3], info)."""
@@ -294,7 +298,8 @@ def iterate(X, state: dict, iters=1, rank=None, lam=None, max_lloyd=100, kappa=1
     lp, ldl = _colmajor(state["L"], "L")
     sp, lds = _colmajor(state["S"], "S")
     tp, ldt = _colmajor(state["Theta"], "Theta")
-    p = make_params(c, lam, 0.0, max(iters, 1), 1e-4, kappa, rho_max, max_lloyd, 0, precision)
+    p = make_params(c, lam, 0.0, max(iters, 1), 1e-4, kappa, rho_max, max_lloyd, 0, precision,
+                    sparse_norm)
     rho = ct.c_double(float(state["rho"]))
     norms = (ct.c_double * (3 * max(iters, 1)))()
     info = Info()
