@@ -120,6 +120,7 @@ def _column_outliers(d, n, c, seed, dtype):
 
 @pytest.mark.parametrize("shape,dtype,precision", [
     ((517, 300, 4), np.float64, rp.F64),
+    ((1000, 257, 3), np.float64, rp.F64),   # even d: the two-wide FP64 vector path
     ((1037, 777, 5), np.float32, rp.F32),
     ((2051, 300, 40), np.float32, rp.BF16GEMM_F32)])
 def test_l21_solve_iteration_locked(shape, dtype, precision):
