@@ -35,6 +35,21 @@ def test_params_default_and_strings():
     assert "gfx950" in rp.version()
 
 
+def test_params_mirror_covers_the_c_struct():
+    """respca_params_default clears sizeof(respca_params) bytes: on a buffer larger
+    than the Python mirror, the bytes past the mirror stay untouched (so the mirror
+    is not smaller than the C struct) and the mirror's last field, sparse_norm,
+    was written (so it is not larger)."""
+    import ctypes as ct
+    size = ct.sizeof(rp.Params)
+    buf = (ct.c_ubyte * (size + 64))(*([0xAB] * (size + 64)))
+    rp.lib().respca_params_default(ct.cast(buf, ct.POINTER(rp.Params)))
+    assert bytes(buf[size:]) == b"\xab" * 64
+    p = rp.Params.from_buffer(buf)
+    assert p.sparse_norm == 0 and p.init_embedding_rows == 0 and p.precision == rp.F32
+    assert rp.KERNELS["colnorm"] == len(rp.KERNELS) - 1
+
+
 def test_null_handle_is_rejected_without_touching_a_device():
     lib = rp.lib()
     p = rp.default_params()
