@@ -600,3 +600,110 @@ def test_adam_first_step_is_lr_times_sign():
     g = np.array([0.3, -2.0, 1e-3, 0.0])
     p1, m, v = mlp.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 0.01, 0.9, 0.999, 1e-8, 1)
     np.testing.assert_allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# Hand-worked network: dims [2, 3, 3, 3, 2] with small integer weights.  The
+# square hidden matrices are not symmetric, so a transposed W changes the
+# result, and the second output of the first row is negative, so a ReLU after
+# the last layer changes it as well.
+_TINY_DIMS = [2, 3, 3, 3, 2]
+_TINY_LAYERS = [
+    ([[1, 0], [0, 1], [1, -1]], [0, 1, 0]),
+    ([[1, 2, 0], [0, 1, -1], [-1, 0, 1]], [0, 0, 1]),
+    ([[0, 1, 0], [1, 0, 1], [2, -1, 0]], [1, 0, -5]),
+    ([[1, -1, 2], [-1, 0, 1]], [0, -5]),
+]
+
+
+def _tiny_params():
+    flat = []
+    for W, b in _TINY_LAYERS:
+        flat += [float(v) for row in W for v in row] + [float(v) for v in b]
+    return np.array(flat)
+
+
+def test_mlp_forward_on_hand_worked_network():
+    """x = (1, 2): layer 1 gives relu(1, 3, -1) = (1, 3, 0); layer 2 relu(7, 3, 0);
+    layer 3 relu(4, 7, 6); output (4 - 7 + 12, -4 + 6 - 5) = (9, -3).
+    x = (-1, 1): (0, 2, 0) -> (4, 2, 1) -> (3, 5, 1) -> (0, -7)."""
+    from oracle import mlp
+    p = _tiny_params()
+    assert p.size == mlp.layer_slices(_TINY_DIMS)[1] == 9 + 12 + 12 + 8
+    y, acts = mlp.forward(p, _TINY_DIMS, np.array([[1.0, 2.0], [-1.0, 1.0]]))
+    np.testing.assert_array_equal(y, [[9.0, -3.0], [0.0, -7.0]])
+    np.testing.assert_array_equal(acts[1], [[1, 3, 0], [0, 2, 0]])
+    np.testing.assert_array_equal(acts[2], [[7, 3, 0], [4, 2, 1]])
+    np.testing.assert_array_equal(acts[3], [[4, 7, 6], [3, 5, 1]])
+
+
+def test_mlp_loss_value_and_gradient_by_hand():
+    """y = ((9, -3), (0, -7)), t = ((8, -1), (0, -7)), last-output weight 3:
+    row 1 gives 1^2 + 3 (-2)^2 = 13, row 2 gives 0, loss 13 / 2; dy = 2 w r / B."""
+    from oracle import mlp
+    y = np.array([[9.0, -3.0], [0.0, -7.0]])
+    t = np.array([[8.0, -1.0], [0.0, -7.0]])
+    loss, dy = mlp.loss_grad(y, t, 3.0)
+    assert loss == 6.5
+    np.testing.assert_array_equal(dy, [[1.0, -6.0], [0.0, 0.0]])
+    # the last output carries the weight, not the first
+    loss_first, _ = mlp.loss_grad(y[:, ::-1], t[:, ::-1], 3.0)
+    assert loss_first == (4.0 + 3.0 * 1.0) / 2
+
+
+def test_mlp_backward_on_hand_worked_network():
+    """Gradient of sum(dy * y) for x = (1, 2), dy = (1, 0): the output weights' row 1
+    receives the last hidden activations (4, 7, 6); layer 3 sees the upstream
+    (1, -1, 2) through all-active units, so its weights get outer((1, -1, 2), (7, 3, 0))."""
+    from oracle import mlp
+    p = _tiny_params()
+    x = np.array([[1.0, 2.0]])
+    y, acts = mlp.forward(p, _TINY_DIMS, x)
+    g = mlp.backward(p, _TINY_DIMS, acts, np.array([[1.0, 0.0]]))
+    sl, _ = mlp.layer_slices(_TINY_DIMS)
+    np.testing.assert_array_equal(g[sl[3][0]], [4, 7, 6, 0, 0, 0])
+    np.testing.assert_array_equal(g[sl[3][1]], [1, 0])
+    np.testing.assert_array_equal(g[sl[2][0]], [7, 3, 0, -7, -3, 0, 14, 6, 0])
+    np.testing.assert_array_equal(g[sl[2][1]], [1, -1, 2])
+
+
+def test_features_of_hand_built_sketch():
+    """d = 4, n = 2, c = 5, column norms (3, 4): s = sqrt(25 / 8) = 5 / (2 sqrt 2) and
+    s sqrt(d) = 5 / sqrt 2, so the projections scale by 8 sqrt(2) / 5 and the norm
+    features are log(3 sqrt(2) / 5) and log(4 sqrt(2) / 5); then log 4 / 8, log 2 / 8,
+    5 / 50."""
+    import math
+    from oracle import mlp
+    Y = np.zeros((65, 2))
+    Y[0] = [1.0, -2.0]
+    Y[63] = [0.5, 0.0]
+    Y[64] = [3.0, 4.0]
+    F = mlp.features(Y, 4, 5)
+    k = 8 * math.sqrt(2) / 5
+    assert F.shape == (2, 68)
+    np.testing.assert_allclose(F[:, 0], [k, -2 * k], rtol=1e-14)
+    np.testing.assert_allclose(F[:, 63], [0.5 * k, 0.0], rtol=1e-14)
+    assert np.all(F[:, 1:63] == 0)
+    np.testing.assert_allclose(F[:, 64], [math.log(3 * math.sqrt(2) / 5),
+                                          math.log(4 * math.sqrt(2) / 5)], rtol=1e-10)
+    np.testing.assert_allclose(F[:, 65], math.log(4) / 8, rtol=1e-15)
+    np.testing.assert_allclose(F[:, 66], math.log(2) / 8, rtol=1e-15)
+    np.testing.assert_allclose(F[:, 67], 0.1, rtol=1e-15)
+
+
+def test_adam_second_and_third_steps_by_hand():
+    """Gradients 2, 4, -2 with beta1 = 1/2, beta2 = 3/4, lr = 0.1, eps = 0:
+    m = 1, 5/2, 1/4 and v = 1, 19/4, 73/16; bias-corrected m = 2, 10/3, 2/7 and
+    v = 4, 76/7, 292/37; steps 0.1 * mh / sqrt(vh)."""
+    import math
+    from oracle import mlp
+    p, m, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    expect_m = [1.0, 2.5, 0.25]
+    expect_v = [1.0, 4.75, 4.5625]
+    expect_p = [-0.1]
+    expect_p.append(expect_p[-1] - 0.1 * (10 / 3) / math.sqrt(76 / 7))
+    expect_p.append(expect_p[-1] - 0.1 * (2 / 7) / math.sqrt(292 / 37))
+    for step, g in enumerate([2.0, 4.0, -2.0], start=1):
+        p, m, v = mlp.adam(p, np.array([g]), m, v, 0.1, 0.5, 0.75, 0.0, step)
+        assert m[0] == pytest.approx(expect_m[step - 1], rel=1e-15)
+        assert v[0] == pytest.approx(expect_v[step - 1], rel=1e-15)
+        assert p[0] == pytest.approx(expect_p[step - 1], rel=1e-14)
