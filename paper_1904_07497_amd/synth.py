@@ -198,3 +198,32 @@ def random_state(X: np.ndarray, c: int, seed: int, s_frac: float = 0.1, s_amp: f
     Lp = (np.asarray(X, np.float64) + 0.1 * _fortran(rng.standard_normal((n, d)))).astype(dt, order="F")
     C = _fortran(rng.standard_normal((c, d))).astype(dt, order="F")
     return {"S": S, "Theta": Theta, "L": Lp, "labels": labels, "C": C}
+
+
+def rings(counts=(60, 90), radii=(1.0, 4.0), d: int = 20, noise: float = 0.02, seed: int = 0,
+          frac: float = 0.0, amp: float = 0.0, dtype=np.float64):
+    """Points on concentric circles (the nonlinear group structure spectral
+    clustering separates and K-means does not), placed in a random 2-D plane of
+    R^d: ring k has counts[k] points at uniform random angles and radius radii[k],
+    plus N(0, noise^2) in every coordinate; optionally a fraction `frac` of the
+    entries replaced by sparse values uniform in [-amp, amp] added on top.
+    Columns are shuffled.  Returns (X (d x n), ring index per column)."""
+    rng = np.random.default_rng(seed)
+    basis, _ = np.linalg.qr(rng.standard_normal((d, 2)))
+    cols, member = [], []
+    for k, (m, r) in enumerate(zip(counts, radii)):
+        ang = rng.uniform(0.0, 2.0 * math.pi, m)
+        pts = np.stack([r * np.cos(ang), r * np.sin(ang)])
+        cols.append(basis @ pts + noise * rng.standard_normal((d, m)))
+        member.append(np.full(m, k, dtype=np.int32))
+    X = np.concatenate(cols, axis=1)
+    ring = np.concatenate(member)
+    perm = rng.permutation(X.shape[1])
+    X, ring = X[:, perm], ring[perm]
+    if frac > 0:
+        k = int(round(frac * X.size))
+        pos = rng.choice(X.size, size=k, replace=False)
+        flat = X.reshape(-1, order="F")
+        flat[pos] += rng.uniform(-amp, amp, k)
+        X = flat.reshape(X.shape, order="F")
+    return np.asfortranarray(X.astype(dtype)), ring
