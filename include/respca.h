@@ -168,6 +168,31 @@ respca_status respca_iterate(respca_handle h, const respca_params *params,
                              double *norms, respca_info *info, void *stream);
 
 /*
+ * respca_iterate without device allocation, for callers that cannot allocate
+ * (code running between graph captures, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results and error codes are those of
+ * respca_iterate; its workspace (label sort tables, group partial sums,
+ * distance partials, Lloyd's moved-column tables, status words) comes from a
+ * fixed device array of RESPCA_NOALLOC_SCRATCH_BYTES per GPU, held by the
+ * library until the process ends, instead of the handle.  A problem whose
+ * workspace would exceed it returns RESPCA_ERR_UNSUPPORTED before any work is
+ * enqueued (respca_last_error gives the bytes needed).  The call does not time
+ * kernels (respca_profile_enable has no effect on it).  Every call on one GPU,
+ * from any handle, uses that GPU's single array and leaves its contents behind:
+ * calls that overlap in time on one GPU race and must be serialised by the
+ * caller.
+ */
+#define RESPCA_NOALLOC_SCRATCH_BYTES (64u << 20)
+respca_status respca_iterate_noalloc(respca_handle h, const respca_params *params,
+                                     int64_t d, int64_t n,
+                                     const void *X, int64_t ldx,
+                                     void *L, int64_t ldl,
+                                     void *S, int64_t lds,
+                                     void *Theta, int64_t ldt,
+                                     int32_t *labels, void *C, double *rho, int32_t iters,
+                                     double *norms, respca_info *info, void *stream);
+
+/*
  * K-means of the columns of Y (d x n, ldy): k-means++ seeding driven by
  * splitmix64(params->seed), nearest-seed assignment, group means (an empty group
  * keeps its seed), then Lloyd passes until no label changes or max_lloyd.

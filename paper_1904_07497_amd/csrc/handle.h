@@ -68,6 +68,12 @@ struct respca_handle_s {
     int64_t bsteps = 0;
     // warm start
     respca::DevBuf wsk, wfeat, wacts, wscratch, wred, wcent, embl, embc, wdesc, whash;
+    // Carving mode of ensure(): while arena_on, buffers are cut from [arena_base,
+    // arena_base + arena_cap) instead of allocated (arena_base may be 0 for a
+    // measuring pass that launches nothing); arena_off is the bytes used so far.
+    bool arena_on = false;
+    char* arena_base = nullptr;
+    size_t arena_cap = 0, arena_off = 0;
 };
 
 #define CK(expr)                                                                            \
@@ -90,6 +96,18 @@ namespace respca {
 inline respca_status ensure(respca_handle h, DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (b.bytes >= bytes) return RESPCA_OK;
+    if (h->arena_on) {   // carve (256-byte aligned); never allocates
+        const size_t off = (h->arena_off + 255) & ~(size_t)255;
+        if (bytes > h->arena_cap || off > h->arena_cap - bytes) {
+            h->arena_off = off + bytes;
+            h->err = "scratch area too small for this problem";
+            return RESPCA_ERR_UNSUPPORTED;
+        }
+        b.p = h->arena_base + off;
+        b.bytes = bytes;
+        h->arena_off = off + bytes;
+        return RESPCA_OK;
+    }
     if (b.p) CK(hipFree(b.p));
     b.p = nullptr;
     b.bytes = 0;

@@ -7,6 +7,7 @@
 #include <type_traits>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -17,9 +18,31 @@
 
 using namespace respca;
 
+// Workspace of respca_iterate_noalloc: a fixed device array, one copy per GPU,
+// held until the process ends.  Host code never passes this name to a kernel
+// (on the host it is only a stand-in for the symbol); it uses the per-device
+// address that respca_create looks up with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[RESPCA_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
-const char* kVersion = "librespca 0.2 (gfx950)";
+const char* kVersion = "librespca 0.3 (gfx950)";
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device (= `device`), looked up
+// once per device.
+respca_status lookup_scratch(respca_handle h, int device) {
+    if (device >= kMaxScratchDevices) return RESPCA_OK;   // the no-alloc call reports it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return RESPCA_OK;
+    void* ptr = nullptr;
+    CK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = (char*)ptr;
+    return RESPCA_OK;
+}
 
 // Event bracket around one launch (no-op unless timing is enabled).
 struct ProfScope {
@@ -30,7 +53,8 @@ struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
     ProfScope(respca_handle h_, hipStream_t st_, int k, double by, double fl = 0.0)
         : h(h_), st(st_), kernel(k), bytes(by), flops(fl) {
-        if (!((h->prof_mask >> kernel) & 1u)) return;
+        // not timed while carving from the fixed scratch area (events are created lazily)
+        if (!((h->prof_mask >> kernel) & 1u) || h->arena_on) return;
         a = take();
         b = take();
         if (a && b) (void)hipEventRecord(a, st);
@@ -160,6 +184,11 @@ struct Engine {
         if (nsum > np) np = nsum;
         CKS(ensure(h, h->normp, 3 * np * sizeof(double)));
         CKS(ensure(h, h->chgp, (size_t)assign_partials_max(n) * sizeof(double)));
+        if (h->arena_on) {   // status words in the scratch area, copied back by readback()
+            CKS(ensure(h, h->status, 8 * sizeof(double)));
+            status = (double*)h->status.p;
+            return RESPCA_OK;
+        }
         CKS(ensure_host(h, (16 + 2 * (size_t)c) * sizeof(double)));
         if (!h->hstatus) {   // status words in pinned host memory: no copy before each readback
             CK(hipHostMalloc((void**)&h->hstatus, 8 * sizeof(double), hipHostMallocMapped));
@@ -169,11 +198,30 @@ struct Engine {
         return RESPCA_OK;
     }
 
+    // Every buffer respca_iterate's steps use (setup, Lloyd's group sums and
+    // moved-column update, the l2,1 factors), at their largest sizes.
+    respca_status reserve_iterate(const Resolved& r) {
+        CKS(setup());
+        double* gs = nullptr;
+        CKS(group_sums(gs));
+        CKS(reserve_update());
+        if (r.sparse_norm == RESPCA_SPARSE_L21) CKS(ensure(h, h->l21f, (size_t)n * sizeof(double)));
+        return RESPCA_OK;
+    }
+
     int32_t* perm() { return (int32_t*)h->perm.p; }
     int32_t* counts() { return (int32_t*)h->counts.p; }
 
     respca_status readback(double out[4]) {
         CK(hipGetLastError());
+        if (h->arena_on) {
+            double w[5];
+            CK(hipMemcpyAsync(w, status, sizeof(w), hipMemcpyDeviceToHost, st));
+            CK(hipStreamSynchronize(st));
+            for (int i = 0; i < 4; ++i) out[i] = w[i];
+            refined += (int64_t)w[4];
+            return RESPCA_OK;
+        }
         CK(hipStreamSynchronize(st));   // the kernels wrote the words themselves
         const volatile double* w = h->hstatus;
         for (int i = 0; i < 4; ++i) out[i] = w[i];
@@ -226,8 +274,7 @@ struct Engine {
     // only the `moved` columns whose label changed (moved <= moved_cap()); the
     // group counts follow.  The sort tables are left as they were (the caller
     // re-sorts before it needs them).
-    respca_status update_means(const T* Y, int64_t ldy, const int32_t* neu, const int32_t* old,
-                               int64_t moved, T* C) {
+    respca_status reserve_update() {
         const int maxs = changed_max_segments(moved_cap(), c);
         CKS(ensure(h, h->cnt2, c * sizeof(int32_t)));
         CKS(ensure(h, h->cbc, (size_t)changed_sort_scratch_ints(n, c) * sizeof(int32_t)));
@@ -237,6 +284,13 @@ struct Engine {
         CKS(ensure(h, h->csegf, (2 * (size_t)c + 1) * sizeof(int32_t)));
         CKS(ensure(h, h->cnseg, sizeof(int32_t)));
         CKS(ensure(h, h->cpart, (size_t)maxs * d * sizeof(double)));
+        return RESPCA_OK;
+    }
+
+    respca_status update_means(const T* Y, int64_t ldy, const int32_t* neu, const int32_t* old,
+                               int64_t moved, T* C) {
+        const int maxs = changed_max_segments(moved_cap(), c);
+        CKS(reserve_update());
         int32_t* cnt2 = (int32_t*)h->cnt2.p;
         launch_changed_sort(neu, old, n, c, (int32_t*)h->cbc.p, counts(), cnt2, (int32_t*)h->cperm.p,
                             (int32_t*)h->csegb.p, (int32_t*)h->csegl.p, (int32_t*)h->csegf.p,
@@ -610,6 +664,10 @@ respca_status respca_create(respca_handle* out, int32_t device) {
         delete h;
         return RESPCA_ERR_HIP;
     }
+    // The scratch address of this device; on failure respca_iterate_noalloc
+    // retries and reports the error, every other entry point works without it.
+    if (lookup_scratch(h, device) != RESPCA_OK) (void)hipGetLastError();
+    h->err.clear();
     *out = h;
     return RESPCA_OK;
 }
@@ -748,15 +806,15 @@ respca_status respca_solve(respca_handle h, const respca_params* params, int64_t
     return s;
 }
 
-respca_status respca_iterate(respca_handle h, const respca_params* params, int64_t d, int64_t n,
-                             const void* X, int64_t ldx, void* L, int64_t ldl, void* S, int64_t lds,
-                             void* Theta, int64_t ldt, int32_t* labels, void* C, double* rho,
-                             int32_t iters, double* norms, respca_info* info, void* stream) {
-    if (!h) return RESPCA_ERR_INVALID;
-    respca_info local{};
-    respca_info* out = info ? info : &local;
-    std::memset(out, 0, sizeof(*out));
-    Resolved r;
+}  // extern "C"
+
+namespace {
+
+// Argument checks of respca_iterate and respca_iterate_noalloc.
+respca_status check_iterate(respca_handle h, const respca_params* params, int64_t d, int64_t n,
+                            const void* X, int64_t ldx, void* L, int64_t ldl, void* S, int64_t lds,
+                            void* Theta, int64_t ldt, int32_t* labels, void* C, double* rho,
+                            int32_t iters, Resolved& r) {
     respca_status s = resolve(h, params, d, n, r);
     if (s == RESPCA_OK) {
         const size_t w = r.precision == RESPCA_F64 ? 8 : 4;
@@ -776,15 +834,123 @@ respca_status respca_iterate(respca_handle h, const respca_params* params, int64
                 s = fail(h, RESPCA_ERR_INVALID, "X, L, S and Theta must not overlap");
         }
     }
+    return s;
+}
+
+respca_status run_iterate(respca_handle h, const Resolved& r, int64_t d, int64_t n, const void* X,
+                          int64_t ldx, void* L, int64_t ldl, void* S, int64_t lds, void* Theta,
+                          int64_t ldt, int32_t* labels, void* C, double* rho, int32_t iters,
+                          double* norms, respca_info* out, hipStream_t st) {
+    if (r.precision == RESPCA_F64)
+        return iterate_t<double>(h, r, d, n, (const double*)X, ldx, (double*)L, ldl, (double*)S,
+                                 lds, (double*)Theta, ldt, labels, (double*)C, rho, iters, norms,
+                                 out, st);
+    return iterate_t<float>(h, r, d, n, (const float*)X, ldx, (float*)L, ldl, (float*)S, lds,
+                            (float*)Theta, ldt, labels, (float*)C, rho, iters, norms, out, st);
+}
+
+// Workspace buffers of the single-solve engine.  While a no-alloc call runs,
+// the handle's own (allocated) buffers are set aside and these point into the
+// scratch area; they are put back when the call returns, so the other entry
+// points never see (or free) scratch memory.
+struct ArenaScope {
+    respca_handle h;
+    std::vector<DevBuf*> bufs;
+    std::vector<DevBuf> saved;
+    explicit ArenaScope(respca_handle h_) : h(h_) {
+        bufs = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
+                &h->nseg, &h->sortbc, &h->pmeans, &h->dots, &h->cnorm, &h->lab_a, &h->lab_b,
+                &h->d2, &h->chosen, &h->seeds, &h->u, &h->normp, &h->chgp, &h->status,
+                &h->l21f, &h->zcopy, &h->zsc, &h->ynorm, &h->gsum, &h->cnt2, &h->cbc,
+                &h->cperm, &h->csegb, &h->csegl, &h->csegf, &h->cnseg, &h->cpart};
+        for (DevBuf* b : bufs) saved.push_back(*b);
+    }
+    // Start carving from base (nullptr: a measuring pass that launches nothing).
+    void begin(char* base, size_t cap) {
+        for (DevBuf* b : bufs) *b = DevBuf{};
+        h->arena_on = true;
+        h->arena_base = base;
+        h->arena_cap = cap;
+        h->arena_off = 0;
+    }
+    ~ArenaScope() {
+        for (size_t i = 0; i < bufs.size(); ++i) *bufs[i] = saved[i];
+        h->arena_on = false;
+        h->arena_base = nullptr;
+        h->arena_cap = 0;
+        h->arena_off = 0;
+    }
+};
+
+template <typename T>
+respca_status reserve_iterate_t(respca_handle h, const Resolved& r, int64_t d, int64_t n) {
+    Engine<T> e{h, nullptr, d, n, r.c, r.precision == RESPCA_BF16GEMM_F32};
+    return e.reserve_iterate(r);
+}
+
+}  // namespace
+
+extern "C" {
+
+respca_status respca_iterate(respca_handle h, const respca_params* params, int64_t d, int64_t n,
+                             const void* X, int64_t ldx, void* L, int64_t ldl, void* S, int64_t lds,
+                             void* Theta, int64_t ldt, int32_t* labels, void* C, double* rho,
+                             int32_t iters, double* norms, respca_info* info, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    respca_info local{};
+    respca_info* out = info ? info : &local;
+    std::memset(out, 0, sizeof(*out));
+    Resolved r;
+    respca_status s = check_iterate(h, params, d, n, X, ldx, L, ldl, S, lds, Theta, ldt, labels, C,
+                                    rho, iters, r);
     if (s == RESPCA_OK) s = bind_device(h);
+    if (s == RESPCA_OK)
+        s = run_iterate(h, r, d, n, X, ldx, L, ldl, S, lds, Theta, ldt, labels, C, rho, iters,
+                        norms, out, (hipStream_t)stream);
+    out->status = s;
+    return s;
+}
+
+respca_status respca_iterate_noalloc(respca_handle h, const respca_params* params, int64_t d,
+                                     int64_t n, const void* X, int64_t ldx, void* L, int64_t ldl,
+                                     void* S, int64_t lds, void* Theta, int64_t ldt,
+                                     int32_t* labels, void* C, double* rho, int32_t iters,
+                                     double* norms, respca_info* info, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    respca_info local{};
+    respca_info* out = info ? info : &local;
+    std::memset(out, 0, sizeof(*out));
+    Resolved r;
+    respca_status s = check_iterate(h, params, d, n, X, ldx, L, ldl, S, lds, Theta, ldt, labels, C,
+                                    rho, iters, r);
+    if (s == RESPCA_OK) s = bind_device(h);
+    if (s == RESPCA_OK && h->device >= kMaxScratchDevices)
+        s = fail(h, RESPCA_ERR_UNSUPPORTED, "no scratch area for device ordinals above 63");
+    if (s == RESPCA_OK) s = lookup_scratch(h, h->device);
     if (s == RESPCA_OK) {
-        hipStream_t st = (hipStream_t)stream;
-        if (r.precision == RESPCA_F64)
-            s = iterate_t<double>(h, r, d, n, (const double*)X, ldx, (double*)L, ldl, (double*)S, lds,
-                                  (double*)Theta, ldt, labels, (double*)C, rho, iters, norms, out, st);
-        else
-            s = iterate_t<float>(h, r, d, n, (const float*)X, ldx, (float*)L, ldl, (float*)S, lds,
-                                 (float*)Theta, ldt, labels, (float*)C, rho, iters, norms, out, st);
+        char* base = nullptr;
+        {
+            std::lock_guard<std::mutex> lock(g_scratch_mu);
+            base = g_scratch_ptr[h->device];
+        }
+        ArenaScope arena(h);
+        // measure first, so that a problem too large fails before any work is enqueued
+        arena.begin(nullptr, ~(size_t)0 >> 1);
+        s = r.precision == RESPCA_F64 ? reserve_iterate_t<double>(h, r, d, n)
+                                      : reserve_iterate_t<float>(h, r, d, n);
+        const size_t need = h->arena_off;
+        if (s == RESPCA_OK && need > (size_t)RESPCA_NOALLOC_SCRATCH_BYTES)
+            s = fail(h, RESPCA_ERR_UNSUPPORTED,
+                     "problem needs " + std::to_string(need) + " bytes of scratch, the maximum is " +
+                         std::to_string((size_t)RESPCA_NOALLOC_SCRATCH_BYTES));
+        if (s == RESPCA_OK) {
+            arena.begin(base, RESPCA_NOALLOC_SCRATCH_BYTES);
+            s = r.precision == RESPCA_F64 ? reserve_iterate_t<double>(h, r, d, n)
+                                          : reserve_iterate_t<float>(h, r, d, n);
+        }
+        if (s == RESPCA_OK)
+            s = run_iterate(h, r, d, n, X, ldx, L, ldl, S, lds, Theta, ldt, labels, C, rho, iters,
+                            norms, out, (hipStream_t)stream);
     }
     out->status = s;
     return s;

@@ -24,6 +24,7 @@ F64, F32, BF16GEMM_F32 = 0, 1, 2
 # Every symbol include/respca.h declares.
 EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_status_string",
            "respca_last_error", "respca_version", "respca_solve", "respca_iterate",
+           "respca_iterate_noalloc",
            "respca_kmeans", "respca_profile_enable", "respca_profile_query",
            "respca_solve_batched", "respca_autotune_batched", "respca_profile_batched_phases",
            "respca_mlp_param_count", "respca_mlp_act_count", "respca_sketch", "respca_features",
@@ -90,6 +91,8 @@ def lib():
         L.respca_iterate.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, i64, vp, i64,
                                      vp, i64, vp, vp, ct.POINTER(ct.c_double), i32,
                                      ct.POINTER(ct.c_double), ct.POINTER(Info), vp]
+        L.respca_iterate_noalloc.restype = i32
+        L.respca_iterate_noalloc.argtypes = L.respca_iterate.argtypes
         L.respca_profile_enable.restype = i32
         L.respca_profile_enable.argtypes = [vp, i32]
         L.respca_profile_query.restype = i32
@@ -283,10 +286,11 @@ def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho
 
 
 def iterate(X, state: dict, iters=1, rank=None, lam=None, max_lloyd=100, kappa=1.5, rho_max=1e10,
-            precision=None, stream=None, sparse_norm=0):
+            precision=None, stream=None, sparse_norm=0, noalloc=False):
     """Run ``iters`` outer iterations in place on ``state`` (device tensors L, S,
     Theta (d x n column-major), labels (int32[n]), C (d x c column-major, ld = d)
-    and float rho).  Returns (norms [iters x 3], info)."""
+    and float rho).  Returns (norms [iters x 3], info).  noalloc: call
+    respca_iterate_noalloc (workspace from the library's fixed scratch area)."""
     import numpy as np
     precision = _dtype_precision(X, precision)
     d, n = X.shape
@@ -304,10 +308,10 @@ def iterate(X, state: dict, iters=1, rank=None, lam=None, max_lloyd=100, kappa=1
     norms = (ct.c_double * (3 * max(iters, 1)))()
     info = Info()
     h = handle(X.device.index or 0)
-    s = lib().respca_iterate(h._h, ct.byref(p), d, n, xp, ldx, lp, ldl, sp, lds, tp, ldt,
-                             state["labels"].data_ptr(), C.data_ptr(), ct.byref(rho), int(iters),
-                             ct.cast(norms, ct.POINTER(ct.c_double)), ct.byref(info),
-                             _stream(stream))
+    fn = lib().respca_iterate_noalloc if noalloc else lib().respca_iterate
+    s = fn(h._h, ct.byref(p), d, n, xp, ldx, lp, ldl, sp, lds, tp, ldt,
+           state["labels"].data_ptr(), C.data_ptr(), ct.byref(rho), int(iters),
+           ct.cast(norms, ct.POINTER(ct.c_double)), ct.byref(info), _stream(stream))
     h.check(s)
     state["rho"] = rho.value
     return np.ctypeslib.as_array(norms)[: 3 * iters].reshape(-1, 3).copy(), info.as_dict()
