@@ -3,7 +3,9 @@ CPU checker timed beside it.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload large]
                     [--precision bf16|fp32] [--no-compare] [--no-cpu-baseline]
-                    [--tune-cache FILE] [--calibrate-copy]
+                    [--tune-cache FILE] [--calibrate-copy] [--calibrate-mix] [--no-accuracy]
+    python bench.py --workload small          (500 x 500 FP64, compared with the oracle)
+    python bench.py --summarize-counters UNIT WORKLOAD ROOT   (no GPU)
 
 A step is one whole RES-PCA solve (initial K-means of X, then outer ALM
 iterations L -> p -> S -> Theta/rho until the Sec. 5 criterion <= tol) of
@@ -61,6 +63,16 @@ WORKLOADS = {
                            "lambda=0.01, tol=1e-6, column-wise l2,1 penalty on S (the alternative "
                            "norm of Sec. 3) in place of l1", d=10000, n=10000, rank=100, lam=0.01,
                       tol=1e-6, gen="large", sparse_norm=1),
+    "small": dict(name="RES-PCA FP64 500x500 rank-25 (U, V iid N(0,1)) + 5% sparse in [-50,50], c=25, "
+                       "lambda=1/sqrt(500), tol=1e-7; seeds 0-4, each solve compared with the FP64 "
+                       "oracle's whole solve", d=500, n=500, rank=25, lam=1.0 / 500 ** 0.5, tol=1e-7,
+                  seeds=(0, 1, 2, 3, 4), gen="small"),
+    "spectral": dict(name="RES-PCA FP32 with the spectral-clustering p-step (Sec. 4.2 nonlinear "
+                          "alternative): 3 concentric rings (radii 1, 3, 6; 2000, 2500, 3500 points) in "
+                          "a random plane of R^2000, N(0, 0.02^2) noise, 1% of entries offset by "
+                          "U[-1, 1], c=3, sigma=0.7, lambda=0.2, tol=1e-6", d=2000,
+                     counts=(2000, 2500, 3500), radii=(1.0, 3.0, 6.0), rank=3, sigma=0.7, lam=0.2,
+                     tol=1e-6, gen="spectral"),
     "scaling": dict(name="scalability (Sec. 5): seeded random subsets of the synthetic 240x320x2000 "
                          "clip at ratios 1/8, 1/4, 1/2, 1 of n (all d) and of d (all n), c=5, "
                          "lambda=sqrt(max(d,n)), 30 outer iterations (no tolerance), 10 runs each",
@@ -114,6 +126,91 @@ def make_input(wl, dtype):
     return X
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cores() -> int:
+    """CPU cores this process may run on (the oracle itself is single-threaded)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def timed_oracle_solve(X64, c, lam, tol, seed=0):
+    """One whole FP64 oracle solve, timed (one thread)."""
+    import oracle
+    t = time.perf_counter()
+    o = oracle.solve(X64, oracle.make_params(c, lam=lam, tol=tol, seed=seed))
+    return {"seconds": round(time.perf_counter() - t, 3), "iters": o["info"]["iters"],
+            "shape": list(X64.shape), "c": c}
+
+
+def accuracy_vs_oracle(rp, Xd, X, wl, prec, T, final_L, sample=64, seed=0):
+    """Error of the solve's last iteration against the FP64 oracle: the GPU
+    trajectory is replayed to iterate T-1 (respca_kmeans + respca_iterate, the
+    same kernels in the same order as respca_solve), the oracle then takes the
+    last iteration from that state at `sample` seeded columns (group means over
+    every column, then per column L, S, Theta) and the GPU its last iteration;
+    relative Frobenius errors over the sampled columns, labels compared where
+    the oracle's nearest and second-nearest centroid distances are clear of the
+    FP32 rounding of the distance computation."""
+    import numpy as np
+    import torch
+    import oracle
+    d, n = X.shape
+    c = wl["rank"]
+    labels, C, _ = rp.kmeans(Xd, c, seed=seed, max_lloyd=100, precision=prec)
+    st = {"L": rp.empty_colmajor(d, n, Xd.dtype, Xd.device).zero_(),
+          "S": rp.empty_colmajor(d, n, Xd.dtype, Xd.device).zero_(),
+          "Theta": rp.empty_colmajor(d, n, Xd.dtype, Xd.device).zero_(),
+          "labels": labels, "C": C, "rho": 1e-4}
+    if T > 1:
+        rp.iterate(Xd, st, iters=T - 1, lam=wl["lam"], max_lloyd=100, precision=prec,
+                   sparse_norm=wl.get("sparse_norm", 0))
+    host = {k: (np.asfortranarray(v.cpu().numpy().astype(np.float64)) if torch.is_tensor(v)
+                and v.dtype != torch.int32 else (v.cpu().numpy() if torch.is_tensor(v) else v))
+            for k, v in st.items()}
+    rho_t = st["rho"]
+    rp.iterate(Xd, st, iters=1, lam=wl["lam"], max_lloyd=1, precision=prec,
+               sparse_norm=wl.get("sparse_norm", 0))
+    replay_diff = float(torch.linalg.norm(st["L"].double() - final_L.double()) /
+                        torch.linalg.norm(final_L.double()))
+    rng = np.random.default_rng(seed)
+    sel = np.unique(np.concatenate([[0, n - 1], rng.choice(n, sample - 2, replace=False)]))
+    t = time.perf_counter()
+    o = oracle.step_columns(oracle.make_params(c, lam=wl["lam"], max_lloyd=1,
+                                               sparse_norm=wl.get("sparse_norm", 0)),
+                            np.asfortranarray(X.astype(np.float64)), host, sel)
+    t_or = time.perf_counter() - t
+    idx = torch.from_numpy(sel).to(Xd.device)
+
+    def rel(g, ref):
+        g = np.asarray(g.index_select(1, idx).double().cpu().numpy())
+        den = np.linalg.norm(ref)
+        return float(np.linalg.norm(g - ref) / (den if den > 0 else 1.0))
+
+    mu = o["mu"]
+    dist = ((o["L"][:, :, None] - mu[:, None, :]) ** 2).sum(axis=0)
+    srt = np.sort(dist, axis=1)
+    cn = np.sqrt((mu ** 2).sum(axis=0)).max()
+    ln = np.sqrt((o["L"] ** 2).sum(axis=0))
+    sep = (srt[:, 1] - srt[:, 0]) > 2 * d * np.finfo(np.float32).eps * (cn ** 2 + 2 * cn * ln + ln ** 2)
+    lab = st["labels"].cpu().numpy()[sel]
+    Xsel = X[:, sel].astype(np.float64)
+    dth = st["Theta"].index_select(1, idx).double().cpu().numpy() / rho_t - o["Theta"] / rho_t
+    return {"rel_err_L": rel(st["L"], o["L"]), "rel_err_S": rel(st["S"], o["S"]),
+            "err_Theta_over_rho_vs_X": float(np.linalg.norm(dth) / np.linalg.norm(Xsel)),
+            "labels_equal_on_separated": int((lab == o["labels"])[sep].sum()),
+            "separated_columns": int(sep.sum()), "columns": int(sel.size),
+            "replayed_L_vs_timed_solve": replay_diff, "oracle_seconds": round(t_or, 2),
+            "how": (f"last iteration ({T}) of the timed solve's trajectory, replayed on the GPU to "
+                    f"iterate {T - 1}; the FP64 oracle takes iteration {T} from that state at "
+                    f"{sel.size} seeded columns (group means over all columns)")}
+
+
 def cpu_baseline(X, wl, gpu_info):
     """Time the FP64 CPU checker on one outer iteration of the same workload and
     scale to one whole solve with the iteration / pass counts of the GPU solve."""
@@ -149,7 +246,7 @@ def cpu_baseline(X, wl, gpu_info):
               f"solve time = {c}*seed pass + {il + 1} init assignment+centroid passes + {it} "
               f"iterations + {ll - it} extra Lloyd passes (counts of the GPU solve) = {t_solve:.1f} s")
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": sample}
+            "sample": sample, "host_cores_available": host_cores()}
 
 
 def batched_cpu_baseline(Xh_median, c_median, lam_median, shapes, ranks, infos, count):
@@ -178,6 +275,8 @@ def batched_cpu_baseline(Xh_median, c_median, lam_median, shapes, ranks, infos, 
         total += (ci * td + (f["init_lloyd"] + 1) * (ta + tm) + f["iters"] * (tb + ta)
                   + (f["lloyd_steps"] - f["iters"]) * (ta + tm))
     return {"value": count / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cores_available": host_cores(),
+            "median_instance_whole_solve": timed_oracle_solve(X64, c, lam_median, 1e-6),
             "sample": (f"FP64 oracle on the median instance ({d}x{n}, c={c}): one outer iteration "
                        f"{t_step:.3f} s, one assignment pass {t_assign:.3f} s, one centroid pass "
                        f"{t_mean:.4f} s, one k-means++ distance pass {t_d2:.4f} s; every instance's "
@@ -400,6 +499,86 @@ def calibrate_copy(args):
                       "launches": max(args.steps, 1)}), flush=True)
 
 
+def calibrate_mix(args):
+    """Practical bandwidth ceilings: the library's streaming probe over 1 GiB
+    arrays for the read/write mixes of the method's passes."""
+    from paper_1904_07497_amd import respca as rp
+    mixes = [(1, 0, "streaming read"), (1, 1, "copy"), (3, 0, "means pass (X, S, Theta)"),
+             (3, 1, "3 reads + 1 write"), (4, 3, "sweep (X, S, Theta, L in; L, S, Theta out)")]
+    out = []
+    for r, w, what in mixes:
+        gbps, ms = rp.bandwidth_probe(r, w, 1 << 30, reps=max(args.steps, 5))
+        out.append({"reads": r, "writes": w, "what": what, "GBps": round(gbps, 1),
+                    "frac_of_8TBps": round(gbps / HBM_PEAK_GBS, 4), "ms_per_launch": round(ms, 4)})
+    print(json.dumps({"bandwidth_probe": out, "bytes_per_array": 1 << 30,
+                      "reps": max(args.steps, 5)}), flush=True)
+
+
+# kernels (name prefixes) that make up each profiled unit, for the counter summaries
+UNIT_KERNELS = {
+    "sweep": ("k_sweep_seg",),
+    "means": ("k_group_partial",),
+    "distance": ("k_split_centroids", "k_dist_", "k_refine_", "k_assign_finish", "k_argmin",
+                 "k_col_sqnorm", "respca::k_assign_finish"),
+    "colnorm": ("k_l21_factor",),
+    "batched": ("k_batched",),
+}
+
+
+def read_counter_csvs(root):
+    """Mean counter value per (kernel, counter) over the dispatches in every
+    *counter_collection.csv under `root` (rocprofv3 --pmc -f csv output)."""
+    import csv
+    sums, counts = {}, {}
+    for dirpath, _, files in os.walk(root):
+        for fn in files:
+            if not fn.endswith("counter_collection.csv"):
+                continue
+            with open(os.path.join(dirpath, fn)) as f:
+                for row in csv.DictReader(f):
+                    key = (row["Kernel_Name"], row["Counter_Name"])
+                    sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+                    counts[key] = counts.get(key, 0) + 1
+    return {k: (sums[k] / counts[k], counts[k]) for k in sums}
+
+
+def summarize_counters(unit, workload, root):
+    """Per-launch HBM bytes of one unit from FETCH_SIZE / WRITE_SIZE counter runs
+    (root/{copy,<workload>}_{FETCH_SIZE,WRITE_SIZE}), each scaled by what the same
+    counter reads for the 1 GiB device copy of --calibrate-copy; writes
+    profiles/traffic_<unit>_<workload>.json with the hash of the unit's sources."""
+    def one(sub, counter):
+        vals = read_counter_csvs(os.path.join(root, f"{sub}_{counter}"))
+        return {k[0]: v for k, v in vals.items() if k[1] == counter}
+
+    factors = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        copy = [v for k, v in one("copy", counter).items() if "copyBuffer" in k]
+        if not copy:
+            raise SystemExit(f"no copy kernel in {root}/copy_{counter}")
+        factors[counter] = (1 << 30) / (copy[0][0] * 1024.0)
+    fetch, write = one(workload, "FETCH_SIZE"), one(workload, "WRITE_SIZE")
+    parts, total = [], 0.0
+    for name in sorted(fetch):
+        if not any(name.startswith(p) for p in UNIT_KERNELS[unit]):
+            continue
+        fb = fetch[name][0] * 1024.0 * factors["FETCH_SIZE"]
+        wb = write.get(name, (0.0, 0))[0] * 1024.0 * factors["WRITE_SIZE"]
+        parts.append({"kernel": name, "dispatches": fetch[name][1],
+                      "fetch_kib_per_dispatch": round(fetch[name][0], 1),
+                      "write_kib_per_dispatch": round(write.get(name, (0.0, 0))[0], 1),
+                      "fetch_bytes_per_dispatch": int(fb), "write_bytes_per_dispatch": int(wb)})
+        total += fb + wb
+    rec = {"kernel": unit, "workload": workload, "bytes_per_launch": int(total),
+           "fetch_factor": round(factors["FETCH_SIZE"], 5),
+           "write_factor": round(factors["WRITE_SIZE"], 5),
+           "kernel_source_sha": kernel_source_sha(unit), "parts": parts}
+    path = os.path.join(ROOT, "profiles", f"traffic_{unit}_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -411,11 +590,21 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the other precision in the same run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the last-iteration comparison with the FP64 oracle")
     ap.add_argument("--tune-cache", default=None,
                     help="batched tile-shape cache file (read if it holds the shape bucket, else written)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--calibrate-mix", action="store_true",
+                    help="run only the streaming bandwidth probe for the passes' read/write mixes")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("UNIT", "WORKLOAD", "ROOT"),
+                    help="write profiles/traffic_UNIT_WORKLOAD.json from FETCH_SIZE/WRITE_SIZE "
+                         "counter runs under ROOT (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
               f"single MI355X; see the sharding notes in the design document)", file=sys.stderr)
@@ -429,6 +618,9 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args)
         return
+    if args.calibrate_mix:
+        calibrate_mix(args)
+        return
     wl = WORKLOADS[args.workload]
     if wl["gen"] == "batched":
         bench_batched(args, wl)
@@ -438,6 +630,12 @@ def main():
         return
     if wl["gen"] == "scaling":
         bench_scaling(args, wl)
+        return
+    if wl["gen"] == "small":
+        bench_small(args, wl)
+        return
+    if wl["gen"] == "spectral":
+        bench_spectral(args, wl)
         return
     X = make_input(wl, np.float32)
     Xd = torch.from_numpy(X).to("cuda:0")
@@ -495,6 +693,15 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(name, args.workload),
                 "kernel": name, "bytes_per_launch": bpl, "mean_launch_ms": round(secs * 1e3, 4)}
 
+    def sweep_with_ceiling(r, rp, array_bytes):
+        """The sweep's figure beside the measured ceiling of its 4-read/3-write mix
+        (the library's streaming probe over arrays of the sweep's size)."""
+        gbps, _ = rp.bandwidth_probe(4, 3, (array_bytes // 16) * 16, reps=10)
+        r = dict(r)
+        r["ceiling_4r3w_GBps"] = round(gbps, 1)
+        r["frac_of_ceiling"] = round(r["achieved"] / gbps, 4) if gbps > 0 else None
+        return r
+
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                    "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
                    "TFLOPs": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["ms"] > 0 and v["flops"] else None}
@@ -519,7 +726,7 @@ def main():
                    "iters": infos[-1]["iters"], "lloyd_steps": infos[-1]["lloyd_steps"],
                    "init_lloyd": infos[-1]["init_lloyd"], "refined_columns": infos[-1]["refined"]},
         "sweep_GBps": roofline_of("sweep")["achieved"],
-        "sweep_roofline": roofline_of("sweep"),
+        "sweep_roofline": sweep_with_ceiling(roofline_of("sweep"), rp, d * n * 4),
         "kernels": kernels,
         "kernels_note": "per-unit event times of one extra solve with every unit timed",
         "roofline": roofline_of(dom),
@@ -547,8 +754,192 @@ def main():
     if wl.get("sparse_norm", 0):
         line["config"]["sparse_norm"] = "l2,1"
         line["colnorm_roofline"] = roofline_of("colnorm")
+    if not args.no_accuracy:
+        prec = rp.BF16GEMM_F32 if args.precision == "bf16" else rp.F32
+        line["accuracy_vs_oracle"] = accuracy_vs_oracle(rp, Xd, X, wl, prec, infos[-1]["iters"],
+                                                        out[0])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, wl, infos[-1])
+    print(json.dumps(line), flush=True)
+
+
+def bench_spectral(args, wl):
+    """Whole solves with the spectral p-step; the dominant kernels are the affinity
+    (Gram matrix on FP64 MFMA, 2 n^2 d flops) and the eigen block products."""
+    import numpy as np
+    import torch
+    import oracle
+    from oracle import spectral as osp
+    from paper_1904_07497_amd import respca as rp
+    from paper_1904_07497_amd import synth
+
+    X, ring = synth.rings(counts=wl["counts"], radii=wl["radii"], d=wl["d"], noise=0.02, seed=5,
+                          frac=0.01, amp=1.0, dtype=np.float32)
+    d, n = X.shape
+    Xd = torch.from_numpy(X).to("cuda:0")
+    kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=rp.F32,
+              pstep=rp.PSTEP_SPECTRAL, sigma=wl["sigma"])
+    out = (rp.empty_colmajor(d, n, Xd.dtype, Xd.device), rp.empty_colmajor(d, n, Xd.dtype, Xd.device),
+           torch.empty(n, dtype=torch.int32, device=Xd.device))
+    for _ in range(max(args.warmup, 1)):
+        info = rp.solve(Xd, out=out, **kw)["info"]
+        progress(f"spectral warm-up solve: {info['iters']} iterations, {info['eig_iters']} "
+                 f"eigen iterations")
+    torch.cuda.synchronize()
+    rp.profile_enable(True, units=["affinity", "eigen", "sweep"])
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        info = rp.solve(Xd, out=out, **kw)["info"]
+        progress(f"spectral timed solve {i + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = rp.profile_query()
+    rp.profile_enable(False)
+    lab = out[2].cpu().numpy()
+    recovered = bool(np.array_equal(lab == lab[0], ring == ring[0]) or
+                     all(len(set(lab[ring == r])) == 1 for r in range(len(wl["counts"]))))
+
+    def unit(name, peak, unit_name, use_flops):
+        k = prof[name]
+        nl = max(k["launches"], 1)
+        secs = k["ms"] / 1e3 / nl
+        per = (k["flops"] if use_flops else k["bytes"]) / nl
+        ach = per / secs / (1e12 if use_flops else 1e9) if secs > 0 else 0.0
+        return {"bound": "mfma" if use_flops else "hbm", "achieved": round(ach, 2), "peak": peak,
+                "unit": unit_name, "frac": round(ach / peak, 4), "traffic": None, "kernel": name,
+                ("flops_per_launch" if use_flops else "bytes_per_launch"): per,
+                "launches": k["launches"], "mean_launch_ms": round(secs * 1e3, 4)}
+
+    line = {
+        "metric": "RPCA solves/s + sweep HBM GB/s at rel-err<=1e-5 (BF16/learned vs plain FP32)",
+        "value": round(args.steps / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(args.warmup, 1),
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "d": d, "n": n, "c": wl["rank"], "iters": info["iters"],
+                   "lloyd_steps": info["lloyd_steps"], "eig_iters": info["eig_iters"],
+                   "eig_unconverged": info["eig_unconverged"], "rings_recovered": recovered},
+        "roofline": unit("affinity", 78.6, "TFLOP/s", True),
+        "eigen_roofline": unit("eigen", HBM_PEAK_GBS, "GB/s", False),
+        "sweep_roofline": unit("sweep", HBM_PEAK_GBS, "GB/s", False),
+    }
+    progress("spectral GPU part done; CPU baseline")
+    if not args.no_cpu_baseline:
+        # the FP64 oracle's spectral p-step (affinity, normalisation, dense eigensolver,
+        # Lloyd on the rows) on a 1200-column subset, scaled to n columns by n^2 d for
+        # the affinity and n^3 for the eigensolver
+        rng = np.random.default_rng(0)
+        m = 1200
+        sub = np.asfortranarray(X[:, np.sort(rng.choice(n, m, replace=False))].astype(np.float64))
+        t = time.perf_counter()
+        W = osp.affinity(sub, wl["sigma"])
+        t_aff = time.perf_counter() - t
+        t = time.perf_counter()
+        A, _ = osp.normalized_affinity(W)
+        np.linalg.eigh(A)
+        t_eig = time.perf_counter() - t
+        scale2, scale3 = (n / m) ** 2, (n / m) ** 3
+        per_pstep = t_aff * scale2 + t_eig * scale3
+        sweep_s = 0.0
+        st = {"L": np.zeros((d, m), order="F"), "S": np.zeros((d, m), order="F"),
+              "Theta": np.zeros((d, m), order="F"), "labels": (np.arange(m) % wl["rank"]).astype(np.int32),
+              "C": np.zeros((d, wl["rank"]), order="F"), "rho": 1e-4}
+        t = time.perf_counter()
+        oracle.step(oracle.make_params(wl["rank"], lam=wl["lam"], max_lloyd=1), sub, st)
+        sweep_s = (time.perf_counter() - t) * (n / m)
+        total = (info["iters"] + 1) * per_pstep + info["iters"] * sweep_s
+        line["cpu_baseline"] = {"value": 1.0 / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                "host_cores_available": host_cores(),
+                                "sample": (f"FP64 oracle on a {m}-column subset: affinity {t_aff:.2f} s, "
+                                           f"normalisation + dense eigensolver {t_eig:.2f} s, one K-means "
+                                           f"outer iteration {sweep_s * m / n:.2f} s; scaled to n={n} by "
+                                           f"n^2 (affinity), n^3 (eigensolver) and n (iteration), times "
+                                           f"{info['iters'] + 1} spectral clusterings and {info['iters']} "
+                                           f"iterations = {total:.0f} s")}
+    print(json.dumps(line), flush=True)
+
+
+def bench_small(args, wl):
+    """The 500 x 500 FP64 configuration: whole solves of five seeded inputs per
+    step (latency-bound: 47 iterations of a 2 MB problem), each compared with the
+    FP64 oracle's whole solve of the same input."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1904_07497_amd import respca as rp
+    from paper_1904_07497_amd import synth
+
+    Xh = [synth.config_small(s)[0] for s in wl["seeds"]]
+    Xs = [torch.from_numpy(X).to("cuda:0") for X in Xh]
+    kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=rp.F64)
+    outs = [(rp.empty_colmajor(500, 500, torch.float64, "cuda:0"),
+             rp.empty_colmajor(500, 500, torch.float64, "cuda:0"),
+             torch.empty(500, dtype=torch.int32, device="cuda:0")) for _ in Xs]
+    for _ in range(max(args.warmup, 1)):
+        for X, o in zip(Xs, outs):
+            rp.solve(X, out=o, **kw)
+    torch.cuda.synchronize()
+    rp.profile_enable(True, units=["sweep"])
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = [rp.solve(X, out=o, **kw)["info"] for X, o in zip(Xs, outs)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = rp.profile_query()["sweep"]
+    rp.profile_enable(False)
+    acc = []
+    t_or = 0.0
+    for X, o, inf in zip(Xh, outs, infos):
+        t = time.perf_counter()
+        ref = oracle.solve(X, oracle.make_params(wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0))
+        t_or += time.perf_counter() - t
+        nL = np.linalg.norm(ref["L"])
+        nS = np.linalg.norm(ref["S"])
+        acc.append({"rel_err_L": float(np.linalg.norm(o[0].cpu().numpy() - ref["L"]) / nL),
+                    "rel_err_S": float(np.linalg.norm(o[1].cpu().numpy() - ref["S"]) / nS),
+                    "labels_equal": bool(np.array_equal(o[2].cpu().numpy(), ref["labels"])),
+                    "iters": inf["iters"], "oracle_iters": ref["info"]["iters"]})
+    count = len(Xs) * args.steps
+    nl = max(prof["launches"], 1)
+    secs = prof["ms"] / 1e3 / nl
+    ach = prof["bytes"] / nl / secs / 1e9 if secs > 0 else 0.0
+    line = {
+        "metric": "RPCA solves/s + sweep HBM GB/s at rel-err<=1e-5 (BF16/learned vs plain FP32)",
+        "value": round(count / elapsed, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(args.warmup, 1),
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "d": 500, "n": 500, "c": wl["rank"],
+                   "solves_per_step": len(Xs), "iters": [a["iters"] for a in acc]},
+        "accuracy_vs_oracle": {"max_rel_err_L": max(a["rel_err_L"] for a in acc),
+                               "max_rel_err_S": max(a["rel_err_S"] for a in acc),
+                               "labels_equal": all(a["labels_equal"] for a in acc),
+                               "iters_equal": all(a["iters"] == a["oracle_iters"] for a in acc),
+                               "how": "whole GPU solve vs whole FP64 oracle solve, each seed"},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "sweep",
+                     "bytes_per_launch": prof["bytes"] / nl, "mean_launch_ms": round(secs * 1e3, 4),
+                     "note": "a 500 x 500 FP64 sweep moves 14 MB: launch latency, not HBM, bounds it"},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = {"value": round(len(Xh) / t_or, 4), "unit": "solves/s", "cores": 1,
+                                "kind": "oracle", "host_cores_available": host_cores(),
+                                "sample": (f"whole FP64 oracle solves of the same {len(Xh)} inputs, "
+                                           f"timed ({t_or:.2f} s in total)")}
     print(json.dumps(line), flush=True)
 
 

@@ -69,6 +69,24 @@ typedef enum {
     RESPCA_SPARSE_L21 = 1
 } respca_sparse_norm;
 
+/* How the p-step finds the groups.  KMEANS is the method of Sec. 4.2: Lloyd's
+ * passes on the columns of L from the current groups.  SPECTRAL is the nonlinear
+ * alternative the end of Sec. 4.2 names (and the Remark closing Sec. 3): normalised
+ * spectral clustering (Ng, Jordan & Weiss 2001) of the columns of L with the
+ * Gaussian affinity W_ij = exp(-||L_i - L_j||^2 / (2 sigma^2)), W_ii = 0,
+ * A = D^{-1/2} W D^{-1/2}, rows of the eigenvectors of the c largest eigenvalues
+ * scaled to unit length, then Lloyd's passes on those rows from the current groups
+ * (centroids = group means of the rows, an empty group at zero).  The initial
+ * groups are the spectral clustering of X's columns with k-means++ seeding from
+ * `seed` then Lloyd.  L-, S- and multiplier steps are unchanged.  It holds the
+ * n x n affinity in FP64 (8 n^2 bytes): n <= 32768 and c <= 40, else
+ * RESPCA_ERR_UNSUPPORTED; solve and iterate only (batched, no-alloc and
+ * init_embedding: RESPCA_ERR_UNSUPPORTED). */
+typedef enum {
+    RESPCA_PSTEP_KMEANS = 0,
+    RESPCA_PSTEP_SPECTRAL = 1
+} respca_pstep;
+
 typedef struct {
     double   lambda;      /* weight of the group-variance term of eq_obj (Sec. 3); must be
                              >= 0.  NaN selects sqrt(max(d, n)), the value of Sec. 5.1.   */
@@ -98,6 +116,9 @@ typedef struct {
     int32_t  init_embedding_rows;
     int32_t  sparse_norm; /* respca_sparse_norm; default RESPCA_SPARSE_L1; other values
                              RESPCA_ERR_INVALID                                             */
+    int32_t  pstep;       /* respca_pstep; default RESPCA_PSTEP_KMEANS                      */
+    double   spectral_sigma; /* kernel width sigma of the spectral p-step (> 0, finite; the
+                             paper gives none); ignored by the K-means p-step; default 0   */
 } respca_params;
 
 typedef struct {
@@ -111,6 +132,9 @@ typedef struct {
     double  rho_final;    /* rho used by the last iteration                             */
     int64_t refined;      /* bf16 mode: column decisions re-taken exactly (all passes;
                              zero at most 16 groups, where nothing is re-taken)          */
+    int32_t eig_iters;    /* spectral p-step: filtered subspace iterations, all p-steps  */
+    int32_t eig_unconverged; /* spectral p-step: embeddings whose eigen residual stayed
+                             above 1e-10 after 200 iterations                            */
 } respca_info;
 
 typedef struct respca_handle_s *respca_handle;
@@ -205,6 +229,21 @@ respca_status respca_kmeans(respca_handle h, const respca_params *params,
                             int32_t *labels, void *C, respca_info *info, void *stream);
 
 /*
+ * Row embedding of the spectral p-step on its own (RESPCA_PSTEP_SPECTRAL): for
+ * the columns of Y (d x n, ldy; double if precision is RESPCA_F64, else float)
+ * emb (device, c x n doubles, leading dimension c) receives the unit rows of
+ * the eigenvectors of the c largest eigenvalues of D^{-1/2} W D^{-1/2},
+ * W_ij = exp(-||Y_i - Y_j||^2 / (2 sigma^2)), W_ii = 0 (any orthonormal basis of
+ * that eigenspace: K-means of the rows depends only on their distances).
+ * eigenvalues (host, nullable) receives the c largest eigenvalues (decreasing),
+ * info (host, nullable) eig_iters / eig_unconverged.  Limits as for the p-step.
+ */
+respca_status respca_spectral_embedding(respca_handle h, int32_t precision, int64_t d, int64_t n,
+                                        const void *Y, int64_t ldy, int32_t c, double sigma,
+                                        uint64_t seed, double *emb, double *eigenvalues,
+                                        respca_info *info, void *stream);
+
+/*
  * Batched solve: `batch` independent RES-PCA problems of uneven size, each run
  * exactly as respca_solve would run it (its own initial K-means, iteration
  * count, Lloyd passes and Sec. 5 stopping test), all inside one persistent
@@ -243,6 +282,19 @@ respca_status respca_autotune_batched(respca_handle h, const respca_params *para
                                       const char *cache_path, double *best_ms, void *stream);
 
 /*
+ * The batched solver's tile shape, set by hand or read back (host values).
+ * Accepted values are the tuner's candidates: jc (sweep columns per work item)
+ * in {4, 8, 16, 32}, slice_rows (rows per distance slice) in {512, 1024, 2048},
+ * blocks_per_cu (persistent workgroups per compute unit) in {1, 2}; anything
+ * else is RESPCA_ERR_INVALID and leaves the shape unchanged.  The defaults are
+ * (8, 1024, 2).  Needs no device.
+ */
+respca_status respca_set_batched_tile(respca_handle h, int32_t jc, int32_t slice_rows,
+                                      int32_t blocks_per_cu);
+respca_status respca_get_batched_tile(respca_handle h, int32_t *jc, int32_t *slice_rows,
+                                      int32_t *blocks_per_cu);
+
+/*
  * Kernel timing.  While enabled, every launch of the kernels listed in
  * respca_kernel_id is bracketed by HIP events recorded on the stream it is
  * launched on, and the library accumulates, per kernel, the number of
@@ -263,7 +315,12 @@ typedef enum {
                                      + 1 + 2 per initial Lloyd pass + 11 per outer iteration
                                      + 2 per extra Lloyd pass, times d n 4                          */
     RESPCA_KERNEL_COLNORM = 5,    /* l2,1 S-step column norms: reads X, S, Theta                     */
-    RESPCA_KERNEL_COUNT = 6
+    RESPCA_KERNEL_AFFINITY = 6,   /* spectral p-step: Gram matrix on FP64 MFMA + Gaussian affinity;
+                                     bytes = the d x n operand + the n x n FP64 affinity written,
+                                     flops = 2 n^2 d                                               */
+    RESPCA_KERNEL_EIGEN = 7,      /* spectral p-step: one block product A Y (reads the n x n
+                                     normalised affinity; flops 2 n^2 k, k = min(n, c + 8))        */
+    RESPCA_KERNEL_COUNT = 8
 } respca_kernel_id;
 
 /* enable: 0 turns timing off; otherwise bit k (1 << k) times the launches of
@@ -275,6 +332,20 @@ respca_status respca_profile_enable(respca_handle h, int32_t enable);
  * contraction's 2 c d n per pass; zero for the streaming kernels). */
 respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t *launches,
                                    double *total_ms, double *bytes, double *flops);
+
+/*
+ * Streaming bandwidth probe (measurement support, not part of the method): a
+ * kernel that reads `reads` arrays (1..4) and writes `writes` arrays (0..3) of
+ * bytes_per_array bytes each (a positive multiple of 16), float4 loads and
+ * stores, launched reps times on `stream` between two events after one warm-up
+ * launch.  *gbps (host) receives (reads + writes) * bytes_per_array / time per
+ * launch, *ms_per_launch the mean launch time (either may be NULL).  The arrays
+ * live in the handle's workspace (allocated on demand).  The sweep's mix is 4
+ * reads and 3 writes, the means pass's 3 reads, a copy's 1 and 1.
+ */
+respca_status respca_bandwidth_probe(respca_handle h, int32_t reads, int32_t writes,
+                                     int64_t bytes_per_array, int32_t reps, double *gbps,
+                                     double *ms_per_launch, void *stream);
 
 /*
  * Learned warm start (an addition to the paper's method; all FP32, device

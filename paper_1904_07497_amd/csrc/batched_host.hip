@@ -71,6 +71,8 @@ respca_status validate(respca_handle h, const respca_params* params, int32_t bat
             return fail(h, RESPCA_ERR_UNSUPPORTED, "batched solver runs FP32 instances only");
         if (res[i].sparse_norm != RESPCA_SPARSE_L1)
             return fail(h, RESPCA_ERR_UNSUPPORTED, "batched solver runs the l1 penalty only");
+        if (res[i].pstep != RESPCA_PSTEP_KMEANS)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "batched solver runs the K-means p-step only");
         if (!X[i] || !L[i] || !S[i]) return fail(h, RESPCA_ERR_INVALID, "NULL matrix pointer");
         if (ldx[i] < d[i] || ldl[i] < d[i] || lds[i] < d[i])
             return fail(h, RESPCA_ERR_INVALID, "leading dimension < d");
@@ -361,6 +363,24 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     return worst;
 }
 
+// Candidate tile shapes of the tuner (the only shapes the batched kernel takes).
+constexpr int kTuneJc[] = {4, 8, 16, 32};
+constexpr int kTuneRows[] = {512, 1024, 2048};
+constexpr int kTuneBpc[] = {1, 2};
+// Bumped whenever the batched kernel changes, so stale cache lines are not used.
+constexpr const char* kTuneVersion = "k3";
+
+template <size_t N>
+bool one_of(int v, const int (&set)[N]) {
+    for (int x : set)
+        if (x == v) return true;
+    return false;
+}
+
+bool tile_valid(int jc, int rows, int bpc) {
+    return one_of(jc, kTuneJc) && one_of(rows, kTuneRows) && one_of(bpc, kTuneBpc);
+}
+
 std::string bucket_key(int32_t batch, const int64_t* d, const int64_t* n, const std::vector<Resolved>& r,
                        int device) {
     std::vector<double> dn(batch);
@@ -375,7 +395,7 @@ std::string bucket_key(int32_t batch, const int64_t* d, const int64_t* n, const 
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
     for (auto& ch : arch) if (ch == ' ' || ch == ':') ch = '_';
     char key[256];
-    std::snprintf(key, sizeof(key), "%s_b%d_dn2^%d_c%d", arch.c_str(), batch,
+    std::snprintf(key, sizeof(key), "%s_%s_b%d_dn2^%d_c%d", arch.c_str(), kTuneVersion, batch,
                   (int)std::lround(std::log2(std::max(dn[batch / 2], 1.0))), cmax);
     return key;
 }
@@ -415,20 +435,21 @@ respca_status respca_autotune_batched(respca_handle h, const respca_params* para
             double ms;
             bool found = false;
             while (std::fscanf(f, "%255s %d %d %d %lf", k, &jc, &rows, &bpc, &ms) == 5)
-                if (key == k) { h->tune = BatchTune{jc, rows, bpc}; if (best_ms) *best_ms = ms; found = true; }
+                if (key == k && tile_valid(jc, rows, bpc)) {
+                    h->tune = BatchTune{jc, rows, bpc};
+                    if (best_ms) *best_ms = ms;
+                    found = true;
+                }
             std::fclose(f);
             if (found) return RESPCA_OK;
         }
     }
-    const int jcs[] = {4, 8, 16, 32};
-    const int rows_c[] = {512, 1024, 2048};
-    const int bpcs[] = {1, 2};
     BatchTune best = h->tune;
     double best_t = 1e300;
     std::vector<respca_info> info(batch);
-    for (int bpc : bpcs)
-        for (int rows : rows_c)
-            for (int jc : jcs) {
+    for (int bpc : kTuneBpc)
+        for (int rows : kTuneRows)
+            for (int jc : kTuneJc) {
                 h->tune = BatchTune{jc, rows, bpc};
                 Call call;
                 plan(h->tune, batch, d, n, X, ldx, L, ldl, S, lds, nullptr, res, call);
@@ -447,6 +468,24 @@ respca_status respca_autotune_batched(respca_handle h, const respca_params* para
             std::fclose(f);
         }
     }
+    return RESPCA_OK;
+}
+
+respca_status respca_set_batched_tile(respca_handle h, int32_t jc, int32_t slice_rows,
+                                      int32_t blocks_per_cu) {
+    if (!h) return RESPCA_ERR_INVALID;
+    if (!tile_valid(jc, slice_rows, blocks_per_cu))
+        return fail(h, RESPCA_ERR_INVALID, "tile shape is not one of the tuner's candidates");
+    h->tune = BatchTune{jc, slice_rows, blocks_per_cu};
+    return RESPCA_OK;
+}
+
+respca_status respca_get_batched_tile(respca_handle h, int32_t* jc, int32_t* slice_rows,
+                                      int32_t* blocks_per_cu) {
+    if (!h) return RESPCA_ERR_INVALID;
+    if (jc) *jc = h->tune.jc;
+    if (slice_rows) *slice_rows = h->tune.slice_rows;
+    if (blocks_per_cu) *blocks_per_cu = h->tune.blocks_per_cu;
     return RESPCA_OK;
 }
 

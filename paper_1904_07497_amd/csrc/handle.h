@@ -68,6 +68,12 @@ struct respca_handle_s {
     int64_t bsteps = 0;
     // warm start
     respca::DevBuf wsk, wfeat, wacts, wscratch, wred, wcent, embl, embc, wdesc, whash;
+    respca::DevBuf probe;           // arrays of the bandwidth probe
+    // spectral p-step: affinity (n x n), norms, scales, eigen blocks, partials,
+    // small matrices, the row embedding and its centroids
+    respca::DevBuf sp_w, sp_q, sp_s, sp_y, sp_z, sp_yp, sp_t, sp_part, sp_small, sp_emb, sp_cent;
+    double* sp_status = nullptr;      // pinned host words the eigen loop reads back
+    double* sp_status_dev = nullptr;
     // Carving mode of ensure(): while arena_on, buffers are cut from [arena_base,
     // arena_base + arena_cap) instead of allocated (arena_base may be 0 for a
     // measuring pass that launches nothing); arena_off is the bytes used so far.
@@ -126,6 +132,45 @@ inline respca_status ensure_host(respca_handle h, size_t bytes) {
     return RESPCA_OK;
 }
 
+// Event bracket around one launch (no-op unless timing is enabled).
+struct ProfScope {
+    respca_handle h;
+    hipStream_t st;
+    int kernel;
+    double bytes, flops;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(respca_handle h_, hipStream_t st_, int k, double by, double fl = 0.0)
+        : h(h_), st(st_), kernel(k), bytes(by), flops(fl) {
+        // not timed while carving from the fixed scratch area (events are created lazily)
+        if (!((h->prof_mask >> kernel) & 1u) || h->arena_on) return;
+        a = take();
+        b = take();
+        if (a && b) (void)hipEventRecord(a, st);
+    }
+    ~ProfScope() {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, st);
+        h->prof_pending.push_back({kernel, a, b, bytes, flops});
+    }
+    hipEvent_t take() {
+        if (!h->prof_pool.empty()) {
+            hipEvent_t e = h->prof_pool.back();
+            h->prof_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+inline respca_status ensure_spectral_status(respca_handle h) {
+    if (h->sp_status) return RESPCA_OK;
+    CK(hipHostMalloc((void**)&h->sp_status, 8 * sizeof(double), hipHostMallocMapped));
+    CK(hipHostGetDevicePointer((void**)&h->sp_status_dev, h->sp_status, 0));
+    return RESPCA_OK;
+}
+
 inline respca_status fail(respca_handle h, respca_status s, const std::string& msg) {
     if (h) h->err = msg;
     return s;
@@ -147,6 +192,8 @@ inline double uniform01(uint64_t& state) {
 struct Resolved {
     double lambda, tol, rho0, kappa, rho_max;
     int c, max_iter, max_lloyd, precision, sparse_norm;
+    int pstep;
+    double sigma;   // spectral p-step kernel width
     uint64_t seed;
     const int32_t* init_labels;
     double* history;

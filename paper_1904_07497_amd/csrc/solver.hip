@@ -15,6 +15,7 @@
 #include "../../include/respca.h"
 #include "handle.h"
 #include "kernels.h"
+#include "spectral.h"
 
 using namespace respca;
 
@@ -43,38 +44,6 @@ respca_status lookup_scratch(respca_handle h, int device) {
     g_scratch_ptr[device] = (char*)ptr;
     return RESPCA_OK;
 }
-
-// Event bracket around one launch (no-op unless timing is enabled).
-struct ProfScope {
-    respca_handle h;
-    hipStream_t st;
-    int kernel;
-    double bytes, flops;
-    hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(respca_handle h_, hipStream_t st_, int k, double by, double fl = 0.0)
-        : h(h_), st(st_), kernel(k), bytes(by), flops(fl) {
-        // not timed while carving from the fixed scratch area (events are created lazily)
-        if (!((h->prof_mask >> kernel) & 1u) || h->arena_on) return;
-        a = take();
-        b = take();
-        if (a && b) (void)hipEventRecord(a, st);
-    }
-    ~ProfScope() {
-        if (!a || !b) return;
-        (void)hipEventRecord(b, st);
-        h->prof_pending.push_back({kernel, a, b, bytes, flops});
-    }
-    hipEvent_t take() {
-        if (!h->prof_pool.empty()) {
-            hipEvent_t e = h->prof_pool.back();
-            h->prof_pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-};
 
 // Fold finished event pairs into the counters; call after a stream sync.
 void prof_resolve(respca_handle h) {
@@ -108,6 +77,8 @@ respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d
     r.max_lloyd = p->max_lloyd;
     r.precision = p->precision;
     r.sparse_norm = p->sparse_norm;
+    r.pstep = p->pstep;
+    r.sigma = p->spectral_sigma;
     r.seed = p->seed;
     r.init_labels = p->init_labels;
     r.history = p->history;
@@ -134,6 +105,16 @@ respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d
     if (r.max_lloyd < 1) return fail(h, RESPCA_ERR_INVALID, "max_lloyd must be >= 1");
     if (r.precision != RESPCA_F64 && r.precision != RESPCA_F32 && r.precision != RESPCA_BF16GEMM_F32)
         return fail(h, RESPCA_ERR_INVALID, "unknown precision");
+    if (r.pstep != RESPCA_PSTEP_KMEANS && r.pstep != RESPCA_PSTEP_SPECTRAL)
+        return fail(h, RESPCA_ERR_INVALID, "pstep must be RESPCA_PSTEP_KMEANS or RESPCA_PSTEP_SPECTRAL");
+    if (r.pstep == RESPCA_PSTEP_SPECTRAL) {
+        if (!(r.sigma > 0.0) || !std::isfinite(r.sigma))
+            return fail(h, RESPCA_ERR_INVALID, "spectral_sigma must be finite and > 0");
+        if (r.c > kSpectralMaxGroups || n > kSpectralMaxN)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "spectral p-step: c <= 40 and n <= 32768");
+        if (r.init_embedding)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "spectral p-step: no init_embedding");
+    }
     return RESPCA_OK;
 }
 
@@ -428,6 +409,37 @@ struct Engine {
         return RESPCA_OK;
     }
 
+    SpectralStats spec;
+
+    // Groups from the row embedding of the columns of Y (spectral clustering):
+    // with `fresh`, k-means++ from seed then Lloyd (the initialisation);
+    // otherwise Lloyd from the current groups, their centroids the group means of
+    // the rows (an empty group at zero).  The K-means runs on a second engine over
+    // the c x n embedding, which shares the handle's sort and distance buffers, so
+    // the caller's sort tables are stale afterwards.
+    respca_status spectral_groups(const Resolved& r, const T* Y, int64_t ldy, bool fresh,
+                                  int32_t*& cur, int32_t*& alt, int& steps) {
+        CKS(ensure(h, h->sp_emb, (size_t)c * n * sizeof(double)));
+        CKS(ensure(h, h->sp_cent, (size_t)c * c * sizeof(double)));
+        double* emb = (double*)h->sp_emb.p;
+        double* cent = (double*)h->sp_cent.p;
+        CKS(spectral_embed<T>(h, Y, ldy, d, n, c, r.sigma, r.seed, emb, &spec, st));
+        Engine<double> e2{h, st, (int64_t)c, n, c, false};
+        CKS(e2.setup());
+        steps = 0;
+        if (fresh) {
+            CKS(e2.kmeans(emb, c, r.seed, r.max_lloyd, cent, cur, alt, steps));
+        } else {
+            launch_zero2d<double>(cent, c, c, c, st);
+            e2.sort(cur);
+            e2.group_means(false, emb, c, nullptr, 0, nullptr, 0, 0.0, cent);
+            CKS(e2.lloyd(emb, c, cent, cur, alt, r.max_lloyd, steps, nullptr));
+        }
+        CKS(setup());   // this engine's buffers at its own sizes again
+        next_ready = false;
+        return RESPCA_OK;
+    }
+
     // One outer iteration; norms receives the three Frobenius norms.
     respca_status iterate_once(const Resolved& r, const T* X, int64_t ldx, T* L, int64_t ldl, T* S,
                                int64_t lds, T* Th, int64_t ldt, T* C, int32_t*& cur, int32_t*& alt,
@@ -463,6 +475,12 @@ struct Engine {
                                      inv_next, (double*)h->normp.p, (double*)h->pmeans.p, st, fac);
         }
         launch_sum_partials((const double*)h->normp.p, np, 3, status, st);
+        if (r.pstep == RESPCA_PSTEP_SPECTRAL) {
+            double s[4];
+            CKS(readback(s));   // the sweep's norms, before the p-step reuses the buffers
+            for (int i = 0; i < 3; ++i) norms[i] = std::sqrt(s[i]);
+            return spectral_groups(r, L, ldl, false, cur, alt, steps);   // Sec. 4.2, nonlinear form
+        }
         double first[4];
         CKS(lloyd(L, ldl, C, cur, alt, r.max_lloyd, steps, first));  // Sec. 4.2
         for (int i = 0; i < 3; ++i) norms[i] = std::sqrt(first[i]);
@@ -531,6 +549,14 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
         launch_zero2d<T>(C, d, d, r.c, st);
         e.sort(cur);
         e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C);
+    } else if (r.pstep == RESPCA_PSTEP_SPECTRAL) {
+        // spectral clustering of X's columns, then as with given initial labels
+        int steps = 0;
+        CKS(e.spectral_groups(r, X, ldx, true, cur, alt, steps));
+        info->init_lloyd = steps;
+        launch_zero2d<T>(C, d, d, r.c, st);
+        e.sort(cur);
+        e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C);
     } else {
         int steps = 0;
         CKS(e.kmeans(X, ldx, r.seed, r.max_lloyd, C, cur, alt, steps));
@@ -565,6 +591,8 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
     if (labels) CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     CK(hipStreamSynchronize(st));
     info->refined = e.refined;
+    info->eig_iters = (int32_t)e.spec.iters;
+    info->eig_unconverged = (int32_t)e.spec.unconverged;
     return (respca_status)info->status;
 }
 
@@ -601,6 +629,8 @@ respca_status iterate_t(respca_handle h, const Resolved& r, int64_t d, int64_t n
     CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     CK(hipStreamSynchronize(st));
     info->refined = e.refined;
+    info->eig_iters = (int32_t)e.spec.iters;
+    info->eig_unconverged = (int32_t)e.spec.unconverged;
     info->status = RESPCA_OK;
     return RESPCA_OK;
 }
@@ -687,7 +717,9 @@ void respca_destroy(respca_handle h) {
     if (h->bws.p) (void)hipFree(h->bws.p);
     if (h->bstage) (void)hipHostFree(h->bstage);
     respca::DevBuf* wbufs[] = {&h->wsk, &h->wfeat, &h->wacts, &h->wscratch, &h->wred, &h->wcent,
-                               &h->embl, &h->embc, &h->wdesc, &h->whash};
+                               &h->embl, &h->embc, &h->wdesc, &h->whash, &h->probe,
+                               &h->sp_w, &h->sp_q, &h->sp_s, &h->sp_y, &h->sp_z, &h->sp_yp,
+                               &h->sp_t, &h->sp_part, &h->sp_small, &h->sp_emb, &h->sp_cent};
     for (respca::DevBuf* b : wbufs)
         if (b->p) (void)hipFree(b->p);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
@@ -699,6 +731,7 @@ void respca_destroy(respca_handle h) {
         if (b->p) (void)hipFree(b->p);
     if (h->hstage) (void)hipHostFree(h->hstage);
     if (h->hstatus) (void)hipHostFree(h->hstatus);
+    if (h->sp_status) (void)hipHostFree(h->sp_status);
     delete h;
 }
 
@@ -721,6 +754,8 @@ void respca_params_default(respca_params* p) {
     p->init_embedding = nullptr;
     p->init_embedding_ld = 0;
     p->init_embedding_rows = 0;
+    p->pstep = RESPCA_PSTEP_KMEANS;
+    p->spectral_sigma = 0.0;
 }
 
 const char* respca_status_string(respca_status s) {
@@ -926,6 +961,8 @@ respca_status respca_iterate_noalloc(respca_handle h, const respca_params* param
     if (s == RESPCA_OK) s = bind_device(h);
     if (s == RESPCA_OK && h->device >= kMaxScratchDevices)
         s = fail(h, RESPCA_ERR_UNSUPPORTED, "no scratch area for device ordinals above 63");
+    if (s == RESPCA_OK && r.pstep != RESPCA_PSTEP_KMEANS)
+        s = fail(h, RESPCA_ERR_UNSUPPORTED, "the no-alloc entry point runs the K-means p-step only");
     if (s == RESPCA_OK) s = lookup_scratch(h, h->device);
     if (s == RESPCA_OK) {
         char* base = nullptr;
@@ -951,6 +988,44 @@ respca_status respca_iterate_noalloc(respca_handle h, const respca_params* param
         if (s == RESPCA_OK)
             s = run_iterate(h, r, d, n, X, ldx, L, ldl, S, lds, Theta, ldt, labels, C, rho, iters,
                             norms, out, (hipStream_t)stream);
+    }
+    out->status = s;
+    return s;
+}
+
+respca_status respca_spectral_embedding(respca_handle h, int32_t precision, int64_t d, int64_t n,
+                                        const void* Y, int64_t ldy, int32_t c, double sigma,
+                                        uint64_t seed, double* emb, double* eigenvalues,
+                                        respca_info* info, void* stream) {
+    if (!h) return RESPCA_ERR_INVALID;
+    respca_info local{};
+    respca_info* out = info ? info : &local;
+    std::memset(out, 0, sizeof(*out));
+    respca_status s = RESPCA_OK;
+    if (!Y || !emb) s = fail(h, RESPCA_ERR_INVALID, "NULL argument");
+    else if (d < 1 || n < 2 || d >= (int64_t)INT32_MAX || ldy < d)
+        s = fail(h, RESPCA_ERR_INVALID, "need d >= 1, n >= 2, ldy >= d");
+    else if (c < 1 || c >= n) s = fail(h, RESPCA_ERR_INVALID, "c must be in [1, n)");
+    else if (!(sigma > 0.0) || !std::isfinite(sigma))
+        s = fail(h, RESPCA_ERR_INVALID, "sigma must be finite and > 0");
+    else if (precision != RESPCA_F64 && precision != RESPCA_F32 && precision != RESPCA_BF16GEMM_F32)
+        s = fail(h, RESPCA_ERR_INVALID, "unknown precision");
+    else if (c > kSpectralMaxGroups || n > kSpectralMaxN)
+        s = fail(h, RESPCA_ERR_UNSUPPORTED, "spectral embedding: c <= 40 and n <= 32768");
+    if (s == RESPCA_OK) s = bind_device(h);
+    if (s == RESPCA_OK) {
+        hipStream_t st = (hipStream_t)stream;
+        SpectralStats stats;
+        s = precision == RESPCA_F64
+                ? spectral_embed<double>(h, (const double*)Y, ldy, d, n, c, sigma, seed, emb, &stats, st)
+                : spectral_embed<float>(h, (const float*)Y, ldy, d, n, c, sigma, seed, emb, &stats, st);
+        if (s == RESPCA_OK && eigenvalues) s = spectral_eigenvalues(h, n, c, eigenvalues, st);
+        if (s == RESPCA_OK) {
+            if (hipStreamSynchronize(st) != hipSuccess) s = fail(h, RESPCA_ERR_HIP, "stream sync failed");
+            prof_resolve(h);
+        }
+        out->eig_iters = (int32_t)stats.iters;
+        out->eig_unconverged = (int32_t)stats.unconverged;
     }
     out->status = s;
     return s;

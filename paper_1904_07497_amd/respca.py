@@ -24,16 +24,19 @@ F64, F32, BF16GEMM_F32 = 0, 1, 2
 # Every symbol include/respca.h declares.
 EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_status_string",
            "respca_last_error", "respca_version", "respca_solve", "respca_iterate",
-           "respca_iterate_noalloc",
+           "respca_iterate_noalloc", "respca_spectral_embedding",
            "respca_kmeans", "respca_profile_enable", "respca_profile_query",
            "respca_solve_batched", "respca_autotune_batched", "respca_profile_batched_phases",
+           "respca_set_batched_tile", "respca_get_batched_tile", "respca_bandwidth_probe",
            "respca_mlp_param_count", "respca_mlp_act_count", "respca_sketch", "respca_features",
            "respca_mlp_forward", "respca_mlp_backward", "respca_mlp_loss", "respca_mlp_adam",
            "respca_warmstart", "respca_warmstart_batched")
 WARM_IN, WARM_OUT = 68, 65
 BATCH_PHASES = ("pack", "init", "seed_distance", "seed_draw", "seed_gather", "sort", "means",
                 "finalize", "sweep", "distance", "argmin", "control")
-KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3, "batched": 4, "colnorm": 5}
+KERNELS = {"sweep": 0, "means": 1, "distance": 2, "seeding": 3, "batched": 4, "colnorm": 5,
+           "affinity": 6, "eigen": 7}
+PSTEP_KMEANS, PSTEP_SPECTRAL = 0, 1
 
 
 class Params(ct.Structure):
@@ -43,13 +46,14 @@ class Params(ct.Structure):
                 ("precision", ct.c_int32), ("init_labels", ct.c_void_p),
                 ("history", ct.POINTER(ct.c_double)), ("init_embedding", ct.c_void_p),
                 ("init_embedding_ld", ct.c_int64), ("init_embedding_rows", ct.c_int32),
-                ("sparse_norm", ct.c_int32)]
+                ("sparse_norm", ct.c_int32), ("pstep", ct.c_int32), ("spectral_sigma", ct.c_double)]
 
 
 class Info(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("lloyd_steps", ct.c_int32), ("init_lloyd", ct.c_int32),
                 ("status", ct.c_int32), ("primal", ct.c_double), ("dL", ct.c_double),
-                ("dS", ct.c_double), ("rho_final", ct.c_double), ("refined", ct.c_int64)]
+                ("dS", ct.c_double), ("rho_final", ct.c_double), ("refined", ct.c_int64),
+                ("eig_iters", ct.c_int32), ("eig_unconverged", ct.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -91,6 +95,10 @@ def lib():
         L.respca_iterate.argtypes = [vp, ct.POINTER(Params), i64, i64, vp, i64, vp, i64, vp, i64,
                                      vp, i64, vp, vp, ct.POINTER(ct.c_double), i32,
                                      ct.POINTER(ct.c_double), ct.POINTER(Info), vp]
+        L.respca_spectral_embedding.restype = i32
+        L.respca_spectral_embedding.argtypes = [vp, i32, i64, i64, vp, i64, i32, ct.c_double,
+                                                ct.c_uint64, vp, ct.POINTER(ct.c_double),
+                                                ct.POINTER(Info), vp]
         L.respca_iterate_noalloc.restype = i32
         L.respca_iterate_noalloc.argtypes = L.respca_iterate.argtypes
         L.respca_profile_enable.restype = i32
@@ -106,6 +114,14 @@ def lib():
         L.respca_autotune_batched.restype = i32
         L.respca_autotune_batched.argtypes = [vp, ct.POINTER(Params), i32, i64p, i64p, arr, i64p, arr,
                                               i64p, arr, i64p, ct.c_char_p, ct.POINTER(ct.c_double), vp]
+        L.respca_bandwidth_probe.restype = i32
+        L.respca_bandwidth_probe.argtypes = [vp, i32, i32, i64, i32, ct.POINTER(ct.c_double),
+                                             ct.POINTER(ct.c_double), vp]
+        L.respca_set_batched_tile.restype = i32
+        L.respca_set_batched_tile.argtypes = [vp, i32, i32, i32]
+        i32p = ct.POINTER(ct.c_int32)
+        L.respca_get_batched_tile.restype = i32
+        L.respca_get_batched_tile.argtypes = [vp, i32p, i32p, i32p]
         L.respca_profile_batched_phases.restype = i32
         L.respca_profile_batched_phases.argtypes = [vp, ct.POINTER(ct.c_double), i32,
                                                     ct.POINTER(ct.c_int64)]
@@ -155,13 +171,14 @@ def default_params() -> Params:
 
 
 def make_params(rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
-                max_lloyd=100, seed=0, precision=F32, sparse_norm=0) -> Params:
+                max_lloyd=100, seed=0, precision=F32, sparse_norm=0, pstep=0, sigma=0.0) -> Params:
     p = default_params()
     p.lam = math.nan if lam is None else float(lam)
     p.rank, p.tol, p.max_iter = int(rank), float(tol), int(max_iter)
     p.rho0, p.kappa, p.rho_max = float(rho0), float(kappa), float(rho_max)
     p.max_lloyd, p.seed, p.precision = int(max_lloyd), int(seed) & (2**64 - 1), int(precision)
     p.sparse_norm = int(sparse_norm)
+    p.pstep, p.spectral_sigma = int(pstep), float(sigma)
     return p
 
 
@@ -242,9 +259,10 @@ def _stream(stream):
 
 def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
           max_lloyd=100, seed=0, precision=None, init_labels=None, history=False,
-          out=None, stream=None, init_embedding=None, sparse_norm=0):
+          out=None, stream=None, init_embedding=None, sparse_norm=0, pstep=0, sigma=0.0):
     """RES-PCA of X (d x n column-major tensor).  Returns dict(L, S, labels, info[, history]).
-    sparse_norm: 0 the l1 penalty on S, 1 the column-wise l2,1 penalty."""
+    sparse_norm: 0 the l1 penalty on S, 1 the column-wise l2,1 penalty.  pstep:
+    PSTEP_KMEANS, or PSTEP_SPECTRAL with kernel width sigma."""
     import torch
     precision = _dtype_precision(X, precision)
     d, n = X.shape
@@ -258,7 +276,7 @@ def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho
     lp, ldl = _colmajor(L, "L")
     sp, lds = _colmajor(S, "S")
     p = make_params(rank, lam, tol, max_iter, rho0, kappa, rho_max, max_lloyd, seed, precision,
-                    sparse_norm)
+                    sparse_norm, pstep, sigma)
     hist = None
     if history:
         hist = (ct.c_double * (3 * max_iter))()
@@ -286,7 +304,8 @@ def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho
 
 
 def iterate(X, state: dict, iters=1, rank=None, lam=None, max_lloyd=100, kappa=1.5, rho_max=1e10,
-            precision=None, stream=None, sparse_norm=0, noalloc=False):
+            precision=None, stream=None, sparse_norm=0, noalloc=False, pstep=0, sigma=0.0,
+            seed=0):
     """Run ``iters`` outer iterations in place on ``state`` (device tensors L, S,
     Theta (d x n column-major), labels (int32[n]), C (d x c column-major, ld = d)
     and float rho).  Returns (norms [iters x 3], info).  noalloc: call
@@ -302,8 +321,8 @@ def iterate(X, state: dict, iters=1, rank=None, lam=None, max_lloyd=100, kappa=1
     lp, ldl = _colmajor(state["L"], "L")
     sp, lds = _colmajor(state["S"], "S")
     tp, ldt = _colmajor(state["Theta"], "Theta")
-    p = make_params(c, lam, 0.0, max(iters, 1), 1e-4, kappa, rho_max, max_lloyd, 0, precision,
-                    sparse_norm)
+    p = make_params(c, lam, 0.0, max(iters, 1), 1e-4, kappa, rho_max, max_lloyd, seed, precision,
+                    sparse_norm, pstep, sigma)
     rho = ct.c_double(float(state["rho"]))
     norms = (ct.c_double * (3 * max(iters, 1)))()
     info = Info()
@@ -315,6 +334,27 @@ def iterate(X, state: dict, iters=1, rank=None, lam=None, max_lloyd=100, kappa=1
     h.check(s)
     state["rho"] = rho.value
     return np.ctypeslib.as_array(norms)[: 3 * iters].reshape(-1, 3).copy(), info.as_dict()
+
+
+def spectral_embedding(Y, rank, sigma, seed=0, precision=None, stream=None):
+    """Row embedding of the spectral p-step for the columns of Y: returns (emb
+    (rank x n float64, column j = unit row j of the top-rank eigenvectors),
+    eigenvalues (numpy, decreasing), info)."""
+    import numpy as np
+    import torch
+    precision = _dtype_precision(Y, precision)
+    d, n = Y.shape
+    yp, ldy = _colmajor(Y, "Y")
+    emb = torch.empty((n, rank), dtype=torch.float64, device=Y.device).T
+    vals = (ct.c_double * rank)()
+    info = Info()
+    h = handle(Y.device.index or 0)
+    s = lib().respca_spectral_embedding(h._h, int(precision), d, n, yp, ldy, int(rank), float(sigma),
+                                        int(seed) & (2**64 - 1), emb.data_ptr(),
+                                        ct.cast(vals, ct.POINTER(ct.c_double)), ct.byref(info),
+                                        _stream(stream))
+    h.check(s, allow=(OK,))
+    return emb, np.ctypeslib.as_array(vals).copy(), info.as_dict()
 
 
 def kmeans(Y, rank, seed=0, max_lloyd=100, precision=None, stream=None):
@@ -437,6 +477,30 @@ def autotune_batched(Xs, params_list, cache_path=None, outs=None, stream=None, d
                                       _stream(stream))
     h.check(s, allow=(OK,))
     return best.value
+
+
+def set_batched_tile(jc: int, slice_rows: int, blocks_per_cu: int, device: int = 0):
+    """Set the batched solver's tile shape (one of the tuner's candidates)."""
+    h = handle(device)
+    h.check(lib().respca_set_batched_tile(h._h, int(jc), int(slice_rows), int(blocks_per_cu)))
+
+
+def get_batched_tile(device: int = 0) -> tuple:
+    """The batched solver's current tile shape (jc, slice_rows, blocks_per_cu)."""
+    h = handle(device)
+    a, b, c = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    h.check(lib().respca_get_batched_tile(h._h, ct.byref(a), ct.byref(b), ct.byref(c)))
+    return a.value, b.value, c.value
+
+
+def bandwidth_probe(reads: int, writes: int, bytes_per_array: int, reps: int = 10,
+                    stream=None, device: int = 0) -> tuple:
+    """Streaming probe of a read/write mix; returns (GB/s, ms per launch)."""
+    h = handle(device)
+    g, ms = ct.c_double(0.0), ct.c_double(0.0)
+    h.check(lib().respca_bandwidth_probe(h._h, int(reads), int(writes), int(bytes_per_array),
+                                         int(reps), ct.byref(g), ct.byref(ms), _stream(stream)))
+    return g.value, ms.value
 
 
 def batched_phases(device: int = 0) -> dict:

@@ -38,7 +38,7 @@ def test_params_default_and_strings():
 def test_params_mirror_covers_the_c_struct():
     """respca_params_default clears sizeof(respca_params) bytes: on a buffer larger
     than the Python mirror, the bytes past the mirror stay untouched (so the mirror
-    is not smaller than the C struct) and the mirror's last field, sparse_norm,
+    is not smaller than the C struct) and the mirror's last field, spectral_sigma,
     was written (so it is not larger)."""
     import ctypes as ct
     size = ct.sizeof(rp.Params)
@@ -47,7 +47,8 @@ def test_params_mirror_covers_the_c_struct():
     assert bytes(buf[size:]) == b"\xab" * 64
     p = rp.Params.from_buffer(buf)
     assert p.sparse_norm == 0 and p.init_embedding_rows == 0 and p.precision == rp.F32
-    assert rp.KERNELS["colnorm"] == len(rp.KERNELS) - 1
+    assert p.pstep == rp.PSTEP_KMEANS and p.spectral_sigma == 0.0
+    assert rp.KERNELS["eigen"] == len(rp.KERNELS) - 1
 
 
 def test_null_handle_is_rejected_without_touching_a_device():

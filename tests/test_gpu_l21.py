@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 from paper_1904_07497_amd import respca as rp  # noqa: E402
 from paper_1904_07497_amd import synth  # noqa: E402
+from tests._trajectory import column_support_check, trajectory  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -139,6 +140,12 @@ def test_l21_solve_iteration_locked(shape, dtype, precision):
     tol = F64_TOL if dtype == np.float64 else F32_TOL
     assert rel(host(g["L"]), o["L"], nX) <= tol
     assert rel(host(g["S"]), o["S"], nX) <= tol
+    st, th_prev, rho_t, _ = trajectory(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=2,
+                                                             sparse_norm=1), T)
+    sep, zfrac = column_support_check(X.astype(np.float64), st["L"], th_prev, rho_t, host(g["S"]),
+                                      st["S"], np.finfo(dtype).eps)
+    say(f"l21 column support: {sep:.4f} separated, {zfrac:.4f} zero")
+    assert sep > 0.95 and 0 < zfrac < 1
     # free-running: same stopping iteration
     g2 = rp.solve(dev(X), rank=c, lam=lam, tol=1e-6, seed=2, precision=precision, sparse_norm=1)
     assert abs(g2["info"]["iters"] - T) <= 1

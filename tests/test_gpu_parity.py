@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 from paper_1904_07497_amd import respca as rp  # noqa: E402
 from paper_1904_07497_amd import synth  # noqa: E402
+from tests._trajectory import support_check, trajectory  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +86,11 @@ def test_solve_f64_small_config(lam):
     assert rel(host(g["L"]), o["L"], nX) <= F64_TOL
     assert rel(host(g["S"]), o["S"], nX) <= F64_TOL
     assert abs(gi["primal"] - oi["primal"]) <= 1e-9 * max(oi["primal"], 1e-12) + 1e-16
+    st, th_prev, rho_t, _ = trajectory(X, oracle.make_params(25, lam=lam, tol=1e-7, seed=0),
+                                       max_iter=oi["iters"])
+    frac = support_check(X, st["L"], th_prev, rho_t, host(g["S"]), st["S"], np.finfo(np.float64).eps)
+    say(f"S support: {frac:.4f} of entries separated")
+    assert frac > 0.99
 
 
 @pytest.mark.parametrize("shape,lam", [((1037, 777, 5), None), ((2051, 300, 7), 0.3),
@@ -106,6 +112,11 @@ def test_solve_f32_grouped_iteration_locked(shape, lam):
     nX = np.linalg.norm(X.astype(np.float64))
     assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
     assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+    st, th_prev, rho_t, _ = trajectory(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=1), T)
+    frac = support_check(X.astype(np.float64), st["L"], th_prev, rho_t, host(g["S"]), st["S"],
+                         np.finfo(np.float32).eps)
+    say(f"S support: {frac:.4f} of entries separated")
+    assert frac > 0.5
     # free-running: same stopping iteration
     g2 = rp.solve(dev(X), rank=c, lam=lam, tol=1e-6, seed=1)
     assert abs(g2["info"]["iters"] - T) <= 1
@@ -131,6 +142,11 @@ def test_solve_single_lloyd_step_matches_oracle(precision):
     nX = np.linalg.norm(X.astype(np.float64))
     assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
     assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+    st, th_prev, rho_t, _ = trajectory(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=3,
+                                                             max_lloyd=1), T)
+    frac = support_check(X.astype(np.float64), st["L"], th_prev, rho_t, host(g["S"]), st["S"],
+                         np.finfo(np.float32).eps)
+    assert frac > 0.5
 
 
 def test_solve_f32_video_clip_matches_oracle_and_table2_counts():
@@ -254,6 +270,69 @@ def test_iterate_full_size_sampled_columns():
     np.testing.assert_array_equal(lab[sep], o["labels"][sep])
 
 
+def test_gaussian_rank100_steps_along_the_oracle_trajectory():
+    """2000 x 2000, rank 100 (U, V iid N(0, 1)), 10 % corruptions in [-100, 100],
+    c = 100, lambda = 0.01 (the 10^4 x 10^4 workload's construction at a size the
+    oracle solves in under a minute).  At t = 1, T/2 and T - 1 of the oracle's own
+    trajectory (T its stop at tol 1e-6), one GPU iteration with the full p-step
+    (up to 100 Lloyd passes), FP32 and bounded mode, from the oracle's state cast
+    to FP32, against one oracle iteration from the same cast state: L, S and
+    Theta/rho to the FP32 bar, labels on well-separated columns, S support."""
+    d = n = 2000
+    c = 100
+    lam = 0.01
+    X, _, _ = synth.low_rank_plus_sparse(d, n, c, 0.10, 100.0, seed=11, dtype=np.float32)
+    Xo = X.astype(np.float64)
+    p = oracle.make_params(c, lam=lam, tol=1e-6, seed=1)
+    say("rank-100 trajectory: oracle")
+    o = oracle.solve(X, p)
+    T = o["info"]["iters"]
+    stops = sorted({1, T // 2, T - 1})
+    labels, C, _ = oracle.kmeans(Xo, c, 1, 100)
+    st = {"L": np.zeros((d, n), order="F"), "S": np.zeros((d, n), order="F"),
+          "Theta": np.zeros((d, n), order="F"), "labels": labels, "C": C, "rho": p.rho0}
+    nX = np.linalg.norm(Xo)
+    eps = np.finfo(np.float32).eps
+    for t in range(1, stops[-1] + 1):
+        st = oracle.step(p, Xo, st)
+        if t not in stops:
+            continue
+        # the state both sides start from: the oracle's iterate t, cast to FP32
+        cast = {k: (v.astype(np.float32).astype(np.float64) if k in ("L", "S", "Theta", "C") else v)
+                for k, v in st.items()}
+        ref = oracle.step(p, Xo, cast)
+        for prec in (rp.F32, rp.BF16GEMM_F32):
+            gs = _gpu_state(cast, np.float32)
+            _, info = rp.iterate(dev(X), gs, iters=1, lam=lam, max_lloyd=100, precision=prec)
+            lab = gs["labels"].cpu().numpy()
+            # labels: identical where the top-2 squared-distance gap of the oracle's
+            # last assignment (its final L against its final centroids) is clear of
+            # the FP32 rounding of the distances
+            dist = ((ref["L"][:, :, None] - ref["C"][:, None, :]) ** 2).sum(axis=0)
+            srt = np.sort(dist, axis=1)
+            cn = np.sqrt((ref["C"] ** 2).sum(axis=0)).max()
+            ln = np.sqrt((ref["L"] ** 2).sum(axis=0))
+            sep = (srt[:, 1] - srt[:, 0]) > 2 * d * eps * (cn ** 2 + 2 * cn * ln + ln ** 2)
+            flips = int((lab != ref["labels"]).sum())
+            say(f"t={t}/{T} precision={prec}: Lloyd {info['lloyd_steps']}/{ref['lloyd']}, "
+                f"label flips {flips}, separated {sep.mean():.3f}")
+            np.testing.assert_array_equal(lab[sep], ref["labels"][sep])
+            if flips == 0:
+                assert info["lloyd_steps"] == ref["lloyd"]
+            # L, S and Theta come before the p-step in the iteration (they use the
+            # groups the state carries), so they are compared whatever the labels
+            for k in ("L", "S"):
+                assert rel(host(gs[k]), ref[k], nX) <= F32_TOL, (t, prec, k)
+            # Theta / rho is a term of D = X - S + Theta / rho, so its error is measured
+            # on the scale of X (for unsaturated entries Theta = rho B, and B = X - L +
+            # Theta / rho carries the FP32 rounding of X - L)
+            dth = np.linalg.norm(host(gs["Theta"]) / cast["rho"] - ref["Theta"] / cast["rho"]) / nX
+            assert dth <= F32_TOL, (t, prec, dth)
+            frac = support_check(Xo, ref["L"], cast["Theta"], cast["rho"], host(gs["S"]),
+                                 ref["S"], eps)
+            assert frac > 0.5
+
+
 # ------------------------------------------------------------- full size
 
 @pytest.mark.parametrize("precision", [rp.F32, rp.BF16GEMM_F32])
@@ -356,6 +435,10 @@ def test_bf16_solve_matches_oracle(shape, lam):
     nX = np.linalg.norm(X.astype(np.float64))
     assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
     assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+    st, th_prev, rho_t, _ = trajectory(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=1), T)
+    frac = support_check(X.astype(np.float64), st["L"], th_prev, rho_t, host(g["S"]), st["S"],
+                         np.finfo(np.float32).eps)
+    assert frac > 0.5
 
 
 def test_bf16_kmeans_matches_oracle():
@@ -533,22 +616,51 @@ def _batch_mix(seed=7):
     return shapes, Xs
 
 
-def test_batched_matches_oracle_per_instance():
-    """Every instance of a ragged batch, solved in one persistent launch, meets the
-    FP32 bar against the oracle run on that instance alone (iteration-locked)."""
-    shapes, Xs = _batch_mix()
-    lams = [0.5 if i % 3 == 0 else float(np.sqrt(max(s[0], s[1]))) for i, s in enumerate(shapes)]
-    T = []
-    for X, (d, n, c), lam, i in zip(Xs, shapes, lams, range(len(shapes))):
-        o = oracle.solve(X, oracle.make_params(c, lam=lam, tol=1e-6, seed=i))
-        T.append(o)
+_BATCH_ORACLE = {}
+
+
+def _batch_mix_oracle():
+    """The ragged mix and, per instance, the oracle's trajectory to its stop at
+    tol 1e-6 (computed once per test session)."""
+    if not _BATCH_ORACLE:
+        shapes, Xs = _batch_mix()
+        lams = [0.5 if i % 3 == 0 else float(np.sqrt(max(s[0], s[1]))) for i, s in enumerate(shapes)]
+        runs = []
+        for i, (X, (d, n, c), lam) in enumerate(zip(Xs, shapes, lams)):
+            p = oracle.make_params(c, lam=lam, tol=1e-6, seed=i)
+            o = oracle.solve(X, p)
+            runs.append((o, trajectory(X, p, o["info"]["iters"])))
+        _BATCH_ORACLE.update(shapes=shapes, Xs=Xs, lams=lams, runs=runs)
+    return _BATCH_ORACLE
+
+
+# (jc, slice_rows, blocks_per_cu): the default, the tuner's corners and the shape
+# the tuner picks for the 256-instance mix
+BATCH_TILES = [(8, 1024, 2), (4, 512, 1), (32, 2048, 2), (4, 2048, 2), (32, 512, 1),
+               (16, 1024, 2)]
+
+
+@pytest.mark.parametrize("tile", BATCH_TILES)
+def test_batched_matches_oracle_per_instance(tile):
+    """Every instance of a ragged batch, solved in one persistent launch with the
+    given tile shape, meets the FP32 bar against the oracle run on that instance
+    alone (iteration-locked): labels, initial Lloyd count, L, S and the support
+    of S on well-separated entries."""
+    mix = _batch_mix_oracle()
+    shapes, Xs, lams, runs = mix["shapes"], mix["Xs"], mix["lams"], mix["runs"]
+    rp.set_batched_tile(*tile)
+    assert rp.get_batched_tile() == tile
     plist, keep = rp.batch_params([s[2] for s in shapes], lams, tol=0.0,
                                   max_iter=0, seeds=list(range(len(shapes))))
-    for p, o in zip(plist, T):
+    for p, (o, _) in zip(plist, runs):
         p.max_iter = o["info"]["iters"]
     Xd = [dev(X) for X in Xs]
-    outs, infos, status = rp.solve_batched(Xd, plist)
-    for i, (X, o) in enumerate(zip(Xs, T)):
+    say(f"batched tile {tile}")
+    try:
+        outs, infos, status = rp.solve_batched(Xd, plist)
+    finally:
+        rp.set_batched_tile(8, 1024, 2)
+    for i, (X, (o, (st, th_prev, rho_t, _))) in enumerate(zip(Xs, runs)):
         say(f"batched instance {i} {shapes[i]} iters {infos[i]['iters']} / {o['info']['iters']}")
         assert infos[i]["iters"] == o["info"]["iters"]
         assert infos[i]["init_lloyd"] == o["info"]["init_lloyd"]
@@ -556,6 +668,84 @@ def test_batched_matches_oracle_per_instance():
         nX = np.linalg.norm(X.astype(np.float64))
         assert rel(host(outs[i][0]), o["L"], nX) <= F32_TOL, i
         assert rel(host(outs[i][1]), o["S"], nX) <= F32_TOL, i
+        frac = support_check(X.astype(np.float64), st["L"], th_prev, rho_t, host(outs[i][1]),
+                             st["S"], np.finfo(np.float32).eps)
+        assert frac > 0.5, (i, frac)
+
+
+# the eight smallest instances (by d n) of the 256-instance size mix, seeds 3 000 000 + i
+CONFIG3_SMALLEST = [134, 192, 99, 123, 246, 199, 136, 142]
+
+
+def test_batched_size_mix_instances_match_oracle():
+    """Instances of the 256-instance size mix itself (Gaussian U V^T of rank 5-50,
+    1-20 % corruptions in [-50, 50], c = rank, lambda = 1/sqrt(max(d, n))), solved
+    together in one persistent launch, each iteration-locked to the oracle's stop
+    at tol 1e-6 with the full p-step (up to 100 Lloyd passes): labels, initial
+    Lloyd counts, L and S to the FP32 bar and the support of S on well-separated
+    entries.  The data have no group structure, so K-means decisions can be close;
+    every label that differs from the oracle's is printed."""
+    Xs, ranks, lams, runs = [], [], [], []
+    for k, i in enumerate(CONFIG3_SMALLEST):
+        X, r, meta = synth.batch_instance(i)
+        lam = 1.0 / np.sqrt(max(meta["d"], meta["n"]))
+        p = oracle.make_params(r, lam=lam, tol=1e-6, seed=k)
+        o = oracle.solve(X, p)
+        assert o["status"] == 0
+        Xs.append(X)
+        ranks.append(r)
+        lams.append(lam)
+        runs.append((o, trajectory(X, p, o["info"]["iters"])))
+    plist, _ = rp.batch_params(ranks, lams, tol=0.0, max_iter=0, seeds=list(range(len(Xs))))
+    for p, (o, _) in zip(plist, runs):
+        p.max_iter = o["info"]["iters"]
+    outs, infos, _ = rp.solve_batched([dev(X) for X in Xs], plist)
+    for k, (X, (o, (st, th_prev, rho_t, _))) in enumerate(zip(Xs, runs)):
+        lab = outs[k][2].cpu().numpy()
+        flips = np.flatnonzero(lab != o["labels"])
+        say(f"size-mix instance {CONFIG3_SMALLEST[k]} {X.shape} c={ranks[k]}: iters "
+            f"{infos[k]['iters']}/{o['info']['iters']}, init Lloyd {infos[k]['init_lloyd']}/"
+            f"{o['info']['init_lloyd']}, label flips {flips.size} {flips[:10].tolist()}")
+        assert infos[k]["iters"] == o["info"]["iters"]
+        assert infos[k]["init_lloyd"] == o["info"]["init_lloyd"]
+        assert flips.size == 0
+        nX = np.linalg.norm(X.astype(np.float64))
+        assert rel(host(outs[k][0]), o["L"], nX) <= F32_TOL, k
+        assert rel(host(outs[k][1]), o["S"], nX) <= F32_TOL, k
+        frac = support_check(X.astype(np.float64), st["L"], th_prev, rho_t, host(outs[k][1]),
+                             st["S"], np.finfo(np.float32).eps)
+        assert frac > 0.5, (k, frac)
+
+
+def test_batched_tile_setter_and_tuned_cache(tmp_path):
+    """Tile shapes outside the tuner's candidates are refused; the tuner's choice
+    is written to the cache file, read back by a later call (same key), and a
+    line with a shape outside the candidates is ignored (the tuner runs again)."""
+    with pytest.raises(rp.RespcaError):
+        rp.set_batched_tile(0, 1024, 2)
+    with pytest.raises(rp.RespcaError):
+        rp.set_batched_tile(8, 1000, 2)
+    assert rp.get_batched_tile() == (8, 1024, 2)
+    shapes, Xs = _batch_mix()
+    lams = [1.0] * len(shapes)
+    plist, _ = rp.batch_params([s[2] for s in shapes], lams, tol=1e-4, max_iter=5)
+    Xd = [dev(X) for X in Xs]
+    cache = tmp_path / "tune.txt"
+    ms = rp.autotune_batched(Xd, plist, cache_path=str(cache))
+    tuned = rp.get_batched_tile()
+    lines = cache.read_text().split()
+    assert len(lines) == 5 and tuple(int(v) for v in lines[1:4]) == tuned and ms > 0
+    key = lines[0]
+    assert "_k3_" in key
+    rp.set_batched_tile(*(BATCH_TILES[1] if tuned != BATCH_TILES[1] else BATCH_TILES[2]))
+    assert rp.autotune_batched(Xd, plist, cache_path=str(cache)) == pytest.approx(float(lines[4]))
+    assert rp.get_batched_tile() == tuned
+    # a corrupt line for the same key is skipped: the tuner searches and appends again
+    cache.write_text(f"{key} 0 1024 2 0.001\n")
+    rp.autotune_batched(Xd, plist, cache_path=str(cache))
+    rows = cache.read_text().strip().split("\n")
+    assert len(rows) == 2 and rows[1].split()[0] == key
+    rp.set_batched_tile(8, 1024, 2)
 
 
 def test_batched_special_instances_and_replay():

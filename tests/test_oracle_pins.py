@@ -707,3 +707,24 @@ def test_adam_second_and_third_steps_by_hand():
         assert m[0] == pytest.approx(expect_m[step - 1], rel=1e-15)
         assert v[0] == pytest.approx(expect_v[step - 1], rel=1e-15)
         assert p[0] == pytest.approx(expect_p[step - 1], rel=1e-14)
+
+
+@pytest.mark.parametrize("sparse_norm,use_init", [(0, False), (1, False), (0, True)])
+def test_stepwise_trajectory_reproduces_the_solve(orc, sparse_norm, use_init):
+    """The test helper that drives the oracle one iteration at a time (to expose
+    the last S-step's inputs) ends exactly where oracle.solve ends."""
+    from tests._trajectory import trajectory
+    from paper_1904_07497_amd import synth
+    X, _, _, _ = synth.clustered(40, 60, 3, seed=5, sep=4.0, noise=0.5, frac=0.05, amp=10.0)
+    p = orc.make_params(3, lam=0.7, tol=1e-7, seed=2, sparse_norm=sparse_norm)
+    init = np.arange(60, dtype=np.int32) % 3 if use_init else None
+    o = orc.solve(X, p, init_labels=init)
+    st, th_prev, rho_t, T = trajectory(X, p, init_labels=init)
+    assert T == o["info"]["iters"] > 2
+    np.testing.assert_array_equal(st["L"], o["L"])
+    np.testing.assert_array_equal(st["S"], o["S"])
+    np.testing.assert_array_equal(st["labels"], o["labels"])
+    assert rho_t == o["info"]["rho_final"]
+    # the last multiplier update: Theta_T - Theta_{T-1} = rho_T (X - L - S)
+    np.testing.assert_allclose(st["Theta"] - th_prev, rho_t * (X - st["L"] - st["S"]),
+                               atol=1e-12 * np.abs(X).max() * max(rho_t, 1.0))
