@@ -68,11 +68,12 @@ WORKLOADS = {
                        "oracle's whole solve", d=500, n=500, rank=25, lam=1.0 / 500 ** 0.5, tol=1e-7,
                   seeds=(0, 1, 2, 3, 4), gen="small"),
     "spectral": dict(name="RES-PCA FP32 with the spectral-clustering p-step (Sec. 4.2 nonlinear "
-                          "alternative): 3 concentric rings (radii 1, 3, 6; 2000, 2500, 3500 points) in "
-                          "a random plane of R^2000, N(0, 0.02^2) noise, 1% of entries offset by "
-                          "U[-1, 1], c=3, sigma=0.7, lambda=0.2, tol=1e-6", d=2000,
-                     counts=(2000, 2500, 3500), radii=(1.0, 3.0, 6.0), rank=3, sigma=0.7, lam=0.2,
-                     tol=1e-6, gen="spectral"),
+                          "alternative): 3 concentric rings (radii 1, 4, 7; 2000, 2500, 3500 points) in "
+                          "a random plane of R^2000, N(0, 0.002^2) noise, 0.02% of entries offset by "
+                          "U[-0.3, 0.3], c=3, kernel width 0.1 x the columns' spread (relative), "
+                          "lambda=0.05, tol=1e-6", d=2000,
+                     counts=(2000, 2500, 3500), radii=(1.0, 4.0, 7.0), noise=0.002, frac=0.0002,
+                     amp=0.3, rank=3, sigma=-0.1, lam=0.05, tol=1e-6, gen="spectral"),
     "scaling": dict(name="scalability (Sec. 5): seeded random subsets of the synthetic 240x320x2000 "
                          "clip at ratios 1/8, 1/4, 1/2, 1 of n (all d) and of d (all n), c=5, "
                          "lambda=sqrt(max(d,n)), 30 outer iterations (no tolerance), 10 runs each",
@@ -408,7 +409,8 @@ def bench_warmstart(args, wl):
         infos, keep = [], []
         for Xs, ranks, lams, outs in chunks:
             emb, rho0s, fbs = rp.warmstart_batched(Xs, ranks, P, hidden, sseed)
-            plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s, init_embeddings=emb)
+            plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s, init_embeddings=emb,
+                                       embedding_refine=args.embedding_refine)
             infos += rp.solve_batched(Xs, plist, outs=outs)[1]
             keep.append((emb, k, fbs))
         return infos, keep
@@ -468,6 +470,7 @@ def bench_warmstart(args, wl):
                    "warm_converged": sum(f["status"] == 0 for f in warm),
                    "cold_converged": sum(f["status"] == 0 for f in cold),
                    "fallbacks": int(fallbacks),
+                   "embedding_refine": args.embedding_refine,
                    "err_vs_planted_ratio_warm_over_cold": {
                        "median": round(float(np.median(ratio)), 5), "max": round(float(ratio.max()), 5)},
                    "tuner_seconds": round(tune_s, 2)},
@@ -519,10 +522,17 @@ UNIT_KERNELS = {
     "sweep": ("k_sweep_seg",),
     "means": ("k_group_partial",),
     "distance": ("k_split_centroids", "k_dist_", "k_refine_", "k_assign_finish", "k_argmin",
-                 "k_col_sqnorm", "respca::k_assign_finish"),
+                 "k_col_sqnorm"),
     "colnorm": ("k_l21_factor",),
     "batched": ("k_batched",),
 }
+
+
+def kernel_base(name):
+    """The kernel's own identifier from a (demangled or mangled) dispatch name."""
+    import re
+    m = re.search(r"(k_[a-z0-9_]+)", name)
+    return m.group(1) if m else name
 
 
 def read_counter_csvs(root):
@@ -560,11 +570,11 @@ def summarize_counters(unit, workload, root):
     fetch, write = one(workload, "FETCH_SIZE"), one(workload, "WRITE_SIZE")
     parts, total = [], 0.0
     for name in sorted(fetch):
-        if not any(name.startswith(p) for p in UNIT_KERNELS[unit]):
+        if not any(kernel_base(name).startswith(p) for p in UNIT_KERNELS[unit]):
             continue
         fb = fetch[name][0] * 1024.0 * factors["FETCH_SIZE"]
         wb = write.get(name, (0.0, 0))[0] * 1024.0 * factors["WRITE_SIZE"]
-        parts.append({"kernel": name, "dispatches": fetch[name][1],
+        parts.append({"kernel": name.split("(")[0], "dispatches": fetch[name][1],
                       "fetch_kib_per_dispatch": round(fetch[name][0], 1),
                       "write_kib_per_dispatch": round(write.get(name, (0.0, 0))[0], 1),
                       "fetch_bytes_per_dispatch": int(fb), "write_bytes_per_dispatch": int(wb)})
@@ -590,6 +600,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the other precision in the same run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--embedding-refine", type=int, default=1, choices=[0, 1],
+                    help="warmstart workload: Lloyd passes on X after the embedding's K-means (1) "
+                         "or the iterations straight from the embedding's groups (0)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the last-iteration comparison with the FP64 oracle")
     ap.add_argument("--tune-cache", default=None,
@@ -773,8 +786,8 @@ def bench_spectral(args, wl):
     from paper_1904_07497_amd import respca as rp
     from paper_1904_07497_amd import synth
 
-    X, ring = synth.rings(counts=wl["counts"], radii=wl["radii"], d=wl["d"], noise=0.02, seed=5,
-                          frac=0.01, amp=1.0, dtype=np.float32)
+    X, ring = synth.rings(counts=wl["counts"], radii=wl["radii"], d=wl["d"], noise=wl["noise"], seed=5,
+                          frac=wl["frac"], amp=wl["amp"], dtype=np.float32)
     d, n = X.shape
     Xd = torch.from_numpy(X).to("cuda:0")
     kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=rp.F32,
@@ -796,8 +809,10 @@ def bench_spectral(args, wl):
     prof = rp.profile_query()
     rp.profile_enable(False)
     lab = out[2].cpu().numpy()
-    recovered = bool(np.array_equal(lab == lab[0], ring == ring[0]) or
-                     all(len(set(lab[ring == r])) == 1 for r in range(len(wl["counts"]))))
+    groups = len(wl["counts"])
+    recovered = bool(all(len(set(lab[ring == r])) == 1 for r in range(groups))
+                     and len(set(lab.tolist())) == groups)
+    ring_groups = [np.bincount(lab[ring == r], minlength=wl["rank"]).tolist() for r in range(groups)]
 
     def unit(name, peak, unit_name, use_flops):
         k = prof[name]
@@ -825,7 +840,8 @@ def bench_spectral(args, wl):
         "data": "synthetic",
         "config": {"workload": wl["name"], "d": d, "n": n, "c": wl["rank"], "iters": info["iters"],
                    "lloyd_steps": info["lloyd_steps"], "eig_iters": info["eig_iters"],
-                   "eig_unconverged": info["eig_unconverged"], "rings_recovered": recovered},
+                   "eig_unconverged": info["eig_unconverged"], "rings_recovered": recovered,
+                   "groups_per_ring": ring_groups},
         "roofline": unit("affinity", 78.6, "TFLOP/s", True),
         "eigen_roofline": unit("eigen", HBM_PEAK_GBS, "GB/s", False),
         "sweep_roofline": unit("sweep", HBM_PEAK_GBS, "GB/s", False),

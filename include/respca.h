@@ -117,8 +117,16 @@ typedef struct {
     int32_t  sparse_norm; /* respca_sparse_norm; default RESPCA_SPARSE_L1; other values
                              RESPCA_ERR_INVALID                                             */
     int32_t  pstep;       /* respca_pstep; default RESPCA_PSTEP_KMEANS                      */
-    double   spectral_sigma; /* kernel width sigma of the spectral p-step (> 0, finite; the
-                             paper gives none); ignored by the K-means p-step; default 0   */
+    double   spectral_sigma; /* kernel width of the spectral p-step (the paper gives none):
+                             > 0 the width sigma itself; < 0 relative, sigma = |value| times
+                             the RMS distance of the clustered columns to their mean column
+                             (follows the scale of L, which the L-step shrinks toward the
+                             group means in early iterations); 0 or non-finite
+                             RESPCA_ERR_INVALID with the spectral p-step; default 0        */
+    int32_t  init_embedding_refine; /* with init_embedding: 1 (default) runs the Lloyd passes
+                             on X after the embedding's K-means, 0 starts the iterations
+                             from the embedding's groups directly; other values
+                             RESPCA_ERR_INVALID                                             */
 } respca_params;
 
 typedef struct {
@@ -134,7 +142,7 @@ typedef struct {
                              zero at most 16 groups, where nothing is re-taken)          */
     int32_t eig_iters;    /* spectral p-step: filtered subspace iterations, all p-steps  */
     int32_t eig_unconverged; /* spectral p-step: embeddings whose eigen residual stayed
-                             above 1e-10 after 200 iterations                            */
+                             above 1e-10 after 100 iterations                            */
 } respca_info;
 
 typedef struct respca_handle_s *respca_handle;
@@ -233,7 +241,9 @@ respca_status respca_kmeans(respca_handle h, const respca_params *params,
  * the columns of Y (d x n, ldy; double if precision is RESPCA_F64, else float)
  * emb (device, c x n doubles, leading dimension c) receives the unit rows of
  * the eigenvectors of the c largest eigenvalues of D^{-1/2} W D^{-1/2},
- * W_ij = exp(-||Y_i - Y_j||^2 / (2 sigma^2)), W_ii = 0 (any orthonormal basis of
+ * W_ij = exp(-||Y_i - Y_j||^2 / (2 s^2)), W_ii = 0, s = sigma for sigma > 0 and
+ * |sigma| times the RMS distance of the columns to their mean for sigma < 0
+ * (sigma = 0 or non-finite: RESPCA_ERR_INVALID) (any orthonormal basis of
  * that eigenspace: K-means of the rows depends only on their distances).
  * eigenvalues (host, nullable) receives the c largest eigenvalues (decreasing),
  * info (host, nullable) eig_iters / eig_unconverged.  Limits as for the p-step.
@@ -317,7 +327,7 @@ typedef enum {
     RESPCA_KERNEL_COLNORM = 5,    /* l2,1 S-step column norms: reads X, S, Theta                     */
     RESPCA_KERNEL_AFFINITY = 6,   /* spectral p-step: Gram matrix on FP64 MFMA + Gaussian affinity;
                                      bytes = the d x n operand + the n x n FP64 affinity written,
-                                     flops = 2 n^2 d                                               */
+                                     flops = n (n + 1) d (the symmetric half of Y^T Y)             */
     RESPCA_KERNEL_EIGEN = 7,      /* spectral p-step: one block product A Y (reads the n x n
                                      normalised affinity; flops 2 n^2 k, k = min(n, c + 8))        */
     RESPCA_KERNEL_COUNT = 8

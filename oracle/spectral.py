@@ -10,6 +10,7 @@ direct nonlinear extension).  The paper gives no further detail, so this module
 takes the normalised spectral clustering of Ng, Jordan & Weiss (NIPS 2001):
 
   affinity      W_ij = exp(-||y_i - y_j||^2 / (2 sigma^2)) for i != j, W_ii = 0
+                (sigma given, or a multiple of the columns' spread: kernel_width)
   normalisation A = D^{-1/2} W D^{-1/2},  D = diag(sum_j W_ij)
                 (a point with zero degree gets a zero row and column)
   embedding     U = eigenvectors of the c largest eigenvalues of A (n x c)
@@ -33,15 +34,33 @@ import numpy as np
 import oracle
 
 
+def spread(Y):
+    """Root mean square distance of the columns of Y to their mean column."""
+    Y = np.asarray(Y, np.float64)
+    mean = Y.mean(axis=1, keepdims=True)
+    return float(np.sqrt(np.mean(np.sum((Y - mean) ** 2, axis=0))))
+
+
+def kernel_width(Y, sigma):
+    """The kernel width: sigma itself when positive; when negative, |sigma| times the
+    spread of the columns (a width that follows the scale of L, which the L-step
+    shrinks toward the group means by rho / (2 lambda + rho) in early iterations)."""
+    return sigma if sigma > 0 else -sigma * spread(Y)
+
+
 def affinity(Y, sigma):
     """W (n x n) for the columns of Y (d x n): Gaussian kernel of the squared
-    Euclidean distance, computed as the sum of squared differences; zero diagonal."""
+    Euclidean distance, computed as the sum of squared differences; zero diagonal.
+    sigma < 0 selects the relative width of kernel_width."""
     Y = np.asarray(Y, np.float64)
     n = Y.shape[1]
+    sigma = kernel_width(Y, sigma)
+    # a zero width (all columns equal) makes every distance zero: W = 1 off the diagonal
+    inv = 0.0 if sigma == 0.0 else 1.0 / (2.0 * sigma * sigma)
     W = np.zeros((n, n))
     for j in range(n):
         diff = Y - Y[:, j:j + 1]
-        W[:, j] = np.exp(-np.sum(diff * diff, axis=0) / (2.0 * sigma * sigma))
+        W[:, j] = np.exp(-np.sum(diff * diff, axis=0) * inv)
         W[j, j] = 0.0
     return W
 

@@ -54,6 +54,7 @@ struct BatchInst {
     // parameters
     double lambda, tol, rho0, kappa, rho_max;
     int max_iter, max_lloyd;
+    int refine_x;              // embedding starts: Lloyd on X after the embedding's K-means
     // state
     int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, ref_lloyd, status, nseg;
     int next_ready;            // pmeans and the sort tables hold the next L-step's group sums

@@ -360,7 +360,7 @@ __device__ void control_instance(BatchInst& B, int* active) {
     const int mode = mode0;
     B.pmode = mode;
     if (mode == M_MEANSX) {   // embedding groups: Lloyd on X next, once; then the iterations
-        if (B.Z && B.ref_lloyd == 0) { B.mode = M_REFX; } else { B.mode = M_ITER; }
+        if (B.Z && B.refine_x && B.ref_lloyd == 0) { B.mode = M_REFX; } else { B.mode = M_ITER; }
         return;
     }
     const int changed = (int)ch;

@@ -113,6 +113,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.init_labels = r.init_labels;
         B.Ec = r.init_embedding;
         B.lde = r.emb_ld;
+        B.refine_x = r.emb_refine;
         B.ldx = ldx[i];
         B.ldl = ldl[i];
         B.lds = lds[i];

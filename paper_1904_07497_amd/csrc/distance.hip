@@ -915,7 +915,7 @@ size_t assign_workspace_bytes<float>(int64_t d, int64_t n, int c) {
 
 template <>
 size_t assign_workspace_bytes<double>(int64_t d, int64_t n, int c) {
-    return (size_t)row_blocks(d) * (size_t)c * (size_t)n * sizeof(double);
+    return (size_t)dots_slices(d, n, c) * (size_t)c * (size_t)n * sizeof(double);
 }
 
 template <>
@@ -1049,7 +1049,7 @@ int launch_assign<double>(const double* C, int64_t d, int c, const double* Y, in
     if (changed_extra) *changed_extra = 0;
     double* part = (double*)work;
     launch_dots<double>(C, d, c, Y, ldy, n, part, st);
-    return launch_argmin<double>(part, row_blocks(d), c, n, cnorm, old_labels, new_labels,
+    return launch_argmin<double>(part, dots_slices(d, n, c), c, n, cnorm, old_labels, new_labels,
                                  changed_partial, st);
 }
 

@@ -71,7 +71,8 @@ struct respca_handle_s {
     respca::DevBuf probe;           // arrays of the bandwidth probe
     // spectral p-step: affinity (n x n), norms, scales, eigen blocks, partials,
     // small matrices, the row embedding and its centroids
-    respca::DevBuf sp_w, sp_q, sp_s, sp_y, sp_z, sp_yp, sp_t, sp_part, sp_small, sp_emb, sp_cent;
+    respca::DevBuf sp_w, sp_q, sp_s, sp_y, sp_z, sp_yp, sp_t, sp_part, sp_small, sp_emb, sp_cent,
+        sp_mean;
     double* sp_status = nullptr;      // pinned host words the eigen loop reads back
     double* sp_status_dev = nullptr;
     // Carving mode of ensure(): while arena_on, buffers are cut from [arena_base,
@@ -200,6 +201,7 @@ struct Resolved {
     const float* init_embedding;
     int64_t emb_ld;
     int emb_rows;
+    int emb_refine;   // Lloyd on X after the embedding's K-means (1) or not (0)
 };
 
 respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_t n, Resolved& r);

@@ -96,7 +96,12 @@ void launch_l21_factor(const T* X, int64_t ldx, const T* S, int64_t lds, const T
                        double beta, double rho, double inv_rho, double* fac, hipStream_t st);
 
 
-// Split-d centroid/column dot products: part[(rb*c + k)*n + j] = sum_{i in slice rb} C[i,k] Y[i,j].
+// Split-d centroid/column dot products: part[(rb*c + k)*n + j] = sum_{i in slice rb} C[i,k] Y[i,j],
+// over dots_slices(d, n, c) slices of dots_slice_rows(d, n, c) rows (whole 32-row
+// stages, at most kRowsPerBlock; short slices when the column tiles alone would
+// leave the GPU idle).
+int64_t dots_slice_rows(int64_t d, int64_t n, int c);
+int dots_slices(int64_t d, int64_t n, int c);
 template <typename T>
 void launch_dots(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t n, T* part,
                  hipStream_t st);

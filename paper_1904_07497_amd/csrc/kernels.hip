@@ -462,12 +462,12 @@ __global__ __launch_bounds__(kBlock) void k_l21_factor(
 
 // -------------------------------------------------------------------- dots
 
-// Tile: 64 columns x CT = 16*KB groups, over one kRowsPerBlock slice of rows,
+// Tile: 64 columns x CT = 16*KB groups, over one slice of slice_rows rows,
 // staged through LDS 32 rows at a time; each thread owns a KB x 4 block.
 template <typename T, int KB>
 __global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ C, int64_t d, int c,
                                                  const T* __restrict__ Y, int64_t ldy, int64_t n,
-                                                 T* __restrict__ part) {
+                                                 int64_t slice_rows, T* __restrict__ part) {
     constexpr int CT = 16 * KB, JT = 64, RT = 32;
     __shared__ T As[RT][CT + 4];
     __shared__ T Bs[RT][JT + 4];
@@ -475,8 +475,8 @@ __global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ C, int64_
     const int64_t j0 = (int64_t)blockIdx.x * JT;
     const int k0 = blockIdx.y * CT;
     const int rb = blockIdx.z;
-    const int64_t rbeg = (int64_t)rb * kRowsPerBlock;
-    const int64_t rend = rbeg + kRowsPerBlock < d ? rbeg + kRowsPerBlock : d;
+    const int64_t rbeg = (int64_t)rb * slice_rows;
+    const int64_t rend = rbeg + slice_rows < d ? rbeg + slice_rows : d;
     T acc[KB][4];
 #pragma unroll
     for (int a = 0; a < KB; ++a)
@@ -524,23 +524,35 @@ __global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ C, int64_
     }
 }
 
+// Sixteen lanes per column: lane q scores groups q, q + 16, ... (slices summed in
+// order), then the lanes keep the smallest distance, the lowest group on ties.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_argmin(const T* __restrict__ part, int nrb, int c,
                                                    int64_t n, const double* __restrict__ cnorm,
                                                    const int32_t* __restrict__ old_labels,
                                                    int32_t* __restrict__ new_labels,
                                                    double* __restrict__ changed_partial) {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double changed = 0.0;
-    if (j < n) {
-        int best = 0;
-        double bestd = INFINITY;
-        for (int k = 0; k < c; ++k) {
+    const int q = threadIdx.x & 15;
+    const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = j < n;
+    double bestd = INFINITY;
+    int bestk = INT_MAX;
+    if (live)
+        for (int k = q; k < c; k += 16) {
             double dot = 0.0;
             for (int rb = 0; rb < nrb; ++rb) dot += (double)part[((int64_t)rb * c + k) * n + j];
             const double dist = cnorm[k] - 2.0 * dot;
-            if (dist < bestd) { bestd = dist; best = k; }
+            if (dist < bestd) { bestd = dist; bestk = k; }
         }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        const double od = __shfl_xor(bestd, o, 16);
+        const int ok = __shfl_xor(bestk, o, 16);
+        if (od < bestd || (od == bestd && ok < bestk)) { bestd = od; bestk = ok; }
+    }
+    double changed = 0.0;
+    if (live && q == 0) {
+        const int best = bestk == INT_MAX ? 0 : bestk;
         new_labels[j] = best;
         changed = (old_labels[j] != best) ? 1.0 : 0.0;
     }
@@ -956,23 +968,41 @@ void launch_l21_factor(const T* X, int64_t ldx, const T* S, int64_t lds, const T
                                                     (T)alpha, (T)beta, (T)inv_rho, rho, fac);
 }
 
+int64_t dots_slice_rows(int64_t d, int64_t n, int c) {
+    const int64_t ct = c <= 32 ? 32 : (c <= 64 ? 64 : 128);
+    const int64_t tiles = ((n + 63) / 64) * ((c + ct - 1) / ct);
+    int64_t slices = (512 + tiles - 1) / tiles;                 // about 512 workgroups
+    const int64_t stages = (d + 31) / 32;
+    if (slices > stages) slices = stages;
+    if (slices < 1) slices = 1;
+    int64_t rows = ((d + slices - 1) / slices + 31) / 32 * 32;  // whole 32-row stages
+    if (rows > kRowsPerBlock) rows = kRowsPerBlock;
+    return rows;
+}
+
+int dots_slices(int64_t d, int64_t n, int c) {
+    const int64_t rows = dots_slice_rows(d, n, c);
+    return (int)((d + rows - 1) / rows);
+}
+
 template <typename T>
 void launch_dots(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t n, T* part,
                  hipStream_t st) {
-    const unsigned gx = (unsigned)((n + 63) / 64), gz = (unsigned)row_blocks(d);
+    const int64_t rows = dots_slice_rows(d, n, c);
+    const unsigned gx = (unsigned)((n + 63) / 64), gz = (unsigned)dots_slices(d, n, c);
     if (c <= 32)
-        k_dots<T, 2><<<dim3(gx, (c + 31) / 32, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, part);
+        k_dots<T, 2><<<dim3(gx, (c + 31) / 32, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, rows, part);
     else if (c <= 64)
-        k_dots<T, 4><<<dim3(gx, (c + 63) / 64, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, part);
+        k_dots<T, 4><<<dim3(gx, (c + 63) / 64, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, rows, part);
     else
-        k_dots<T, 8><<<dim3(gx, (c + 127) / 128, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, part);
+        k_dots<T, 8><<<dim3(gx, (c + 127) / 128, gz), kBlock, 0, st>>>(C, d, c, Y, ldy, n, rows, part);
 }
 
 template <typename T>
 int launch_argmin(const T* part, int nrb, int c, int64_t n, const double* cnorm,
                   const int32_t* old_labels, int32_t* new_labels, double* changed_partial,
                   hipStream_t st) {
-    const int g = (int)((n + kBlock - 1) / kBlock);
+    const int g = (int)((n + 15) / 16);
     k_argmin<T><<<g, kBlock, 0, st>>>(part, nrb, c, n, cnorm, old_labels, new_labels,
                                       changed_partial);
     return g;

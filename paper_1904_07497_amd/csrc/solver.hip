@@ -85,11 +85,14 @@ respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d
     r.init_embedding = p->init_labels ? nullptr : (const float*)p->init_embedding;
     r.emb_ld = p->init_embedding_ld;
     r.emb_rows = p->init_embedding_rows;
+    r.emb_refine = p->init_embedding_refine;
     if (r.init_embedding) {
         if (r.emb_rows < 1 || r.emb_ld < r.emb_rows)
             return fail(h, RESPCA_ERR_INVALID, "init_embedding rows/leading dimension invalid");
         if (p->precision == RESPCA_F64)
             return fail(h, RESPCA_ERR_UNSUPPORTED, "init_embedding needs an FP32 precision");
+        if (r.emb_refine != 0 && r.emb_refine != 1)
+            return fail(h, RESPCA_ERR_INVALID, "init_embedding_refine must be 0 or 1");
     }
     if (!(r.lambda >= 0.0) || !std::isfinite(2.0 * r.lambda))
         return fail(h, RESPCA_ERR_INVALID, "lambda must be finite and >= 0");
@@ -108,8 +111,8 @@ respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d
     if (r.pstep != RESPCA_PSTEP_KMEANS && r.pstep != RESPCA_PSTEP_SPECTRAL)
         return fail(h, RESPCA_ERR_INVALID, "pstep must be RESPCA_PSTEP_KMEANS or RESPCA_PSTEP_SPECTRAL");
     if (r.pstep == RESPCA_PSTEP_SPECTRAL) {
-        if (!(r.sigma > 0.0) || !std::isfinite(r.sigma))
-            return fail(h, RESPCA_ERR_INVALID, "spectral_sigma must be finite and > 0");
+        if (r.sigma == 0.0 || !std::isfinite(r.sigma))
+            return fail(h, RESPCA_ERR_INVALID, "spectral_sigma must be finite and nonzero");
         if (r.c > kSpectralMaxGroups || n > kSpectralMaxN)
             return fail(h, RESPCA_ERR_UNSUPPORTED, "spectral p-step: c <= 40 and n <= 32768");
         if (r.init_embedding)
@@ -423,7 +426,8 @@ struct Engine {
         CKS(ensure(h, h->sp_cent, (size_t)c * c * sizeof(double)));
         double* emb = (double*)h->sp_emb.p;
         double* cent = (double*)h->sp_cent.p;
-        CKS(spectral_embed<T>(h, Y, ldy, d, n, c, r.sigma, r.seed, emb, &spec, st));
+        // after the first embedding of this call the previous Ritz vectors seed the next
+        CKS(spectral_embed<T>(h, Y, ldy, d, n, c, r.sigma, r.seed, emb, &spec, st, spec.calls > 0));
         Engine<double> e2{h, st, (int64_t)c, n, c, false};
         CKS(e2.setup());
         steps = 0;
@@ -527,13 +531,15 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
         CKS(e.setup());
         CK(hipMemcpyAsync(cur, h->embl.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
         // Lloyd on the columns of X from the means of X over those groups (empty at zero)
-        launch_zero2d<T>(C, d, d, r.c, st);
-        double* gs = nullptr;
-        CKS(e.group_sums(gs));
-        e.sort(cur);
-        e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C, gs);
         int ref = 0;
-        CKS(e.lloyd(X, ldx, C, cur, alt, r.max_lloyd, ref, nullptr, true));
+        if (r.emb_refine) {
+            launch_zero2d<T>(C, d, d, r.c, st);
+            double* gs = nullptr;
+            CKS(e.group_sums(gs));
+            e.sort(cur);
+            e.group_means(false, X, ldx, nullptr, 0, nullptr, 0, T(0), C, gs);
+            CKS(e.lloyd(X, ldx, C, cur, alt, r.max_lloyd, ref, nullptr, true));
+        }
         info->init_lloyd = steps + ref;
         // then as with given initial labels
         launch_zero2d<T>(C, d, d, r.c, st);
@@ -719,7 +725,8 @@ void respca_destroy(respca_handle h) {
     respca::DevBuf* wbufs[] = {&h->wsk, &h->wfeat, &h->wacts, &h->wscratch, &h->wred, &h->wcent,
                                &h->embl, &h->embc, &h->wdesc, &h->whash, &h->probe,
                                &h->sp_w, &h->sp_q, &h->sp_s, &h->sp_y, &h->sp_z, &h->sp_yp,
-                               &h->sp_t, &h->sp_part, &h->sp_small, &h->sp_emb, &h->sp_cent};
+                               &h->sp_t, &h->sp_part, &h->sp_small, &h->sp_emb, &h->sp_cent,
+                               &h->sp_mean};
     for (respca::DevBuf* b : wbufs)
         if (b->p) (void)hipFree(b->p);
     DevBuf* bufs[] = {&h->theta, &h->cbuf, &h->perm, &h->counts, &h->segb, &h->segl, &h->segf,
@@ -756,6 +763,7 @@ void respca_params_default(respca_params* p) {
     p->init_embedding_rows = 0;
     p->pstep = RESPCA_PSTEP_KMEANS;
     p->spectral_sigma = 0.0;
+    p->init_embedding_refine = 1;
 }
 
 const char* respca_status_string(respca_status s) {
@@ -1006,8 +1014,8 @@ respca_status respca_spectral_embedding(respca_handle h, int32_t precision, int6
     else if (d < 1 || n < 2 || d >= (int64_t)INT32_MAX || ldy < d)
         s = fail(h, RESPCA_ERR_INVALID, "need d >= 1, n >= 2, ldy >= d");
     else if (c < 1 || c >= n) s = fail(h, RESPCA_ERR_INVALID, "c must be in [1, n)");
-    else if (!(sigma > 0.0) || !std::isfinite(sigma))
-        s = fail(h, RESPCA_ERR_INVALID, "sigma must be finite and > 0");
+    else if (sigma == 0.0 || !std::isfinite(sigma))
+        s = fail(h, RESPCA_ERR_INVALID, "sigma must be finite and nonzero");
     else if (precision != RESPCA_F64 && precision != RESPCA_F32 && precision != RESPCA_BF16GEMM_F32)
         s = fail(h, RESPCA_ERR_INVALID, "unknown precision");
     else if (c > kSpectralMaxGroups || n > kSpectralMaxN)

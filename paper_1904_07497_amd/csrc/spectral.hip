@@ -6,16 +6,17 @@
 // the K-means machinery of the solver.
 //
 // GPU design (all FP64 after the load of the columns):
-//   - W from the Gram matrix Y^T Y on FP64 MFMA tiles (v_mfma_f64_16x16x4f64),
-//     the Gaussian of q_i + q_j - 2 G_ij applied in the tile's epilogue, so the
-//     Gram matrix is never stored (the one dense GEMM of the method);
+//   - W from the Gram matrix Y^T Y on FP64 MFMA tiles (v_mfma_f64_16x16x4f64) of
+//     the upper triangle, the Gaussian of q_i + q_j - 2 G_ij applied in the
+//     tile's epilogue and the tile written with its mirror, so the Gram matrix is
+//     never stored (the one dense GEMM of the method);
 //   - degrees (one wave per row, fixed order) and the symmetric scaling in place;
 //   - the top-c eigenvectors by Chebyshev-filtered subspace iteration with a
-//     block of k = min(n, c + 8) vectors: block products A Y read A once per
-//     product (lane = row, A symmetric, so a wave reads 64 contiguous entries of
-//     one column), Rayleigh-Ritz in one workgroup (Cholesky of Y^T Y, Jacobi on
-//     the k x k projected matrix), two Rayleigh-Ritz passes per filter so the
-//     block stays orthonormal to rounding.
+//     block of k = min(n, c + 8) vectors: block products A Y on FP64 MFMA read A
+//     once per product, Rayleigh-Ritz in one workgroup (Cholesky of Y^T Y,
+//     Jacobi on the k x k projected matrix), two Rayleigh-Ritz passes per filter
+//     so the block stays orthonormal to rounding; within a solve each p-step's
+//     iteration starts from the previous p-step's Ritz vectors.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -44,35 +45,91 @@ __device__ inline double wsum(double v) {
     return v;
 }
 
-// q_j = ||Y_j||^2 in double, one wave per column, fixed order.
+// q_j = ||Y_j||^2 in double, one wave per column, fixed order; with mean (the
+// mean column), also dev[j] = ||Y_j - mean||^2.
 template <typename T>
 __global__ __launch_bounds__(kSpBlock) void k_sp_colsq(const T* __restrict__ Y, int64_t ldy,
-                                                       int64_t d, int64_t n, double* __restrict__ q) {
+                                                       int64_t d, int64_t n, double* __restrict__ q,
+                                                       const double* __restrict__ mean,
+                                                       double* __restrict__ dev) {
     const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= n) return;
     const T* y = Y + j * ldy;
-    double s = 0.0;
+    double s = 0.0, e = 0.0;
     for (int64_t i = lane; i < d; i += 64) {
         const double v = (double)y[i];
         s += v * v;
+        if (mean) {
+            const double u = v - mean[i];
+            e += u * u;
+        }
     }
     s = wsum(s);
     if (lane == 0) q[j] = s;
+    if (mean) {
+        e = wsum(e);
+        if (lane == 0) dev[j] = e;
+    }
+}
+
+// Column sums of Y over column splits: part[s][i] = sum over the split's columns
+// (in order) of Y[i][j]; thread = row i.
+template <typename T>
+__global__ __launch_bounds__(kSpBlock) void k_sp_rowsum(const T* __restrict__ Y, int64_t ldy,
+                                                        int64_t d, int64_t n, int64_t jchunk,
+                                                        double* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * kSpBlock + threadIdx.x;
+    if (i >= d) return;
+    const int64_t jb = (int64_t)blockIdx.y * jchunk;
+    const int64_t je = jb + jchunk < n ? jb + jchunk : n;
+    double s = 0.0;
+    for (int64_t j = jb; j < je; ++j) s += (double)Y[j * ldy + i];
+    part[(int64_t)blockIdx.y * d + i] = s;
+}
+
+// mean[i] = (sum of the splits' partials, in order) / n.
+__global__ __launch_bounds__(kSpBlock) void k_sp_mean(const double* __restrict__ part, int splits,
+                                                      int64_t d, int64_t n, double* __restrict__ mean) {
+    const int64_t i = (int64_t)blockIdx.x * kSpBlock + threadIdx.x;
+    if (i >= d) return;
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += part[(int64_t)sp * d + i];
+    mean[i] = s / (double)n;
+}
+
+// out[3] = (1/n) sum_j dev[j] (the squared spread), one workgroup, fixed order.
+__global__ __launch_bounds__(kSpBlock) void k_sp_spread(const double* __restrict__ dev, int64_t n,
+                                                        double* __restrict__ out) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += kSpBlock) s += dev[j];
+    s = wsum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[3] = (((red[0] + red[1]) + red[2]) + red[3]) / (double)n;
 }
 
 // W[i*n + j] = exp(-max(q_i + q_j - 2 G_ij, 0) * inv2s2) for i != j, 0 on the
-// diagonal, G = Y^T Y.  One workgroup per 64 x 64 tile (i block = blockIdx.x,
-// j block = blockIdx.y); four waves of 32 x 32, each 2 x 2 MFMA blocks of 16 x 16.
-// W is symmetric, so W[i*n + j] is entry (i, j) in either storage order; writing
-// it with j fastest makes each 16-lane group store 128 contiguous bytes.
+// diagonal, G = Y^T Y.  One workgroup per 64 x 64 tile of the upper triangle
+// (i block = blockIdx.x <= j block = blockIdx.y; the others leave at once); four
+// waves of 32 x 32, each 2 x 2 FP64 MFMA blocks of 16 x 16.  The tile's values
+// pass through LDS (rows skewed by their index, so reading a column is free of
+// bank conflicts) and are written twice, as rows of W and (off the diagonal) as
+// rows of the transposed tile, both with 64 consecutive doubles per wave.
 template <typename T>
 __global__ __launch_bounds__(kSpBlock) void k_sp_affinity(const T* __restrict__ Y, int64_t ldy,
                                                           int64_t d, int64_t n,
                                                           const double* __restrict__ q, double inv2s2,
                                                           double* __restrict__ W) {
-    __shared__ double As[2][kGramK][kGramTile];
-    __shared__ double Bs[2][kGramK][kGramTile];
+    if (blockIdx.x > blockIdx.y) return;   // lower triangle: written by its mirror tile
+    // two stages of A and B, rows padded by 16 doubles so that the lanes reading
+    // four consecutive rows of a stage fall in different banks; then the tile
+    constexpr int kPad = kGramTile + 16;
+    __shared__ double smem[2 * 2 * kGramK * kPad];
+    static_assert(2 * 2 * kGramK * kPad >= kGramTile * kGramTile, "the tile fits the staging space");
+    double (*As)[kGramK][kPad] = reinterpret_cast<double (*)[kGramK][kPad]>(smem);
+    double (*Bs)[kGramK][kPad] = reinterpret_cast<double (*)[kGramK][kPad]>(smem + 2 * kGramK * kPad);
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -133,20 +190,33 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_affinity(const T* __restrict__ 
         __syncthreads();
     }
     // epilogue: register r of a lane holds row lane / 16 + 4 r, column lane % 16 of
-    // each 16 x 16 block (the FP64 MFMA's output order)
+    // each 16 x 16 block (the FP64 MFMA's output order); tile element (mm, nn) goes
+    // to smem[mm * 64 + (nn + mm) % 64]
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + wi + x * 16 + (lane >> 4) + 4 * r;
-                const int64_t j = j0 + wj + y * 16 + (lane & 15);
-                if (i < n && j < n) {
-                    const double dist = q[i] + q[j] - 2.0 * acc[x][y][r];
-                    W[i * n + j] = (i == j) ? 0.0 : exp(-(dist > 0.0 ? dist : 0.0) * inv2s2);
-                }
+                const int mm = wi + x * 16 + (lane >> 4) + 4 * r;
+                const int nn = wj + y * 16 + (lane & 15);
+                const int64_t i = i0 + mm, j = j0 + nn;
+                const double dist = ((i < n) ? q[i] : 0.0) + ((j < n) ? q[j] : 0.0) - 2.0 * acc[x][y][r];
+                smem[mm * kGramTile + ((nn + mm) & (kGramTile - 1))] =
+                    (i == j) ? 0.0 : exp(-(dist > 0.0 ? dist : 0.0) * inv2s2);
             }
+    __syncthreads();
+    for (int e = t; e < kGramTile * kGramTile; e += kSpBlock) {
+        const int mm = e / kGramTile, nn = e % kGramTile;
+        const int64_t i = i0 + mm, j = j0 + nn;
+        if (i < n && j < n) W[i * n + j] = smem[mm * kGramTile + ((nn + mm) & (kGramTile - 1))];
+    }
+    if (blockIdx.x == blockIdx.y) return;
+    for (int e = t; e < kGramTile * kGramTile; e += kSpBlock) {
+        const int nn = e / kGramTile, mm = e % kGramTile;
+        const int64_t i = i0 + mm, j = j0 + nn;
+        if (i < n && j < n) W[j * n + i] = smem[mm * kGramTile + ((nn + mm) & (kGramTile - 1))];
+    }
 }
 
 // s_i = deg_i^{-1/2} (0 for deg_i = 0), deg_i = sum_j W_ij in index order per
@@ -174,47 +244,60 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_scale(double* __restrict__ W, i
     }
 }
 
-// Block product, split over the summation index: P[split][i][q] = sum over j in
-// the split's range of A[j*n + i] Y[j][q]  (A symmetric, so this is (A Y)[i][q]).
-// Lane = row i (64 rows per wave, reading 64 contiguous entries of column j), Y
-// rows row-major n x k (the same Y[j][.] for every lane); the four waves of a
-// workgroup take interleaved j and add their sums in wave order at the end.
-template <int KM>
-__global__ __launch_bounds__(kSpBlock) void k_sp_mv(const double* __restrict__ A, int64_t n,
-                                                    const double* __restrict__ Y, int k,
-                                                    int64_t jchunk, double* __restrict__ P) {
-    __shared__ double red[64][KM];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+// Block product split over the summation index, P[split][i][q] = sum over j in
+// the split's range of A_ij Y[j][q] (A symmetric: A_ij is stored at A[j n + i]),
+// on FP64 MFMA (v_mfma_f64_16x16x4f64): a wave owns 16 rows i and multiplies A[i][j0..j0+3] (A operand, lane = row i % 16 and j
+// offset lane / 16: 128 contiguous bytes of A per j) by Y[j0..j0+3][16 columns]
+// (B operand, staged in LDS 64 rows at a time for the four waves of the
+// workgroup, columns past k zero), NQB blocks of 16 columns; sixteen j steps'
+// loads of A are issued before their MFMAs.
+constexpr int kMvRows = 64;   // Y rows staged per LDS pass
+
+template <int NQB>
+__global__ __launch_bounds__(kSpBlock) void k_sp_mv_mfma(const double* __restrict__ A, int64_t n,
+                                                         const double* __restrict__ Y, int k,
+                                                         int64_t jchunk, double* __restrict__ P) {
+    __shared__ double Ys[kMvRows][16 * NQB];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
+    const bool live = i < n;
     const int64_t jb = (int64_t)blockIdx.y * jchunk;
     int64_t je = jb + jchunk;
     if (je > n) je = n;
-    double acc[KM];
+    dbl4 acc[NQB];
 #pragma unroll
-    for (int q = 0; q < KM; ++q) acc[q] = 0.0;
-    const bool live = i < n;
-    for (int64_t j = jb + wave; j < je; j += 4) {
-        const double a = live ? A[j * n + i] : 0.0;
-        const double* y = Y + j * k;
-#pragma unroll
-        for (int q = 0; q < KM; ++q)
-            if (q < k) acc[q] += a * y[q];
-    }
-    // ((wave 0 + wave 1) + wave 2) + wave 3 through one LDS buffer
-    for (int w = 1; w < 4; ++w) {
-        if (wave == w)
-#pragma unroll
-            for (int q = 0; q < KM; ++q) red[lane][q] = acc[q];
+    for (int x = 0; x < NQB; ++x) acc[x] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int jo = lane >> 4;   // j offset within a step of four
+    for (int64_t js = jb; js < je; js += kMvRows) {
+        for (int e = t; e < kMvRows * 16 * NQB; e += kSpBlock) {
+            const int jj = e / (16 * NQB), q = e - jj * (16 * NQB);
+            const int64_t j = js + jj;
+            Ys[jj][q] = (j < je && q < k) ? Y[j * k + q] : 0.0;
+        }
         __syncthreads();
-        if (wave == 0)
+        double a[kMvRows / 4];
 #pragma unroll
-            for (int q = 0; q < KM; ++q) acc[q] += red[lane][q];
+        for (int st = 0; st < kMvRows / 4; ++st) {
+            const int64_t j = js + 4 * st + jo;
+            a[st] = (live && j < je) ? A[j * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int st = 0; st < kMvRows / 4; ++st)
+#pragma unroll
+            for (int x = 0; x < NQB; ++x)
+                acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], Ys[4 * st + jo][16 * x + (lane & 15)],
+                                                             acc[x], 0, 0, 0);
         __syncthreads();
     }
-    if (wave == 0 && live) {
-        double* out = P + ((int64_t)blockIdx.y * n + i) * k;
-        for (int q = 0; q < k; ++q) out[q] = acc[q];
-    }
+    // register r of a lane: row lane / 16 + 4 r of the wave's 16, column lane % 16
+#pragma unroll
+    for (int x = 0; x < NQB; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + (lane >> 4) + 4 * r;
+            const int q = 16 * x + (lane & 15);
+            if (row < n && q < k) P[((int64_t)blockIdx.y * n + row) * k + q] = acc[x][r];
+        }
 }
 
 // Z[i][q] = sum over splits (in order) of P[split][i][q].
@@ -549,7 +632,7 @@ int spectral_block(int64_t n, int c) {
 template <typename T>
 respca_status spectral_embed(respca_handle h, const T* Y, int64_t ldy, int64_t d, int64_t n, int c,
                              double sigma, uint64_t seed, double* emb, SpectralStats* stats,
-                             hipStream_t st) {
+                             hipStream_t st, bool warm) {
     const int k = spectral_block(n, c);
     const int64_t nk = n * (int64_t)k;
     CKS(ensure(h, h->sp_w, (size_t)n * (size_t)n * sizeof(double)));
@@ -590,14 +673,38 @@ respca_status spectral_embed(respca_handle h, const T* Y, int64_t ldy, int64_t d
     double* hst = h->sp_status;         // pinned host words the kernels write
     double* dst = h->sp_status_dev;
 
-    // affinity, degrees, normalisation
+    // column norms; for a relative width (sigma < 0) the spread of the columns
     const unsigned cb = (unsigned)((n + 3) / 4);
-    k_sp_colsq<T><<<cb, kSpBlock, 0, st>>>(Y, ldy, d, n, q);
+    double width = sigma;
+    if (sigma > 0.0) {
+        k_sp_colsq<T><<<cb, kSpBlock, 0, st>>>(Y, ldy, d, n, q, nullptr, nullptr);
+    } else {
+        // column sums over splits (the n-vector s holds the deviations afterwards)
+        int64_t rsplits = 64;
+        if (rsplits > n) rsplits = n;
+        const int64_t rchunk = (n + rsplits - 1) / rsplits;
+        rsplits = (n + rchunk - 1) / rchunk;
+        CKS(ensure(h, h->sp_mean, (size_t)d * (rsplits + 1) * sizeof(double)));
+        double* rpart = (double*)h->sp_mean.p + d;
+        double* mean = (double*)h->sp_mean.p;
+        k_sp_rowsum<T><<<dim3((unsigned)((d + kSpBlock - 1) / kSpBlock), (unsigned)rsplits), kSpBlock,
+                         0, st>>>(Y, ldy, d, n, rchunk, rpart);
+        k_sp_mean<<<(unsigned)((d + kSpBlock - 1) / kSpBlock), kSpBlock, 0, st>>>(rpart, (int)rsplits, d,
+                                                                               n, mean);
+        k_sp_colsq<T><<<cb, kSpBlock, 0, st>>>(Y, ldy, d, n, q, mean, s);
+        k_sp_spread<<<1, kSpBlock, 0, st>>>(s, n, dst);
+        CK(hipGetLastError());
+        CK(hipStreamSynchronize(st));
+        const volatile double* w = hst;
+        width = -sigma * std::sqrt(w[3]);
+    }
     const unsigned tb = (unsigned)((n + kGramTile - 1) / kGramTile);
-    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    // a zero width (all columns equal) makes every distance zero: W = 1 off the diagonal
+    const double inv2s2 = width > 0.0 ? 1.0 / (2.0 * width * width) : 0.0;
     {
+        // algorithmic work: the upper triangle of the Gram matrix, n (n + 1) d products
         ProfScope ps(h, st, RESPCA_KERNEL_AFFINITY, (double)d * n * sizeof(T) + 8.0 * (double)n * n,
-                     2.0 * (double)n * (double)n * (double)d);
+                     (double)n * (double)(n + 1) * (double)d);
         k_sp_affinity<T><<<dim3(tb, tb), kSpBlock, 0, st>>>(Y, ldy, d, n, q, inv2s2, W);
     }
     k_sp_degree<<<cb, kSpBlock, 0, st>>>(W, n, s);
@@ -606,9 +713,9 @@ respca_status spectral_embed(respca_handle h, const T* Y, int64_t ldy, int64_t d
     auto product = [&](const double* in, double* out) {
         ProfScope ps(h, st, RESPCA_KERNEL_EIGEN, 8.0 * (double)n * n, 2.0 * (double)n * n * k);
         const dim3 g((unsigned)rblocks, (unsigned)splits);
-        if (k <= 16) k_sp_mv<16><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
-        else if (k <= 32) k_sp_mv<32><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
-        else k_sp_mv<48><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
+        if (k <= 16) k_sp_mv_mfma<1><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
+        else if (k <= 32) k_sp_mv_mfma<2><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
+        else k_sp_mv_mfma<3><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
         k_sp_mv_reduce<<<blocks_for(nk), kSpBlock, 0, st>>>(P, (int)splits, nk, out);
     };
     auto rayleigh_ritz = [&]() {   // on (Yb, Zb = A Yb): orthonormal Ritz vectors, theta
@@ -619,7 +726,8 @@ respca_status spectral_embed(respca_handle h, const T* Y, int64_t ldy, int64_t d
         }
     };
 
-    k_sp_init<<<blocks_for(nk), kSpBlock, 0, st>>>(Yb, nk, seed ^ 0x5EC7A1C1A5731B5DULL);
+    if (!warm)   // else the previous call's Ritz vectors (same n and k) start the iteration
+        k_sp_init<<<blocks_for(nk), kSpBlock, 0, st>>>(Yb, nk, seed ^ 0x5EC7A1C1A5731B5DULL);
     product(Yb, Zb);
     rayleigh_ritz();
     const double tol2 = 1e-20;   // squared residual norm of each wanted Ritz pair
@@ -680,10 +788,10 @@ respca_status spectral_embed(respca_handle h, const T* Y, int64_t ldy, int64_t d
 
 template respca_status spectral_embed<float>(respca_handle, const float*, int64_t, int64_t, int64_t,
                                              int, double, uint64_t, double*, SpectralStats*,
-                                             hipStream_t);
+                                             hipStream_t, bool);
 template respca_status spectral_embed<double>(respca_handle, const double*, int64_t, int64_t, int64_t,
                                               int, double, uint64_t, double*, SpectralStats*,
-                                              hipStream_t);
+                                              hipStream_t, bool);
 
 // Copy of the eigenvalues of the last call (k values, decreasing).
 respca_status spectral_eigenvalues(respca_handle h, int64_t n, int c, double* out, hipStream_t st) {

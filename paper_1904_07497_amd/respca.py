@@ -46,7 +46,8 @@ class Params(ct.Structure):
                 ("precision", ct.c_int32), ("init_labels", ct.c_void_p),
                 ("history", ct.POINTER(ct.c_double)), ("init_embedding", ct.c_void_p),
                 ("init_embedding_ld", ct.c_int64), ("init_embedding_rows", ct.c_int32),
-                ("sparse_norm", ct.c_int32), ("pstep", ct.c_int32), ("spectral_sigma", ct.c_double)]
+                ("sparse_norm", ct.c_int32), ("pstep", ct.c_int32), ("spectral_sigma", ct.c_double),
+                ("init_embedding_refine", ct.c_int32)]
 
 
 class Info(ct.Structure):
@@ -259,7 +260,8 @@ def _stream(stream):
 
 def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
           max_lloyd=100, seed=0, precision=None, init_labels=None, history=False,
-          out=None, stream=None, init_embedding=None, sparse_norm=0, pstep=0, sigma=0.0):
+          out=None, stream=None, init_embedding=None, sparse_norm=0, pstep=0, sigma=0.0,
+          embedding_refine=1):
     """RES-PCA of X (d x n column-major tensor).  Returns dict(L, S, labels, info[, history]).
     sparse_norm: 0 the l1 penalty on S, 1 the column-wise l2,1 penalty.  pstep:
     PSTEP_KMEANS, or PSTEP_SPECTRAL with kernel width sigma."""
@@ -291,6 +293,7 @@ def solve(X, rank=0, lam=None, tol=1e-3, max_iter=500, rho0=1e-4, kappa=1.5, rho
         ep, eld = _colmajor(init_embedding, "init_embedding")
         p.init_embedding, p.init_embedding_ld = ep, eld
         p.init_embedding_rows = init_embedding.shape[0]
+        p.init_embedding_refine = int(embedding_refine)
     info = Info()
     h = handle(X.device.index or 0)
     s = lib().respca_solve(h._h, ct.byref(p), d, n, xp, ldx, lp, ldl, sp, lds, labels.data_ptr(),
@@ -419,7 +422,8 @@ def _batch_args(Xs, params_list, outs):
 
 
 def batch_params(ranks, lams=None, tol=1e-6, max_iter=500, rho0=1e-4, kappa=1.5, rho_max=1e10,
-                 max_lloyd=100, seeds=None, init_labels=None, init_embeddings=None):
+                 max_lloyd=100, seeds=None, init_labels=None, init_embeddings=None,
+                 embedding_refine=1):
     """Per-instance Params (FP32).  ``rho0`` may be a scalar or a per-instance list;
     ``init_labels`` a list of device int32 tensors or None entries; ``init_embeddings``
     a list of (rows, n) column-major float32 device tensors or None entries."""
@@ -439,6 +443,7 @@ def batch_params(ranks, lams=None, tol=1e-6, max_iter=500, rho0=1e-4, kappa=1.5,
                 raise ValueError("init_embedding must be float32")
             ep, eld = _colmajor(e, "init_embedding")
             p.init_embedding, p.init_embedding_ld, p.init_embedding_rows = ep, eld, e.shape[0]
+            p.init_embedding_refine = int(embedding_refine)
             keep.append(e)
         out.append(p)
     return out, keep

@@ -38,8 +38,8 @@ def test_params_default_and_strings():
 def test_params_mirror_covers_the_c_struct():
     """respca_params_default clears sizeof(respca_params) bytes: on a buffer larger
     than the Python mirror, the bytes past the mirror stay untouched (so the mirror
-    is not smaller than the C struct) and the mirror's last field, spectral_sigma,
-    was written (so it is not larger)."""
+    is not smaller than the C struct) and the mirror's last field,
+    init_embedding_refine, was written (so it is not larger)."""
     import ctypes as ct
     size = ct.sizeof(rp.Params)
     buf = (ct.c_ubyte * (size + 64))(*([0xAB] * (size + 64)))
@@ -48,6 +48,7 @@ def test_params_mirror_covers_the_c_struct():
     p = rp.Params.from_buffer(buf)
     assert p.sparse_norm == 0 and p.init_embedding_rows == 0 and p.precision == rp.F32
     assert p.pstep == rp.PSTEP_KMEANS and p.spectral_sigma == 0.0
+    assert p.init_embedding_refine == 1
     assert rp.KERNELS["eigen"] == len(rp.KERNELS) - 1
 
 

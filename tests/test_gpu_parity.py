@@ -871,20 +871,24 @@ def _refine_on_x(X, lab, c, max_lloyd=100):
     return lab2, steps
 
 
-def _oracle_from_embedding(X, E, c, lam, seed, **kw):
+def _oracle_from_embedding(X, E, c, lam, seed, refine=True, **kw):
     lab, _, steps = oracle.kmeans(E, c, seed, 100)
-    lab2, ref = _refine_on_x(X, lab, c)
-    o = oracle.solve(X, oracle.make_params(c, lam=lam, seed=seed, **kw), init_labels=lab2)
+    ref = 0
+    if refine:
+        lab, ref = _refine_on_x(X, lab, c)
+    o = oracle.solve(X, oracle.make_params(c, lam=lam, seed=seed, **kw), init_labels=lab)
     return o, steps + ref
 
 
-def test_init_embedding_single_solve_matches_oracle():
-    """Groups from K-means of an embedding's columns, refined by Lloyd on X, then the
-    iterations: identical to the oracle's chain from the same embedding."""
+@pytest.mark.parametrize("refine", [1, 0])
+def test_init_embedding_single_solve_matches_oracle(refine):
+    """Groups from K-means of an embedding's columns, refined by Lloyd on X (or not:
+    init_embedding_refine = 0), then the iterations: identical to the oracle's chain
+    from the same embedding."""
     for i, (X, E, Ed, c, lam) in enumerate(_embedding_cases()):
-        o, steps = _oracle_from_embedding(X, E, c, lam, seed=i + 3, tol=1e-6)
+        o, steps = _oracle_from_embedding(X, E, c, lam, seed=i + 3, refine=bool(refine), tol=1e-6)
         g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=o["info"]["iters"], seed=i + 3,
-                     precision=rp.F32, init_embedding=Ed)
+                     precision=rp.F32, init_embedding=Ed, embedding_refine=refine)
         say(f"embedding case {i} {X.shape} iters {g['info']['iters']} init_lloyd "
             f"{g['info']['init_lloyd']} / {steps}")
         assert g["info"]["init_lloyd"] == steps
@@ -896,8 +900,10 @@ def test_init_embedding_single_solve_matches_oracle():
         rp.solve(dev(X, np.float64), rank=c, precision=rp.F64, init_embedding=Ed)
 
 
-def test_init_embedding_batched_matches_oracle():
-    """Embedding, label and cold instances side by side in one persistent launch."""
+@pytest.mark.parametrize("refine", [1, 0])
+def test_init_embedding_batched_matches_oracle(refine):
+    """Embedding, label and cold instances side by side in one persistent launch
+    (embedding groups refined by Lloyd on X, or not)."""
     cases = _embedding_cases()
     shapes, Xs = _batch_mix()
     X_lab, X_cold = Xs[1], Xs[2]
@@ -909,7 +915,8 @@ def test_init_embedding_batched_matches_oracle():
     T = []
     for i, (X, r, lam, sd) in enumerate(zip(Xall, ranks, lams, seeds)):
         if i < len(cases):
-            o, steps = _oracle_from_embedding(X, cases[i][1], r, lam, sd, tol=1e-6)
+            o, steps = _oracle_from_embedding(X, cases[i][1], r, lam, sd, refine=bool(refine),
+                                              tol=1e-6)
             o["emb_steps"] = steps
         elif i == len(cases):
             o = oracle.solve(X, oracle.make_params(r, lam=lam, tol=1e-6, seed=sd), init_labels=lab0)
@@ -919,7 +926,7 @@ def test_init_embedding_batched_matches_oracle():
     emb = [cs[2] for cs in cases] + [None, None]
     labs = [None] * len(cases) + [torch.from_numpy(lab0).cuda(), None]
     plist, keep = rp.batch_params(ranks, lams, tol=0.0, max_iter=0, seeds=seeds, init_labels=labs,
-                                  init_embeddings=emb)
+                                  init_embeddings=emb, embedding_refine=refine)
     for p, o in zip(plist, T):
         p.max_iter = o["info"]["iters"]
     outs, infos, status = rp.solve_batched([dev(X) for X in Xall], plist)

@@ -48,7 +48,7 @@ def _blocks(d, n, c, seed, spread=0.3, sep=20.0):
     return np.asfortranarray(X), lab
 
 
-@pytest.mark.parametrize("case", ["rings", "blocks", "ragged"])
+@pytest.mark.parametrize("case", ["rings", "blocks", "ragged", "relative"])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_embedding_matches_oracle(case, dtype):
     if case == "rings":
@@ -57,9 +57,13 @@ def test_embedding_matches_oracle(case, dtype):
     elif case == "blocks":
         X, _ = _blocks(37, 301, 5, seed=2)
         c, sigma = 5, 3.0
-    else:   # several 64-column tiles with a ragged edge, 16-row stages with a ragged tail
+    elif case == "ragged":   # several 64-column tiles with a ragged edge, ragged 16-row stages
         X, _ = synth.rings(counts=(400, 500, 333), radii=(1.0, 3.0, 6.0), d=131, seed=3)
         c, sigma = 3, 0.7
+    else:   # relative width: 0.15 times the spread of the columns, data scaled by 1e-3
+        X, _ = synth.rings(counts=(300, 400), radii=(1.0, 4.0), d=40, seed=6)
+        X = 1e-3 * X
+        c, sigma = 2, -0.15
     X = X.astype(dtype, order="F")
     Xo = X.astype(np.float64)
     say(f"embedding {case} {X.shape} c={c} {np.dtype(dtype).name}")
@@ -79,6 +83,7 @@ def test_embedding_matches_oracle(case, dtype):
 def test_embedding_argument_checks():
     X = dev(np.ones((4, 10)))
     for kw, status in [(dict(sigma=0.0), rp.ERR_INVALID), (dict(sigma=float("nan")), rp.ERR_INVALID),
+                       (dict(sigma=float("-inf")), rp.ERR_INVALID),
                        (dict(rank=10), rp.ERR_INVALID), (dict(rank=41), rp.ERR_UNSUPPORTED)]:
         args = dict(rank=2, sigma=1.0)
         args.update(kw)
@@ -120,6 +125,27 @@ def test_spectral_solve_matches_oracle(dtype, precision):
     frac = support_check(Xo, o["L"], o["theta_prev"], o["rho_t"], host(g["S"]), o["S"],
                          np.finfo(dtype).eps)
     assert frac > 0.5
+
+
+def test_spectral_solve_relative_width_matches_oracle():
+    """The relative kernel width (sigma < 0: |sigma| times the columns' spread, which
+    follows L as the L-step shrinks it): three rings, iteration-locked FP32 solve
+    against the oracle; the groups are the rings."""
+    X, ring = synth.rings(counts=(150, 200, 250), radii=(1.0, 4.0, 7.0), d=30, noise=0.01, seed=8,
+                          frac=0.01, amp=0.5, dtype=np.float32)
+    c, sigma, lam = 3, -0.1, 0.05
+    p = oracle.make_params(c, lam=lam, tol=1e-6, seed=0)
+    o = osp.solve(X, p, sigma)
+    T = o["info"]["iters"]
+    g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=T, seed=0, precision=rp.F32,
+                 pstep=rp.PSTEP_SPECTRAL, sigma=sigma)
+    assert g["info"]["iters"] == T and g["info"]["eig_unconverged"] == 0
+    np.testing.assert_array_equal(g["labels"].cpu().numpy(), o["labels"])
+    lab = o["labels"]
+    assert all(len(set(lab[ring == r])) == 1 for r in range(3)) and len(set(lab.tolist())) == 3
+    nX = np.linalg.norm(X.astype(np.float64))
+    assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
+    assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
 
 
 def test_spectral_iterate_matches_oracle_step():

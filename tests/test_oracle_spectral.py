@@ -144,3 +144,17 @@ def test_spectral_solve_recovers_rings_where_kmeans_pstep_does_not():
     assert agree < 0.8
     # the stopping criterion holds at the returned iterate
     assert np.linalg.norm(X - o["L"] - o["S"]) <= 1e-6 * np.linalg.norm(X) * (1 + 1e-9)
+
+
+def test_relative_width_follows_the_scale_of_the_data():
+    """sigma < 0 is relative: |sigma| times the RMS distance of the columns to their
+    mean, so scaling the data by any factor leaves the affinity unchanged.  The
+    spread of three points on a line at 0, 1, 5 is sqrt((4 + 1 + 9) / 3)."""
+    Y = np.array([[0.0, 1.0, 5.0]])
+    assert sp.spread(Y) == pytest.approx(math.sqrt(14 / 3), rel=1e-15)
+    assert sp.kernel_width(Y, 0.7) == 0.7
+    assert sp.kernel_width(Y, -0.5) == pytest.approx(0.5 * math.sqrt(14 / 3), rel=1e-15)
+    X, _ = synth.rings(seed=1)
+    np.testing.assert_allclose(sp.affinity(X, -0.2), sp.affinity(1e-3 * X, -0.2), rtol=1e-12,
+                               atol=1e-300)
+    np.testing.assert_allclose(sp.affinity(X, -0.2), sp.affinity(X, 0.2 * sp.spread(X)), rtol=1e-14)
