@@ -589,6 +589,87 @@ def summarize_counters(unit, workload, root):
     print(json.dumps(rec), flush=True)
 
 
+def display_name(name):
+    """A dispatch name without its argument list and namespaces."""
+    name = name.split("(")[0] if not name.startswith("_Z") else kernel_base(name)
+    for pre in ("void ", "respca::(anonymous namespace)::", "respca::", "(anonymous namespace)::"):
+        name = name.replace(pre, "")
+    return name
+
+
+def summarize_stats(root, title, command, out_name):
+    """profiles/<out_name>.md from a rocprofv3 --kernel-trace --stats run (the
+    *kernel_stats.csv under root): calls, total, average, min and max per kernel."""
+    import csv
+    path = None
+    for dirpath, _, files in os.walk(root):
+        for fn in files:
+            if fn.endswith("kernel_stats.csv"):
+                path = os.path.join(dirpath, fn)
+    if path is None:
+        raise SystemExit(f"no kernel_stats.csv under {root}")
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# Kernel statistics: {title}", "",
+             "Command (on one MI355X; rocprofv3 runs from /tmp, R is the repository root):", "",
+             "```", "cd /tmp && export TMPDIR=/tmp; R=<repository root>", command, "```", "",
+             "| kernel | calls | total ms | avg us | min us | max us | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = display_name(r["Name"])
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    out = os.path.join(ROOT, "profiles", f"{out_name}.md")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
+
+
+def summarize_pmc(root, title, command, out_name, top=8):
+    """profiles/<out_name>.md from one rocprofv3 --pmc run with SQ_VALU_MFMA_BUSY_CYCLES,
+    SQ_INSTS_VALU_MFMA_MOPS_*, SQ_WAIT_INST_ANY, SQ_WAVE_CYCLES, SQ_LDS_BANK_CONFLICT,
+    SQ_LDS_IDX_ACTIVE and GRBM_GUI_ACTIVE: per kernel (mean per dispatch) the MFMA
+    busy fraction of the SIMD cycles, the fraction of wave cycles spent waiting,
+    the LDS bank-conflict cycles per active LDS cycle and the MFMA flops.
+    GRBM_GUI_ACTIVE is summed over the 8 XCDs, so a dispatch lasts GRBM / 8 cycles
+    on each of the 1024 SIMDs (256 CUs x 4)."""
+    import collections
+    vals = read_counter_csvs(root)
+    per = collections.defaultdict(dict)
+    calls = {}
+    for (k, cn), (v, c) in vals.items():
+        per[k][cn] = v
+        calls[k] = max(calls.get(k, 0), c)
+    rows = []
+    for k, cs in per.items():
+        cyc = cs.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+        if cyc <= 0:
+            continue
+        mops = sum(v for cn, v in cs.items() if cn.startswith("SQ_INSTS_VALU_MFMA_MOPS"))
+        busy = cs.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (cyc * 1024)
+        wait = cs.get("SQ_WAIT_INST_ANY", 0.0) / max(cs.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        lds = cs.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(cs.get("SQ_LDS_IDX_ACTIVE", 0.0), 1.0)
+        rows.append((cyc * calls[k], display_name(k), calls[k], cyc, busy, wait, lds, mops * 512))
+    rows.sort(key=lambda r: -r[0])
+    lines = [f"# MFMA and wait counters: {title}", "",
+             "Command (on one MI355X; rocprofv3 runs from /tmp, R is the repository root):", "",
+             "```", "cd /tmp && export TMPDIR=/tmp; R=<repository root>", command, "```", "",
+             "Per dispatch (means): cycles = GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs); "
+             "MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (cycles x 1024 SIMDs); waiting = "
+             "SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; LDS conflicts = SQ_LDS_BANK_CONFLICT / "
+             "SQ_LDS_IDX_ACTIVE; MFMA flops = SQ_INSTS_VALU_MFMA_MOPS_* x 512.", "",
+             "| kernel | dispatches | cycles | MFMA busy | waiting | LDS conflicts | MFMA flops |",
+             "|---|---|---|---|---|---|---|"]
+    for _, name, n, cyc, busy, wait, lds, fl in rows[:top]:
+        lines.append(f"| `{name}` | {n} | {cyc:.0f} | {100 * busy:.1f} % | {100 * wait:.1f} % | "
+                     f"{lds:.2f} | {fl:.3e} |")
+    out = os.path.join(ROOT, "profiles", f"{out_name}.md")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -614,7 +695,18 @@ def main():
     ap.add_argument("--summarize-counters", nargs=3, metavar=("UNIT", "WORKLOAD", "ROOT"),
                     help="write profiles/traffic_UNIT_WORKLOAD.json from FETCH_SIZE/WRITE_SIZE "
                          "counter runs under ROOT (no GPU needed)")
+    ap.add_argument("--summarize-stats", nargs=4, metavar=("ROOT", "TITLE", "COMMAND", "NAME"),
+                    help="write profiles/NAME.md from a rocprofv3 --stats run under ROOT (no GPU needed)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("ROOT", "TITLE", "COMMAND", "NAME"),
+                    help="write profiles/NAME.md from a rocprofv3 --pmc MFMA/wait counter run under "
+                         "ROOT (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
+        return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
         return

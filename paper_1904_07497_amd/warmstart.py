@@ -318,6 +318,10 @@ def main(argv=None):
     ap.add_argument("--heldout", type=int, default=1024)
     ap.add_argument("--out", default=str(MODEL_PATH))
     ap.add_argument("--eval-only", action="store_true", help="evaluate the model stored at --out")
+    ap.add_argument("--curve", default=None,
+                    help="comma-separated training sizes: train one model on each prefix of the "
+                         "--instances generated ones and evaluate each on the held-out set "
+                         "(prints one JSON line per size; --out is not written)")
     a = ap.parse_args(argv)
 
     def log(msg):
@@ -342,6 +346,23 @@ def main(argv=None):
         log(f"training data {c0 + len(seeds)}/{a.instances} instances, {sum(f.shape[0] for f in Fs)} "
             f"columns; cold iters {np.mean(stats['cold_iters']):.2f} -> best {np.mean(stats['best_iters']):.2f} "
             f"({time.perf_counter() - t0:.0f}s)")
+    if a.curve:
+        import json
+        sizes = sorted(int(v) for v in a.curve.split(","))
+        cols = np.cumsum([0] + [f.shape[0] for f in Fs])   # columns before instance chunk k
+        per_chunk = a.chunk
+        for size in sizes:
+            k = (min(size, a.instances) + per_chunk - 1) // per_chunk
+            Fk = torch.cat(Fs[:k])
+            Tk = torch.cat(Ts[:k])
+            Pk, hist = train(Fk, Tk, hidden=a.hidden, epochs=a.epochs, log=log)
+            res = evaluate(Pk, a.hidden, [HELDOUT_BASE + i for i in range(a.heldout)], log=log)
+            line = {"training_instances": min(size, a.instances), "training_columns": int(cols[k]),
+                    "val_loss": [round(v, 6) for v in hist]}
+            line.update(summary(res))
+            print(json.dumps(line), flush=True)
+            del Fk, Tk, Pk
+        return
     F = torch.cat(Fs)
     T = torch.cat(Ts)
     del Fs, Ts
