@@ -68,12 +68,11 @@ WORKLOADS = {
                        "oracle's whole solve", d=500, n=500, rank=25, lam=1.0 / 500 ** 0.5, tol=1e-7,
                   seeds=(0, 1, 2, 3, 4), gen="small"),
     "spectral": dict(name="RES-PCA FP32 with the spectral-clustering p-step (Sec. 4.2 nonlinear "
-                          "alternative): 3 concentric rings (radii 1, 4, 7; 2000, 2500, 3500 points) in "
-                          "a random plane of R^2000, N(0, 0.002^2) noise, 0.02% of entries offset by "
-                          "U[-0.3, 0.3], c=3, kernel width 0.1 x the columns' spread (relative), "
-                          "lambda=0.05, tol=1e-6", d=2000,
-                     counts=(2000, 2500, 3500), radii=(1.0, 4.0, 7.0), noise=0.002, frac=0.0002,
-                     amp=0.3, rank=3, sigma=-0.1, lam=0.05, tol=1e-6, gen="spectral"),
+                          "alternative): two interleaved half circles (two moons, 4000 points each) in "
+                          "a random plane of R^2000, N(0, 0.001^2) noise, 0.02% of entries offset by "
+                          "U[-0.3, 0.3], c=2, kernel width 0.1 x the columns' spread (relative), "
+                          "lambda=0.05, tol=1e-6", d=2000, counts=(4000, 4000), noise=0.001,
+                     frac=0.0002, amp=0.3, rank=2, sigma=-0.1, lam=0.05, tol=1e-6, gen="spectral"),
     "scaling": dict(name="scalability (Sec. 5): seeded random subsets of the synthetic 240x320x2000 "
                          "clip at ratios 1/8, 1/4, 1/2, 1 of n (all d) and of d (all n), c=5, "
                          "lambda=sqrt(max(d,n)), 30 outer iterations (no tolerance), 10 runs each",
@@ -574,7 +573,7 @@ def summarize_counters(unit, workload, root):
             continue
         fb = fetch[name][0] * 1024.0 * factors["FETCH_SIZE"]
         wb = write.get(name, (0.0, 0))[0] * 1024.0 * factors["WRITE_SIZE"]
-        parts.append({"kernel": name.split("(")[0], "dispatches": fetch[name][1],
+        parts.append({"kernel": display_name(name), "dispatches": fetch[name][1],
                       "fetch_kib_per_dispatch": round(fetch[name][0], 1),
                       "write_kib_per_dispatch": round(write.get(name, (0.0, 0))[0], 1),
                       "fetch_bytes_per_dispatch": int(fb), "write_bytes_per_dispatch": int(wb)})
@@ -591,10 +590,11 @@ def summarize_counters(unit, workload, root):
 
 def display_name(name):
     """A dispatch name without its argument list and namespaces."""
-    name = name.split("(")[0] if not name.startswith("_Z") else kernel_base(name)
-    for pre in ("void ", "respca::(anonymous namespace)::", "respca::", "(anonymous namespace)::"):
+    if name.startswith("_Z"):
+        return kernel_base(name)
+    for pre in ("void ", "respca::", "(anonymous namespace)::"):
         name = name.replace(pre, "")
-    return name
+    return name.split("(")[0]
 
 
 def summarize_stats(root, title, command, out_name):
@@ -878,8 +878,8 @@ def bench_spectral(args, wl):
     from paper_1904_07497_amd import respca as rp
     from paper_1904_07497_amd import synth
 
-    X, ring = synth.rings(counts=wl["counts"], radii=wl["radii"], d=wl["d"], noise=wl["noise"], seed=5,
-                          frac=wl["frac"], amp=wl["amp"], dtype=np.float32)
+    X, moon = synth.moons(counts=wl["counts"], d=wl["d"], noise=wl["noise"], seed=5, frac=wl["frac"],
+                          amp=wl["amp"], dtype=np.float32)
     d, n = X.shape
     Xd = torch.from_numpy(X).to("cuda:0")
     kw = dict(rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=rp.F32,
@@ -902,9 +902,18 @@ def bench_spectral(args, wl):
     rp.profile_enable(False)
     lab = out[2].cpu().numpy()
     groups = len(wl["counts"])
-    recovered = bool(all(len(set(lab[ring == r])) == 1 for r in range(groups))
-                     and len(set(lab.tolist())) == groups)
-    ring_groups = [np.bincount(lab[ring == r], minlength=wl["rank"]).tolist() for r in range(groups)]
+
+    def per_moon(labels):
+        return [np.bincount(labels[moon == r], minlength=wl["rank"]).tolist() for r in range(groups)]
+
+    def recovered(labels):
+        return bool(all(len(set(labels[moon == r])) == 1 for r in range(groups))
+                    and len(set(labels.tolist())) == groups)
+
+    moon_groups = per_moon(lab)
+    # the same solve with the K-means p-step, for contrast (untimed)
+    km = rp.solve(Xd, rank=wl["rank"], lam=wl["lam"], tol=wl["tol"], seed=0, precision=rp.F32)
+    km_lab = km["labels"].cpu().numpy()
 
     def unit(name, peak, unit_name, use_flops):
         k = prof[name]
@@ -932,8 +941,9 @@ def bench_spectral(args, wl):
         "data": "synthetic",
         "config": {"workload": wl["name"], "d": d, "n": n, "c": wl["rank"], "iters": info["iters"],
                    "lloyd_steps": info["lloyd_steps"], "eig_iters": info["eig_iters"],
-                   "eig_unconverged": info["eig_unconverged"], "rings_recovered": recovered,
-                   "groups_per_ring": ring_groups},
+                   "eig_unconverged": info["eig_unconverged"], "moons_recovered": recovered(lab),
+                   "groups_per_moon": moon_groups, "kmeans_pstep_recovered": recovered(km_lab),
+                   "kmeans_pstep_groups_per_moon": per_moon(km_lab)},
         "roofline": unit("affinity", 78.6, "TFLOP/s", True),
         "eigen_roofline": unit("eigen", HBM_PEAK_GBS, "GB/s", False),
         "sweep_roofline": unit("sweep", HBM_PEAK_GBS, "GB/s", False),

@@ -227,3 +227,32 @@ def rings(counts=(60, 90), radii=(1.0, 4.0), d: int = 20, noise: float = 0.02, s
         flat[pos] += rng.uniform(-amp, amp, k)
         X = flat.reshape(X.shape, order="F")
     return np.asfortranarray(X.astype(dtype)), ring
+
+
+def moons(counts=(300, 300), d: int = 20, noise: float = 0.05, seed: int = 0,
+          frac: float = 0.0, amp: float = 0.0, dtype=np.float64):
+    """Two interleaved half circles of radius 1 (the classic two-moons layout, whose
+    groups K-means splits across and spectral clustering follows): moon 0 at angles
+    t in [0, pi] on (cos t, sin t), moon 1 on (1 - cos t, 1/2 - sin t), placed in
+    a random 2-D plane of R^d with N(0, noise^2) in every coordinate; optionally a
+    fraction `frac` of the entries offset by values uniform in [-amp, amp].
+    Columns are shuffled.  Returns (X (d x n), moon index per column)."""
+    rng = np.random.default_rng(seed)
+    basis, _ = np.linalg.qr(rng.standard_normal((d, 2)))
+    cols, member = [], []
+    for k, m in enumerate(counts):
+        t = rng.uniform(0.0, math.pi, m)
+        pts = np.stack([np.cos(t), np.sin(t)]) if k == 0 else np.stack([1.0 - np.cos(t), 0.5 - np.sin(t)])
+        cols.append(basis @ pts + noise * rng.standard_normal((d, m)))
+        member.append(np.full(m, k, dtype=np.int32))
+    X = np.concatenate(cols, axis=1)
+    moon = np.concatenate(member)
+    perm = rng.permutation(X.shape[1])
+    X, moon = X[:, perm], moon[perm]
+    if frac > 0:
+        k = int(round(frac * X.size))
+        pos = rng.choice(X.size, size=k, replace=False)
+        flat = X.reshape(-1, order="F")
+        flat[pos] += rng.uniform(-amp, amp, k)
+        X = flat.reshape(X.shape, order="F")
+    return np.asfortranarray(X.astype(dtype)), moon

@@ -148,6 +148,28 @@ def test_spectral_solve_relative_width_matches_oracle():
     assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
 
 
+def test_spectral_solve_two_moons_matches_oracle():
+    """The spectral benchmark's kind of data at a smaller size (two moons, relative
+    width 0.1, lambda 0.05): iteration-locked FP32 solve against the oracle, and the
+    groups are the moons."""
+    X, moon = synth.moons(counts=(300, 300), d=100, noise=0.005, seed=5, frac=0.002, amp=0.3,
+                          dtype=np.float32)
+    c, sigma, lam = 2, -0.1, 0.05
+    p = oracle.make_params(c, lam=lam, tol=1e-6, seed=0)
+    o = osp.solve(X, p, sigma)
+    T = o["info"]["iters"]
+    say(f"spectral moons solve {X.shape} T={T}")
+    g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=T, seed=0, precision=rp.F32,
+                 pstep=rp.PSTEP_SPECTRAL, sigma=sigma)
+    assert g["info"]["iters"] == T and g["info"]["eig_unconverged"] == 0
+    assert g["info"]["lloyd_steps"] == o["info"]["lloyd_steps"]
+    np.testing.assert_array_equal(g["labels"].cpu().numpy(), o["labels"])
+    assert np.array_equal(o["labels"] == o["labels"][0], moon == moon[0])
+    nX = np.linalg.norm(X.astype(np.float64))
+    assert rel(host(g["L"]), o["L"], nX) <= F32_TOL
+    assert rel(host(g["S"]), o["S"], nX) <= F32_TOL
+
+
 def test_spectral_iterate_matches_oracle_step():
     """One iteration with the spectral p-step from an arbitrary state (three blocks,
     random groups): labels, L, S and Theta / rho against the oracle's step."""

@@ -146,6 +146,22 @@ def test_spectral_solve_recovers_rings_where_kmeans_pstep_does_not():
     assert np.linalg.norm(X - o["L"] - o["S"]) <= 1e-6 * np.linalg.norm(X) * (1 + 1e-9)
 
 
+def test_spectral_solve_recovers_two_moons_where_kmeans_pstep_does_not():
+    """Two moons (interleaved half circles with distinct means, the shape of the
+    spectral benchmark workload at a smaller size), 0.2 % of entries offset: with
+    the relative kernel width the spectral p-step keeps the moons from the first
+    clustering to convergence, the K-means p-step cuts across them."""
+    X, moon = synth.moons(counts=(300, 300), d=100, noise=0.005, seed=5, frac=0.002, amp=0.3)
+    p = oracle.make_params(2, lam=0.05, tol=1e-6, seed=0)
+    init, _ = sp.spectral_init(X, 2, -0.1, 0)
+    assert np.array_equal(init == init[0], moon == moon[0])
+    o = sp.solve(X, p, -0.1)
+    assert o["info"]["status"] == 0
+    assert np.array_equal(o["labels"] == o["labels"][0], moon == moon[0])
+    km = oracle.solve(X, p)["labels"]
+    assert max(np.mean(km == moon), np.mean(km != moon)) < 0.9
+
+
 def test_relative_width_follows_the_scale_of_the_data():
     """sigma < 0 is relative: |sigma| times the RMS distance of the columns to their
     mean, so scaling the data by any factor leaves the affinity unchanged.  The
