@@ -51,7 +51,9 @@ WORKLOADS = {
                            "of the batched size mix (d, n log-uniform in [200, 4000], rank 5..50, "
                            "1-20% sparse in [-50,50]) drawn on the device, c=rank, "
                            "lambda=1/sqrt(max(d,n)), tol=1e-6; launches of 256 instances, network "
-                           "pass included", instances=1024, chunk=256, tol=1e-6, gen="warmstart"),
+                           "pass included; warm runs start from the predicted rho0 (groups: the "
+                           "cold start's K-means of X unless --warm-groups embedding)",
+                      instances=1024, chunk=256, tol=1e-6, gen="warmstart"),
     "video": dict(name="RES-PCA FP32 synthetic 240x320x2000 clip (rank-5 background, 4 moving 20x20 "
                        "squares, 8-bit scale), c=5, lambda=sqrt(76800), tol=1e-6", d=76800, n=2000,
                   rank=5, lam=None, tol=1e-6, gen="video"),
@@ -380,8 +382,10 @@ def bench_batched(args, wl):
 
 def bench_warmstart(args, wl):
     """Held-out instances solved from the learned warm start (network pass, then
-    the batched solver from the predicted groups and rho0) against the cold start
-    on the same instances; a step is one pass over all of them."""
+    the batched solver from the predicted rho0, with the groups of the cold start's
+    K-means of X or, --warm-groups embedding, of the predicted centroid sketches)
+    against the cold start on the same instances; a step is one pass over all of
+    them."""
     import numpy as np
     import torch
 
@@ -408,8 +412,11 @@ def bench_warmstart(args, wl):
         infos, keep = [], []
         for Xs, ranks, lams, outs in chunks:
             emb, rho0s, fbs = rp.warmstart_batched(Xs, ranks, P, hidden, sseed)
-            plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s, init_embeddings=emb,
-                                       embedding_refine=args.embedding_refine)
+            if args.warm_groups == "embedding":
+                plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s, init_embeddings=emb,
+                                           embedding_refine=args.embedding_refine)
+            else:   # the predicted rho0 only; groups by the cold start's K-means of X
+                plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s)
             infos += rp.solve_batched(Xs, plist, outs=outs)[1]
             keep.append((emb, k, fbs))
         return infos, keep
@@ -436,6 +443,7 @@ def bench_warmstart(args, wl):
         cold = cold_pass()
     torch.cuda.synchronize()
     cold_s = time.perf_counter() - t0
+    cold_phases = rp.batched_phases()   # the last cold launch
     cold_err = errors()
     rp.profile_enable(True)
     t0 = time.perf_counter()
@@ -445,6 +453,14 @@ def bench_warmstart(args, wl):
     warm_s = time.perf_counter() - t0
     prof = rp.profile_query()["batched"]
     rp.profile_enable(False)
+    warm_phases = rp.batched_phases()   # the last warm launch (same instances as cold_phases)
+    # the network pass alone (sketch, features, MLP, pooling) for all chunks
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for Xs, ranks, _, _ in chunks:
+        rp.warmstart_batched(Xs, ranks, P, hidden, sseed)
+    torch.cuda.synchronize()
+    net_ms = 1e3 * (time.perf_counter() - t0) / len(chunks)
     warm_err = errors()
     fallbacks = sum(sum(k[2]) for k in keep)
     ratio = np.array(warm_err) / np.array(cold_err)
@@ -470,11 +486,14 @@ def bench_warmstart(args, wl):
                    "cold_converged": sum(f["status"] == 0 for f in cold),
                    "fallbacks": int(fallbacks),
                    "embedding_refine": args.embedding_refine,
+                   "warm_groups": args.warm_groups,
                    "err_vs_planted_ratio_warm_over_cold": {
                        "median": round(float(np.median(ratio)), 5), "max": round(float(ratio.max()), 5)},
                    "tuner_seconds": round(tune_s, 2)},
         "cold_solves_per_s": round(count * args.steps / cold_s, 2),
         "speedup_vs_cold": round(cold_s / warm_s, 4),
+        "network_pass_ms_per_launch": round(net_ms, 3),
+        "phases_ms_last_launch": {"warm": warm_phases, "cold": cold_phases},
         "roofline": batched_roofline(prof, "warmstart"),
     }
     if not args.no_cpu_baseline:
@@ -505,8 +524,10 @@ def calibrate_mix(args):
     """Practical bandwidth ceilings: the library's streaming probe over 1 GiB
     arrays for the read/write mixes of the method's passes."""
     from paper_1904_07497_amd import respca as rp
-    mixes = [(1, 0, "streaming read"), (1, 1, "copy"), (3, 0, "means pass (X, S, Theta)"),
-             (3, 1, "3 reads + 1 write"), (4, 3, "sweep (X, S, Theta, L in; L, S, Theta out)")]
+    mixes = [(1, 0, "streaming read"), (1, 1, "copy"), (2, 0, "means pass on the compact state (X, B)"),
+             (3, 0, "means pass (X, S, Theta)"), (3, 1, "3 reads + 1 write"),
+             (3, 2, "l1 sweep on the compact state (X, B, L in; L, B out)"),
+             (4, 3, "sweep (X, S, Theta, L in; L, S, Theta out)")]
     out = []
     for r, w, what in mixes:
         gbps, ms = rp.bandwidth_probe(r, w, 1 << 30, reps=max(args.steps, 5))
@@ -684,6 +705,10 @@ def main():
     ap.add_argument("--embedding-refine", type=int, default=1, choices=[0, 1],
                     help="warmstart workload: Lloyd passes on X after the embedding's K-means (1) "
                          "or the iterations straight from the embedding's groups (0)")
+    ap.add_argument("--warm-groups", default="kmeans", choices=["embedding", "kmeans"],
+                    help="warmstart workload: initial groups from the predicted centroid sketches "
+                         "(embedding) or from the cold start's K-means of X, with the predicted "
+                         "rho0 in both (kmeans)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the last-iteration comparison with the FP64 oracle")
     ap.add_argument("--tune-cache", default=None,
@@ -799,11 +824,13 @@ def main():
                 "kernel": name, "bytes_per_launch": bpl, "mean_launch_ms": round(secs * 1e3, 4)}
 
     def sweep_with_ceiling(r, rp, array_bytes):
-        """The sweep's figure beside the measured ceiling of its 4-read/3-write mix
-        (the library's streaming probe over arrays of the sweep's size)."""
-        gbps, _ = rp.bandwidth_probe(4, 3, (array_bytes // 16) * 16, reps=10)
+        """The sweep's figure beside the measured ceiling of its read/write mix (the
+        library's streaming probe over arrays of the sweep's size): 3 reads + 2
+        writes for the l1 sweep on the compact state, 4 + 3 for the l2,1 sweep."""
+        reads, writes = (4, 3) if wl.get("sparse_norm", 0) == 1 else (3, 2)
+        gbps, _ = rp.bandwidth_probe(reads, writes, (array_bytes // 16) * 16, reps=10)
         r = dict(r)
-        r["ceiling_4r3w_GBps"] = round(gbps, 1)
+        r[f"ceiling_{reads}r{writes}w_GBps"] = round(gbps, 1)
         r["frac_of_ceiling"] = round(r["achieved"] / gbps, 4) if gbps > 0 else None
         return r
 

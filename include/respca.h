@@ -170,7 +170,11 @@ const char   *respca_version(void);
  * rho = rho0, groups = K-means of the columns of X (k-means++ seeding from
  * splitmix64(seed), then Lloyd) unless params->init_labels is given.
  * ||X||_F == 0 returns RESPCA_OK with L = S = 0, labels 0 and iters = 0.
- * Returns RESPCA_OK, RESPCA_NOT_CONVERGED or an error.
+ * With the l1 penalty, S also holds the iteration's working state (X - L +
+ * Theta/rho, from which the S-step and the multiplier follow) and receives the
+ * sparse part when the iterations end.
+ * Returns RESPCA_OK, RESPCA_NOT_CONVERGED or an error (then L and S are
+ * unspecified).
  */
 respca_status respca_solve(respca_handle h, const respca_params *params,
                            int64_t d, int64_t n,

@@ -26,8 +26,7 @@ struct BatchInst {
     // internal copies, zero-padded to dp rows (leading dimension dp)
     float* X;
     float* L;
-    float* S;
-    float* Th;
+    float* S;                  // B = X - L + Theta/rho of the last sweep (S and Theta follow)
     float* Z;                  // embedding copy zero-padded to kdp rows (null without one)
     float* C;                  // centroids, leading dimension = rows of the current K-means matrix
     int32_t* lab[2];
@@ -58,13 +57,14 @@ struct BatchInst {
     // state
     int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, ref_lloyd, status, nseg;
     int next_ready;            // pmeans and the sort tables hold the next L-step's group sums
-    int meansd;                // outer iterations that ran the means pass over X, S, Theta
+    int meansd;                // outer iterations that ran the means pass over X and B
     int pmode;                 // mode of the previous step
     int moved;                 // columns whose label the previous step's assignment changed
     int inc;                   // this step's means are the incremental update (moved columns only)
     int inc_steps[2];          // incremental means steps on the d-row matrices [0] / the embedding [1]
     int64_t inc_cols[2];       // columns those steps read (two per moved column)
     double rho, nx, rho_final, primal, dL, dS;
+    double rho_prev;           // penalty of the last sweep: S holds the compact state B of it
 };
 
 // Phases of the persistent kernel, for its per-phase timing.

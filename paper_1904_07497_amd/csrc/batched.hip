@@ -403,6 +403,7 @@ __device__ void control_instance(BatchInst& B, int* active) {
         return;
     }
     if (changed) B.cur ^= 1;
+    B.rho_prev = B.rho;   // the penalty this iteration's sweep used
     const double next = B.kappa * B.rho;
     B.rho = next < B.rho_max ? next : B.rho_max;
     const double crit = fmax(B.primal, fmax(B.dL, B.dS));
@@ -511,8 +512,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                     a += (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z + (double)x.w * x.w;
                     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
                     *reinterpret_cast<float4*>(B.L + j * B.dp + r) = z;
-                    *reinterpret_cast<float4*>(B.S + j * B.dp + r) = z;
-                    *reinterpret_cast<float4*>(B.Th + j * B.dp + r) = z;
+                    *reinterpret_cast<float4*>(B.S + j * B.dp + r) = z;   // B = 0: S = Theta = 0
                 }
             }
         }
@@ -548,6 +548,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             B.inc_steps[0] = B.inc_steps[1] = 0;
             B.inc_cols[0] = B.inc_cols[1] = 0;
             B.rho = B.rho0;
+            B.rho_prev = B.rho0;   // B = 0 stands for S = Theta = 0 at any penalty
             B.rho_final = 0.0;
             B.primal = B.dL = B.dS = 0.0;
             B.nseg = 0;
@@ -663,10 +664,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             const int64_t r0 = (int64_t)rb * kBatchRows;
             if (r0 >= rows) return;
             double* out = B.pmeans + (int64_t)s * rows;
-            if (mode == M_ITER)
-                group_partial_tile<float, 4, true, kBatchRows, 4>(
-                    B.X, B.dp, B.S, B.dp, B.Th, B.dp, (float)(1.0 / B.rho), B.dp, B.perm, B.segb[s],
-                    B.segl[s], r0, out);
+            if (mode == M_ITER)   // D from the compact state B of the last sweep
+                group_partial_tile<float, 4, true, kBatchRows, 4, true>(
+                    B.X, B.dp, B.S, B.dp, nullptr, 0, (float)(1.0 / B.rho), B.dp, B.perm, B.segb[s],
+                    B.segl[s], r0, out, (float)B.rho_prev, (float)(1.0 / B.rho_prev));
             else
                 group_partial_tile<float, 4, false, kBatchRows, 4>(
                     kmeans_matrix(B, mode), rows, nullptr, 0, nullptr, 0, 0.f, rows, B.perm,
@@ -816,10 +817,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 const double next = B.kappa * rho;
                 const double inv_next = 1.0 / (next < B.rho_max ? next : B.rho_max);
                 const int begin = B.segb[sg];
-                seg_sweep_tile<float, 4, kBatchRows, 4, 2>(
-                    B.X, B.dp, B.L, B.dp, B.S, B.dp, B.Th, B.dp, B.C, B.lab[B.cur][B.perm[begin]], B.dp,
+                seg_sweep_tile<float, 4, kBatchRows, 4, 2, false, true>(   // compact l1 state in S
+                    B.X, B.dp, B.L, B.dp, B.S, B.dp, nullptr, 0, B.C, B.lab[B.cur][B.perm[begin]], B.dp,
                     B.perm, begin, B.segl[sg], r0, (float)alpha, (float)beta, (float)rho,
-                    (float)(1.0 / rho), (float)inv_next, a0, a1, a2, B.pmeans + (int64_t)sg * B.dp);
+                    (float)(1.0 / rho), (float)inv_next, a0, a1, a2, B.pmeans + (int64_t)sg * B.dp,
+                    nullptr, (float)B.rho_prev, (float)(1.0 / B.rho_prev));
             }
             block_sum3(a0, a1, a2);
             if (threadIdx.x == 0) {
@@ -937,7 +939,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         if (!grid_sync(gs, nb, tmo, BP_CONTROL, tclk)) return;
     }
 
-    // ---- results: L, S (first d rows) and labels into the caller's buffers
+    // ---- results: L, S = soft(B, 1/rho of the last sweep) (first d rows) and labels
+    //      into the caller's buffers
     load_tab(A.off_tile);
     for (int t = threadIdx.x; t < batch; t += kBlock) s_mode[t] = 1;
     __syncthreads();
@@ -949,10 +952,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         const int64_t r0 = (int64_t)rb * kBatchRows;
         const int64_t r1 = min((int64_t)B.d, r0 + kBatchRows);
         const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wave per column
+        const float tau = (float)(1.0 / B.rho_prev);
         for (int64_t j = j0 + w; j < j1; j += kBlock / 64)
             for (int64_t r = r0 + lane; r < r1; r += 64) {
                 B.Lc[j * B.ldl + r] = B.L[j * B.dp + r];
-                B.Sc[j * B.lds + r] = B.S[j * B.dp + r];
+                B.Sc[j * B.lds + r] = soft_threshold(B.S[j * B.dp + r], tau);
             }
     });
     for (int i = blockIdx.x; i < batch; i += nb) {

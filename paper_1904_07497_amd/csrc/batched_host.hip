@@ -155,8 +155,7 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
         B.X = (float*)take(dpn);
         B.L = (float*)take(dpn);
-        B.S = (float*)take(dpn);
-        B.Th = (float*)take(dpn);
+        B.S = (float*)take(dpn);   // the compact l1 state B = X - L + Theta/rho until the end
         B.Z = B.Ec ? (float*)take((size_t)B.kdp * B.n * sizeof(float)) : nullptr;
         B.C = (float*)take((size_t)B.mrows * B.c * sizeof(float));
         B.lab[0] = (int32_t*)take(B.n * sizeof(int32_t));
@@ -226,7 +225,7 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     const double* u_dev = (const double*)(base + L.u_off);
     for (int i = 0; i < batch; ++i) {
         BatchInst& B = call.inst[i];
-        fix(B.X); fix(B.L); fix(B.S); fix(B.Th); fix(B.C); fix(B.lab[0]); fix(B.lab[1]); fix(B.perm);
+        fix(B.X); fix(B.L); fix(B.S); fix(B.C); fix(B.lab[0]); fix(B.lab[1]); fix(B.perm);
         fix(B.counts); fix(B.segb); fix(B.segl); fix(B.segf); fix(B.pmeans); fix(B.part); fix(B.d2);
         fix(B.chosen); fix(B.seeds); fix(B.cnorm); fix(B.gsum); fix(B.sweep_part); fix(B.chg);
         if (B.Ec) fix(B.Z);
@@ -322,13 +321,14 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
     for (int i = 0; i < batch; ++i) {
         const BatchInst& B = out[i];
         if (B.status >= 0 && B.nx > 0.0) {
-            // passes over X: ||X||; 7 + 1 per outer iteration (sweep, assignment) and 3
-            // more for each that ran the means pass (the others had the group sums from
-            // the previous sweep); 2 per extra Lloyd pass on L; and the start: the means
+            // passes over X: ||X||; 5 + 1 per outer iteration (the sweep on the compact
+            // state: X, B, L in and L, B out; the assignment) and 2 more for each that
+            // ran the means pass over X and B (the others had the group sums from the
+            // previous sweep); 2 per extra Lloyd pass on L; and the start: the means
             // of X for given labels, seeding (c passes) + nearest-seed assignment + 2 per
             // Lloyd pass for a cold start, or for an embedding 2 per Lloyd pass on X plus
             // two means of X, with its seeding and Lloyd passes counted on the embedding
-            double px = 1.0 + 8.0 * B.iters + 3.0 * B.meansd + 2.0 * (B.lloyd_total - B.iters);
+            double px = 1.0 + 6.0 * B.iters + 2.0 * B.meansd + 2.0 * (B.lloyd_total - B.iters);
             double pz = 0.0;
             if (call.inst[i].init_labels) px += 1.0;
             else if (B.Z) {

@@ -259,6 +259,19 @@ __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __res
     }
 }
 
+// The l1 proximal step and the multiplier it leaves: soft(b, tau) =
+// sign(b) max(|b| - tau, 0), and clip(t) = t clamped to [-1, 1] (a NaN stays NaN).
+template <typename T>
+__device__ inline T soft_threshold(T b, T tau) {
+    const T mag = fabs(b) - tau;
+    return mag > T(0) ? copysign(mag, b) : T(0);
+}
+
+template <typename T>
+__device__ inline T clip_unit(T t) {
+    return t > T(1) ? T(1) : (t < T(-1) ? T(-1) : t);
+}
+
 // The fused sweep over one group segment: the `len` columns perm[begin..) (all in
 // group p) over rows [r0, r0 + ROWS), CG column groups of kBlock / CG threads
 // (group g takes the segment's columns g, g + CG, ...), U columns in flight.  Per
@@ -268,7 +281,13 @@ __device__ inline void sweep_tile(const T* __restrict__ X, int64_t ldx, T* __res
 // groups added in group order), written to out[i] (this segment's d-vector).
 // L21: the column-wise (l2,1) S-step, S_j = fac[j] B_j with the per-column factor
 // max(0, 1 - 1/(rho ||B_j||)) computed beforehand over the whole column.
-template <typename T, int V, int ROWS, int CG, int U, bool L21 = false>
+// COMPACT (l1 only): the state is B = X - L + Theta_old / rho, kept in S (Th is
+// not used).  The l1 S-step and the multiplier update are functions of B alone:
+// S = soft(B, 1/rho) and Theta_old + rho (X - L - S) = rho (B - S) = clip(rho B), so
+// S and Theta of the previous iteration are recovered from its B with its
+// penalty rho_prev, and the sweep reads X, B, L and writes L, B (five d x n
+// streams instead of seven).
+template <typename T, int V, int ROWS, int CG, int U, bool L21 = false, bool COMPACT = false>
 __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* __restrict__ L,
                                       int64_t ldl, T* __restrict__ S, int64_t lds,
                                       T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
@@ -276,7 +295,9 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
                                       int begin, int len, int64_t r0, T alpha, T beta, T rho,
                                       T inv_rho, T inv_rho_next, double& a0, double& a1, double& a2,
                                       double* __restrict__ out,
-                                      const double* __restrict__ fac = nullptr) {
+                                      const double* __restrict__ fac = nullptr,
+                                      T rho_prev = T(0), T inv_rho_prev = T(0)) {
+    static_assert(!(COMPACT && L21), "the compact state holds the l1 form only");
     constexpr int TPC = kBlock / CG;
     constexpr int NS = ROWS / (TPC * V);
     static_assert(NS >= 1 && NS * TPC * V == ROWS, "row block must tile the column group");
@@ -310,17 +331,25 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
                 if (!FULL && jj[u] < 0) continue;
                 vload<T, V>(X + jj[u] * ldx + i, xs[u]);
                 vload<T, V>(S + jj[u] * lds + i, ss[u]);
-                vload<T, V>(Th + jj[u] * ldt + i, ts[u]);
+                if constexpr (!COMPACT) vload<T, V>(Th + jj[u] * ldt + i, ts[u]);
                 vload<T, V>(L + jj[u] * ldl + i, lps[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (!FULL && jj[u] < 0) continue;
                 const int64_t j = jj[u];
-                T ln[V], sn[V], tn[V];
+                T ln[V], sn[V], tn[V], bn[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const T x = xs[u][v], sv = ss[u][v], t = ts[u][v];
+                    const T x = xs[u][v];
+                    T sv, t;
+                    if constexpr (COMPACT) {
+                        sv = soft_threshold(ss[u][v], inv_rho_prev);
+                        t = clip_unit(rho_prev * ss[u][v]);
+                    } else {
+                        sv = ss[u][v];
+                        t = ts[u][v];
+                    }
                     const T dv = x - sv + t * inv_rho;
                     ln[v] = alpha * dv + beta * m[v];
                     const T b = x - ln[v] + t * inv_rho;
@@ -331,7 +360,8 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
                         sn[v] = mag > T(0) ? copysign(mag, b) : T(0);
                     }
                     const T rr = x - ln[v] - sn[v];
-                    tn[v] = t + rho * rr;
+                    tn[v] = COMPACT ? clip_unit(rho * b) : t + rho * rr;
+                    bn[v] = b;
                     const double dl = (double)ln[v] - (double)lps[u][v];
                     const double ds = (double)sn[v] - (double)sv;
                     a0 += (double)rr * (double)rr;
@@ -340,8 +370,12 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
                     acc[a][v] += (double)(x - sn[v] + tn[v] * inv_rho_next);
                 }
                 vstore<T, V>(L + j * ldl + i, ln);
-                vstore<T, V>(S + j * lds + i, sn);
-                vstore<T, V>(Th + j * ldt + i, tn);
+                if constexpr (COMPACT) {
+                    vstore<T, V>(S + j * lds + i, bn);
+                } else {
+                    vstore<T, V>(S + j * lds + i, sn);
+                    vstore<T, V>(Th + j * ldt + i, tn);
+                }
             }
         }
     };
@@ -381,12 +415,15 @@ __device__ inline void seg_sweep_tile(const T* __restrict__ X, int64_t ldx, T* _
 // written to out[i] (out points at this segment's d-vector).  With CG column
 // groups, group g sums the segment's columns g, g + CG, ... and the CG partial
 // sums are added in group order at the end; the order of every sum is fixed.
-template <typename T, int V, bool WITH_D, int ROWS = kRowsPerBlock, int CG = 1>
+// COMPACT (with D): S holds the compact state B of the previous sweep (penalty
+// rho_prev), from which D = X - soft(B, 1/rho_prev) + clip(rho_prev B) * inv_rho.
+template <typename T, int V, bool WITH_D, int ROWS = kRowsPerBlock, int CG = 1, bool COMPACT = false>
 __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
                                           const T* __restrict__ S, int64_t lds,
                                           const T* __restrict__ Th, int64_t ldt, T inv_rho,
                                           int64_t d, const int32_t* __restrict__ perm, int begin,
-                                          int len, int64_t r0, double* __restrict__ out) {
+                                          int len, int64_t r0, double* __restrict__ out,
+                                          T rho_prev = T(0), T inv_rho_prev = T(0)) {
     constexpr int TPC = kBlock / CG;
     constexpr int NS = ROWS / (TPC * V);
     static_assert(NS >= 1 && NS * TPC * V == ROWS, "row block must tile the column group");
@@ -401,7 +438,13 @@ __device__ inline void group_partial_tile(const T* __restrict__ A, int64_t lda,
         for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
     auto value = [&](int64_t j, int64_t i, T (&x)[V]) {
         vload<T, V>(A + j * lda + i, x);
-        if constexpr (WITH_D) {
+        if constexpr (WITH_D && COMPACT) {
+            T bv[V];
+            vload<T, V>(S + j * lds + i, bv);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                x[v] = x[v] - soft_threshold(bv[v], inv_rho_prev) + clip_unit(rho_prev * bv[v]) * inv_rho;
+        } else if constexpr (WITH_D) {
             T sv[V], tv[V];
             vload<T, V>(S + j * lds + i, sv);
             vload<T, V>(Th + j * ldt + i, tv);

@@ -90,6 +90,32 @@ int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t l
 // B = X - L + Theta * inv_rho and L the L-step's alpha D + beta C[:, labels[j]]
 // (D = X - S + Theta * inv_rho), evaluated as the sweep evaluates it.  Passing
 // fac to launch_sweep_seg then makes its S-step S_j = fac[j] B_j.
+// The l1 sweep on the compact state: B (d x n, ldb) holds X - L + Theta/rho of
+// the previous iteration (penalty rho_prev), from which S = soft(B, 1/rho_prev)
+// and Theta = clip(rho_prev B); reads X, B, L and writes L and the new B.  Same
+// norm partials, next-step group sums and grid as launch_sweep_seg.
+template <typename T>
+int launch_sweep_seg_compact(const T* X, int64_t ldx, T* L, int64_t ldl, T* B, int64_t ldb,
+                             const T* C, const int32_t* labels, const int32_t* perm,
+                             const int32_t* seg_begin, const int32_t* seg_len, const int32_t* nseg,
+                             int64_t d, int64_t n, int c, double alpha, double beta, double rho,
+                             double inv_rho, double inv_rho_next, double rho_prev,
+                             double inv_rho_prev, double* norm_partial, double* next_partial,
+                             hipStream_t st);
+
+// Group partial sums of D = X - S + Theta inv_rho from the compact state (as
+// launch_group_partial with with_d).
+template <typename T>
+void launch_group_partial_compact(const T* X, int64_t ldx, const T* B, int64_t ldb, T inv_rho,
+                                  T rho_prev, T inv_rho_prev, int64_t d, int64_t n, int c,
+                                  const int32_t* perm, const int32_t* seg_begin,
+                                  const int32_t* seg_len, const int32_t* nseg, double* partial,
+                                  hipStream_t st);
+
+// B <- soft(B, tau) in place (the S of a compact state).
+template <typename T>
+void launch_soft_inplace(T* B, int64_t ldb, int64_t d, int64_t n, double tau, hipStream_t st);
+
 template <typename T>
 void launch_l21_factor(const T* X, int64_t ldx, const T* S, int64_t lds, const T* Th, int64_t ldt,
                        const T* C, const int32_t* labels, int64_t d, int64_t n, double alpha,

@@ -182,17 +182,19 @@ __global__ __launch_bounds__(kSortChunk) void k_sort_scatter(const int32_t* __re
 // ---------------------------------------------------------- group partials
 
 // Grid (segment slots, row slices); slots past the real segment count exit.
-template <typename T, int V, bool WITH_D>
+// COMPACT: S holds the compact state B (penalty rho_prev); Th is not read.
+template <typename T, int V, bool WITH_D, bool COMPACT = false>
 __global__ __launch_bounds__(kBlock) void k_group_partial(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ S, int64_t lds,
     const T* __restrict__ Th, int64_t ldt, T inv_rho, int64_t d, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ seg_begin, const int32_t* __restrict__ seg_len,
-    const int32_t* __restrict__ nseg, int nrb, double* __restrict__ partial) {
+    const int32_t* __restrict__ nseg, int nrb, double* __restrict__ partial, T rho_prev = T(0),
+    T inv_rho_prev = T(0)) {
     const int s = (int)(blockIdx.x / nrb);   // row blocks vary fastest
     if (s >= *nseg) return;
-    group_partial_tile<T, V, WITH_D>(A, lda, S, lds, Th, ldt, inv_rho, d, perm, seg_begin[s],
-                                     seg_len[s], (int64_t)(blockIdx.x % nrb) * kRowsPerBlock,
-                                     partial + (int64_t)s * d);
+    group_partial_tile<T, V, WITH_D, kRowsPerBlock, 1, COMPACT>(
+        A, lda, S, lds, Th, ldt, inv_rho, d, perm, seg_begin[s], seg_len[s],
+        (int64_t)(blockIdx.x % nrb) * kRowsPerBlock, partial + (int64_t)s * d, rho_prev, inv_rho_prev);
 }
 
 template <typename T>
@@ -392,7 +394,9 @@ __global__ __launch_bounds__(kBlock) void k_col_sqnorm(const T* C, int64_t d, do
 // it writes the group sums of D at the next penalty, which let the next
 // iteration skip its means pass when the p-step keeps every label.  Slots past
 // the segment count write zero norms.  L21: column-wise S-step from fac.
-template <typename T, int V, bool L21>
+// COMPACT: the l1 sweep on the compact state B (kept in S, previous penalty
+// rho_prev; Th is not used), see seg_sweep_tile.
+template <typename T, int V, bool L21, bool COMPACT = false>
 __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     const T* __restrict__ X, int64_t ldx, T* __restrict__ L, int64_t ldl, T* __restrict__ S,
     int64_t lds, T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
@@ -400,17 +404,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     const int32_t* __restrict__ seg_begin, const int32_t* __restrict__ seg_len,
     const int32_t* __restrict__ nseg, int64_t d, int nrb, T alpha, T beta, T rho, T inv_rho,
     T inv_rho_next, double* __restrict__ norm_partial, double* __restrict__ next_partial,
-    const double* __restrict__ fac) {
+    const double* __restrict__ fac, T rho_prev = T(0), T inv_rho_prev = T(0)) {
     const int sg = (int)(blockIdx.x / nrb);
     const int64_t r0 = (int64_t)(blockIdx.x % nrb) * kRowsPerBlock;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (sg < *nseg) {
         const int begin = seg_begin[sg];
-        seg_sweep_tile<T, V, kRowsPerBlock, 1, 4, L21>(X, ldx, L, ldl, S, lds, Th, ldt, C,
-                                                       labels[perm[begin]], d, perm, begin,
-                                                       seg_len[sg], r0, alpha, beta, rho, inv_rho,
-                                                       inv_rho_next, a0, a1, a2,
-                                                       next_partial + (int64_t)sg * d, fac);
+        seg_sweep_tile<T, V, kRowsPerBlock, 1, 4, L21, COMPACT>(
+            X, ldx, L, ldl, S, lds, Th, ldt, C, labels[perm[begin]], d, perm, begin, seg_len[sg], r0,
+            alpha, beta, rho, inv_rho, inv_rho_next, a0, a1, a2, next_partial + (int64_t)sg * d, fac,
+            rho_prev, inv_rho_prev);
     }
     block_sum3(a0, a1, a2);
     if (threadIdx.x == 0) {
@@ -941,7 +944,7 @@ int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t l
         kern<<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, S, lds, Th, ldt, C, labels, perm, seg_begin,
                                       seg_len, nseg, d, nrb, (T)alpha, (T)beta, (T)rho,
                                       (T)inv_rho, (T)inv_rho_next, norm_partial, next_partial,
-                                      l21_fac);
+                                      l21_fac, T(0), T(0));
     };
     if (l21_fac) {
         if (v == VV) go(k_sweep_seg<T, VV, true>);
@@ -951,6 +954,69 @@ int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t l
         else go(k_sweep_seg<T, 1, false>);
     }
     return (int)grid;
+}
+
+template <typename T>
+int launch_sweep_seg_compact(const T* X, int64_t ldx, T* L, int64_t ldl, T* B, int64_t ldb,
+                             const T* C, const int32_t* labels, const int32_t* perm,
+                             const int32_t* seg_begin, const int32_t* seg_len, const int32_t* nseg,
+                             int64_t d, int64_t n, int c, double alpha, double beta, double rho,
+                             double inv_rho, double inv_rho_next, double rho_prev,
+                             double inv_rho_prev, double* norm_partial, double* next_partial,
+                             hipStream_t st) {
+    const int nrb = row_blocks(d);
+    const unsigned grid = (unsigned)max_segments(n, c) * (unsigned)nrb;
+    constexpr int VV = 16 / sizeof(T);
+    const int v = pick_vec<T>(d, {{X, ldx}, {L, ldl}, {B, ldb}, {C, d}});
+    auto go = [&](auto kern) {
+        kern<<<grid, kBlock, 0, st>>>(X, ldx, L, ldl, B, ldb, nullptr, 0, C, labels, perm, seg_begin,
+                                      seg_len, nseg, d, nrb, (T)alpha, (T)beta, (T)rho,
+                                      (T)inv_rho, (T)inv_rho_next, norm_partial, next_partial,
+                                      nullptr, (T)rho_prev, (T)inv_rho_prev);
+    };
+    if (v == VV) go(k_sweep_seg<T, VV, false, true>);
+    else go(k_sweep_seg<T, 1, false, true>);
+    return (int)grid;
+}
+
+template <typename T>
+void launch_group_partial_compact(const T* X, int64_t ldx, const T* B, int64_t ldb, T inv_rho,
+                                  T rho_prev, T inv_rho_prev, int64_t d, int64_t n, int c,
+                                  const int32_t* perm, const int32_t* seg_begin,
+                                  const int32_t* seg_len, const int32_t* nseg, double* partial,
+                                  hipStream_t st) {
+    const int nrb = row_blocks(d);
+    const unsigned grid = (unsigned)max_segments(n, c) * (unsigned)nrb;
+    if (grid == 0) return;
+    constexpr int VV = 16 / sizeof(T);
+    const int v = pick_vec<T>(d, {{X, ldx}, {B, ldb}});
+    if (v == VV)
+        k_group_partial<T, VV, true, true><<<grid, kBlock, 0, st>>>(
+            X, ldx, B, ldb, nullptr, 0, inv_rho, d, perm, seg_begin, seg_len, nseg, nrb, partial,
+            rho_prev, inv_rho_prev);
+    else
+        k_group_partial<T, 1, true, true><<<grid, kBlock, 0, st>>>(
+            X, ldx, B, ldb, nullptr, 0, inv_rho, d, perm, seg_begin, seg_len, nseg, nrb, partial,
+            rho_prev, inv_rho_prev);
+}
+
+// S = soft(B, tau) in place over a d x n column-major matrix.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_soft_inplace(T* __restrict__ B, int64_t ldb, int64_t d,
+                                                         int64_t n, T tau) {
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < d;
+             i += (int64_t)gridDim.x * kBlock)
+            B[j * ldb + i] = soft_threshold(B[j * ldb + i], tau);
+}
+
+template <typename T>
+void launch_soft_inplace(T* B, int64_t ldb, int64_t d, int64_t n, double tau, hipStream_t st) {
+    if (d == 0 || n == 0) return;
+    const int64_t bx = (d + kBlock - 1) / kBlock;
+    const int64_t by = n < 16384 ? n : 16384;   // columns strided beyond that
+    k_soft_inplace<T><<<dim3((unsigned)(bx < 64 ? bx : 64), (unsigned)by), kBlock, 0, st>>>(B, ldb, d, n,
+                                                                                         (T)tau);
 }
 
 template <typename T>
@@ -1080,6 +1146,17 @@ void launch_gather_cols(const T* Y, int64_t ldy, int64_t d, const int32_t* idx, 
                                      const int32_t*, const int32_t*, int64_t, int64_t, int,        \
                                      double, double, double, double, double, double*, double*,     \
                                      hipStream_t, const double*);                                  \
+    template int launch_sweep_seg_compact<T>(const T*, int64_t, T*, int64_t, T*, int64_t,         \
+                                             const T*, const int32_t*, const int32_t*,             \
+                                             const int32_t*, const int32_t*, const int32_t*,       \
+                                             int64_t, int64_t, int, double, double, double,        \
+                                             double, double, double, double, double*, double*,     \
+                                             hipStream_t);                                         \
+    template void launch_group_partial_compact<T>(const T*, int64_t, const T*, int64_t, T, T, T,  \
+                                                  int64_t, int64_t, int, const int32_t*,           \
+                                                  const int32_t*, const int32_t*, const int32_t*,  \
+                                                  double*, hipStream_t);                           \
+    template void launch_soft_inplace<T>(T*, int64_t, int64_t, int64_t, double, hipStream_t);     \
     template void launch_l21_factor<T>(const T*, int64_t, const T*, int64_t, const T*, int64_t,   \
                                        const T*, const int32_t*, int64_t, int64_t, double, double,  \
                                        double, double, double*, hipStream_t);                      \

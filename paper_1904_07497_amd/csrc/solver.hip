@@ -444,10 +444,15 @@ struct Engine {
         return RESPCA_OK;
     }
 
-    // One outer iteration; norms receives the three Frobenius norms.
+    // One outer iteration; norms receives the three Frobenius norms.  rho_prev > 0
+    // selects the compact l1 state: S holds B = X - L + Theta/rho_prev of the
+    // previous iteration (S and Theta follow from it) and Th is not used.
     respca_status iterate_once(const Resolved& r, const T* X, int64_t ldx, T* L, int64_t ldl, T* S,
                                int64_t lds, T* Th, int64_t ldt, T* C, int32_t*& cur, int32_t*& alt,
-                               double rho, double norms[3], int& steps) {
+                               double rho, double norms[3], int& steps, double rho_prev = 0.0) {
+        const bool compact = rho_prev > 0.0;
+        if (compact && r.sparse_norm == RESPCA_SPARSE_L21)
+            return fail(h, RESPCA_ERR_UNSUPPORTED, "compact state with the l2,1 penalty");
         const double alpha = rho / (2.0 * r.lambda + rho);
         const double beta = (2.0 * r.lambda) / (2.0 * r.lambda + rho);
         const double inv = 1.0 / rho;
@@ -455,6 +460,17 @@ struct Engine {
         const double inv_next = 1.0 / (next < r.rho_max ? next : r.rho_max);
         if (next_ready) {
             // the previous sweep summed D over these same groups at this rho
+            launch_group_finalize<T>((const double*)h->pmeans.p, d, c, counts(),
+                                     (const int32_t*)h->segf.p, C, st);
+        } else if (compact) {
+            sort(cur);                                               // Sec. 4.1: groups of D
+            {
+                ProfScope ps(h, st, RESPCA_KERNEL_MEANS, 2.0 * (double)d * n * sizeof(T));
+                launch_group_partial_compact<T>(X, ldx, S, lds, (T)inv, (T)rho_prev,
+                                                (T)(1.0 / rho_prev), d, n, c, perm(),
+                                                (const int32_t*)h->segb.p, (const int32_t*)h->segl.p,
+                                                (const int32_t*)h->nseg.p, (double*)h->pmeans.p, st);
+            }
             launch_group_finalize<T>((const double*)h->pmeans.p, d, c, counts(),
                                      (const int32_t*)h->segf.p, C, st);
         } else {
@@ -471,7 +487,14 @@ struct Engine {
             fac = (const double*)h->l21f.p;
         }
         int np = 0;
-        {
+        if (compact) {
+            ProfScope ps(h, st, RESPCA_KERNEL_SWEEP, 5.0 * (double)d * n * sizeof(T));
+            np = launch_sweep_seg_compact<T>(X, ldx, L, ldl, S, lds, C, cur, perm(),
+                                             (const int32_t*)h->segb.p, (const int32_t*)h->segl.p,
+                                             (const int32_t*)h->nseg.p, d, n, c, alpha, beta, rho, inv,
+                                             inv_next, rho_prev, 1.0 / rho_prev, (double*)h->normp.p,
+                                             (double*)h->pmeans.p, st);
+        } else {
             ProfScope ps(h, st, RESPCA_KERNEL_SWEEP, 7.0 * (double)d * n * sizeof(T));
             np = launch_sweep_seg<T>(X, ldx, L, ldl, S, lds, Th, ldt, C, cur, perm(),
                                      (const int32_t*)h->segb.p, (const int32_t*)h->segl.p,
@@ -500,9 +523,12 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
                       respca_info* info, hipStream_t st) {
     Engine<T> e{h, st, d, n, r.c, r.precision == RESPCA_BF16GEMM_F32};
     CKS(e.setup());
-    CKS(ensure(h, h->theta, (size_t)d * n * sizeof(T)));
+    // l1 penalty: the compact state (S holds B = X - L + Theta/rho until the end,
+    // when it becomes soft(B, 1/rho)); l2,1: S and Theta as they are
+    const bool compact = r.sparse_norm != RESPCA_SPARSE_L21;
+    if (!compact) CKS(ensure(h, h->theta, (size_t)d * n * sizeof(T)));
     CKS(ensure(h, h->cbuf, (size_t)d * r.c * sizeof(T)));
-    T* Th = (T*)h->theta.p;
+    T* Th = compact ? nullptr : (T*)h->theta.p;
     T* C = (T*)h->cbuf.p;
     int32_t* cur = (int32_t*)h->lab_a.p;
     int32_t* alt = (int32_t*)h->lab_b.p;
@@ -511,8 +537,8 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
     CKS(e.sumsq(X, ldx, nx2));
     if (!std::isfinite(nx2)) return fail(h, RESPCA_ERR_NONFINITE, "X contains NaN or Inf");
     launch_zero2d<T>(L, ldl, d, n, st);
-    launch_zero2d<T>(S, lds, d, n, st);
-    launch_zero2d<T>(Th, d, d, n, st);
+    launch_zero2d<T>(S, lds, d, n, st);   // S = Theta = 0, or B = 0
+    if (!compact) launch_zero2d<T>(Th, d, d, n, st);
     if (nx2 == 0.0) {
         if (labels) launch_zero_i32(labels, n, st);
         CK(hipStreamSynchronize(st));
@@ -570,11 +596,14 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
     }
 
     double rho = r.rho0;
+    double rho_prev = r.rho0;   // B = 0 stands for S = Theta = 0 at any penalty
     info->status = RESPCA_NOT_CONVERGED;
     for (int t = 1; t <= r.max_iter; ++t) {
         double norms[3];
         int steps = 0;
-        CKS(e.iterate_once(r, X, ldx, L, ldl, S, lds, Th, d, C, cur, alt, rho, norms, steps));
+        CKS(e.iterate_once(r, X, ldx, L, ldl, S, lds, Th, d, C, cur, alt, rho, norms, steps,
+                           compact ? rho_prev : 0.0));
+        rho_prev = rho;
         info->lloyd_steps += steps;
         info->iters = t;
         info->rho_final = rho;
@@ -594,6 +623,8 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
             break;
         }
     }
+    // S of the last iteration from its B, with the threshold that iteration used
+    if (compact) launch_soft_inplace<T>(S, lds, d, n, 1.0 / rho_prev, st);
     if (labels) CK(hipMemcpyAsync(labels, cur, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     CK(hipStreamSynchronize(st));
     info->refined = e.refined;

@@ -234,10 +234,14 @@ def train(F, T, hidden=HIDDEN, epochs=8, batch=4096, lr=1e-3, w_last=16.0, seed=
 
 # ---------------------------------------------------------------- evaluation
 
-def evaluate(params, hidden, seeds, sketch_seed=SKETCH_SEED, chunk=256, log=print):
+def evaluate(params, hidden, seeds, sketch_seed=SKETCH_SEED, chunk=256, log=print,
+             groups="embedding"):
     """Cold start against the learned warm start on the instances `seeds` (batched,
     `chunk` per launch).  Solve times are of a second, timed call (graph already
-    captured); the warm time includes the network pass.  Returns per-instance lists."""
+    captured); the warm time includes the network pass.  groups: "embedding" starts
+    from the K-means of the predicted centroid sketches, "kmeans" from the cold
+    start's K-means of X (the warm start then supplies rho0 only).  Returns
+    per-instance lists."""
     import torch
     res = {k: [] for k in ("cold_iters", "warm_iters", "cold_err", "warm_err", "cold_status",
                            "warm_status", "fallback", "cold_lloyd", "warm_lloyd", "cold_init_lloyd",
@@ -266,7 +270,8 @@ def evaluate(params, hidden, seeds, sketch_seed=SKETCH_SEED, chunk=256, log=prin
             emb, rho0s, fbs = rp.warmstart_batched(Xs, ranks, params, hidden, sketch_seed)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            _, warm = _solve(Xs, ranks, rho0=rho0s, init_embeddings=emb, outs=outs)
+            _, warm = _solve(Xs, ranks, rho0=rho0s, outs=outs,
+                             init_embeddings=emb if groups == "embedding" else None)
             torch.cuda.synchronize()
         warm_s += time.perf_counter() - t0
         net_s += t1 - t0
