@@ -51,8 +51,8 @@ WORKLOADS = {
                            "of the batched size mix (d, n log-uniform in [200, 4000], rank 5..50, "
                            "1-20% sparse in [-50,50]) drawn on the device, c=rank, "
                            "lambda=1/sqrt(max(d,n)), tol=1e-6; launches of 256 instances, network "
-                           "pass included; warm runs start from the predicted rho0 (groups: the "
-                           "cold start's K-means of X unless --warm-groups embedding)",
+                           "pass included; warm runs start from the predicted rho0 and the K-means "
+                           "of X seeded by k-means++ on the predicted centroid sketches",
                       instances=1024, chunk=256, tol=1e-6, gen="warmstart"),
     "video": dict(name="RES-PCA FP32 synthetic 240x320x2000 clip (rank-5 background, 4 moving 20x20 "
                        "squares, 8-bit scale), c=5, lambda=sqrt(76800), tol=1e-6", d=76800, n=2000,
@@ -382,10 +382,10 @@ def bench_batched(args, wl):
 
 def bench_warmstart(args, wl):
     """Held-out instances solved from the learned warm start (network pass, then
-    the batched solver from the predicted rho0, with the groups of the cold start's
-    K-means of X or, --warm-groups embedding, of the predicted centroid sketches)
-    against the cold start on the same instances; a step is one pass over all of
-    them."""
+    the batched solver from the predicted rho0, with the groups of the K-means of X
+    seeded on the predicted centroid sketches; --warm-groups kmeans: the cold
+    start's K-means of X; embedding: the K-means of the sketches themselves) against
+    the cold start on the same instances; a step is one pass over all of them."""
     import numpy as np
     import torch
 
@@ -415,6 +415,9 @@ def bench_warmstart(args, wl):
             if args.warm_groups == "embedding":
                 plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s, init_embeddings=emb,
                                            embedding_refine=args.embedding_refine)
+            elif args.warm_groups == "seeds":   # seeds placed on the embedding, K-means of X
+                plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s, init_embeddings=emb,
+                                           embedding_refine=2)
             else:   # the predicted rho0 only; groups by the cold start's K-means of X
                 plist, k = rp.batch_params(ranks, lams, tol=wl["tol"], rho0=rho0s)
             infos += rp.solve_batched(Xs, plist, outs=outs)[1]
@@ -705,10 +708,11 @@ def main():
     ap.add_argument("--embedding-refine", type=int, default=1, choices=[0, 1],
                     help="warmstart workload: Lloyd passes on X after the embedding's K-means (1) "
                          "or the iterations straight from the embedding's groups (0)")
-    ap.add_argument("--warm-groups", default="kmeans", choices=["embedding", "kmeans"],
-                    help="warmstart workload: initial groups from the predicted centroid sketches "
-                         "(embedding) or from the cold start's K-means of X, with the predicted "
-                         "rho0 in both (kmeans)")
+    ap.add_argument("--warm-groups", default="seeds", choices=["embedding", "kmeans", "seeds"],
+                    help="warmstart workload, with the predicted rho0 in every case: initial groups "
+                         "from the K-means of the predicted centroid sketches (embedding), from the "
+                         "cold start's K-means of X (kmeans), or from the K-means of X seeded by "
+                         "k-means++ on the predicted sketches (seeds)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the last-iteration comparison with the FP64 oracle")
     ap.add_argument("--tune-cache", default=None,

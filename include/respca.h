@@ -125,8 +125,11 @@ typedef struct {
                              RESPCA_ERR_INVALID with the spectral p-step; default 0        */
     int32_t  init_embedding_refine; /* with init_embedding: 1 (default) runs the Lloyd passes
                              on X after the embedding's K-means, 0 starts the iterations
-                             from the embedding's groups directly; other values
-                             RESPCA_ERR_INVALID                                             */
+                             from the embedding's groups directly, 2 uses the embedding
+                             for the k-means++ seeding only (distances between embedding
+                             columns place the c seeds; the seed columns of X then start
+                             the nearest-seed assignment and Lloyd on X, as without an
+                             embedding); other values RESPCA_ERR_INVALID                   */
 } respca_params;
 
 typedef struct {

@@ -54,6 +54,8 @@ struct BatchInst {
     double lambda, tol, rho0, kappa, rho_max;
     int max_iter, max_lloyd;
     int refine_x;              // embedding starts: Lloyd on X after the embedding's K-means
+    int seed_only;             // embedding starts: the embedding only places the k-means++
+                               // seeds; their columns of X start the K-means of X
     // state
     int mode, cur, iters, lloyd_iter, lloyd_total, init_lloyd, ref_lloyd, status, nseg;
     int next_ready;            // pmeans and the sort tables hold the next L-step's group sums

@@ -133,13 +133,16 @@ __device__ inline int moved_segments(int moved, int c) {
 
 // Matrix whose columns the current mode clusters, and its row count (= its
 // leading dimension and that of the centroids).
+// (With seed_only the embedding serves the seeding distances alone: the nearest-
+// seed assignment and the K-means that follows run on X.)
+__device__ inline bool kmeans_on_z(const BatchInst& B) { return B.Z && !B.seed_only; }
 __device__ inline const float* kmeans_matrix(const BatchInst& B, int m) {
     if (m == M_ITER || m == M_LL) return B.L;
     if (m == M_MEANSX || m == M_REFX) return B.X;
-    return B.Z ? B.Z : B.X;
+    return kmeans_on_z(B) ? B.Z : B.X;
 }
 __device__ inline int mode_rows(const BatchInst& B, int m) {
-    return (m == M_SEED || m == M_KMX) ? B.kdp : B.dp;
+    return (m == M_SEED || m == M_KMX) && kmeans_on_z(B) ? B.kdp : B.dp;
 }
 
 // ------------------------------------------------------- per-instance work
@@ -370,7 +373,7 @@ __device__ void control_instance(BatchInst& B, int* active) {
         B.init_lloyd += 1;
         if (changed == 0 || B.init_lloyd >= B.max_lloyd) {
             if (changed) B.cur ^= 1;
-            B.mode = B.Z ? M_MEANSX : M_ITER;   // embedding groups: means of X next
+            B.mode = kmeans_on_z(B) ? M_MEANSX : M_ITER;   // embedding groups: means of X next
         } else {
             B.cur ^= 1;
         }
@@ -620,8 +623,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     load_tab(A.off_kc);
     for_items(batch, s_tab, s_mode, is_seed, [&](int i, int k) {
         BatchInst& B = inst[i];
-        const float* src = (B.Z ? B.Z : B.X) + (int64_t)B.seeds[k] * B.kdp;
-        for (int64_t r = threadIdx.x; r < B.kdp; r += kBlock) B.C[(int64_t)k * B.kdp + r] = src[r];
+        const int rows = mode_rows(B, M_SEED);
+        const float* src = kmeans_matrix(B, M_SEED) + (int64_t)B.seeds[k] * rows;
+        for (int64_t r = threadIdx.x; r < rows; r += kBlock) B.C[(int64_t)k * rows + r] = src[r];
     });
     if (!grid_sync(gs, nb, tmo, BP_GATHER, tclk)) return;
 
@@ -643,7 +647,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             if (threadIdx.x == 0) {
                 B.inc = inc ? 1 : 0;
                 if (inc) {
-                    const int z = (m == M_KMX && B.Z) ? 1 : 0;
+                    const int z = (m == M_KMX && kmeans_on_z(B)) ? 1 : 0;
                     B.inc_steps[z] += 1;
                     B.inc_cols[z] += 2 * (int64_t)B.moved;
                 }

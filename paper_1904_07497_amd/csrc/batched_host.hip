@@ -113,7 +113,8 @@ void plan(const BatchTune& tune, int32_t batch, const int64_t* d, const int64_t*
         B.init_labels = r.init_labels;
         B.Ec = r.init_embedding;
         B.lde = r.emb_ld;
-        B.refine_x = r.emb_refine;
+        B.refine_x = r.emb_refine == 1 ? 1 : 0;
+        B.seed_only = r.emb_refine == 2 ? 1 : 0;
         B.ldx = ldx[i];
         B.ldl = ldl[i];
         B.lds = lds[i];
@@ -331,7 +332,10 @@ respca_status run_batched(respca_handle h, const Call& call_in, int32_t batch, h
             double px = 1.0 + 6.0 * B.iters + 2.0 * B.meansd + 2.0 * (B.lloyd_total - B.iters);
             double pz = 0.0;
             if (call.inst[i].init_labels) px += 1.0;
-            else if (B.Z) {
+            else if (B.Z && B.seed_only) {   // seeding passes on the embedding, the rest on X
+                px += 1.0 + 2.0 * B.init_lloyd;
+                pz = (double)B.c;
+            } else if (B.Z) {
                 px += 2.0 + 2.0 * B.ref_lloyd;
                 pz = (double)B.c + 1.0 + 2.0 * (B.init_lloyd - B.ref_lloyd);
             } else px += (double)B.c + 1.0 + 2.0 * B.init_lloyd;

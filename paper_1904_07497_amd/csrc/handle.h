@@ -201,7 +201,7 @@ struct Resolved {
     const float* init_embedding;
     int64_t emb_ld;
     int emb_rows;
-    int emb_refine;   // Lloyd on X after the embedding's K-means (1) or not (0)
+    int emb_refine;   // Lloyd on X after the embedding's K-means (1), not (0), or seeding only (2)
 };
 
 respca_status resolve(respca_handle h, const respca_params* p, int64_t d, int64_t n, Resolved& r);

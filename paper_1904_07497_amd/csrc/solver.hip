@@ -91,8 +91,8 @@ respca_status respca::resolve(respca_handle h, const respca_params* p, int64_t d
             return fail(h, RESPCA_ERR_INVALID, "init_embedding rows/leading dimension invalid");
         if (p->precision == RESPCA_F64)
             return fail(h, RESPCA_ERR_UNSUPPORTED, "init_embedding needs an FP32 precision");
-        if (r.emb_refine != 0 && r.emb_refine != 1)
-            return fail(h, RESPCA_ERR_INVALID, "init_embedding_refine must be 0 or 1");
+        if (r.emb_refine < 0 || r.emb_refine > 2)
+            return fail(h, RESPCA_ERR_INVALID, "init_embedding_refine must be 0, 1 or 2");
     }
     if (!(r.lambda >= 0.0) || !std::isfinite(2.0 * r.lambda))
         return fail(h, RESPCA_ERR_INVALID, "lambda must be finite and >= 0");
@@ -342,6 +342,13 @@ struct Engine {
     // means (empty groups keep the seed), then Lloyd.
     respca_status kmeans(const T* Y, int64_t ldy, uint64_t seed, int max_lloyd, T* C,
                          int32_t*& cur, int32_t*& alt, int& steps) {
+        CKS(place_seeds(Y, ldy, seed));
+        return from_seeds(Y, ldy, max_lloyd, C, cur, alt, steps);
+    }
+
+    // k-means++ seeding of the columns of Y (splitmix64(seed) uniforms): the c seed
+    // column indices in h->seeds.
+    respca_status place_seeds(const T* Y, int64_t ldy, uint64_t seed) {
         CKS(ensure(h, h->d2, n * sizeof(double)));
         CKS(ensure(h, h->chosen, n * sizeof(int32_t)));
         CKS(ensure(h, h->seeds, c * sizeof(int32_t)));
@@ -400,7 +407,14 @@ struct Engine {
                 launch_d2<T>(Y, ldy, d, n, seeds, m, (double*)h->d2.p, st);
             }
         }
-        launch_gather_cols<T>(Y, ldy, d, seeds, c, C, st);
+        return RESPCA_OK;
+    }
+
+    // K-means of the columns of Y from the seeds in h->seeds: centroids = the seed
+    // columns of Y, nearest-seed assignment, then Lloyd.
+    respca_status from_seeds(const T* Y, int64_t ldy, int max_lloyd, T* C, int32_t*& cur,
+                             int32_t*& alt, int& steps) {
+        launch_gather_cols<T>(Y, ldy, d, (const int32_t*)h->seeds.p, c, C, st);
         launch_zero_i32(cur, n, st);
         assign(Y, ldy, C, cur, alt);
         std::swap(cur, alt);
@@ -547,7 +561,19 @@ respca_status solve_t(respca_handle h, const Resolved& r, int64_t d, int64_t n, 
     }
     const double nX = std::sqrt(nx2);
 
-    if (r.init_embedding) {
+    if (r.init_embedding && r.emb_refine == 2) {
+        // the embedding places the k-means++ seeds; their columns of X start the
+        // K-means of X (as without an embedding)
+        {
+            Engine<float> ez{h, st, r.emb_rows, n, r.c, false};
+            CKS(ez.setup());
+            CKS(ez.place_seeds(r.init_embedding, r.emb_ld, r.seed));
+        }
+        CKS(e.setup());
+        int steps = 0;
+        CKS(e.from_seeds(X, ldx, r.max_lloyd, C, cur, alt, steps));
+        info->init_lloyd = steps;
+    } else if (r.init_embedding) {
         // groups from K-means of the embedding's columns, then as with init labels
         CKS(ensure(h, h->embl, n * sizeof(int32_t)));
         CKS(ensure(h, h->embc, (size_t)r.emb_rows * r.c * sizeof(float)));

@@ -114,34 +114,45 @@ __global__ __launch_bounds__(256) void k_sketch_mfma_b(const WarmDesc* __restric
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) acc[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
     double nrm = 0.0;
-    for (int64_t i0 = 0; i0 < w.d; i0 += 16) {
-        const int64_t r = i0 + 4 * g;
-        float xv[4] = {0.f, 0.f, 0.f, 0.f};
-        uint64_t hv[4] = {0, 0, 0, 0};
-        if (vec && r + 4 <= w.d) {
-            if (colok) {
-                const float4 t = *reinterpret_cast<const float4*>(x + r);
-                xv[0] = t.x; xv[1] = t.y; xv[2] = t.z; xv[3] = t.w;
-            }
+    // four 16-row steps per pass: their loads are issued together, then the steps
+    // are multiplied in row order (the same order as one step at a time)
+    constexpr int U = 4;
+    for (int64_t i0 = 0; i0 < w.d; i0 += 16 * U) {
+        float xv[U][4];
+        uint64_t hv[U][4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) hv[e] = hash[r + e];
-        } else {
+        for (int u = 0; u < U; ++u) {
+            const int64_t r = i0 + 16 * u + 4 * g;
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (r + e < w.d) {
-                    xv[e] = colok ? x[r + e] : 0.f;
-                    hv[e] = hash[r + e];
+            for (int e = 0; e < 4; ++e) { xv[u][e] = 0.f; hv[u][e] = 0; }
+            if (vec && r + 4 <= w.d) {
+                if (colok) {
+                    const float4 t = *reinterpret_cast<const float4*>(x + r);
+                    xv[u][0] = t.x; xv[u][1] = t.y; xv[u][2] = t.z; xv[u][3] = t.w;
                 }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) hv[u][e] = hash[r + e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (r + e < w.d) {
+                        xv[u][e] = colok ? x[r + e] : 0.f;
+                        hv[u][e] = hash[r + e];
+                    }
+            }
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) nrm += (double)xv[e] * (double)xv[e];
+        for (int u = 0; u < U; ++u) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+            for (int e = 0; e < 4; ++e) nrm += (double)xv[u][e] * (double)xv[u][e];
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                const float a = ((hv[e] >> (16 * kb + q)) & 1ull) ? -0.125f : 0.125f;
-                acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xv[e], acc[kb], 0, 0, 0);
-            }
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) {
+                    const float a = ((hv[u][e] >> (16 * kb + q)) & 1ull) ? -0.125f : 0.125f;
+                    acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xv[u][e], acc[kb], 0, 0, 0);
+                }
+        }
     }
     nrm += __shfl_xor(nrm, 16);
     nrm += __shfl_xor(nrm, 32);
@@ -384,16 +395,105 @@ void launch_features(const float* Y, int64_t d, int64_t n, int c, double* total,
 }
 
 // acts: [a1 (B x h) | a2 (B x h) | a3 (B x h) | y (B x 65)], y is the network output.
+// One dense layer of the forward pass on the FP32 matrix cores:
+// C[m][n] = act(sum_k A[m][k] W[n][k] + bias[n]) with A row-major (lda = K), W the
+// layer's [N][K] row-major weights and C row-major (ldc = N); K % 4 == 0.  A wave
+// takes 16 rows and NB blocks of 16 outputs (the grid's y index steps over
+// 16 NB-column chunks); per 16-deep chunk of K, lane (q, g) = (lane % 16, lane / 16)
+// loads A[row q][k0 + 4g .. +3] and W[col 16b + q][k0 + 4g .. +3] as single
+// 16-byte loads and feeds them to four v_mfma_f32_16x16x4f32 steps: step s takes
+// k = k0 + 4g + s from lane group g, the same permutation of K on both operands,
+// so each output is the whole sum.  Output register v of a block is row 4g + v,
+// column q.
+template <int NB, bool RELU>
+__global__ __launch_bounds__(256) void k_dense_mfma(int64_t M, int N, int K,
+                                                    const float* __restrict__ A,
+                                                    const float* __restrict__ W,
+                                                    const float* __restrict__ bias,
+                                                    float* __restrict__ C) {
+    const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (m0 >= M) return;
+    const int n0 = blockIdx.y * 16 * NB;
+    const int64_t ra = m0 + q < M ? m0 + q : M - 1;   // rows past M: loads clamped, not written
+    const float* ap = A + ra * K + 4 * g;
+    const float* wp[NB];
+    bool wok[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int n = n0 + 16 * b + q;
+        wok[b] = n < N;
+        wp[b] = W + (int64_t)(wok[b] ? n : 0) * K + 4 * g;
+    }
+    f32x4 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const bool kok = k0 + 4 * g < K;
+        const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 a = kok ? *reinterpret_cast<const f32x4*>(ap + k0) : z;
+        f32x4 w[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) w[b] = (kok && wok[b]) ? *reinterpret_cast<const f32x4*>(wp[b] + k0) : z;
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], w[b][st], acc[b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int n = n0 + 16 * b + q;
+        if (!wok[b]) continue;
+        const float bn = bias[n];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t m = m0 + 4 * g + v;
+            if (m >= M) continue;
+            float y = acc[b][v] + bn;
+            if (RELU) y = y > 0.f ? y : 0.f;
+            C[m * N + n] = y;
+        }
+    }
+}
+
+template <int NB>
+void dense_mfma(int64_t M, int N, int K, const float* A, const float* W, const float* bias, bool relu,
+                float* C, hipStream_t st) {
+    const dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 16 * NB - 1) / (16 * NB)));
+    if (relu) k_dense_mfma<NB, true><<<grid, 256, 0, st>>>(M, N, K, A, W, bias, C);
+    else k_dense_mfma<NB, false><<<grid, 256, 0, st>>>(M, N, K, A, W, bias, C);
+}
+
+// A layer through the matrix-core kernel (output blocks per wave: the fewest of
+// 1, 2, 4, 5, 8, 16 that cover N, at most 16).
+void dense(int64_t M, int N, int K, const float* A, const float* W, const float* bias, bool relu,
+           float* C, hipStream_t st) {
+    const int nb = (N + 15) / 16;
+    if (nb <= 1) dense_mfma<1>(M, N, K, A, W, bias, relu, C, st);
+    else if (nb <= 2) dense_mfma<2>(M, N, K, A, W, bias, relu, C, st);
+    else if (nb <= 4) dense_mfma<4>(M, N, K, A, W, bias, relu, C, st);
+    else if (nb <= 5) dense_mfma<5>(M, N, K, A, W, bias, relu, C, st);
+    else if (nb <= 8) dense_mfma<8>(M, N, K, A, W, bias, relu, C, st);
+    else dense_mfma<16>(M, N, K, A, W, bias, relu, C, st);
+}
+
 void launch_mlp_forward(const float* P, int hidden, int batch, const float* x, float* acts,
                         hipStream_t st) {
     const int dims[5] = {kWarmIn, hidden, hidden, hidden, kWarmOut};
     const float* a = x;
     const float* w = P;
     float* out = acts;
+    // the matrix-core layers load 16 bytes at a time: every layer's rows and weight
+    // blocks are then 16-byte aligned when the three buffers are (widths are
+    // multiples of 4); otherwise the LDS-tiled FP32 kernel
+    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+    const bool mfma = al16(P) && al16(x) && al16(acts) && hidden % 4 == 0;
     for (int l = 0; l < 4; ++l) {
         const int in = dims[l], o = dims[l + 1];
         const float* b = w + (int64_t)in * o;
-        gemm(batch, o, in, a, in, 1, w, 1, in, b, l < 3 ? 1 : 0, nullptr, false, out, o, st);
+        if (mfma) dense(batch, o, in, a, w, b, l < 3, out, st);   // weights [o][in], bias after them
+        else gemm(batch, o, in, a, in, 1, w, 1, in, b, l < 3 ? 1 : 0, nullptr, false, out, o, st);
         a = out;
         out += (int64_t)batch * o;
         w = b + o;

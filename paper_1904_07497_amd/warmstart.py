@@ -132,10 +132,10 @@ def load_model(path=MODEL_PATH, device="cuda"):
 # ------------------------------------------------------------------- solving
 
 def _solve(Xs, ranks, rho0=COLD_RHO0, init_labels=None, init_embeddings=None, outs=None,
-           tol=TOL):
+           tol=TOL, embedding_refine=1):
     lams = [lam_of(*X.shape) for X in Xs]
     plist, keep = rp.batch_params(ranks, lams, tol=tol, rho0=rho0, init_labels=init_labels,
-                                  init_embeddings=init_embeddings)
+                                  init_embeddings=init_embeddings, embedding_refine=embedding_refine)
     outs, infos, _ = rp.solve_batched(Xs, plist, outs=outs)
     return outs, infos
 
@@ -240,7 +240,8 @@ def evaluate(params, hidden, seeds, sketch_seed=SKETCH_SEED, chunk=256, log=prin
     `chunk` per launch).  Solve times are of a second, timed call (graph already
     captured); the warm time includes the network pass.  groups: "embedding" starts
     from the K-means of the predicted centroid sketches, "kmeans" from the cold
-    start's K-means of X (the warm start then supplies rho0 only).  Returns
+    start's K-means of X (the warm start then supplies rho0 only), "seeds" from the
+    K-means of X seeded by k-means++ on the predicted sketches.  Returns
     per-instance lists."""
     import torch
     res = {k: [] for k in ("cold_iters", "warm_iters", "cold_err", "warm_err", "cold_status",
@@ -271,7 +272,8 @@ def evaluate(params, hidden, seeds, sketch_seed=SKETCH_SEED, chunk=256, log=prin
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             _, warm = _solve(Xs, ranks, rho0=rho0s, outs=outs,
-                             init_embeddings=emb if groups == "embedding" else None)
+                             init_embeddings=None if groups == "kmeans" else emb,
+                             embedding_refine=2 if groups == "seeds" else 1)
             torch.cuda.synchronize()
         warm_s += time.perf_counter() - t0
         net_s += t1 - t0

@@ -871,7 +871,19 @@ def _refine_on_x(X, lab, c, max_lloyd=100):
     return lab2, steps
 
 
-def _oracle_from_embedding(X, E, c, lam, seed, refine=True, **kw):
+def _oracle_from_embedding(X, E, c, lam, seed, refine=1, **kw):
+    """The oracle's chain for an embedding start: K-means of the embedding's columns
+    (then Lloyd on X when refine == 1), or with refine == 2 k-means++ seeds placed on
+    the embedding whose columns of X start the nearest-seed assignment and Lloyd on X."""
+    if refine == 2:
+        seeds = oracle.kmeanspp(E, c, seed)
+        X64 = np.asarray(X, np.float64, order="F")
+        C = np.asfortranarray(X64[:, seeds])
+        lab = oracle.assign(X64, C)
+        C, _ = oracle.group_means(X64, lab, c, mean_init=C)
+        lab, _, steps = oracle.lloyd(X64, C, lab, 100)
+        o = oracle.solve(X, oracle.make_params(c, lam=lam, seed=seed, **kw), init_labels=lab)
+        return o, steps
     lab, _, steps = oracle.kmeans(E, c, seed, 100)
     ref = 0
     if refine:
@@ -880,13 +892,13 @@ def _oracle_from_embedding(X, E, c, lam, seed, refine=True, **kw):
     return o, steps + ref
 
 
-@pytest.mark.parametrize("refine", [1, 0])
+@pytest.mark.parametrize("refine", [1, 0, 2])
 def test_init_embedding_single_solve_matches_oracle(refine):
     """Groups from K-means of an embedding's columns, refined by Lloyd on X (or not:
-    init_embedding_refine = 0), then the iterations: identical to the oracle's chain
-    from the same embedding."""
+    init_embedding_refine = 0), or K-means of X from seeds placed on the embedding
+    (2), then the iterations: identical to the oracle's chain from the same embedding."""
     for i, (X, E, Ed, c, lam) in enumerate(_embedding_cases()):
-        o, steps = _oracle_from_embedding(X, E, c, lam, seed=i + 3, refine=bool(refine), tol=1e-6)
+        o, steps = _oracle_from_embedding(X, E, c, lam, seed=i + 3, refine=refine, tol=1e-6)
         g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=o["info"]["iters"], seed=i + 3,
                      precision=rp.F32, init_embedding=Ed, embedding_refine=refine)
         say(f"embedding case {i} {X.shape} iters {g['info']['iters']} init_lloyd "
@@ -900,10 +912,11 @@ def test_init_embedding_single_solve_matches_oracle(refine):
         rp.solve(dev(X, np.float64), rank=c, precision=rp.F64, init_embedding=Ed)
 
 
-@pytest.mark.parametrize("refine", [1, 0])
+@pytest.mark.parametrize("refine", [1, 0, 2])
 def test_init_embedding_batched_matches_oracle(refine):
     """Embedding, label and cold instances side by side in one persistent launch
-    (embedding groups refined by Lloyd on X, or not)."""
+    (embedding groups refined by Lloyd on X, or not, or seeds placed on the
+    embedding for the K-means of X)."""
     cases = _embedding_cases()
     shapes, Xs = _batch_mix()
     X_lab, X_cold = Xs[1], Xs[2]
@@ -915,7 +928,7 @@ def test_init_embedding_batched_matches_oracle(refine):
     T = []
     for i, (X, r, lam, sd) in enumerate(zip(Xall, ranks, lams, seeds)):
         if i < len(cases):
-            o, steps = _oracle_from_embedding(X, cases[i][1], r, lam, sd, refine=bool(refine),
+            o, steps = _oracle_from_embedding(X, cases[i][1], r, lam, sd, refine=refine,
                                               tol=1e-6)
             o["emb_steps"] = steps
         elif i == len(cases):
