@@ -542,8 +542,20 @@ __global__ __launch_bounds__(kBlock) void k_argmin(const T* __restrict__ part, i
     int bestk = INT_MAX;
     if (live)
         for (int k = q; k < c; k += 16) {
+            // eight slices' loads issued together (indices clamped, the extra values
+            // not added), then added in slice order
             double dot = 0.0;
-            for (int rb = 0; rb < nrb; ++rb) dot += (double)part[((int64_t)rb * c + k) * n + j];
+            for (int rb0 = 0; rb0 < nrb; rb0 += 8) {
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int rb = rb0 + u < nrb ? rb0 + u : nrb - 1;
+                    v[u] = part[((int64_t)rb * c + k) * n + j];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (rb0 + u < nrb) dot += (double)v[u];
+            }
             const double dist = cnorm[k] - 2.0 * dot;
             if (dist < bestd) { bestd = dist; bestk = k; }
         }
