@@ -224,6 +224,46 @@ def test_soft_threshold_minimises_scalar_problem(orc):
                     assert S[i, j] == 0.0
 
 
+def test_compact_state_reproduces_the_oracle_iterations(orc):
+    """The whole solve keeps only B = X - L + Theta/rho between iterations: with the
+    l1 S-step, S = soft(B, 1/rho) and Theta = clip(rho B) (the identity above), so
+    D = X - S + Theta/rho_next and the L-step need nothing else.  This restates that
+    recurrence in FP64 (group means by plain NumPy, the oracle's own labels at each
+    step) and follows the oracle's iterations from S = Theta = 0 for 25 steps with a
+    growing penalty: L, S and Theta agree to rounding at every step."""
+    X, _, _, _ = synth.clustered(40, 60, 4, seed=21, sep=3.0, noise=0.5, frac=0.1, amp=20.0)
+    X = np.asfortranarray(X)
+    d, n = X.shape
+    c, lam = 4, 0.3
+    p = orc.make_params(c, lam=lam, rho0=1e-2, kappa=1.5)
+    lab0, C0, _ = orc.kmeans(X, c, 0, 100)
+    st = {"L": np.zeros((d, n), order="F"), "S": np.zeros((d, n), order="F"),
+          "Theta": np.zeros((d, n), order="F"), "labels": lab0, "C": C0, "rho": p.rho0}
+    B = np.zeros((d, n))
+    rho_prev = p.rho0
+    soft = lambda b, t: np.sign(b) * np.maximum(np.abs(b) - t, 0.0)
+    for _ in range(25):
+        rho = st["rho"]
+        labels = st["labels"]
+        S_prev, Th_prev = soft(B, 1.0 / rho_prev), np.clip(rho_prev * B, -1.0, 1.0)
+        D = X - S_prev + Th_prev / rho
+        mu = np.zeros((d, c))
+        for k in range(c):
+            if np.any(labels == k):
+                mu[:, k] = D[:, labels == k].mean(axis=1)
+            else:
+                mu[:, k] = st["C"][:, k]
+        alpha = rho / (2 * lam + rho)
+        L = alpha * D + (1 - alpha) * mu[:, labels]
+        B = X - L + Th_prev / rho
+        rho_prev = rho
+        st = orc.step(p, X, st)
+        scale = np.linalg.norm(X)
+        assert np.linalg.norm(L - st["L"]) <= 1e-12 * scale
+        assert np.linalg.norm(soft(B, 1.0 / rho) - st["S"]) <= 1e-12 * scale
+        assert np.abs(np.clip(rho * B, -1.0, 1.0) - st["Theta"]).max() <= 1e-9
+
+
 def test_theta_update_is_clipped_scaled_residual(orc):
     """From Sec. 4.3-4.4: Theta + rho (X - L - soft(B, 1/rho)) = clip(rho B, -1, 1);
     so |Theta| <= 1 and Theta = sign(S) on the support of S."""
