@@ -417,6 +417,39 @@ def test_padded_leading_dimension_and_determinism():
     assert rel(host(p["S"]), o["S"], nX) <= F32_TOL
 
 
+@pytest.mark.parametrize("dtype,precision", [(np.float64, rp.F64), (np.float32, rp.F32)])
+def test_stopped_solve_returns_the_last_sparse_part_in_padded_outputs(dtype, precision):
+    """A solve stopped by max_iter (not by the tolerance) returns the L and S of its
+    last iteration (the whole solve keeps B = X - L + Theta/rho in S and turns it into
+    soft(B, 1/rho) at the end); L and S in buffers with a padded leading dimension
+    (d + 3): the padding rows keep their contents."""
+    d, n, c = 203, 150, 4
+    X, _, _, _ = synth.clustered(d, n, c, seed=9, sep=4.0, noise=0.5, frac=0.05, amp=8.0, dtype=dtype)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    bufL = torch.full((n, d + 3), 7.25, dtype=tdt, device="cuda")
+    bufS = torch.full((n, d + 3), -3.5, dtype=tdt, device="cuda")
+    L, S = bufL.T[:d], bufS.T[:d]
+    assert L.stride() == (1, d + 3)
+    labels = torch.empty(n, dtype=torch.int32, device="cuda")
+    for T in (1, 4):
+        g = rp.solve(dev(X), rank=c, lam=0.6, tol=1e-12, max_iter=T, seed=5, precision=precision,
+                     out=(L, S, labels), history=True)
+        o = oracle.solve(X, oracle.make_params(c, lam=0.6, tol=1e-12, max_iter=T, seed=5),
+                         history=True)
+        assert g["status"] == rp.NOT_CONVERGED and g["info"]["iters"] == T
+        assert o["info"]["iters"] == T
+        # the per-iteration criterion terms (primal, dL, dS relative to ||X||)
+        assert g["history"].shape == o["history"].shape == (T, 3)
+        np.testing.assert_allclose(g["history"], o["history"],
+                                   rtol=1e-9 if dtype == np.float64 else 1e-4, atol=1e-12)
+        nX = np.linalg.norm(X.astype(np.float64))
+        tol = F64_TOL if dtype == np.float64 else F32_TOL
+        assert rel(host(L), o["L"], nX) <= tol
+        assert rel(host(S), o["S"], nX) <= tol
+        np.testing.assert_array_equal(labels.cpu().numpy(), o["labels"])
+        assert torch.all(bufL[:, d:] == 7.25) and torch.all(bufS[:, d:] == -3.5)
+
+
 # ------------------------------------------------------ bf16 distance mode
 
 @pytest.mark.parametrize("shape,lam", [((1037, 777, 5), None), ((2051, 300, 40), 0.3)])
