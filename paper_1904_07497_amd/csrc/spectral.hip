@@ -10,9 +10,11 @@
 //     the upper triangle, the Gaussian of q_i + q_j - 2 G_ij applied in the
 //     tile's epilogue and the tile written with its mirror, so the Gram matrix is
 //     never stored (the one dense GEMM of the method);
-//   - degrees (one wave per row, fixed order) and the symmetric scaling in place;
+//   - degrees (one wave per row, fixed order); A itself is never formed: a block
+//     product A Y is computed as s o (W (s o Y)) with s = D^{-1/2}, the two
+//     diagonal scalings folded into the product's load and reduction;
 //   - the top-c eigenvectors by Chebyshev-filtered subspace iteration with a
-//     block of k = min(n, c + 8) vectors: block products A Y on FP64 MFMA read A
+//     block of k = min(n, c + 8) vectors: block products A Y on FP64 MFMA read W
 //     once per product, Rayleigh-Ritz in one workgroup (Cholesky of Y^T Y,
 //     Jacobi on the k x k projected matrix), two Rayleigh-Ritz passes per filter
 //     so the block stays orthonormal to rounding; within a solve each p-step's
@@ -233,30 +235,22 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_degree(const double* __restrict
     if (lane == 0) s[i] = acc > 0.0 ? 1.0 / sqrt(acc) : 0.0;
 }
 
-// A = diag(s) W diag(s) in place.
-__global__ __launch_bounds__(kSpBlock) void k_sp_scale(double* __restrict__ W, int64_t n,
-                                                       const double* __restrict__ s) {
-    const int64_t total = n * n;
-    const int64_t stride = (int64_t)gridDim.x * kSpBlock;
-    for (int64_t e = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; e < total; e += stride) {
-        const int64_t i = e / n, j = e - i * n;
-        W[e] = s[i] * W[e] * s[j];
-    }
-}
-
 // Block product split over the summation index, P[split][i][q] = sum over j in
-// the split's range of A_ij Y[j][q] (A symmetric: A_ij is stored at A[j n + i]),
-// on FP64 MFMA (v_mfma_f64_16x16x4f64): a wave owns 16 rows i and multiplies A[i][j0..j0+3] (A operand, lane = row i % 16 and j
-// offset lane / 16: 128 contiguous bytes of A per j) by Y[j0..j0+3][16 columns]
-// (B operand, staged in LDS 64 rows at a time for the four waves of the
-// workgroup, columns past k zero), NQB blocks of 16 columns; sixteen j steps'
-// loads of A are issued before their MFMAs.
+// the split's range of A_ij s_j Y[j][q] (A is the affinity W, symmetric: A_ij is
+// stored at A[j n + i]; s_j is applied as Y is staged), on FP64 MFMA
+// (v_mfma_f64_16x16x4f64): a wave owns 16 rows i and multiplies A[i][j0..j0+3]
+// (A operand, lane = row i % 16 and j offset lane / 16: 128 contiguous bytes of A
+// per j) by s_j Y[j0..j0+3][16 columns] (B operand, staged in LDS 64 rows at a
+// time for the four waves of the workgroup, columns past k zero), NQB blocks of
+// 16 columns; sixteen j steps' loads of A are issued before the stage's Y is
+// staged and before their MFMAs.
 constexpr int kMvRows = 64;   // Y rows staged per LDS pass
 
 template <int NQB>
 __global__ __launch_bounds__(kSpBlock) void k_sp_mv_mfma(const double* __restrict__ A, int64_t n,
                                                          const double* __restrict__ Y, int k,
-                                                         int64_t jchunk, double* __restrict__ P) {
+                                                         int64_t jchunk, const double* __restrict__ sj,
+                                                         double* __restrict__ P) {
     __shared__ double Ys[kMvRows][16 * NQB];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
@@ -269,18 +263,19 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_mv_mfma(const double* __restric
     for (int x = 0; x < NQB; ++x) acc[x] = dbl4{0.0, 0.0, 0.0, 0.0};
     const int jo = lane >> 4;   // j offset within a step of four
     for (int64_t js = jb; js < je; js += kMvRows) {
-        for (int e = t; e < kMvRows * 16 * NQB; e += kSpBlock) {
-            const int jj = e / (16 * NQB), q = e - jj * (16 * NQB);
-            const int64_t j = js + jj;
-            Ys[jj][q] = (j < je && q < k) ? Y[j * k + q] : 0.0;
-        }
-        __syncthreads();
+        // the stage's loads of A go out before the staging of Y, so the two overlap
         double a[kMvRows / 4];
 #pragma unroll
         for (int st = 0; st < kMvRows / 4; ++st) {
             const int64_t j = js + 4 * st + jo;
             a[st] = (live && j < je) ? A[j * n + i] : 0.0;
         }
+        for (int e = t; e < kMvRows * 16 * NQB; e += kSpBlock) {
+            const int jj = e / (16 * NQB), q = e - jj * (16 * NQB);
+            const int64_t j = js + jj;
+            Ys[jj][q] = (j < je && q < k) ? sj[j] * Y[j * k + q] : 0.0;
+        }
+        __syncthreads();
 #pragma unroll
         for (int st = 0; st < kMvRows / 4; ++st)
 #pragma unroll
@@ -300,14 +295,16 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_mv_mfma(const double* __restric
         }
 }
 
-// Z[i][q] = sum over splits (in order) of P[split][i][q].
+// Z[i][q] = s_i times the sum over splits (in order) of P[split][i][q].
 __global__ __launch_bounds__(kSpBlock) void k_sp_mv_reduce(const double* __restrict__ P, int splits,
-                                                           int64_t nk, double* __restrict__ Z) {
+                                                           int64_t nk, int k,
+                                                           const double* __restrict__ si,
+                                                           double* __restrict__ Z) {
     const int64_t e = (int64_t)blockIdx.x * kSpBlock + threadIdx.x;
     if (e >= nk) return;
     double s = P[e];
     for (int sp = 1; sp < splits; ++sp) s += P[(int64_t)sp * nk + e];
-    Z[e] = s;
+    Z[e] = si[e / k] * s;
 }
 
 // Chebyshev step on rows: out = alpha (Z - c0 Y) - beta Yprev.
@@ -708,15 +705,16 @@ respca_status spectral_embed(respca_handle h, const T* Y, int64_t ldy, int64_t d
         k_sp_affinity<T><<<dim3(tb, tb), kSpBlock, 0, st>>>(Y, ldy, d, n, q, inv2s2, W);
     }
     k_sp_degree<<<cb, kSpBlock, 0, st>>>(W, n, s);
-    k_sp_scale<<<2048, kSpBlock, 0, st>>>(W, n, s);
+    // A = D^-1/2 W D^-1/2 is never formed: each block product scales the rows of Y
+    // by s on the way into LDS and the rows of the result by s at the end
 
     auto product = [&](const double* in, double* out) {
         ProfScope ps(h, st, RESPCA_KERNEL_EIGEN, 8.0 * (double)n * n, 2.0 * (double)n * n * k);
         const dim3 g((unsigned)rblocks, (unsigned)splits);
-        if (k <= 16) k_sp_mv_mfma<1><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
-        else if (k <= 32) k_sp_mv_mfma<2><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
-        else k_sp_mv_mfma<3><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, P);
-        k_sp_mv_reduce<<<blocks_for(nk), kSpBlock, 0, st>>>(P, (int)splits, nk, out);
+        if (k <= 16) k_sp_mv_mfma<1><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, s, P);
+        else if (k <= 32) k_sp_mv_mfma<2><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, s, P);
+        else k_sp_mv_mfma<3><<<g, kSpBlock, 0, st>>>(W, n, in, k, jchunk, s, P);
+        k_sp_mv_reduce<<<blocks_for(nk), kSpBlock, 0, st>>>(P, (int)splits, nk, k, s, out);
     };
     auto rayleigh_ritz = [&]() {   // on (Yb, Zb = A Yb): orthonormal Ritz vectors, theta
         for (int pass = 0; pass < 2; ++pass) {
