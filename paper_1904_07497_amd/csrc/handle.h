@@ -51,8 +51,12 @@ struct respca_handle_s {
     // incremental Lloyd means: group sums, next counts, the moved-column sort and its partials
     respca::DevBuf gsum, cnt2, cbc, cperm, csegb, csegl, csegf, cnseg, cpart;
     double* hstage = nullptr;  // pinned host staging (uniforms, small copies)
-    double* hstatus = nullptr;      // pinned host status words the kernels write directly
+    // Pinned host copy of the status words (words 0..7) and the sequence number of
+    // the last copy (word 8), written by the device after the words; the host
+    // polls word 8 instead of synchronizing the stream.
+    double* hstatus = nullptr;
     double* hstatus_dev = nullptr;  // the same memory as the device sees it
+    uint64_t status_seq = 0;        // last sequence number asked for
     size_t hstage_bytes = 0;
     // batched solver
     respca::BatchTune tune;

@@ -3,6 +3,7 @@
 // iterations L -> p -> S -> Theta/rho until the Sec. 5 criterion holds).
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <type_traits>
 #include <cstdio>
@@ -45,11 +46,34 @@ respca_status lookup_scratch(respca_handle h, int device) {
     return RESPCA_OK;
 }
 
-// Fold finished event pairs into the counters; call after a stream sync.
+// Host polling of a readback gives up after this long and synchronizes the stream
+// (which also reports a failed kernel).
+constexpr double kStatusSpinSeconds = 2e-3;
+
+// Publishes `count` status words to pinned host memory: the words first, then,
+// after a system-scope fence, the sequence number the host waits for.  Word 4
+// (columns refined by the last assignment pass) is cleared once published, so
+// each pass is counted once.  One thread; the stores are ordinary vector stores.
+__global__ void k_publish_status(double* __restrict__ words, int count,
+                                 volatile double* host_words, volatile uint64_t* host_seq,
+                                 uint64_t seq) {
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < count; ++i) host_words[i] = words[i];
+    if (count > 4) words[4] = 0.0;
+    __threadfence_system();
+    *host_seq = seq;
+    __threadfence_system();
+}
+
+// Fold finished event pairs into the counters; call once the work they bracket has
+// finished (a pair whose end event still reads as pending is waited for).
 void prof_resolve(respca_handle h) {
     for (auto& p : h->prof_pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        hipError_t e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e == hipErrorNotReady && hipEventSynchronize(p.b) == hipSuccess)
+            e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e == hipSuccess) {
             h->prof_launches[p.kernel] += 1;
             h->prof_ms[p.kernel] += ms;
             h->prof_bytes[p.kernel] += p.bytes;
@@ -144,7 +168,7 @@ struct Engine {
     int c;
     bool bf16;       // split-bf16 MFMA distances with exact refinement (float runs)
     int nrb;
-    double* status;  // pinned host words (device view): [0..2] norms^2, [3] changed count, [4] refined columns
+    double* status;  // device words: [0..2] norms^2, [3] changed count, [4] refined columns
     int64_t refined = 0;
     bool next_ready = false;   // pmeans / sort tables hold the next L-step's group sums of D
 
@@ -168,17 +192,19 @@ struct Engine {
         if (nsum > np) np = nsum;
         CKS(ensure(h, h->normp, 3 * np * sizeof(double)));
         CKS(ensure(h, h->chgp, (size_t)assign_partials_max(n) * sizeof(double)));
-        if (h->arena_on) {   // status words in the scratch area, copied back by readback()
-            CKS(ensure(h, h->status, 8 * sizeof(double)));
-            status = (double*)h->status.p;
-            return RESPCA_OK;
-        }
+        // status words in device memory (in the scratch area while arena_on);
+        // readback() brings them to the host
+        CKS(ensure(h, h->status, 8 * sizeof(double)));
+        status = (double*)h->status.p;
+        if (h->arena_on) return RESPCA_OK;
+        CK(hipMemsetAsync(status, 0, 8 * sizeof(double), st));
         CKS(ensure_host(h, (16 + 2 * (size_t)c) * sizeof(double)));
-        if (!h->hstatus) {   // status words in pinned host memory: no copy before each readback
-            CK(hipHostMalloc((void**)&h->hstatus, 8 * sizeof(double), hipHostMallocMapped));
+        if (!h->hstatus) {   // pinned host copy: words 0..7, sequence number in word 8
+            CK(hipHostMalloc((void**)&h->hstatus, 16 * sizeof(double), hipHostMallocMapped));
             CK(hipHostGetDevicePointer((void**)&h->hstatus_dev, h->hstatus, 0));
+            std::memset(h->hstatus, 0, 16 * sizeof(double));
+            h->status_seq = 0;
         }
-        status = h->hstatus_dev;
         return RESPCA_OK;
     }
 
@@ -206,7 +232,25 @@ struct Engine {
             refined += (int64_t)w[4];
             return RESPCA_OK;
         }
-        CK(hipStreamSynchronize(st));   // the kernels wrote the words themselves
+        // The words reach the host behind a sequence number; polling it costs a few
+        // microseconds where a stream synchronization costs ~20 (a pass is a chain
+        // of short kernels, so this is paid every Lloyd pass and every iteration).
+        const uint64_t seq = ++h->status_seq;
+        volatile uint64_t* hseq = (volatile uint64_t*)(h->hstatus + 8);
+        k_publish_status<<<1, 64, 0, st>>>(status, 5, h->hstatus_dev,
+                                           (uint64_t*)(h->hstatus_dev + 8), seq);
+        CK(hipGetLastError());
+        {
+            const auto t0 = std::chrono::steady_clock::now();
+            while (*hseq != seq &&
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() <
+                       kStatusSpinSeconds) {
+            }
+        }
+        if (*hseq != seq) {
+            CK(hipStreamSynchronize(st));
+            if (*hseq != seq) return fail(h, RESPCA_ERR_HIP, "status words did not reach the host");
+        }
         const volatile double* w = h->hstatus;
         for (int i = 0; i < 4; ++i) out[i] = w[i];
         refined += (int64_t)w[4];
