@@ -551,7 +551,7 @@ SINGLE_KERNEL_UNITS = ("sweep", "colnorm")
 UNIT_KERNELS = {
     "sweep": ("k_sweep_seg",),
     "means": ("k_group_partial",),
-    "distance": ("k_split_centroids", "k_dist_", "k_refine_", "k_assign_finish", "k_argmin",
+    "distance": ("k_split_centroids", "k_dist_", "k_refine", "k_assign_finish", "k_argmin",
                  "k_col_sqnorm"),
     "colnorm": ("k_l21_factor",),
     "batched": ("k_batched",),

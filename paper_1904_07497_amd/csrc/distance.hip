@@ -406,122 +406,105 @@ __global__ __launch_bounds__(256) void k_dist_argmin_bounded_r(
     if (threadIdx.x == 0) changed_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// Exact squared distances (double differences of the FP32 values) for the
-// refinement list.  Workgroup (slot, t) takes list items slot, slot + gridDim.x,
-// ... and their t-th candidate; 256 threads x 4 independent loads per step.
+// The refinement list, one item per workgroup of kRefineThreads at a time: the
+// exact squared distances (double differences of the FP32 values) of the column
+// to its candidates -- or, when it had more than kMaxCand, to every group, eight
+// at a time -- each thread taking rows tid, tid + kRefineThreads, ... (four rows
+// per step, all candidates' loads issued together), reduced over waves in wave
+// order; the smallest distance (lowest group on ties) gives the label.
 constexpr int kRefineSlots = 256;
+constexpr int kRefineThreads = 1024;
+constexpr int kRefineRows = 4;   // rows per thread and step, all loads issued together
 
-__global__ __launch_bounds__(256) void k_refine_dist(const float* __restrict__ C, int64_t d, int c,
-                                                     const float* __restrict__ Y, int64_t ldy,
-                                                     const int* __restrict__ counters,
-                                                     const int32_t* __restrict__ list,
-                                                     const int32_t* __restrict__ cand,
-                                                     double* __restrict__ refdist) {
-    __shared__ double sh[4];
-    const int count = counters[0];
-    const int t = blockIdx.y;
+__global__ __launch_bounds__(kRefineThreads) void k_refine(const float* __restrict__ C, int64_t d,
+                                                           int c, const float* __restrict__ Y,
+                                                           int64_t ldy,
+                                                           const int* __restrict__ counters,
+                                                           const int32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ cand,
+                                                           const int32_t* __restrict__ old_labels,
+                                                           int32_t* __restrict__ new_labels,
+                                                           int* __restrict__ changed_count) {
+    constexpr int NW = kRefineThreads / 64;
+    __shared__ double sh[NW][kMaxCand];
     static_assert(kMaxCand == 8, "candidate rows are read as two int4");
+    const int count = counters[0];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int item = blockIdx.x; item < count; item += gridDim.x) {
         const int64_t j = list[item];
-        // entries after the end marker (-2) are stale; -1 (every group) is handled per wave
         const int4* row = reinterpret_cast<const int4*>(cand + j * kMaxCand);
         const int4 c0 = row[0], c1 = row[1];
         const int cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-        bool valid = true;
+        const bool every = cv[0] == -1;
+        int ncand = 0;   // candidates up to the first end marker
+        if (!every) {
+            bool live = true;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) valid = valid && (u > t || cv[u] >= 0);
-        int k = -1;   // uniform across the workgroup
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (u == t && valid) k = cv[u];
-        if (k < 0 || k >= c) continue;
+            for (int u = 0; u < 8; ++u) {
+                live = live && cv[u] >= 0 && cv[u] < c;
+                ncand += live ? 1 : 0;
+            }
+        }
         const float* y = Y + j * ldy;
-        const float* ck = C + (int64_t)k * d;
-        double acc = 0.0;
-        for (int64_t i = threadIdx.x; i < d; i += 1024) {
-            float a[4], b[4];   // loads clamped into the column, tails zeroed after
+        double best = INFINITY;
+        int bestk = INT_MAX;
+        for (int k0 = 0; k0 < (every ? c : ncand); k0 += 8) {
+            int ks[8];
+            const int nk = every ? min(8, c - k0) : ncand;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t ii = i + 256 * u < d ? i + 256 * u : d - 1;
-                a[u] = y[ii];
-                b[u] = ck[ii];
+            for (int u = 0; u < 8; ++u) ks[u] = every ? min(k0 + u, c - 1) : cv[u < ncand ? u : 0];
+            double acc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+            for (int64_t i = threadIdx.x; i < d; i += kRefineRows * kRefineThreads) {
+                // rows i + r kRefineThreads; those past the column's end are clamped
+                // into it and contribute zero
+                float yv[kRefineRows], cv2[kRefineRows][8];
+#pragma unroll
+                for (int r = 0; r < kRefineRows; ++r) {
+                    const int64_t ii = i + r * kRefineThreads < d ? i + r * kRefineThreads : i;
+                    yv[r] = y[ii];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) cv2[r][u] = C[(int64_t)ks[u] * d + ii];
+                }
+#pragma unroll
+                for (int r = 0; r < kRefineRows; ++r) {
+                    const bool in = i + r * kRefineThreads < d;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const double e = in ? (double)yv[r] - (double)cv2[r][u] : 0.0;
+                        acc[u] += e * e;
+                    }
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double e = i + 256 * u < d ? (double)a[u] - (double)b[u] : 0.0;
-                acc += e * e;
-            }
-        }
-        acc = wave_sum_d(acc);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) refdist[(int64_t)item * kMaxCand + t] = sh[0] + sh[1] + sh[2] + sh[3];
-    }
-}
-
-// One list item, one wave.
-__device__ inline void refine_pick_item(const float* __restrict__ C, int64_t d, int c,
-                                        const float* __restrict__ Y, int64_t ldy,
-                                        const int32_t* __restrict__ list,
-                                        const int32_t* __restrict__ cand,
-                                        const double* __restrict__ refdist,
-                                        const int32_t* __restrict__ old_labels,
-                                        int32_t* __restrict__ new_labels,
-                                        int* __restrict__ changed_count, int item, int lane) {
-    const int64_t j = list[item];
-    const int32_t* cj = cand + j * kMaxCand;
-    double best = INFINITY;
-    int bestk = INT_MAX;
-    if (cj[0] == -1) {
-        const float* y = Y + j * ldy;
-        for (int k = 0; k < c; ++k) {
-            const float* ck = C + (int64_t)k * d;
-            double acc = 0.0;
-            for (int64_t i = lane; i < d; i += 64) {
-                const double e = (double)y[i] - (double)ck[i];
-                acc += e * e;
-            }
-            acc = wave_sum_d(acc);
-            if (acc < best) { best = acc; bestk = k; }
-        }
-    } else {
-        const int4 c0 = reinterpret_cast<const int4*>(cj)[0], c1 = reinterpret_cast<const int4*>(cj)[1];
-        const int cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-        double dv[8];
+            for (int u = 0; u < 8; ++u) acc[u] = wave_sum_d(acc[u]);
+            __syncthreads();   // the previous round's reads of sh are done
+            if (lane == 0) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) dv[t] = refdist[(int64_t)item * kMaxCand + t];
-        bool live = true;   // candidates up to the first end marker
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            live = live && cv[t] >= 0;
-            if (live && (dv[t] < best || (dv[t] == best && cv[t] < bestk))) { best = dv[t]; bestk = cv[t]; }
+                for (int u = 0; u < 8; ++u) sh[wave][u] = acc[u];
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int u = 0; u < nk; ++u) {
+                    double s = 0.0;
+                    for (int w = 0; w < NW; ++w) s += sh[w][u];
+                    const int k = every ? k0 + u : cv[u];
+                    if (s < best || (s == best && k < bestk)) {
+                        best = s;
+                        bestk = k;
+                    }
+                }
+            }
+            if (!every) break;
         }
+        if (threadIdx.x == 0) {
+            const int lab = bestk == INT_MAX ? 0 : bestk;
+            new_labels[j] = lab;
+            if (old_labels[j] != lab) atomicAdd(changed_count, 1);
+        }
+        __syncthreads();   // sh is reused by the next item
     }
-    if (lane == 0) {
-        const int lab = bestk == INT_MAX ? 0 : bestk;
-        new_labels[j] = lab;
-        if (old_labels[j] != lab) atomicAdd(changed_count, 1);
-    }
-}
-
-// Per list item: smallest exact distance among its candidates (lowest group on
-// ties).  Items with more than kMaxCand candidates are scored against every
-// group by one wave here (rare).
-__global__ __launch_bounds__(256) void k_refine_pick(const float* __restrict__ C, int64_t d, int c,
-                                                     const float* __restrict__ Y, int64_t ldy,
-                                                     const int* __restrict__ counters,
-                                                     const int32_t* __restrict__ list,
-                                                     const int32_t* __restrict__ cand,
-                                                     const double* __restrict__ refdist,
-                                                     const int32_t* __restrict__ old_labels,
-                                                     int32_t* __restrict__ new_labels,
-                                                     int* __restrict__ changed_count) {
-    const int lane = threadIdx.x & 63;
-    const int count = counters[0];
-    for (int item = blockIdx.x * 4 + (threadIdx.x >> 6); item < count; item += gridDim.x * 4)
-        refine_pick_item(C, d, c, Y, ldy, list, cand, refdist, old_labels, new_labels, changed_count,
-                         item, lane);
 }
 
 // ---- bounded mode with at most 16 groups: FP64 dot products on the vector units
@@ -866,8 +849,8 @@ bool use_direct(int64_t d, int c, const float* Y, int64_t ldy, bool bf16) {
 }  // namespace
 
 // Workspace layout (float runs): counters (int x 4, padded to 256 bytes) |
-// refinement list [n] | (16-aligned) candidates [n][kMaxCand] | (8-aligned) exact
-// distances [n][kMaxCand] (double) | (256-aligned) split centroids [kpad][ldq] x 16
+// refinement list [n] | (16-aligned) candidates [n][kMaxCand] | (256-aligned)
+// split centroids [kpad][ldq] x 16
 // bytes, ldq = ceil(d / 32) * 8 | (256-aligned) partial dots [slices][n][kpad] |
 // column norm partials [slices][n], sized for the larger slice count of the two
 // tile plans.
@@ -877,7 +860,6 @@ struct WorkLayout {
     int* counters;
     int32_t* list;
     int32_t* cand;
-    double* refdist;
     uint4* csp;
     float* part;
     float* ynorm;
@@ -891,8 +873,7 @@ WorkLayout work_layout(void* work, int64_t d, int64_t n, int c, int slices) {
     w.counters = (int*)base;
     w.list = (int32_t*)(base + 256);
     w.cand = (int32_t*)align_up((uintptr_t)(w.list + n), 16);
-    w.refdist = (double*)align_up((uintptr_t)(w.cand + n * kMaxCand), 8);
-    w.csp = (uint4*)align_up((uintptr_t)(w.refdist + n * kMaxCand), 256);
+    w.csp = (uint4*)align_up((uintptr_t)(w.cand + n * kMaxCand), 256);
     const int kpad = (c + 15) / 16 * 16;
     w.part = (float*)align_up((uintptr_t)(w.csp + (int64_t)kpad * split_ldq(d)), 256);
     w.ynorm = w.part + (size_t)slices * n * kpad;
@@ -955,7 +936,6 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
     int* counters = w.counters;                       // [0] list length, [1] refined changes
     int32_t* list = w.list;
     int32_t* cand = w.cand;
-    double* refdist = w.refdist;
     uint4* csp = w.csp;
     float* part = w.part;
     float* ynorm = w.ynorm;
@@ -1029,11 +1009,8 @@ int launch_assign<float>(const float* C, int64_t d, int c, const float* Y, int64
                                                   old_labels, new_labels, changed_partial, counters,
                                                   list, cand);
 #undef RESPCA_ARGMIN_R
-    k_refine_dist<<<dim3(kRefineSlots, kMaxCand), 256, 0, st>>>(C, d, c, Y, ldy, counters, list,
-                                                                  cand, refdist);
-    k_refine_pick<<<kRefineSlots / 4, 256, 0, st>>>(C, d, c, Y, ldy, counters, list, cand,
-                                                           refdist, old_labels, new_labels,
-                                                           counters + 1);
+    k_refine<<<kRefineSlots, kRefineThreads, 0, st>>>(C, d, c, Y, ldy, counters, list, cand,
+                                                      old_labels, new_labels, counters + 1);
     // refined changes are added to the partial list by the caller via changed_extra
     if (changed_extra) *changed_extra = 1;
     return gb;

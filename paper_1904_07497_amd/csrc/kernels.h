@@ -63,9 +63,12 @@ void launch_changed_sort(const int32_t* new_labels, const int32_t* old_labels, i
                          int32_t* bc, const int32_t* counts_old, int32_t* counts_new, int32_t* perm,
                          int32_t* seg_begin, int32_t* seg_len, int32_t* seg_first, int32_t* nseg,
                          int max_seg, hipStream_t st);
+// The update also copies counts_new to counts_out (the group counts the next
+// pass starts from).
 template <typename T>
 void launch_group_update(const double* partial, int64_t d, int c, const int32_t* counts_new,
-                         const int32_t* seg_first, double* gsum, T* C, hipStream_t st);
+                         const int32_t* seg_first, double* gsum, T* C, int32_t* counts_out,
+                         hipStream_t st);
 
 // out[k] = ||C[:, k]||^2 in double.
 template <typename T>
@@ -157,10 +160,22 @@ int launch_assign(const T* C, int64_t d, int c, const T* Y, int64_t ldy, int64_t
                   double* changed_partial, bool bf16, int* changed_extra, hipStream_t st);
 int* assign_refine_counters(void* work, int64_t d, int64_t n, int c);
 // out[0] += counter (or out[0] = counter when set), one thread.
+// Status words a finishing kernel can also hand to the host: the five device
+// words `words` (norms, changed count, refined count) are copied to the pinned
+// host words `host`, then, after a system-scope fence, `seq` goes to `host_seq`.
+// seq == 0: nothing is published.
+struct StatusPublish {
+    const double* words = nullptr;
+    double* host = nullptr;
+    uint64_t* host_seq = nullptr;
+    uint64_t seq = 0;
+};
 // out[0] = sum of `count` changed-count partials plus counters[1]; out[1] =
-// counters[0] (counters may be null: refinement counts then read as zero).
+// counters[0] (counters may be null: refinement counts then read as zero).  With
+// pub.seq set (pub.words + 3 == out), the words are published with out[0..1] as
+// computed here, and out[1] is left at zero so the refined count is taken once.
 void launch_assign_finish(const double* partial, int count, const int* counters, double* out,
-                          hipStream_t st);
+                          hipStream_t st, const StatusPublish& pub = StatusPublish());
 void launch_add_int(const int* counter, double* out, hipStream_t st, bool set = false);
 inline int64_t assign_partials_max(int64_t n) { return (n + 15) / 16; }
 

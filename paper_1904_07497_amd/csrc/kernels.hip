@@ -353,8 +353,10 @@ __global__ __launch_bounds__(kBlock) void k_group_update(const double* __restric
                                                          int64_t d, int c,
                                                          const int32_t* __restrict__ counts_new,
                                                          const int32_t* __restrict__ seg_first,
-                                                         double* __restrict__ gsum, T* C) {
+                                                         double* __restrict__ gsum, T* C,
+                                                         int32_t* __restrict__ counts_out) {
     const int k = blockIdx.y;
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts_out[k] = counts_new[k];
     const int e0 = seg_first[k], e1 = seg_first[k + 1];
     const int l0 = seg_first[c + k], l1 = seg_first[c + k + 1];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -738,7 +740,10 @@ __device__ inline int block_min_i(int v, int* sh) {
 
 // Inverse-CDF draw of the next seed: thread t sums a contiguous chunk, a block
 // scan gives each chunk its starting running sum, and the first index whose
-// running sum exceeds u*total wins.
+// running sum exceeds u*total wins.  Chunks of at most kPickReg entries are
+// loaded once, all loads issued together, and kept in registers for the search.
+constexpr int kPickReg = 16;
+
 __global__ __launch_bounds__(kPickThreads) void k_pick(const double* __restrict__ d2, int64_t n,
                                                        const double* __restrict__ u, int m,
                                                        int32_t* seeds, int32_t* chosen) {
@@ -747,8 +752,18 @@ __global__ __launch_bounds__(kPickThreads) void k_pick(const double* __restrict_
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t chunk = (n + kPickThreads - 1) / kPickThreads;
     const int64_t lo = tid * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const bool inreg = chunk <= kPickReg;   // uniform
+    double v[kPickReg];
     double loc = 0.0;
-    for (int64_t j = lo; j < hi; ++j) loc += d2[j];
+    if (inreg) {
+#pragma unroll
+        for (int e = 0; e < kPickReg; ++e) v[e] = lo + e < hi ? d2[lo + e] : 0.0;
+#pragma unroll
+        for (int e = 0; e < kPickReg; ++e)
+            if (lo + e < hi) loc += v[e];
+    } else {
+        for (int64_t j = lo; j < hi; ++j) loc += d2[j];
+    }
     double x = loc;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -768,9 +783,18 @@ __global__ __launch_bounds__(kPickThreads) void k_pick(const double* __restrict_
         const double target = u[m] * total;
         int cand = INT_MAX;
         double run = pre;
-        for (int64_t j = lo; j < hi; ++j) {
-            run += d2[j];
-            if (run > target) { cand = (int)j; break; }
+        if (inreg) {
+#pragma unroll
+            for (int e = 0; e < kPickReg; ++e)
+                if (lo + e < hi && cand == INT_MAX) {
+                    run += v[e];
+                    if (run > target) cand = (int)(lo + e);
+                }
+        } else {
+            for (int64_t j = lo; j < hi; ++j) {
+                run += d2[j];
+                if (run > target) { cand = (int)j; break; }
+            }
         }
         s = block_min_i(cand, ish);
         if (s == INT_MAX) {
@@ -830,19 +854,33 @@ int launch_sumsq(const T* X, int64_t ldx, int64_t d, int64_t n, double* partial,
 // End of an assignment pass: out[0] = changed labels (partials + refined), out[1]
 // = refined columns (0 without a refinement list).
 __global__ __launch_bounds__(kBlock) void k_assign_finish(const double* partial, int count,
-                                                          const int* counters, double* out) {
+                                                          const int* counters, double* out,
+                                                          StatusPublish pub) {
     double a = 0.0, b = 0.0, c = 0.0;
     for (int r = threadIdx.x; r < count; r += kBlock) a += partial[r];
     block_sum3(a, b, c);
     if (threadIdx.x == 0) {
-        out[0] = a + (counters ? (double)counters[1] : 0.0);
-        out[1] = counters ? (double)counters[0] : 0.0;
+        const double changed = a + (counters ? (double)counters[1] : 0.0);
+        const double refined = counters ? (double)counters[0] : 0.0;
+        out[0] = changed;
+        if (pub.seq == 0) {
+            out[1] = refined;
+            return;
+        }
+        out[1] = 0.0;
+        volatile double* host = pub.host;
+        for (int i = 0; i < 3; ++i) host[i] = pub.words[i];
+        host[3] = changed;
+        host[4] = refined;
+        __threadfence_system();
+        *(volatile uint64_t*)pub.host_seq = pub.seq;
+        __threadfence_system();
     }
 }
 
 void launch_assign_finish(const double* partial, int count, const int* counters, double* out,
-                          hipStream_t st) {
-    k_assign_finish<<<1, kBlock, 0, st>>>(partial, count, counters, out);
+                          hipStream_t st, const StatusPublish& pub) {
+    k_assign_finish<<<1, kBlock, 0, st>>>(partial, count, counters, out, pub);
 }
 
 __global__ void k_add_int(const int* counter, double* out, int set) {
@@ -929,9 +967,10 @@ void launch_changed_sort(const int32_t* new_labels, const int32_t* old_labels, i
 
 template <typename T>
 void launch_group_update(const double* partial, int64_t d, int c, const int32_t* counts_new,
-                         const int32_t* seg_first, double* gsum, T* C, hipStream_t st) {
+                         const int32_t* seg_first, double* gsum, T* C, int32_t* counts_out,
+                         hipStream_t st) {
     k_group_update<T><<<dim3((unsigned)((d + kBlock - 1) / kBlock), c), kBlock, 0, st>>>(
-        partial, d, c, counts_new, seg_first, gsum, C);
+        partial, d, c, counts_new, seg_first, gsum, C, counts_out);
 }
 
 template <typename T>
@@ -1153,7 +1192,7 @@ void launch_gather_cols(const T* Y, int64_t ldy, int64_t d, const int32_t* idx, 
     template void launch_group_finalize<T>(const double*, int64_t, int, const int32_t*,            \
                                            const int32_t*, T*, hipStream_t, double*);              \
     template void launch_group_update<T>(const double*, int64_t, int, const int32_t*,              \
-                                         const int32_t*, double*, T*, hipStream_t);                \
+                                         const int32_t*, double*, T*, int32_t*, hipStream_t);      \
     template void launch_col_sqnorm<T>(const T*, int64_t, int, double*, hipStream_t);              \
     template int launch_sweep_seg<T>(const T*, int64_t, T*, int64_t, T*, int64_t, T*, int64_t,    \
                                      const T*, const int32_t*, const int32_t*, const int32_t*,     \

@@ -170,6 +170,7 @@ struct Engine {
     int nrb;
     double* status;  // device words: [0..2] norms^2, [3] changed count, [4] refined columns
     int64_t refined = 0;
+    uint64_t published_seq = 0;   // sequence number of words already being published
     bool next_ready = false;   // pmeans / sort tables hold the next L-step's group sums of D
 
     respca_status setup() {
@@ -235,11 +236,15 @@ struct Engine {
         // The words reach the host behind a sequence number; polling it costs a few
         // microseconds where a stream synchronization costs ~20 (a pass is a chain
         // of short kernels, so this is paid every Lloyd pass and every iteration).
-        const uint64_t seq = ++h->status_seq;
+        uint64_t seq = published_seq;   // set when the last kernel published the words
+        published_seq = 0;
+        if (seq == 0) {
+            seq = ++h->status_seq;
+            k_publish_status<<<1, 64, 0, st>>>(status, 5, h->hstatus_dev,
+                                               (uint64_t*)(h->hstatus_dev + 8), seq);
+            CK(hipGetLastError());
+        }
         volatile uint64_t* hseq = (volatile uint64_t*)(h->hstatus + 8);
-        k_publish_status<<<1, 64, 0, st>>>(status, 5, h->hstatus_dev,
-                                           (uint64_t*)(h->hstatus_dev + 8), seq);
-        CK(hipGetLastError());
         {
             const auto t0 = std::chrono::steady_clock::now();
             while (*hseq != seq &&
@@ -331,8 +336,7 @@ struct Engine {
                                     (double*)h->cpart.p, st, changed_max_segments(moved, c));
         }
         launch_group_update<T>((const double*)h->cpart.p, d, c, cnt2, (const int32_t*)h->csegf.p,
-                               (double*)h->gsum.p, C, st);
-        CK(hipMemcpyAsync(counts(), cnt2, c * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+                               (double*)h->gsum.p, C, counts(), st);
         return RESPCA_OK;
     }
 
@@ -346,9 +350,18 @@ struct Engine {
             g = launch_assign<T>(C, d, c, Y, ldy, n, (double*)h->cnorm.p, old, neu, h->dots.p,
                                  (double*)h->chgp.p, bf16, &extra, st);
         }
+        // the finishing kernel also publishes the words for the readback that follows
+        StatusPublish pub;
+        if (!h->arena_on) {
+            pub.words = status;
+            pub.host = h->hstatus_dev;
+            pub.host_seq = (uint64_t*)(h->hstatus_dev + 8);
+            pub.seq = ++h->status_seq;
+            published_seq = pub.seq;
+        }
         launch_assign_finish((const double*)h->chgp.p, g,
                              extra ? assign_refine_counters(h->dots.p, d, n, c) : nullptr, status + 3,
-                             st);
+                             st, pub);
     }
 
     // Lloyd passes on the columns of Y from (cur, C); see oracle_lloyd for the
