@@ -36,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+STREAM_NT_BYTES = 64 * 1024 * 1024   # arrays the library streams nontemporally (per array)
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # dense, per MI355X
 
 WORKLOADS = {
@@ -537,9 +538,11 @@ def calibrate_mix(args):
              (4, 3, "sweep (X, S, Theta, L in; L, S, Theta out)")]
     out = []
     for r, w, what in mixes:
-        gbps, ms = rp.bandwidth_probe(r, w, 1 << 30, reps=max(args.steps, 5))
-        out.append({"reads": r, "writes": w, "what": what, "GBps": round(gbps, 1),
-                    "frac_of_8TBps": round(gbps / HBM_PEAK_GBS, 4), "ms_per_launch": round(ms, 4)})
+        for nt in (False, True):
+            gbps, ms = rp.bandwidth_probe(r, w, 1 << 30, reps=max(args.steps, 5), nontemporal=nt)
+            out.append({"reads": r, "writes": w, "nontemporal": nt, "what": what,
+                        "GBps": round(gbps, 1), "frac_of_8TBps": round(gbps / HBM_PEAK_GBS, 4),
+                        "ms_per_launch": round(ms, 4)})
     print(json.dumps({"bandwidth_probe": out, "bytes_per_array": 1 << 30,
                       "reps": max(args.steps, 5)}), flush=True)
 
@@ -842,12 +845,15 @@ def main():
 
     def sweep_with_ceiling(r, rp, array_bytes):
         """The sweep's figure beside the measured ceiling of its read/write mix (the
-        library's streaming probe over arrays of the sweep's size): 3 reads + 2
+        library's streaming probe over arrays of the sweep's size, in the sweep's
+        own load/store form: nontemporal from 64 MiB per array): 3 reads + 2
         writes for the l1 sweep on the compact state, 4 + 3 for the l2,1 sweep."""
         reads, writes = (4, 3) if wl.get("sparse_norm", 0) == 1 else (3, 2)
-        gbps, _ = rp.bandwidth_probe(reads, writes, (array_bytes // 16) * 16, reps=10)
+        nt = array_bytes >= STREAM_NT_BYTES
+        gbps, _ = rp.bandwidth_probe(reads, writes, (array_bytes // 16) * 16, reps=10, nontemporal=nt)
         r = dict(r)
         r[f"ceiling_{reads}r{writes}w_GBps"] = round(gbps, 1)
+        r["ceiling_nontemporal"] = nt
         r["frac_of_ceiling"] = round(r["achieved"] / gbps, 4) if gbps > 0 else None
         return r
 

@@ -354,15 +354,17 @@ respca_status respca_profile_query(respca_handle h, int32_t kernel, int64_t *lau
  * Streaming bandwidth probe (measurement support, not part of the method): a
  * kernel that reads `reads` arrays (1..4) and writes `writes` arrays (0..3) of
  * bytes_per_array bytes each (a positive multiple of 16), float4 loads and
- * stores, launched reps times on `stream` between two events after one warm-up
- * launch.  *gbps (host) receives (reads + writes) * bytes_per_array / time per
- * launch, *ms_per_launch the mean launch time (either may be NULL).  The arrays
- * live in the handle's workspace (allocated on demand).  The sweep's mix is 4
- * reads and 3 writes, the means pass's 3 reads, a copy's 1 and 1.
+ * stores (nontemporal ones when `nontemporal` is nonzero, the form the sweep and
+ * the means passes use on arrays of 64 MiB and more), launched reps times on
+ * `stream` between two events after one warm-up launch.  *gbps (host) receives
+ * (reads + writes) * bytes_per_array / time per launch, *ms_per_launch the mean
+ * launch time (either may be NULL).  The arrays live in the handle's workspace
+ * (allocated on demand).  The l1 sweep's mix on the compact state is 3 reads and
+ * 2 writes, the l2,1 sweep's 4 and 3, a copy's 1 and 1.
  */
 respca_status respca_bandwidth_probe(respca_handle h, int32_t reads, int32_t writes,
-                                     int64_t bytes_per_array, int32_t reps, double *gbps,
-                                     double *ms_per_launch, void *stream);
+                                     int32_t nontemporal, int64_t bytes_per_array, int32_t reps,
+                                     double *gbps, double *ms_per_launch, void *stream);
 
 /*
  * Learned warm start (an addition to the paper's method; all FP32, device

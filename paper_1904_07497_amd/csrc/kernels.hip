@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kSortChunk) void k_sort_scatter(const int32_t* __re
 
 // Grid (segment slots, row slices); slots past the real segment count exit.
 // COMPACT: S holds the compact state B (penalty rho_prev); Th is not read.
-template <typename T, int V, bool WITH_D, bool COMPACT = false>
+template <typename T, int V, bool WITH_D, bool COMPACT = false, bool NT = false>
 __global__ __launch_bounds__(kBlock) void k_group_partial(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ S, int64_t lds,
     const T* __restrict__ Th, int64_t ldt, T inv_rho, int64_t d, const int32_t* __restrict__ perm,
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_group_partial(
     T inv_rho_prev = T(0)) {
     const int s = (int)(blockIdx.x / nrb);   // row blocks vary fastest
     if (s >= *nseg) return;
-    group_partial_tile<T, V, WITH_D, kRowsPerBlock, 1, COMPACT>(
+    group_partial_tile<T, V, WITH_D, kRowsPerBlock, 1, COMPACT, NT>(
         A, lda, S, lds, Th, ldt, inv_rho, d, perm, seg_begin[s], seg_len[s],
         (int64_t)(blockIdx.x % nrb) * kRowsPerBlock, partial + (int64_t)s * d, rho_prev, inv_rho_prev);
 }
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_col_sqnorm(const T* C, int64_t d, do
 // the segment count write zero norms.  L21: column-wise S-step from fac.
 // COMPACT: the l1 sweep on the compact state B (kept in S, previous penalty
 // rho_prev; Th is not used), see seg_sweep_tile.
-template <typename T, int V, bool L21, bool COMPACT = false, int UU = 4>
+template <typename T, int V, bool L21, bool COMPACT = false, int UU = 4, bool NT = false>
 __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     const T* __restrict__ X, int64_t ldx, T* __restrict__ L, int64_t ldl, T* __restrict__ S,
     int64_t lds, T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_seg(
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (sg < *nseg) {
         const int begin = seg_begin[sg];
-        seg_sweep_tile<T, V, kRowsPerBlock, 1, UU, L21, COMPACT>(
+        seg_sweep_tile<T, V, kRowsPerBlock, 1, UU, L21, COMPACT, NT>(
             X, ldx, L, ldl, S, lds, Th, ldt, C, labels[perm[begin]], d, perm, begin, seg_len[sg], r0,
             alpha, beta, rho, inv_rho, inv_rho_next, a0, a1, a2, next_partial + (int64_t)sg * d, fac,
             rho_prev, inv_rho_prev);
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_seg(
 // double over the column (fixed order: thread stride, then the block sum), with
 // B_j formed in T exactly as the sweep forms it, and stores the block soft
 // threshold factor max(0, 1 - 1/(rho ||B_j||)).
-template <typename T, int V>
+template <typename T, int V, bool NT = false>
 __global__ __launch_bounds__(kBlock) void k_l21_factor(
     const T* __restrict__ X, int64_t ldx, const T* __restrict__ S, int64_t lds,
     const T* __restrict__ Th, int64_t ldt, const T* __restrict__ C,
@@ -445,9 +445,9 @@ __global__ __launch_bounds__(kBlock) void k_l21_factor(
         double a = 0.0, b0 = 0.0, c0 = 0.0;
         for (int64_t i = (int64_t)threadIdx.x * V; i < d; i += (int64_t)kBlock * V) {
             T xs[V], ss[V], ts[V], ms[V];
-            vload<T, V>(x + i, xs);
-            vload<T, V>(s + i, ss);
-            vload<T, V>(t + i, ts);
+            sload<NT, T, V>(x + i, xs);
+            sload<NT, T, V>(s + i, ss);
+            sload<NT, T, V>(t + i, ts);
             vload<T, V>(m + i, ms);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -907,6 +907,16 @@ void launch_label_sort(const int32_t* labels, int64_t n, int c, int32_t* bc, int
     k_sort_scatter<<<nb, kSortChunk, 0, st>>>(labels, (int)n, c, bc, perm);
 }
 
+// Whole passes over d x n arrays of at least this many bytes each load and store
+// them nontemporally (see sload): such arrays exceed what the caches keep between
+// passes, while small ones (a 500 x 500 problem) are faster cached.
+constexpr double kStreamNtBytes = 64.0 * 1024 * 1024;
+
+template <typename T>
+bool stream_nt(int64_t d, int64_t n) {
+    return (double)d * (double)n * sizeof(T) >= kStreamNtBytes;
+}
+
 template <typename T>
 void launch_group_partial(bool with_d, const T* A, int64_t lda, const T* S, int64_t lds,
                           const T* Th, int64_t ldt, T inv_rho, int64_t d, int64_t n, int c,
@@ -917,24 +927,21 @@ void launch_group_partial(bool with_d, const T* A, int64_t lda, const T* S, int6
     if (grid == 0) return;
     int v = with_d ? pick_vec<T>(d, {{A, lda}, {S, lds}, {Th, ldt}}) : pick_vec<T>(d, {{A, lda}});
     constexpr int VV = 16 / sizeof(T);
+    // a whole pass (not the moved columns only) over large arrays: nontemporal
+    const bool nt = max_seg < 0 && stream_nt<T>(d, n);
+    const T* S2 = with_d ? S : A;
+    const T* Th2 = with_d ? Th : A;
+    const int64_t lds2 = with_d ? lds : lda, ldt2 = with_d ? ldt : lda;
+    auto go = [&](auto kern) {
+        kern<<<grid, kBlock, 0, st>>>(A, lda, S2, lds2, Th2, ldt2, inv_rho, d, perm, seg_begin,
+                                      seg_len, nseg, nrb, partial, T(0), T(0));
+    };
     if (with_d) {
-        if (v == VV)
-            k_group_partial<T, VV, true><<<grid, kBlock, 0, st>>>(A, lda, S, lds, Th, ldt, inv_rho, d,
-                                                                  perm, seg_begin, seg_len, nseg, nrb,
-                                                                  partial);
-        else
-            k_group_partial<T, 1, true><<<grid, kBlock, 0, st>>>(A, lda, S, lds, Th, ldt, inv_rho, d,
-                                                                 perm, seg_begin, seg_len, nseg, nrb,
-                                                                 partial);
+        if (v == VV) nt ? go(k_group_partial<T, VV, true, false, true>) : go(k_group_partial<T, VV, true>);
+        else nt ? go(k_group_partial<T, 1, true, false, true>) : go(k_group_partial<T, 1, true>);
     } else {
-        if (v == VV)
-            k_group_partial<T, VV, false><<<grid, kBlock, 0, st>>>(A, lda, A, lda, A, lda, inv_rho, d,
-                                                                   perm, seg_begin, seg_len, nseg, nrb,
-                                                                   partial);
-        else
-            k_group_partial<T, 1, false><<<grid, kBlock, 0, st>>>(A, lda, A, lda, A, lda, inv_rho, d,
-                                                                  perm, seg_begin, seg_len, nseg, nrb,
-                                                                  partial);
+        if (v == VV) nt ? go(k_group_partial<T, VV, false, false, true>) : go(k_group_partial<T, VV, false>);
+        else nt ? go(k_group_partial<T, 1, false, false, true>) : go(k_group_partial<T, 1, false>);
     }
 }
 
@@ -997,12 +1004,13 @@ int launch_sweep_seg(const T* X, int64_t ldx, T* L, int64_t ldl, T* S, int64_t l
                                       (T)inv_rho, (T)inv_rho_next, norm_partial, next_partial,
                                       l21_fac, T(0), T(0));
     };
+    const bool nt = stream_nt<T>(d, n);
     if (l21_fac) {
-        if (v == VV) go(k_sweep_seg<T, VV, true>);
-        else go(k_sweep_seg<T, 1, true>);
+        if (v == VV) nt ? go(k_sweep_seg<T, VV, true, false, 4, true>) : go(k_sweep_seg<T, VV, true>);
+        else nt ? go(k_sweep_seg<T, 1, true, false, 4, true>) : go(k_sweep_seg<T, 1, true>);
     } else {
-        if (v == VV) go(k_sweep_seg<T, VV, false>);
-        else go(k_sweep_seg<T, 1, false>);
+        if (v == VV) nt ? go(k_sweep_seg<T, VV, false, false, 4, true>) : go(k_sweep_seg<T, VV, false>);
+        else nt ? go(k_sweep_seg<T, 1, false, false, 4, true>) : go(k_sweep_seg<T, 1, false>);
     }
     return (int)grid;
 }
@@ -1027,8 +1035,10 @@ int launch_sweep_seg_compact(const T* X, int64_t ldx, T* L, int64_t ldl, T* B, i
     };
     // eight columns in flight per thread (2, 4, 6, 8 measured: 8 is the fastest
     // at 10^4 x 10^4 despite two waves per SIMD)
-    if (v == VV) go(k_sweep_seg<T, VV, false, true, 8>);
-    else go(k_sweep_seg<T, 1, false, true, 8>);
+    // large arrays nontemporal (see stream_nt)
+    const bool nt = stream_nt<T>(d, n);
+    if (v == VV) nt ? go(k_sweep_seg<T, VV, false, true, 8, true>) : go(k_sweep_seg<T, VV, false, true, 8>);
+    else nt ? go(k_sweep_seg<T, 1, false, true, 8, true>) : go(k_sweep_seg<T, 1, false, true, 8>);
     return (int)grid;
 }
 
@@ -1043,14 +1053,13 @@ void launch_group_partial_compact(const T* X, int64_t ldx, const T* B, int64_t l
     if (grid == 0) return;
     constexpr int VV = 16 / sizeof(T);
     const int v = pick_vec<T>(d, {{X, ldx}, {B, ldb}});
-    if (v == VV)
-        k_group_partial<T, VV, true, true><<<grid, kBlock, 0, st>>>(
-            X, ldx, B, ldb, nullptr, 0, inv_rho, d, perm, seg_begin, seg_len, nseg, nrb, partial,
-            rho_prev, inv_rho_prev);
-    else
-        k_group_partial<T, 1, true, true><<<grid, kBlock, 0, st>>>(
-            X, ldx, B, ldb, nullptr, 0, inv_rho, d, perm, seg_begin, seg_len, nseg, nrb, partial,
-            rho_prev, inv_rho_prev);
+    auto go = [&](auto kern) {
+        kern<<<grid, kBlock, 0, st>>>(X, ldx, B, ldb, nullptr, 0, inv_rho, d, perm, seg_begin,
+                                      seg_len, nseg, nrb, partial, rho_prev, inv_rho_prev);
+    };
+    const bool nt = stream_nt<T>(d, n);
+    if (v == VV) nt ? go(k_group_partial<T, VV, true, true, true>) : go(k_group_partial<T, VV, true, true>);
+    else nt ? go(k_group_partial<T, 1, true, true, true>) : go(k_group_partial<T, 1, true, true>);
 }
 
 // S = soft(B, tau) in place over a d x n column-major matrix.
@@ -1079,12 +1088,13 @@ void launch_l21_factor(const T* X, int64_t ldx, const T* S, int64_t lds, const T
     constexpr int VV = 16 / sizeof(T);
     const int v = pick_vec<T>(d, {{X, ldx}, {S, lds}, {Th, ldt}, {C, d}});
     const unsigned grid = (unsigned)(n < 65536 ? n : 65536);
-    if (v == VV)
-        k_l21_factor<T, VV><<<grid, kBlock, 0, st>>>(X, ldx, S, lds, Th, ldt, C, labels, d, n,
-                                                     (T)alpha, (T)beta, (T)inv_rho, rho, fac);
-    else
-        k_l21_factor<T, 1><<<grid, kBlock, 0, st>>>(X, ldx, S, lds, Th, ldt, C, labels, d, n,
-                                                    (T)alpha, (T)beta, (T)inv_rho, rho, fac);
+    auto go = [&](auto kern) {
+        kern<<<grid, kBlock, 0, st>>>(X, ldx, S, lds, Th, ldt, C, labels, d, n, (T)alpha, (T)beta,
+                                      (T)inv_rho, rho, fac);
+    };
+    const bool nt = stream_nt<T>(d, n);
+    if (v == VV) nt ? go(k_l21_factor<T, VV, true>) : go(k_l21_factor<T, VV>);
+    else nt ? go(k_l21_factor<T, 1, true>) : go(k_l21_factor<T, 1>);
 }
 
 int64_t dots_slice_rows(int64_t d, int64_t n, int c) {
@@ -1160,6 +1170,9 @@ void launch_d2_bounded(const float* Y, int64_t ldy, int64_t d, int64_t n, const 
     // FP32 error of A: per-term rounding (3 units) plus at most 8 ceil(d / 512) lane
     // additions, doubled
     const float eta = (float)(2.0 * (3.0 + 8.0 * (double)((d + 511) / 512)) * std::ldexp(1.0, -24));
+    // (the FP16 copy, 2 d n bytes, is re-read by every seed's pass: plain loads,
+    // which keep part of it in the last-level cache; nontemporal ones cost 4.7 ->
+    // 5.5 ms of seeding per 10^4 x 10^4 solve)
     if (pick_vec<float>(d, {{Y, ldy}}) == 4)
         k_d2_bounded<4><<<g, kBlock, 0, st>>>(Y, ldy, d, n, seeds, m, d2, Z, d2_copy_ld(d), zsc,
                                               ynorm, eta);

@@ -1,6 +1,7 @@
 // Streaming bandwidth probe: the practical HBM ceiling of a given mix of
-// reads and writes on this GPU (the sweep reads four d x n arrays and writes
-// three; the means pass reads three; a copy reads one and writes one).  Used to
+// reads and writes on this GPU, with plain or nontemporal loads and stores (the
+// l1 sweep on the compact state reads three d x n arrays and writes two; the
+// means pass reads two; a copy reads one and writes one).  Used to
 // put the streaming kernels' achieved bandwidth beside what the memory system
 // delivers for the same mix, not only beside the 8 TB/s peak.
 #include <hip/hip_runtime.h>
@@ -22,8 +23,9 @@ struct ProbePtrs {
     float4* out[3];
 };
 
-template <int R, int W>
+template <int R, int W, bool NT>
 __global__ __launch_bounds__(kProbeBlock) void k_stream_mix(ProbePtrs p, int64_t n4) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
     const int64_t stride = (int64_t)gridDim.x * kProbeBlock * kProbeUnroll;
     for (int64_t base = (int64_t)blockIdx.x * kProbeBlock * kProbeUnroll + threadIdx.x; base < n4;
          base += stride) {
@@ -33,7 +35,14 @@ __global__ __launch_bounds__(kProbeBlock) void k_stream_mix(ProbePtrs p, int64_t
 #pragma unroll
             for (int u = 0; u < kProbeUnroll; ++u) {
                 const int64_t i = base + (int64_t)u * kProbeBlock;
-                v[r][u] = i < n4 ? p.in[r][i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                if (i >= n4) {
+                    v[r][u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                } else if constexpr (NT) {
+                    const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.in[r] + i));
+                    v[r][u] = make_float4(t[0], t[1], t[2], t[3]);
+                } else {
+                    v[r][u] = p.in[r][i];
+                }
             }
 #pragma unroll
         for (int u = 0; u < kProbeUnroll; ++u) {
@@ -50,7 +59,11 @@ __global__ __launch_bounds__(kProbeBlock) void k_stream_mix(ProbePtrs p, int64_t
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
                     const float f = (float)(w + 1);
-                    p.out[w][i] = make_float4(s.x * f, s.y * f, s.z * f, s.w * f);
+                    if constexpr (NT)
+                        __builtin_nontemporal_store(f4{s.x * f, s.y * f, s.z * f, s.w * f},
+                                                    reinterpret_cast<f4*>(p.out[w] + i));
+                    else
+                        p.out[w][i] = make_float4(s.x * f, s.y * f, s.z * f, s.w * f);
                 }
             }
             if (W == 0 && i < n4 && s.x == -1.2345f) p.out[0][i] = s;   // keeps the loads alive
@@ -64,27 +77,31 @@ __global__ __launch_bounds__(kProbeBlock) void k_probe_fill(float4* a, int64_t n
         a[i] = make_float4(v, v + 1.f, v + 2.f, v + 3.f);
 }
 
-template <int R, int W>
+template <int R, int W, bool NT>
 void launch_mix(const ProbePtrs& p, int64_t n4, int grid, hipStream_t st) {
-    k_stream_mix<R, W><<<grid, kProbeBlock, 0, st>>>(p, n4);
+    k_stream_mix<R, W, NT><<<grid, kProbeBlock, 0, st>>>(p, n4);
 }
 
 using MixFn = void (*)(const ProbePtrs&, int64_t, int, hipStream_t);
 
-MixFn mix_fn(int r, int w) {
+template <bool NT>
+MixFn mix_fn_t(int r, int w) {
     static const MixFn table[4][4] = {
-        {launch_mix<1, 0>, launch_mix<1, 1>, launch_mix<1, 2>, launch_mix<1, 3>},
-        {launch_mix<2, 0>, launch_mix<2, 1>, launch_mix<2, 2>, launch_mix<2, 3>},
-        {launch_mix<3, 0>, launch_mix<3, 1>, launch_mix<3, 2>, launch_mix<3, 3>},
-        {launch_mix<4, 0>, launch_mix<4, 1>, launch_mix<4, 2>, launch_mix<4, 3>}};
+        {launch_mix<1, 0, NT>, launch_mix<1, 1, NT>, launch_mix<1, 2, NT>, launch_mix<1, 3, NT>},
+        {launch_mix<2, 0, NT>, launch_mix<2, 1, NT>, launch_mix<2, 2, NT>, launch_mix<2, 3, NT>},
+        {launch_mix<3, 0, NT>, launch_mix<3, 1, NT>, launch_mix<3, 2, NT>, launch_mix<3, 3, NT>},
+        {launch_mix<4, 0, NT>, launch_mix<4, 1, NT>, launch_mix<4, 2, NT>, launch_mix<4, 3, NT>}};
     return table[r - 1][w];
 }
+
+MixFn mix_fn(int r, int w, bool nt) { return nt ? mix_fn_t<true>(r, w) : mix_fn_t<false>(r, w); }
 
 }  // namespace
 
 extern "C" respca_status respca_bandwidth_probe(respca_handle h, int32_t reads, int32_t writes,
-                                                int64_t bytes_per_array, int32_t reps,
-                                                double* gbps, double* ms_per_launch, void* stream) {
+                                                int32_t nontemporal, int64_t bytes_per_array,
+                                                int32_t reps, double* gbps, double* ms_per_launch,
+                                                void* stream) {
     if (!h) return RESPCA_ERR_INVALID;
     if (reads < 1 || reads > 4 || writes < 0 || writes > 3 || reps < 1 || bytes_per_array < 16 ||
         bytes_per_array % 16 != 0)
@@ -109,7 +126,7 @@ extern "C" respca_status respca_bandwidth_probe(respca_handle h, int32_t reads, 
     const int64_t need = (n4 + (int64_t)kProbeBlock * kProbeUnroll - 1) / ((int64_t)kProbeBlock * kProbeUnroll);
     const int grid = (int)(need < (int64_t)prop.multiProcessorCount * 16 ? need
                                                                           : (int64_t)prop.multiProcessorCount * 16);
-    MixFn fn = mix_fn(reads, writes);
+    MixFn fn = mix_fn(reads, writes, nontemporal != 0);
     fn(p, n4, grid, st);   // warm-up
     hipEvent_t a = nullptr, b = nullptr;
     CK(hipEventCreate(&a));

@@ -116,7 +116,7 @@ def lib():
         L.respca_autotune_batched.argtypes = [vp, ct.POINTER(Params), i32, i64p, i64p, arr, i64p, arr,
                                               i64p, arr, i64p, ct.c_char_p, ct.POINTER(ct.c_double), vp]
         L.respca_bandwidth_probe.restype = i32
-        L.respca_bandwidth_probe.argtypes = [vp, i32, i32, i64, i32, ct.POINTER(ct.c_double),
+        L.respca_bandwidth_probe.argtypes = [vp, i32, i32, i32, i64, i32, ct.POINTER(ct.c_double),
                                              ct.POINTER(ct.c_double), vp]
         L.respca_set_batched_tile.restype = i32
         L.respca_set_batched_tile.argtypes = [vp, i32, i32, i32]
@@ -499,12 +499,13 @@ def get_batched_tile(device: int = 0) -> tuple:
 
 
 def bandwidth_probe(reads: int, writes: int, bytes_per_array: int, reps: int = 10,
-                    stream=None, device: int = 0) -> tuple:
+                    stream=None, device: int = 0, nontemporal: bool = False) -> tuple:
     """Streaming probe of a read/write mix; returns (GB/s, ms per launch)."""
     h = handle(device)
     g, ms = ct.c_double(0.0), ct.c_double(0.0)
-    h.check(lib().respca_bandwidth_probe(h._h, int(reads), int(writes), int(bytes_per_array),
-                                         int(reps), ct.byref(g), ct.byref(ms), _stream(stream)))
+    h.check(lib().respca_bandwidth_probe(h._h, int(reads), int(writes), int(bool(nontemporal)),
+                                         int(bytes_per_array), int(reps), ct.byref(g), ct.byref(ms),
+                                         _stream(stream)))
     return g.value, ms.value
 
 
