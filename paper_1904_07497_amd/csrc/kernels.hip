@@ -643,12 +643,15 @@ __global__ __launch_bounds__(kBlock) void k_d2_first(const float* __restrict__ Y
 }
 
 // Bounded D^2 update for seeds m >= 1 (float runs).  A lower bound on
-// ||y_j - y_s|| comes from the fp16 copy of y_j and the FP32 seed column:
-// sqrt(A / (1 + eta)) - E_j, with A the FP32 sum of (z_i sc_j - y_s,i)^2 (relative
-// error at most eta) and E_j = 2^-10 ||y_j|| + 2^-24 sc_j sqrt(d) the copy's error
-// bound (twice the rounding bound).  When the bound already exceeds d2[j] the
-// minimum cannot change and the exact distance is skipped; otherwise it is
-// computed exactly as in k_d2, so d2 holds the same values either way.
+// ||y_j - y_s|| comes from the fp16 copies of both columns: sqrt(A / (1 + eta)) -
+// E_j - E_s, with A the FP32 sum of (z_j,i sc_j - z_s,i sc_s)^2 (relative error at
+// most eta; z_s,i sc_s is exact up to underflow, below 2^-149 per row) and E_j =
+// 2^-10 ||y_j|| + 2^-24 sc_j sqrt(d) a copy's error bound (twice the rounding
+// bound), E_s the seed copy's, plus sqrt(d) 2^-149.  When the bound already exceeds
+// d2[j] the minimum cannot change and the exact distance is skipped; otherwise it
+// is computed exactly as in k_d2, so d2 holds the same values either way.  Reading
+// the seed's copy instead of its FP32 column halves what each pass takes from the
+// caches for the seed.
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_d2_bounded(const float* __restrict__ Y, int64_t ldy,
                                                        int64_t d, int64_t n,
@@ -660,64 +663,48 @@ __global__ __launch_bounds__(kBlock) void k_d2_bounded(const float* __restrict__
     const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (j >= n) return;
-    const float* ys = Y + (int64_t)seeds[m] * ldy;
+    const int64_t sd = seeds[m];
+    const float* ys = Y + sd * ldy;
     const _Float16* zj = Z + j * ldz;
-    const float sc = zsc[j];
+    const _Float16* zs = Z + sd * ldz;
+    const float sc = zsc[j], scs = zsc[sd];
     typedef _Float16 half8 __attribute__((ext_vector_type(8)));
     float acc = 0.f;
     int64_t i = (int64_t)lane * 8;
-    if constexpr (V == 4) {
-        // whole 512-row passes, four at a time: their loads are issued before any of
-        // their arithmetic (the same additions in the same order as below)
-        constexpr int U = 4;
-        const int64_t nfull = d / 512;
-        for (int64_t t = 0; t + U <= nfull; t += U, i += 512 * U) {
-            half8 z[U];
-            float4 a[U], b[U];
+    // whole 512-row passes, four at a time: their loads are issued before any of
+    // their arithmetic (the same additions in the same order as below)
+    constexpr int U = 4;
+    const int64_t nfull = d / 512;
+    for (int64_t t = 0; t + U <= nfull; t += U, i += 512 * U) {
+        half8 z[U], w[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                z[u] = *reinterpret_cast<const half8*>(zj + i + 512 * u);
-                a[u] = *reinterpret_cast<const float4*>(ys + i + 512 * u);
-                b[u] = *reinterpret_cast<const float4*>(ys + i + 512 * u + 4);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float y[8] = {a[u].x, a[u].y, a[u].z, a[u].w, b[u].x, b[u].y, b[u].z, b[u].w};
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const float t2 = fmaf((float)z[u][e], sc, -y[e]);
-                    acc = fmaf(t2, t2, acc);
-                }
-            }
+        for (int u = 0; u < U; ++u) {
+            z[u] = *reinterpret_cast<const half8*>(zj + i + 512 * u);
+            w[u] = *reinterpret_cast<const half8*>(zs + i + 512 * u);
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float t2 = fmaf((float)z[u][e], sc, -((float)w[u][e] * scs));
+                acc = fmaf(t2, t2, acc);
+            }
     }
-    for (; i < d; i += 512) {   // ldz % 8 == 0: 16-byte loads
+    for (; i < ldz; i += 512) {   // ldz % 8 == 0: 16-byte loads; both copies are zero past row d
         const half8 z = *reinterpret_cast<const half8*>(zj + i);
-        float y[8];
-        if (i + 8 <= d) {
-            if constexpr (V == 4) {
-                const float4 a = *reinterpret_cast<const float4*>(ys + i);
-                const float4 b = *reinterpret_cast<const float4*>(ys + i + 4);
-                y[0] = a.x; y[1] = a.y; y[2] = a.z; y[3] = a.w;
-                y[4] = b.x; y[5] = b.y; y[6] = b.z; y[7] = b.w;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) y[e] = ys[i + e];
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) y[e] = i + e < d ? ys[i + e] : 0.f;
-        }
+        const half8 w = *reinterpret_cast<const half8*>(zs + i);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const float t = fmaf((float)z[e], sc, -y[e]);
+            const float t = fmaf((float)z[e], sc, -((float)w[e] * scs));
             acc = fmaf(t, t, acc);
         }
     }
     // A less the largest total of underflowed squares (2^-148 per term), then the
     // relative error; an infinite or NaN A never skips
-    const double A = wave_sum((double)acc) - (double)d * ldexp(1.0, -148);
-    const double E = (ldexp(1.0, -10) * ynorm[j] + ldexp(1.0, -24) * (double)sc * sqrt((double)d)) *
+    const double A = wave_sum((double)acc) - (double)ldz * ldexp(1.0, -148);
+    const double rd = sqrt((double)d);
+    const double E = (ldexp(1.0, -10) * (ynorm[j] + ynorm[sd]) +
+                      ldexp(1.0, -24) * ((double)sc + (double)scs) * rd + ldexp(1.0, -149) * rd) *
                      (1.0 + 1e-6);
     const double lb = sqrt(fmax(A, 0.0) / (1.0 + (double)eta)) - E;
     const double cur = d2[j];
