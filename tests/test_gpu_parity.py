@@ -122,6 +122,35 @@ def test_solve_f32_grouped_iteration_locked(shape, lam):
     assert abs(g2["info"]["iters"] - T) <= 1
 
 
+@pytest.mark.parametrize("dtype,d,n", [(np.float64, 3000, 3000), (np.float32, 4096, 4200)])
+def test_solve_above_the_nontemporal_size_iteration_locked(dtype, d, n):
+    """Arrays of 64 MiB and more take the nontemporal forms of the sweep and the
+    means passes (FP64: double2 loads and stores): six iterations, iteration-locked
+    to the oracle, on grouped data; labels equal, L and S within the precision's bar,
+    the support of S equal on well-separated entries."""
+    c, T = 6, 6
+    assert d * n * np.dtype(dtype).itemsize >= 64 << 20
+    say(f"solve {np.dtype(dtype).name} {d}x{n} above the nontemporal size")
+    X, _, _, _ = synth.clustered(d, n, c, seed=17, sep=4.0, noise=0.5, frac=0.05, amp=10.0,
+                                 dtype=dtype)
+    lam = float(np.sqrt(max(d, n)))
+    prm = oracle.make_params(c, lam=lam, tol=0.0, max_iter=T, seed=2)
+    o = oracle.solve(X, prm)
+    g = rp.solve(dev(X), rank=c, lam=lam, tol=0.0, max_iter=T, seed=2,
+                 precision=rp.F64 if dtype == np.float64 else rp.F32)
+    assert g["info"]["iters"] == o["info"]["iters"] == T
+    np.testing.assert_array_equal(g["labels"].cpu().numpy(), o["labels"])
+    tol = F64_TOL if dtype == np.float64 else F32_TOL
+    nX = np.linalg.norm(X.astype(np.float64))
+    assert rel(host(g["L"]), o["L"], nX) <= tol
+    assert rel(host(g["S"]), o["S"], nX) <= tol
+    st, th_prev, rho_t, _ = trajectory(X, prm, T)
+    frac = support_check(X.astype(np.float64), st["L"], th_prev, rho_t, host(g["S"]), st["S"],
+                         np.finfo(dtype).eps)
+    say(f"S support: {frac:.4f} of entries separated")
+    assert frac > 0.5
+
+
 @pytest.mark.parametrize("precision", [rp.F32, rp.BF16GEMM_F32])
 def test_solve_single_lloyd_step_matches_oracle(precision):
     """p-step of one Lloyd assignment per outer iteration (max_lloyd = 1, also for
