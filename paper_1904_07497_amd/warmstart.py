@@ -16,8 +16,8 @@ calls and moves tensors.  For every column the network predicts
 
 rho0* of a training instance is the largest value on the grid 1e-4 * 1.5^k
 whose run, started from the cold run's groups, still converges to the same
-error against the planted L as the cold run (within 1 %).  The solver stays
-the judge: whatever the network predicts, the iterations run to tolerance.
+error against the planted L as the cold run (within 1 %).  The solver has the
+last word: whatever the network predicts, the iterations run to tolerance.
 
 At inference the predicted sketches are clustered (64 coordinates instead of d),
 Lloyd on X refines those groups, and the iterations start from them with the
