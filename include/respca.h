@@ -261,6 +261,19 @@ respca_status respca_spectral_embedding(respca_handle h, int32_t precision, int6
                                         respca_info *info, void *stream);
 
 /*
+ * Anomaly scores (Sec. 5.3, the anomaly-detection experiment: the columns of the
+ * recovered S with a large l2 norm are the outlying samples): out[j] = ||S_j||_2
+ * for the n columns of S (d x n, leading dimension lds >= max(d, 1); double if
+ * precision is RESPCA_F64, else float), summed in double in a fixed order.  out:
+ * device, n doubles, written on `stream`.  d = 0 gives zeros; n = 0 does
+ * nothing.  RESPCA_ERR_INVALID for a bad precision, negative sizes, lds < d or a
+ * null pointer with d, n > 0.  The threshold that separates outliers is the
+ * caller's (the paper blanks scores below 5 on its data).
+ */
+respca_status respca_column_norms(respca_handle h, int32_t precision, int64_t d, int64_t n,
+                                  const void *S, int64_t lds, double *out, void *stream);
+
+/*
  * Batched solve: `batch` independent RES-PCA problems of uneven size, each run
  * exactly as respca_solve would run it (its own initial K-means, iteration
  * count, Lloyd passes and Sec. 5 stopping test), all inside one persistent

@@ -77,6 +77,7 @@ def lib():
         L.oracle_s_step.argtypes = [i64, i64, f64, dp, dp, dp, dp]
         L.oracle_s_step_l21.argtypes = [i64, i64, f64, dp, dp, dp, dp]
         L.oracle_theta_step.argtypes = [i64, i64, f64, dp, dp, dp, dp]
+        L.oracle_column_norms.argtypes = [i64, i64, dp, dp]
         L.oracle_step.restype = i32
         L.oracle_step.argtypes = [P(Params), i64, i64, dp, dp, dp, dp, ip, dp, dp, dp]
         L.oracle_step_columns.argtypes = [P(Params), i64, i64, dp, dp, dp, ip, dp, f64, i64, lp,
@@ -208,6 +209,15 @@ def s_step(X, L, Theta, rho, sparse_norm=0):
     f = lib().oracle_s_step_l21 if sparse_norm == 1 else lib().oracle_s_step
     f(d, n, float(rho), _dp(X), _dp(L), _dp(Theta), _dp(S))
     return S
+
+
+def column_norms(S):
+    """Sec. 5.3 anomaly scores: ||S_j||_2 for every column of S."""
+    S = _f64(S)
+    d, n = S.shape
+    out = np.zeros(n)
+    lib().oracle_column_norms(d, n, _dp(S), _dp(out))
+    return out
 
 
 def theta_step(X, L, S, Theta, rho):

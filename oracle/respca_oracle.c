@@ -237,6 +237,18 @@ void oracle_s_step_l21(int64_t d, int64_t n, double rho, const double *X,
     }
 }
 
+/* Sec. 5.3 (anomaly detection): the l2 norm of each column of S, the score by
+   which the outlying samples are read off the recovered sparse part. */
+void oracle_column_norms(int64_t d, int64_t n, const double *S, double *out)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        const double *s = S + j * d;
+        double q = 0.0;
+        for (int64_t i = 0; i < d; ++i) q += s[i] * s[i];
+        out[j] = sqrt(q);
+    }
+}
+
 void oracle_theta_step(int64_t d, int64_t n, double rho, const double *X,
                        const double *L, const double *S, double *Theta)
 {

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librespca.so")
 SOURCES = ["kernels.hip", "distance.hip", "batched.hip", "warmstart.hip", "solver.hip",
-           "batched_host.hip", "warmstart_host.hip", "probe.hip", "spectral.hip"]
+           "batched_host.hip", "warmstart_host.hip", "probe.hip", "spectral.hip", "anomaly.hip"]
 
 # Packed-FP32 VALU ops are disabled for every device pass; the host pass warns
 # that it does not know the feature, which is harmless.

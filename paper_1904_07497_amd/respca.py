@@ -30,7 +30,7 @@ EXPORTS = ("respca_create", "respca_destroy", "respca_params_default", "respca_s
            "respca_set_batched_tile", "respca_get_batched_tile", "respca_bandwidth_probe",
            "respca_mlp_param_count", "respca_mlp_act_count", "respca_sketch", "respca_features",
            "respca_mlp_forward", "respca_mlp_backward", "respca_mlp_loss", "respca_mlp_adam",
-           "respca_warmstart", "respca_warmstart_batched")
+           "respca_warmstart", "respca_warmstart_batched", "respca_column_norms")
 WARM_IN, WARM_OUT = 68, 65
 BATCH_PHASES = ("pack", "init", "seed_distance", "seed_draw", "seed_gather", "sort", "means",
                 "finalize", "sweep", "distance", "argmin", "control")
@@ -100,6 +100,8 @@ def lib():
         L.respca_spectral_embedding.argtypes = [vp, i32, i64, i64, vp, i64, i32, ct.c_double,
                                                 ct.c_uint64, vp, ct.POINTER(ct.c_double),
                                                 ct.POINTER(Info), vp]
+        L.respca_column_norms.restype = i32
+        L.respca_column_norms.argtypes = [vp, i32, i64, i64, vp, i64, vp, vp]
         L.respca_iterate_noalloc.restype = i32
         L.respca_iterate_noalloc.argtypes = L.respca_iterate.argtypes
         L.respca_profile_enable.restype = i32
@@ -358,6 +360,20 @@ def spectral_embedding(Y, rank, sigma, seed=0, precision=None, stream=None):
                                         _stream(stream))
     h.check(s, allow=(OK,))
     return emb, np.ctypeslib.as_array(vals).copy(), info.as_dict()
+
+
+def column_norms(S, precision=None, stream=None):
+    """Anomaly scores of Sec. 5.3: the l2 norm of every column of S (d x n,
+    column-major), float64 on S's device."""
+    import torch
+    precision = _dtype_precision(S, precision)
+    d, n = S.shape
+    sp, lds = _colmajor(S, "S")
+    out = torch.empty(n, dtype=torch.float64, device=S.device)
+    h = handle(S.device.index or 0)
+    h.check(lib().respca_column_norms(h._h, int(precision), d, n, sp, max(lds, 1), out.data_ptr(),
+                                      _stream(stream)), allow=(OK,))
+    return out
 
 
 def kmeans(Y, rank, seed=0, max_lloyd=100, precision=None, stream=None):

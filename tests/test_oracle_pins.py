@@ -768,3 +768,55 @@ def test_stepwise_trajectory_reproduces_the_solve(orc, sparse_norm, use_init):
     # the last multiplier update: Theta_T - Theta_{T-1} = rho_T (X - L - S)
     np.testing.assert_allclose(st["Theta"] - th_prev, rho_t * (X - st["L"] - st["S"]),
                                atol=1e-12 * np.abs(X).max() * max(rho_t, 1.0))
+
+
+# ------------------------------------------------ anomaly scores (Sec. 5.3)
+
+def test_column_norms_closed_forms(orc):
+    """||S_j||_2 on columns whose norms are known by hand: a 3-4-5 column, a zero
+    column, a constant column (sqrt(d) |a|), a single nonzero entry."""
+    S = np.zeros((4, 4), order="F")
+    S[0, 0], S[2, 0] = 3.0, -4.0
+    S[:, 2] = -2.5
+    S[3, 3] = -7.0
+    np.testing.assert_array_equal(orc.column_norms(S), [5.0, 0.0, 5.0, 7.0])
+    assert orc.column_norms(np.zeros((0, 3), order="F")).tolist() == [0.0, 0.0, 0.0]
+
+
+def test_column_norms_of_the_l21_s_step(orc):
+    """The column-wise S-step shrinks each column of B = X - L + Theta/rho toward
+    zero by 1/rho in norm: ||S_j|| = max(0, ||B_j|| - 1/rho) (the block soft
+    threshold of Sec. 3's alternative penalty)."""
+    rng = np.random.default_rng(11)
+    d, n, rho = 30, 50, 2.0
+    X = np.asfortranarray(rng.normal(size=(d, n)) * rng.uniform(0.01, 0.5, n))
+    L = np.asfortranarray(rng.normal(scale=0.02, size=(d, n)))
+    Th = np.asfortranarray(rng.uniform(-1, 1, (d, n)) * rng.uniform(0.0, 0.1, n))
+    S = orc.s_step(X, L, Th, rho, sparse_norm=1)
+    Bn = np.sqrt(((X - L + Th / rho) ** 2).sum(axis=0))
+    expect = np.maximum(0.0, Bn - 1.0 / rho)
+    assert (expect == 0).any() and (expect > 0).any()
+    np.testing.assert_allclose(orc.column_norms(S), expect, rtol=1e-13, atol=1e-15)
+
+
+def _planted_outlier_columns(seed=3):
+    """Grouped inlier columns plus ten columns from an unrelated distribution
+    (the shape of the Sec. 5.3 experiment: a few samples unlike the rest)."""
+    rng = np.random.default_rng(seed)
+    d, n_in, n_out, c = 60, 190, 10, 3
+    Xi, _, _, _ = synth.clustered(d, n_in, c, seed=5, sep=3.0, noise=0.3, frac=0.0, amp=0.0)
+    Xo = rng.normal(0.0, 3.0, (d, n_out))
+    X = np.concatenate([Xi, Xo], axis=1)
+    perm = rng.permutation(X.shape[1])
+    return np.asfortranarray(X[:, perm]), np.sort(np.where(perm >= n_in)[0]), c
+
+
+def test_l21_solve_scores_flag_the_planted_outlier_columns(orc):
+    """Sec. 5.3 in miniature: after an l2,1 solve the ten largest column norms of
+    S are the ten planted outlier columns, and every inlier column of S is zero."""
+    X, out_idx, c = _planted_outlier_columns()
+    o = orc.solve(X, orc.make_params(c, lam=0.1, tol=1e-7, sparse_norm=1, seed=0))
+    sc = orc.column_norms(o["S"])
+    np.testing.assert_array_equal(np.sort(np.argsort(-sc)[:10]), out_idx)
+    inl = np.setdiff1d(np.arange(X.shape[1]), out_idx)
+    assert np.all(sc[inl] == 0.0) and np.all(sc[out_idx] > 10.0)
